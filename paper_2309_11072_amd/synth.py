@@ -1,0 +1,146 @@
+"""Seeded synthetic Radiance (RGBE) images.
+
+This module only makes inputs: it holds none of the encoder's arithmetic and is
+shared by the GPU tests, the oracle tests and the benchmark.  The public HDR
+photo sets the paper measures on are not available, so these images stand in
+for them with the shape the paper uses (full-colour Radiance pixels, Sec. IV)
+and a controllable exponent spread.
+
+Recipe (per image):
+  1. Z ~ N(0, 1) of shape H x W from numpy's PCG64(seed);
+  2. Z is smoothed by a Gaussian of `smooth` pixels (reflect borders) and
+     divided by its empirical standard deviation;
+  3. log2 luminance = sigma_l * Z;
+  4. per-channel chroma ratios rho_c ~ U[0.5, 2] on a `cell`-pixel grid,
+     bilinearly interpolated and normalised to unit Rec. 709 luminance;
+  5. f_c = 2^(log2 luminance) * rho_c;
+  6. optionally a Bernoulli(spec_frac) mask multiplies f by 2^spec_stops;
+  7. packing into RGBE with the forward converter of Sec. II.A (Eq. 1-2),
+     read through frexp so the largest mantissa stays in [128, 255]: with
+     v = max_c f_c = m 2^e, m in [0.5, 1): E = e + 128, M_c = floor(f_c 2^(8-e)).
+"""
+from __future__ import annotations
+
+import hashlib
+from dataclasses import dataclass
+
+import numpy as np
+from scipy.ndimage import gaussian_filter
+
+
+def pack_rgbe(f: np.ndarray) -> np.ndarray:
+    """float64 [H, W, 3] (non-negative) -> uint8 [H, W, 4] (R, G, B, E)."""
+    f = np.asarray(f, np.float64)
+    v = f.max(axis=-1)
+    m, e = np.frexp(v)
+    lit = v >= 2.0 ** -128
+    E = np.where(lit, e + 128, 0)
+    if np.any(E > 255):
+        raise ValueError("value too large for RGBE")
+    M = np.floor(np.ldexp(f, (8 - e)[..., None]))
+    M = np.where(lit[..., None], M, 0)
+    out = np.empty(f.shape[:2] + (4,), np.uint8)
+    out[..., :3] = M.astype(np.uint8)
+    out[..., 3] = E.astype(np.uint8)
+    return out
+
+
+def _bilinear(grid: np.ndarray, H: int, W: int, cell: int) -> np.ndarray:
+    gy = (np.arange(H) + 0.5) / cell
+    gx = (np.arange(W) + 0.5) / cell
+    y0 = np.floor(gy).astype(np.int64)
+    x0 = np.floor(gx).astype(np.int64)
+    wy = (gy - y0)[:, None]
+    wx = (gx - x0)[None, :]
+    g = grid
+    a = g[:, y0][:, :, x0]
+    b = g[:, y0][:, :, x0 + 1]
+    c = g[:, y0 + 1][:, :, x0]
+    d = g[:, y0 + 1][:, :, x0 + 1]
+    return (a * (1 - wx) + b * wx) * (1 - wy) + (c * (1 - wx) + d * wx) * wy
+
+
+def generate(H: int, W: int, sigma_l: float, seed: int, spec_frac: float = 0.0,
+             spec_stops: float = 10.0, smooth: float = 8.0, cell: int = 32) -> np.ndarray:
+    """One seeded synthetic RGBE image, uint8 [H, W, 4]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    z = rng.standard_normal((H, W))
+    z = gaussian_filter(z, smooth, mode="reflect")
+    sd = z.std()
+    if sd > 0:
+        z /= sd
+    log2l = sigma_l * z
+    gh, gw = H // cell + 2, W // cell + 2
+    rho = _bilinear(rng.uniform(0.5, 2.0, (3, gh, gw)), H, W, cell)
+    rho /= (0.2126 * rho[0] + 0.7152 * rho[1] + 0.0722 * rho[2])[None]
+    f = np.exp2(log2l)[..., None] * np.moveaxis(rho, 0, -1)
+    if spec_frac > 0:
+        mask = rng.random((H, W)) < spec_frac
+        f[mask] *= 2.0 ** spec_stops
+    return pack_rgbe(f)
+
+
+def sha256(a: np.ndarray) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+@dataclass
+class ImageSpec:
+    H: int
+    W: int
+    sigma_l: float
+    q: int
+    seed: int
+    spec_frac: float = 0.0
+
+    def make(self) -> np.ndarray:
+        return generate(self.H, self.W, self.sigma_l, self.seed, self.spec_frac)
+
+
+ASPECTS = (4 / 3, 16 / 9, 1.0)
+
+
+def _draw_sizes(n, a_lo, a_hi, rng):
+    out = []
+    for _ in range(n):
+        A = rng.uniform(a_lo, a_hi)
+        r = ASPECTS[rng.integers(0, 3)]
+        W = int(round(np.sqrt(A * r)))
+        H = int(round(A / W))
+        out.append((max(H, 1), max(W, 1)))
+    return out
+
+
+def config1() -> ImageSpec:
+    """512x384 image, sigma 2.5, no speculars, q 90 (oracle-sized case)."""
+    return ImageSpec(384, 512, 2.5, 90, 1)
+
+
+def config2() -> ImageSpec:
+    """3840x2160 image, sigma 4, 5% speculars at +10 stops, q 75."""
+    return ImageSpec(2160, 3840, 4.0, 75, 2, 0.05)
+
+
+def config3(n: int = 64) -> list:
+    """64 uneven images, 640x480 .. 3840x2160 pixels' worth of area,
+    sigma in [1.5, 4], q in [50, 95]."""
+    rng = np.random.Generator(np.random.PCG64(3))
+    sizes = _draw_sizes(n, 640 * 480, 3840 * 2160, rng)
+    return [ImageSpec(H, W, float(rng.uniform(1.5, 4.0)), int(rng.integers(50, 96)), 3000 + i)
+            for i, (H, W) in enumerate(sizes)]
+
+
+def config4_train() -> list:
+    return [ImageSpec(2160, 3840, 4.0, 75, 4000 + i, 0.05) for i in range(2)]
+
+
+def config4_eval() -> list:
+    return [ImageSpec(1080, 1920, 4.0, 75, 4100 + i, 0.05) for i in range(16)]
+
+
+def config5(n: int = 256) -> list:
+    """256 uneven images of 1 MP .. 33 MP, sigma in [1, 5], q in [30, 98]."""
+    rng = np.random.Generator(np.random.PCG64(5))
+    sizes = _draw_sizes(n, 1.0e6, 7680 * 4320, rng)
+    return [ImageSpec(H, W, float(rng.uniform(1.0, 5.0)), int(rng.integers(30, 99)), 5000 + i)
+            for i, (H, W) in enumerate(sizes)]
