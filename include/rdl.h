@@ -1,0 +1,157 @@
+/*
+ * rdl.h -- C ABI of the MI355X (gfx950) encoder for dual-layer lossless coding
+ * of Radiance (RGBE) HDR images, after Suzuki et al., "Lightning-Fast
+ * Dual-Layer Lossless Coding for Radiance Format High Dynamic Range Images"
+ * (arXiv 2309.11072).
+ *
+ * Plain C99.  No C++ or torch type crosses this boundary and no function
+ * throws.  Every data pointer is a DEVICE pointer unless the comment says
+ * "host"; the caller owns every data buffer.  `stream` is a hipStream_t
+ * passed as void* (NULL = the null stream).  Calls only enqueue work on
+ * `stream` and never synchronise it; an argument error is returned before
+ * anything is enqueued.  One rdl_ctx must not be used from two host threads
+ * or on two streams at the same time.
+ *
+ * Layouts (all row-major, pixel (y, x) at index y*W + x):
+ *   rgbe   uint8 [H][W][4]  R, G, B mantissas then the shared exponent E
+ *                           (Sec. II.A, Fig. 1).  Any 32-bit word is accepted.
+ *   sdr    uint8 [H][W][3]  the base-layer SDR image S exactly as a JPEG
+ *                           decoder returns it (Sec. III.A: "encoded-decoded
+ *                           SDRI").
+ *   resid  7*H*W bytes      int16 r[3][H][W] = M - M* (Eq. 8), then uint8
+ *                           E[H][W]: the enhancement layer's two planes.
+ *   header rdl_header       side information of Sec. III.C: one fixed-point
+ *                           (a_E, b_E) per channel and exponent value.
+ */
+#ifndef RDL_H
+#define RDL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RDL_MAGIC 0x314C4452u /* "RDL1" little-endian */
+#define RDL_VERSION 1u
+
+/* Status codes.  RDL_EHIP: the HIP runtime reported an error (rdl_strerror
+ * then names it).  RDL_ECORRUPT: a header failed validation. */
+enum {
+    RDL_OK = 0,
+    RDL_EINVAL = -1,
+    RDL_EHIP = -2,
+    RDL_ECORRUPT = -3,
+    RDL_ENOMEM = -4,
+    RDL_EUNSUPPORTED = -5
+};
+
+/* Side information (Sec. III.C: each parameter is a 32-bit value; the decoder
+ * reads them and never recomputes them).  a_q has 22 and b_q 14 fractional
+ * bits: a_E = a_q / 2^22, b_E = b_q / 2^14.  Written in device memory by the
+ * encoder so that a whole encode can be captured in a graph.  7232 bytes. */
+typedef struct rdl_header {
+    uint32_t magic;      /* RDL_MAGIC */
+    uint32_t version;    /* RDL_VERSION */
+    int32_t H, W, q;     /* image size and base-layer JPEG quality */
+    int32_t k_img;       /* tone-mapping key: Q = 2^16 k_img + f_key */
+    int32_t f_key;       /* (Q is minus the Q16 mean log2 luminance)  */
+    float sigma;         /* 0.18 * 2^(f_key / 2^16)                    */
+    int64_t lambda_sum;  /* Q16 sum of log2 luminance over lit pixels  */
+    int64_t n_lit;       /* number of pixels with E != 0               */
+    int32_t estimator;   /* 0: SLR in every region; 1: flag[][] chooses */
+    int32_t n_regions;   /* number of exponent values present          */
+    uint64_t model_hash; /* learned estimator in use (0 if none)       */
+    int32_t a_q[3][256]; /* slope per (channel, E), Q22                */
+    int32_t b_q[3][256]; /* intercept per (channel, E), Q14            */
+    uint8_t present[256];  /* 1 if some pixel has exponent E            */
+    uint8_t flag[3][256];  /* 0 = SLR estimate, 1 = learned estimate    */
+} rdl_header;
+
+typedef struct rdl_ctx rdl_ctx;
+
+/* Create a context on HIP device `device`: uploads the frozen tables and
+ * allocates a small scratch area (grown on demand).  Host pointer out. */
+int rdl_create(rdl_ctx **out, int device);
+void rdl_destroy(rdl_ctx *ctx);
+const char *rdl_strerror(int code);
+
+/* Bytes of the residual buffer for an H x W image: 7*H*W. 0 if invalid. */
+size_t rdl_resid_bytes(int H, int W);
+size_t rdl_header_bytes(void);
+
+/* Host-side validation of a header copied to the host: magic, version, size
+ * and parameter bounds (|a_q| <= 255*2^22).  RDL_OK or RDL_ECORRUPT. */
+int rdl_header_validate(const rdl_header *host_hdr, int H, int W);
+
+/* Encoder (Sec. III, Fig. 2 bottom; all four steps on the GPU):
+ *   (a) RGBE unpack + global Reinhard tone mapping to an 8-bit SDRI (Sec. IV);
+ *   (b) JPEG-style 4:4:4 8x8 integer FDCT, quantise (Annex K tables scaled by
+ *       q), dequantise, integer IDCT: out_sdr = S, what Decoder 1 returns;
+ *   (c) S* = GF(S) and, per (channel, E), exact sums of Eq. 9-10, then the
+ *       fixed-point slope and intercept -> out_coeffs;
+ *   (d) out_resid = M - M* with M* = round(a_E S* + b_E) in [0, 255] (Eq. 8).
+ * rgbe: H*W*4 bytes; out_sdr: H*W*3; out_coeffs: one rdl_header; out_resid:
+ * rdl_resid_bytes(H, W).  1 <= H, W; H*W < 2^31; 1 <= q <= 100.  Buffers
+ * must not overlap.  RDL_EINVAL on a bad argument. */
+int rdl_encode_enh(rdl_ctx *ctx, const uint8_t *rgbe, int H, int W, int q, uint8_t *out_sdr,
+                   rdl_header *out_coeffs, void *out_resid, void *stream);
+
+/* Decoder of the enhancement layer (Sec. I: the HDR image is recovered by
+ * adding the residuals; Sec. III.C: parameters are read, not recomputed):
+ * S* = GF(sdr), M = M*(a_E, b_E, S*) + r, out_rgbe = (M, E).  coeffs is a
+ * DEVICE header (as written by rdl_encode_enh).  If status (device int32,
+ * may be NULL) is given it receives RDL_OK, or RDL_ECORRUPT when the header's
+ * magic, version or size do not match or a decoded mantissa leaves [0, 255]. */
+int rdl_decode_enh(rdl_ctx *ctx, const uint8_t *sdr, const rdl_header *coeffs, const void *resid,
+                   int H, int W, uint8_t *out_rgbe, int32_t *status, void *stream);
+
+/* Batched encoder: n images of any sizes and qualities in one pass per stage
+ * (every stage kernel walks a flattened tile space over all images).  imgs is
+ * a HOST array of n descriptors.  The first call for a given set of buffers
+ * captures the stage kernels in a HIP graph; later calls with the same
+ * descriptors replay it.  Each image is encoded exactly as rdl_encode_enh
+ * would encode it. */
+typedef struct rdl_image {
+    const uint8_t *rgbe;
+    int32_t H, W, q;
+    uint8_t *sdr;
+    rdl_header *hdr;
+    void *resid;
+} rdl_image;
+int rdl_encode_batch(rdl_ctx *ctx, const rdl_image *imgs, int n, void *stream);
+
+/* Residual histograms for the zeroth-order-entropy metric: hist int64
+ * [3][511], hist[c][r + 255] counts residual value r of channel c. */
+int rdl_resid_hist(rdl_ctx *ctx, const void *resid, int H, int W, int64_t *hist, void *stream);
+
+/* ---- Stage entry points (each is one step of rdl_encode_enh, for checks) ---- */
+
+/* Key statistic (Sec. IV, Reinhard's operator needs the log-average
+ * luminance): out2 int64[2] = {Lambda, N'}: the Q16 sum of log2 luminance over
+ * pixels with E != 0, and their number. */
+int rdl_stage_keystat(rdl_ctx *ctx, const uint8_t *rgbe, int H, int W, int64_t *out2, void *stream);
+
+/* Tone mapping + base layer from a key statistic (int64[2] from
+ * rdl_stage_keystat).  out_sdr0 (may be NULL) receives the tone-mapped SDRI
+ * before JPEG (H*W*3); out_sdr receives S; out_dct (may be NULL) receives the
+ * quantised coefficients int16 [3][H8][W8] (H8, W8 rounded up to 8). */
+int rdl_stage_tmo_base(rdl_ctx *ctx, const uint8_t *rgbe, int H, int W, int q, const int64_t *keystat,
+                       uint8_t *out_sdr0, uint8_t *out_sdr, int16_t *out_dct, void *stream);
+
+/* Regression fit (Sec. III.B, Eq. 9-10): sums int64 [256][13] per exponent:
+ * {n, then per channel c at 1+4c: sum s, sum m, sum s^2, sum s m} with
+ * s = GF(sdr)_c and m = M_c; then the header's coefficients.  keystat may
+ * be NULL (the header's key fields are then zero). */
+int rdl_stage_fit(rdl_ctx *ctx, const uint8_t *rgbe, const uint8_t *sdr, int H, int W, int q,
+                  const int64_t *keystat, int64_t *out_sums, rdl_header *out_coeffs, void *stream);
+
+/* Residuals from given coefficients (Eq. 8). */
+int rdl_stage_resid(rdl_ctx *ctx, const uint8_t *rgbe, const uint8_t *sdr, const rdl_header *coeffs,
+                    int H, int W, void *out_resid, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RDL_H */

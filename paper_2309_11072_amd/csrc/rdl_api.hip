@@ -1,0 +1,437 @@
+// rdl_api.hip -- host side of the C ABI declared in include/rdl.h.
+//
+// Validates arguments, builds the per-launch image descriptor table, keeps the
+// context's device scratch (key statistic and regression sums per image) and
+// enqueues the stage kernels on the caller's stream.  Nothing here computes
+// any part of the encoding: every step runs in the kernels of
+// rdl_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "rdl_internal.h"
+
+using namespace rdl;
+
+struct GraphEntry {
+    std::vector<ImgDesc> key;  // descriptors the graph was captured for
+    ImgDesc *d_desc = nullptr;
+    int64_t *d_scratch = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+struct rdl_ctx {
+    int device = 0;
+    // scratch for direct (uncaptured) launches
+    ImgDesc *d_desc = nullptr;
+    size_t desc_cap = 0;
+    int64_t *d_scratch = nullptr;
+    size_t scratch_cap = 0;  // images
+    std::vector<GraphEntry> graphs;  // captured encoders, oldest first
+    std::vector<ImgDesc> last_key;   // descriptors of the last direct launch
+};
+
+namespace {
+
+thread_local char g_err[256] = "";
+constexpr size_t kMaxGraphs = 8;
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int hip_fail(hipError_t e, const char *where) {
+    snprintf(g_err, sizeof g_err, "%s: %s", where, hipGetErrorString(e));
+    return RDL_EHIP;
+}
+
+#define HIPCHK(expr)                                   \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+    } while (0)
+
+bool size_ok(int H, int W) { return H >= 1 && W >= 1 && (int64_t)H * W < ((int64_t)1 << 31); }
+
+bool aligned4(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 3) == 0; }
+
+int ensure_desc(rdl_ctx *c, size_t n) {
+    if (n <= c->desc_cap) return RDL_OK;
+    if (c->d_desc) HIPCHK(hipFree(c->d_desc));
+    c->d_desc = nullptr;
+    c->desc_cap = 0;
+    HIPCHK(hipMalloc(&c->d_desc, n * sizeof(ImgDesc)));
+    c->desc_cap = n;
+    return RDL_OK;
+}
+
+int ensure_scratch(rdl_ctx *c, size_t n) {
+    if (n <= c->scratch_cap) return RDL_OK;
+    if (c->d_scratch) HIPCHK(hipFree(c->d_scratch));
+    c->d_scratch = nullptr;
+    c->scratch_cap = 0;
+    HIPCHK(hipMalloc(&c->d_scratch, n * SCRATCH_I64 * sizeof(int64_t)));
+    c->scratch_cap = n;
+    return RDL_OK;
+}
+
+// Assign each image its first workgroup per kernel family.
+void layout(std::vector<ImgDesc> &v, int &npx, int &nblk, int &ntile) {
+    npx = nblk = ntile = 0;
+    for (auto &d : v) {
+        d.wg_px = npx;
+        d.wg_blk = nblk;
+        d.wg_tile = ntile;
+        npx += wgs_px(d.H, d.W);
+        nblk += wgs_blk(d.H, d.W);
+        ntile += wgs_tile(d.H, d.W);
+    }
+}
+
+int upload(rdl_ctx *c, const std::vector<ImgDesc> &v, hipStream_t s) {
+    int rc = ensure_desc(c, v.size());
+    if (rc) return rc;
+    // Pageable source: the runtime stages it before returning, so the vector
+    // may be reused as soon as this call returns.
+    HIPCHK(hipMemcpyAsync(c->d_desc, v.data(), v.size() * sizeof(ImgDesc), hipMemcpyHostToDevice, s));
+    return RDL_OK;
+}
+
+int check_launch(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, what);
+    return RDL_OK;
+}
+
+// Enqueue the full encoder for the images of d (device table) on s.
+void enqueue_encode(const ImgDesc *d, int n, int wpx, int wblk, int wtile, hipStream_t s) {
+    launch_zero(d, n, s);
+    launch_keystat(d, n, wpx, s);
+    launch_tmo_base(d, n, wblk, s);
+    launch_fit_sums(d, n, wtile, s);
+    launch_solve(d, n, s);
+    launch_resid(d, n, wtile, s);
+}
+
+ImgDesc blank() {
+    ImgDesc d;
+    memset(&d, 0, sizeof d);
+    return d;
+}
+
+bool same_key(const std::vector<ImgDesc> &a, const std::vector<ImgDesc> &b) {
+    return a.size() == b.size() && memcmp(a.data(), b.data(), a.size() * sizeof(ImgDesc)) == 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *rdl_strerror(int code) {
+    switch (code) {
+        case RDL_OK: return "ok";
+        case RDL_EINVAL: return "invalid argument";
+        case RDL_EHIP: return g_err[0] ? g_err : "HIP runtime error";
+        case RDL_ECORRUPT: return "corrupt header or stream";
+        case RDL_ENOMEM: return "out of memory";
+        case RDL_EUNSUPPORTED: return "unsupported";
+        default: return "unknown error";
+    }
+}
+
+size_t rdl_resid_bytes(int H, int W) { return size_ok(H, W) ? (size_t)7 * H * W : 0; }
+size_t rdl_header_bytes(void) { return sizeof(rdl_header); }
+
+int rdl_create(rdl_ctx **out, int device) {
+    if (!out) return RDL_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return RDL_EINVAL;
+    DeviceGuard g(device);
+    int bad = 0;
+    HIPCHK(upload_tables(&bad));
+    if (bad) {
+        snprintf(g_err, sizeof g_err, "gamma bucket table violates its one-threshold-per-bucket bound");
+        return RDL_EUNSUPPORTED;
+    }
+    rdl_ctx *c = new (std::nothrow) rdl_ctx();
+    if (!c) return RDL_ENOMEM;
+    c->device = device;
+    *out = c;
+    return RDL_OK;
+}
+
+void rdl_destroy(rdl_ctx *c) {
+    if (!c) return;
+    DeviceGuard g(c->device);
+    for (auto &e : c->graphs) {
+        if (e.exec) (void)hipGraphExecDestroy(e.exec);
+        if (e.d_desc) (void)hipFree(e.d_desc);
+        if (e.d_scratch) (void)hipFree(e.d_scratch);
+    }
+    if (c->d_desc) (void)hipFree(c->d_desc);
+    if (c->d_scratch) (void)hipFree(c->d_scratch);
+    delete c;
+}
+
+int rdl_header_validate(const rdl_header *h, int H, int W) {
+    if (!h) return RDL_EINVAL;
+    if (h->magic != RDL_MAGIC || h->version != RDL_VERSION || h->H != H || h->W != W) return RDL_ECORRUPT;
+    if (h->q < 1 || h->q > 100 || h->estimator < 0 || h->estimator > 1) return RDL_ECORRUPT;
+    const int64_t amax = (int64_t)255 << 22;
+    for (int c = 0; c < 3; ++c)
+        for (int e = 0; e < 256; ++e) {
+            if (h->a_q[c][e] > amax || h->a_q[c][e] < -amax) return RDL_ECORRUPT;
+            if (!h->present[e] && (h->a_q[c][e] || h->b_q[c][e])) return RDL_ECORRUPT;
+            if (h->flag[c][e] > 1) return RDL_ECORRUPT;
+        }
+    return RDL_OK;
+}
+
+int rdl_encode_enh(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int q, uint8_t *out_sdr, rdl_header *out_coeffs,
+                   void *out_resid, void *stream) {
+    rdl_image im;
+    im.rgbe = rgbe;
+    im.H = H;
+    im.W = W;
+    im.q = q;
+    im.sdr = out_sdr;
+    im.hdr = out_coeffs;
+    im.resid = out_resid;
+    return rdl_encode_batch(c, &im, 1, stream);
+}
+
+int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
+    if (!c || !imgs || n < 1) return RDL_EINVAL;
+    for (int k = 0; k < n; ++k) {
+        const rdl_image &m = imgs[k];
+        if (!m.rgbe || !m.sdr || !m.hdr || !m.resid) return RDL_EINVAL;
+        if (!size_ok(m.H, m.W) || m.q < 1 || m.q > 100) return RDL_EINVAL;
+        if (!aligned4(m.rgbe) || !aligned4(m.hdr) || (reinterpret_cast<uintptr_t>(m.resid) & 1)) return RDL_EINVAL;
+    }
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<ImgDesc> v(n, blank());
+    for (int k = 0; k < n; ++k) {
+        ImgDesc &d = v[k];
+        d.rgbe = imgs[k].rgbe;
+        d.sdr = imgs[k].sdr;
+        d.hdr = imgs[k].hdr;
+        d.resid = (uint8_t *)imgs[k].resid;
+        d.H = imgs[k].H;
+        d.W = imgs[k].W;
+        d.q = imgs[k].q;
+        d.flags = F_ZERO_KS | F_ZERO_SUMS;
+    }
+    int wpx, wblk, wtile;
+    layout(v, wpx, wblk, wtile);
+
+    // Replay a graph captured earlier for exactly these descriptors.
+    for (auto &e : c->graphs)
+        if (same_key(e.key, v)) {
+            HIPCHK(hipGraphLaunch(e.exec, s));
+            return RDL_OK;
+        }
+
+    if (!same_key(c->last_key, v)) {
+        // First sight of these buffers: launch directly from the context's
+        // own table and scratch.
+        c->last_key = v;
+        int rc = ensure_scratch(c, n);
+        if (rc) return rc;
+        std::vector<ImgDesc> dv = v;
+        for (int k = 0; k < n; ++k) {
+            dv[k].ks = c->d_scratch + (size_t)k * SCRATCH_I64;
+            dv[k].sums = dv[k].ks + 2;
+        }
+        rc = upload(c, dv, s);
+        if (rc) return rc;
+        enqueue_encode(c->d_desc, n, wpx, wblk, wtile, s);
+        return check_launch("encoder kernels");
+    }
+
+    // Second call with the same buffers: capture the stage kernels once, with
+    // a table and scratch of their own, and replay the graph from now on.
+    if (c->graphs.size() >= kMaxGraphs) {
+        HIPCHK(hipStreamSynchronize(s));
+        GraphEntry &old = c->graphs.front();
+        (void)hipGraphExecDestroy(old.exec);
+        (void)hipFree(old.d_desc);
+        (void)hipFree(old.d_scratch);
+        c->graphs.erase(c->graphs.begin());
+    }
+    GraphEntry e;
+    e.key = v;
+    HIPCHK(hipMalloc(&e.d_scratch, (size_t)n * SCRATCH_I64 * sizeof(int64_t)));
+    std::vector<ImgDesc> dv = v;
+    for (int k = 0; k < n; ++k) {
+        dv[k].ks = e.d_scratch + (size_t)k * SCRATCH_I64;
+        dv[k].sums = dv[k].ks + 2;
+    }
+    HIPCHK(hipMalloc(&e.d_desc, (size_t)n * sizeof(ImgDesc)));
+    HIPCHK(hipMemcpy(e.d_desc, dv.data(), (size_t)n * sizeof(ImgDesc), hipMemcpyHostToDevice));
+    hipStream_t cs;
+    HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t graph;
+    hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (err == hipSuccess) {
+        enqueue_encode(e.d_desc, n, wpx, wblk, wtile, cs);
+        err = hipStreamEndCapture(cs, &graph);
+    }
+    if (err == hipSuccess) {
+        err = hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+    }
+    (void)hipStreamDestroy(cs);
+    if (err != hipSuccess) {
+        (void)hipFree(e.d_desc);
+        (void)hipFree(e.d_scratch);
+        return hip_fail(err, "graph capture of the encoder");
+    }
+    HIPCHK(hipGraphLaunch(e.exec, s));
+    c->graphs.push_back(std::move(e));
+    return RDL_OK;
+}
+
+int rdl_decode_enh(rdl_ctx *c, const uint8_t *sdr, const rdl_header *coeffs, const void *resid, int H, int W,
+                   uint8_t *out_rgbe, int32_t *status, void *stream) {
+    if (!c || !sdr || !coeffs || !resid || !out_rgbe || !size_ok(H, W)) return RDL_EINVAL;
+    if (!aligned4(out_rgbe) || !aligned4(coeffs) || (reinterpret_cast<uintptr_t>(resid) & 1)) return RDL_EINVAL;
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<ImgDesc> v(1, blank());
+    v[0].sdr = (uint8_t *)sdr;
+    v[0].hdr = (rdl_header *)coeffs;
+    v[0].resid = (uint8_t *)resid;
+    v[0].out_rgbe = out_rgbe;
+    v[0].status = status;
+    v[0].H = H;
+    v[0].W = W;
+    int wpx, wblk, wtile;
+    layout(v, wpx, wblk, wtile);
+    int rc = upload(c, v, s);
+    if (rc) return rc;
+    launch_decode(c->d_desc, 1, wtile, s);
+    return check_launch("k_decode");
+}
+
+int rdl_resid_hist(rdl_ctx *c, const void *resid, int H, int W, int64_t *hist, void *stream) {
+    if (!c || !resid || !hist || !size_ok(H, W)) return RDL_EINVAL;
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<ImgDesc> v(1, blank());
+    v[0].resid = (uint8_t *)resid;
+    v[0].hist = hist;
+    v[0].H = H;
+    v[0].W = W;
+    v[0].flags = F_ZERO_HIST;
+    int wpx, wblk, wtile;
+    layout(v, wpx, wblk, wtile);
+    int rc = upload(c, v, s);
+    if (rc) return rc;
+    launch_zero(c->d_desc, 1, s);
+    launch_hist(c->d_desc, 1, wtile, s);
+    return check_launch("k_hist");
+}
+
+int rdl_stage_keystat(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int64_t *out2, void *stream) {
+    if (!c || !rgbe || !out2 || !size_ok(H, W) || !aligned4(rgbe)) return RDL_EINVAL;
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<ImgDesc> v(1, blank());
+    v[0].rgbe = rgbe;
+    v[0].ks = out2;
+    v[0].H = H;
+    v[0].W = W;
+    v[0].flags = F_ZERO_KS;
+    int wpx, wblk, wtile;
+    layout(v, wpx, wblk, wtile);
+    int rc = upload(c, v, s);
+    if (rc) return rc;
+    launch_zero(c->d_desc, 1, s);
+    launch_keystat(c->d_desc, 1, wpx, s);
+    return check_launch("k_keystat");
+}
+
+int rdl_stage_tmo_base(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int q, const int64_t *keystat, uint8_t *out_sdr0,
+                       uint8_t *out_sdr, int16_t *out_dct, void *stream) {
+    if (!c || !rgbe || !keystat || !out_sdr || !size_ok(H, W) || q < 1 || q > 100 || !aligned4(rgbe)) return RDL_EINVAL;
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<ImgDesc> v(1, blank());
+    v[0].rgbe = rgbe;
+    v[0].ks = (int64_t *)keystat;
+    v[0].sdr0 = out_sdr0;
+    v[0].sdr = out_sdr;
+    v[0].dct = out_dct;
+    v[0].H = H;
+    v[0].W = W;
+    v[0].q = q;
+    int wpx, wblk, wtile;
+    layout(v, wpx, wblk, wtile);
+    int rc = upload(c, v, s);
+    if (rc) return rc;
+    launch_tmo_base(c->d_desc, 1, wblk, s);
+    return check_launch("k_tmo_base");
+}
+
+int rdl_stage_fit(rdl_ctx *c, const uint8_t *rgbe, const uint8_t *sdr, int H, int W, int q, const int64_t *keystat,
+                  int64_t *out_sums, rdl_header *out_coeffs, void *stream) {
+    if (!c || !rgbe || !sdr || !out_sums || !out_coeffs || !size_ok(H, W) || q < 1 || q > 100) return RDL_EINVAL;
+    if (!aligned4(rgbe) || !aligned4(out_coeffs)) return RDL_EINVAL;
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<ImgDesc> v(1, blank());
+    v[0].rgbe = rgbe;
+    v[0].sdr = (uint8_t *)sdr;
+    v[0].ks = (int64_t *)keystat;
+    v[0].sums = out_sums;
+    v[0].hdr = out_coeffs;
+    v[0].H = H;
+    v[0].W = W;
+    v[0].q = q;
+    v[0].flags = F_ZERO_SUMS;
+    int wpx, wblk, wtile;
+    layout(v, wpx, wblk, wtile);
+    int rc = upload(c, v, s);
+    if (rc) return rc;
+    launch_zero(c->d_desc, 1, s);
+    launch_fit_sums(c->d_desc, 1, wtile, s);
+    launch_solve(c->d_desc, 1, s);
+    return check_launch("k_fit_sums/k_solve");
+}
+
+int rdl_stage_resid(rdl_ctx *c, const uint8_t *rgbe, const uint8_t *sdr, const rdl_header *coeffs, int H, int W,
+                    void *out_resid, void *stream) {
+    if (!c || !rgbe || !sdr || !coeffs || !out_resid || !size_ok(H, W)) return RDL_EINVAL;
+    if (!aligned4(rgbe) || !aligned4(coeffs) || (reinterpret_cast<uintptr_t>(out_resid) & 1)) return RDL_EINVAL;
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<ImgDesc> v(1, blank());
+    v[0].rgbe = rgbe;
+    v[0].sdr = (uint8_t *)sdr;
+    v[0].hdr = (rdl_header *)coeffs;
+    v[0].resid = (uint8_t *)out_resid;
+    v[0].H = H;
+    v[0].W = W;
+    int wpx, wblk, wtile;
+    layout(v, wpx, wblk, wtile);
+    int rc = upload(c, v, s);
+    if (rc) return rc;
+    launch_resid(c->d_desc, 1, wtile, s);
+    return check_launch("k_resid");
+}
+
+}  // extern "C"

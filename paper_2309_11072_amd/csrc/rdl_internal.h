@@ -1,0 +1,61 @@
+// rdl_internal.h -- shared between the HIP kernels and the host C-ABI layer
+// of the MI355X encoder (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rdl.h"
+
+namespace rdl {
+
+// Work decomposition, fixed for every stage kernel.
+constexpr int KS_THREADS = 256;    // key statistic: 256 lanes x 16 px
+constexpr int KS_PX_PER_WG = 4096;
+constexpr int BLK_WG = 32;        // tone map + base layer: 32 blocks of one block row,
+constexpr int BLK_THREADS = 256;   //   8 lanes per block
+constexpr int TILE_H = 16;         // GF-based stages: 16 x 128 px tiles,
+constexpr int TILE_W = 128;        //   256 lanes x 8 consecutive px
+constexpr int TILE_THREADS = 256;
+constexpr int RUN = 8;
+constexpr int NSUM = 13;           // n, then (sum s, sum m, sum s^2, sum s m) x 3
+constexpr int SCRATCH_I64 = 2 + 256 * NSUM + 6;  // per image, padded to 64 B
+constexpr int GAMMA_LUT_N = 21 * 128;             // float-bit buckets 2^-20 .. 2^1
+
+// One image of a launch.  Every kernel walks a flattened workgroup space over
+// all images of the launch; wg_* is this image's first workgroup.
+struct ImgDesc {
+    const uint8_t *rgbe;   // [H][W][4]
+    uint8_t *sdr0;         // optional [H][W][3] tone-mapped SDRI
+    uint8_t *sdr;          // [H][W][3]
+    int16_t *dct;          // optional [3][H8][W8]
+    rdl_header *hdr;
+    uint8_t *resid;        // 7*H*W
+    int64_t *ks;           // [2] Lambda, N'
+    int64_t *sums;         // [256][13]
+    int32_t *status;       // decode only, optional
+    uint8_t *out_rgbe;     // decode only
+    int64_t *hist;         // [3][511] residual histograms
+    int32_t H, W, q, flags;
+    int32_t wg_px, wg_blk, wg_tile, pad;
+};
+
+enum : int32_t { F_ZERO_KS = 1, F_ZERO_SUMS = 2, F_ZERO_HIST = 4 };
+
+inline int wgs_px(int H, int W) { return (int)(((int64_t)H * W + KS_PX_PER_WG - 1) / KS_PX_PER_WG); }
+inline int wgs_blk(int H, int W) { return ((H + 7) / 8) * (((W + 7) / 8 + BLK_WG - 1) / BLK_WG); }
+inline int wgs_tile(int H, int W) { return ((H + TILE_H - 1) / TILE_H) * ((W + TILE_W - 1) / TILE_W); }
+
+// Kernel launchers (defined in rdl_kernels.hip).
+hipError_t upload_tables(int *bad_table);
+const uint8_t *dev_gamma_lut();
+const float *dev_gamma_thr();
+void launch_zero(const ImgDesc *d, int n, hipStream_t s);
+void launch_keystat(const ImgDesc *d, int n, int wgs, hipStream_t s);
+void launch_tmo_base(const ImgDesc *d, int n, int wgs, hipStream_t s);
+void launch_fit_sums(const ImgDesc *d, int n, int wgs, hipStream_t s);
+void launch_solve(const ImgDesc *d, int n, hipStream_t s);
+void launch_resid(const ImgDesc *d, int n, int wgs, hipStream_t s);
+void launch_decode(const ImgDesc *d, int n, int wgs, hipStream_t s);
+void launch_hist(const ImgDesc *d, int n, int wgs, hipStream_t s);
+
+}  // namespace rdl

@@ -1,0 +1,852 @@
+// rdl_kernels.hip -- gfx950 kernels of the dual-layer lossless Radiance
+// encoder (Suzuki et al., arXiv 2309.11072) and of its enhancement-layer
+// decoder.
+//
+// Every stage is exact integer arithmetic except the tone-mapping operator,
+// which is FP32 with a fixed operation order: the file is built with
+// -ffp-contract=off (and says so again below), divisions are correctly
+// rounded, and no transcendental function is evaluated per pixel -- the
+// logarithm and the exponentials come from frozen tables.  Integer sums are
+// accumulated with integer atomics, so results do not depend on scheduling.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "rdl_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace rdl {
+
+typedef short short2v __attribute__((ext_vector_type(2)));
+
+// ---------------------------------------------------------------------------
+// Frozen tables (filled once per device by upload_tables()).
+// ---------------------------------------------------------------------------
+__device__ int32_t g_log2f[4096];   // round(2^16 log2(1 + (i + 0.5)/4096))
+__device__ float g_exp2h[256];      // fl32(2^(j/256))
+__device__ float g_exp2l[256];      // fl32(2^(j/65536))
+__device__ float g_thr[257];        // [k] = fl32(((k - 0.5)/255)^2.2), [256] = +inf
+__device__ uint8_t g_glut[GAMMA_LUT_N];  // #{k : thr[k] <= bucket start}
+
+// ITU-T T.81 Annex K, Tables K.1 and K.2 (natural order).
+__constant__ int c_annex_k[2][64] = {
+    {16, 11, 10, 16, 24, 40, 51, 61,     12, 12, 14, 19, 26, 58, 60, 55,
+     14, 13, 16, 24, 40, 57, 69, 56,     14, 17, 22, 29, 51, 87, 80, 62,
+     18, 22, 37, 56, 68, 109, 103, 77,   24, 35, 55, 64, 81, 104, 113, 92,
+     49, 64, 78, 87, 103, 121, 120, 101, 72, 92, 95, 98, 112, 100, 103, 99},
+    {17, 18, 24, 47, 99, 99, 99, 99, 18, 21, 26, 66, 99, 99, 99, 99,
+     24, 26, 56, 99, 99, 99, 99, 99, 47, 66, 99, 99, 99, 99, 99, 99,
+     99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99,
+     99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99}};
+
+// DCT basis K[u][x] = round(2^13 c_u cos((2x+1) u pi / 16)), c_0 = 1/sqrt(8),
+// c_u = 1/2: the 8-point DCT-II scaled by 2^13.
+constexpr int KD[8][8] = {
+    {2896, 2896, 2896, 2896, 2896, 2896, 2896, 2896},
+    {4017, 3406, 2276, 799, -799, -2276, -3406, -4017},
+    {3784, 1567, -1567, -3784, -3784, -1567, 1567, 3784},
+    {3406, -799, -4017, -2276, 2276, 4017, 799, -3406},
+    {2896, -2896, -2896, 2896, 2896, -2896, -2896, 2896},
+    {2276, -4017, 799, 3406, -3406, -799, 4017, -2276},
+    {1567, -3784, 3784, -1567, -1567, 3784, -3784, 1567},
+    {799, -2276, 3406, -4017, 4017, -3406, 2276, -799}};
+
+__host__ __device__ constexpr int pk16(int lo, int hi) {
+    return (int)(((unsigned)lo & 0xffffu) | ((unsigned)hi << 16));
+}
+
+__device__ __forceinline__ int dot2(int a, int b, int c) {
+    return __builtin_amdgcn_sdot2(__builtin_bit_cast(short2v, a), __builtin_bit_cast(short2v, b), c, false);
+}
+__device__ __forceinline__ int pack_i16(int lo, int hi) {
+    return __builtin_bit_cast(int, __builtin_amdgcn_cvt_pk_i16(lo, hi));
+}
+
+// ---------------------------------------------------------------------------
+// Helpers shared by the kernels of this file.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Image of workgroup `wg`: the last image whose first workgroup is <= wg.
+__device__ __forceinline__ int find_img(const ImgDesc *__restrict__ D, int n, int wg, int which) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        int w = which == 0 ? D[mid].wg_px : (which == 1 ? D[mid].wg_blk : D[mid].wg_tile);
+        if (w <= wg) lo = mid; else hi = mid - 1;
+    }
+    return uniform(lo);
+}
+
+__device__ __forceinline__ int64_t floor_div64(int64_t a, int64_t b) {  // b > 0
+    int64_t q = a / b;
+    if ((a % b) != 0 && a < 0) q -= 1;
+    return q;
+}
+
+// Key of the global Reinhard operator: Q = floor(-Lambda / N') =
+// 2^16 k_img + f, sigma = (0.18 * 2^(f>>8 / 256)) * 2^((f&255)/65536).
+__device__ void key_params(const int64_t *ks, int &k_img, int &f_key, float &sigma, int64_t &L, int64_t &N) {
+    L = ks[0];
+    N = ks[1];
+    if (N <= 0) { k_img = 0; f_key = 0; sigma = 0.0f; return; }
+    int64_t Q = floor_div64(-L, N);
+    int64_t k = Q >> 16;
+    int f = (int)(Q - k * 65536);
+    float s = 0.18f * g_exp2h[f >> 8];
+    s = s * g_exp2l[f & 255];
+    k_img = (int)k;
+    f_key = f;
+    sigma = s;
+}
+
+__device__ __forceinline__ uint32_t lum_y(uint32_t w) {
+    return 13933u * (w & 255u) + 46871u * ((w >> 8) & 255u) + 4732u * ((w >> 16) & 255u) + 32768u;
+}
+
+// ---------------------------------------------------------------------------
+// K0 zero: clear the per-image accumulators of a launch.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_zero(const ImgDesc *__restrict__ D, int n) {
+    const int i = blockIdx.x;
+    if (i >= n) return;
+    const ImgDesc d = D[i];
+    if ((d.flags & F_ZERO_KS) && d.ks && threadIdx.x < 2) d.ks[threadIdx.x] = 0;
+    if ((d.flags & F_ZERO_SUMS) && d.sums)
+        for (int k = threadIdx.x; k < 256 * NSUM; k += 256) d.sums[k] = 0;
+    if ((d.flags & F_ZERO_HIST) && d.hist)
+        for (int k = threadIdx.x; k < 3 * 511; k += 256) d.hist[k] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// K1 key statistic: Lambda = sum over E != 0 of 2^16 (E - 136) + lambda(Y),
+// N' = #{E != 0}.  lambda(Y) = 2^16 (floor(log2 Y) - 16) + LOG2F[12 bits of Y
+// after its leading one].  Memory bound: 4 B/px, 128-bit loads.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t lambda_px(uint32_t w, const int32_t *s_log2f) {
+    uint32_t E = w >> 24;
+    uint32_t Y = lum_y(w);
+    int p = 31 - __builtin_clz(Y);
+    int idx = (int)((Y >> (p - 12)) & 4095u);
+    int v = 65536 * (p - 16 + (int)E - 136) + s_log2f[idx];
+    return E ? (int64_t)v : 0;
+}
+
+__global__ __launch_bounds__(KS_THREADS) void k_keystat(const ImgDesc *__restrict__ D, int n) {
+    __shared__ int32_t s_log2f[4096];
+    __shared__ int64_t s_red[2][KS_THREADS / 64];
+    for (int k = threadIdx.x; k < 4096; k += KS_THREADS) s_log2f[k] = g_log2f[k];
+    const int i = find_img(D, n, blockIdx.x, 0);
+    const ImgDesc &d = D[i];
+    const int64_t npx = (int64_t)d.H * d.W;
+    const int64_t base = (int64_t)(blockIdx.x - d.wg_px) * KS_PX_PER_WG;
+    __syncthreads();
+    int64_t L = 0;
+    int cnt = 0;
+    const uint32_t *p32 = (const uint32_t *)d.rgbe;
+#pragma unroll
+    for (int it = 0; it < KS_PX_PER_WG / (KS_THREADS * 4); ++it) {
+        int64_t px = base + (int64_t)(it * KS_THREADS + threadIdx.x) * 4;
+        uint32_t w[4];
+        if (px + 4 <= npx && ((reinterpret_cast<uintptr_t>(p32 + px) & 15) == 0)) {
+            uint4 v = *reinterpret_cast<const uint4 *>(p32 + px);
+            w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) w[j] = (px + j < npx) ? p32[px + j] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            L += lambda_px(w[j], s_log2f);
+            cnt += (w[j] >> 24) != 0;
+        }
+    }
+    // wave reduction then one atomic per workgroup (integer: order-free)
+    for (int off = 32; off > 0; off >>= 1) {
+        L += __shfl_down(L, off, 64);
+        cnt += __shfl_down(cnt, off, 64);
+    }
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { s_red[0][wv] = L; s_red[1][wv] = cnt; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t a = 0, b = 0;
+        for (int k = 0; k < KS_THREADS / 64; ++k) { a += s_red[0][k]; b += s_red[1][k]; }
+        atomicAdd((unsigned long long *)&d.ks[0], (unsigned long long)a);
+        atomicAdd((unsigned long long *)&d.ks[1], (unsigned long long)b);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K2 tone mapping + base layer, per 8x8 block:
+//   RGBE -> TMO (FP32) -> 8-bit codes -> JFIF YCbCr -> FDCT (row, column)
+//   -> quantise / dequantise -> IDCT (column, row) -> RGB -> S.
+// Both 1-D transforms use the even/odd split of the DCT basis
+// (K[u][7-x] = (-1)^u K[u][x]) on int16 pairs with v_dot2_i32_i16; this is an
+// exact refactoring of the sums, so the results equal the plain matrix form.
+// ---------------------------------------------------------------------------
+// code = #{k : thr[k] <= C}: the float's bucket (exponent + 7 mantissa bits)
+// gives the count at the bucket start, and at most one threshold lies inside
+// a bucket (checked on the host when the table is built).
+__device__ __forceinline__ int gamma_code(float C, const uint8_t *lut, const float *thr) {
+    int idx = (int)(__float_as_uint(C) >> 16) - ((127 - 20) << 7);
+    idx = min(max(idx, 0), GAMMA_LUT_N - 1);
+    int c0 = lut[idx];
+    return c0 + (C >= thr[c0 + 1] ? 1 : 0);
+}
+
+// Global Reinhard operator, hue preserving, per pixel.  P = sigma 2^k',
+// k' = k_img + E - 136 (clamped at 40: the 1 in 1 + t is then absorbed and the
+// result is exactly the clamped one); t = P * Y * 2^-16, D = 1 + t, R = 1/D,
+// C_c = (P * (M_c + 0.5)) * R.
+__device__ __forceinline__ void tmo_px(uint32_t w, int kbase, float sigma, bool any_lit, const uint8_t *lut,
+                                       const float *thr, int &r, int &g, int &b) {
+    const int E = (int)(w >> 24);
+    int kp = kbase + E;
+    const bool zero = (E == 0) | (kp < -64) | !any_lit;
+    kp = min(kp, 40);
+    const float P = ldexpf(sigma, kp);
+    const float Pl = ldexpf(sigma, kp - 16);
+    const float t = Pl * (float)lum_y(w);
+    const float Dn = 1.0f + t;
+    const float R = 1.0f / Dn;
+    const float c0 = (P * ((float)(w & 255u) + 0.5f)) * R;
+    const float c1 = (P * ((float)((w >> 8) & 255u) + 0.5f)) * R;
+    const float c2 = (P * ((float)((w >> 16) & 255u) + 0.5f)) * R;
+    r = zero ? 0 : gamma_code(c0, lut, thr);
+    g = zero ? 0 : gamma_code(c1, lut, thr);
+    b = zero ? 0 : gamma_code(c2, lut, thr);
+}
+
+__device__ __forceinline__ void rgb_to_ycc(int R, int G, int B, int &Y, int &Cb, int &Cr) {
+    Y = (19595 * R + 38470 * G + 7471 * B + 32768) >> 16;
+    Cb = (-11058 * R - 21710 * G + 32768 * B + 8388608 + 32768) >> 16;
+    Cr = (32768 * R - 27439 * G - 5329 * B + 8388608 + 32768) >> 16;
+}
+
+__device__ __forceinline__ void ycc_to_rgb(int Y, int Cb, int Cr, int &R, int &G, int &B) {
+    const int cb = Cb - 128, cr = Cr - 128;
+    R = min(max(Y + ((91881 * cr + 32768) >> 16), 0), 255);
+    G = min(max(Y + ((-22554 * cb - 46802 * cr + 32768) >> 16), 0), 255);
+    B = min(max(Y + ((116130 * cb + 32768) >> 16), 0), 255);
+}
+
+__device__ __forceinline__ int padd(int a, int b) {
+    return __builtin_bit_cast(int, __builtin_bit_cast(short2v, a) + __builtin_bit_cast(short2v, b));
+}
+__device__ __forceinline__ int psub(int a, int b) {
+    return __builtin_bit_cast(int, __builtin_bit_cast(short2v, a) - __builtin_bit_cast(short2v, b));
+}
+// Forward even/odd pairs: KF(u, 0) = (K[u][0], K[u][1]), KF(u, 1) = (K[u][2], K[u][3]).
+__device__ __forceinline__ int KF(int u, int h) { return pk16(KD[u][2 * h], KD[u][2 * h + 1]); }
+// Inverse pairs over the frequency index: KI(y, parity, h) =
+// (K[4h + parity][y], K[4h + parity + 2][y]).
+__device__ __forceinline__ int KI(int y, int par, int h) {
+    return pk16(KD[4 * h + par][y], KD[4 * h + par + 2][y]);
+}
+
+// 1-D forward transform of 8 samples given as the even/odd pairs
+// S01 = (x0+x7, x1+x6), S23 = (x2+x5, x3+x4), D01, D23 (differences):
+// out[u] = sum_x K[u][x] x_x + bias.
+__device__ __forceinline__ void fdct1(int S01, int S23, int D01, int D23, int bias, int out[8]) {
+#pragma unroll
+    for (int u = 0; u < 8; u += 2) out[u] = dot2(KF(u, 0), S01, dot2(KF(u, 1), S23, bias));
+#pragma unroll
+    for (int u = 1; u < 8; u += 2) out[u] = dot2(KF(u, 0), D01, dot2(KF(u, 1), D23, bias));
+}
+
+// 1-D inverse transform of 8 coefficients given as pairs E0 = (c0, c2),
+// E1 = (c4, c6), O0 = (c1, c3), O1 = (c5, c7): out[y] = sum_v K[v][y] c_v + bias.
+__device__ __forceinline__ void idct1(int E0, int E1, int O0, int O1, int bias, int out[8]) {
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+        const int e = dot2(KI(y, 0, 0), E0, dot2(KI(y, 0, 1), E1, bias));
+        const int o = dot2(KI(y, 1, 0), O0, dot2(KI(y, 1, 1), O1, 0));
+        out[y] = e + o;
+        out[7 - y] = e - o;
+    }
+}
+
+__global__ __launch_bounds__(BLK_THREADS) void k_tmo_base(const ImgDesc *__restrict__ D, int n) {
+    // A workgroup owns a strip of BLK_WG horizontally adjacent 8x8 blocks of
+    // one block row.  Lane t works on block j = t % BLK_WG as its row (phases
+    // 1 and 3) or column (phase 2) r = t / BLK_WG; two LDS transposes join the
+    // phases.  Slot stride 33 words keeps every half-wave access conflict-free.
+    __shared__ uint8_t s_lut[GAMMA_LUT_N];
+    __shared__ float s_thr[257];
+    __shared__ uint32_t s_QM[2][64];  // ceil(2^20 / Q) | Q << 24
+    __shared__ uint32_t s_X[3][BLK_WG][33];
+    const int i = find_img(D, n, blockIdx.x, 1);
+    const ImgDesc &d = D[i];
+    const int H = d.H, W = d.W;
+    for (int k = threadIdx.x; k < GAMMA_LUT_N; k += BLK_THREADS) s_lut[k] = g_glut[k];
+    for (int k = threadIdx.x; k < 257; k += BLK_THREADS) s_thr[k] = g_thr[k];
+    if (threadIdx.x < 128) {
+        // IJG quality scaling of the Annex K tables, and a 20-bit reciprocal
+        // per entry: floor(a / Q) == (a * ceil(2^20 / Q)) >> 20 for a < 4096.
+        const int t = threadIdx.x >> 6, e = threadIdx.x & 63;
+        const int q = d.q;
+        const int s = q < 50 ? 5000 / q : 200 - 2 * q;
+        int Qv = (c_annex_k[t][e] * s + 50) / 100;
+        Qv = min(max(Qv, 1), 255);
+        s_QM[t][e] = (((1u << 20) + (uint32_t)Qv - 1u) / (uint32_t)Qv) | ((uint32_t)Qv << 24);
+    }
+    int k_img, f_key;
+    float sigma;
+    int64_t L, N;
+    key_params(d.ks, k_img, f_key, sigma, L, N);
+    const int kbase = k_img - 136;
+    const bool any_lit = N > 0;
+
+    const int nbx = (W + 7) >> 3, nby = (H + 7) >> 3;
+    const int nstrip = (nbx + BLK_WG - 1) / BLK_WG;
+    const int wgi = blockIdx.x - d.wg_blk;
+    const int by = wgi / nstrip;
+    const int j = threadIdx.x % BLK_WG, r = threadIdx.x / BLK_WG;
+    const int bx = (wgi - by * nstrip) * BLK_WG + j;
+    const bool active = bx < nbx && by < nby;
+    const int x0 = bx * 8;
+    __syncthreads();
+
+    // Phase 1: lane = row r.  RGBE -> TMO -> YCbCr -> FDCT row pass; the row
+    // outputs go to the slot transposed, at position r ^ (r >> 2) of column u,
+    // so a column reads back as the pairs (0,1), (2,3), (5,4), (7,6).
+    if (active) {
+        const int yl = by * 8 + r;
+        const uint32_t *row = (const uint32_t *)d.rgbe + (int64_t)min(yl, H - 1) * W;
+        uint32_t px[8];
+        if (x0 + 8 <= W) {
+#pragma unroll
+            for (int x = 0; x < 8; ++x) px[x] = row[x0 + x];
+        } else {
+#pragma unroll
+            for (int x = 0; x < 8; ++x) px[x] = row[min(x0 + x, W - 1)];
+        }
+        int ch[3][8];
+#pragma unroll
+        for (int x = 0; x < 8; ++x) {
+            int cr, cg, cb;
+            tmo_px(px[x], kbase, sigma, any_lit, s_lut, s_thr, cr, cg, cb);
+            if (d.sdr0 && yl < H && x0 + x < W) {
+                uint8_t *o = d.sdr0 + 3 * ((int64_t)yl * W + x0 + x);
+                o[0] = (uint8_t)cr; o[1] = (uint8_t)cg; o[2] = (uint8_t)cb;
+            }
+            int Y, Cb, Cr;
+            rgb_to_ycc(cr, cg, cb, Y, Cb, Cr);
+            ch[0][x] = Y - 128;
+            ch[1][x] = Cb - 128;
+            ch[2][x] = Cr - 128;
+        }
+        const int pos = r ^ (r >> 2);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int A01 = pack_i16(ch[c][0], ch[c][1]), A23 = pack_i16(ch[c][2], ch[c][3]);
+            const int B76 = pack_i16(ch[c][7], ch[c][6]), B54 = pack_i16(ch[c][5], ch[c][4]);
+            int T[8];
+            fdct1(padd(A01, B76), padd(A23, B54), psub(A01, B76), psub(A23, B54), 1024, T);
+            int16_t *slot = reinterpret_cast<int16_t *>(&s_X[c][j][0]);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) slot[u * 8 + pos] = (int16_t)(T[u] >> 11);
+        }
+    }
+    __syncthreads();
+
+    // Phase 2: lane = column u = r.  FDCT column pass, quantise, dequantise,
+    // IDCT column pass; outputs go back transposed at position
+    // (u & 1) * 4 + (u >> 1) of row y, i.e. a row reads back as the pairs
+    // (0,2), (4,6), (1,3), (5,7).
+    const int u = r;
+    int col[3][4];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) col[c][k] = (int)s_X[c][j][u * 4 + k];
+    __syncthreads();
+    if (active) {
+        const int H8 = nby * 8, W8 = nbx * 8;
+        const int pos2 = (u & 1) * 4 + (u >> 1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const uint32_t *QM = s_QM[c ? 1 : 0];
+            int F[8];
+            fdct1(padd(col[c][0], col[c][3]), padd(col[c][1], col[c][2]), psub(col[c][0], col[c][3]),
+                  psub(col[c][1], col[c][2]), 16384, F);
+            int dq[8];
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                const int f = F[v] >> 15;
+                const uint32_t qm = QM[v * 8 + u];
+                const uint32_t a = (uint32_t)abs(f) + (qm >> 25);
+                const int qa = (int)(__umul24(a, qm) >> 20);
+                const int Fq = f < 0 ? -qa : qa;
+                if (d.dct) d.dct[((int64_t)c * H8 + by * 8 + v) * W8 + x0 + u] = (int16_t)Fq;
+                dq[v] = Fq * (int)(qm >> 24);
+            }
+            int t[8];
+            idct1(pack_i16(dq[0], dq[2]), pack_i16(dq[4], dq[6]), pack_i16(dq[1], dq[3]), pack_i16(dq[5], dq[7]), 1024, t);
+            int16_t *slot = reinterpret_cast<int16_t *>(&s_X[c][j][0]);
+#pragma unroll
+            for (int y = 0; y < 8; ++y) slot[y * 8 + pos2] = (int16_t)(t[y] >> 11);
+        }
+    }
+    __syncthreads();
+
+    // Phase 3: lane = row y = r.  IDCT row pass, + 128, clamp, inverse colour
+    // transform, crop, store S.
+    if (!active) return;
+    const int y = r;
+    const int yy = by * 8 + y;
+    if (yy >= H) return;
+    uint32_t rec[3][2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const uint32_t *rw = &s_X[c][j][y * 4];
+        int o[8];
+        idct1((int)rw[0], (int)rw[1], (int)rw[2], (int)rw[3], 16384 + (128 << 15), o);
+        uint32_t w0 = 0, w1 = 0;
+#pragma unroll
+        for (int x = 0; x < 8; ++x) {
+            const uint32_t v = (uint32_t)min(max(o[x] >> 15, 0), 255);
+            if (x < 4) w0 |= v << (8 * x); else w1 |= v << (8 * (x - 4));
+        }
+        rec[c][0] = w0;
+        rec[c][1] = w1;
+    }
+    uint8_t *orow = d.sdr + 3 * ((int64_t)yy * W + x0);
+    uint32_t o[6];
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+        const int sh = 8 * (x & 3), wd = x >> 2;
+        int R, G, B;
+        ycc_to_rgb((rec[0][wd] >> sh) & 255, (rec[1][wd] >> sh) & 255, (rec[2][wd] >> sh) & 255, R, G, B);
+        const uint32_t rgb = (uint32_t)R | ((uint32_t)G << 8) | ((uint32_t)B << 16);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int p = 3 * x + k;
+            const uint32_t byte = (rgb >> (8 * k)) & 255u;
+            if ((p & 3) == 0) o[p >> 2] = byte; else o[p >> 2] |= byte << (8 * (p & 3));
+        }
+    }
+    if (x0 + 8 <= W && ((reinterpret_cast<uintptr_t>(orow) & 3) == 0)) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) reinterpret_cast<uint32_t *>(orow)[k] = o[k];
+    } else {
+        const int nx = min(8, W - x0);
+        for (int k = 0; k < 3 * nx; ++k) orow[k] = (uint8_t)(o[k >> 2] >> (8 * (k & 3)));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// GF-based stages share one tile loader: S for a (TILE_H + 2) x (TILE_W + 2)
+// window with a one-pixel ring, replicated at the image border, one 32-bit
+// word (R | G << 8 | B << 16) per pixel in LDS.
+// ---------------------------------------------------------------------------
+struct TileLds {
+    uint32_t s[TILE_H + 2][TILE_W + 2];
+};
+
+__device__ __forceinline__ void load_s_tile(TileLds &t, const uint8_t *__restrict__ sdr, int H, int W, int ty0,
+                                            int tx0) {
+    for (int k = threadIdx.x; k < (TILE_H + 2) * (TILE_W + 2); k += TILE_THREADS) {
+        const int ry = k / (TILE_W + 2), rx = k - ry * (TILE_W + 2);
+        const int yy = min(max(ty0 + ry - 1, 0), H - 1);
+        const int xx = min(max(tx0 + rx - 1, 0), W - 1);
+        const uint8_t *p = sdr + 3 * ((int64_t)yy * W + xx);
+        t.s[ry][rx] = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
+    }
+}
+
+// S* for the RUN pixels of one lane: (1,6,1) x (1,6,1) / 64, round half up.
+// out[j] packs channel bytes like the tile.
+__device__ __forceinline__ void gf_run(const TileLds &t, int ly, int lx, uint32_t out[RUN]) {
+    int vs[RUN + 2][3];
+#pragma unroll
+    for (int j = 0; j < RUN + 2; ++j) {
+        const uint32_t a = t.s[ly][lx + j], b = t.s[ly + 1][lx + j], c = t.s[ly + 2][lx + j];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch)
+            vs[j][ch] = (int)((a >> (8 * ch)) & 255u) + 6 * (int)((b >> (8 * ch)) & 255u) + (int)((c >> (8 * ch)) & 255u);
+    }
+#pragma unroll
+    for (int j = 0; j < RUN; ++j) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            const int v = (vs[j][ch] + 6 * vs[j + 1][ch] + vs[j + 2][ch] + 32) >> 6;
+            o |= (uint32_t)v << (8 * ch);
+        }
+        out[j] = o;
+    }
+}
+
+__device__ __forceinline__ void load_rgbe_run(const uint8_t *rgbe, int W, int y, int x, int nx, uint32_t w[RUN]) {
+    const uint32_t *row = (const uint32_t *)rgbe + (int64_t)y * W;
+    if (nx == RUN && ((reinterpret_cast<uintptr_t>(row + x) & 15) == 0)) {
+        const uint4 a = *reinterpret_cast<const uint4 *>(row + x);
+        const uint4 b = *reinterpret_cast<const uint4 *>(row + x + 4);
+        w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
+        w[4] = b.x; w[5] = b.y; w[6] = b.z; w[7] = b.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < RUN; ++j) w[j] = row[x + min(j, nx - 1)];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K3 fit sums: per (channel, E) n, sum s, sum m, sum s^2, sum s m over the
+// image (Eq. 9-10), s = S*_c, m = M_c.  Each lane walks its run keeping one
+// register accumulator per exponent run and flushes it into 32-bit LDS bins
+// when E changes; each workgroup then adds its bins into the image's int64
+// sums with integer atomics.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(TILE_THREADS) void k_fit_sums(const ImgDesc *__restrict__ D, int n) {
+    __shared__ TileLds t;
+    __shared__ uint32_t bins[256][NSUM];
+    const int i = find_img(D, n, blockIdx.x, 2);
+    const ImgDesc &d = D[i];
+    const int H = d.H, W = d.W;
+    const int ntx = (W + TILE_W - 1) / TILE_W;
+    const int tile = blockIdx.x - d.wg_tile;
+    const int ty0 = (tile / ntx) * TILE_H, tx0 = (tile % ntx) * TILE_W;
+    for (int k = threadIdx.x; k < 256 * NSUM; k += TILE_THREADS) (&bins[0][0])[k] = 0;
+    load_s_tile(t, d.sdr, H, W, ty0, tx0);
+    __syncthreads();
+
+    const int ly = threadIdx.x / (TILE_W / RUN), lx = (threadIdx.x % (TILE_W / RUN)) * RUN;
+    const int y = ty0 + ly, x = tx0 + lx;
+    if (y < H && x < W) {
+        const int nx = min(RUN, W - x);
+        uint32_t ss[RUN], w[RUN];
+        gf_run(t, ly, lx, ss);
+        load_rgbe_run(d.rgbe, W, y, x, nx, w);
+        int cur = (int)(w[0] >> 24);
+        uint32_t acc[NSUM];
+#pragma unroll
+        for (int k = 0; k < NSUM; ++k) acc[k] = 0;
+#pragma unroll
+        for (int j = 0; j < RUN; ++j) {
+            if (j < nx) {
+                const int e = (int)(w[j] >> 24);
+                if (e != cur) {
+#pragma unroll
+                    for (int k = 0; k < NSUM; ++k) {
+                        if (acc[k]) atomicAdd(&bins[cur][k], acc[k]);
+                        acc[k] = 0;
+                    }
+                    cur = e;
+                }
+                acc[0] += 1;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const uint32_t s = (ss[j] >> (8 * c)) & 255u, m = (w[j] >> (8 * c)) & 255u;
+                    acc[1 + 4 * c] += s;
+                    acc[2 + 4 * c] += m;
+                    acc[3 + 4 * c] += s * s;
+                    acc[4 + 4 * c] += s * m;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NSUM; ++k)
+            if (acc[k]) atomicAdd(&bins[cur][k], acc[k]);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 256; e += TILE_THREADS) {
+        if (bins[e][0] == 0) continue;
+        unsigned long long *g = (unsigned long long *)(d.sums + (int64_t)e * NSUM);
+#pragma unroll
+        for (int k = 0; k < NSUM; ++k)
+            if (bins[e][k]) atomicAdd(g + k, (unsigned long long)bins[e][k]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K4 solve: one workgroup per image, one lane per exponent value.  Exact
+// 128-bit least squares (Eq. 6-7 / 9-10) with fixed-point rounding:
+// a_q = rhu(2^22 num / den), b_q = rhu((2^22 Sm - a_q Ss) / (2^8 n)).
+// ---------------------------------------------------------------------------
+typedef __int128 i128;
+typedef unsigned __int128 u128;
+
+__device__ __forceinline__ int clz128(u128 v) {
+    const uint64_t hi = (uint64_t)(v >> 64), lo = (uint64_t)v;
+    return hi ? __builtin_clzll(hi) : (lo ? 64 + __builtin_clzll(lo) : 128);
+}
+
+// Unsigned long division by shift-and-subtract, d > 0.
+__device__ u128 udiv128(u128 num, u128 den) {
+    if (den > num) return 0;
+    const int sh = clz128(den) - clz128(num);
+    den <<= sh;
+    u128 q = 0;
+    for (int k = 0; k <= sh; ++k) {
+        q <<= 1;
+        if (num >= den) { num -= den; q |= 1; }
+        den >>= 1;
+    }
+    return q;
+}
+
+__device__ i128 floor_div128(i128 a, i128 b) {  // b > 0
+    if (a >= 0) return (i128)udiv128((u128)a, (u128)b);
+    return -(i128)udiv128((u128)(-a) + (u128)b - 1, (u128)b);
+}
+
+__device__ __forceinline__ i128 rhu128(i128 x, i128 y) { return floor_div128(2 * x + y, 2 * y); }
+
+__global__ __launch_bounds__(256) void k_solve(const ImgDesc *__restrict__ D, int n) {
+    const int i = blockIdx.x;
+    const ImgDesc &d = D[i];
+    rdl_header *h = d.hdr;
+    const int e = threadIdx.x;
+    const int64_t *b = d.sums + (int64_t)e * NSUM;
+    const i128 nn = b[0];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        int32_t aq = 0, bq = 0;
+        if (nn > 0) {
+            const i128 Ss = b[1 + 4 * c], Sm = b[2 + 4 * c], Sss = b[3 + 4 * c], Ssm = b[4 + 4 * c];
+            const i128 num = nn * Ssm - Ss * Sm;
+            const i128 den = nn * Sss - Ss * Ss;
+            const i128 a = den == 0 ? (i128)0 : rhu128(num * ((i128)1 << 22), den);
+            const i128 bb = rhu128(Sm * ((i128)1 << 22) - a * Ss, nn * 256);
+            aq = (int32_t)a;
+            bq = (int32_t)bb;
+        }
+        h->a_q[c][e] = aq;
+        h->b_q[c][e] = bq;
+        h->flag[c][e] = 0;
+    }
+    h->present[e] = nn > 0;
+    const int nreg = __syncthreads_count(nn > 0);
+    if (e == 0) {
+        int k_img = 0, f_key = 0;
+        float sigma = 0.0f;
+        int64_t L = 0, N = 0;
+        if (d.ks) key_params(d.ks, k_img, f_key, sigma, L, N);
+        h->magic = RDL_MAGIC;
+        h->version = RDL_VERSION;
+        h->H = d.H;
+        h->W = d.W;
+        h->q = d.q;
+        h->k_img = k_img;
+        h->f_key = f_key;
+        h->sigma = sigma;
+        h->lambda_sum = L;
+        h->n_lit = N;
+        h->estimator = 0;
+        h->n_regions = nreg;
+        h->model_hash = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K5 residuals: r = M - M*, M* = clamp((a_q s + 2^8 b_q + 2^21) >> 22, 0, 255)
+// (Eq. 8), written as int16 planes, plus the exponent plane.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int mstar(int32_t aq, int32_t bq, int s) {
+    const int64_t v = ((int64_t)aq * s + (int64_t)bq * 256 + (1 << 21)) >> 22;
+    return (int)min(max(v, (int64_t)0), (int64_t)255);
+}
+
+__global__ __launch_bounds__(TILE_THREADS) void k_resid(const ImgDesc *__restrict__ D, int n) {
+    __shared__ TileLds t;
+    const int i = find_img(D, n, blockIdx.x, 2);
+    const ImgDesc &d = D[i];
+    const int H = d.H, W = d.W;
+    const int ntx = (W + TILE_W - 1) / TILE_W;
+    const int tile = blockIdx.x - d.wg_tile;
+    const int ty0 = (tile / ntx) * TILE_H, tx0 = (tile % ntx) * TILE_W;
+    load_s_tile(t, d.sdr, H, W, ty0, tx0);
+    __syncthreads();
+    const int ly = threadIdx.x / (TILE_W / RUN), lx = (threadIdx.x % (TILE_W / RUN)) * RUN;
+    const int y = ty0 + ly, x = tx0 + lx;
+    if (y >= H || x >= W) return;
+    const int nx = min(RUN, W - x);
+    uint32_t ss[RUN], w[RUN];
+    gf_run(t, ly, lx, ss);
+    load_rgbe_run(d.rgbe, W, y, x, nx, w);
+    const rdl_header *h = d.hdr;
+    const int64_t npx = (int64_t)H * W;
+    const int64_t o = (int64_t)y * W + x;
+    int16_t *r = (int16_t *)d.resid;
+    uint8_t *Ep = d.resid + 6 * npx;
+    int rv[3][RUN];
+#pragma unroll
+    for (int j = 0; j < RUN; ++j) {
+        const int e = (int)(w[j] >> 24);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int s = (int)((ss[j] >> (8 * c)) & 255u);
+            rv[c][j] = (int)((w[j] >> (8 * c)) & 255u) - mstar(h->a_q[c][e], h->b_q[c][e], s);
+        }
+    }
+    const bool vec = nx == RUN && (W & 7) == 0 && ((reinterpret_cast<uintptr_t>(d.resid) & 15) == 0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        int16_t *rp = r + c * npx + o;
+        if (vec) {
+            uint4 v;
+            v.x = (uint32_t)pack_i16(rv[c][0], rv[c][1]);
+            v.y = (uint32_t)pack_i16(rv[c][2], rv[c][3]);
+            v.z = (uint32_t)pack_i16(rv[c][4], rv[c][5]);
+            v.w = (uint32_t)pack_i16(rv[c][6], rv[c][7]);
+            *reinterpret_cast<uint4 *>(rp) = v;
+        } else {
+            for (int j = 0; j < nx; ++j) rp[j] = (int16_t)rv[c][j];
+        }
+    }
+    if (vec) {
+        uint2 v;
+        v.x = (w[0] >> 24) | ((w[1] >> 24) << 8) | ((w[2] >> 24) << 16) | ((w[3] >> 24) << 24);
+        v.y = (w[4] >> 24) | ((w[5] >> 24) << 8) | ((w[6] >> 24) << 16) | ((w[7] >> 24) << 24);
+        *reinterpret_cast<uint2 *>(Ep + o) = v;
+    } else {
+        for (int j = 0; j < nx; ++j) Ep[o + j] = (uint8_t)(w[j] >> 24);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// K6 decode: M = M* + r, RGBE out.  The header is checked first; a mismatch
+// or a mantissa outside [0, 255] sets *status = RDL_ECORRUPT.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(TILE_THREADS) void k_decode(const ImgDesc *__restrict__ D, int n) {
+    __shared__ TileLds t;
+    const int i = find_img(D, n, blockIdx.x, 2);
+    const ImgDesc &d = D[i];
+    const int H = d.H, W = d.W;
+    const rdl_header *h = d.hdr;
+    const bool ok = h->magic == RDL_MAGIC && h->version == RDL_VERSION && h->H == H && h->W == W;
+    if (!ok) {
+        if (threadIdx.x == 0 && d.status) atomicExch(d.status, RDL_ECORRUPT);
+        return;
+    }
+    const int ntx = (W + TILE_W - 1) / TILE_W;
+    const int tile = blockIdx.x - d.wg_tile;
+    const int ty0 = (tile / ntx) * TILE_H, tx0 = (tile % ntx) * TILE_W;
+    load_s_tile(t, d.sdr, H, W, ty0, tx0);
+    __syncthreads();
+    const int ly = threadIdx.x / (TILE_W / RUN), lx = (threadIdx.x % (TILE_W / RUN)) * RUN;
+    const int y = ty0 + ly, x = tx0 + lx;
+    if (y >= H || x >= W) return;
+    const int nx = min(RUN, W - x);
+    uint32_t ss[RUN];
+    gf_run(t, ly, lx, ss);
+    const int64_t npx = (int64_t)H * W;
+    const int64_t o = (int64_t)y * W + x;
+    const int16_t *r = (const int16_t *)d.resid;
+    const uint8_t *Ep = d.resid + 6 * npx;
+    uint32_t *out = (uint32_t *)d.out_rgbe + o;
+    bool bad = false;
+    for (int j = 0; j < nx; ++j) {
+        const int e = Ep[o + j];
+        uint32_t word = (uint32_t)e << 24;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int s = (int)((ss[j] >> (8 * c)) & 255u);
+            const int m = mstar(h->a_q[c][e], h->b_q[c][e], s) + r[c * npx + o + j];
+            bad |= (m < 0) | (m > 255);
+            word |= (uint32_t)(m & 255) << (8 * c);
+        }
+        out[j] = word;
+    }
+    if (bad && d.status) atomicExch(d.status, RDL_ECORRUPT);
+}
+
+// ---------------------------------------------------------------------------
+// K7 residual histograms: hist[c][r + 255].
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(TILE_THREADS) void k_hist(const ImgDesc *__restrict__ D, int n) {
+    __shared__ uint32_t hb[3][511];
+    const int i = find_img(D, n, blockIdx.x, 2);
+    const ImgDesc &d = D[i];
+    const int H = d.H, W = d.W;
+    for (int k = threadIdx.x; k < 3 * 511; k += TILE_THREADS) (&hb[0][0])[k] = 0;
+    __syncthreads();
+    const int ntx = (W + TILE_W - 1) / TILE_W;
+    const int tile = blockIdx.x - d.wg_tile;
+    const int ty0 = (tile / ntx) * TILE_H, tx0 = (tile % ntx) * TILE_W;
+    const int ly = threadIdx.x / (TILE_W / RUN), lx = (threadIdx.x % (TILE_W / RUN)) * RUN;
+    const int y = ty0 + ly, x = tx0 + lx;
+    if (y < H && x < W) {
+        const int nx = min(RUN, W - x);
+        const int64_t npx = (int64_t)H * W;
+        const int16_t *r = (const int16_t *)d.resid + (int64_t)y * W + x;
+        for (int c = 0; c < 3; ++c)
+            for (int j = 0; j < nx; ++j) atomicAdd(&hb[c][min(max(r[c * npx + j] + 255, 0), 510)], 1u);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < 3 * 511; k += TILE_THREADS) {
+        const uint32_t v = (&hb[0][0])[k];
+        if (v) atomicAdd((unsigned long long *)&d.hist[k], (unsigned long long)v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side: tables and launchers.
+// ---------------------------------------------------------------------------
+hipError_t upload_tables(int *bad_table) {
+    *bad_table = 0;
+    static int32_t log2f[4096];
+    static float eh[256], el[256], thr[257];
+    static uint8_t glut[GAMMA_LUT_N];
+    for (int k = 0; k < 4096; ++k) log2f[k] = (int32_t)std::llround(65536.0 * std::log2(1.0 + (k + 0.5) / 4096.0));
+    for (int j = 0; j < 256; ++j) {
+        eh[j] = (float)std::exp2(j / 256.0);
+        el[j] = (float)std::exp2(j / 65536.0);
+    }
+    thr[0] = 0.0f;
+    for (int k = 1; k < 256; ++k) thr[k] = (float)std::pow((k - 0.5) / 255.0, 2.2);
+    thr[256] = INFINITY;
+    // Bucket b covers floats whose top 16 bits are b + ((127 - 20) << 7).
+    for (int b = 0; b < GAMMA_LUT_N; ++b) {
+        uint32_t lo_bits = (uint32_t)(b + ((127 - 20) << 7)) << 16;
+        uint32_t hi_bits = lo_bits + (1u << 16);
+        float lo, hi;
+        memcpy(&lo, &lo_bits, 4);
+        memcpy(&hi, &hi_bits, 4);
+        int cnt = 0, inside = 0;
+        for (int k = 1; k < 256; ++k) {
+            if (thr[k] <= lo) cnt++;
+            else if (thr[k] < hi) inside++;
+        }
+        if (inside > 1) *bad_table = 1;
+        glut[b] = (uint8_t)cnt;
+    }
+    // Below the first bucket every code is 0; from the last bucket up every
+    // code is 255 or 254 + one compare.
+    if (thr[1] <= ldexpf(1.0f, -20)) *bad_table = 1;
+    hipError_t e;
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(g_log2f), log2f, sizeof log2f)) != hipSuccess) return e;
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(g_exp2h), eh, sizeof eh)) != hipSuccess) return e;
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(g_exp2l), el, sizeof el)) != hipSuccess) return e;
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(g_thr), thr, sizeof thr)) != hipSuccess) return e;
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(g_glut), glut, sizeof glut)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+void launch_zero(const ImgDesc *d, int n, hipStream_t s) { hipLaunchKernelGGL(k_zero, dim3(n), dim3(256), 0, s, d, n); }
+void launch_keystat(const ImgDesc *d, int n, int wgs, hipStream_t s) {
+    hipLaunchKernelGGL(k_keystat, dim3(wgs), dim3(KS_THREADS), 0, s, d, n);
+}
+void launch_tmo_base(const ImgDesc *d, int n, int wgs, hipStream_t s) {
+    hipLaunchKernelGGL(k_tmo_base, dim3(wgs), dim3(BLK_THREADS), 0, s, d, n);
+}
+void launch_fit_sums(const ImgDesc *d, int n, int wgs, hipStream_t s) {
+    hipLaunchKernelGGL(k_fit_sums, dim3(wgs), dim3(TILE_THREADS), 0, s, d, n);
+}
+void launch_solve(const ImgDesc *d, int n, hipStream_t s) { hipLaunchKernelGGL(k_solve, dim3(n), dim3(256), 0, s, d, n); }
+void launch_resid(const ImgDesc *d, int n, int wgs, hipStream_t s) {
+    hipLaunchKernelGGL(k_resid, dim3(wgs), dim3(TILE_THREADS), 0, s, d, n);
+}
+void launch_decode(const ImgDesc *d, int n, int wgs, hipStream_t s) {
+    hipLaunchKernelGGL(k_decode, dim3(wgs), dim3(TILE_THREADS), 0, s, d, n);
+}
+void launch_hist(const ImgDesc *d, int n, int wgs, hipStream_t s) {
+    hipLaunchKernelGGL(k_hist, dim3(wgs), dim3(TILE_THREADS), 0, s, d, n);
+}
+
+}  // namespace rdl

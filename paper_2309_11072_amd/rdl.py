@@ -1,0 +1,208 @@
+"""Python binding of ``librdl.so`` (the C ABI in ``include/rdl.h``).
+
+Argument marshalling only: every step of the encoder and decoder runs in the
+HIP kernels behind the C ABI.  PyTorch provides device memory and streams.
+If the library has not been built, or no GPU is present, calls fail loudly;
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime before librdl.so binds to it)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librdl.so")
+
+RDL_MAGIC = 0x314C4452
+RDL_OK, RDL_EINVAL, RDL_EHIP, RDL_ECORRUPT, RDL_ENOMEM, RDL_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+
+#: Byte layout of ``rdl_header`` (7232 bytes, little endian).
+HEADER_DTYPE = np.dtype([
+    ("magic", "<u4"), ("version", "<u4"), ("H", "<i4"), ("W", "<i4"), ("q", "<i4"),
+    ("k_img", "<i4"), ("f_key", "<i4"), ("sigma", "<f4"), ("lambda_sum", "<i8"), ("n_lit", "<i8"),
+    ("estimator", "<i4"), ("n_regions", "<i4"), ("model_hash", "<u8"),
+    ("a_q", "<i4", (3, 256)), ("b_q", "<i4", (3, 256)), ("present", "u1", (256,)), ("flag", "u1", (3, 256)),
+])
+HEADER_BYTES = HEADER_DTYPE.itemsize
+
+# Exported symbols of include/rdl.h with their argument types.
+_vp, _i, _i64p = C.c_void_p, C.c_int, C.c_void_p
+_SIGS = {
+    "rdl_create": ([C.POINTER(C.c_void_p), _i], _i),
+    "rdl_destroy": ([_vp], None),
+    "rdl_strerror": ([_i], C.c_char_p),
+    "rdl_resid_bytes": ([_i, _i], C.c_size_t),
+    "rdl_header_bytes": ([], C.c_size_t),
+    "rdl_header_validate": ([_vp, _i, _i], _i),
+    "rdl_encode_enh": ([_vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp], _i),
+    "rdl_decode_enh": ([_vp, _vp, _vp, _vp, _i, _i, _vp, _vp, _vp], _i),
+    "rdl_encode_batch": ([_vp, _vp, _i, _vp], _i),
+    "rdl_resid_hist": ([_vp, _vp, _i, _i, _vp, _vp], _i),
+    "rdl_stage_keystat": ([_vp, _vp, _i, _i, _vp, _vp], _i),
+    "rdl_stage_tmo_base": ([_vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp], _i),
+    "rdl_stage_fit": ([_vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp], _i),
+    "rdl_stage_resid": ([_vp, _vp, _vp, _vp, _i, _i, _vp, _vp], _i),
+}
+
+
+class RdlImage(C.Structure):
+    _fields_ = [("rgbe", C.c_void_p), ("H", C.c_int32), ("W", C.c_int32), ("q", C.c_int32),
+                ("sdr", C.c_void_p), ("hdr", C.c_void_p), ("resid", C.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load librdl.so and declare its functions.  Raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError("librdl.so is not built (run __graft_entry__.build()); there is no CPU fallback")
+        L = C.CDLL(path)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+class RdlError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = load_library().rdl_strerror(code).decode()
+        super().__init__("%s failed: %s (%d)" % (where, msg, code))
+        self.code = code
+
+
+def _chk(rc: int, where: str):
+    if rc != RDL_OK:
+        raise RdlError(rc, where)
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous"
+    return t.data_ptr()
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def header_from_bytes(buf) -> np.void:
+    """Parse a header copied to the host (a uint8 tensor/array of 7232 bytes)."""
+    if isinstance(buf, torch.Tensor):
+        buf = buf.detach().cpu().numpy()
+    return np.frombuffer(np.ascontiguousarray(buf).tobytes(), HEADER_DTYPE)[0]
+
+
+def split_resid(resid: torch.Tensor, H: int, W: int):
+    """(int16 r[3][H][W], uint8 E[H][W]) views of a residual buffer."""
+    npx = H * W
+    r = resid[: 6 * npx].view(torch.int16).view(3, H, W)
+    E = resid[6 * npx: 7 * npx].view(H, W)
+    return r, E
+
+
+class Codec:
+    """One rdl_ctx on one device."""
+
+    def __init__(self, device: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the encoder runs only on the GPU")
+        L = load_library()
+        self.device = device
+        h = C.c_void_p()
+        _chk(L.rdl_create(C.byref(h), device), "rdl_create")
+        self._h = h
+        self._L = L
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.rdl_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- buffers
+    def alloc_outputs(self, H: int, W: int):
+        dev = torch.device("cuda", self.device)
+        sdr = torch.empty((H, W, 3), dtype=torch.uint8, device=dev)
+        hdr = torch.empty(HEADER_BYTES, dtype=torch.uint8, device=dev)
+        resid = torch.empty(7 * H * W, dtype=torch.uint8, device=dev)
+        return sdr, hdr, resid
+
+    # -------------------------------------------------------------- encoder
+    def encode_enh(self, rgbe: torch.Tensor, q: int, out=None, stream=None):
+        """rgbe: uint8 [H, W, 4] on the device.  Returns (sdr, header, resid)."""
+        H, W = int(rgbe.shape[0]), int(rgbe.shape[1])
+        sdr, hdr, resid = out if out is not None else self.alloc_outputs(H, W)
+        _chk(self._L.rdl_encode_enh(self._h, _ptr(rgbe), H, W, int(q), _ptr(sdr), _ptr(hdr), _ptr(resid),
+                                    _stream(stream)), "rdl_encode_enh")
+        return sdr, hdr, resid
+
+    def encode_batch(self, items, stream=None):
+        """items: list of (rgbe, q, sdr, hdr, resid) device tensors."""
+        arr = (RdlImage * len(items))()
+        for k, (rgbe, q, sdr, hdr, resid) in enumerate(items):
+            arr[k] = RdlImage(_ptr(rgbe), int(rgbe.shape[0]), int(rgbe.shape[1]), int(q), _ptr(sdr), _ptr(hdr),
+                              _ptr(resid))
+        _chk(self._L.rdl_encode_batch(self._h, arr, len(items), _stream(stream)), "rdl_encode_batch")
+
+    def decode_enh(self, sdr: torch.Tensor, hdr: torch.Tensor, resid: torch.Tensor, H: int, W: int,
+                   out: torch.Tensor | None = None, status: torch.Tensor | None = None, stream=None):
+        out = out if out is not None else torch.empty((H, W, 4), dtype=torch.uint8, device=sdr.device)
+        _chk(self._L.rdl_decode_enh(self._h, _ptr(sdr), _ptr(hdr), _ptr(resid), H, W, _ptr(out), _ptr(status),
+                                    _stream(stream)), "rdl_decode_enh")
+        return out
+
+    def resid_hist(self, resid: torch.Tensor, H: int, W: int, stream=None):
+        hist = torch.empty((3, 511), dtype=torch.int64, device=resid.device)
+        _chk(self._L.rdl_resid_hist(self._h, _ptr(resid), H, W, _ptr(hist), _stream(stream)), "rdl_resid_hist")
+        return hist
+
+    # -------------------------------------------------------------- stages
+    def stage_keystat(self, rgbe: torch.Tensor, stream=None):
+        out = torch.empty(2, dtype=torch.int64, device=rgbe.device)
+        _chk(self._L.rdl_stage_keystat(self._h, _ptr(rgbe), int(rgbe.shape[0]), int(rgbe.shape[1]), _ptr(out),
+                                       _stream(stream)), "rdl_stage_keystat")
+        return out
+
+    def stage_tmo_base(self, rgbe: torch.Tensor, q: int, keystat: torch.Tensor, want_sdr0=False, want_dct=False,
+                       stream=None):
+        H, W = int(rgbe.shape[0]), int(rgbe.shape[1])
+        dev = rgbe.device
+        sdr = torch.empty((H, W, 3), dtype=torch.uint8, device=dev)
+        sdr0 = torch.empty((H, W, 3), dtype=torch.uint8, device=dev) if want_sdr0 else None
+        dct = None
+        if want_dct:
+            dct = torch.empty((3, (H + 7) // 8 * 8, (W + 7) // 8 * 8), dtype=torch.int16, device=dev)
+        _chk(self._L.rdl_stage_tmo_base(self._h, _ptr(rgbe), H, W, int(q), _ptr(keystat), _ptr(sdr0), _ptr(sdr),
+                                        _ptr(dct), _stream(stream)), "rdl_stage_tmo_base")
+        return sdr, sdr0, dct
+
+    def stage_fit(self, rgbe: torch.Tensor, sdr: torch.Tensor, q: int, keystat: torch.Tensor | None = None,
+                  stream=None):
+        H, W = int(rgbe.shape[0]), int(rgbe.shape[1])
+        sums = torch.empty((256, 13), dtype=torch.int64, device=rgbe.device)
+        hdr = torch.empty(HEADER_BYTES, dtype=torch.uint8, device=rgbe.device)
+        _chk(self._L.rdl_stage_fit(self._h, _ptr(rgbe), _ptr(sdr), H, W, int(q), _ptr(keystat), _ptr(sums), _ptr(hdr),
+                                   _stream(stream)), "rdl_stage_fit")
+        return sums, hdr
+
+    def stage_resid(self, rgbe: torch.Tensor, sdr: torch.Tensor, hdr: torch.Tensor, stream=None):
+        H, W = int(rgbe.shape[0]), int(rgbe.shape[1])
+        resid = torch.empty(7 * H * W, dtype=torch.uint8, device=rgbe.device)
+        _chk(self._L.rdl_stage_resid(self._h, _ptr(rgbe), _ptr(sdr), _ptr(hdr), H, W, _ptr(resid), _stream(stream)),
+             "rdl_stage_resid")
+        return resid

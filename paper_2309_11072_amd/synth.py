@@ -9,7 +9,8 @@ and a controllable exponent spread.
 Recipe (per image):
   1. Z ~ N(0, 1) of shape H x W from numpy's PCG64(seed);
   2. Z is smoothed by a Gaussian of `smooth` pixels (reflect borders) and
-     divided by its empirical standard deviation;
+     standardised (empirical mean removed, divided by the empirical standard
+     deviation; a field too small to vary is taken as flat);
   3. log2 luminance = sigma_l * Z;
   4. per-channel chroma ratios rho_c ~ U[0.5, 2] on a `cell`-pixel grid,
      bilinearly interpolated and normalised to unit Rec. 709 luminance;
@@ -66,9 +67,9 @@ def generate(H: int, W: int, sigma_l: float, seed: int, spec_frac: float = 0.0,
     rng = np.random.Generator(np.random.PCG64(seed))
     z = rng.standard_normal((H, W))
     z = gaussian_filter(z, smooth, mode="reflect")
+    z -= z.mean()
     sd = z.std()
-    if sd > 0:
-        z /= sd
+    z = z / sd if sd > 1e-6 else np.zeros_like(z)
     log2l = sigma_l * z
     gh, gw = H // cell + 2, W // cell + 2
     rho = _bilinear(rng.uniform(0.5, 2.0, (3, gh, gw)), H, W, cell)

@@ -1,0 +1,211 @@
+"""GPU parity: every output of the HIP path through the C ABI equals the CPU
+oracle element by element (bit-exact: all outputs are integers, and the FP32
+tone map is specified to the operation), stage by stage and end to end, on
+sizes that span several tiles with ragged edges, on the degenerate cases, and
+at the full 3840x2160 size in the launch configuration the benchmark times."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2309_11072_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def codec():
+    from paper_2309_11072_amd import rdl
+    c = rdl.Codec(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def rdl_mod():
+    from paper_2309_11072_amd import rdl
+    return rdl
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+SIZES = [(1, 1), (1, 9), (7, 1), (7, 9), (8, 8), (9, 17), (16, 128), (17, 129), (33, 40), (61, 83),
+         (130, 300), (255, 257)]
+
+
+def _images():
+    out = []
+    for k, (H, W) in enumerate(SIZES):
+        out.append(("synth%dx%d" % (H, W), synth.generate(H, W, 1.5 + (k % 4), seed=100 + k,
+                                                          spec_frac=0.05 if k % 2 else 0.0), 30 + 6 * k))
+    rng = np.random.default_rng(5)
+    out.append(("random-words", rng.integers(0, 256, (37, 45, 4)).astype(np.uint8), 75))
+    z = np.zeros((20, 24, 4), np.uint8)
+    out.append(("all-E0", z, 50))
+    g = np.zeros((24, 16, 4), np.uint8)
+    g[...] = [150, 150, 150, 140]
+    out.append(("grey", g, 90))
+    sp = synth.config1()
+    out.append(("config1-512x384", sp.make(), sp.q))
+    return out
+
+
+IMAGES = _images()
+
+
+@pytest.mark.parametrize("name,x,q", IMAGES, ids=[n for n, _, _ in IMAGES])
+def test_stages_match_oracle(codec, O, name, x, q):
+    H, W = x.shape[:2]
+    _say("stages", name, H, W, q)
+    d = _dev(x)
+    ks = codec.stage_keystat(d)
+    lam, n = O.keystat(x)
+    assert ks.cpu().tolist() == [lam, n]
+
+    k, f, s = O.key_params(lam, n)
+    S0 = O.tmo(x, k, s, n)
+    S, dct = O.base_layer(S0, q, want_dct=True)
+    sdr, sdr0, ddct = codec.stage_tmo_base(d, q, ks, want_sdr0=True, want_dct=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(sdr0.cpu().numpy(), S0), "tone-mapped SDRI"
+    assert np.array_equal(ddct.cpu().numpy(), dct), "quantised DCT coefficients"
+    assert np.array_equal(sdr.cpu().numpy(), S), "decoded SDRI"
+
+    Ss = O.gf(S)
+    sums_ref = O.sums(Ss, x)
+    a, b, pr = O.solve(sums_ref)
+    sums, hdr = codec.stage_fit(d, sdr, q, ks)
+    assert np.array_equal(sums.cpu().numpy(), sums_ref), "regression sums"
+    from paper_2309_11072_amd import rdl
+    h = rdl.header_from_bytes(hdr)
+    assert np.array_equal(h["a_q"], a) and np.array_equal(h["b_q"], b)
+    assert np.array_equal(h["present"], pr)
+    assert (h["k_img"], h["f_key"], h["lambda_sum"], h["n_lit"]) == (k, f, lam, n)
+    assert h["sigma"] == s
+
+    resid = codec.stage_resid(d, sdr, hdr)
+    assert np.array_equal(resid.cpu().numpy(), O.resid(Ss, x, a, b)), "residuals"
+
+
+@pytest.mark.parametrize("name,x,q", IMAGES, ids=[n for n, _, _ in IMAGES])
+def test_encode_decode_match_oracle(codec, O, rdl_mod, name, x, q):
+    H, W = x.shape[:2]
+    _say("encode", name, H, W, q)
+    d = _dev(x)
+    out = codec.alloc_outputs(H, W)
+    for t in out:
+        t.fill_(0xAA)  # poison: every byte must be written
+    sdr, hdr, resid = codec.encode_enh(d, q, out=out)
+    ref = O.encode_enh(x, q)
+    assert np.array_equal(sdr.cpu().numpy(), ref["sdr"])
+    assert np.array_equal(resid.cpu().numpy(), ref["resid"])
+    h = rdl_mod.header_from_bytes(hdr)
+    assert h["magic"] == rdl_mod.RDL_MAGIC and (h["H"], h["W"], h["q"]) == (H, W, q)
+    assert np.array_equal(h["a_q"], ref["a_q"]) and np.array_equal(h["b_q"], ref["b_q"])
+    assert h["n_regions"] == int(ref["present"].sum())
+    assert rdl_mod.load_library().rdl_header_validate(hdr.cpu().numpy().ctypes.data, H, W) == 0
+    # a second call replays the captured graph: identical outputs
+    sdr2, hdr2, resid2 = codec.encode_enh(d, q, out=out)
+    sdr3, hdr3, resid3 = codec.encode_enh(d, q, out=out)
+    assert np.array_equal(resid3.cpu().numpy(), ref["resid"]) and np.array_equal(sdr3.cpu().numpy(), ref["sdr"])
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    back = codec.decode_enh(sdr, hdr, resid, H, W, status=status)
+    assert np.array_equal(back.cpu().numpy(), x), "GPU round trip"
+    assert int(status.item()) == 0
+    hist = codec.resid_hist(resid, H, W)
+    assert np.array_equal(hist.cpu().numpy(), O.resid_hist(ref["resid"], H * W))
+
+
+def test_decode_of_oracle_stream(codec, O):
+    x = synth.generate(70, 90, 3.0, seed=77, spec_frac=0.05)
+    _say("decode oracle stream 70x90")
+    ref = O.encode_enh(x, 60)
+    # build a device header from the oracle's parameters by encoding on the GPU
+    # (identical) and check the decoder on the oracle's residual bytes
+    d = _dev(x)
+    sdr, hdr, _ = codec.encode_enh(d, 60)
+    back = codec.decode_enh(_dev(ref["sdr"]), hdr, _dev(ref["resid"]), 70, 90)
+    assert np.array_equal(back.cpu().numpy(), x)
+
+
+def test_decode_rejects_corrupt_header(codec, rdl_mod):
+    x = synth.generate(20, 30, 2.0, seed=3)
+    _say("corrupt header")
+    sdr, hdr, resid = codec.encode_enh(_dev(x), 70)
+    bad = hdr.clone()
+    bad[0] ^= 0xFF  # magic
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    codec.decode_enh(sdr, bad, resid, 20, 30, status=status)
+    assert int(status.item()) == rdl_mod.RDL_ECORRUPT
+    status.zero_()
+    codec.decode_enh(sdr, hdr, resid, 20, 30, status=status)
+    assert int(status.item()) == 0
+    h = hdr.cpu().numpy().copy()
+    lib = rdl_mod.load_library()
+    assert lib.rdl_header_validate(h.ctypes.data, 20, 31) == rdl_mod.RDL_ECORRUPT
+    hv = h.view(rdl_mod.HEADER_DTYPE)
+    hv["a_q"][0, 0, 5] = 256 << 22
+    assert lib.rdl_header_validate(h.ctypes.data, 20, 30) == rdl_mod.RDL_ECORRUPT
+
+
+def test_invalid_arguments(codec, rdl_mod):
+    _say("invalid arguments")
+    L = rdl_mod.load_library()
+    h = codec._h
+    x = torch.zeros((4, 4, 4), dtype=torch.uint8, device="cuda")
+    sdr, hdr, resid = codec.alloc_outputs(4, 4)
+    s = torch.cuda.current_stream().cuda_stream
+    E = rdl_mod.RDL_EINVAL
+    assert L.rdl_encode_enh(h, x.data_ptr(), 0, 4, 75, sdr.data_ptr(), hdr.data_ptr(), resid.data_ptr(), s) == E
+    assert L.rdl_encode_enh(h, x.data_ptr(), 4, 4, 0, sdr.data_ptr(), hdr.data_ptr(), resid.data_ptr(), s) == E
+    assert L.rdl_encode_enh(h, x.data_ptr(), 4, 4, 101, sdr.data_ptr(), hdr.data_ptr(), resid.data_ptr(), s) == E
+    assert L.rdl_encode_enh(h, None, 4, 4, 75, sdr.data_ptr(), hdr.data_ptr(), resid.data_ptr(), s) == E
+    assert L.rdl_encode_enh(h, x.data_ptr() + 1, 4, 4, 75, sdr.data_ptr(), hdr.data_ptr(), resid.data_ptr(), s) == E
+    assert L.rdl_encode_enh(None, x.data_ptr(), 4, 4, 75, sdr.data_ptr(), hdr.data_ptr(), resid.data_ptr(), s) == E
+    assert L.rdl_resid_bytes(0, 5) == 0 and L.rdl_resid_bytes(3, 5) == 105
+    assert L.rdl_encode_batch(h, None, 1, s) == E
+
+
+def test_batch_uneven_matches_oracle(codec, O):
+    specs = [(50, 70, 2.0, 55), (33, 200, 4.0, 90), (128, 64, 1.5, 30), (9, 9, 3.0, 98), (101, 131, 2.5, 75)]
+    _say("batch of", len(specs))
+    xs = [synth.generate(H, W, s, seed=900 + k, spec_frac=0.05) for k, (H, W, s, q) in enumerate(specs)]
+    items = []
+    for x, (H, W, s, q) in zip(xs, specs):
+        sdr, hdr, resid = codec.alloc_outputs(H, W)
+        items.append((_dev(x), q, sdr, hdr, resid))
+    for rep in range(3):  # direct launch, then capture, then replay
+        for it in items:
+            for t in it[2:]:
+                t.fill_(0xAA)
+        codec.encode_batch(items)
+        torch.cuda.synchronize()
+        for x, it, (H, W, s, q) in zip(xs, items, specs):
+            ref = O.encode_enh(x, q)
+            assert np.array_equal(it[2].cpu().numpy(), ref["sdr"]), (rep, H, W)
+            assert np.array_equal(it[4].cpu().numpy(), ref["resid"]), (rep, H, W)
+
+
+def test_full_size_config2(codec, O, rdl_mod):
+    """3840x2160, sigma 4, 5% speculars, q 75: the benchmark's workload and
+    launch configuration, compared with the oracle on every output."""
+    sp = synth.config2()
+    _say("config2 full size", sp.H, sp.W)
+    x = sp.make()
+    d = _dev(x)
+    out = codec.alloc_outputs(sp.H, sp.W)
+    for _ in range(3):
+        sdr, hdr, resid = codec.encode_enh(d, sp.q, out=out)
+    torch.cuda.synchronize()
+    ref = O.encode_enh(x, sp.q)
+    assert np.array_equal(sdr.cpu().numpy(), ref["sdr"])
+    assert np.array_equal(resid.cpu().numpy(), ref["resid"])
+    h = rdl_mod.header_from_bytes(hdr)
+    assert np.array_equal(h["a_q"], ref["a_q"]) and np.array_equal(h["b_q"], ref["b_q"])
+    back = codec.decode_enh(sdr, hdr, resid, sp.H, sp.W)
+    assert torch.equal(back, d)
