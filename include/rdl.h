@@ -151,6 +151,26 @@ int rdl_stage_fit(rdl_ctx *ctx, const uint8_t *rgbe, const uint8_t *sdr, int H, 
 int rdl_stage_resid(rdl_ctx *ctx, const uint8_t *rgbe, const uint8_t *sdr, const rdl_header *coeffs,
                     int H, int W, void *out_resid, void *stream);
 
+/* ---- Instrumentation ---- */
+
+/* Stage kernels of rdl_encode_enh in launch order; the index into ms[] of
+ * rdl_profile_encode. */
+enum {
+    RDL_STAGE_KEYSTAT = 0,  /* key statistic                           */
+    RDL_STAGE_TMO_BASE = 1, /* tone map + JPEG-style base layer -> S   */
+    RDL_STAGE_FIT = 2,      /* GF + per-(channel, E) regression sums   */
+    RDL_STAGE_SOLVE = 3,    /* fixed-point coefficients -> header      */
+    RDL_STAGE_RESID = 4,    /* GF + estimate + residual planes         */
+    RDL_NSTAGES = 5
+};
+
+/* Runs the same kernels as rdl_encode_enh (same arguments and outputs), one
+ * launch at a time with a pair of HIP events around each launch on `stream`,
+ * `reps` times, and writes the mean duration of each stage in milliseconds to
+ * the HOST array ms[RDL_NSTAGES].  Synchronises `stream`; not capturable. */
+int rdl_profile_encode(rdl_ctx *ctx, const uint8_t *rgbe, int H, int W, int q, uint8_t *out_sdr,
+                       rdl_header *out_coeffs, void *out_resid, int reps, float *ms, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

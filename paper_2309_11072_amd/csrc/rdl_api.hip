@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -82,21 +83,40 @@ int ensure_scratch(rdl_ctx *c, size_t n) {
     c->d_scratch = nullptr;
     c->scratch_cap = 0;
     HIPCHK(hipMalloc(&c->d_scratch, n * SCRATCH_I64 * sizeof(int64_t)));
+    HIPCHK(hipMemset(c->d_scratch, 0, n * SCRATCH_I64 * sizeof(int64_t)));  // accumulators start at zero
     c->scratch_cap = n;
     return RDL_OK;
 }
 
+struct Grid {
+    int px = 0, blk = 0, tile = 0, fit = 0, res = 0;
+};
+
 // Assign each image its first workgroup per kernel family.
-void layout(std::vector<ImgDesc> &v, int &npx, int &nblk, int &ntile) {
-    npx = nblk = ntile = 0;
+Grid layout(std::vector<ImgDesc> &v) {
+    Grid g;
     for (auto &d : v) {
-        d.wg_px = npx;
-        d.wg_blk = nblk;
-        d.wg_tile = ntile;
-        npx += wgs_px(d.H, d.W);
-        nblk += wgs_blk(d.H, d.W);
-        ntile += wgs_tile(d.H, d.W);
+        d.wg_px = g.px;
+        d.wg_blk = g.blk;
+        d.wg_tile = g.tile;
+        d.wg_fit = g.fit;
+        d.wg_res = g.res;
+        g.px += wgs_px(d.H, d.W);
+        g.blk += wgs_blk(d.H, d.W);
+        g.tile += wgs_tile(d.H, d.W);
+        g.fit += wgs_strip(d.H, d.W);
+        g.res += wgs_strip(d.H, d.W);
     }
+    return g;
+}
+
+// Point an image's accumulators into a scratch block of SCRATCH_I64 int64.
+void bind_scratch(ImgDesc &d, int64_t *base) {
+    d.ks = base + SCR_KS;
+    d.nks = std::min(KS_STRIPES, std::max(1, wgs_px(d.H, d.W)));
+    d.sums = base + SCR_SUMS;
+    d.part = base + SCR_PART;
+    d.nfs = std::min(FIT_STRIPES, std::max(1, wgs_strip(d.H, d.W)));
 }
 
 int upload(rdl_ctx *c, const std::vector<ImgDesc> &v, hipStream_t s) {
@@ -114,14 +134,14 @@ int check_launch(const char *what) {
     return RDL_OK;
 }
 
-// Enqueue the full encoder for the images of d (device table) on s.
-void enqueue_encode(const ImgDesc *d, int n, int wpx, int wblk, int wtile, hipStream_t s) {
-    launch_zero(d, n, s);
-    launch_keystat(d, n, wpx, s);
-    launch_tmo_base(d, n, wblk, s);
-    launch_fit_sums(d, n, wtile, s);
+// Enqueue the full encoder for the images of d (device table) on s.  The
+// scratch accumulators are zero on entry and k_solve leaves them zero.
+void enqueue_encode(const ImgDesc *d, int n, const Grid &g, hipStream_t s) {
+    launch_keystat(d, n, g.px, s);
+    launch_tmo_base(d, n, g.blk, s);
+    launch_fit_sums(d, n, g.fit, s);
     launch_solve(d, n, s);
-    launch_resid(d, n, wtile, s);
+    launch_resid(d, n, g.res, s);
 }
 
 ImgDesc blank() {
@@ -233,10 +253,9 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
         d.H = imgs[k].H;
         d.W = imgs[k].W;
         d.q = imgs[k].q;
-        d.flags = F_ZERO_KS | F_ZERO_SUMS;
+        d.flags = F_CLEAN_KS;
     }
-    int wpx, wblk, wtile;
-    layout(v, wpx, wblk, wtile);
+    const Grid gr = layout(v);
 
     // Replay a graph captured earlier for exactly these descriptors.
     for (auto &e : c->graphs)
@@ -252,13 +271,10 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
         int rc = ensure_scratch(c, n);
         if (rc) return rc;
         std::vector<ImgDesc> dv = v;
-        for (int k = 0; k < n; ++k) {
-            dv[k].ks = c->d_scratch + (size_t)k * SCRATCH_I64;
-            dv[k].sums = dv[k].ks + 2;
-        }
+        for (int k = 0; k < n; ++k) bind_scratch(dv[k], c->d_scratch + (size_t)k * SCRATCH_I64);
         rc = upload(c, dv, s);
         if (rc) return rc;
-        enqueue_encode(c->d_desc, n, wpx, wblk, wtile, s);
+        enqueue_encode(c->d_desc, n, gr, s);
         return check_launch("encoder kernels");
     }
 
@@ -275,11 +291,9 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
     GraphEntry e;
     e.key = v;
     HIPCHK(hipMalloc(&e.d_scratch, (size_t)n * SCRATCH_I64 * sizeof(int64_t)));
+    HIPCHK(hipMemset(e.d_scratch, 0, (size_t)n * SCRATCH_I64 * sizeof(int64_t)));
     std::vector<ImgDesc> dv = v;
-    for (int k = 0; k < n; ++k) {
-        dv[k].ks = e.d_scratch + (size_t)k * SCRATCH_I64;
-        dv[k].sums = dv[k].ks + 2;
-    }
+    for (int k = 0; k < n; ++k) bind_scratch(dv[k], e.d_scratch + (size_t)k * SCRATCH_I64);
     HIPCHK(hipMalloc(&e.d_desc, (size_t)n * sizeof(ImgDesc)));
     HIPCHK(hipMemcpy(e.d_desc, dv.data(), (size_t)n * sizeof(ImgDesc), hipMemcpyHostToDevice));
     hipStream_t cs;
@@ -287,7 +301,7 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
     hipGraph_t graph;
     hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (err == hipSuccess) {
-        enqueue_encode(e.d_desc, n, wpx, wblk, wtile, cs);
+        enqueue_encode(e.d_desc, n, gr, cs);
         err = hipStreamEndCapture(cs, &graph);
     }
     if (err == hipSuccess) {
@@ -319,11 +333,10 @@ int rdl_decode_enh(rdl_ctx *c, const uint8_t *sdr, const rdl_header *coeffs, con
     v[0].status = status;
     v[0].H = H;
     v[0].W = W;
-    int wpx, wblk, wtile;
-    layout(v, wpx, wblk, wtile);
+    const Grid gr = layout(v);
     int rc = upload(c, v, s);
     if (rc) return rc;
-    launch_decode(c->d_desc, 1, wtile, s);
+    launch_decode(c->d_desc, 1, gr.res, s);
     return check_launch("k_decode");
 }
 
@@ -337,12 +350,11 @@ int rdl_resid_hist(rdl_ctx *c, const void *resid, int H, int W, int64_t *hist, v
     v[0].H = H;
     v[0].W = W;
     v[0].flags = F_ZERO_HIST;
-    int wpx, wblk, wtile;
-    layout(v, wpx, wblk, wtile);
+    const Grid gr = layout(v);
     int rc = upload(c, v, s);
     if (rc) return rc;
     launch_zero(c->d_desc, 1, s);
-    launch_hist(c->d_desc, 1, wtile, s);
+    launch_hist(c->d_desc, 1, gr.tile, s);
     return check_launch("k_hist");
 }
 
@@ -352,16 +364,18 @@ int rdl_stage_keystat(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int64_t *ou
     hipStream_t s = (hipStream_t)stream;
     std::vector<ImgDesc> v(1, blank());
     v[0].rgbe = rgbe;
-    v[0].ks = out2;
     v[0].H = H;
     v[0].W = W;
-    v[0].flags = F_ZERO_KS;
-    int wpx, wblk, wtile;
-    layout(v, wpx, wblk, wtile);
-    int rc = upload(c, v, s);
+    v[0].flags = F_CLEAN_KS;
+    const Grid gr = layout(v);
+    int rc = ensure_scratch(c, 1);
     if (rc) return rc;
-    launch_zero(c->d_desc, 1, s);
-    launch_keystat(c->d_desc, 1, wpx, s);
+    bind_scratch(v[0], c->d_scratch);
+    c->last_key.clear();
+    rc = upload(c, v, s);
+    if (rc) return rc;
+    launch_keystat(c->d_desc, 1, gr.px, s);
+    launch_key_total(c->d_desc, 1, out2, s);
     return check_launch("k_keystat");
 }
 
@@ -373,17 +387,17 @@ int rdl_stage_tmo_base(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int q, con
     std::vector<ImgDesc> v(1, blank());
     v[0].rgbe = rgbe;
     v[0].ks = (int64_t *)keystat;
+    v[0].nks = 1;
     v[0].sdr0 = out_sdr0;
     v[0].sdr = out_sdr;
     v[0].dct = out_dct;
     v[0].H = H;
     v[0].W = W;
     v[0].q = q;
-    int wpx, wblk, wtile;
-    layout(v, wpx, wblk, wtile);
+    const Grid gr = layout(v);
     int rc = upload(c, v, s);
     if (rc) return rc;
-    launch_tmo_base(c->d_desc, 1, wblk, s);
+    launch_tmo_base(c->d_desc, 1, gr.blk, s);
     return check_launch("k_tmo_base");
 }
 
@@ -396,19 +410,21 @@ int rdl_stage_fit(rdl_ctx *c, const uint8_t *rgbe, const uint8_t *sdr, int H, in
     std::vector<ImgDesc> v(1, blank());
     v[0].rgbe = rgbe;
     v[0].sdr = (uint8_t *)sdr;
-    v[0].ks = (int64_t *)keystat;
-    v[0].sums = out_sums;
     v[0].hdr = out_coeffs;
     v[0].H = H;
     v[0].W = W;
     v[0].q = q;
-    v[0].flags = F_ZERO_SUMS;
-    int wpx, wblk, wtile;
-    layout(v, wpx, wblk, wtile);
-    int rc = upload(c, v, s);
+    const Grid gr = layout(v);
+    int rc = ensure_scratch(c, 1);
     if (rc) return rc;
-    launch_zero(c->d_desc, 1, s);
-    launch_fit_sums(c->d_desc, 1, wtile, s);
+    bind_scratch(v[0], c->d_scratch);
+    v[0].ks = (int64_t *)keystat;
+    v[0].nks = 1;
+    v[0].sums = out_sums;
+    c->last_key.clear();
+    rc = upload(c, v, s);
+    if (rc) return rc;
+    launch_fit_sums(c->d_desc, 1, gr.fit, s);
     launch_solve(c->d_desc, 1, s);
     return check_launch("k_fit_sums/k_solve");
 }
@@ -426,12 +442,63 @@ int rdl_stage_resid(rdl_ctx *c, const uint8_t *rgbe, const uint8_t *sdr, const r
     v[0].resid = (uint8_t *)out_resid;
     v[0].H = H;
     v[0].W = W;
-    int wpx, wblk, wtile;
-    layout(v, wpx, wblk, wtile);
+    const Grid gr = layout(v);
     int rc = upload(c, v, s);
     if (rc) return rc;
-    launch_resid(c->d_desc, 1, wtile, s);
+    launch_resid(c->d_desc, 1, gr.res, s);
     return check_launch("k_resid");
+}
+
+int rdl_profile_encode(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int q, uint8_t *out_sdr, rdl_header *out_coeffs,
+                       void *out_resid, int reps, float *ms, void *stream) {
+    if (!c || !rgbe || !out_sdr || !out_coeffs || !out_resid || !ms || reps < 1) return RDL_EINVAL;
+    if (!size_ok(H, W) || q < 1 || q > 100 || !aligned4(rgbe) || !aligned4(out_coeffs)) return RDL_EINVAL;
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<ImgDesc> v(1, blank());
+    v[0].rgbe = rgbe;
+    v[0].sdr = out_sdr;
+    v[0].hdr = out_coeffs;
+    v[0].resid = (uint8_t *)out_resid;
+    v[0].H = H;
+    v[0].W = W;
+    v[0].q = q;
+    v[0].flags = F_CLEAN_KS;
+    const Grid gr = layout(v);
+    int rc = ensure_scratch(c, 1);
+    if (rc) return rc;
+    bind_scratch(v[0], c->d_scratch);
+    c->last_key.clear();
+    rc = upload(c, v, s);
+    if (rc) return rc;
+    hipEvent_t ev[2 * RDL_NSTAGES];
+    for (int k = 0; k < 2 * RDL_NSTAGES; ++k) HIPCHK(hipEventCreate(&ev[k]));
+    double acc[RDL_NSTAGES] = {0};
+    hipError_t err = hipSuccess;
+    for (int r = 0; r < reps && err == hipSuccess; ++r) {
+        const ImgDesc *d = c->d_desc;
+        for (int st = 0; st < RDL_NSTAGES; ++st) {
+            (void)hipEventRecord(ev[2 * st], s);
+            switch (st) {
+                case RDL_STAGE_KEYSTAT: launch_keystat(d, 1, gr.px, s); break;
+                case RDL_STAGE_TMO_BASE: launch_tmo_base(d, 1, gr.blk, s); break;
+                case RDL_STAGE_FIT: launch_fit_sums(d, 1, gr.fit, s); break;
+                case RDL_STAGE_SOLVE: launch_solve(d, 1, s); break;
+                case RDL_STAGE_RESID: launch_resid(d, 1, gr.res, s); break;
+            }
+            (void)hipEventRecord(ev[2 * st + 1], s);
+        }
+        err = hipStreamSynchronize(s);
+        for (int st = 0; st < RDL_NSTAGES && err == hipSuccess; ++st) {
+            float t = 0;
+            err = hipEventElapsedTime(&t, ev[2 * st], ev[2 * st + 1]);
+            acc[st] += t;
+        }
+    }
+    for (int k = 0; k < 2 * RDL_NSTAGES; ++k) (void)hipEventDestroy(ev[k]);
+    if (err != hipSuccess) return hip_fail(err, "rdl_profile_encode");
+    for (int st = 0; st < RDL_NSTAGES; ++st) ms[st] = (float)(acc[st] / reps);
+    return RDL_OK;
 }
 
 }  // extern "C"

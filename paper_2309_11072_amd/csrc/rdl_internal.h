@@ -9,16 +9,27 @@
 namespace rdl {
 
 // Work decomposition, fixed for every stage kernel.
-constexpr int KS_THREADS = 256;    // key statistic: 256 lanes x 16 px
-constexpr int KS_PX_PER_WG = 4096;
+constexpr int KS_THREADS = 256;    // key statistic: 256 lanes x 64 px
+constexpr int KS_PX_PER_WG = 16384;
+constexpr int KS_STRIPES = 16;     // partial-sum copies per image, so that no
+constexpr int FIT_STRIPES = 4;     //   address takes more than a few atomics
 constexpr int BLK_WG = 32;        // tone map + base layer: 32 blocks of one block row,
 constexpr int BLK_THREADS = 256;   //   8 lanes per block
-constexpr int TILE_H = 16;         // GF-based stages: 16 x 128 px tiles,
+constexpr int STRIP_W = 256;       // GF-based stages (fit, residual, decode): a wave
+constexpr int STRIP_RH = 16;       //   walks 16 rows of a 256-px strip, 4 px per
+constexpr int STRIP_WAVES = 4;     //   lane; 4 waves stacked per workgroup
+constexpr int STRIP_THREADS = 64 * STRIP_WAVES;
+constexpr int STRIP_H = STRIP_RH * STRIP_WAVES;
+constexpr int TILE_H = 16;         // residual histogram: 16 x 128 px tiles,
 constexpr int TILE_W = 128;        //   256 lanes x 8 consecutive px
 constexpr int TILE_THREADS = 256;
 constexpr int RUN = 8;
 constexpr int NSUM = 13;           // n, then (sum s, sum m, sum s^2, sum s m) x 3
-constexpr int SCRATCH_I64 = 2 + 256 * NSUM + 6;  // per image, padded to 64 B
+// Per-image scratch (int64): key-statistic stripes, final sums, sum stripes.
+constexpr int SCR_KS = 0;
+constexpr int SCR_SUMS = 2 * KS_STRIPES;
+constexpr int SCR_PART = SCR_SUMS + 256 * NSUM;
+constexpr int SCRATCH_I64 = SCR_PART + FIT_STRIPES * 256 * NSUM;
 constexpr int GAMMA_LUT_N = 21 * 128;             // float-bit buckets 2^-20 .. 2^1
 
 // One image of a launch.  Every kernel walks a flattened workgroup space over
@@ -30,30 +41,36 @@ struct ImgDesc {
     int16_t *dct;          // optional [3][H8][W8]
     rdl_header *hdr;
     uint8_t *resid;        // 7*H*W
-    int64_t *ks;           // [2] Lambda, N'
-    int64_t *sums;         // [256][13]
+    int64_t *ks;           // [nks][2] partial (Lambda, N'), summed by readers
+    int64_t *sums;         // [256][13] regression sums (written by k_solve)
+    int64_t *part;         // [nfs][256][13] partial regression sums
     int32_t *status;       // decode only, optional
     uint8_t *out_rgbe;     // decode only
     int64_t *hist;         // [3][511] residual histograms
     int32_t H, W, q, flags;
-    int32_t wg_px, wg_blk, wg_tile, pad;
+    int32_t nks, nfs, pad0, pad1;
+    int32_t wg_px, wg_blk, wg_tile, wg_fit, wg_res, pad2;
 };
 
-enum : int32_t { F_ZERO_KS = 1, F_ZERO_SUMS = 2, F_ZERO_HIST = 4 };
+// Accumulator hygiene: scratch stripes are all-zero between launch sequences
+// (zeroed at allocation; k_solve and k_key_total zero what they consume).
+// F_ZERO_* ask k_zero to clear a caller's buffer, F_CLEAN_KS lets the
+// consumer zero the key-statistic stripes (only when they are scratch).
+enum : int32_t { F_ZERO_KS = 1, F_ZERO_SUMS = 2, F_ZERO_HIST = 4, F_CLEAN_KS = 8 };
 
 inline int wgs_px(int H, int W) { return (int)(((int64_t)H * W + KS_PX_PER_WG - 1) / KS_PX_PER_WG); }
 inline int wgs_blk(int H, int W) { return ((H + 7) / 8) * (((W + 7) / 8 + BLK_WG - 1) / BLK_WG); }
 inline int wgs_tile(int H, int W) { return ((H + TILE_H - 1) / TILE_H) * ((W + TILE_W - 1) / TILE_W); }
+inline int wgs_strip(int H, int W) { return ((H + STRIP_H - 1) / STRIP_H) * ((W + STRIP_W - 1) / STRIP_W); }
 
 // Kernel launchers (defined in rdl_kernels.hip).
 hipError_t upload_tables(int *bad_table);
-const uint8_t *dev_gamma_lut();
-const float *dev_gamma_thr();
 void launch_zero(const ImgDesc *d, int n, hipStream_t s);
 void launch_keystat(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_tmo_base(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_fit_sums(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_solve(const ImgDesc *d, int n, hipStream_t s);
+void launch_key_total(const ImgDesc *d, int n, int64_t *out2, hipStream_t s);
 void launch_resid(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_decode(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_hist(const ImgDesc *d, int n, int wgs, hipStream_t s);

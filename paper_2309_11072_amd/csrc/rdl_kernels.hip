@@ -75,7 +75,7 @@ __device__ __forceinline__ int find_img(const ImgDesc *__restrict__ D, int n, in
     int lo = 0, hi = n - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        int w = which == 0 ? D[mid].wg_px : (which == 1 ? D[mid].wg_blk : D[mid].wg_tile);
+        int w = which == 0 ? D[mid].wg_px : which == 1 ? D[mid].wg_blk : which == 2 ? D[mid].wg_tile : which == 3 ? D[mid].wg_fit : D[mid].wg_res;
         if (w <= wg) lo = mid; else hi = mid - 1;
     }
     return uniform(lo);
@@ -87,11 +87,16 @@ __device__ __forceinline__ int64_t floor_div64(int64_t a, int64_t b) {  // b > 0
     return q;
 }
 
-// Key of the global Reinhard operator: Q = floor(-Lambda / N') =
-// 2^16 k_img + f, sigma = (0.18 * 2^(f>>8 / 256)) * 2^((f&255)/65536).
-__device__ void key_params(const int64_t *ks, int &k_img, int &f_key, float &sigma, int64_t &L, int64_t &N) {
-    L = ks[0];
-    N = ks[1];
+// Key of the global Reinhard operator from the nks partial (Lambda, N')
+// pairs: Q = floor(-Lambda / N') = 2^16 k_img + f,
+// sigma = (0.18 * 2^((f >> 8) / 256)) * 2^((f & 255) / 65536).
+__device__ void key_params(const int64_t *ks, int nks, int &k_img, int &f_key, float &sigma, int64_t &L, int64_t &N) {
+    L = 0;
+    N = 0;
+    for (int k = 0; k < nks; ++k) {
+        L += ks[2 * k];
+        N += ks[2 * k + 1];
+    }
     if (N <= 0) { k_img = 0; f_key = 0; sigma = 0.0f; return; }
     int64_t Q = floor_div64(-L, N);
     int64_t k = Q >> 16;
@@ -114,9 +119,9 @@ __global__ __launch_bounds__(256) void k_zero(const ImgDesc *__restrict__ D, int
     const int i = blockIdx.x;
     if (i >= n) return;
     const ImgDesc d = D[i];
-    if ((d.flags & F_ZERO_KS) && d.ks && threadIdx.x < 2) d.ks[threadIdx.x] = 0;
-    if ((d.flags & F_ZERO_SUMS) && d.sums)
-        for (int k = threadIdx.x; k < 256 * NSUM; k += 256) d.sums[k] = 0;
+    if ((d.flags & F_ZERO_KS) && d.ks && threadIdx.x < 2 * d.nks) d.ks[threadIdx.x] = 0;
+    if ((d.flags & F_ZERO_SUMS) && d.part)
+        for (int k = threadIdx.x; k < d.nfs * 256 * NSUM; k += 256) d.part[k] = 0;
     if ((d.flags & F_ZERO_HIST) && d.hist)
         for (int k = threadIdx.x; k < 3 * 511; k += 256) d.hist[k] = 0;
 }
@@ -126,45 +131,55 @@ __global__ __launch_bounds__(256) void k_zero(const ImgDesc *__restrict__ D, int
 // N' = #{E != 0}.  lambda(Y) = 2^16 (floor(log2 Y) - 16) + LOG2F[12 bits of Y
 // after its leading one].  Memory bound: 4 B/px, 128-bit loads.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int64_t lambda_px(uint32_t w, const int32_t *s_log2f) {
-    uint32_t E = w >> 24;
-    uint32_t Y = lum_y(w);
-    int p = 31 - __builtin_clz(Y);
-    int idx = (int)((Y >> (p - 12)) & 4095u);
-    int v = 65536 * (p - 16 + (int)E - 136) + s_log2f[idx];
-    return E ? (int64_t)v : 0;
+__device__ __forceinline__ int lambda_px(uint32_t w, const uint16_t *s_log2f) {
+    const uint32_t E = w >> 24;
+    const uint32_t Y = lum_y(w);
+    const int p = 31 - __builtin_clz(Y);
+    const int idx = (int)((Y >> (p - 12)) & 4095u);
+    const int v = 65536 * (p - 16 + (int)E - 136) + (int)s_log2f[idx];
+    return E ? v : 0;
 }
 
 __global__ __launch_bounds__(KS_THREADS) void k_keystat(const ImgDesc *__restrict__ D, int n) {
-    __shared__ int32_t s_log2f[4096];
+    __shared__ uint16_t s_log2f[4096];  // every entry is below 2^16
     __shared__ int64_t s_red[2][KS_THREADS / 64];
-    for (int k = threadIdx.x; k < 4096; k += KS_THREADS) s_log2f[k] = g_log2f[k];
+    for (int k = threadIdx.x; k < 4096; k += KS_THREADS) s_log2f[k] = (uint16_t)g_log2f[k];
     const int i = find_img(D, n, blockIdx.x, 0);
     const ImgDesc &d = D[i];
     const int64_t npx = (int64_t)d.H * d.W;
-    const int64_t base = (int64_t)(blockIdx.x - d.wg_px) * KS_PX_PER_WG;
+    const int wgl = blockIdx.x - d.wg_px;
+    const int64_t base = (int64_t)wgl * KS_PX_PER_WG;
     __syncthreads();
     int64_t L = 0;
     int cnt = 0;
     const uint32_t *p32 = (const uint32_t *)d.rgbe;
+    const bool al = (reinterpret_cast<uintptr_t>(p32) & 15) == 0;
+    constexpr int NIT = KS_PX_PER_WG / (KS_THREADS * 4);
+    uint4 v[NIT];
 #pragma unroll
-    for (int it = 0; it < KS_PX_PER_WG / (KS_THREADS * 4); ++it) {
-        int64_t px = base + (int64_t)(it * KS_THREADS + threadIdx.x) * 4;
-        uint32_t w[4];
-        if (px + 4 <= npx && ((reinterpret_cast<uintptr_t>(p32 + px) & 15) == 0)) {
-            uint4 v = *reinterpret_cast<const uint4 *>(p32 + px);
-            w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+    for (int it = 0; it < NIT; ++it) {  // all loads in flight before any use
+        const int64_t px = base + (int64_t)(it * KS_THREADS + threadIdx.x) * 4;
+        if (al && px + 4 <= npx) {
+            v[it] = *reinterpret_cast<const uint4 *>(p32 + px);
         } else {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) w[j] = (px + j < npx) ? p32[px + j] : 0u;
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            L += lambda_px(w[j], s_log2f);
-            cnt += (w[j] >> 24) != 0;
+            v[it].x = px + 0 < npx ? p32[px + 0] : 0u;
+            v[it].y = px + 1 < npx ? p32[px + 1] : 0u;
+            v[it].z = px + 2 < npx ? p32[px + 2] : 0u;
+            v[it].w = px + 3 < npx ? p32[px + 3] : 0u;
         }
     }
-    // wave reduction then one atomic per workgroup (integer: order-free)
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const uint32_t w[4] = {v[it].x, v[it].y, v[it].z, v[it].w};
+        int part = 0;  // |part| < 4 * 2^16 * 145: no overflow
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            part += lambda_px(w[j], s_log2f);
+            cnt += (w[j] >> 24) != 0;
+        }
+        L += part;
+    }
+    // wave reduction, then one atomic pair per workgroup into its stripe
     for (int off = 32; off > 0; off >>= 1) {
         L += __shfl_down(L, off, 64);
         cnt += __shfl_down(cnt, off, 64);
@@ -175,9 +190,24 @@ __global__ __launch_bounds__(KS_THREADS) void k_keystat(const ImgDesc *__restric
     if (threadIdx.x == 0) {
         int64_t a = 0, b = 0;
         for (int k = 0; k < KS_THREADS / 64; ++k) { a += s_red[0][k]; b += s_red[1][k]; }
-        atomicAdd((unsigned long long *)&d.ks[0], (unsigned long long)a);
-        atomicAdd((unsigned long long *)&d.ks[1], (unsigned long long)b);
+        unsigned long long *ks = (unsigned long long *)(d.ks + 2 * (wgl % d.nks));
+        atomicAdd(ks, (unsigned long long)a);
+        atomicAdd(ks + 1, (unsigned long long)b);
     }
+}
+
+// Sum of the key-statistic stripes of each image into out2 (stage check).
+__global__ void k_key_total(const ImgDesc *__restrict__ D, int n, int64_t *out2) {
+    const int i = blockIdx.x;
+    if (i >= n || threadIdx.x != 0) return;
+    int64_t L = 0, N = 0;
+    for (int k = 0; k < D[i].nks; ++k) {
+        L += D[i].ks[2 * k];
+        N += D[i].ks[2 * k + 1];
+        if (D[i].flags & F_CLEAN_KS) D[i].ks[2 * k] = D[i].ks[2 * k + 1] = 0;
+    }
+    out2[2 * i] = L;
+    out2[2 * i + 1] = N;
 }
 
 // ---------------------------------------------------------------------------
@@ -297,7 +327,7 @@ __global__ __launch_bounds__(BLK_THREADS) void k_tmo_base(const ImgDesc *__restr
     int k_img, f_key;
     float sigma;
     int64_t L, N;
-    key_params(d.ks, k_img, f_key, sigma, L, N);
+    key_params(d.ks, d.nks, k_img, f_key, sigma, L, N);
     const int kbase = k_img - 136;
     const bool any_lit = N > 0;
 
@@ -440,193 +470,306 @@ __global__ __launch_bounds__(BLK_THREADS) void k_tmo_base(const ImgDesc *__restr
 }
 
 // ---------------------------------------------------------------------------
-// GF-based stages share one tile loader: S for a (TILE_H + 2) x (TILE_W + 2)
-// window with a one-pixel ring, replicated at the image border, one 32-bit
-// word (R | G << 8 | B << 16) per pixel in LDS.
+// GF streaming, shared by the fit, residual and decode kernels.  A wave owns a
+// strip of STRIP_W = 256 px (four consecutive pixels per lane) and STRIP_RH
+// rows.  It walks down its rows holding S of rows y-1, y, y+1 in registers and
+// takes the horizontal neighbours of its four pixels from the adjacent lanes
+// (DPP wave shifts) or, at the strip ends, from one halo pixel per lane (lane
+// 0: left of the strip, every other lane: right of it).  The (1,6,1) filter
+// runs on two packed fields per pixel, lo = R | B << 16 and hi = G; no field
+// exceeds 64 * 255 < 2^16, so packed integer adds never carry across fields.
 // ---------------------------------------------------------------------------
-struct TileLds {
-    uint32_t s[TILE_H + 2][TILE_W + 2];
-};
-
-__device__ __forceinline__ void load_s_tile(TileLds &t, const uint8_t *__restrict__ sdr, int H, int W, int ty0,
-                                            int tx0) {
-    for (int k = threadIdx.x; k < (TILE_H + 2) * (TILE_W + 2); k += TILE_THREADS) {
-        const int ry = k / (TILE_W + 2), rx = k - ry * (TILE_W + 2);
-        const int yy = min(max(ty0 + ry - 1, 0), H - 1);
-        const int xx = min(max(tx0 + rx - 1, 0), W - 1);
-        const uint8_t *p = sdr + 3 * ((int64_t)yy * W + xx);
-        t.s[ry][rx] = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
-    }
+__device__ __forceinline__ uint32_t load_px3(const uint8_t *p) {
+    return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
 }
 
-// S* for the RUN pixels of one lane: (1,6,1) x (1,6,1) / 64, round half up.
-// out[j] packs channel bytes like the tile.
-__device__ __forceinline__ void gf_run(const TileLds &t, int ly, int lx, uint32_t out[RUN]) {
-    int vs[RUN + 2][3];
-#pragma unroll
-    for (int j = 0; j < RUN + 2; ++j) {
-        const uint32_t a = t.s[ly][lx + j], b = t.s[ly + 1][lx + j], c = t.s[ly + 2][lx + j];
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch)
-            vs[j][ch] = (int)((a >> (8 * ch)) & 255u) + 6 * (int)((b >> (8 * ch)) & 255u) + (int)((c >> (8 * ch)) & 255u);
-    }
-#pragma unroll
-    for (int j = 0; j < RUN; ++j) {
-        uint32_t o = 0;
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            const int v = (vs[j][ch] + 6 * vs[j + 1][ch] + vs[j + 2][ch] + 32) >> 6;
-            o |= (uint32_t)v << (8 * ch);
-        }
-        out[j] = o;
-    }
-}
-
-__device__ __forceinline__ void load_rgbe_run(const uint8_t *rgbe, int W, int y, int x, int nx, uint32_t w[RUN]) {
-    const uint32_t *row = (const uint32_t *)rgbe + (int64_t)y * W;
-    if (nx == RUN && ((reinterpret_cast<uintptr_t>(row + x) & 15) == 0)) {
-        const uint4 a = *reinterpret_cast<const uint4 *>(row + x);
-        const uint4 b = *reinterpret_cast<const uint4 *>(row + x + 4);
-        w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
-        w[4] = b.x; w[5] = b.y; w[6] = b.z; w[7] = b.w;
+// Pixels x .. x+3 of row y of S as R | G << 8 | B << 16 (top byte
+// unspecified); a pixel at x >= W repeats pixel W-1.  `end` bounds the S
+// buffer: the aligned 16-byte read is used only when it stays inside.
+__device__ __forceinline__ void load_quad(const uint8_t *__restrict__ sdr, uintptr_t end, int W, int y, int x,
+                                          uint32_t p[4]) {
+    const uint8_t *a = sdr + 3 * ((int64_t)y * W + x);
+    const uintptr_t al = reinterpret_cast<uintptr_t>(a) & ~(uintptr_t)3;
+    if (x + 4 <= W && al + 16 <= end) {
+        const uint32_t *q = reinterpret_cast<const uint32_t *>(al);
+        const uint32_t sh = (uint32_t)(reinterpret_cast<uintptr_t>(a) & 3);
+        const uint32_t d0 = q[0], d1 = q[1], d2 = q[2], d3 = q[3];
+        const uint32_t e0 = __builtin_amdgcn_alignbyte(d1, d0, sh);
+        const uint32_t e1 = __builtin_amdgcn_alignbyte(d2, d1, sh);
+        const uint32_t e2 = __builtin_amdgcn_alignbyte(d3, d2, sh);
+        p[0] = e0;
+        p[1] = __builtin_amdgcn_alignbyte(e1, e0, 3);
+        p[2] = __builtin_amdgcn_alignbyte(e2, e1, 2);
+        p[3] = e2 >> 8;
     } else {
 #pragma unroll
-        for (int j = 0; j < RUN; ++j) w[j] = row[x + min(j, nx - 1)];
+        for (int j = 0; j < 4; ++j) p[j] = load_px3(sdr + 3 * ((int64_t)y * W + min(x + j, W - 1)));
     }
+}
+
+// RGBE words of pixels x .. x+3 of row y (x >= W repeats W-1).
+__device__ __forceinline__ void load_rgbe4(const uint8_t *__restrict__ rgbe, int W, int y, int x, uint32_t w[4]) {
+    const uint32_t *row = reinterpret_cast<const uint32_t *>(rgbe) + (int64_t)y * W;
+    if (x + 4 <= W && (reinterpret_cast<uintptr_t>(row + x) & 15) == 0) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(row + x);
+        w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) w[j] = row[min(x + j, W - 1)];
+    }
+}
+
+__device__ __forceinline__ uint32_t dpp_from_left(uint32_t v) {  // lane l gets lane l-1
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t dpp_from_right(uint32_t v) {  // lane l gets lane l+1
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xF, 0xF, false);
+}
+
+struct GfWindow {
+    uint32_t lo[3][4], hi[3][4];  // rows y-1, y, y+1 of the lane's pixels
+    uint32_t hlo[3], hhi[3];      // the same rows of the lane's halo pixel
+};
+
+__device__ __forceinline__ void gf_load_row(GfWindow &g, int slot, const uint8_t *__restrict__ sdr, uintptr_t end,
+                                            int H, int W, int y, int x, int hx) {
+    const int yy = min(max(y, 0), H - 1);
+    uint32_t p[4];
+    load_quad(sdr, end, W, yy, x, p);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        g.lo[slot][j] = p[j] & 0x00FF00FFu;
+        g.hi[slot][j] = (p[j] >> 8) & 0xFFu;
+    }
+    const uint32_t h = load_px3(sdr + 3 * ((int64_t)yy * W + hx));
+    g.hlo[slot] = h & 0x00FF00FFu;
+    g.hhi[slot] = (h >> 8) & 0xFFu;
+}
+
+__device__ __forceinline__ void gf_roll(GfWindow &g) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        g.lo[0][j] = g.lo[1][j]; g.lo[1][j] = g.lo[2][j];
+        g.hi[0][j] = g.hi[1][j]; g.hi[1][j] = g.hi[2][j];
+    }
+    g.hlo[0] = g.hlo[1]; g.hlo[1] = g.hlo[2];
+    g.hhi[0] = g.hhi[1]; g.hhi[1] = g.hhi[2];
+}
+
+__device__ __forceinline__ uint32_t vsum(uint32_t a, uint32_t b, uint32_t c) { return a + c + __umul24(b, 6u); }
+__device__ __forceinline__ uint32_t hsum(uint32_t l, uint32_t m, uint32_t r) { return l + r + (m << 2) + (m << 1); }
+
+// S* of the lane's four pixels for the middle row: s[c][j], c = R, G, B.
+// Must be called by the whole wave (DPP).
+__device__ __forceinline__ void gf_quad(const GfWindow &g, int lane, int s[3][4]) {
+    uint32_t vlo[4], vhi[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        vlo[j] = vsum(g.lo[0][j], g.lo[1][j], g.lo[2][j]);
+        vhi[j] = vsum(g.hi[0][j], g.hi[1][j], g.hi[2][j]);
+    }
+    const uint32_t hvlo = vsum(g.hlo[0], g.hlo[1], g.hlo[2]), hvhi = vsum(g.hhi[0], g.hhi[1], g.hhi[2]);
+    uint32_t llo = dpp_from_left(vlo[3]), lhi = dpp_from_left(vhi[3]);
+    uint32_t rlo = dpp_from_right(vlo[0]), rhi = dpp_from_right(vhi[0]);
+    if (lane == 0) { llo = hvlo; lhi = hvhi; }
+    if (lane == 63) { rlo = hvlo; rhi = hvhi; }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t Llo = j == 0 ? llo : vlo[j - 1], Lhi = j == 0 ? lhi : vhi[j - 1];
+        const uint32_t Rlo = j == 3 ? rlo : vlo[j + 1], Rhi = j == 3 ? rhi : vhi[j + 1];
+        const uint32_t tlo = hsum(Llo, vlo[j], Rlo) + 0x00200020u;  // + 32 in each field
+        const uint32_t thi = hsum(Lhi, vhi[j], Rhi) + 32u;
+        s[0][j] = (int)((tlo >> 6) & 255u);
+        s[2][j] = (int)((tlo >> 22) & 255u);
+        s[1][j] = (int)(thi >> 6);
+    }
+}
+
+// The strip of a workgroup and the rows of its wave.
+struct StripPos {
+    int lane, x, hx, ya, yb;
+};
+__device__ __forceinline__ StripPos strip_pos(int wgl, int H, int W) {
+    StripPos p;
+    const int nsx = (W + STRIP_W - 1) / STRIP_W;
+    const int sy = wgl / nsx, sx = wgl - sy * nsx;
+    p.lane = threadIdx.x & 63;
+    const int x0 = sx * STRIP_W;
+    p.x = x0 + 4 * p.lane;
+    p.hx = p.lane == 0 ? max(x0 - 1, 0) : min(x0 + STRIP_W, W - 1);
+    p.ya = sy * STRIP_H + (threadIdx.x >> 6) * STRIP_RH;
+    p.yb = min(p.ya + STRIP_RH, H);
+    return p;
 }
 
 // ---------------------------------------------------------------------------
 // K3 fit sums: per (channel, E) n, sum s, sum m, sum s^2, sum s m over the
-// image (Eq. 9-10), s = S*_c, m = M_c.  Each lane walks its run keeping one
-// register accumulator per exponent run and flushes it into 32-bit LDS bins
-// when E changes; each workgroup then adds its bins into the image's int64
-// sums with integer atomics.
+// image (Eq. 9-10), s = S*_c, m = M_c.  Each lane keeps one register
+// accumulator for its current exponent run and, when E changes, adds it to
+// the workgroup's LDS bins (32-bit totals, added in pairs with 64-bit LDS
+// atomics; a workgroup covers 16384 px, so no total reaches 2^32).  At the
+// end the workgroup adds its present bins into one of the image's int64
+// stripes with integer atomics.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(TILE_THREADS) void k_fit_sums(const ImgDesc *__restrict__ D, int n) {
-    __shared__ TileLds t;
-    __shared__ uint32_t bins[256][NSUM];
-    const int i = find_img(D, n, blockIdx.x, 2);
+__device__ __forceinline__ void flush_run(uint32_t (*bins)[14], int e, uint32_t acc[NSUM]) {
+    unsigned long long *b = reinterpret_cast<unsigned long long *>(&bins[e][0]);
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+        const uint32_t lo = acc[2 * k], hi = 2 * k + 1 < NSUM ? acc[2 * k + 1] : 0u;
+        atomicAdd(b + k, (unsigned long long)lo | ((unsigned long long)hi << 32));
+    }
+#pragma unroll
+    for (int k = 0; k < NSUM; ++k) acc[k] = 0;
+}
+
+__global__ __launch_bounds__(STRIP_THREADS) void k_fit_sums(const ImgDesc *__restrict__ D, int n) {
+    __shared__ __align__(8) uint32_t bins[256][14];
+    const int i = find_img(D, n, blockIdx.x, 3);
     const ImgDesc &d = D[i];
     const int H = d.H, W = d.W;
-    const int ntx = (W + TILE_W - 1) / TILE_W;
-    const int tile = blockIdx.x - d.wg_tile;
-    const int ty0 = (tile / ntx) * TILE_H, tx0 = (tile % ntx) * TILE_W;
-    for (int k = threadIdx.x; k < 256 * NSUM; k += TILE_THREADS) (&bins[0][0])[k] = 0;
-    load_s_tile(t, d.sdr, H, W, ty0, tx0);
+    const int wgl = blockIdx.x - d.wg_fit;
+    for (int k = threadIdx.x; k < 256 * 14; k += STRIP_THREADS) (&bins[0][0])[k] = 0;
     __syncthreads();
-
-    const int ly = threadIdx.x / (TILE_W / RUN), lx = (threadIdx.x % (TILE_W / RUN)) * RUN;
-    const int y = ty0 + ly, x = tx0 + lx;
-    if (y < H && x < W) {
-        const int nx = min(RUN, W - x);
-        uint32_t ss[RUN], w[RUN];
-        gf_run(t, ly, lx, ss);
-        load_rgbe_run(d.rgbe, W, y, x, nx, w);
-        int cur = (int)(w[0] >> 24);
+    const StripPos sp = strip_pos(wgl, H, W);
+    const uintptr_t end = reinterpret_cast<uintptr_t>(d.sdr) + 3 * (uintptr_t)H * W;
+    if (sp.ya < H) {  // uniform per wave
+        GfWindow g;
+        gf_load_row(g, 0, d.sdr, end, H, W, sp.ya - 1, sp.x, sp.hx);
+        gf_load_row(g, 1, d.sdr, end, H, W, sp.ya, sp.x, sp.hx);
+        int cur = -1;
         uint32_t acc[NSUM];
 #pragma unroll
         for (int k = 0; k < NSUM; ++k) acc[k] = 0;
+        for (int y = sp.ya; y < sp.yb; ++y) {
+            gf_load_row(g, 2, d.sdr, end, H, W, y + 1, sp.x, sp.hx);
+            int s[3][4];
+            gf_quad(g, sp.lane, s);
+            uint32_t w[4];
+            load_rgbe4(d.rgbe, W, y, sp.x, w);
 #pragma unroll
-        for (int j = 0; j < RUN; ++j) {
-            if (j < nx) {
-                const int e = (int)(w[j] >> 24);
-                if (e != cur) {
-#pragma unroll
-                    for (int k = 0; k < NSUM; ++k) {
-                        if (acc[k]) atomicAdd(&bins[cur][k], acc[k]);
-                        acc[k] = 0;
+            for (int j = 0; j < 4; ++j) {
+                if (sp.x + j < W) {
+                    const int e = (int)(w[j] >> 24);
+                    if (e != cur) {
+                        if (cur >= 0) flush_run(bins, cur, acc);
+                        cur = e;
                     }
-                    cur = e;
-                }
-                acc[0] += 1;
+                    acc[0] += 1;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const uint32_t s = (ss[j] >> (8 * c)) & 255u, m = (w[j] >> (8 * c)) & 255u;
-                    acc[1 + 4 * c] += s;
-                    acc[2 + 4 * c] += m;
-                    acc[3 + 4 * c] += s * s;
-                    acc[4 + 4 * c] += s * m;
+                    for (int c = 0; c < 3; ++c) {
+                        const uint32_t sv = (uint32_t)s[c][j], m = (w[j] >> (8 * c)) & 255u;
+                        acc[1 + 4 * c] += sv;
+                        acc[2 + 4 * c] += m;
+                        acc[3 + 4 * c] = __umul24(sv, sv) + acc[3 + 4 * c];
+                        acc[4 + 4 * c] = __umul24(sv, m) + acc[4 + 4 * c];
+                    }
                 }
             }
+            gf_roll(g);
         }
-#pragma unroll
-        for (int k = 0; k < NSUM; ++k)
-            if (acc[k]) atomicAdd(&bins[cur][k], acc[k]);
+        if (cur >= 0) flush_run(bins, cur, acc);
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < 256; e += TILE_THREADS) {
+    unsigned long long *gp = (unsigned long long *)(d.part + (int64_t)(wgl % d.nfs) * 256 * NSUM);
+    for (int e = threadIdx.x; e < 256; e += STRIP_THREADS) {
         if (bins[e][0] == 0) continue;
-        unsigned long long *g = (unsigned long long *)(d.sums + (int64_t)e * NSUM);
 #pragma unroll
         for (int k = 0; k < NSUM; ++k)
-            if (bins[e][k]) atomicAdd(g + k, (unsigned long long)bins[e][k]);
+            if (bins[e][k]) atomicAdd(gp + e * NSUM + k, (unsigned long long)bins[e][k]);
     }
 }
-
 // ---------------------------------------------------------------------------
-// K4 solve: one workgroup per image, one lane per exponent value.  Exact
-// 128-bit least squares (Eq. 6-7 / 9-10) with fixed-point rounding:
-// a_q = rhu(2^22 num / den), b_q = rhu((2^22 Sm - a_q Ss) / (2^8 n)).
+// K4 solve: one workgroup per image, one lane per exponent value.  The lane
+// first adds up the image's sum stripes (and writes the totals), then solves
+// the least-squares line exactly in 128-bit integers (Eq. 6-7 / 9-10) with
+// fixed-point rounding: a_q = rhu(2^22 num / den),
+// b_q = rhu((2^22 Sm - a_q Ss) / (2^8 n)).
 // ---------------------------------------------------------------------------
 typedef __int128 i128;
-typedef unsigned __int128 u128;
 
-__device__ __forceinline__ int clz128(u128 v) {
-    const uint64_t hi = (uint64_t)(v >> 64), lo = (uint64_t)v;
-    return hi ? __builtin_clzll(hi) : (lo ? 64 + __builtin_clzll(lo) : 128);
+__device__ __forceinline__ double i128_to_double(i128 v) {
+    const int64_t hi = (int64_t)(v >> 64);
+    const uint64_t lo = (uint64_t)v;
+    return (double)hi * 18446744073709551616.0 + (double)lo;
 }
 
-// Unsigned long division by shift-and-subtract, d > 0.
-__device__ u128 udiv128(u128 num, u128 den) {
-    if (den > num) return 0;
-    const int sh = clz128(den) - clz128(num);
-    den <<= sh;
-    u128 q = 0;
-    for (int k = 0; k <= sh; ++k) {
-        q <<= 1;
-        if (num >= den) { num -= den; q |= 1; }
-        den >>= 1;
-    }
+// floor(N / D) for D > 0 when the quotient is known to be far below 2^50
+// (here |quotient| < 2^32): a float64 estimate is within one of it, and is
+// corrected exactly with the 128-bit remainder.
+__device__ i128 floor_div128(i128 N, i128 D) {
+    const double qd = floor(i128_to_double(N) / i128_to_double(D));
+    int64_t q = (int64_t)qd;
+    i128 r = N - (i128)q * D;
+    for (int k = 0; k < 4 && r < 0; ++k) { q -= 1; r += D; }
+    for (int k = 0; k < 4 && r >= D; ++k) { q += 1; r -= D; }
     return q;
-}
-
-__device__ i128 floor_div128(i128 a, i128 b) {  // b > 0
-    if (a >= 0) return (i128)udiv128((u128)a, (u128)b);
-    return -(i128)udiv128((u128)(-a) + (u128)b - 1, (u128)b);
 }
 
 __device__ __forceinline__ i128 rhu128(i128 x, i128 y) { return floor_div128(2 * x + y, 2 * y); }
 
-__global__ __launch_bounds__(256) void k_solve(const ImgDesc *__restrict__ D, int n) {
+__global__ __launch_bounds__(1024) void k_solve(const ImgDesc *__restrict__ D, int n) {
+    __shared__ int64_t s_b[3][256][NSUM];
+    __shared__ int s_cnt[4];
     const int i = blockIdx.x;
     const ImgDesc &d = D[i];
     rdl_header *h = d.hdr;
-    const int e = threadIdx.x;
-    const int64_t *b = d.sums + (int64_t)e * NSUM;
-    const i128 nn = b[0];
+    const int e = threadIdx.x & 255, g = threadIdx.x >> 8;
+    // Add up the stripes (lane group g takes stripes g, g+4, ...) and leave
+    // them zeroed for the next launch.
+    int64_t b[NSUM];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        int32_t aq = 0, bq = 0;
-        if (nn > 0) {
-            const i128 Ss = b[1 + 4 * c], Sm = b[2 + 4 * c], Sss = b[3 + 4 * c], Ssm = b[4 + 4 * c];
-            const i128 num = nn * Ssm - Ss * Sm;
-            const i128 den = nn * Sss - Ss * Ss;
-            const i128 a = den == 0 ? (i128)0 : rhu128(num * ((i128)1 << 22), den);
-            const i128 bb = rhu128(Sm * ((i128)1 << 22) - a * Ss, nn * 256);
-            aq = (int32_t)a;
-            bq = (int32_t)bb;
+    for (int k = 0; k < NSUM; ++k) b[k] = 0;
+    for (int st = g; st < d.nfs; st += 4) {
+        int64_t *p = d.part + ((int64_t)st * 256 + e) * NSUM;
+#pragma unroll
+        for (int k = 0; k < NSUM; ++k) {
+            b[k] += p[k];
+            p[k] = 0;
         }
-        h->a_q[c][e] = aq;
-        h->b_q[c][e] = bq;
-        h->flag[c][e] = 0;
     }
-    h->present[e] = nn > 0;
-    const int nreg = __syncthreads_count(nn > 0);
-    if (e == 0) {
+    if (g > 0) {
+#pragma unroll
+        for (int k = 0; k < NSUM; ++k) s_b[g - 1][e][k] = b[k];
+    }
+    __syncthreads();
+    bool present = false;
+    if (g == 0) {
+#pragma unroll
+        for (int k = 0; k < NSUM; ++k) b[k] += s_b[0][e][k] + s_b[1][e][k] + s_b[2][e][k];
+#pragma unroll
+        for (int k = 0; k < NSUM; ++k) d.sums[e * NSUM + k] = b[k];
+        const i128 nn = b[0];
+        present = nn > 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            int32_t aq = 0, bq = 0;
+            if (nn > 0) {
+                const i128 Ss = b[1 + 4 * c], Sm = b[2 + 4 * c], Sss = b[3 + 4 * c], Ssm = b[4 + 4 * c];
+                const i128 num = nn * Ssm - Ss * Sm;
+                const i128 den = nn * Sss - Ss * Ss;
+                const i128 a = den == 0 ? (i128)0 : rhu128(num * ((i128)1 << 22), den);
+                const i128 bb = rhu128(Sm * ((i128)1 << 22) - a * Ss, nn * 256);
+                aq = (int32_t)a;
+                bq = (int32_t)bb;
+            }
+            h->a_q[c][e] = aq;
+            h->b_q[c][e] = bq;
+            h->flag[c][e] = 0;
+        }
+        h->present[e] = present;
+        const unsigned long long bal = __ballot(present);
+        if ((e & 63) == 0) s_cnt[e >> 6] = __popcll(bal);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
         int k_img = 0, f_key = 0;
         float sigma = 0.0f;
         int64_t L = 0, N = 0;
-        if (d.ks) key_params(d.ks, k_img, f_key, sigma, L, N);
+        if (d.ks) {
+            key_params(d.ks, d.nks, k_img, f_key, sigma, L, N);
+            if (d.flags & F_CLEAN_KS)
+                for (int k = 0; k < 2 * d.nks; ++k) d.ks[k] = 0;
+        }
         h->magic = RDL_MAGIC;
         h->version = RDL_VERSION;
         h->H = d.H;
@@ -638,74 +781,80 @@ __global__ __launch_bounds__(256) void k_solve(const ImgDesc *__restrict__ D, in
         h->lambda_sum = L;
         h->n_lit = N;
         h->estimator = 0;
-        h->n_regions = nreg;
+        h->n_regions = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
         h->model_hash = 0;
     }
 }
 
 // ---------------------------------------------------------------------------
 // K5 residuals: r = M - M*, M* = clamp((a_q s + 2^8 b_q + 2^21) >> 22, 0, 255)
-// (Eq. 8), written as int16 planes, plus the exponent plane.
+// (Eq. 8), written as int16 planes, plus the exponent plane.  Same strip walk
+// as the fit, with the image's coefficients in LDS.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int mstar(int32_t aq, int32_t bq, int s) {
     const int64_t v = ((int64_t)aq * s + (int64_t)bq * 256 + (1 << 21)) >> 22;
     return (int)min(max(v, (int64_t)0), (int64_t)255);
 }
 
-__global__ __launch_bounds__(TILE_THREADS) void k_resid(const ImgDesc *__restrict__ D, int n) {
-    __shared__ TileLds t;
-    const int i = find_img(D, n, blockIdx.x, 2);
+__global__ __launch_bounds__(STRIP_THREADS) void k_resid(const ImgDesc *__restrict__ D, int n) {
+    __shared__ int2 s_ab[3][256];
+    const int i = find_img(D, n, blockIdx.x, 4);
     const ImgDesc &d = D[i];
     const int H = d.H, W = d.W;
-    const int ntx = (W + TILE_W - 1) / TILE_W;
-    const int tile = blockIdx.x - d.wg_tile;
-    const int ty0 = (tile / ntx) * TILE_H, tx0 = (tile % ntx) * TILE_W;
-    load_s_tile(t, d.sdr, H, W, ty0, tx0);
-    __syncthreads();
-    const int ly = threadIdx.x / (TILE_W / RUN), lx = (threadIdx.x % (TILE_W / RUN)) * RUN;
-    const int y = ty0 + ly, x = tx0 + lx;
-    if (y >= H || x >= W) return;
-    const int nx = min(RUN, W - x);
-    uint32_t ss[RUN], w[RUN];
-    gf_run(t, ly, lx, ss);
-    load_rgbe_run(d.rgbe, W, y, x, nx, w);
+    const int wgl = blockIdx.x - d.wg_res;
     const rdl_header *h = d.hdr;
+    for (int k = threadIdx.x; k < 3 * 256; k += STRIP_THREADS) {
+        const int c = k >> 8, e = k & 255;
+        s_ab[c][e] = make_int2(h->a_q[c][e], h->b_q[c][e]);
+    }
+    __syncthreads();
+    const StripPos sp = strip_pos(wgl, H, W);
+    if (sp.ya >= H) return;  // uniform per wave; no barrier follows
+    const uintptr_t end = reinterpret_cast<uintptr_t>(d.sdr) + 3 * (uintptr_t)H * W;
     const int64_t npx = (int64_t)H * W;
-    const int64_t o = (int64_t)y * W + x;
     int16_t *r = (int16_t *)d.resid;
     uint8_t *Ep = d.resid + 6 * npx;
-    int rv[3][RUN];
+    const bool al = (W & 3) == 0 && ((reinterpret_cast<uintptr_t>(d.resid) & 7) == 0);
+    GfWindow g;
+    gf_load_row(g, 0, d.sdr, end, H, W, sp.ya - 1, sp.x, sp.hx);
+    gf_load_row(g, 1, d.sdr, end, H, W, sp.ya, sp.x, sp.hx);
+    for (int y = sp.ya; y < sp.yb; ++y) {
+        gf_load_row(g, 2, d.sdr, end, H, W, y + 1, sp.x, sp.hx);
+        int s[3][4];
+        gf_quad(g, sp.lane, s);
+        gf_roll(g);
+        if (sp.x >= W) continue;
+        uint32_t w[4];
+        load_rgbe4(d.rgbe, W, y, sp.x, w);
+        int rv[3][4];
 #pragma unroll
-    for (int j = 0; j < RUN; ++j) {
-        const int e = (int)(w[j] >> 24);
+        for (int j = 0; j < 4; ++j) {
+            const int e = (int)(w[j] >> 24);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const int s = (int)((ss[j] >> (8 * c)) & 255u);
-            rv[c][j] = (int)((w[j] >> (8 * c)) & 255u) - mstar(h->a_q[c][e], h->b_q[c][e], s);
+            for (int c = 0; c < 3; ++c) {
+                const int2 ab = s_ab[c][e];
+                rv[c][j] = (int)((w[j] >> (8 * c)) & 255u) - mstar(ab.x, ab.y, s[c][j]);
+            }
         }
-    }
-    const bool vec = nx == RUN && (W & 7) == 0 && ((reinterpret_cast<uintptr_t>(d.resid) & 15) == 0);
+        const int64_t o = (int64_t)y * W + sp.x;
+        if (al && sp.x + 4 <= W) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        int16_t *rp = r + c * npx + o;
-        if (vec) {
-            uint4 v;
-            v.x = (uint32_t)pack_i16(rv[c][0], rv[c][1]);
-            v.y = (uint32_t)pack_i16(rv[c][2], rv[c][3]);
-            v.z = (uint32_t)pack_i16(rv[c][4], rv[c][5]);
-            v.w = (uint32_t)pack_i16(rv[c][6], rv[c][7]);
-            *reinterpret_cast<uint4 *>(rp) = v;
+            for (int c = 0; c < 3; ++c) {
+                uint2 v;
+                v.x = (uint32_t)pack_i16(rv[c][0], rv[c][1]);
+                v.y = (uint32_t)pack_i16(rv[c][2], rv[c][3]);
+                *reinterpret_cast<uint2 *>(r + c * npx + o) = v;
+            }
+            *reinterpret_cast<uint32_t *>(Ep + o) =
+                (w[0] >> 24) | ((w[1] >> 24) << 8) | ((w[2] >> 24) << 16) | ((w[3] >> 24) << 24);
         } else {
-            for (int j = 0; j < nx; ++j) rp[j] = (int16_t)rv[c][j];
+            const int nx = min(4, W - sp.x);
+            for (int j = 0; j < nx; ++j) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) r[c * npx + o + j] = (int16_t)rv[c][j];
+                Ep[o + j] = (uint8_t)(w[j] >> 24);
+            }
         }
-    }
-    if (vec) {
-        uint2 v;
-        v.x = (w[0] >> 24) | ((w[1] >> 24) << 8) | ((w[2] >> 24) << 16) | ((w[3] >> 24) << 24);
-        v.y = (w[4] >> 24) | ((w[5] >> 24) << 8) | ((w[6] >> 24) << 16) | ((w[7] >> 24) << 24);
-        *reinterpret_cast<uint2 *>(Ep + o) = v;
-    } else {
-        for (int j = 0; j < nx; ++j) Ep[o + j] = (uint8_t)(w[j] >> 24);
     }
 }
 
@@ -713,9 +862,9 @@ __global__ __launch_bounds__(TILE_THREADS) void k_resid(const ImgDesc *__restric
 // K6 decode: M = M* + r, RGBE out.  The header is checked first; a mismatch
 // or a mantissa outside [0, 255] sets *status = RDL_ECORRUPT.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(TILE_THREADS) void k_decode(const ImgDesc *__restrict__ D, int n) {
-    __shared__ TileLds t;
-    const int i = find_img(D, n, blockIdx.x, 2);
+__global__ __launch_bounds__(STRIP_THREADS) void k_decode(const ImgDesc *__restrict__ D, int n) {
+    __shared__ int2 s_ab[3][256];
+    const int i = find_img(D, n, blockIdx.x, 4);
     const ImgDesc &d = D[i];
     const int H = d.H, W = d.W;
     const rdl_header *h = d.hdr;
@@ -724,38 +873,45 @@ __global__ __launch_bounds__(TILE_THREADS) void k_decode(const ImgDesc *__restri
         if (threadIdx.x == 0 && d.status) atomicExch(d.status, RDL_ECORRUPT);
         return;
     }
-    const int ntx = (W + TILE_W - 1) / TILE_W;
-    const int tile = blockIdx.x - d.wg_tile;
-    const int ty0 = (tile / ntx) * TILE_H, tx0 = (tile % ntx) * TILE_W;
-    load_s_tile(t, d.sdr, H, W, ty0, tx0);
+    for (int k = threadIdx.x; k < 3 * 256; k += STRIP_THREADS) {
+        const int c = k >> 8, e = k & 255;
+        s_ab[c][e] = make_int2(h->a_q[c][e], h->b_q[c][e]);
+    }
     __syncthreads();
-    const int ly = threadIdx.x / (TILE_W / RUN), lx = (threadIdx.x % (TILE_W / RUN)) * RUN;
-    const int y = ty0 + ly, x = tx0 + lx;
-    if (y >= H || x >= W) return;
-    const int nx = min(RUN, W - x);
-    uint32_t ss[RUN];
-    gf_run(t, ly, lx, ss);
+    const StripPos sp = strip_pos(blockIdx.x - d.wg_res, H, W);
+    if (sp.ya >= H) return;
+    const uintptr_t end = reinterpret_cast<uintptr_t>(d.sdr) + 3 * (uintptr_t)H * W;
     const int64_t npx = (int64_t)H * W;
-    const int64_t o = (int64_t)y * W + x;
     const int16_t *r = (const int16_t *)d.resid;
     const uint8_t *Ep = d.resid + 6 * npx;
-    uint32_t *out = (uint32_t *)d.out_rgbe + o;
+    uint32_t *out = reinterpret_cast<uint32_t *>(d.out_rgbe);
     bool bad = false;
-    for (int j = 0; j < nx; ++j) {
-        const int e = Ep[o + j];
-        uint32_t word = (uint32_t)e << 24;
+    GfWindow g;
+    gf_load_row(g, 0, d.sdr, end, H, W, sp.ya - 1, sp.x, sp.hx);
+    gf_load_row(g, 1, d.sdr, end, H, W, sp.ya, sp.x, sp.hx);
+    for (int y = sp.ya; y < sp.yb; ++y) {
+        gf_load_row(g, 2, d.sdr, end, H, W, y + 1, sp.x, sp.hx);
+        int s[3][4];
+        gf_quad(g, sp.lane, s);
+        gf_roll(g);
+        if (sp.x >= W) continue;
+        const int64_t o = (int64_t)y * W + sp.x;
+        const int nx = min(4, W - sp.x);
+        for (int j = 0; j < nx; ++j) {
+            const int e = Ep[o + j];
+            uint32_t word = (uint32_t)e << 24;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const int s = (int)((ss[j] >> (8 * c)) & 255u);
-            const int m = mstar(h->a_q[c][e], h->b_q[c][e], s) + r[c * npx + o + j];
-            bad |= (m < 0) | (m > 255);
-            word |= (uint32_t)(m & 255) << (8 * c);
+            for (int c = 0; c < 3; ++c) {
+                const int2 ab = s_ab[c][e];
+                const int m = mstar(ab.x, ab.y, s[c][j]) + r[c * npx + o + j];
+                bad |= (m < 0) | (m > 255);
+                word |= (uint32_t)(m & 255) << (8 * c);
+            }
+            out[o + j] = word;
         }
-        out[j] = word;
     }
     if (bad && d.status) atomicExch(d.status, RDL_ECORRUPT);
 }
-
 // ---------------------------------------------------------------------------
 // K7 residual histograms: hist[c][r + 255].
 // ---------------------------------------------------------------------------
@@ -836,14 +992,17 @@ void launch_tmo_base(const ImgDesc *d, int n, int wgs, hipStream_t s) {
     hipLaunchKernelGGL(k_tmo_base, dim3(wgs), dim3(BLK_THREADS), 0, s, d, n);
 }
 void launch_fit_sums(const ImgDesc *d, int n, int wgs, hipStream_t s) {
-    hipLaunchKernelGGL(k_fit_sums, dim3(wgs), dim3(TILE_THREADS), 0, s, d, n);
+    hipLaunchKernelGGL(k_fit_sums, dim3(wgs), dim3(STRIP_THREADS), 0, s, d, n);
 }
-void launch_solve(const ImgDesc *d, int n, hipStream_t s) { hipLaunchKernelGGL(k_solve, dim3(n), dim3(256), 0, s, d, n); }
+void launch_solve(const ImgDesc *d, int n, hipStream_t s) { hipLaunchKernelGGL(k_solve, dim3(n), dim3(1024), 0, s, d, n); }
+void launch_key_total(const ImgDesc *d, int n, int64_t *out2, hipStream_t s) {
+    hipLaunchKernelGGL(k_key_total, dim3(n), dim3(64), 0, s, d, n, out2);
+}
 void launch_resid(const ImgDesc *d, int n, int wgs, hipStream_t s) {
-    hipLaunchKernelGGL(k_resid, dim3(wgs), dim3(TILE_THREADS), 0, s, d, n);
+    hipLaunchKernelGGL(k_resid, dim3(wgs), dim3(STRIP_THREADS), 0, s, d, n);
 }
 void launch_decode(const ImgDesc *d, int n, int wgs, hipStream_t s) {
-    hipLaunchKernelGGL(k_decode, dim3(wgs), dim3(TILE_THREADS), 0, s, d, n);
+    hipLaunchKernelGGL(k_decode, dim3(wgs), dim3(STRIP_THREADS), 0, s, d, n);
 }
 void launch_hist(const ImgDesc *d, int n, int wgs, hipStream_t s) {
     hipLaunchKernelGGL(k_hist, dim3(wgs), dim3(TILE_THREADS), 0, s, d, n);

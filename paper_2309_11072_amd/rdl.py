@@ -45,7 +45,11 @@ _SIGS = {
     "rdl_stage_tmo_base": ([_vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp], _i),
     "rdl_stage_fit": ([_vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp], _i),
     "rdl_stage_resid": ([_vp, _vp, _vp, _vp, _i, _i, _vp, _vp], _i),
+    "rdl_profile_encode": ([_vp, _vp, _i, _i, _i, _vp, _vp, _vp, _i, _vp, _vp], _i),
 }
+
+STAGES = ("keystat", "tmo_base", "fit_sums", "solve", "resid")
+KERNELS = ("k_keystat", "k_tmo_base", "k_fit_sums", "k_solve", "k_resid")
 
 
 class RdlImage(C.Structure):
@@ -170,6 +174,15 @@ class Codec:
         hist = torch.empty((3, 511), dtype=torch.int64, device=resid.device)
         _chk(self._L.rdl_resid_hist(self._h, _ptr(resid), H, W, _ptr(hist), _stream(stream)), "rdl_resid_hist")
         return hist
+
+    def profile_encode(self, rgbe: torch.Tensor, q: int, out, reps: int = 20, stream=None):
+        """Mean duration in ms of each stage kernel (HIP events on the stream)."""
+        H, W = int(rgbe.shape[0]), int(rgbe.shape[1])
+        sdr, hdr, resid = out
+        ms = (C.c_float * len(STAGES))()
+        _chk(self._L.rdl_profile_encode(self._h, _ptr(rgbe), H, W, int(q), _ptr(sdr), _ptr(hdr), _ptr(resid), int(reps),
+                                        ms, _stream(stream)), "rdl_profile_encode")
+        return dict(zip(STAGES, [float(v) for v in ms]))
 
     # -------------------------------------------------------------- stages
     def stage_keystat(self, rgbe: torch.Tensor, stream=None):

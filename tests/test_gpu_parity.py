@@ -81,6 +81,10 @@ def test_stages_match_oracle(codec, O, name, x, q):
     a, b, pr = O.solve(sums_ref)
     sums, hdr = codec.stage_fit(d, sdr, q, ks)
     assert np.array_equal(sums.cpu().numpy(), sums_ref), "regression sums"
+    # the accumulators are left clean: a second fit gives the same sums
+    sums2, _ = codec.stage_fit(d, sdr, q, ks)
+    assert np.array_equal(sums2.cpu().numpy(), sums_ref), "regression sums, second call"
+    assert codec.stage_keystat(d).cpu().tolist() == [lam, n]
     from paper_2309_11072_amd import rdl
     h = rdl.header_from_bytes(hdr)
     assert np.array_equal(h["a_q"], a) and np.array_equal(h["b_q"], b)
