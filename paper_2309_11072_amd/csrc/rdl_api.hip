@@ -138,7 +138,7 @@ int check_launch(const char *what) {
 // scratch accumulators are zero on entry and k_solve leaves them zero.
 void enqueue_encode(const ImgDesc *d, int n, const Grid &g, hipStream_t s) {
     launch_keystat(d, n, g.px, s);
-    launch_tmo_base(d, n, g.blk, s);
+    launch_tmo_base(d, n, g.blk, false, s);
     launch_fit_sums(d, n, g.fit, s);
     launch_solve(d, n, s);
     launch_resid(d, n, g.res, s);
@@ -397,7 +397,7 @@ int rdl_stage_tmo_base(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int q, con
     const Grid gr = layout(v);
     int rc = upload(c, v, s);
     if (rc) return rc;
-    launch_tmo_base(c->d_desc, 1, gr.blk, s);
+    launch_tmo_base(c->d_desc, 1, gr.blk, out_sdr0 != nullptr || out_dct != nullptr, s);
     return check_launch("k_tmo_base");
 }
 
@@ -481,7 +481,7 @@ int rdl_profile_encode(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int q, uin
             (void)hipEventRecord(ev[2 * st], s);
             switch (st) {
                 case RDL_STAGE_KEYSTAT: launch_keystat(d, 1, gr.px, s); break;
-                case RDL_STAGE_TMO_BASE: launch_tmo_base(d, 1, gr.blk, s); break;
+                case RDL_STAGE_TMO_BASE: launch_tmo_base(d, 1, gr.blk, false, s); break;
                 case RDL_STAGE_FIT: launch_fit_sums(d, 1, gr.fit, s); break;
                 case RDL_STAGE_SOLVE: launch_solve(d, 1, s); break;
                 case RDL_STAGE_RESID: launch_resid(d, 1, gr.res, s); break;

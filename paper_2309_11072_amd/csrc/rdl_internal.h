@@ -9,7 +9,7 @@
 namespace rdl {
 
 // Work decomposition, fixed for every stage kernel.
-constexpr int KS_THREADS = 256;    // key statistic: 256 lanes x 64 px
+constexpr int KS_THREADS = 512;    // key statistic: 512 lanes x 32 px
 constexpr int KS_PX_PER_WG = 16384;
 constexpr int KS_STRIPES = 16;     // partial-sum copies per image, so that no
 constexpr int FIT_STRIPES = 4;     //   address takes more than a few atomics
@@ -27,7 +27,7 @@ constexpr int RUN = 8;
 constexpr int NSUM = 13;           // n, then (sum s, sum m, sum s^2, sum s m) x 3
 // Per-image scratch (int64): key-statistic stripes, final sums, sum stripes.
 constexpr int SCR_KS = 0;
-constexpr int SCR_SUMS = 2 * KS_STRIPES;
+constexpr int SCR_SUMS = SCR_KS + 2 * KS_STRIPES;
 constexpr int SCR_PART = SCR_SUMS + 256 * NSUM;
 constexpr int SCRATCH_I64 = SCR_PART + FIT_STRIPES * 256 * NSUM;
 constexpr int GAMMA_LUT_N = 21 * 128;             // float-bit buckets 2^-20 .. 2^1
@@ -54,8 +54,8 @@ struct ImgDesc {
 
 // Accumulator hygiene: scratch stripes are all-zero between launch sequences
 // (zeroed at allocation; k_solve and k_key_total zero what they consume).
-// F_ZERO_* ask k_zero to clear a caller's buffer, F_CLEAN_KS lets the
-// consumer zero the key-statistic stripes (only when they are scratch).
+// F_ZERO_* ask k_zero to clear a caller's buffer; F_CLEAN_KS lets the last
+// consumer zero the key-statistic stripes (set only when they are scratch).
 enum : int32_t { F_ZERO_KS = 1, F_ZERO_SUMS = 2, F_ZERO_HIST = 4, F_CLEAN_KS = 8 };
 
 inline int wgs_px(int H, int W) { return (int)(((int64_t)H * W + KS_PX_PER_WG - 1) / KS_PX_PER_WG); }
@@ -67,7 +67,7 @@ inline int wgs_strip(int H, int W) { return ((H + STRIP_H - 1) / STRIP_H) * ((W 
 hipError_t upload_tables(int *bad_table);
 void launch_zero(const ImgDesc *d, int n, hipStream_t s);
 void launch_keystat(const ImgDesc *d, int n, int wgs, hipStream_t s);
-void launch_tmo_base(const ImgDesc *d, int n, int wgs, hipStream_t s);
+void launch_tmo_base(const ImgDesc *d, int n, int wgs, bool extra, hipStream_t s);
 void launch_fit_sums(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_solve(const ImgDesc *d, int n, hipStream_t s);
 void launch_key_total(const ImgDesc *d, int n, int64_t *out2, hipStream_t s);

@@ -87,9 +87,21 @@ __device__ __forceinline__ int64_t floor_div64(int64_t a, int64_t b) {  // b > 0
     return q;
 }
 
-// Key of the global Reinhard operator from the nks partial (Lambda, N')
-// pairs: Q = floor(-Lambda / N') = 2^16 k_img + f,
-// sigma = (0.18 * 2^((f >> 8) / 256)) * 2^((f & 255) / 65536).
+// Key of the global Reinhard operator: Q = floor(-Lambda / N') =
+// 2^16 k_img + f, sigma = (0.18 * 2^((f >> 8) / 256)) * 2^((f & 255) / 65536).
+__device__ void key_from(int64_t L, int64_t N, int &k_img, int &f_key, float &sigma) {
+    if (N <= 0) { k_img = 0; f_key = 0; sigma = 0.0f; return; }
+    const int64_t Q = floor_div64(-L, N);
+    const int64_t k = Q >> 16;
+    const int f = (int)(Q - k * 65536);
+    float s = 0.18f * g_exp2h[f >> 8];
+    s = s * g_exp2l[f & 255];
+    k_img = (int)k;
+    f_key = f;
+    sigma = s;
+}
+
+// The same from nks partial (Lambda, N') pairs.
 __device__ void key_params(const int64_t *ks, int nks, int &k_img, int &f_key, float &sigma, int64_t &L, int64_t &N) {
     L = 0;
     N = 0;
@@ -97,15 +109,7 @@ __device__ void key_params(const int64_t *ks, int nks, int &k_img, int &f_key, f
         L += ks[2 * k];
         N += ks[2 * k + 1];
     }
-    if (N <= 0) { k_img = 0; f_key = 0; sigma = 0.0f; return; }
-    int64_t Q = floor_div64(-L, N);
-    int64_t k = Q >> 16;
-    int f = (int)(Q - k * 65536);
-    float s = 0.18f * g_exp2h[f >> 8];
-    s = s * g_exp2l[f & 255];
-    k_img = (int)k;
-    f_key = f;
-    sigma = s;
+    key_from(L, N, k_img, f_key, sigma);
 }
 
 __device__ __forceinline__ uint32_t lum_y(uint32_t w) {
@@ -143,21 +147,18 @@ __device__ __forceinline__ int lambda_px(uint32_t w, const uint16_t *s_log2f) {
 __global__ __launch_bounds__(KS_THREADS) void k_keystat(const ImgDesc *__restrict__ D, int n) {
     __shared__ uint16_t s_log2f[4096];  // every entry is below 2^16
     __shared__ int64_t s_red[2][KS_THREADS / 64];
-    for (int k = threadIdx.x; k < 4096; k += KS_THREADS) s_log2f[k] = (uint16_t)g_log2f[k];
     const int i = find_img(D, n, blockIdx.x, 0);
     const ImgDesc &d = D[i];
     const int64_t npx = (int64_t)d.H * d.W;
     const int wgl = blockIdx.x - d.wg_px;
     const int64_t base = (int64_t)wgl * KS_PX_PER_WG;
-    __syncthreads();
-    int64_t L = 0;
-    int cnt = 0;
     const uint32_t *p32 = (const uint32_t *)d.rgbe;
     const bool al = (reinterpret_cast<uintptr_t>(p32) & 15) == 0;
+    // Pixel loads first (they do not depend on the table), then the table.
     constexpr int NIT = KS_PX_PER_WG / (KS_THREADS * 4);
     uint4 v[NIT];
 #pragma unroll
-    for (int it = 0; it < NIT; ++it) {  // all loads in flight before any use
+    for (int it = 0; it < NIT; ++it) {
         const int64_t px = base + (int64_t)(it * KS_THREADS + threadIdx.x) * 4;
         if (al && px + 4 <= npx) {
             v[it] = *reinterpret_cast<const uint4 *>(p32 + px);
@@ -168,6 +169,10 @@ __global__ __launch_bounds__(KS_THREADS) void k_keystat(const ImgDesc *__restric
             v[it].w = px + 3 < npx ? p32[px + 3] : 0u;
         }
     }
+    for (int k = threadIdx.x; k < 4096; k += KS_THREADS) s_log2f[k] = (uint16_t)g_log2f[k];
+    __syncthreads();
+    int64_t L = 0;
+    int cnt = 0;
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
         const uint32_t w[4] = {v[it].x, v[it].y, v[it].z, v[it].w};
@@ -196,7 +201,8 @@ __global__ __launch_bounds__(KS_THREADS) void k_keystat(const ImgDesc *__restric
     }
 }
 
-// Sum of the key-statistic stripes of each image into out2 (stage check).
+// Sum of the key-statistic stripes of each image into out2 (stage check);
+// the scratch stripes are left zero.
 __global__ void k_key_total(const ImgDesc *__restrict__ D, int n, int64_t *out2) {
     const int i = blockIdx.x;
     if (i >= n || threadIdx.x != 0) return;
@@ -251,19 +257,6 @@ __device__ __forceinline__ void tmo_px(uint32_t w, int kbase, float sigma, bool 
     b = zero ? 0 : gamma_code(c2, lut, thr);
 }
 
-__device__ __forceinline__ void rgb_to_ycc(int R, int G, int B, int &Y, int &Cb, int &Cr) {
-    Y = (19595 * R + 38470 * G + 7471 * B + 32768) >> 16;
-    Cb = (-11058 * R - 21710 * G + 32768 * B + 8388608 + 32768) >> 16;
-    Cr = (32768 * R - 27439 * G - 5329 * B + 8388608 + 32768) >> 16;
-}
-
-__device__ __forceinline__ void ycc_to_rgb(int Y, int Cb, int Cr, int &R, int &G, int &B) {
-    const int cb = Cb - 128, cr = Cr - 128;
-    R = min(max(Y + ((91881 * cr + 32768) >> 16), 0), 255);
-    G = min(max(Y + ((-22554 * cb - 46802 * cr + 32768) >> 16), 0), 255);
-    B = min(max(Y + ((116130 * cb + 32768) >> 16), 0), 255);
-}
-
 __device__ __forceinline__ int padd(int a, int b) {
     return __builtin_bit_cast(int, __builtin_bit_cast(short2v, a) + __builtin_bit_cast(short2v, b));
 }
@@ -300,23 +293,37 @@ __device__ __forceinline__ void idct1(int E0, int E1, int O0, int O1, int bias, 
     }
 }
 
+// Per-lane constants of the quantiser for coefficient (v, u): qm = M | Q << 24
+// with M = ceil(2^20 / Q), so floor(a / Q) == (a * M) >> 20 for a < 4096.
+__device__ __forceinline__ int quant_dequant(int F, uint32_t qm, int &Fq) {
+    const int f = F >> 15;
+    const int sg = f >> 31;                          // 0 or -1
+    const uint32_t af = (uint32_t)((f ^ sg) - sg);   // |f|
+    const uint32_t qa = __umul24(af + (qm >> 25), qm) >> 20;
+    Fq = ((int)qa ^ sg) - sg;
+    const int da = (int)__umul24(qa, qm >> 24);
+    return (da ^ sg) - sg;
+}
+
+template <bool EXTRA>
 __global__ __launch_bounds__(BLK_THREADS) void k_tmo_base(const ImgDesc *__restrict__ D, int n) {
     // A workgroup owns a strip of BLK_WG horizontally adjacent 8x8 blocks of
     // one block row.  Lane t works on block j = t % BLK_WG as its row (phases
     // 1 and 3) or column (phase 2) r = t / BLK_WG; two LDS transposes join the
     // phases.  Slot stride 33 words keeps every half-wave access conflict-free.
+    // EXTRA also writes the tone-mapped SDRI and the quantised coefficients.
     __shared__ uint8_t s_lut[GAMMA_LUT_N];
     __shared__ float s_thr[257];
-    __shared__ uint32_t s_QM[2][64];  // ceil(2^20 / Q) | Q << 24
+    __shared__ uint32_t s_QM[2][64];
     __shared__ uint32_t s_X[3][BLK_WG][33];
+    __shared__ int s_key[3];
     const int i = find_img(D, n, blockIdx.x, 1);
     const ImgDesc &d = D[i];
     const int H = d.H, W = d.W;
     for (int k = threadIdx.x; k < GAMMA_LUT_N; k += BLK_THREADS) s_lut[k] = g_glut[k];
     for (int k = threadIdx.x; k < 257; k += BLK_THREADS) s_thr[k] = g_thr[k];
     if (threadIdx.x < 128) {
-        // IJG quality scaling of the Annex K tables, and a 20-bit reciprocal
-        // per entry: floor(a / Q) == (a * ceil(2^20 / Q)) >> 20 for a < 4096.
+        // IJG quality scaling of the Annex K tables.
         const int t = threadIdx.x >> 6, e = threadIdx.x & 63;
         const int q = d.q;
         const int s = q < 50 ? 5000 / q : 200 - 2 * q;
@@ -324,12 +331,15 @@ __global__ __launch_bounds__(BLK_THREADS) void k_tmo_base(const ImgDesc *__restr
         Qv = min(max(Qv, 1), 255);
         s_QM[t][e] = (((1u << 20) + (uint32_t)Qv - 1u) / (uint32_t)Qv) | ((uint32_t)Qv << 24);
     }
-    int k_img, f_key;
-    float sigma;
-    int64_t L, N;
-    key_params(d.ks, d.nks, k_img, f_key, sigma, L, N);
-    const int kbase = k_img - 136;
-    const bool any_lit = N > 0;
+    if (threadIdx.x == 0) {
+        int k_img, f_key;
+        float sigma;
+        int64_t L, N;
+        key_params(d.ks, d.nks, k_img, f_key, sigma, L, N);
+        s_key[0] = k_img - 136;
+        s_key[1] = __float_as_int(sigma);
+        s_key[2] = N > 0;
+    }
 
     const int nbx = (W + 7) >> 3, nby = (H + 7) >> 3;
     const int nstrip = (nbx + BLK_WG - 1) / BLK_WG;
@@ -340,10 +350,13 @@ __global__ __launch_bounds__(BLK_THREADS) void k_tmo_base(const ImgDesc *__restr
     const bool active = bx < nbx && by < nby;
     const int x0 = bx * 8;
     __syncthreads();
+    const int kbase = s_key[0];
+    const float sigma = __int_as_float(s_key[1]);
+    const bool any_lit = s_key[2] != 0;
 
-    // Phase 1: lane = row r.  RGBE -> TMO -> YCbCr -> FDCT row pass; the row
-    // outputs go to the slot transposed, at position r ^ (r >> 2) of column u,
-    // so a column reads back as the pairs (0,1), (2,3), (5,4), (7,6).
+    // Phase 1: lane = row r.  RGBE -> TMO -> YCbCr - 128 -> FDCT row pass; the
+    // row outputs go to the slot transposed, at position r ^ (r >> 2) of
+    // column u, so a column reads back as the pairs (0,1), (2,3), (5,4), (7,6).
     if (active) {
         const int yl = by * 8 + r;
         const uint32_t *row = (const uint32_t *)d.rgbe + (int64_t)min(yl, H - 1) * W;
@@ -360,15 +373,15 @@ __global__ __launch_bounds__(BLK_THREADS) void k_tmo_base(const ImgDesc *__restr
         for (int x = 0; x < 8; ++x) {
             int cr, cg, cb;
             tmo_px(px[x], kbase, sigma, any_lit, s_lut, s_thr, cr, cg, cb);
-            if (d.sdr0 && yl < H && x0 + x < W) {
+            if (EXTRA && d.sdr0 && yl < H && x0 + x < W) {
                 uint8_t *o = d.sdr0 + 3 * ((int64_t)yl * W + x0 + x);
                 o[0] = (uint8_t)cr; o[1] = (uint8_t)cg; o[2] = (uint8_t)cb;
             }
-            int Y, Cb, Cr;
-            rgb_to_ycc(cr, cg, cb, Y, Cb, Cr);
-            ch[0][x] = Y - 128;
-            ch[1][x] = Cb - 128;
-            ch[2][x] = Cr - 128;
+            // JFIF forward transform with the level shift folded into the
+            // rounding constant (a multiple of 2^16 passes through the shift).
+            ch[0][x] = (19595 * cr + 38470 * cg + 7471 * cb + 32768 - (128 << 16)) >> 16;
+            ch[1][x] = (-11058 * cr - 21710 * cg + 32768 * cb + 32768) >> 16;
+            ch[2][x] = (32768 * cr - 27439 * cg - 5329 * cb + 32768) >> 16;
         }
         const int pos = r ^ (r >> 2);
 #pragma unroll
@@ -394,26 +407,26 @@ __global__ __launch_bounds__(BLK_THREADS) void k_tmo_base(const ImgDesc *__restr
     for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int k = 0; k < 4; ++k) col[c][k] = (int)s_X[c][j][u * 4 + k];
+    uint32_t qm[2][8];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) qm[t][v] = s_QM[t][v * 8 + u];
     __syncthreads();
     if (active) {
         const int H8 = nby * 8, W8 = nbx * 8;
         const int pos2 = (u & 1) * 4 + (u >> 1);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const uint32_t *QM = s_QM[c ? 1 : 0];
             int F[8];
             fdct1(padd(col[c][0], col[c][3]), padd(col[c][1], col[c][2]), psub(col[c][0], col[c][3]),
                   psub(col[c][1], col[c][2]), 16384, F);
             int dq[8];
 #pragma unroll
             for (int v = 0; v < 8; ++v) {
-                const int f = F[v] >> 15;
-                const uint32_t qm = QM[v * 8 + u];
-                const uint32_t a = (uint32_t)abs(f) + (qm >> 25);
-                const int qa = (int)(__umul24(a, qm) >> 20);
-                const int Fq = f < 0 ? -qa : qa;
-                if (d.dct) d.dct[((int64_t)c * H8 + by * 8 + v) * W8 + x0 + u] = (int16_t)Fq;
-                dq[v] = Fq * (int)(qm >> 24);
+                int Fq;
+                dq[v] = quant_dequant(F[v], qm[c ? 1 : 0][v], Fq);
+                if (EXTRA && d.dct) d.dct[((int64_t)c * H8 + by * 8 + v) * W8 + x0 + u] = (int16_t)Fq;
             }
             int t[8];
             idct1(pack_i16(dq[0], dq[2]), pack_i16(dq[4], dq[6]), pack_i16(dq[1], dq[3]), pack_i16(dq[5], dq[7]), 1024, t);
@@ -430,42 +443,39 @@ __global__ __launch_bounds__(BLK_THREADS) void k_tmo_base(const ImgDesc *__restr
     const int y = r;
     const int yy = by * 8 + y;
     if (yy >= H) return;
-    uint32_t rec[3][2];
+    int smp[3][8];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const uint32_t *rw = &s_X[c][j][y * 4];
         int o[8];
         idct1((int)rw[0], (int)rw[1], (int)rw[2], (int)rw[3], 16384 + (128 << 15), o);
-        uint32_t w0 = 0, w1 = 0;
 #pragma unroll
-        for (int x = 0; x < 8; ++x) {
-            const uint32_t v = (uint32_t)min(max(o[x] >> 15, 0), 255);
-            if (x < 4) w0 |= v << (8 * x); else w1 |= v << (8 * (x - 4));
-        }
-        rec[c][0] = w0;
-        rec[c][1] = w1;
+        for (int x = 0; x < 8; ++x) smp[c][x] = min(max(o[x] >> 15, 0), 255);
     }
-    uint8_t *orow = d.sdr + 3 * ((int64_t)yy * W + x0);
-    uint32_t o[6];
+    uint32_t ow[6];
 #pragma unroll
     for (int x = 0; x < 8; ++x) {
-        const int sh = 8 * (x & 3), wd = x >> 2;
-        int R, G, B;
-        ycc_to_rgb((rec[0][wd] >> sh) & 255, (rec[1][wd] >> sh) & 255, (rec[2][wd] >> sh) & 255, R, G, B);
+        // JFIF inverse transform; the chroma offset of 128 is folded into the
+        // rounding constants.
+        const int Yv = smp[0][x], cb = smp[1][x], cr = smp[2][x];
+        const int R = min(max(Yv + ((91881 * cr + 32768 - 91881 * 128) >> 16), 0), 255);
+        const int G = min(max(Yv + ((-22554 * cb - 46802 * cr + 32768 + (22554 + 46802) * 128) >> 16), 0), 255);
+        const int B = min(max(Yv + ((116130 * cb + 32768 - 116130 * 128) >> 16), 0), 255);
         const uint32_t rgb = (uint32_t)R | ((uint32_t)G << 8) | ((uint32_t)B << 16);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const int p = 3 * x + k;
             const uint32_t byte = (rgb >> (8 * k)) & 255u;
-            if ((p & 3) == 0) o[p >> 2] = byte; else o[p >> 2] |= byte << (8 * (p & 3));
+            if ((p & 3) == 0) ow[p >> 2] = byte; else ow[p >> 2] |= byte << (8 * (p & 3));
         }
     }
+    uint8_t *orow = d.sdr + 3 * ((int64_t)yy * W + x0);
     if (x0 + 8 <= W && ((reinterpret_cast<uintptr_t>(orow) & 3) == 0)) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) reinterpret_cast<uint32_t *>(orow)[k] = o[k];
+        for (int k = 0; k < 6; ++k) reinterpret_cast<uint32_t *>(orow)[k] = ow[k];
     } else {
         const int nx = min(8, W - x0);
-        for (int k = 0; k < 3 * nx; ++k) orow[k] = (uint8_t)(o[k >> 2] >> (8 * (k & 3)));
+        for (int k = 0; k < 3 * nx; ++k) orow[k] = (uint8_t)(ow[k >> 2] >> (8 * (k & 3)));
     }
 }
 
@@ -988,8 +998,11 @@ void launch_zero(const ImgDesc *d, int n, hipStream_t s) { hipLaunchKernelGGL(k_
 void launch_keystat(const ImgDesc *d, int n, int wgs, hipStream_t s) {
     hipLaunchKernelGGL(k_keystat, dim3(wgs), dim3(KS_THREADS), 0, s, d, n);
 }
-void launch_tmo_base(const ImgDesc *d, int n, int wgs, hipStream_t s) {
-    hipLaunchKernelGGL(k_tmo_base, dim3(wgs), dim3(BLK_THREADS), 0, s, d, n);
+void launch_tmo_base(const ImgDesc *d, int n, int wgs, bool extra, hipStream_t s) {
+    if (extra)
+        hipLaunchKernelGGL(k_tmo_base<true>, dim3(wgs), dim3(BLK_THREADS), 0, s, d, n);
+    else
+        hipLaunchKernelGGL(k_tmo_base<false>, dim3(wgs), dim3(BLK_THREADS), 0, s, d, n);
 }
 void launch_fit_sums(const ImgDesc *d, int n, int wgs, hipStream_t s) {
     hipLaunchKernelGGL(k_fit_sums, dim3(wgs), dim3(STRIP_THREADS), 0, s, d, n);
