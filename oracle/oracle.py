@@ -58,8 +58,16 @@ def lib():
         L.oracle_decode_enh.argtypes = [vp, vp, vp, vp, C.c_int, C.c_int, vp]
         L.oracle_decode_enh.restype = C.c_int
         L.oracle_resid_hist.argtypes = [vp, i64, vp]
-        if hasattr(L, "oracle_mlp_forward"):
-            L.oracle_mlp_forward.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, vp]
+        L.oracle_mlp_estimate.argtypes = [vp, vp, vp, C.c_int, C.c_int, i32, vp, vp]
+        L.oracle_mlp_estimate.restype = C.c_int
+        L.oracle_log2q16.argtypes = [i64]
+        L.oracle_log2q16.restype = i64
+        L.oracle_hist_cost.argtypes = [vp, C.c_int]
+        L.oracle_hist_cost.restype = i64
+        L.oracle_encode_learned.argtypes = [vp, C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.oracle_encode_learned.restype = C.c_int
+        L.oracle_decode_learned.argtypes = [vp, vp, vp, vp, i32, vp, vp, C.c_int, C.c_int, vp]
+        L.oracle_decode_learned.restype = C.c_int
         _lib = L
     return _lib
 
@@ -234,3 +242,58 @@ def bits_per_pixel(hist: np.ndarray) -> float:
         p = h[h > 0] / n
         tot += float(-(p * np.log2(p)).sum())
     return tot
+
+
+# ---------------------------------------------------------------- learned estimator
+def _blob(blob: bytes):
+    return np.frombuffer(blob, np.uint8).copy()
+
+
+def mlp_estimate(S: np.ndarray, rgbe: np.ndarray, k_img: int, blob: bytes) -> np.ndarray:
+    S = np.ascontiguousarray(S, np.uint8)
+    rgbe = np.ascontiguousarray(rgbe, np.uint8)
+    H, W = S.shape[:2]
+    out = np.zeros((H, W, 3), np.uint8)
+    b = _blob(blob)
+    rc = lib().oracle_mlp_estimate(_p(S), _p(rgbe), None, H, W, k_img, _p(b), _p(out))
+    if rc:
+        raise ValueError("bad model blob")
+    return out
+
+
+def log2q16(x: int) -> int:
+    return int(lib().oracle_log2q16(int(x)))
+
+
+def hist_cost(h) -> int:
+    h = np.ascontiguousarray(h, np.int64)
+    return int(lib().oracle_hist_cost(_p(h), h.size))
+
+
+def encode_learned(rgbe: np.ndarray, q: int, blob: bytes) -> dict:
+    rgbe = np.ascontiguousarray(rgbe, np.uint8)
+    H, W = rgbe.shape[:2]
+    sdr = np.zeros((H, W, 3), np.uint8)
+    a = np.zeros((3, 256), np.int32)
+    b = np.zeros((3, 256), np.int32)
+    pr = np.zeros(256, np.uint8)
+    fl = np.zeros((3, 256), np.uint8)
+    par = np.zeros(5, np.int64)
+    res = np.zeros(7 * H * W, np.uint8)
+    bb = _blob(blob)
+    rc = lib().oracle_encode_learned(_p(rgbe), H, W, q, _p(bb), _p(sdr), _p(a), _p(b), _p(pr), _p(fl), _p(par),
+                                     _p(res))
+    if rc:
+        raise ValueError("oracle_encode_learned failed with %d" % rc)
+    return dict(sdr=sdr, a_q=a, b_q=b, present=pr, flag=fl, k_img=int(par[2]), resid=res)
+
+
+def decode_learned(sdr, a_q, b_q, flag, k_img, blob, resid, H, W) -> np.ndarray:
+    out = np.zeros((H, W, 4), np.uint8)
+    bb = _blob(blob)
+    rc = lib().oracle_decode_learned(_p(np.ascontiguousarray(sdr, np.uint8)), _p(np.ascontiguousarray(a_q, np.int32)),
+                                     _p(np.ascontiguousarray(b_q, np.int32)), _p(np.ascontiguousarray(flag, np.uint8)),
+                                     k_img, _p(bb), _p(np.ascontiguousarray(resid).view(np.uint8)), H, W, _p(out))
+    if rc:
+        raise ValueError("oracle_decode_learned failed with %d" % rc)
+    return out

@@ -534,3 +534,198 @@ void oracle_resid_hist(const void *resid, int64_t npx, int64_t *hist /* [3][511]
     for (int c = 0; c < 3; c++)
         for (int64_t i = 0; i < npx; i++) hist[c * 511 + r[c * npx + i] + 255] += 1;
 }
+
+/* ------------------------------------------------------------------------ */
+/* C16: learned int8 mantissa estimator (an extension, not in the paper: the */
+/* paper's estimator needs no learning, Sec. I).  Model blob, little endian:  */
+/*   u32 magic 'RDLM', u32 version 1, u64 hash, u32 reserved[2];            */
+/*   i8  W1[32][32] (out, in)   i32 B1[32][32] (bin, out)                    */
+/*   i32 m1[32], r1[32]                                                      */
+/*   i8  W2[32][32]             i32 B2[32], m2[32], r2[32]                    */
+/*   i8  W3[16][32]             i32 B3[16], m3[16], r3[16]                    */
+/* Input features x[3k + c] = S(y + dy, x + dx)_c - 128 for the 3x3          */
+/* neighbourhood k = 3(dy+1) + (dx+1) (replicated at the image border),      */
+/* x[27..31] = 0.  Exponent bin b = clamp(E - 136 + k_img + 24, 0, 31): the  */
+/* exponent one-hot enters as the bias row B1[b].                            */
+/* Hidden layers: a = clamp((h m + 2^(r-1)) >> r, 0, 127) (64-bit product).  */
+/* Output c (0..2): q8 = (o m3 + 2^(r3-1)) >> r3, M_L = clamp((q8 + 128) >> 8). */
+/* ------------------------------------------------------------------------ */
+#define MLP_BYTES 7512
+
+typedef struct {
+    const int8_t *W1, *W2, *W3;
+    const int32_t *B1, *m1, *r1, *B2, *m2, *r2, *B3, *m3, *r3;
+} mlp_view;
+
+static int mlp_parse(const uint8_t *blob, mlp_view *v)
+{
+    uint32_t magic, version;
+    memcpy(&magic, blob, 4);
+    memcpy(&version, blob + 4, 4);
+    if (magic != 0x4D4C4452u || version != 1u) return -3;
+    const uint8_t *p = blob + 24;
+    v->W1 = (const int8_t *)p; p += 1024;
+    v->B1 = (const int32_t *)p; p += 4096;
+    v->m1 = (const int32_t *)p; p += 128;
+    v->r1 = (const int32_t *)p; p += 128;
+    v->W2 = (const int8_t *)p; p += 1024;
+    v->B2 = (const int32_t *)p; p += 128;
+    v->m2 = (const int32_t *)p; p += 128;
+    v->r2 = (const int32_t *)p; p += 128;
+    v->W3 = (const int8_t *)p; p += 512;
+    v->B3 = (const int32_t *)p; p += 64;
+    v->m3 = (const int32_t *)p; p += 64;
+    v->r3 = (const int32_t *)p; p += 64;
+    return (p - blob) == MLP_BYTES ? 0 : -3;
+}
+
+static int64_t shr_round(int64_t v, int r) { return (v + ((int64_t)1 << (r - 1))) >> r; }
+
+/* Learned estimate for one pixel: feat[32] int8 features, b the bin. */
+static void mlp_pixel(const mlp_view *v, const int feat[32], int b, int out[3])
+{
+    int a1[32], a2[32];
+    for (int n = 0; n < 32; n++) {
+        int64_t h = v->B1[b * 32 + n];
+        for (int k = 0; k < 32; k++) h += (int64_t)v->W1[n * 32 + k] * feat[k];
+        int64_t q = shr_round(h * v->m1[n], v->r1[n]);
+        a1[n] = q < 0 ? 0 : (q > 127 ? 127 : (int)q);
+    }
+    for (int n = 0; n < 32; n++) {
+        int64_t h = v->B2[n];
+        for (int k = 0; k < 32; k++) h += (int64_t)v->W2[n * 32 + k] * a1[k];
+        int64_t q = shr_round(h * v->m2[n], v->r2[n]);
+        a2[n] = q < 0 ? 0 : (q > 127 ? 127 : (int)q);
+    }
+    for (int c = 0; c < 3; c++) {
+        int64_t o = v->B3[c];
+        for (int k = 0; k < 32; k++) o += (int64_t)v->W3[c * 32 + k] * a2[k];
+        int64_t q8 = shr_round(o * v->m3[c], v->r3[c]);
+        int64_t m = (q8 + 128) >> 8;
+        out[c] = m < 0 ? 0 : (m > 255 ? 255 : (int)m);
+    }
+}
+
+/* M_L[H][W][3] for the decoded SDRI S and the exponents of rgbe (or of an
+ * exponent plane Ep if rgbe is NULL). */
+int oracle_mlp_estimate(const uint8_t *S, const uint8_t *rgbe, const uint8_t *Ep, int H, int W, int32_t k_img,
+                        const uint8_t *blob, uint8_t *ML)
+{
+    mlp_view v;
+    if (mlp_parse(blob, &v)) return -3;
+    for (int y = 0; y < H; y++)
+        for (int x = 0; x < W; x++) {
+            int feat[32] = {0};
+            for (int dy = -1; dy <= 1; dy++)
+                for (int dx = -1; dx <= 1; dx++) {
+                    int k = 3 * (dy + 1) + (dx + 1);
+                    const uint8_t *p = S + 3 * ((int64_t)clampi(y + dy, 0, H - 1) * W + clampi(x + dx, 0, W - 1));
+                    for (int c = 0; c < 3; c++) feat[3 * k + c] = (int)p[c] - 128;
+                }
+            int64_t i = (int64_t)y * W + x;
+            int E = rgbe ? rgbe[4 * i + 3] : Ep[i];
+            int b = clampi(E - 136 + k_img + 24, 0, 31);
+            int out[3];
+            mlp_pixel(&v, feat, b, out);
+            for (int c = 0; c < 3; c++) ML[3 * i + c] = (uint8_t)out[c];
+        }
+    return 0;
+}
+
+/* L(x) = Q16 log2 of a count x >= 1: 2^16 floor(log2 x) + LOG2F[the 12 bits
+ * after the leading one, zero-filled]; L(0) = 0. */
+int64_t oracle_log2q16(int64_t x)
+{
+    init_tables();
+    if (x <= 0) return 0;
+    int p = 62;
+    while (!((x >> p) & 1)) p--;
+    int64_t idx = p >= 12 ? (x >> (p - 12)) & 4095 : (x << (12 - p)) & 4095;
+    return (int64_t)65536 * p + LOG2F[idx];
+}
+
+/* Integer entropy cost of a histogram: sum_v h_v (L(n) - L(h_v)), i.e.
+ * 2^16 n H0 up to the table's rounding. */
+int64_t oracle_hist_cost(const int64_t *h, int nbins)
+{
+    int64_t n = 0, cost = 0;
+    for (int v = 0; v < nbins; v++) n += h[v];
+    int64_t Ln = oracle_log2q16(n);
+    for (int v = 0; v < nbins; v++)
+        if (h[v]) cost += h[v] * (Ln - oracle_log2q16(h[v]));
+    return cost;
+}
+
+/* Learned encoder: the plain encoder, then per (c, E) region the learned
+ * estimate replaces M* where its residual histogram has the strictly lower
+ * cost (ties keep SLR); flag[c][E] records the choice. */
+int oracle_encode_learned(const uint8_t *rgbe, int H, int W, int q, const uint8_t *blob, uint8_t *out_sdr,
+                          int32_t *a_q, int32_t *b_q, uint8_t *present, uint8_t *flag, int64_t *params_out,
+                          void *out_resid)
+{
+    int rc = oracle_encode_enh(rgbe, H, W, q, out_sdr, a_q, b_q, present, NULL, params_out, out_resid);
+    if (rc) return rc;
+    int64_t npx = (int64_t)H * W;
+    uint8_t *ss = (uint8_t *)malloc(3 * npx), *ML = (uint8_t *)malloc(3 * npx);
+    int64_t *hs = (int64_t *)calloc((size_t)3 * 256 * 511, sizeof(int64_t));
+    int64_t *hl = (int64_t *)calloc((size_t)3 * 256 * 511, sizeof(int64_t));
+    if (!ss || !ML || !hs || !hl) return -4;
+    oracle_gf(out_sdr, H, W, ss);
+    rc = oracle_mlp_estimate(out_sdr, rgbe, NULL, H, W, (int32_t)params_out[2], blob, ML);
+    if (rc) return rc;
+    for (int64_t i = 0; i < npx; i++) {
+        int e = rgbe[4 * i + 3];
+        for (int c = 0; c < 3; c++) {
+            int m = rgbe[4 * i + c];
+            int rs = m - mstar(a_q[c * 256 + e], b_q[c * 256 + e], ss[3 * i + c]);
+            int rl = m - ML[3 * i + c];
+            hs[((int64_t)c * 256 + e) * 511 + rs + 255] += 1;
+            hl[((int64_t)c * 256 + e) * 511 + rl + 255] += 1;
+        }
+    }
+    for (int c = 0; c < 3; c++)
+        for (int e = 0; e < 256; e++) {
+            int64_t cs = oracle_hist_cost(hs + ((int64_t)c * 256 + e) * 511, 511);
+            int64_t cl = oracle_hist_cost(hl + ((int64_t)c * 256 + e) * 511, 511);
+            flag[c * 256 + e] = present[e] && cl < cs;
+        }
+    int16_t *r = (int16_t *)out_resid;
+    for (int64_t i = 0; i < npx; i++) {
+        int e = rgbe[4 * i + 3];
+        for (int c = 0; c < 3; c++)
+            if (flag[c * 256 + e]) r[c * npx + i] = (int16_t)((int)rgbe[4 * i + c] - ML[3 * i + c]);
+    }
+    free(ss);
+    free(ML);
+    free(hs);
+    free(hl);
+    return 0;
+}
+
+/* Learned decoder: M = (flag ? M_L : M*) + r. */
+int oracle_decode_learned(const uint8_t *sdr, const int32_t *a_q, const int32_t *b_q, const uint8_t *flag,
+                          int32_t k_img, const uint8_t *blob, const void *resid, int H, int W, uint8_t *out_rgbe)
+{
+    int64_t npx = (int64_t)H * W;
+    uint8_t *ss = (uint8_t *)malloc(3 * npx), *ML = (uint8_t *)malloc(3 * npx);
+    if (!ss || !ML) return -4;
+    oracle_gf(sdr, H, W, ss);
+    const uint8_t *Ep = (const uint8_t *)resid + 6 * npx;
+    int rc = oracle_mlp_estimate(sdr, NULL, Ep, H, W, k_img, blob, ML);
+    if (rc) return rc;
+    const int16_t *r = (const int16_t *)resid;
+    int bad = 0;
+    for (int64_t i = 0; i < npx; i++) {
+        int e = Ep[i];
+        for (int c = 0; c < 3; c++) {
+            int est = flag[c * 256 + e] ? ML[3 * i + c] : mstar(a_q[c * 256 + e], b_q[c * 256 + e], ss[3 * i + c]);
+            int m = est + r[c * npx + i];
+            if (m < 0 || m > 255) bad = 1;
+            out_rgbe[4 * i + c] = (uint8_t)m;
+        }
+        out_rgbe[4 * i + 3] = (uint8_t)e;
+    }
+    free(ss);
+    free(ML);
+    return bad ? -3 : 0;
+}

@@ -145,3 +145,23 @@ def config5(n: int = 256) -> list:
     sizes = _draw_sizes(n, 1.0e6, 7680 * 4320, rng)
     return [ImageSpec(H, W, float(rng.uniform(1.0, 5.0)), int(rng.integers(30, 99)), 5000 + i)
             for i, (H, W) in enumerate(sizes)]
+
+
+def random_model(seed: int, scale: int = 8) -> bytes:
+    """A seeded random int8 estimator model (test input), within the value
+    limits of the model format, with activations that neither vanish nor
+    saturate on synthetic images."""
+    from . import model_format
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p = {
+        "W1": np.zeros((32, 32), np.int8), "B1": rng.integers(-3000, 3000, (32, 32)),
+        "m1": rng.integers(512, 2047, 32), "r1": rng.integers(15, 18, 32),
+        "W2": rng.integers(-scale, scale + 1, (32, 32)), "B2": rng.integers(-2000, 4000, 32),
+        "m2": rng.integers(512, 2047, 32), "r2": rng.integers(13, 16, 32),
+        "W3": np.zeros((16, 32), np.int8), "B3": np.zeros(16, np.int64),
+        "m3": np.full(16, 1024), "r3": np.full(16, 6),
+    }
+    p["W1"][:, :27] = rng.integers(-scale, scale + 1, (32, 27))
+    p["W3"][:3] = rng.integers(-scale, scale + 1, (3, 32))
+    p["B3"][:3] = rng.integers(0, 2000, 3)
+    return model_format.pack(p)

@@ -501,3 +501,110 @@ def test_generator_seeded():
     b = synth.generate(20, 30, 3.0, seed=4)
     c = synth.generate(20, 30, 3.0, seed=5)
     assert np.array_equal(a, b) and not np.array_equal(a, c)
+
+
+# ---------------------------------------------------------------- learned estimator
+def _model(**over):
+    from paper_2309_11072_amd import model_format
+    p = {"W1": np.zeros((32, 32)), "B1": np.zeros((32, 32)), "m1": np.ones(32), "r1": np.ones(32),
+         "W2": np.zeros((32, 32)), "B2": np.zeros(32), "m2": np.ones(32), "r2": np.ones(32),
+         "W3": np.zeros((16, 32)), "B3": np.zeros(16), "m3": np.ones(16), "r3": np.ones(16)}
+    p.update(over)
+    return model_format.pack(p)
+
+
+def test_mlp_pass_through_closed_form(O):
+    """Layer 1 copies feature f to neuron f (ReLU, requant (2h + 1) >> 1 = h),
+    layer 2 copies, layer 3 outputs neuron 12 + c (the centre pixel's channel c)
+    plus 128, scaled to Q8: M_L = S_c for S_c >= 128 and 128 below."""
+    W1 = np.zeros((32, 32)); W1[np.arange(27), np.arange(27)] = 1
+    W2 = np.eye(32)
+    W3 = np.zeros((16, 32)); W3[np.arange(3), 12 + np.arange(3)] = 1
+    blob = _model(W1=W1, m1=np.full(32, 2), W2=W2, m2=np.full(32, 2),
+                  W3=W3, B3=np.full(16, 128), m3=np.full(16, 512))
+    rng = np.random.default_rng(21)
+    S = rng.integers(0, 256, (9, 11, 3)).astype(np.uint8)
+    x = rng.integers(0, 256, (9, 11, 4)).astype(np.uint8)
+    ML = O.mlp_estimate(S, x, 0, blob)
+    exp = np.where(S >= 128, np.minimum(S.astype(int), 255 + 128), 128)
+    assert np.array_equal(ML.astype(int), exp)
+
+
+def test_mlp_exponent_bin_closed_form(O):
+    """Neuron 31 carries only the bin bias B1[b][31] = 4b; it is copied to the
+    output: M_L = 4 * clamp(E - 136 + k_img + 24, 0, 31) for every channel."""
+    B1 = np.zeros((32, 32)); B1[:, 31] = 4 * np.arange(32)
+    W2 = np.zeros((32, 32)); W2[31, 31] = 1
+    W3 = np.zeros((16, 32)); W3[:3, 31] = 1
+    blob = _model(B1=B1, m1=np.full(32, 2), W2=W2, m2=np.full(32, 2), W3=W3, m3=np.full(16, 512))
+    S = np.full((4, 5, 3), 77, np.uint8)
+    x = np.zeros((4, 5, 4), np.uint8)
+    x[..., 3] = np.arange(20).reshape(4, 5) * 13
+    for k_img in (-40, 0, 9):
+        ML = O.mlp_estimate(S, x, k_img, blob)
+        b = np.clip(x[..., 3].astype(int) - 136 + k_img + 24, 0, 31)
+        assert np.array_equal(ML[..., 0], 4 * b) and np.array_equal(ML[..., 2], 4 * b)
+
+
+def test_mlp_feature_order_and_border(O):
+    """Feature 3k + c is neighbour k = 3(dy+1) + (dx+1), channel c, replicated at
+    the border: a one-hot first layer that reads feature f reproduces that
+    neighbour (offset by 128) at every pixel, including the corners."""
+    rng = np.random.default_rng(22)
+    S = rng.integers(128, 256, (5, 6, 3)).astype(np.uint8)
+    x = np.zeros((5, 6, 4), np.uint8)
+    for f in (0, 4, 13, 26):
+        k, c = divmod(f, 3)
+        dy, dx = k // 3 - 1, k % 3 - 1
+        W1 = np.zeros((32, 32)); W1[0, f] = 1
+        W2 = np.zeros((32, 32)); W2[0, 0] = 1
+        W3 = np.zeros((16, 32)); W3[0, 0] = 1
+        blob = _model(W1=W1, m1=np.full(32, 2), W2=W2, m2=np.full(32, 2), W3=W3, B3=np.full(16, 128),
+                      m3=np.full(16, 512))
+        ML = O.mlp_estimate(S, x, 0, blob)
+        yy = np.clip(np.arange(5)[:, None] + dy, 0, 4)
+        xx = np.clip(np.arange(6)[None, :] + dx, 0, 5)
+        assert np.array_equal(ML[..., 0], S[yy, xx, c])
+
+
+def test_log2q16_and_cost_closed_forms(O):
+    """L(2^k) = 2^16 k + LOG2F[0]; a histogram of 2^j equal bins of 2^i counts
+    has cost n * 2^16 * j exactly (the table terms cancel)."""
+    lg = O.tables()[0]
+    for k in range(0, 40):
+        assert O.log2q16(1 << k) == 65536 * k + int(lg[0])
+    for i, j in [(0, 1), (3, 2), (5, 4), (2, 8)]:
+        h = np.zeros(511, np.int64)
+        h[:1 << j] = 1 << i
+        n = (1 << i) * (1 << j)
+        assert O.hist_cost(h) == n * 65536 * j
+    h = np.zeros(511, np.int64); h[7] = 99
+    assert O.hist_cost(h) == 0
+    for x in [3, 5, 1000, 123456789]:
+        assert abs(O.log2q16(x) / 65536.0 - math.log2(x)) < 2e-4
+
+
+def test_learned_round_trip_and_flags(O):
+    """Check 1 for the learned path (random int8 models, synthetic images and
+    random words), and the selection rule: a flag is set exactly where the
+    learned residuals' integer cost is strictly below the SLR residuals'."""
+    from paper_2309_11072_amd import synth as sy
+    cases = [(sy.generate(37, 53, 3.0, seed=31, spec_frac=0.05), 75, 1),
+             (sy.generate(24, 70, 1.5, seed=32), 40, 2),
+             (np.random.default_rng(33).integers(0, 256, (13, 17, 4)).astype(np.uint8), 90, 3)]
+    for x, q, ms in cases:
+        H, W = x.shape[:2]
+        blob = sy.random_model(ms)
+        r = O.encode_learned(x, q, blob)
+        y = O.decode_learned(r["sdr"], r["a_q"], r["b_q"], r["flag"], r["k_img"], blob, r["resid"], H, W)
+        assert np.array_equal(x, y)
+        plain = O.encode_enh(x, q)
+        ML = O.mlp_estimate(plain["sdr"], x, plain["k_img"], blob)
+        rs, _ = O.split_resid(plain["resid"], H, W)
+        for c in range(3):
+            for e in np.nonzero(plain["present"])[0]:
+                sel = x[..., 3] == e
+                hs = np.bincount(rs[c][sel].astype(int) + 255, minlength=511)
+                hl = np.bincount((x[..., c][sel].astype(int) - ML[..., c][sel]) + 255, minlength=511)
+                assert r["flag"][c, e] == int(O.hist_cost(hl) < O.hist_cost(hs))
+        assert r["flag"][:, plain["present"] == 0].sum() == 0
