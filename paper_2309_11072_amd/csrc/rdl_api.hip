@@ -9,6 +9,7 @@
 
 #include <cstdio>
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -21,6 +22,8 @@ struct GraphEntry {
     std::vector<ImgDesc> key;  // descriptors the graph was captured for
     ImgDesc *d_desc = nullptr;
     int64_t *d_scratch = nullptr;
+    uint8_t *d_ml = nullptr;      // learned path only
+    uint32_t *d_lhist = nullptr;  // learned path only
     hipGraphExec_t exec = nullptr;
 };
 
@@ -33,6 +36,14 @@ struct rdl_ctx {
     size_t scratch_cap = 0;  // images
     std::vector<GraphEntry> graphs;  // captured encoders, oldest first
     std::vector<ImgDesc> last_key;   // descriptors of the last direct launch
+    // learned estimator
+    uint8_t *d_model = nullptr;
+    uint64_t model_hash = 0;
+    int estimator = 0;
+    uint8_t *d_ml = nullptr;  // direct launches: learned estimates
+    size_t ml_cap = 0;        // bytes
+    uint32_t *d_lhist = nullptr;
+    size_t lhist_cap = 0;     // images
 };
 
 namespace {
@@ -89,8 +100,53 @@ int ensure_scratch(rdl_ctx *c, size_t n) {
 }
 
 struct Grid {
-    int px = 0, blk = 0, tile = 0, fit = 0, res = 0;
+    int px = 0, blk = 0, tile = 0, fit = 0, res = 0, learn = 0;
 };
+
+int ensure_learn_scratch(rdl_ctx *c, size_t ml_bytes, size_t n) {
+    if (ml_bytes > c->ml_cap) {
+        if (c->d_ml) HIPCHK(hipFree(c->d_ml));
+        c->d_ml = nullptr;
+        c->ml_cap = 0;
+        HIPCHK(hipMalloc(&c->d_ml, ml_bytes));
+        c->ml_cap = ml_bytes;
+    }
+    if (n > c->lhist_cap) {
+        if (c->d_lhist) HIPCHK(hipFree(c->d_lhist));
+        c->d_lhist = nullptr;
+        c->lhist_cap = 0;
+        HIPCHK(hipMalloc(&c->d_lhist, n * lhist_words() * sizeof(uint32_t)));
+        HIPCHK(hipMemset(c->d_lhist, 0, n * lhist_words() * sizeof(uint32_t)));  // k_select keeps it zero
+        c->lhist_cap = n;
+    }
+    return RDL_OK;
+}
+
+// Point the learned-path buffers of each image into an estimate buffer of
+// sum(3*H*W) bytes and n histogram blocks.
+void bind_learn(std::vector<ImgDesc> &v, uint8_t *ml, uint32_t *lhist) {
+    size_t off = 0;
+    for (size_t k = 0; k < v.size(); ++k) {
+        v[k].ml = ml + off;
+        v[k].lhist = lhist + k * lhist_words();
+        off += (size_t)3 * v[k].H * v[k].W;
+    }
+}
+
+size_t total_ml_bytes(const std::vector<ImgDesc> &v) {
+    size_t t = 0;
+    for (auto &d : v) t += (size_t)3 * d.H * d.W;
+    return t;
+}
+
+uint64_t fnv1a64(const uint8_t *p, size_t n) {
+    uint64_t h = 0xCBF29CE484222325ull;
+    for (size_t k = 0; k < n; ++k) {
+        h ^= p[k];
+        h *= 0x100000001B3ull;
+    }
+    return h;
+}
 
 // Assign each image its first workgroup per kernel family.
 Grid layout(std::vector<ImgDesc> &v) {
@@ -101,11 +157,13 @@ Grid layout(std::vector<ImgDesc> &v) {
         d.wg_tile = g.tile;
         d.wg_fit = g.fit;
         d.wg_res = g.res;
+        d.wg_learn = g.learn;
         g.px += wgs_px(d.H, d.W);
         g.blk += wgs_blk(d.H, d.W);
         g.tile += wgs_tile(d.H, d.W);
         g.fit += wgs_strip(d.H, d.W);
         g.res += wgs_strip(d.H, d.W);
+        g.learn += wgs_learn(d.H, d.W);
     }
     return g;
 }
@@ -136,11 +194,15 @@ int check_launch(const char *what) {
 
 // Enqueue the full encoder for the images of d (device table) on s.  The
 // scratch accumulators are zero on entry and k_solve leaves them zero.
-void enqueue_encode(const ImgDesc *d, int n, const Grid &g, hipStream_t s) {
+void enqueue_encode(const ImgDesc *d, int n, const Grid &g, bool learned, hipStream_t s) {
     launch_keystat(d, n, g.px, s);
     launch_tmo_base(d, n, g.blk, false, s);
     launch_fit_sums(d, n, g.fit, s);
     launch_solve(d, n, s);
+    if (learned) {
+        launch_learn(d, n, g.learn, s);
+        launch_select(d, n, s);
+    }
     launch_resid(d, n, g.res, s);
 }
 
@@ -200,7 +262,12 @@ void rdl_destroy(rdl_ctx *c) {
         if (e.exec) (void)hipGraphExecDestroy(e.exec);
         if (e.d_desc) (void)hipFree(e.d_desc);
         if (e.d_scratch) (void)hipFree(e.d_scratch);
+        if (e.d_ml) (void)hipFree(e.d_ml);
+        if (e.d_lhist) (void)hipFree(e.d_lhist);
     }
+    if (c->d_model) (void)hipFree(c->d_model);
+    if (c->d_ml) (void)hipFree(c->d_ml);
+    if (c->d_lhist) (void)hipFree(c->d_lhist);
     if (c->d_desc) (void)hipFree(c->d_desc);
     if (c->d_scratch) (void)hipFree(c->d_scratch);
     delete c;
@@ -241,6 +308,8 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
         if (!size_ok(m.H, m.W) || m.q < 1 || m.q > 100) return RDL_EINVAL;
         if (!aligned4(m.rgbe) || !aligned4(m.hdr) || (reinterpret_cast<uintptr_t>(m.resid) & 1)) return RDL_EINVAL;
     }
+    const bool learned = c->estimator == 1;
+    if (learned && !c->d_model) return RDL_EUNSUPPORTED;
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
     std::vector<ImgDesc> v(n, blank());
@@ -254,6 +323,10 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
         d.W = imgs[k].W;
         d.q = imgs[k].q;
         d.flags = F_CLEAN_KS;
+        if (learned) {
+            d.model = c->d_model;
+            d.model_hash = c->model_hash;
+        }
     }
     const Grid gr = layout(v);
 
@@ -272,9 +345,14 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
         if (rc) return rc;
         std::vector<ImgDesc> dv = v;
         for (int k = 0; k < n; ++k) bind_scratch(dv[k], c->d_scratch + (size_t)k * SCRATCH_I64);
+        if (learned) {
+            rc = ensure_learn_scratch(c, total_ml_bytes(v), n);
+            if (rc) return rc;
+            bind_learn(dv, c->d_ml, c->d_lhist);
+        }
         rc = upload(c, dv, s);
         if (rc) return rc;
-        enqueue_encode(c->d_desc, n, gr, s);
+        enqueue_encode(c->d_desc, n, gr, learned, s);
         return check_launch("encoder kernels");
     }
 
@@ -286,6 +364,8 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
         (void)hipGraphExecDestroy(old.exec);
         (void)hipFree(old.d_desc);
         (void)hipFree(old.d_scratch);
+        if (old.d_ml) (void)hipFree(old.d_ml);
+        if (old.d_lhist) (void)hipFree(old.d_lhist);
         c->graphs.erase(c->graphs.begin());
     }
     GraphEntry e;
@@ -294,6 +374,12 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
     HIPCHK(hipMemset(e.d_scratch, 0, (size_t)n * SCRATCH_I64 * sizeof(int64_t)));
     std::vector<ImgDesc> dv = v;
     for (int k = 0; k < n; ++k) bind_scratch(dv[k], e.d_scratch + (size_t)k * SCRATCH_I64);
+    if (learned) {
+        HIPCHK(hipMalloc(&e.d_ml, total_ml_bytes(v)));
+        HIPCHK(hipMalloc(&e.d_lhist, (size_t)n * lhist_words() * sizeof(uint32_t)));
+        HIPCHK(hipMemset(e.d_lhist, 0, (size_t)n * lhist_words() * sizeof(uint32_t)));
+        bind_learn(dv, e.d_ml, e.d_lhist);
+    }
     HIPCHK(hipMalloc(&e.d_desc, (size_t)n * sizeof(ImgDesc)));
     HIPCHK(hipMemcpy(e.d_desc, dv.data(), (size_t)n * sizeof(ImgDesc), hipMemcpyHostToDevice));
     hipStream_t cs;
@@ -301,7 +387,7 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
     hipGraph_t graph;
     hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (err == hipSuccess) {
-        enqueue_encode(e.d_desc, n, gr, cs);
+        enqueue_encode(e.d_desc, n, gr, learned, cs);
         err = hipStreamEndCapture(cs, &graph);
     }
     if (err == hipSuccess) {
@@ -312,6 +398,8 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
     if (err != hipSuccess) {
         (void)hipFree(e.d_desc);
         (void)hipFree(e.d_scratch);
+        if (e.d_ml) (void)hipFree(e.d_ml);
+        if (e.d_lhist) (void)hipFree(e.d_lhist);
         return hip_fail(err, "graph capture of the encoder");
     }
     HIPCHK(hipGraphLaunch(e.exec, s));
@@ -333,10 +421,13 @@ int rdl_decode_enh(rdl_ctx *c, const uint8_t *sdr, const rdl_header *coeffs, con
     v[0].status = status;
     v[0].H = H;
     v[0].W = W;
+    v[0].model = c->d_model;
+    v[0].model_hash = c->model_hash;
     const Grid gr = layout(v);
     int rc = upload(c, v, s);
     if (rc) return rc;
     launch_decode(c->d_desc, 1, gr.res, s);
+    if (c->d_model) launch_decode_learned(c->d_desc, 1, gr.learn, s);
     return check_launch("k_decode");
 }
 
@@ -498,6 +589,57 @@ int rdl_profile_encode(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int q, uin
     for (int k = 0; k < 2 * RDL_NSTAGES; ++k) (void)hipEventDestroy(ev[k]);
     if (err != hipSuccess) return hip_fail(err, "rdl_profile_encode");
     for (int st = 0; st < RDL_NSTAGES; ++st) ms[st] = (float)(acc[st] / reps);
+    return RDL_OK;
+}
+
+int rdl_set_model(rdl_ctx *c, const void *blob, size_t nbytes) {
+    if (!c) return RDL_EINVAL;
+    DeviceGuard g(c->device);
+    if (!blob) {
+        if (c->d_model) HIPCHK(hipDeviceSynchronize());
+        if (c->d_model) (void)hipFree(c->d_model);
+        c->d_model = nullptr;
+        c->model_hash = 0;
+        c->estimator = 0;
+        return RDL_OK;
+    }
+    if (nbytes != (size_t)MODEL_BYTES) return RDL_EINVAL;
+    const uint8_t *b = (const uint8_t *)blob;
+    uint32_t magic, version;
+    uint64_t hash;
+    memcpy(&magic, b, 4);
+    memcpy(&version, b + 4, 4);
+    memcpy(&hash, b + 8, 8);
+    if (magic != 0x4D4C4452u || version != 1u) return RDL_ECORRUPT;
+    if (fnv1a64(b + 24, MODEL_BYTES - 24) != hash) return RDL_ECORRUPT;
+    auto i32 = [&](int off, int k) {
+        int32_t v;
+        memcpy(&v, b + off + 4 * k, 4);
+        return v;
+    };
+    // Value limits that keep every requantisation product below 2^31.
+    const int offs_m[3] = {5144, 6552, 7384}, offs_r[3] = {5272, 6680, 7448}, cnt[3] = {32, 32, 16};
+    for (int l = 0; l < 3; ++l)
+        for (int k = 0; k < cnt[l]; ++k) {
+            const int32_t m = i32(offs_m[l], k), r = i32(offs_r[l], k);
+            if (m < 1 || m >= (1 << 11) || r < 1 || r > 28) return RDL_ECORRUPT;
+        }
+    for (int k = 0; k < 1024; ++k)
+        if (std::abs(i32(1048, k)) > (1 << 18)) return RDL_ECORRUPT;
+    for (int k = 0; k < 32; ++k)
+        if (std::abs(i32(6424, k)) > (1 << 18)) return RDL_ECORRUPT;
+    for (int k = 0; k < 16; ++k)
+        if (std::abs(i32(7320, k)) > (1 << 18)) return RDL_ECORRUPT;
+    if (!c->d_model) HIPCHK(hipMalloc(&c->d_model, MODEL_BYTES));
+    HIPCHK(hipMemcpy(c->d_model, b, MODEL_BYTES, hipMemcpyHostToDevice));
+    c->model_hash = hash;
+    return RDL_OK;
+}
+
+int rdl_set_estimator(rdl_ctx *c, int mode) {
+    if (!c || mode < 0 || mode > 1) return RDL_EINVAL;
+    if (mode == 1 && !c->d_model) return RDL_EUNSUPPORTED;
+    c->estimator = mode;
     return RDL_OK;
 }
 

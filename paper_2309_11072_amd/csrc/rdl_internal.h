@@ -20,6 +20,9 @@ constexpr int STRIP_RH = 16;       //   walks 16 rows of a 256-px strip, 4 px pe
 constexpr int STRIP_WAVES = 4;     //   lane; 4 waves stacked per workgroup
 constexpr int STRIP_THREADS = 64 * STRIP_WAVES;
 constexpr int STRIP_H = STRIP_RH * STRIP_WAVES;
+constexpr int HIST_STRIPES = 4;    // learned path: copies of the per-region histograms
+constexpr int LEARN_W = 64, LEARN_H = 64;  // learned path: 64 x 64 px per workgroup
+constexpr int MODEL_BYTES = 7512;
 constexpr int TILE_H = 16;         // residual histogram: 16 x 128 px tiles,
 constexpr int TILE_W = 128;        //   256 lanes x 8 consecutive px
 constexpr int TILE_THREADS = 256;
@@ -47,9 +50,13 @@ struct ImgDesc {
     int32_t *status;       // decode only, optional
     uint8_t *out_rgbe;     // decode only
     int64_t *hist;         // [3][511] residual histograms
+    uint8_t *ml;           // learned path: [H][W][3] learned estimates
+    uint32_t *lhist;       // learned path: [HIST_STRIPES][2][3][256][511] residual histograms
+    const uint8_t *model;  // learned path: model blob (device)
+    uint64_t model_hash;
     int32_t H, W, q, flags;
     int32_t nks, nfs, pad0, pad1;
-    int32_t wg_px, wg_blk, wg_tile, wg_fit, wg_res, pad2;
+    int32_t wg_px, wg_blk, wg_tile, wg_fit, wg_res, wg_learn;
 };
 
 // Accumulator hygiene: scratch stripes are all-zero between launch sequences
@@ -62,6 +69,8 @@ inline int wgs_px(int H, int W) { return (int)(((int64_t)H * W + KS_PX_PER_WG - 
 inline int wgs_blk(int H, int W) { return ((H + 7) / 8) * (((W + 7) / 8 + BLK_WG - 1) / BLK_WG); }
 inline int wgs_tile(int H, int W) { return ((H + TILE_H - 1) / TILE_H) * ((W + TILE_W - 1) / TILE_W); }
 inline int wgs_strip(int H, int W) { return ((H + STRIP_H - 1) / STRIP_H) * ((W + STRIP_W - 1) / STRIP_W); }
+inline int wgs_learn(int H, int W) { return ((H + LEARN_H - 1) / LEARN_H) * ((W + LEARN_W - 1) / LEARN_W); }
+inline size_t lhist_words() { return (size_t)HIST_STRIPES * 2 * 3 * 256 * 511; }
 
 // Kernel launchers (defined in rdl_kernels.hip).
 hipError_t upload_tables(int *bad_table);
@@ -74,5 +83,8 @@ void launch_key_total(const ImgDesc *d, int n, int64_t *out2, hipStream_t s);
 void launch_resid(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_decode(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_hist(const ImgDesc *d, int n, int wgs, hipStream_t s);
+void launch_learn(const ImgDesc *d, int n, int wgs, hipStream_t s);
+void launch_select(const ImgDesc *d, int n, hipStream_t s);
+void launch_decode_learned(const ImgDesc *d, int n, int wgs, hipStream_t s);
 
 }  // namespace rdl

@@ -75,7 +75,7 @@ __device__ __forceinline__ int find_img(const ImgDesc *__restrict__ D, int n, in
     int lo = 0, hi = n - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        int w = which == 0 ? D[mid].wg_px : which == 1 ? D[mid].wg_blk : which == 2 ? D[mid].wg_tile : which == 3 ? D[mid].wg_fit : D[mid].wg_res;
+        int w = which == 0 ? D[mid].wg_px : which == 1 ? D[mid].wg_blk : which == 2 ? D[mid].wg_tile : which == 3 ? D[mid].wg_fit : which == 4 ? D[mid].wg_res : D[mid].wg_learn;
         if (w <= wg) lo = mid; else hi = mid - 1;
     }
     return uniform(lo);
@@ -808,14 +808,17 @@ __device__ __forceinline__ int mstar(int32_t aq, int32_t bq, int s) {
 
 __global__ __launch_bounds__(STRIP_THREADS) void k_resid(const ImgDesc *__restrict__ D, int n) {
     __shared__ int2 s_ab[3][256];
+    __shared__ uint8_t s_fl[3][256];
     const int i = find_img(D, n, blockIdx.x, 4);
     const ImgDesc &d = D[i];
     const int H = d.H, W = d.W;
     const int wgl = blockIdx.x - d.wg_res;
     const rdl_header *h = d.hdr;
+    const bool learned = d.ml != nullptr;
     for (int k = threadIdx.x; k < 3 * 256; k += STRIP_THREADS) {
         const int c = k >> 8, e = k & 255;
         s_ab[c][e] = make_int2(h->a_q[c][e], h->b_q[c][e]);
+        s_fl[c][e] = learned ? h->flag[c][e] : 0;
     }
     __syncthreads();
     const StripPos sp = strip_pos(wgl, H, W);
@@ -843,7 +846,9 @@ __global__ __launch_bounds__(STRIP_THREADS) void k_resid(const ImgDesc *__restri
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const int2 ab = s_ab[c][e];
-                rv[c][j] = (int)((w[j] >> (8 * c)) & 255u) - mstar(ab.x, ab.y, s[c][j]);
+                int est = mstar(ab.x, ab.y, s[c][j]);
+                if (learned && s_fl[c][e] && sp.x + j < W) est = d.ml[3 * ((int64_t)y * W + sp.x + j) + c];
+                rv[c][j] = (int)((w[j] >> (8 * c)) & 255u) - est;
             }
         }
         const int64_t o = (int64_t)y * W + sp.x;
@@ -879,10 +884,11 @@ __global__ __launch_bounds__(STRIP_THREADS) void k_decode(const ImgDesc *__restr
     const int H = d.H, W = d.W;
     const rdl_header *h = d.hdr;
     const bool ok = h->magic == RDL_MAGIC && h->version == RDL_VERSION && h->H == H && h->W == W;
-    if (!ok) {
+    if (!ok || (h->estimator != 0 && !d.model)) {
         if (threadIdx.x == 0 && d.status) atomicExch(d.status, RDL_ECORRUPT);
         return;
     }
+    if (h->estimator != 0) return;  // decoded by k_decode_learned
     for (int k = threadIdx.x; k < 3 * 256; k += STRIP_THREADS) {
         const int c = k >> 8, e = k & 255;
         s_ab[c][e] = make_int2(h->a_q[c][e], h->b_q[c][e]);
@@ -922,6 +928,392 @@ __global__ __launch_bounds__(STRIP_THREADS) void k_decode(const ImgDesc *__restr
     }
     if (bad && d.status) atomicExch(d.status, RDL_ECORRUPT);
 }
+// ---------------------------------------------------------------------------
+// Learned int8 mantissa estimator (an extension beyond the paper, whose
+// estimator needs no learning).  Model blob layout (little endian, 7512 B):
+// 24-byte head, then W1 i8[32][32] (out, in), B1 i32[32][32] (exponent bin,
+// out), m1/r1 i32[32], W2 i8[32][32], B2/m2/r2 i32[32], W3 i8[16][32],
+// B3/m3/r3 i32[16].  Features: the 3x3 neighbourhood of S, 3 bytes per
+// neighbour (S - 128 as int8), 27 of 32 slots; the exponent enters as the bias
+// row B1[bin], bin = clamp(E - 136 + k_img + 24, 0, 31).  Hidden layers:
+// a = clamp((h m + 2^(r-1)) >> r, 0, 127); output: q8 = (o m3 + 2^(r3-1)) >>
+// r3, M_L = clamp((q8 + 128) >> 8, 0, 255).  The library accepts only models
+// whose multipliers, shifts and biases keep every product below 2^31, so
+// 32-bit arithmetic equals the exact one.
+//
+// Each layer is an int8 MFMA D = W X with pixels along N: v_mfma_i32_16x16x32
+// takes lane l's A bytes = W[l%16][8(l/16) .. +7], B bytes = X[8(l/16) .. +7]
+// [l%16] and returns D[4(l/16) + t][l%16], t = 0..3, i.e. four output neurons
+// of one pixel per lane.
+// ---------------------------------------------------------------------------
+constexpr int MB_W1 = 24, MB_B1 = 1048, MB_M1 = 5144, MB_R1 = 5272, MB_W2 = 5400, MB_B2 = 6424, MB_M2 = 6552,
+              MB_R2 = 6680, MB_W3 = 6808, MB_B3 = 7320, MB_M3 = 7384, MB_R3 = 7448;
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+struct MlpLane {
+    long w1a, w1b, w2a, w2b, w3;  // this lane's A fragments
+    int m1[8], r1[8], m2[8], r2[8], b2[8], m3[4], r3[4], b3[4];
+};
+
+__device__ __forceinline__ void mlp_lane_load(MlpLane &L, const uint8_t *__restrict__ blob, int lane) {
+    const int j = lane & 15, q = lane >> 4;
+    L.w1a = *reinterpret_cast<const long *>(blob + MB_W1 + j * 32 + 8 * q);
+    L.w1b = *reinterpret_cast<const long *>(blob + MB_W1 + (16 + j) * 32 + 8 * q);
+    L.w2a = *reinterpret_cast<const long *>(blob + MB_W2 + j * 32 + 8 * q);
+    L.w2b = *reinterpret_cast<const long *>(blob + MB_W2 + (16 + j) * 32 + 8 * q);
+    L.w3 = *reinterpret_cast<const long *>(blob + MB_W3 + j * 32 + 8 * q);
+    const int32_t *m1 = reinterpret_cast<const int32_t *>(blob + MB_M1), *r1 = reinterpret_cast<const int32_t *>(blob + MB_R1);
+    const int32_t *m2 = reinterpret_cast<const int32_t *>(blob + MB_M2), *r2 = reinterpret_cast<const int32_t *>(blob + MB_R2);
+    const int32_t *b2 = reinterpret_cast<const int32_t *>(blob + MB_B2);
+    const int32_t *m3 = reinterpret_cast<const int32_t *>(blob + MB_M3), *r3 = reinterpret_cast<const int32_t *>(blob + MB_R3);
+    const int32_t *b3 = reinterpret_cast<const int32_t *>(blob + MB_B3);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int na = 4 * q + t, nb = 16 + 4 * q + t;
+        L.m1[t] = m1[na]; L.r1[t] = r1[na]; L.m1[4 + t] = m1[nb]; L.r1[4 + t] = r1[nb];
+        L.m2[t] = m2[na]; L.r2[t] = r2[na]; L.m2[4 + t] = m2[nb]; L.r2[4 + t] = r2[nb];
+        L.b2[t] = b2[na]; L.b2[4 + t] = b2[nb];
+        L.m3[t] = m3[na]; L.r3[t] = r3[na]; L.b3[t] = b3[na];
+    }
+}
+
+__device__ __forceinline__ uint32_t requant_u8(int h, int m, int r) {
+    const int v = (__mul24(h, m) + (1 << (r - 1))) >> r;
+    return (uint32_t)min(max(v, 0), 127);
+}
+
+__device__ __forceinline__ uint32_t requant4(const v4i h, const int *m, const int *r) {
+    return requant_u8(h[0], m[0], r[0]) | (requant_u8(h[1], m[1], r[1]) << 8) | (requant_u8(h[2], m[2], r[2]) << 16) |
+           (requant_u8(h[3], m[3], r[3]) << 24);
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Per-wave LDS of the estimator: 64 pixels' features (32 bytes each), their
+// bins, one 16-pixel transposition area and the 64 outputs.
+struct MlpWaveLds {
+    uint32_t feat[64][8];
+    uint32_t xp[16][8];
+    uint32_t ml[64];
+    int bin[64];
+};
+
+// M_L for the 64 pixels of a wave (feat and bin filled by the caller, every
+// lane of the wave active).  B1 is the bias table in LDS.
+__device__ __forceinline__ void mlp_wave64(MlpWaveLds &w, const int32_t (*B1)[32], const MlpLane &L, int lane) {
+    const int j = lane & 15, q = lane >> 4;
+#pragma unroll 1
+    for (int g = 0; g < 4; ++g) {
+        const int p = 16 * g + j;
+        const long xb = *reinterpret_cast<const long *>(&w.feat[p][2 * q]);
+        const int b = w.bin[p];
+        const v4i c1a = *reinterpret_cast<const v4i *>(&B1[b][4 * q]);
+        const v4i c1b = *reinterpret_cast<const v4i *>(&B1[b][16 + 4 * q]);
+        const v4i h1a = __builtin_amdgcn_mfma_i32_16x16x32_i8(L.w1a, xb, c1a, 0, 0, 0);
+        const v4i h1b = __builtin_amdgcn_mfma_i32_16x16x32_i8(L.w1b, xb, c1b, 0, 0, 0);
+        w.xp[j][q] = requant4(h1a, L.m1, L.r1);
+        w.xp[j][4 + q] = requant4(h1b, L.m1 + 4, L.r1 + 4);
+        wave_lds_sync();
+        const long a1 = *reinterpret_cast<const long *>(&w.xp[j][2 * q]);
+        wave_lds_sync();
+        const v4i c2a = {L.b2[0], L.b2[1], L.b2[2], L.b2[3]};
+        const v4i c2b = {L.b2[4], L.b2[5], L.b2[6], L.b2[7]};
+        const v4i h2a = __builtin_amdgcn_mfma_i32_16x16x32_i8(L.w2a, a1, c2a, 0, 0, 0);
+        const v4i h2b = __builtin_amdgcn_mfma_i32_16x16x32_i8(L.w2b, a1, c2b, 0, 0, 0);
+        w.xp[j][q] = requant4(h2a, L.m2, L.r2);
+        w.xp[j][4 + q] = requant4(h2b, L.m2 + 4, L.r2 + 4);
+        wave_lds_sync();
+        const long a2 = *reinterpret_cast<const long *>(&w.xp[j][2 * q]);
+        wave_lds_sync();
+        const v4i c3 = {L.b3[0], L.b3[1], L.b3[2], L.b3[3]};
+        const v4i o = __builtin_amdgcn_mfma_i32_16x16x32_i8(L.w3, a2, c3, 0, 0, 0);
+        if (q == 0) {  // neurons 0, 1, 2 are the R, G, B estimates of pixel p
+            uint32_t word = 0;
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                const int q8 = (__mul24(o[t], L.m3[t]) + (1 << (L.r3[t] - 1))) >> L.r3[t];
+                word |= (uint32_t)min(max((q8 + 128) >> 8, 0), 255) << (8 * t);
+            }
+            w.ml[p] = word;
+        }
+    }
+    wave_lds_sync();
+}
+
+// Features of the pixel at tile position (ly, lx): the nine neighbours'
+// bytes (S - 128) concatenated, 27 bytes, then 5 zero bytes.
+template <int TW>
+__device__ __forceinline__ void build_features(const uint32_t (*tile)[TW + 2], int ly, int lx, uint32_t f[8]) {
+    uint32_t w[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) w[k] = (tile[ly + k / 3][lx + k % 3] & 0xFFFFFFu) ^ 0x808080u;
+    f[0] = w[0] | (w[1] << 24);
+    f[1] = (w[1] >> 8) | (w[2] << 16);
+    f[2] = (w[2] >> 16) | (w[3] << 8);
+    f[3] = w[4] | (w[5] << 24);
+    f[4] = (w[5] >> 8) | (w[6] << 16);
+    f[5] = (w[6] >> 16) | (w[7] << 8);
+    f[6] = w[8];
+    f[7] = 0;
+}
+
+// S* of the tile pixel (ly, lx) from its 3x3 neighbourhood.
+template <int TW>
+__device__ __forceinline__ void gf_at(const uint32_t (*tile)[TW + 2], int ly, int lx, int s[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        int v[3];
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+            const int a = (tile[ly + dy][lx] >> (8 * c)) & 255, b = (tile[ly + dy][lx + 1] >> (8 * c)) & 255,
+                      e = (tile[ly + dy][lx + 2] >> (8 * c)) & 255;
+            v[dy] = a + 6 * b + e;
+        }
+        s[c] = (v[0] + 6 * v[1] + v[2] + 32) >> 6;
+    }
+}
+
+constexpr int LT_W = 64, LT_H = 16, LT_TILES = 4;  // a workgroup walks 4 tiles of 16 x 64 px
+constexpr int HB_SLOTS = 16, HB_BINS = 128;        // LDS histogram window: 16 exponents x r in [-64, 63]
+
+__device__ __forceinline__ void load_lt_tile(uint32_t (*t)[LT_W + 2], const uint8_t *__restrict__ sdr, int H, int W,
+                                             int ty0, int tx0) {
+    for (int k = threadIdx.x; k < (LT_H + 2) * (LT_W + 2); k += 256) {
+        const int ry = k / (LT_W + 2), rx = k - ry * (LT_W + 2);
+        const int yy = min(max(ty0 + ry - 1, 0), H - 1), xx = min(max(tx0 + rx - 1, 0), W - 1);
+        t[ry][rx] = load_px3(sdr + 3 * ((int64_t)yy * W + xx));
+    }
+}
+
+__device__ __forceinline__ int mlp_bin(int e, int k_img) { return min(max(e - 136 + k_img + 24, 0), 31); }
+
+// Encoder side: learned estimates M_L (stored for the residual stage) and,
+// per (channel, E), residual histograms of both estimators.  Histogram counts
+// go to a 16-exponent LDS window (SLR count in the low, learned count in the
+// high half of each word; a workgroup covers 4096 px so neither overflows),
+// anything outside the window or |r| range straight to the image's stripe.
+__global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, int n) {
+    __shared__ uint32_t t[LT_H + 2][LT_W + 2];
+    __shared__ int2 s_ab[3][256];
+    __shared__ int32_t B1[32][32];
+    __shared__ MlpWaveLds wl[4];
+    __shared__ uint32_t hb[3][HB_SLOTS][HB_BINS];
+    __shared__ int s_ebase;
+    const int i = find_img(D, n, blockIdx.x, 5);
+    const ImgDesc &d = D[i];
+    const int H = d.H, W = d.W;
+    const rdl_header *h = d.hdr;
+    const int wgl = blockIdx.x - d.wg_learn;
+    const int ntx = (W + LT_W - 1) / LT_W;
+    const int ty0w = (wgl / ntx) * (LT_H * LT_TILES), tx0 = (wgl % ntx) * LT_W;
+    for (int k = threadIdx.x; k < 3 * 256; k += 256) s_ab[k >> 8][k & 255] = make_int2(h->a_q[k >> 8][k & 255], h->b_q[k >> 8][k & 255]);
+    for (int k = threadIdx.x; k < 1024; k += 256) (&B1[0][0])[k] = reinterpret_cast<const int32_t *>(d.model + MB_B1)[k];
+    for (int k = threadIdx.x; k < 3 * HB_SLOTS * HB_BINS; k += 256) (&hb[0][0][0])[k] = 0;
+    if (threadIdx.x == 0) {
+        const int yy = min(ty0w, H - 1), xx = min(tx0, W - 1);
+        s_ebase = min(max((int)d.rgbe[4 * ((int64_t)yy * W + xx) + 3] - 6, 0), 256 - HB_SLOTS);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    MlpLane L;
+    mlp_lane_load(L, d.model, lane);
+    const int k_img = h->k_img;
+    const int64_t npx = (int64_t)H * W;
+    uint32_t *hist = d.lhist + (size_t)(wgl % HIST_STRIPES) * (2 * 3 * 256 * 511);
+    for (int tt = 0; tt < LT_TILES; ++tt) {
+        const int ty0 = ty0w + tt * LT_H;
+        __syncthreads();
+        if (ty0 < H) load_lt_tile(t, d.sdr, H, W, ty0, tx0);
+        __syncthreads();
+        if (ty0 >= H) continue;  // uniform for the workgroup
+        const int ebase = s_ebase;
+#pragma unroll 1
+        for (int rr = 0; rr < LT_H / 4; ++rr) {
+            const int ly = wave * (LT_H / 4) + rr, y = ty0 + ly, x = tx0 + lane;
+            const bool in = y < H && x < W;
+            uint32_t w = 0;
+            if (in) w = reinterpret_cast<const uint32_t *>(d.rgbe)[(int64_t)y * W + x];
+            const int e = (int)(w >> 24);
+            uint32_t f[8];
+            build_features<LT_W>(t, ly, lane, f);
+            *reinterpret_cast<uint4 *>(&wl[wave].feat[lane][0]) = make_uint4(f[0], f[1], f[2], f[3]);
+            *reinterpret_cast<uint4 *>(&wl[wave].feat[lane][4]) = make_uint4(f[4], f[5], f[6], f[7]);
+            wl[wave].bin[lane] = mlp_bin(e, k_img);
+            wave_lds_sync();
+            mlp_wave64(wl[wave], B1, L, lane);
+            const uint32_t ml = wl[wave].ml[lane];
+            if (!in) continue;
+            int s[3];
+            gf_at<LT_W>(t, ly, lane, s);
+            const int64_t o = (int64_t)y * W + x;
+            const int slot = e - ebase;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int m = (int)((w >> (8 * c)) & 255u);
+                const int mlc = (int)((ml >> (8 * c)) & 255u);
+                d.ml[3 * o + c] = (uint8_t)mlc;
+                const int2 ab = s_ab[c][e];
+                const int rs = m - mstar(ab.x, ab.y, s[c]), rl = m - mlc;
+                if (slot >= 0 && slot < HB_SLOTS && rs >= -64 && rs < 64) atomicAdd(&hb[c][slot][rs + 64], 1u);
+                else atomicAdd(&hist[((0 * 3 + c) * 256 + e) * 511 + rs + 255], 1u);
+                if (slot >= 0 && slot < HB_SLOTS && rl >= -64 && rl < 64) atomicAdd(&hb[c][slot][rl + 64], 1u << 16);
+                else atomicAdd(&hist[((1 * 3 + c) * 256 + e) * 511 + rl + 255], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    const int ebase = s_ebase;
+    for (int k = threadIdx.x; k < 3 * HB_SLOTS * HB_BINS; k += 256) {
+        const uint32_t v = (&hb[0][0][0])[k];
+        if (!v) continue;
+        const int c = k / (HB_SLOTS * HB_BINS), slot = (k / HB_BINS) % HB_SLOTS, bi = k % HB_BINS;
+        const int e = ebase + slot, r = bi - 64;
+        if (v & 0xFFFFu) atomicAdd(&hist[((0 * 3 + c) * 256 + e) * 511 + r + 255], v & 0xFFFFu);
+        if (v >> 16) atomicAdd(&hist[((1 * 3 + c) * 256 + e) * 511 + r + 255], v >> 16);
+    }
+}
+
+// Q16 log2 of a count (0 for 0), from the same frozen table as the key.
+__device__ __forceinline__ int64_t log2q16(uint32_t x) {
+    if (x == 0) return 0;
+    const int p = 31 - __builtin_clz(x);
+    const uint32_t idx = p >= 12 ? (x >> (p - 12)) & 4095u : (x << (12 - p)) & 4095u;
+    return (int64_t)65536 * p + g_log2f[idx];
+}
+
+// One workgroup per (image, exponent): sums the histogram stripes (leaving them
+// zero), computes both estimators' integer entropy costs per channel and sets
+// the flag where the learned cost is strictly lower.
+__global__ __launch_bounds__(256) void k_select(const ImgDesc *__restrict__ D, int n) {
+    __shared__ int64_t s_red[4][2];
+    __shared__ uint32_t s_cnt[2][511];
+    const int i = blockIdx.x >> 8, e = blockIdx.x & 255;
+    if (i >= n) return;
+    const ImgDesc &d = D[i];
+    rdl_header *h = d.hdr;
+    if (e == 0 && threadIdx.x == 0) {
+        h->estimator = 1;
+        h->model_hash = d.model_hash;
+    }
+    if (!h->present[e]) {
+        if (threadIdx.x < 3) h->flag[threadIdx.x][e] = 0;
+        return;
+    }
+    for (int c = 0; c < 3; ++c) {
+        for (int v = threadIdx.x; v < 511; v += 256) {
+#pragma unroll
+            for (int est = 0; est < 2; ++est) {
+                uint32_t acc = 0;
+                for (int st = 0; st < HIST_STRIPES; ++st) {
+                    uint32_t *p = d.lhist + (size_t)st * (2 * 3 * 256 * 511) + ((est * 3 + c) * 256 + e) * 511 + v;
+                    acc += *p;
+                    *p = 0;
+                }
+                s_cnt[est][v] = acc;
+            }
+        }
+        __syncthreads();
+        // n = region size (same for both estimators)
+        int64_t part[2] = {0, 0};
+        uint32_t nn = 0;
+        for (int v = 0; v < 511; ++v) nn += s_cnt[0][v];
+        const int64_t Ln = log2q16(nn);
+        for (int v = threadIdx.x; v < 511; v += 256)
+#pragma unroll
+            for (int est = 0; est < 2; ++est) {
+                const uint32_t hv = s_cnt[est][v];
+                if (hv) part[est] += (int64_t)hv * (Ln - log2q16(hv));
+            }
+#pragma unroll
+        for (int est = 0; est < 2; ++est)
+            for (int off = 32; off > 0; off >>= 1) part[est] += __shfl_down(part[est], off, 64);
+        if ((threadIdx.x & 63) == 0) { s_red[threadIdx.x >> 6][0] = part[0]; s_red[threadIdx.x >> 6][1] = part[1]; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int64_t cs = s_red[0][0] + s_red[1][0] + s_red[2][0] + s_red[3][0];
+            const int64_t cl = s_red[0][1] + s_red[1][1] + s_red[2][1] + s_red[3][1];
+            h->flag[c][e] = cl < cs ? 1 : 0;
+        }
+        __syncthreads();
+    }
+}
+
+// Learned decoder: M = (flag ? M_L : M*) + r for headers with estimator 1.
+__global__ __launch_bounds__(256) void k_decode_learned(const ImgDesc *__restrict__ D, int n) {
+    __shared__ uint32_t t[LT_H + 2][LT_W + 2];
+    __shared__ int2 s_ab[3][256];
+    __shared__ uint8_t s_fl[3][256];
+    __shared__ int32_t B1[32][32];
+    __shared__ MlpWaveLds wl[4];
+    const int i = find_img(D, n, blockIdx.x, 5);
+    const ImgDesc &d = D[i];
+    const int H = d.H, W = d.W;
+    const rdl_header *h = d.hdr;
+    if (h->estimator != 1) return;  // uniform: plain headers are decoded by k_decode
+    const bool ok = h->magic == RDL_MAGIC && h->version == RDL_VERSION && h->H == H && h->W == W &&
+                    h->model_hash == d.model_hash;
+    if (!ok) {
+        if (threadIdx.x == 0 && d.status) atomicExch(d.status, RDL_ECORRUPT);
+        return;
+    }
+    const int wgl = blockIdx.x - d.wg_learn;
+    const int ntx = (W + LT_W - 1) / LT_W;
+    const int ty0w = (wgl / ntx) * (LT_H * LT_TILES), tx0 = (wgl % ntx) * LT_W;
+    for (int k = threadIdx.x; k < 3 * 256; k += 256) {
+        s_ab[k >> 8][k & 255] = make_int2(h->a_q[k >> 8][k & 255], h->b_q[k >> 8][k & 255]);
+        s_fl[k >> 8][k & 255] = h->flag[k >> 8][k & 255];
+    }
+    for (int k = threadIdx.x; k < 1024; k += 256) (&B1[0][0])[k] = reinterpret_cast<const int32_t *>(d.model + MB_B1)[k];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    MlpLane L;
+    mlp_lane_load(L, d.model, lane);
+    const int k_img = h->k_img;
+    const int64_t npx = (int64_t)H * W;
+    const int16_t *r = (const int16_t *)d.resid;
+    const uint8_t *Ep = d.resid + 6 * npx;
+    uint32_t *out = reinterpret_cast<uint32_t *>(d.out_rgbe);
+    bool bad = false;
+    for (int tt = 0; tt < LT_TILES; ++tt) {
+        const int ty0 = ty0w + tt * LT_H;
+        __syncthreads();
+        if (ty0 < H) load_lt_tile(t, d.sdr, H, W, ty0, tx0);
+        __syncthreads();
+        if (ty0 >= H) continue;
+#pragma unroll 1
+        for (int rr = 0; rr < LT_H / 4; ++rr) {
+            const int ly = wave * (LT_H / 4) + rr, y = ty0 + ly, x = tx0 + lane;
+            const bool in = y < H && x < W;
+            const int64_t o = (int64_t)y * W + x;
+            const int e = in ? (int)Ep[o] : 0;
+            uint32_t f[8];
+            build_features<LT_W>(t, ly, lane, f);
+            *reinterpret_cast<uint4 *>(&wl[wave].feat[lane][0]) = make_uint4(f[0], f[1], f[2], f[3]);
+            *reinterpret_cast<uint4 *>(&wl[wave].feat[lane][4]) = make_uint4(f[4], f[5], f[6], f[7]);
+            wl[wave].bin[lane] = mlp_bin(e, k_img);
+            wave_lds_sync();
+            mlp_wave64(wl[wave], B1, L, lane);
+            const uint32_t ml = wl[wave].ml[lane];
+            if (!in) continue;
+            int s[3];
+            gf_at<LT_W>(t, ly, lane, s);
+            uint32_t word = (uint32_t)e << 24;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int2 ab = s_ab[c][e];
+                const int est = s_fl[c][e] ? (int)((ml >> (8 * c)) & 255u) : mstar(ab.x, ab.y, s[c]);
+                const int m = est + r[c * npx + o];
+                bad |= (m < 0) | (m > 255);
+                word |= (uint32_t)(m & 255) << (8 * c);
+            }
+            out[o] = word;
+        }
+    }
+    if (bad && d.status) atomicExch(d.status, RDL_ECORRUPT);
+}
+
 // ---------------------------------------------------------------------------
 // K7 residual histograms: hist[c][r + 255].
 // ---------------------------------------------------------------------------
@@ -1016,6 +1408,15 @@ void launch_resid(const ImgDesc *d, int n, int wgs, hipStream_t s) {
 }
 void launch_decode(const ImgDesc *d, int n, int wgs, hipStream_t s) {
     hipLaunchKernelGGL(k_decode, dim3(wgs), dim3(STRIP_THREADS), 0, s, d, n);
+}
+void launch_learn(const ImgDesc *d, int n, int wgs, hipStream_t s) {
+    hipLaunchKernelGGL(k_learn, dim3(wgs), dim3(256), 0, s, d, n);
+}
+void launch_select(const ImgDesc *d, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_select, dim3(256 * n), dim3(256), 0, s, d, n);
+}
+void launch_decode_learned(const ImgDesc *d, int n, int wgs, hipStream_t s) {
+    hipLaunchKernelGGL(k_decode_learned, dim3(wgs), dim3(256), 0, s, d, n);
 }
 void launch_hist(const ImgDesc *d, int n, int wgs, hipStream_t s) {
     hipLaunchKernelGGL(k_hist, dim3(wgs), dim3(TILE_THREADS), 0, s, d, n);

@@ -46,6 +46,8 @@ _SIGS = {
     "rdl_stage_fit": ([_vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp], _i),
     "rdl_stage_resid": ([_vp, _vp, _vp, _vp, _i, _i, _vp, _vp], _i),
     "rdl_profile_encode": ([_vp, _vp, _i, _i, _i, _vp, _vp, _vp, _i, _vp, _vp], _i),
+    "rdl_set_model": ([_vp, _vp, C.c_size_t], _i),
+    "rdl_set_estimator": ([_vp, _i], _i),
 }
 
 STAGES = ("keystat", "tmo_base", "fit_sums", "solve", "resid")
@@ -137,6 +139,19 @@ class Codec:
             self.close()
         except Exception:
             pass
+
+    # -------------------------------------------------------------- learned estimator
+    def set_model(self, blob: bytes | None):
+        """Load a model blob (host bytes) or clear it (None)."""
+        if blob is None:
+            _chk(self._L.rdl_set_model(self._h, None, 0), "rdl_set_model")
+            return
+        buf = C.create_string_buffer(bytes(blob), len(blob))
+        _chk(self._L.rdl_set_model(self._h, buf, len(blob)), "rdl_set_model")
+
+    def set_estimator(self, mode: int):
+        """0: plain SLR; 1: learned estimate where it beats SLR per region."""
+        _chk(self._L.rdl_set_estimator(self._h, int(mode)), "rdl_set_estimator")
 
     # -------------------------------------------------------------- buffers
     def alloc_outputs(self, H: int, W: int):
