@@ -61,6 +61,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle budget (0 = skip)")
     ap.add_argument("--profile-reps", type=int, default=50)
+    ap.add_argument("--learned-steps", type=int, default=50, help="timed encodes with the learned estimator (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the encoder of one image runs on one device, and this "
@@ -129,6 +130,33 @@ def main():
     copy_gbps = 2 * (1 << 30) * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del a, b
 
+    # learned estimator with per-region SLR fallback, same image, same timing
+    learned = None
+    model_path = os.path.join(ROOT, "paper_2309_11072_amd", "mlp_model.bin")
+    if os.path.exists(model_path) and args.learned_steps > 0:
+        with open(model_path, "rb") as fh:
+            codec.set_model(fh.read())
+        codec.set_estimator(1)
+        outl = codec.alloc_outputs(H, W)
+        for _ in range(3):
+            codec.encode_enh(d, q, out=outl)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.learned_steps):
+            codec.encode_enh(d, q, out=outl)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_l = e0.elapsed_time(e1) / args.learned_steps
+        backl = codec.decode_enh(outl[0], outl[1], outl[2], H, W)
+        hl = codec.resid_hist(outl[2], H, W).cpu().numpy()
+        hdl = rdl.header_from_bytes(outl[1])
+        learned = {"Mpixel_s": round(H * W / (ms_l * 1e-3) / 1e6, 2), "ms_per_step": round(ms_l, 5),
+                   "bits_per_pixel": round(sum(entropy_bits(hl[c].tolist()) for c in range(3)), 4),
+                   "lossless": bool(torch.equal(backl, d)),
+                   "regions_learned": int(hdl["flag"].sum()), "regions": int(3 * hdl["n_regions"]),
+                   "model_hash": "%016x" % int(hdl["model_hash"])}
+        codec.set_estimator(0)
+
     cpu = None
     if args.cpu_seconds > 0:
         cpu = cpu_baseline(x, q, args.cpu_seconds)
@@ -142,7 +170,9 @@ def main():
                                "plain SLR estimator (hipGraph replay)", "H": H, "W": W, "q": q,
                    "seed": sp.seed},
         "lossless": lossless,
-        "bits_per_pixel": {"slr": round(bpp, 4), "learned": None, "e_plane": round(e_bits, 4)},
+        "bits_per_pixel": {"slr": round(bpp, 4), "learned": learned["bits_per_pixel"] if learned else None,
+                           "e_plane": round(e_bits, 4)},
+        "learned": learned,
         "n_regions": int(h["n_regions"]),
         "pipeline_algorithmic_GBps": round(pipe_gbps, 1),
         "pipeline_frac_of_hbm": round(pipe_gbps / HBM_PEAK_GBPS, 4),

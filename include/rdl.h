@@ -148,6 +148,26 @@ int rdl_encode_batch(rdl_ctx *ctx, const rdl_image *imgs, int n, void *stream);
 int rdl_set_model(rdl_ctx *ctx, const void *blob, size_t nbytes);
 int rdl_set_estimator(rdl_ctx *ctx, int mode);
 
+/* ---- Training of the learned estimator (FP32, off the encoder's path) ----
+ * Float model: x = (S - 128)/128 over the 3x3 x 3 neighbourhood, h1 =
+ * W1 x + B1[bin], a1 = ReLU(h1), h2 = W2 a1 + B2, a2 = ReLU(h2), o = W3 a2 +
+ * B3 predicting M/256; mean squared error; Adam (0.9, 0.999, 1e-8).  The
+ * parameter vector holds rdl_train_nparam() floats: W1[32][27], B1[32][32]
+ * (bin, out), W2[32][32], B2[32], W3[3][32], B3[3].
+ * rdl_train_samples builds n sample records (rdl_train_sample_bytes() bytes
+ * each: 27 feature bytes S - 128, bin, M_R, M_G, M_B, pad) for the pixel
+ * indices idx (device int64, y*W + x) of an encoded image (rgbe, its decoded
+ * SDRI sdr, and k_img from its header).  rdl_train_step runs one Adam step on
+ * samples [base, base + batch) (clipped at n_samples), step >= 1; loss_out
+ * (device float, may be NULL) receives the summed squared error of the batch.
+ * Gradient sums are reduced in a fixed order: a step is deterministic. */
+int rdl_train_sample_bytes(void);
+int rdl_train_nparam(void);
+int rdl_train_samples(rdl_ctx *ctx, const uint8_t *rgbe, const uint8_t *sdr, int H, int W, int k_img,
+                      const int64_t *idx, int64_t n, void *out_samples, void *stream);
+int rdl_train_step(rdl_ctx *ctx, float *params, float *adam_m, float *adam_v, const void *samples, int64_t base,
+                   int64_t n_samples, int batch, float lr, int step, float *loss_out, void *stream);
+
 /* Residual histograms for the zeroth-order-entropy metric: hist int64
  * [3][511], hist[c][r + 255] counts residual value r of channel c. */
 int rdl_resid_hist(rdl_ctx *ctx, const void *resid, int H, int W, int64_t *hist, void *stream);

@@ -44,6 +44,9 @@ struct rdl_ctx {
     size_t ml_cap = 0;        // bytes
     uint32_t *d_lhist = nullptr;
     size_t lhist_cap = 0;     // images
+    // training scratch: per-workgroup gradient partials
+    float *d_part = nullptr;
+    size_t part_cap = 0;      // floats
 };
 
 namespace {
@@ -266,6 +269,7 @@ void rdl_destroy(rdl_ctx *c) {
         if (e.d_lhist) (void)hipFree(e.d_lhist);
     }
     if (c->d_model) (void)hipFree(c->d_model);
+    if (c->d_part) (void)hipFree(c->d_part);
     if (c->d_ml) (void)hipFree(c->d_ml);
     if (c->d_lhist) (void)hipFree(c->d_lhist);
     if (c->d_desc) (void)hipFree(c->d_desc);
@@ -641,6 +645,36 @@ int rdl_set_estimator(rdl_ctx *c, int mode) {
     if (mode == 1 && !c->d_model) return RDL_EUNSUPPORTED;
     c->estimator = mode;
     return RDL_OK;
+}
+
+int rdl_train_sample_bytes(void) { return train_sample_bytes(); }
+int rdl_train_nparam(void) { return train_nparam(); }
+
+int rdl_train_samples(rdl_ctx *c, const uint8_t *rgbe, const uint8_t *sdr, int H, int W, int k_img,
+                      const int64_t *idx, int64_t n, void *out_samples, void *stream) {
+    if (!c || !rgbe || !sdr || !idx || !out_samples || !size_ok(H, W) || n < 1) return RDL_EINVAL;
+    DeviceGuard g(c->device);
+    launch_train_samples(rgbe, sdr, H, W, k_img, idx, n, out_samples, (hipStream_t)stream);
+    return check_launch("k_train_samples");
+}
+
+int rdl_train_step(rdl_ctx *c, float *params, float *adam_m, float *adam_v, const void *samples, int64_t base,
+                   int64_t n_samples, int batch, float lr, int step, float *loss_out, void *stream) {
+    if (!c || !params || !adam_m || !adam_v || !samples || batch < 1 || step < 1 || base < 0 || base >= n_samples)
+        return RDL_EINVAL;
+    DeviceGuard g(c->device);
+    const int nwg = (batch + 63) / 64;
+    const size_t need = (size_t)nwg * (train_nparam() + 1);
+    if (need > c->part_cap) {
+        if (c->d_part) HIPCHK(hipFree(c->d_part));
+        c->d_part = nullptr;
+        c->part_cap = 0;
+        HIPCHK(hipMalloc(&c->d_part, need * sizeof(float)));
+        c->part_cap = need;
+    }
+    launch_train_step(params, adam_m, adam_v, samples, base, n_samples, batch, c->d_part,
+                      c->d_part + (size_t)nwg * train_nparam(), lr, step, loss_out, (hipStream_t)stream);
+    return check_launch("k_train_grad/k_train_adam");
 }
 
 }  // extern "C"

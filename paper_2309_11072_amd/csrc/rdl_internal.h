@@ -87,4 +87,12 @@ void launch_learn(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_select(const ImgDesc *d, int n, hipStream_t s);
 void launch_decode_learned(const ImgDesc *d, int n, int wgs, hipStream_t s);
 
+// Training kernels (defined in rdl_train.hip).
+void launch_train_samples(const uint8_t *rgbe, const uint8_t *sdr, int H, int W, int k_img, const int64_t *idx,
+                          int64_t n, void *out, hipStream_t s);
+void launch_train_step(float *prm, float *m1, float *m2, const void *smp, int64_t base, int64_t nsamp, int batch,
+                       float *part, float *ploss, float lr, int step, float *loss_out, hipStream_t s);
+int train_nparam();
+int train_sample_bytes();
+
 }  // namespace rdl

@@ -48,6 +48,10 @@ _SIGS = {
     "rdl_profile_encode": ([_vp, _vp, _i, _i, _i, _vp, _vp, _vp, _i, _vp, _vp], _i),
     "rdl_set_model": ([_vp, _vp, C.c_size_t], _i),
     "rdl_set_estimator": ([_vp, _i], _i),
+    "rdl_train_sample_bytes": ([], _i),
+    "rdl_train_nparam": ([], _i),
+    "rdl_train_samples": ([_vp, _vp, _vp, _i, _i, _i, _vp, C.c_int64, _vp, _vp], _i),
+    "rdl_train_step": ([_vp, _vp, _vp, _vp, _vp, C.c_int64, C.c_int64, _i, C.c_float, _i, _vp, _vp], _i),
 }
 
 STAGES = ("keystat", "tmo_base", "fit_sums", "solve", "resid")
@@ -152,6 +156,24 @@ class Codec:
     def set_estimator(self, mode: int):
         """0: plain SLR; 1: learned estimate where it beats SLR per region."""
         _chk(self._L.rdl_set_estimator(self._h, int(mode)), "rdl_set_estimator")
+
+    # -------------------------------------------------------------- training
+    def train_samples(self, rgbe: torch.Tensor, sdr: torch.Tensor, k_img: int, idx: torch.Tensor,
+                      out: torch.Tensor | None = None, stream=None):
+        """Sample records (uint8 [n, 32]) for the pixel indices idx (int64)."""
+        H, W = int(rgbe.shape[0]), int(rgbe.shape[1])
+        n = int(idx.numel())
+        nb = self._L.rdl_train_sample_bytes()
+        out = out if out is not None else torch.empty((n, nb), dtype=torch.uint8, device=rgbe.device)
+        _chk(self._L.rdl_train_samples(self._h, _ptr(rgbe), _ptr(sdr), H, W, int(k_img), _ptr(idx), n, _ptr(out),
+                                       _stream(stream)), "rdl_train_samples")
+        return out
+
+    def train_step(self, params, adam_m, adam_v, samples, base: int, batch: int, lr: float, step: int,
+                   loss_out=None, stream=None):
+        _chk(self._L.rdl_train_step(self._h, _ptr(params), _ptr(adam_m), _ptr(adam_v), _ptr(samples), int(base),
+                                    int(samples.shape[0]), int(batch), float(lr), int(step), _ptr(loss_out),
+                                    _stream(stream)), "rdl_train_step")
 
     # -------------------------------------------------------------- buffers
     def alloc_outputs(self, H: int, W: int):
