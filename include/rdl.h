@@ -82,7 +82,9 @@ size_t rdl_resid_bytes(int H, int W);
 size_t rdl_header_bytes(void);
 
 /* Host-side validation of a header copied to the host: magic, version, size
- * and parameter bounds (|a_q| <= 255*2^22).  RDL_OK or RDL_ECORRUPT. */
+ * and parameter bounds (|a_q| <= 255*2^22, -65025*2^14 <= b_q <= 65280*2^14,
+ * the ranges every least-squares line through 8-bit data stays in).  RDL_OK
+ * or RDL_ECORRUPT. */
 int rdl_header_validate(const rdl_header *host_hdr, int H, int W);
 
 /* Encoder (Sec. III, Fig. 2 bottom; all four steps on the GPU):
@@ -93,17 +95,20 @@ int rdl_header_validate(const rdl_header *host_hdr, int H, int W);
  *       fixed-point slope and intercept -> out_coeffs;
  *   (d) out_resid = M - M* with M* = round(a_E S* + b_E) in [0, 255] (Eq. 8).
  * rgbe: H*W*4 bytes; out_sdr: H*W*3; out_coeffs: one rdl_header; out_resid:
- * rdl_resid_bytes(H, W).  1 <= H, W; H*W < 2^31; 1 <= q <= 100.  Buffers
- * must not overlap.  RDL_EINVAL on a bad argument. */
+ * rdl_resid_bytes(H, W).  1 <= H, W; W <= 2^28; H*W < 2^31; 1 <= q <= 100.
+ * rgbe, out_sdr and out_coeffs start on 4-byte boundaries, out_resid on a
+ * 2-byte one.  Buffers must not overlap.  RDL_EINVAL on a bad argument. */
 int rdl_encode_enh(rdl_ctx *ctx, const uint8_t *rgbe, int H, int W, int q, uint8_t *out_sdr,
                    rdl_header *out_coeffs, void *out_resid, void *stream);
 
 /* Decoder of the enhancement layer (Sec. I: the HDR image is recovered by
  * adding the residuals; Sec. III.C: parameters are read, not recomputed):
  * S* = GF(sdr), M = M*(a_E, b_E, S*) + r, out_rgbe = (M, E).  coeffs is a
- * DEVICE header (as written by rdl_encode_enh).  If status (device int32,
+ * DEVICE header (as written by rdl_encode_enh); sdr, coeffs and out_rgbe
+ * start on 4-byte boundaries, resid on a 2-byte one.  If status (device int32,
  * may be NULL) is given it receives RDL_OK, or RDL_ECORRUPT when the header's
- * magic, version or size do not match or a decoded mantissa leaves [0, 255]. */
+ * magic, version or size do not match, a coefficient is outside the bounds
+ * rdl_header_validate checks, or a decoded mantissa leaves [0, 255]. */
 int rdl_decode_enh(rdl_ctx *ctx, const uint8_t *sdr, const rdl_header *coeffs, const void *resid,
                    int H, int W, uint8_t *out_rgbe, int32_t *status, void *stream);
 
@@ -210,12 +215,54 @@ enum {
     RDL_NSTAGES = 5
 };
 
-/* Runs the same kernels as rdl_encode_enh (same arguments and outputs), one
- * launch at a time with a pair of HIP events around each launch on `stream`,
- * `reps` times, and writes the mean duration of each stage in milliseconds to
- * the HOST array ms[RDL_NSTAGES].  Synchronises `stream`; not capturable. */
+/* Runs the same kernels as rdl_encode_enh (same arguments and outputs) for
+ * timing: each stage kernel is launched `reps` times back to back between a
+ * pair of HIP events on `stream`, and the mean duration of one launch, in
+ * milliseconds, goes to the HOST array ms[RDL_NSTAGES].  Repeated stages see
+ * scaled sums or cleaned scratch, which leaves their cost unchanged; one
+ * ordinary encode at the end leaves correct outputs.  Synchronises `stream`;
+ * not capturable. */
 int rdl_profile_encode(rdl_ctx *ctx, const uint8_t *rgbe, int H, int W, int q, uint8_t *out_sdr,
                        rdl_header *out_coeffs, void *out_resid, int reps, float *ms, void *stream);
+
+/* ---- Launch-shape tuning ----
+ *
+ * The GF-based stages give each wave a strip of 256 pixels and some rows
+ * (4 waves stacked per workgroup).  Tall strips leave SIMDs idle on small
+ * images; short ones re-read more halo rows of S and, in the fit, make more
+ * workgroups add their partial sums to the same global totals.  The context
+ * keeps one value per tuning parameter and size class floor(log2(H * W))
+ * (0..31), initially 16 rows for the fit and 8 for the residual and decode
+ * walks; a batch uses each image's own class.  The fit's per-(channel, E)
+ * bins in LDS are kept in 1, 2 or 4 copies (initially 4) that neighbouring
+ * lanes alternate between, so that lanes closing runs of the same exponent
+ * at once do not all add to one address; one launch takes the value of its
+ * largest image.  Captured graphs are keyed on the shapes, so a change takes
+ * effect at the next call. */
+enum {
+    RDL_TUNE_FIT_ROWS = 0,   /* rows per wave of the fit (k_fit_sums)         */
+    RDL_TUNE_RESID_ROWS = 1, /* rows per wave of the residual/decode walks    */
+    RDL_TUNE_FIT_BINS = 2,   /* privatised copies of the fit's LDS bins       */
+    RDL_NTUNE = 3
+};
+
+/* Encodes the caller's image once (same arguments and outputs as
+ * rdl_encode_enh, plain estimator), then, for each parameter, launches its
+ * kernel `reps` times back to back for each value (rows: 2, 4, 8, 16, 32;
+ * bin copies: 1, 2, 4), timed
+ * with HIP events on `stream`, and keeps the fastest for the image's size
+ * class; the HOST array best[RDL_NTUNE] (may be NULL) receives the choices.
+ * Outputs hold a correct encode on return.  Synchronises `stream`; not
+ * capturable.  RDL_EINVAL for the argument errors of rdl_encode_enh or
+ * reps < 1. */
+int rdl_autotune(rdl_ctx *ctx, const uint8_t *rgbe, int H, int W, int q, uint8_t *out_sdr,
+                 rdl_header *out_coeffs, void *out_resid, int reps, int *best, void *stream);
+
+/* Read / write one entry (for saving and restoring a tuned table).  Rows are
+ * powers of two in [2, 32], bin copies 1, 2 or 4; anything else, or a
+ * parameter or class out of range, gives RDL_EINVAL. */
+int rdl_get_tuning(rdl_ctx *ctx, int param, int size_class, int *value);
+int rdl_set_tuning(rdl_ctx *ctx, int param, int size_class, int value);
 
 #ifdef __cplusplus
 }

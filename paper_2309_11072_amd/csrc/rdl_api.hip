@@ -47,6 +47,9 @@ struct rdl_ctx {
     // training scratch: per-workgroup gradient partials
     float *d_part = nullptr;
     size_t part_cap = 0;      // floats
+    // launch shapes per tuning parameter and size class floor(log2(H W)):
+    // strip rows per wave of the fit and of the residual/decode walks
+    int tune[RDL_NTUNE][32];
 };
 
 namespace {
@@ -77,7 +80,7 @@ int hip_fail(hipError_t e, const char *where) {
         if (e_ != hipSuccess) return hip_fail(e_, #expr); \
     } while (0)
 
-bool size_ok(int H, int W) { return H >= 1 && W >= 1 && (int64_t)H * W < ((int64_t)1 << 31); }
+bool size_ok(int H, int W) { return H >= 1 && W >= 1 && W <= (1 << 28) && (int64_t)H * W < ((int64_t)1 << 31); }
 
 bool aligned4(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 3) == 0; }
 
@@ -104,6 +107,8 @@ int ensure_scratch(rdl_ctx *c, size_t n) {
 
 struct Grid {
     int px = 0, blk = 0, tile = 0, fit = 0, res = 0, learn = 0;
+    int fit_bins = 1;  // one launch shape for the whole fit launch: the largest image's
+    int64_t fit_px = -1;
 };
 
 int ensure_learn_scratch(rdl_ctx *c, size_t ml_bytes, size_t n) {
@@ -151,10 +156,19 @@ uint64_t fnv1a64(const uint8_t *p, size_t n) {
     return h;
 }
 
-// Assign each image its first workgroup per kernel family.
-Grid layout(std::vector<ImgDesc> &v) {
+int size_class(int H, int W) {
+    const uint64_t px = (uint64_t)H * (uint64_t)W;
+    return 63 - __builtin_clzll(px);  // px >= 1
+}
+
+// Assign each image its launch shape (from the context's tuning table) and
+// its first workgroup per kernel family.
+Grid layout(const rdl_ctx *c, std::vector<ImgDesc> &v) {
     Grid g;
     for (auto &d : v) {
+        d.srh_fit = c->tune[RDL_TUNE_FIT_ROWS][size_class(d.H, d.W)];
+        d.srh_res = c->tune[RDL_TUNE_RESID_ROWS][size_class(d.H, d.W)];
+        d.fit_bins = c->tune[RDL_TUNE_FIT_BINS][size_class(d.H, d.W)];
         d.wg_px = g.px;
         d.wg_blk = g.blk;
         d.wg_tile = g.tile;
@@ -164,8 +178,12 @@ Grid layout(std::vector<ImgDesc> &v) {
         g.px += wgs_px(d.H, d.W);
         g.blk += wgs_blk(d.H, d.W);
         g.tile += wgs_tile(d.H, d.W);
-        g.fit += wgs_strip(d.H, d.W);
-        g.res += wgs_strip(d.H, d.W);
+        g.fit += wgs_strip(d.H, d.W, d.srh_fit);
+        if ((int64_t)d.H * d.W > g.fit_px) {
+            g.fit_px = (int64_t)d.H * d.W;
+            g.fit_bins = d.fit_bins;
+        }
+        g.res += wgs_strip(d.H, d.W, d.srh_res);
         g.learn += wgs_learn(d.H, d.W);
     }
     return g;
@@ -177,7 +195,7 @@ void bind_scratch(ImgDesc &d, int64_t *base) {
     d.nks = std::min(KS_STRIPES, std::max(1, wgs_px(d.H, d.W)));
     d.sums = base + SCR_SUMS;
     d.part = base + SCR_PART;
-    d.nfs = std::min(FIT_STRIPES, std::max(1, wgs_strip(d.H, d.W)));
+    d.nfs = std::min(FIT_STRIPES, std::max(1, wgs_strip(d.H, d.W, d.srh_fit)));
 }
 
 int upload(rdl_ctx *c, const std::vector<ImgDesc> &v, hipStream_t s) {
@@ -200,7 +218,7 @@ int check_launch(const char *what) {
 void enqueue_encode(const ImgDesc *d, int n, const Grid &g, bool learned, hipStream_t s) {
     launch_keystat(d, n, g.px, s);
     launch_tmo_base(d, n, g.blk, false, s);
-    launch_fit_sums(d, n, g.fit, s);
+    launch_fit_sums(d, n, g.fit, g.fit_bins, s);
     launch_solve(d, n, s);
     if (learned) {
         launch_learn(d, n, g.learn, s);
@@ -254,6 +272,11 @@ int rdl_create(rdl_ctx **out, int device) {
     rdl_ctx *c = new (std::nothrow) rdl_ctx();
     if (!c) return RDL_ENOMEM;
     c->device = device;
+    for (int k = 0; k < 32; ++k) {
+        c->tune[RDL_TUNE_FIT_ROWS][k] = SRH_FIT_DEFAULT;
+        c->tune[RDL_TUNE_RESID_ROWS][k] = SRH_RES_DEFAULT;
+        c->tune[RDL_TUNE_FIT_BINS][k] = FIT_BINS_DEFAULT;
+    }
     *out = c;
     return RDL_OK;
 }
@@ -285,6 +308,7 @@ int rdl_header_validate(const rdl_header *h, int H, int W) {
     for (int c = 0; c < 3; ++c)
         for (int e = 0; e < 256; ++e) {
             if (h->a_q[c][e] > amax || h->a_q[c][e] < -amax) return RDL_ECORRUPT;
+            if (h->b_q[c][e] > (int64_t)65280 * 16384 || h->b_q[c][e] < (int64_t)-65025 * 16384) return RDL_ECORRUPT;
             if (!h->present[e] && (h->a_q[c][e] || h->b_q[c][e])) return RDL_ECORRUPT;
             if (h->flag[c][e] > 1) return RDL_ECORRUPT;
         }
@@ -310,7 +334,8 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
         const rdl_image &m = imgs[k];
         if (!m.rgbe || !m.sdr || !m.hdr || !m.resid) return RDL_EINVAL;
         if (!size_ok(m.H, m.W) || m.q < 1 || m.q > 100) return RDL_EINVAL;
-        if (!aligned4(m.rgbe) || !aligned4(m.hdr) || (reinterpret_cast<uintptr_t>(m.resid) & 1)) return RDL_EINVAL;
+        if (!aligned4(m.rgbe) || !aligned4(m.sdr) || !aligned4(m.hdr) || (reinterpret_cast<uintptr_t>(m.resid) & 1))
+            return RDL_EINVAL;
     }
     const bool learned = c->estimator == 1;
     if (learned && !c->d_model) return RDL_EUNSUPPORTED;
@@ -332,7 +357,7 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
             d.model_hash = c->model_hash;
         }
     }
-    const Grid gr = layout(v);
+    const Grid gr = layout(c, v);
 
     // Replay a graph captured earlier for exactly these descriptors.
     for (auto &e : c->graphs)
@@ -414,7 +439,8 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
 int rdl_decode_enh(rdl_ctx *c, const uint8_t *sdr, const rdl_header *coeffs, const void *resid, int H, int W,
                    uint8_t *out_rgbe, int32_t *status, void *stream) {
     if (!c || !sdr || !coeffs || !resid || !out_rgbe || !size_ok(H, W)) return RDL_EINVAL;
-    if (!aligned4(out_rgbe) || !aligned4(coeffs) || (reinterpret_cast<uintptr_t>(resid) & 1)) return RDL_EINVAL;
+    if (!aligned4(out_rgbe) || !aligned4(sdr) || !aligned4(coeffs) || (reinterpret_cast<uintptr_t>(resid) & 1))
+        return RDL_EINVAL;
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
     std::vector<ImgDesc> v(1, blank());
@@ -427,7 +453,7 @@ int rdl_decode_enh(rdl_ctx *c, const uint8_t *sdr, const rdl_header *coeffs, con
     v[0].W = W;
     v[0].model = c->d_model;
     v[0].model_hash = c->model_hash;
-    const Grid gr = layout(v);
+    const Grid gr = layout(c, v);
     int rc = upload(c, v, s);
     if (rc) return rc;
     launch_decode(c->d_desc, 1, gr.res, s);
@@ -445,7 +471,7 @@ int rdl_resid_hist(rdl_ctx *c, const void *resid, int H, int W, int64_t *hist, v
     v[0].H = H;
     v[0].W = W;
     v[0].flags = F_ZERO_HIST;
-    const Grid gr = layout(v);
+    const Grid gr = layout(c, v);
     int rc = upload(c, v, s);
     if (rc) return rc;
     launch_zero(c->d_desc, 1, s);
@@ -462,7 +488,7 @@ int rdl_stage_keystat(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int64_t *ou
     v[0].H = H;
     v[0].W = W;
     v[0].flags = F_CLEAN_KS;
-    const Grid gr = layout(v);
+    const Grid gr = layout(c, v);
     int rc = ensure_scratch(c, 1);
     if (rc) return rc;
     bind_scratch(v[0], c->d_scratch);
@@ -476,7 +502,8 @@ int rdl_stage_keystat(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int64_t *ou
 
 int rdl_stage_tmo_base(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int q, const int64_t *keystat, uint8_t *out_sdr0,
                        uint8_t *out_sdr, int16_t *out_dct, void *stream) {
-    if (!c || !rgbe || !keystat || !out_sdr || !size_ok(H, W) || q < 1 || q > 100 || !aligned4(rgbe)) return RDL_EINVAL;
+    if (!c || !rgbe || !keystat || !out_sdr || !size_ok(H, W) || q < 1 || q > 100 || !aligned4(rgbe) || !aligned4(out_sdr))
+        return RDL_EINVAL;
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
     std::vector<ImgDesc> v(1, blank());
@@ -489,7 +516,7 @@ int rdl_stage_tmo_base(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int q, con
     v[0].H = H;
     v[0].W = W;
     v[0].q = q;
-    const Grid gr = layout(v);
+    const Grid gr = layout(c, v);
     int rc = upload(c, v, s);
     if (rc) return rc;
     launch_tmo_base(c->d_desc, 1, gr.blk, out_sdr0 != nullptr || out_dct != nullptr, s);
@@ -499,7 +526,7 @@ int rdl_stage_tmo_base(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int q, con
 int rdl_stage_fit(rdl_ctx *c, const uint8_t *rgbe, const uint8_t *sdr, int H, int W, int q, const int64_t *keystat,
                   int64_t *out_sums, rdl_header *out_coeffs, void *stream) {
     if (!c || !rgbe || !sdr || !out_sums || !out_coeffs || !size_ok(H, W) || q < 1 || q > 100) return RDL_EINVAL;
-    if (!aligned4(rgbe) || !aligned4(out_coeffs)) return RDL_EINVAL;
+    if (!aligned4(rgbe) || !aligned4(sdr) || !aligned4(out_coeffs)) return RDL_EINVAL;
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
     std::vector<ImgDesc> v(1, blank());
@@ -509,7 +536,7 @@ int rdl_stage_fit(rdl_ctx *c, const uint8_t *rgbe, const uint8_t *sdr, int H, in
     v[0].H = H;
     v[0].W = W;
     v[0].q = q;
-    const Grid gr = layout(v);
+    const Grid gr = layout(c, v);
     int rc = ensure_scratch(c, 1);
     if (rc) return rc;
     bind_scratch(v[0], c->d_scratch);
@@ -519,7 +546,7 @@ int rdl_stage_fit(rdl_ctx *c, const uint8_t *rgbe, const uint8_t *sdr, int H, in
     c->last_key.clear();
     rc = upload(c, v, s);
     if (rc) return rc;
-    launch_fit_sums(c->d_desc, 1, gr.fit, s);
+    launch_fit_sums(c->d_desc, 1, gr.fit, gr.fit_bins, s);
     launch_solve(c->d_desc, 1, s);
     return check_launch("k_fit_sums/k_solve");
 }
@@ -527,7 +554,8 @@ int rdl_stage_fit(rdl_ctx *c, const uint8_t *rgbe, const uint8_t *sdr, int H, in
 int rdl_stage_resid(rdl_ctx *c, const uint8_t *rgbe, const uint8_t *sdr, const rdl_header *coeffs, int H, int W,
                     void *out_resid, void *stream) {
     if (!c || !rgbe || !sdr || !coeffs || !out_resid || !size_ok(H, W)) return RDL_EINVAL;
-    if (!aligned4(rgbe) || !aligned4(coeffs) || (reinterpret_cast<uintptr_t>(out_resid) & 1)) return RDL_EINVAL;
+    if (!aligned4(rgbe) || !aligned4(sdr) || !aligned4(coeffs) || (reinterpret_cast<uintptr_t>(out_resid) & 1))
+        return RDL_EINVAL;
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
     std::vector<ImgDesc> v(1, blank());
@@ -537,7 +565,7 @@ int rdl_stage_resid(rdl_ctx *c, const uint8_t *rgbe, const uint8_t *sdr, const r
     v[0].resid = (uint8_t *)out_resid;
     v[0].H = H;
     v[0].W = W;
-    const Grid gr = layout(v);
+    const Grid gr = layout(c, v);
     int rc = upload(c, v, s);
     if (rc) return rc;
     launch_resid(c->d_desc, 1, gr.res, s);
@@ -547,7 +575,9 @@ int rdl_stage_resid(rdl_ctx *c, const uint8_t *rgbe, const uint8_t *sdr, const r
 int rdl_profile_encode(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int q, uint8_t *out_sdr, rdl_header *out_coeffs,
                        void *out_resid, int reps, float *ms, void *stream) {
     if (!c || !rgbe || !out_sdr || !out_coeffs || !out_resid || !ms || reps < 1) return RDL_EINVAL;
-    if (!size_ok(H, W) || q < 1 || q > 100 || !aligned4(rgbe) || !aligned4(out_coeffs)) return RDL_EINVAL;
+    if (!size_ok(H, W) || q < 1 || q > 100 || !aligned4(rgbe) || !aligned4(out_sdr) || !aligned4(out_coeffs) ||
+        (reinterpret_cast<uintptr_t>(out_resid) & 1))
+        return RDL_EINVAL;
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
     std::vector<ImgDesc> v(1, blank());
@@ -559,40 +589,158 @@ int rdl_profile_encode(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int q, uin
     v[0].W = W;
     v[0].q = q;
     v[0].flags = F_CLEAN_KS;
-    const Grid gr = layout(v);
+    const Grid gr = layout(c, v);
     int rc = ensure_scratch(c, 1);
     if (rc) return rc;
     bind_scratch(v[0], c->d_scratch);
     c->last_key.clear();
     rc = upload(c, v, s);
     if (rc) return rc;
-    hipEvent_t ev[2 * RDL_NSTAGES];
-    for (int k = 0; k < 2 * RDL_NSTAGES; ++k) HIPCHK(hipEventCreate(&ev[k]));
+    // Each stage is launched reps times back to back between two events, so
+    // the mean excludes host launch gaps.  Repeated key statistic and fit
+    // launches scale the image's sums by reps, which leaves every quotient
+    // the solve takes unchanged; repeated solves after the first see cleaned
+    // stripes.  One ordinary encode at the end leaves correct outputs.
+    hipEvent_t ev[2];
+    HIPCHK(hipEventCreate(&ev[0]));
+    HIPCHK(hipEventCreate(&ev[1]));
     double acc[RDL_NSTAGES] = {0};
     hipError_t err = hipSuccess;
-    for (int r = 0; r < reps && err == hipSuccess; ++r) {
-        const ImgDesc *d = c->d_desc;
-        for (int st = 0; st < RDL_NSTAGES; ++st) {
-            (void)hipEventRecord(ev[2 * st], s);
+    const ImgDesc *d = c->d_desc;
+    for (int st = 0; st < RDL_NSTAGES && err == hipSuccess; ++st) {
+        (void)hipEventRecord(ev[0], s);
+        for (int r = 0; r < reps; ++r) {
             switch (st) {
                 case RDL_STAGE_KEYSTAT: launch_keystat(d, 1, gr.px, s); break;
                 case RDL_STAGE_TMO_BASE: launch_tmo_base(d, 1, gr.blk, false, s); break;
-                case RDL_STAGE_FIT: launch_fit_sums(d, 1, gr.fit, s); break;
+                case RDL_STAGE_FIT: launch_fit_sums(d, 1, gr.fit, gr.fit_bins, s); break;
                 case RDL_STAGE_SOLVE: launch_solve(d, 1, s); break;
                 case RDL_STAGE_RESID: launch_resid(d, 1, gr.res, s); break;
             }
-            (void)hipEventRecord(ev[2 * st + 1], s);
         }
-        err = hipStreamSynchronize(s);
-        for (int st = 0; st < RDL_NSTAGES && err == hipSuccess; ++st) {
-            float t = 0;
-            err = hipEventElapsedTime(&t, ev[2 * st], ev[2 * st + 1]);
-            acc[st] += t;
-        }
+        (void)hipEventRecord(ev[1], s);
+        err = hipEventSynchronize(ev[1]);
+        float t = 0;
+        if (err == hipSuccess) err = hipEventElapsedTime(&t, ev[0], ev[1]);
+        acc[st] = t;
     }
-    for (int k = 0; k < 2 * RDL_NSTAGES; ++k) (void)hipEventDestroy(ev[k]);
+    if (err == hipSuccess) {
+        launch_keystat(d, 1, gr.px, s);
+        launch_tmo_base(d, 1, gr.blk, false, s);
+        launch_fit_sums(d, 1, gr.fit, gr.fit_bins, s);
+        launch_solve(d, 1, s);
+        launch_resid(d, 1, gr.res, s);
+        err = hipGetLastError();
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
     if (err != hipSuccess) return hip_fail(err, "rdl_profile_encode");
     for (int st = 0; st < RDL_NSTAGES; ++st) ms[st] = (float)(acc[st] / reps);
+    return RDL_OK;
+}
+
+int rdl_autotune(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int q, uint8_t *out_sdr, rdl_header *out_coeffs,
+                 void *out_resid, int reps, int *best, void *stream) {
+    if (!c || !rgbe || !out_sdr || !out_coeffs || !out_resid || reps < 1) return RDL_EINVAL;
+    if (!size_ok(H, W) || q < 1 || q > 100 || !aligned4(rgbe) || !aligned4(out_sdr) || !aligned4(out_coeffs) ||
+        (reinterpret_cast<uintptr_t>(out_resid) & 1))
+        return RDL_EINVAL;
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    const int cls = size_class(H, W);
+    int rc = ensure_scratch(c, 1);
+    if (rc) return rc;
+    hipEvent_t ev[2];
+    HIPCHK(hipEventCreate(&ev[0]));
+    HIPCHK(hipEventCreate(&ev[1]));
+    hipError_t err = hipSuccess;
+    c->last_key.clear();
+    auto table = [&]() {
+        std::vector<ImgDesc> v(1, blank());
+        v[0].rgbe = rgbe;
+        v[0].sdr = out_sdr;
+        v[0].hdr = out_coeffs;
+        v[0].resid = (uint8_t *)out_resid;
+        v[0].H = H;
+        v[0].W = W;
+        v[0].q = q;
+        v[0].flags = F_CLEAN_KS;
+        return v;
+    };
+    // One full encode first, so that S and the header the timed kernels read
+    // are the image's own.
+    {
+        std::vector<ImgDesc> v = table();
+        const Grid gr = layout(c, v);
+        bind_scratch(v[0], c->d_scratch);
+        rc = upload(c, v, s);
+        if (rc == RDL_OK) enqueue_encode(c->d_desc, 1, gr, false, s);
+    }
+    // Each parameter alone: its kernel launched reps times back to back per
+    // candidate.  Repeated fits only scale the image's sums (the solve that
+    // follows takes the same quotients); repeated residual passes rewrite
+    // the same outputs.
+    for (int p = 0; p < RDL_NTUNE && rc == RDL_OK && err == hipSuccess; ++p) {
+        float best_ms = 0.0f;
+        int pick = c->tune[p][cls];
+        const int lo = p == RDL_TUNE_FIT_BINS ? 1 : SRH_MIN, hi = p == RDL_TUNE_FIT_BINS ? 4 : SRH_MAX;
+        for (int srh = lo; srh <= hi && rc == RDL_OK && err == hipSuccess; srh *= 2) {
+            c->tune[p][cls] = srh;
+            std::vector<ImgDesc> v = table();
+            const Grid gr = layout(c, v);
+            bind_scratch(v[0], c->d_scratch);
+            rc = upload(c, v, s);
+            if (rc) break;
+            const ImgDesc *d = c->d_desc;
+            auto once = [&]() {
+                if (p != RDL_TUNE_RESID_ROWS) launch_fit_sums(d, 1, gr.fit, gr.fit_bins, s);
+                else launch_resid(d, 1, gr.res, s);
+            };
+            once();  // warm-up
+            (void)hipEventRecord(ev[0], s);
+            for (int r = 0; r < reps; ++r) once();
+            (void)hipEventRecord(ev[1], s);
+            if (p != RDL_TUNE_RESID_ROWS) launch_solve(d, 1, s);  // consumes (and cleans) the scaled sums
+            err = hipEventSynchronize(ev[1]);
+            float t = 0.0f;
+            if (err == hipSuccess) err = hipEventElapsedTime(&t, ev[0], ev[1]);
+            if (err == hipSuccess && (srh == lo || t < best_ms)) {
+                best_ms = t;
+                pick = srh;
+            }
+        }
+        c->tune[p][cls] = pick;
+        if (best) best[p] = pick;
+    }
+    // A final ordinary encode with the chosen shapes.
+    if (rc == RDL_OK && err == hipSuccess) {
+        std::vector<ImgDesc> v = table();
+        const Grid gr = layout(c, v);
+        bind_scratch(v[0], c->d_scratch);
+        rc = upload(c, v, s);
+        if (rc == RDL_OK) {
+            enqueue_encode(c->d_desc, 1, gr, false, s);
+            err = hipStreamSynchronize(s);
+        }
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (rc) return rc;
+    if (err != hipSuccess) return hip_fail(err, "rdl_autotune");
+    return RDL_OK;
+}
+
+int rdl_get_tuning(rdl_ctx *c, int param, int size_class, int *value) {
+    if (!c || !value || param < 0 || param >= RDL_NTUNE || size_class < 0 || size_class > 31) return RDL_EINVAL;
+    *value = c->tune[param][size_class];
+    return RDL_OK;
+}
+
+int rdl_set_tuning(rdl_ctx *c, int param, int size_class, int value) {
+    if (!c || param < 0 || param >= RDL_NTUNE || size_class < 0 || size_class > 31) return RDL_EINVAL;
+    const int lo = param == RDL_TUNE_FIT_BINS ? 1 : SRH_MIN, hi = param == RDL_TUNE_FIT_BINS ? 4 : SRH_MAX;
+    if (value < lo || value > hi || (value & (value - 1))) return RDL_EINVAL;
+    c->tune[param][size_class] = value;
     return RDL_OK;
 }
 

@@ -70,6 +70,35 @@ __device__ __forceinline__ int pack_i16(int lo, int hi) {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Every buffer a descriptor points to is device global memory.  Saying so
+// once, when a kernel takes its descriptor, lets every access through it
+// compile to global (not flat) memory instructions, whose waits do not
+// couple with LDS operations.  The detour through an integer keeps the
+// compiler from folding the two address-space casts away again.
+template <class T>
+__device__ __forceinline__ T *glb(T *p) {
+    return (T *)((__attribute__((address_space(1))) T *)(uintptr_t)p);
+}
+__device__ __forceinline__ ImgDesc desc_at(const ImgDesc *__restrict__ D, int i) {
+    ImgDesc d = D[i];
+    d.rgbe = glb(d.rgbe);
+    d.sdr0 = glb(d.sdr0);
+    d.sdr = glb(d.sdr);
+    d.dct = glb(d.dct);
+    d.hdr = glb(d.hdr);
+    d.resid = glb(d.resid);
+    d.ks = glb(d.ks);
+    d.sums = glb(d.sums);
+    d.part = glb(d.part);
+    d.status = glb(d.status);
+    d.out_rgbe = glb(d.out_rgbe);
+    d.hist = glb(d.hist);
+    d.ml = glb(d.ml);
+    d.lhist = glb(d.lhist);
+    d.model = glb(d.model);
+    return d;
+}
+
 // Image of workgroup `wg`: the last image whose first workgroup is <= wg.
 __device__ __forceinline__ int find_img(const ImgDesc *__restrict__ D, int n, int wg, int which) {
     int lo = 0, hi = n - 1;
@@ -122,7 +151,7 @@ __device__ __forceinline__ uint32_t lum_y(uint32_t w) {
 __global__ __launch_bounds__(256) void k_zero(const ImgDesc *__restrict__ D, int n) {
     const int i = blockIdx.x;
     if (i >= n) return;
-    const ImgDesc d = D[i];
+    const ImgDesc d = desc_at(D, i);
     if ((d.flags & F_ZERO_KS) && d.ks && threadIdx.x < 2 * d.nks) d.ks[threadIdx.x] = 0;
     if ((d.flags & F_ZERO_SUMS) && d.part)
         for (int k = threadIdx.x; k < d.nfs * 256 * NSUM; k += 256) d.part[k] = 0;
@@ -148,7 +177,7 @@ __global__ __launch_bounds__(KS_THREADS) void k_keystat(const ImgDesc *__restric
     __shared__ uint16_t s_log2f[4096];  // every entry is below 2^16
     __shared__ int64_t s_red[2][KS_THREADS / 64];
     const int i = find_img(D, n, blockIdx.x, 0);
-    const ImgDesc &d = D[i];
+    const ImgDesc d = desc_at(D, i);
     const int64_t npx = (int64_t)d.H * d.W;
     const int wgl = blockIdx.x - d.wg_px;
     const int64_t base = (int64_t)wgl * KS_PX_PER_WG;
@@ -318,7 +347,7 @@ __global__ __launch_bounds__(BLK_THREADS) void k_tmo_base(const ImgDesc *__restr
     __shared__ uint32_t s_X[3][BLK_WG][33];
     __shared__ int s_key[3];
     const int i = find_img(D, n, blockIdx.x, 1);
-    const ImgDesc &d = D[i];
+    const ImgDesc d = desc_at(D, i);
     const int H = d.H, W = d.W;
     for (int k = threadIdx.x; k < GAMMA_LUT_N; k += BLK_THREADS) s_lut[k] = g_glut[k];
     for (int k = threadIdx.x; k < 257; k += BLK_THREADS) s_thr[k] = g_thr[k];
@@ -481,7 +510,7 @@ __global__ __launch_bounds__(BLK_THREADS) void k_tmo_base(const ImgDesc *__restr
 
 // ---------------------------------------------------------------------------
 // GF streaming, shared by the fit, residual and decode kernels.  A wave owns a
-// strip of STRIP_W = 256 px (four consecutive pixels per lane) and STRIP_RH
+// strip of STRIP_W = 256 px (four consecutive pixels per lane) and srh
 // rows.  It walks down its rows holding S of rows y-1, y, y+1 in registers and
 // takes the horizontal neighbours of its four pixels from the adjacent lanes
 // (DPP wave shifts) or, at the strip ends, from one halo pixel per lane (lane
@@ -501,7 +530,7 @@ __device__ __forceinline__ void load_quad(const uint8_t *__restrict__ sdr, uintp
     const uint8_t *a = sdr + 3 * ((int64_t)y * W + x);
     const uintptr_t al = reinterpret_cast<uintptr_t>(a) & ~(uintptr_t)3;
     if (x + 4 <= W && al + 16 <= end) {
-        const uint32_t *q = reinterpret_cast<const uint32_t *>(al);
+        const uint32_t *q = reinterpret_cast<const uint32_t *>(a - (reinterpret_cast<uintptr_t>(a) & 3));
         const uint32_t sh = (uint32_t)(reinterpret_cast<uintptr_t>(a) & 3);
         const uint32_t d0 = q[0], d1 = q[1], d2 = q[2], d3 = q[3];
         const uint32_t e0 = __builtin_amdgcn_alignbyte(d1, d0, sh);
@@ -519,7 +548,7 @@ __device__ __forceinline__ void load_quad(const uint8_t *__restrict__ sdr, uintp
 
 // RGBE words of pixels x .. x+3 of row y (x >= W repeats W-1).
 __device__ __forceinline__ void load_rgbe4(const uint8_t *__restrict__ rgbe, int W, int y, int x, uint32_t w[4]) {
-    const uint32_t *row = reinterpret_cast<const uint32_t *>(rgbe) + (int64_t)y * W;
+    const uint32_t *row = reinterpret_cast<const uint32_t *>(rgbe + (int64_t)y * (4 * (int64_t)W));
     if (x + 4 <= W && (reinterpret_cast<uintptr_t>(row + x) & 15) == 0) {
         const uint4 v = *reinterpret_cast<const uint4 *>(row + x);
         w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
@@ -566,8 +595,15 @@ __device__ __forceinline__ void gf_roll(GfWindow &g) {
     g.hhi[0] = g.hhi[1]; g.hhi[1] = g.hhi[2];
 }
 
+// The R | B << 16 words are filtered as two 16-bit lanes (packed 16-bit
+// multiply-adds); G words hold one field below 2^16.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ u16x2 as16(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
+__device__ __forceinline__ uint32_t as32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+__device__ __forceinline__ uint32_t vsum2(uint32_t a, uint32_t b, uint32_t c) {
+    return as32(as16(a) + as16(c) + as16(b) * (u16x2)(6));
+}
 __device__ __forceinline__ uint32_t vsum(uint32_t a, uint32_t b, uint32_t c) { return a + c + __umul24(b, 6u); }
-__device__ __forceinline__ uint32_t hsum(uint32_t l, uint32_t m, uint32_t r) { return l + r + (m << 2) + (m << 1); }
 
 // S* of the lane's four pixels for the middle row: s[c][j], c = R, G, B.
 // Must be called by the whole wave (DPP).
@@ -575,10 +611,10 @@ __device__ __forceinline__ void gf_quad(const GfWindow &g, int lane, int s[3][4]
     uint32_t vlo[4], vhi[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        vlo[j] = vsum(g.lo[0][j], g.lo[1][j], g.lo[2][j]);
+        vlo[j] = vsum2(g.lo[0][j], g.lo[1][j], g.lo[2][j]);
         vhi[j] = vsum(g.hi[0][j], g.hi[1][j], g.hi[2][j]);
     }
-    const uint32_t hvlo = vsum(g.hlo[0], g.hlo[1], g.hlo[2]), hvhi = vsum(g.hhi[0], g.hhi[1], g.hhi[2]);
+    const uint32_t hvlo = vsum2(g.hlo[0], g.hlo[1], g.hlo[2]), hvhi = vsum(g.hhi[0], g.hhi[1], g.hhi[2]);
     uint32_t llo = dpp_from_left(vlo[3]), lhi = dpp_from_left(vhi[3]);
     uint32_t rlo = dpp_from_right(vlo[0]), rhi = dpp_from_right(vhi[0]);
     if (lane == 0) { llo = hvlo; lhi = hvhi; }
@@ -587,19 +623,22 @@ __device__ __forceinline__ void gf_quad(const GfWindow &g, int lane, int s[3][4]
     for (int j = 0; j < 4; ++j) {
         const uint32_t Llo = j == 0 ? llo : vlo[j - 1], Lhi = j == 0 ? lhi : vhi[j - 1];
         const uint32_t Rlo = j == 3 ? rlo : vlo[j + 1], Rhi = j == 3 ? rhi : vhi[j + 1];
-        const uint32_t tlo = hsum(Llo, vlo[j], Rlo) + 0x00200020u;  // + 32 in each field
-        const uint32_t thi = hsum(Lhi, vhi[j], Rhi) + 32u;
-        s[0][j] = (int)((tlo >> 6) & 255u);
-        s[2][j] = (int)((tlo >> 22) & 255u);
-        s[1][j] = (int)(thi >> 6);
+        const uint32_t tlo = as32((as16(Llo) + as16(Rlo) + as16(vlo[j]) * (u16x2)(6) + (u16x2)(32)) >> (u16x2)(6));
+        const uint32_t thi = Lhi + Rhi + __umul24(vhi[j], 6u) + 32u;
+        // Each field is at most (64 * 255 + 32) >> 6 = 255; the masks say so.
+        s[0][j] = (int)(tlo & 255u);
+        s[2][j] = (int)((tlo >> 16) & 255u);
+        s[1][j] = (int)((thi >> 6) & 255u);
     }
 }
 
 // The strip of a workgroup and the rows of its wave.
 struct StripPos {
     int lane, x, hx, ya, yb;
+    uint32_t xo3, ho3, xo4;  // byte offsets in a row of S (3x, 3hx) and of RGBE (4x)
+    bool fx;                 // x + 4 <= W: the lane's four pixels are all inside
 };
-__device__ __forceinline__ StripPos strip_pos(int wgl, int H, int W) {
+__device__ __forceinline__ StripPos strip_pos(int wgl, int H, int W, int srh) {
     StripPos p;
     const int nsx = (W + STRIP_W - 1) / STRIP_W;
     const int sy = wgl / nsx, sx = wgl - sy * nsx;
@@ -607,9 +646,143 @@ __device__ __forceinline__ StripPos strip_pos(int wgl, int H, int W) {
     const int x0 = sx * STRIP_W;
     p.x = x0 + 4 * p.lane;
     p.hx = p.lane == 0 ? max(x0 - 1, 0) : min(x0 + STRIP_W, W - 1);
-    p.ya = sy * STRIP_H + (threadIdx.x >> 6) * STRIP_RH;
-    p.yb = min(p.ya + STRIP_RH, H);
+    // Row bounds are the same for every lane of a wave; saying so lets the
+    // row addresses live in scalar registers.
+    p.ya = uniform((sy * STRIP_WAVES + (threadIdx.x >> 6)) * srh);
+    p.yb = uniform(min(p.ya + srh, H));
+    // W <= 2^28, so these fit 32 bits.
+    p.xo3 = 3u * (uint32_t)p.x;
+    p.ho3 = 3u * (uint32_t)p.hx;
+    p.xo4 = 4u * (uint32_t)p.x;
+    p.fx = p.x + 4 <= W;
     return p;
+}
+
+// Chunked walk: the loads of the next CH rows (S row y+1 for the window and
+// the RGBE words of row y) are all issued before the first of them is used, so
+// a wave waits for memory once per CH rows instead of once per row.  A raw
+// S row is kept uncombined until it enters the window: the 16 bytes from the
+// dword boundary at or below the lane's first byte (sh = that byte's offset),
+// or, where that read would pass the row's last pixel or the buffer's end,
+// the four pixels read one by one (sh = 4); the halo pixel as three bytes.
+struct RowRaw {
+    uint32_t d[4];
+    uint32_t h[3];
+    uint32_t sh;
+};
+
+// Row yy (already clamped to the image) of S.  fast: the lane may read 16
+// bytes from the dword boundary at or below its first byte.
+__device__ __forceinline__ void gf_row_issue(RowRaw &r, const uint8_t *__restrict__ sdr, int W, int yy, bool fast,
+                                             const StripPos &sp) {
+    const uint8_t *row = sdr + (int64_t)uniform(yy) * (3 * (int64_t)W);
+    const uint32_t sh = (uint32_t)(reinterpret_cast<uintptr_t>(row) + sp.xo3) & 3u;
+    if (fast) {
+        // The lane's first byte, minus its offset from the dword boundary
+        // below it (S starts on a dword boundary, so this stays inside).
+        const uint32_t *q = reinterpret_cast<const uint32_t *>((row + sp.xo3) - sh);
+        r.d[0] = q[0];
+        r.d[1] = q[1];
+        r.d[2] = q[2];
+        r.d[3] = q[3];
+        r.sh = sh;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) r.d[j] = load_px3(row + 3u * (uint32_t)min(sp.x + j, W - 1));
+        r.sh = 4;
+    }
+    const uint8_t *hp = row + sp.ho3;
+    r.h[0] = hp[0];
+    r.h[1] = hp[1];
+    r.h[2] = hp[2];
+}
+
+// RGBE words of the lane's four pixels of row yy (pixels past W repeat W-1).
+__device__ __forceinline__ void strip_rgbe4(const uint8_t *__restrict__ rgbe, int W, int yy, const StripPos &sp,
+                                            uint32_t w[4]) {
+    const uint8_t *row = rgbe + (int64_t)uniform(yy) * (4 * (int64_t)W);
+    const uint8_t *p = row + sp.xo4;
+    if (sp.fx && (((uint32_t)reinterpret_cast<uintptr_t>(p) & 15u) == 0)) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(p);
+        w[0] = v.x;
+        w[1] = v.y;
+        w[2] = v.z;
+        w[3] = v.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) w[j] = *reinterpret_cast<const uint32_t *>(row + 4u * (uint32_t)min(sp.x + j, W - 1));
+    }
+}
+
+__device__ __forceinline__ void gf_row_finish(GfWindow &g, int slot, const RowRaw &r) {
+    uint32_t p[4];
+    if (r.sh < 4) {
+        const uint32_t e0 = __builtin_amdgcn_alignbyte(r.d[1], r.d[0], r.sh);
+        const uint32_t e1 = __builtin_amdgcn_alignbyte(r.d[2], r.d[1], r.sh);
+        const uint32_t e2 = __builtin_amdgcn_alignbyte(r.d[3], r.d[2], r.sh);
+        p[0] = e0;
+        p[1] = __builtin_amdgcn_alignbyte(e1, e0, 3);
+        p[2] = __builtin_amdgcn_alignbyte(e2, e1, 2);
+        p[3] = e2 >> 8;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) p[j] = r.d[j];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        g.lo[slot][j] = p[j] & 0x00FF00FFu;
+        g.hi[slot][j] = (p[j] >> 8) & 0xFFu;
+    }
+    const uint32_t h = r.h[0] | (r.h[1] << 8) | (r.h[2] << 16);
+    g.hlo[slot] = h & 0x00FF00FFu;
+    g.hhi[slot] = (h >> 8) & 0xFFu;
+}
+
+// Calls row(y, s, w) for y = ya .. yb-1 in order, with s[c][j] = S*_c of the
+// lane's pixels x+j of row y and w[j] their RGBE words.  The whole wave must
+// call it (DPP); ya < yb is uniform per wave.
+constexpr int WALK_CH = 4;
+template <class RowFn>
+__device__ __forceinline__ void strip_walk(const ImgDesc &d, const StripPos &sp, RowFn &&row) {
+    const int H = d.H, W = d.W;
+    // The 16-byte read stays inside S on every row but the last (there the
+    // lane's bytes are followed by a whole row); on the last row it must end
+    // by the buffer's end.
+    const uint8_t *last = d.sdr + (int64_t)(H - 1) * (3 * (int64_t)W);
+    const uint32_t shl = (uint32_t)(reinterpret_cast<uintptr_t>(last) + sp.xo3) & 3u;
+    const bool fast_last = sp.fx && (uint64_t)sp.xo3 - shl + 16u <= 3ull * (uint64_t)W;
+    auto fast = [&](int yy) { return yy < H - 1 ? sp.fx : fast_last; };
+    GfWindow g;
+    {
+        RowRaw r0, r1;
+        const int y0 = max(sp.ya - 1, 0), y1 = sp.ya;
+        gf_row_issue(r0, d.sdr, W, y0, fast(y0), sp);
+        gf_row_issue(r1, d.sdr, W, y1, fast(y1), sp);
+        gf_row_finish(g, 0, r0);
+        gf_row_finish(g, 1, r1);
+    }
+    for (int y0 = sp.ya; y0 < sp.yb; y0 += WALK_CH) {
+        RowRaw nr[WALK_CH];
+        uint32_t w[WALK_CH][4];
+#pragma unroll
+        for (int k = 0; k < WALK_CH; ++k) {
+            // Rows past the strip repeat its last needed row (cache hits, unused).
+            const int ys = min(min(y0 + k + 1, sp.yb), H - 1);
+            gf_row_issue(nr[k], d.sdr, W, ys, fast(ys), sp);
+            strip_rgbe4(d.rgbe, W, min(y0 + k, sp.yb - 1), sp, w[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < WALK_CH; ++k) {
+            const int y = y0 + k;
+            if (y < sp.yb) {  // uniform per wave
+                gf_row_finish(g, 2, nr[k]);
+                int sv[3][4];
+                gf_quad(g, sp.lane, sv);
+                gf_roll(g);
+                row(y, sv, w[k]);
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -617,12 +790,19 @@ __device__ __forceinline__ StripPos strip_pos(int wgl, int H, int W) {
 // image (Eq. 9-10), s = S*_c, m = M_c.  Each lane keeps one register
 // accumulator for its current exponent run and, when E changes, adds it to
 // the workgroup's LDS bins (32-bit totals, added in pairs with 64-bit LDS
-// atomics; a workgroup covers 16384 px, so no total reaches 2^32).  At the
+// atomics; a workgroup covers at most 256 x 4 x 32 = 32768 px and
+// 65025 x 32768 < 2^32, so no total wraps).  At the
 // end the workgroup adds its present bins into one of the image's int64
 // stripes with integer atomics.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void flush_run(uint32_t (*bins)[14], int e, uint32_t acc[NSUM]) {
-    unsigned long long *b = reinterpret_cast<unsigned long long *>(&bins[e][0]);
+// The bins are privatised R ways: lane l adds into copy l % R, so lanes of a
+// wave that end runs of the same exponent at the same instant (neighbours in a
+// smooth region do) hit R different addresses instead of one; the copies are
+// skewed by 16 banks.  R is a tuned launch shape.
+constexpr int BIN_WORDS = 256 * 14 + 16;
+
+__device__ __forceinline__ void flush_run(uint32_t *bins, int e, uint32_t acc[NSUM]) {
+    unsigned long long *b = reinterpret_cast<unsigned long long *>(bins + e * 14);
 #pragma unroll
     for (int k = 0; k < 7; ++k) {
         const uint32_t lo = acc[2 * k], hi = 2 * k + 1 < NSUM ? acc[2 * k + 1] : 0u;
@@ -632,36 +812,29 @@ __device__ __forceinline__ void flush_run(uint32_t (*bins)[14], int e, uint32_t 
     for (int k = 0; k < NSUM; ++k) acc[k] = 0;
 }
 
+template <int R>
 __global__ __launch_bounds__(STRIP_THREADS) void k_fit_sums(const ImgDesc *__restrict__ D, int n) {
-    __shared__ __align__(8) uint32_t bins[256][14];
+    __shared__ __align__(8) uint32_t bins[R * BIN_WORDS];
     const int i = find_img(D, n, blockIdx.x, 3);
-    const ImgDesc &d = D[i];
+    const ImgDesc d = desc_at(D, i);
     const int H = d.H, W = d.W;
     const int wgl = blockIdx.x - d.wg_fit;
-    for (int k = threadIdx.x; k < 256 * 14; k += STRIP_THREADS) (&bins[0][0])[k] = 0;
+    for (int k = threadIdx.x; k < R * BIN_WORDS; k += STRIP_THREADS) bins[k] = 0;
     __syncthreads();
-    const StripPos sp = strip_pos(wgl, H, W);
-    const uintptr_t end = reinterpret_cast<uintptr_t>(d.sdr) + 3 * (uintptr_t)H * W;
+    const StripPos sp = strip_pos(wgl, H, W, d.srh_fit);
     if (sp.ya < H) {  // uniform per wave
-        GfWindow g;
-        gf_load_row(g, 0, d.sdr, end, H, W, sp.ya - 1, sp.x, sp.hx);
-        gf_load_row(g, 1, d.sdr, end, H, W, sp.ya, sp.x, sp.hx);
+        uint32_t *mine = bins + (sp.lane % R) * BIN_WORDS;
         int cur = -1;
         uint32_t acc[NSUM];
 #pragma unroll
         for (int k = 0; k < NSUM; ++k) acc[k] = 0;
-        for (int y = sp.ya; y < sp.yb; ++y) {
-            gf_load_row(g, 2, d.sdr, end, H, W, y + 1, sp.x, sp.hx);
-            int s[3][4];
-            gf_quad(g, sp.lane, s);
-            uint32_t w[4];
-            load_rgbe4(d.rgbe, W, y, sp.x, w);
+        strip_walk(d, sp, [&](int, const int (&s)[3][4], const uint32_t (&w)[4]) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 if (sp.x + j < W) {
                     const int e = (int)(w[j] >> 24);
                     if (e != cur) {
-                        if (cur >= 0) flush_run(bins, cur, acc);
+                        if (cur >= 0) flush_run(mine, cur, acc);
                         cur = e;
                     }
                     acc[0] += 1;
@@ -675,17 +848,25 @@ __global__ __launch_bounds__(STRIP_THREADS) void k_fit_sums(const ImgDesc *__res
                     }
                 }
             }
-            gf_roll(g);
-        }
-        if (cur >= 0) flush_run(bins, cur, acc);
+        });
+        if (cur >= 0) flush_run(mine, cur, acc);
     }
     __syncthreads();
+    // Each copy's totals stay below 2^32 (see above); their sum is taken in
+    // 64 bits.
     unsigned long long *gp = (unsigned long long *)(d.part + (int64_t)(wgl % d.nfs) * 256 * NSUM);
     for (int e = threadIdx.x; e < 256; e += STRIP_THREADS) {
-        if (bins[e][0] == 0) continue;
+        uint64_t cnt = 0;
 #pragma unroll
-        for (int k = 0; k < NSUM; ++k)
-            if (bins[e][k]) atomicAdd(gp + e * NSUM + k, (unsigned long long)bins[e][k]);
+        for (int r = 0; r < R; ++r) cnt += bins[r * BIN_WORDS + e * 14];
+        if (cnt == 0) continue;
+#pragma unroll
+        for (int k = 0; k < NSUM; ++k) {
+            uint64_t v = 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v += bins[r * BIN_WORDS + e * 14 + k];
+            if (v) atomicAdd(gp + e * NSUM + k, (unsigned long long)v);
+        }
     }
 }
 // ---------------------------------------------------------------------------
@@ -721,7 +902,7 @@ __global__ __launch_bounds__(1024) void k_solve(const ImgDesc *__restrict__ D, i
     __shared__ int64_t s_b[3][256][NSUM];
     __shared__ int s_cnt[4];
     const int i = blockIdx.x;
-    const ImgDesc &d = D[i];
+    const ImgDesc d = desc_at(D, i);
     rdl_header *h = d.hdr;
     const int e = threadIdx.x & 255, g = threadIdx.x >> 8;
     // Add up the stripes (lane group g takes stripes g, g+4, ...) and leave
@@ -801,44 +982,58 @@ __global__ __launch_bounds__(1024) void k_solve(const ImgDesc *__restrict__ D, i
 // (Eq. 8), written as int16 planes, plus the exponent plane.  Same strip walk
 // as the fit, with the image's coefficients in LDS.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int mstar(int32_t aq, int32_t bq, int s) {
-    const int64_t v = ((int64_t)aq * s + (int64_t)bq * 256 + (1 << 21)) >> 22;
-    return (int)min(max(v, (int64_t)0), (int64_t)255);
+// Bounds of valid coefficients: |a| <= 255 (a weighted mean of pairwise slopes
+// (m_i - m_j)/(s_i - s_j), |s_i - s_j| >= 1), and b = mean m - a mean s, so
+// -65025 <= b <= 65280; both scaled by their fixed-point units.
+constexpr int32_t AQ_MAX = 255 << 22;
+constexpr int32_t BQ_MIN = -65025 * 16384, BQ_MAX = 65280 * 16384;
+__device__ __forceinline__ bool coef_ok(int32_t aq, int32_t bq) {
+    return aq >= -AQ_MAX && aq <= AQ_MAX && bq >= BQ_MIN && bq <= BQ_MAX;
+}
+
+// A region's coefficients prepared for M* in 32-bit arithmetic: with
+// a_q = 2^8 ah + al (0 <= al < 2^8), x holds ah in its low 24 bits (signed)
+// and al in its top 8, y = b_q + 2^13.
+__device__ __forceinline__ int2 coef_prep(int32_t aq, int32_t bq) {
+    const uint32_t ah = (uint32_t)(aq >> 8) & 0xFFFFFFu, al = (uint32_t)aq & 255u;
+    return make_int2((int)(ah | (al << 24)), bq + 8192);
+}
+
+// M* = clamp(floor((a_q s + 2^8 b_q + 2^21) / 2^22), 0, 255).  The numerator
+// is 2^8 V + u with V = ah s + b_q + 2^13 and 0 <= u = al s < 2^16, so the
+// quotient is floor((V + floor(u / 2^8)) / 2^14); for coefficients within
+// the bounds above |V| < 2^31, so the 32-bit result is exact.
+__device__ __forceinline__ int mstar(int2 k, int s) {
+    const int v = __mul24(k.x, s) + k.y;
+    const int u = (int)((((uint32_t)k.x >> 24) * (uint32_t)s) >> 8);
+    return min(max((v + u) >> 14, 0), 255);
 }
 
 __global__ __launch_bounds__(STRIP_THREADS) void k_resid(const ImgDesc *__restrict__ D, int n) {
     __shared__ int2 s_ab[3][256];
     __shared__ uint8_t s_fl[3][256];
     const int i = find_img(D, n, blockIdx.x, 4);
-    const ImgDesc &d = D[i];
+    const ImgDesc d = desc_at(D, i);
     const int H = d.H, W = d.W;
     const int wgl = blockIdx.x - d.wg_res;
     const rdl_header *h = d.hdr;
     const bool learned = d.ml != nullptr;
     for (int k = threadIdx.x; k < 3 * 256; k += STRIP_THREADS) {
         const int c = k >> 8, e = k & 255;
-        s_ab[c][e] = make_int2(h->a_q[c][e], h->b_q[c][e]);
+        s_ab[c][e] = coef_prep(h->a_q[c][e], h->b_q[c][e]);
         s_fl[c][e] = learned ? h->flag[c][e] : 0;
     }
     __syncthreads();
-    const StripPos sp = strip_pos(wgl, H, W);
+    const StripPos sp = strip_pos(wgl, H, W, d.srh_res);
     if (sp.ya >= H) return;  // uniform per wave; no barrier follows
-    const uintptr_t end = reinterpret_cast<uintptr_t>(d.sdr) + 3 * (uintptr_t)H * W;
     const int64_t npx = (int64_t)H * W;
     int16_t *r = (int16_t *)d.resid;
     uint8_t *Ep = d.resid + 6 * npx;
     const bool al = (W & 3) == 0 && ((reinterpret_cast<uintptr_t>(d.resid) & 7) == 0);
-    GfWindow g;
-    gf_load_row(g, 0, d.sdr, end, H, W, sp.ya - 1, sp.x, sp.hx);
-    gf_load_row(g, 1, d.sdr, end, H, W, sp.ya, sp.x, sp.hx);
-    for (int y = sp.ya; y < sp.yb; ++y) {
-        gf_load_row(g, 2, d.sdr, end, H, W, y + 1, sp.x, sp.hx);
-        int s[3][4];
-        gf_quad(g, sp.lane, s);
-        gf_roll(g);
-        if (sp.x >= W) continue;
-        uint32_t w[4];
-        load_rgbe4(d.rgbe, W, y, sp.x, w);
+    strip_walk(d, sp, [&](int y, const int (&s)[3][4], const uint32_t (&w)[4]) {
+        if (sp.x >= W) return;
+        const int64_t ro = (int64_t)uniform(y) * W;  // row bases are scalar
+        const uint8_t *mlr = learned ? d.ml + 3 * ro : nullptr;
         int rv[3][4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -846,31 +1041,32 @@ __global__ __launch_bounds__(STRIP_THREADS) void k_resid(const ImgDesc *__restri
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const int2 ab = s_ab[c][e];
-                int est = mstar(ab.x, ab.y, s[c][j]);
-                if (learned && s_fl[c][e] && sp.x + j < W) est = d.ml[3 * ((int64_t)y * W + sp.x + j) + c];
+                int est = mstar(ab, s[c][j]);
+                if (learned && s_fl[c][e] && sp.x + j < W) est = mlr[sp.xo3 + 3u * j + c];
                 rv[c][j] = (int)((w[j] >> (8 * c)) & 255u) - est;
             }
         }
-        const int64_t o = (int64_t)y * W + sp.x;
+        int16_t *rr = r + ro;
+        uint8_t *er = Ep + ro;
         if (al && sp.x + 4 <= W) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 uint2 v;
                 v.x = (uint32_t)pack_i16(rv[c][0], rv[c][1]);
                 v.y = (uint32_t)pack_i16(rv[c][2], rv[c][3]);
-                *reinterpret_cast<uint2 *>(r + c * npx + o) = v;
+                *reinterpret_cast<uint2 *>(rr + c * npx + (uint32_t)sp.x) = v;
             }
-            *reinterpret_cast<uint32_t *>(Ep + o) =
+            *reinterpret_cast<uint32_t *>(er + (uint32_t)sp.x) =
                 (w[0] >> 24) | ((w[1] >> 24) << 8) | ((w[2] >> 24) << 16) | ((w[3] >> 24) << 24);
         } else {
             const int nx = min(4, W - sp.x);
             for (int j = 0; j < nx; ++j) {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) r[c * npx + o + j] = (int16_t)rv[c][j];
-                Ep[o + j] = (uint8_t)(w[j] >> 24);
+                for (int c = 0; c < 3; ++c) rr[c * npx + sp.x + j] = (int16_t)rv[c][j];
+                er[sp.x + j] = (uint8_t)(w[j] >> 24);
             }
         }
-    }
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -880,7 +1076,7 @@ __global__ __launch_bounds__(STRIP_THREADS) void k_resid(const ImgDesc *__restri
 __global__ __launch_bounds__(STRIP_THREADS) void k_decode(const ImgDesc *__restrict__ D, int n) {
     __shared__ int2 s_ab[3][256];
     const int i = find_img(D, n, blockIdx.x, 4);
-    const ImgDesc &d = D[i];
+    const ImgDesc d = desc_at(D, i);
     const int H = d.H, W = d.W;
     const rdl_header *h = d.hdr;
     const bool ok = h->magic == RDL_MAGIC && h->version == RDL_VERSION && h->H == H && h->W == W;
@@ -889,12 +1085,21 @@ __global__ __launch_bounds__(STRIP_THREADS) void k_decode(const ImgDesc *__restr
         return;
     }
     if (h->estimator != 0) return;  // decoded by k_decode_learned
+    __shared__ int s_bad;
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
     for (int k = threadIdx.x; k < 3 * 256; k += STRIP_THREADS) {
         const int c = k >> 8, e = k & 255;
-        s_ab[c][e] = make_int2(h->a_q[c][e], h->b_q[c][e]);
+        const int32_t aq = h->a_q[c][e], bq = h->b_q[c][e];
+        if (!coef_ok(aq, bq)) s_bad = 1;
+        s_ab[c][e] = coef_prep(aq, bq);
     }
     __syncthreads();
-    const StripPos sp = strip_pos(blockIdx.x - d.wg_res, H, W);
+    if (s_bad) {  // uniform
+        if (threadIdx.x == 0 && d.status) atomicExch(d.status, RDL_ECORRUPT);
+        return;
+    }
+    const StripPos sp = strip_pos(blockIdx.x - d.wg_res, H, W, d.srh_res);
     if (sp.ya >= H) return;
     const uintptr_t end = reinterpret_cast<uintptr_t>(d.sdr) + 3 * (uintptr_t)H * W;
     const int64_t npx = (int64_t)H * W;
@@ -919,7 +1124,7 @@ __global__ __launch_bounds__(STRIP_THREADS) void k_decode(const ImgDesc *__restr
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const int2 ab = s_ab[c][e];
-                const int m = mstar(ab.x, ab.y, s[c][j]) + r[c * npx + o + j];
+                const int m = mstar(ab, s[c][j]) + r[c * npx + o + j];
                 bad |= (m < 0) | (m > 255);
                 word |= (uint32_t)(m & 255) << (8 * c);
             }
@@ -1104,13 +1309,13 @@ __global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, in
     __shared__ uint32_t hb[3][HB_SLOTS][HB_BINS];
     __shared__ int s_ebase;
     const int i = find_img(D, n, blockIdx.x, 5);
-    const ImgDesc &d = D[i];
+    const ImgDesc d = desc_at(D, i);
     const int H = d.H, W = d.W;
     const rdl_header *h = d.hdr;
     const int wgl = blockIdx.x - d.wg_learn;
     const int ntx = (W + LT_W - 1) / LT_W;
     const int ty0w = (wgl / ntx) * (LT_H * LT_TILES), tx0 = (wgl % ntx) * LT_W;
-    for (int k = threadIdx.x; k < 3 * 256; k += 256) s_ab[k >> 8][k & 255] = make_int2(h->a_q[k >> 8][k & 255], h->b_q[k >> 8][k & 255]);
+    for (int k = threadIdx.x; k < 3 * 256; k += 256) s_ab[k >> 8][k & 255] = coef_prep(h->a_q[k >> 8][k & 255], h->b_q[k >> 8][k & 255]);
     for (int k = threadIdx.x; k < 1024; k += 256) (&B1[0][0])[k] = reinterpret_cast<const int32_t *>(d.model + MB_B1)[k];
     for (int k = threadIdx.x; k < 3 * HB_SLOTS * HB_BINS; k += 256) (&hb[0][0][0])[k] = 0;
     if (threadIdx.x == 0) {
@@ -1156,7 +1361,7 @@ __global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, in
                 const int mlc = (int)((ml >> (8 * c)) & 255u);
                 d.ml[3 * o + c] = (uint8_t)mlc;
                 const int2 ab = s_ab[c][e];
-                const int rs = m - mstar(ab.x, ab.y, s[c]), rl = m - mlc;
+                const int rs = m - mstar(ab, s[c]), rl = m - mlc;
                 if (slot >= 0 && slot < HB_SLOTS && rs >= -64 && rs < 64) atomicAdd(&hb[c][slot][rs + 64], 1u);
                 else atomicAdd(&hist[((0 * 3 + c) * 256 + e) * 511 + rs + 255], 1u);
                 if (slot >= 0 && slot < HB_SLOTS && rl >= -64 && rl < 64) atomicAdd(&hb[c][slot][rl + 64], 1u << 16);
@@ -1192,7 +1397,7 @@ __global__ __launch_bounds__(256) void k_select(const ImgDesc *__restrict__ D, i
     __shared__ uint32_t s_cnt[2][511];
     const int i = blockIdx.x >> 8, e = blockIdx.x & 255;
     if (i >= n) return;
-    const ImgDesc &d = D[i];
+    const ImgDesc d = desc_at(D, i);
     rdl_header *h = d.hdr;
     if (e == 0 && threadIdx.x == 0) {
         h->estimator = 1;
@@ -1249,7 +1454,7 @@ __global__ __launch_bounds__(256) void k_decode_learned(const ImgDesc *__restric
     __shared__ int32_t B1[32][32];
     __shared__ MlpWaveLds wl[4];
     const int i = find_img(D, n, blockIdx.x, 5);
-    const ImgDesc &d = D[i];
+    const ImgDesc d = desc_at(D, i);
     const int H = d.H, W = d.W;
     const rdl_header *h = d.hdr;
     if (h->estimator != 1) return;  // uniform: plain headers are decoded by k_decode
@@ -1262,11 +1467,21 @@ __global__ __launch_bounds__(256) void k_decode_learned(const ImgDesc *__restric
     const int wgl = blockIdx.x - d.wg_learn;
     const int ntx = (W + LT_W - 1) / LT_W;
     const int ty0w = (wgl / ntx) * (LT_H * LT_TILES), tx0 = (wgl % ntx) * LT_W;
+    __shared__ int s_bad;
+    if (threadIdx.x == 0) s_bad = 0;
+    __syncthreads();
     for (int k = threadIdx.x; k < 3 * 256; k += 256) {
-        s_ab[k >> 8][k & 255] = make_int2(h->a_q[k >> 8][k & 255], h->b_q[k >> 8][k & 255]);
+        const int32_t aq = h->a_q[k >> 8][k & 255], bq = h->b_q[k >> 8][k & 255];
+        if (!coef_ok(aq, bq)) s_bad = 1;
+        s_ab[k >> 8][k & 255] = coef_prep(aq, bq);
         s_fl[k >> 8][k & 255] = h->flag[k >> 8][k & 255];
     }
     for (int k = threadIdx.x; k < 1024; k += 256) (&B1[0][0])[k] = reinterpret_cast<const int32_t *>(d.model + MB_B1)[k];
+    __syncthreads();
+    if (s_bad) {  // uniform
+        if (threadIdx.x == 0 && d.status) atomicExch(d.status, RDL_ECORRUPT);
+        return;
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     MlpLane L;
     mlp_lane_load(L, d.model, lane);
@@ -1303,7 +1518,7 @@ __global__ __launch_bounds__(256) void k_decode_learned(const ImgDesc *__restric
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const int2 ab = s_ab[c][e];
-                const int est = s_fl[c][e] ? (int)((ml >> (8 * c)) & 255u) : mstar(ab.x, ab.y, s[c]);
+                const int est = s_fl[c][e] ? (int)((ml >> (8 * c)) & 255u) : mstar(ab, s[c]);
                 const int m = est + r[c * npx + o];
                 bad |= (m < 0) | (m > 255);
                 word |= (uint32_t)(m & 255) << (8 * c);
@@ -1320,7 +1535,7 @@ __global__ __launch_bounds__(256) void k_decode_learned(const ImgDesc *__restric
 __global__ __launch_bounds__(TILE_THREADS) void k_hist(const ImgDesc *__restrict__ D, int n) {
     __shared__ uint32_t hb[3][511];
     const int i = find_img(D, n, blockIdx.x, 2);
-    const ImgDesc &d = D[i];
+    const ImgDesc d = desc_at(D, i);
     const int H = d.H, W = d.W;
     for (int k = threadIdx.x; k < 3 * 511; k += TILE_THREADS) (&hb[0][0])[k] = 0;
     __syncthreads();
@@ -1396,8 +1611,13 @@ void launch_tmo_base(const ImgDesc *d, int n, int wgs, bool extra, hipStream_t s
     else
         hipLaunchKernelGGL(k_tmo_base<false>, dim3(wgs), dim3(BLK_THREADS), 0, s, d, n);
 }
-void launch_fit_sums(const ImgDesc *d, int n, int wgs, hipStream_t s) {
-    hipLaunchKernelGGL(k_fit_sums, dim3(wgs), dim3(STRIP_THREADS), 0, s, d, n);
+void launch_fit_sums(const ImgDesc *d, int n, int wgs, int bins, hipStream_t s) {
+    if (bins >= 4)
+        hipLaunchKernelGGL(k_fit_sums<4>, dim3(wgs), dim3(STRIP_THREADS), 0, s, d, n);
+    else if (bins == 2)
+        hipLaunchKernelGGL(k_fit_sums<2>, dim3(wgs), dim3(STRIP_THREADS), 0, s, d, n);
+    else
+        hipLaunchKernelGGL(k_fit_sums<1>, dim3(wgs), dim3(STRIP_THREADS), 0, s, d, n);
 }
 void launch_solve(const ImgDesc *d, int n, hipStream_t s) { hipLaunchKernelGGL(k_solve, dim3(n), dim3(1024), 0, s, d, n); }
 void launch_key_total(const ImgDesc *d, int n, int64_t *out2, hipStream_t s) {

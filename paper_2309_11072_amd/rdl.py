@@ -8,6 +8,7 @@ there is no CPU fallback.
 from __future__ import annotations
 
 import ctypes as C
+import json
 import os
 
 import numpy as np
@@ -46,6 +47,9 @@ _SIGS = {
     "rdl_stage_fit": ([_vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp], _i),
     "rdl_stage_resid": ([_vp, _vp, _vp, _vp, _i, _i, _vp, _vp], _i),
     "rdl_profile_encode": ([_vp, _vp, _i, _i, _i, _vp, _vp, _vp, _i, _vp, _vp], _i),
+    "rdl_autotune": ([_vp, _vp, _i, _i, _i, _vp, _vp, _vp, _i, _vp, _vp], _i),
+    "rdl_get_tuning": ([_vp, _i, _i, _vp], _i),
+    "rdl_set_tuning": ([_vp, _i, _i, _i], _i),
     "rdl_set_model": ([_vp, _vp, C.c_size_t], _i),
     "rdl_set_estimator": ([_vp, _i], _i),
     "rdl_train_sample_bytes": ([], _i),
@@ -54,6 +58,7 @@ _SIGS = {
     "rdl_train_step": ([_vp, _vp, _vp, _vp, _vp, C.c_int64, C.c_int64, _i, C.c_float, _i, _vp, _vp], _i),
 }
 
+TUNE = ("fit_rows", "resid_rows", "fit_bins")
 STAGES = ("keystat", "tmo_base", "fit_sums", "solve", "resid")
 KERNELS = ("k_keystat", "k_tmo_base", "k_fit_sums", "k_solve", "k_resid")
 
@@ -222,6 +227,41 @@ class Codec:
         return dict(zip(STAGES, [float(v) for v in ms]))
 
     # -------------------------------------------------------------- stages
+    def autotune(self, rgbe: torch.Tensor, q: int, out, reps: int = 10, stream=None) -> dict:
+        """Times the fit and the residual kernels on this image with each
+        strip height, keeps the fastest for its size class, returns them."""
+        H, W = int(rgbe.shape[0]), int(rgbe.shape[1])
+        sdr, hdr, resid = out
+        best = (C.c_int * len(TUNE))()
+        _chk(self._L.rdl_autotune(self._h, _ptr(rgbe), H, W, int(q), _ptr(sdr), _ptr(hdr), _ptr(resid), int(reps),
+                                  best, _stream(stream)), "rdl_autotune")
+        return dict(zip(TUNE, [int(v) for v in best]))
+
+    def get_tuning(self) -> dict:
+        """{parameter: [value of size class floor(log2(H W)) for 0..31]}."""
+        out = {}
+        v = C.c_int(0)
+        for p, name in enumerate(TUNE):
+            row = []
+            for k in range(32):
+                _chk(self._L.rdl_get_tuning(self._h, p, k, C.byref(v)), "rdl_get_tuning")
+                row.append(int(v.value))
+            out[name] = row
+        return out
+
+    def set_tuning(self, table: dict) -> None:
+        for p, name in enumerate(TUNE):
+            for k, v in enumerate(table.get(name, [])):
+                _chk(self._L.rdl_set_tuning(self._h, p, k, int(v)), "rdl_set_tuning")
+
+    def save_tuning(self, path: str) -> None:
+        with open(path, "w") as fh:
+            json.dump(self.get_tuning(), fh)
+
+    def load_tuning(self, path: str) -> None:
+        with open(path) as fh:
+            self.set_tuning(json.load(fh))
+
     def stage_keystat(self, rgbe: torch.Tensor, stream=None):
         out = torch.empty(2, dtype=torch.int64, device=rgbe.device)
         _chk(self._L.rdl_stage_keystat(self._h, _ptr(rgbe), int(rgbe.shape[0]), int(rgbe.shape[1]), _ptr(out),

@@ -42,3 +42,45 @@ def test_header_layout_matches_dtype():
     assert rdl.HEADER_BYTES == 7232
     assert rdl.HEADER_DTYPE.fields["a_q"][1] == 64
     assert rdl.HEADER_DTYPE.fields["present"][1] == 64 + 2 * 3072
+
+
+def _lib():
+    if not os.path.exists(LIB):
+        pytest.fail("librdl.so not built: run __graft_entry__.build()")
+    from paper_2309_11072_amd import rdl
+    return rdl, rdl.load_library()
+
+
+def test_size_limits_host_only():
+    rdl, L = _lib()
+    assert L.rdl_resid_bytes(3, 5) == 105
+    assert L.rdl_resid_bytes(0, 5) == 0 and L.rdl_resid_bytes(5, 0) == 0
+    assert L.rdl_resid_bytes(1, 1 << 28) == 7 << 28
+    assert L.rdl_resid_bytes(1, (1 << 28) + 1) == 0      # width limit (32-bit row offsets)
+    assert L.rdl_resid_bytes(1 << 16, 1 << 15) == 0      # H*W = 2^31
+    assert L.rdl_header_bytes() == rdl.HEADER_BYTES
+
+
+def test_header_validate_bounds_host_only():
+    """rdl_header_validate accepts exactly the coefficient ranges a
+    least-squares line through 8-bit data can take: |a_q| <= 255 2^22 and
+    -65025 2^14 <= b_q <= 65280 2^14."""
+    import ctypes
+    import numpy as np
+    rdl, L = _lib()
+    h = np.zeros(1, rdl.HEADER_DTYPE)
+    h["magic"], h["version"], h["H"], h["W"], h["q"] = rdl.RDL_MAGIC, 1, 7, 9, 75
+    h["present"][0, 17] = 1
+
+    def check(aq, bq):
+        g = h.copy()
+        g["a_q"][0, 1, 17] = aq
+        g["b_q"][0, 1, 17] = bq
+        return L.rdl_header_validate(g.ctypes.data_as(ctypes.c_void_p), 7, 9)
+
+    ok, bad = rdl.RDL_OK, rdl.RDL_ECORRUPT
+    assert check(0, 0) == ok
+    assert check(255 << 22, 65280 << 14) == ok and check(-(255 << 22), -65025 << 14) == ok
+    assert check((255 << 22) + 1, 0) == bad and check(-(255 << 22) - 1, 0) == bad
+    assert check(0, (65280 << 14) + 1) == bad and check(0, (-65025 << 14) - 1) == bad
+    assert L.rdl_header_validate(h.ctypes.data_as(ctypes.c_void_p), 7, 10) == bad

@@ -171,6 +171,13 @@ def test_invalid_arguments(codec, rdl_mod):
     assert L.rdl_encode_enh(h, None, 4, 4, 75, sdr.data_ptr(), hdr.data_ptr(), resid.data_ptr(), s) == E
     assert L.rdl_encode_enh(h, x.data_ptr() + 1, 4, 4, 75, sdr.data_ptr(), hdr.data_ptr(), resid.data_ptr(), s) == E
     assert L.rdl_encode_enh(None, x.data_ptr(), 4, 4, 75, sdr.data_ptr(), hdr.data_ptr(), resid.data_ptr(), s) == E
+    big = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    assert L.rdl_encode_enh(h, x.data_ptr(), 4, 4, 75, big.data_ptr() + 2, hdr.data_ptr(), resid.data_ptr(), s) == E
+    assert L.rdl_encode_enh(h, x.data_ptr(), 1, (1 << 28) + 1, 75, sdr.data_ptr(), hdr.data_ptr(), resid.data_ptr(),
+                            s) == E
+    out = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    assert L.rdl_decode_enh(h, big.data_ptr() + 1, hdr.data_ptr(), resid.data_ptr(), 4, 4, out.data_ptr(), None,
+                            s) == E
     assert L.rdl_resid_bytes(0, 5) == 0 and L.rdl_resid_bytes(3, 5) == 105
     assert L.rdl_encode_batch(h, None, 1, s) == E
 

@@ -1,0 +1,130 @@
+"""GPU parity of the launch-shape tuning: every strip height the tuner may
+pick gives outputs equal to the CPU oracle bit for bit (encode and decode), the
+tuner and the stage profiler leave a correct encode behind, and the tuning
+table rejects shapes outside its range."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2309_11072_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rdl_mod():
+    from paper_2309_11072_amd import rdl
+    return rdl
+
+
+@pytest.fixture()
+def codec(rdl_mod):
+    c = rdl_mod.Codec(0)
+    yield c
+    c.close()
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _size_class(H, W):
+    return (H * W).bit_length() - 1
+
+
+def _check(codec, rdl_mod, O, x, q, out):
+    H, W = x.shape[:2]
+    sdr, hdr, resid = out
+    ref = O.encode_enh(x, q)
+    assert np.array_equal(sdr.cpu().numpy(), ref["sdr"])
+    assert np.array_equal(resid.cpu().numpy(), ref["resid"])
+    h = rdl_mod.header_from_bytes(hdr)
+    assert np.array_equal(h["a_q"], ref["a_q"]) and np.array_equal(h["b_q"], ref["b_q"])
+    assert torch.equal(codec.decode_enh(sdr, hdr, resid, H, W), _dev(x))
+
+
+SHAPES = [(61, 83, 2.0, 40), (130, 300, 3.0, 75), (255, 257, 4.0, 90), (17, 1000, 2.5, 60), (300, 512, 3.5, 80)]
+
+
+@pytest.mark.parametrize("H,W,sig,q", SHAPES, ids=["%dx%d" % s[:2] for s in SHAPES])
+def test_every_strip_height_matches_oracle(codec, rdl_mod, O, H, W, sig, q):
+    x = synth.generate(H, W, sig, seed=1300 + H, spec_frac=0.05)
+    d = _dev(x)
+    table = codec.get_tuning()
+    for fit_rows, resid_rows, bins in ((2, 2, 1), (4, 4, 2), (8, 8, 4), (16, 16, 1), (32, 32, 2), (2, 32, 4),
+                                       (32, 2, 4)):
+        _say("strip rows fit", fit_rows, "resid", resid_rows, "bin copies", bins, "image", H, W)
+        table["fit_rows"][_size_class(H, W)] = fit_rows
+        table["resid_rows"][_size_class(H, W)] = resid_rows
+        table["fit_bins"][_size_class(H, W)] = bins
+        codec.set_tuning(table)
+        out = codec.alloc_outputs(H, W)
+        for t in out:
+            t.fill_(0xAA)
+        for _ in range(3):  # direct launch, capture, replay
+            codec.encode_enh(d, q, out=out)
+        torch.cuda.synchronize()
+        _check(codec, rdl_mod, O, x, q, out)
+
+
+def test_autotune_and_table_round_trip(codec, rdl_mod, O, tmp_path):
+    H, W, q = 257, 700, 75
+    x = synth.generate(H, W, 3.0, seed=1400, spec_frac=0.05)
+    d = _dev(x)
+    out = codec.alloc_outputs(H, W)
+    _say("autotune", H, W)
+    best = codec.autotune(d, q, out, reps=3)
+    assert set(best) == {"fit_rows", "resid_rows", "fit_bins"}
+    assert best["fit_rows"] in (2, 4, 8, 16, 32) and best["resid_rows"] in (2, 4, 8, 16, 32)
+    assert best["fit_bins"] in (1, 2, 4)
+    torch.cuda.synchronize()
+    _check(codec, rdl_mod, O, x, q, out)
+    table = codec.get_tuning()
+    assert all(table[k][_size_class(H, W)] == v for k, v in best.items())
+    p = tmp_path / "tuning.json"
+    codec.save_tuning(str(p))
+    other = rdl_mod.Codec(0)
+    try:
+        other.load_tuning(str(p))
+        assert other.get_tuning() == table
+        out2 = other.alloc_outputs(H, W)
+        other.encode_enh(d, q, out=out2)
+        torch.cuda.synchronize()
+        _check(other, rdl_mod, O, x, q, out2)
+    finally:
+        other.close()
+
+
+def test_profile_encode_leaves_correct_outputs(codec, rdl_mod, O):
+    H, W, q = 200, 301, 85
+    x = synth.generate(H, W, 2.5, seed=1500, spec_frac=0.05)
+    out = codec.alloc_outputs(H, W)
+    for t in out:
+        t.fill_(0x55)
+    _say("profile_encode", H, W)
+    ms = codec.profile_encode(_dev(x), q, out, reps=4)
+    torch.cuda.synchronize()
+    assert set(ms) == {"keystat", "tmo_base", "fit_sums", "solve", "resid"}
+    assert all(v > 0 for v in ms.values())
+    _check(codec, rdl_mod, O, x, q, out)
+
+
+def test_tuning_table_rejects_bad_shapes(codec, rdl_mod):
+    t = codec.get_tuning()
+    assert t["fit_rows"] == [16] * 32 and t["resid_rows"] == [8] * 32 and t["fit_bins"] == [4] * 32
+    for bad in (0, 1, 3, 12, 64):
+        with pytest.raises(rdl_mod.RdlError):
+            codec.set_tuning({"resid_rows": [bad] * 32})
+    for bad in (0, 3, 8):
+        with pytest.raises(rdl_mod.RdlError):
+            codec.set_tuning({"fit_bins": [bad] * 32})
+    L, h = codec._L, codec._h
+    assert L.rdl_set_tuning(h, 0, 32, 4) == rdl_mod.RDL_EINVAL
+    assert L.rdl_set_tuning(h, 0, -1, 4) == rdl_mod.RDL_EINVAL
+    assert L.rdl_set_tuning(h, 3, 0, 4) == rdl_mod.RDL_EINVAL
+    assert L.rdl_set_tuning(h, -1, 0, 4) == rdl_mod.RDL_EINVAL
+    assert codec.get_tuning() == t

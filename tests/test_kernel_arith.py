@@ -1,0 +1,75 @@
+"""CPU checks of integer identities the HIP kernels rely on, written out here
+with numpy (no GPU, no oracle): each kernel form must equal the plain
+definition on every input it can receive."""
+import numpy as np
+
+AQ_MAX = 255 << 22
+BQ_MIN, BQ_MAX = -65025 << 14, 65280 << 14
+
+
+def mstar_def(aq, bq, s):
+    """Eq. 8 with the fixed-point coefficients: clamp(floor((a_q s + 2^8 b_q + 2^21) / 2^22), 0, 255)."""
+    v = (aq.astype(np.int64) * s + bq.astype(np.int64) * 256 + (1 << 21)) >> 22
+    return np.clip(v, 0, 255)
+
+
+def mstar_kernel(aq, bq, s):
+    """The residual kernel's 32-bit form: x = ah (low 24 bits, signed) | al << 24,
+    y = b_q + 2^13; v = mul_i24(x, s) + y; u = (al s) >> 8; clamp((v + u) >> 14)."""
+    aq = aq.astype(np.int64)
+    ah = aq >> 8
+    al = aq & 255
+    x = (ah & 0xFFFFFF) | (al << 24)
+    x24 = ((x & 0xFFFFFF) ^ 0x800000) - 0x800000          # sign-extend bits 0..23
+    v = x24 * s + (bq.astype(np.int64) + 8192)
+    assert np.all(np.abs(v) < 2 ** 31), "32-bit overflow"
+    u = (((x >> 24) & 255) * s) >> 8
+    t = v + u
+    assert np.all(np.abs(t) < 2 ** 31)
+    return np.clip(t >> 14, 0, 255)
+
+
+def test_mstar_32bit_form_equals_definition():
+    rng = np.random.default_rng(7)
+    edges_a = np.array([-AQ_MAX, -AQ_MAX + 1, -(1 << 22), -255, -1, 0, 1, 255, 256, 1 << 22, AQ_MAX - 1, AQ_MAX])
+    edges_b = np.array([BQ_MIN, BQ_MIN + 1, -(1 << 14), -1, 0, 1, 8191, 8192, 1 << 14, BQ_MAX - 1, BQ_MAX])
+    s = np.arange(256, dtype=np.int64)[None, :]
+    A, B = np.meshgrid(edges_a, edges_b, indexing="ij")
+    A, B = A.reshape(-1, 1), B.reshape(-1, 1)
+    assert np.array_equal(mstar_kernel(A, B, s), mstar_def(A, B, s))
+    A = rng.integers(-AQ_MAX, AQ_MAX + 1, (4000, 1))
+    B = rng.integers(BQ_MIN, BQ_MAX + 1, (4000, 1))
+    assert np.array_equal(mstar_kernel(A, B, s), mstar_def(A, B, s))
+    # near the rounding boundaries: a_q s + 2^8 b_q + 2^21 = k 2^22 + {-1, 0, 1}
+    A = rng.integers(-AQ_MAX, AQ_MAX + 1, (4000, 1))
+    S = rng.integers(0, 256, (4000, 1))
+    K = rng.integers(-200, 400, (4000, 1))
+    for off in (-1, 0, 1):
+        Bn = (K * (1 << 22) + off - (1 << 21) - A * S) // 256
+        keep = (Bn >= BQ_MIN) & (Bn <= BQ_MAX)
+        a, b = A[keep][:, None], Bn[keep][:, None]
+        assert np.array_equal(mstar_kernel(a, b, s), mstar_def(a, b, s))
+
+
+def test_mstar_regression_lines_through_pixels():
+    """Coefficients as the solve makes them (least-squares lines through
+    8-bit data) stay within the kernel's bounds."""
+    rng = np.random.default_rng(11)
+    for _ in range(2000):
+        n = int(rng.integers(2, 40))
+        sv = rng.integers(0, 256, n)
+        mv = rng.integers(0, 256, n)
+        num = n * int((sv * mv).sum()) - int(sv.sum()) * int(mv.sum())
+        den = n * int((sv * sv).sum()) - int(sv.sum()) ** 2
+        if den == 0:
+            continue
+        aq = (2 * (num << 22) + den) // (2 * den)
+        bq = (2 * ((int(mv.sum()) << 22) - aq * int(sv.sum())) + 256 * n) // (2 * 256 * n)
+        assert -AQ_MAX <= aq <= AQ_MAX and BQ_MIN <= bq <= BQ_MAX
+
+
+def test_gf_packed_fields_never_carry():
+    """The GF adds (1,6,1) x (1,6,1) weighted 8-bit values in 16-bit lanes:
+    the largest sum, 64 * 255 + 32, stays below 2^16, and >> 6 of it is 255."""
+    top = 64 * 255 + 32
+    assert top < 1 << 16 and top >> 6 == 255

@@ -1,0 +1,103 @@
+"""CPU model of the memory accesses of the strip walk shared by the fit and
+residual kernels (the same index arithmetic as the HIP code, lane by lane):
+every read and write must fall inside its buffer, for every lane, row and
+launch shape, on widths of every residue mod 4 and on S buffers whose rows do
+not start on dword boundaries.  No GPU is needed; this runs before a changed
+walk ever reaches one."""
+import numpy as np
+import pytest
+
+STRIP_W, STRIP_WAVES, WALK_CH = 256, 4, 4
+
+
+def walk_accesses(H, W, srh, sdr_base, rgbe_base, resid_base):
+    """Yields (buffer, first byte, last byte + 1) for every access."""
+    nsx = (W + STRIP_W - 1) // STRIP_W
+    nwg = ((H + srh * STRIP_WAVES - 1) // (srh * STRIP_WAVES)) * nsx
+    end = sdr_base + 3 * H * W
+    npx = H * W
+    for wgl in range(nwg):
+        sy, sx = divmod(wgl, nsx)
+        x0 = sx * STRIP_W
+        for wave in range(STRIP_WAVES):
+            ya = (sy * STRIP_WAVES + wave) * srh
+            if ya >= H:
+                continue
+            yb = min(ya + srh, H)
+            lanes = np.arange(64)
+            x = x0 + 4 * lanes
+            hx = np.where(lanes == 0, max(x0 - 1, 0), min(x0 + STRIP_W, W - 1))
+            xo3, ho3, xo4 = 3 * x, 3 * hx, 4 * x
+            fx = x + 4 <= W
+            last = sdr_base + (H - 1) * 3 * W
+            shl = (last + xo3) & 3
+            fast_last = fx & (xo3 - shl + 16 <= 3 * W)
+
+            def s_row(yy):
+                row = sdr_base + yy * 3 * W
+                fast = fx if yy < H - 1 else fast_last
+                sh = (row + xo3) & 3
+                for l in range(64):
+                    if fast[l]:
+                        a = row + xo3[l] - sh[l]
+                        yield ("sdr", a, a + 16)
+                    else:
+                        for j in range(4):
+                            a = row + 3 * min(x[l] + j, W - 1)
+                            yield ("sdr", a, a + 3)
+                    yield ("sdr", row + ho3[l], row + ho3[l] + 3)
+
+            def rgbe_row(yy):
+                row = rgbe_base + yy * 4 * W
+                for l in range(64):
+                    p = row + xo4[l]
+                    if fx[l] and (p & 15) == 0:
+                        yield ("rgbe", p, p + 16)
+                    else:
+                        for j in range(4):
+                            a = row + 4 * min(x[l] + j, W - 1)
+                            yield ("rgbe", a, a + 4)
+
+            yield from s_row(max(ya - 1, 0))
+            yield from s_row(ya)
+            for y0 in range(ya, yb, WALK_CH):
+                for k in range(WALK_CH):
+                    yield from s_row(min(min(y0 + k + 1, yb), H - 1))
+                    yield from rgbe_row(min(y0 + k, yb - 1))
+                for k in range(WALK_CH):
+                    y = y0 + k
+                    if y >= yb:
+                        continue
+                    al = (W & 3) == 0 and (resid_base & 7) == 0
+                    for l in range(64):
+                        if x[l] >= W:
+                            continue
+                        if al and x[l] + 4 <= W:
+                            for c in range(3):
+                                a = resid_base + 2 * (c * npx + y * W + x[l])
+                                yield ("resid", a, a + 8)
+                            a = resid_base + 6 * npx + y * W + x[l]
+                            yield ("resid", a, a + 4)
+                        else:
+                            for j in range(min(4, W - x[l])):
+                                for c in range(3):
+                                    a = resid_base + 2 * (c * npx + y * W + x[l] + j)
+                                    yield ("resid", a, a + 2)
+                                a = resid_base + 6 * npx + y * W + x[l] + j
+                                yield ("resid", a, a + 1)
+
+
+SHAPES = [(1, 1), (1, 4), (1, 5), (2, 7), (7, 9), (9, 17), (5, 256), (3, 257), (6, 258), (4, 259), (33, 40),
+          (17, 513), (2, 1023)]
+
+
+@pytest.mark.parametrize("H,W", SHAPES, ids=["%dx%d" % s for s in SHAPES])
+@pytest.mark.parametrize("srh", [2, 8, 32])
+def test_strip_walk_stays_inside_buffers(H, W, srh):
+    bases = {"sdr": 4096, "rgbe": 1 << 20, "resid": 1 << 24}
+    sizes = {"sdr": 3 * H * W, "rgbe": 4 * H * W, "resid": 7 * H * W}
+    for sdr_off in (0, 4, 8):   # S buffers start on dword boundaries (the API requires it)
+        for res_off in (0, 2):
+            b = dict(bases, sdr=bases["sdr"] + sdr_off, resid=bases["resid"] + res_off)
+            for buf, lo, hi in walk_accesses(H, W, srh, b["sdr"], b["rgbe"], b["resid"]):
+                assert b[buf] <= lo and hi <= b[buf] + sizes[buf], (buf, lo - b[buf], hi - b[buf], sizes[buf])
