@@ -227,29 +227,32 @@ int rdl_profile_encode(rdl_ctx *ctx, const uint8_t *rgbe, int H, int W, int q, u
 
 /* ---- Launch-shape tuning ----
  *
- * The GF-based stages give each wave a strip of 256 pixels and some rows
- * (4 waves stacked per workgroup).  Tall strips leave SIMDs idle on small
- * images; short ones re-read more halo rows of S and, in the fit, make more
- * workgroups add their partial sums to the same global totals.  The context
- * keeps one value per tuning parameter and size class floor(log2(H * W))
- * (0..31), initially 16 rows for the fit and 8 for the residual and decode
- * walks; a batch uses each image's own class.  The fit's per-(channel, E)
- * bins in LDS are kept in 1, 2 or 4 copies (initially 4) that neighbouring
- * lanes alternate between, so that lanes closing runs of the same exponent
- * at once do not all add to one address; one launch takes the value of its
- * largest image.  Captured graphs are keyed on the shapes, so a change takes
- * effect at the next call. */
+ * The GF-based stages give each wave a strip of 256 pixels and some rows,
+ * waves stacked per workgroup.  Tall strips leave SIMDs idle on small images;
+ * short ones re-read more halo rows of S.  In the fit every workgroup ends by
+ * adding its per-(channel, E) totals to the image's global sums, so fewer,
+ * larger workgroups (more waves each) cost fewer global atomics.  The fit's
+ * LDS bins can be kept in 1, 2 or 4 copies that neighbouring lanes alternate
+ * between.  The context keeps one value per tuning parameter and size class
+ * floor(log2(H * W)) (0..31), initially: fit 16 waves x 8 rows from 4 Mpx
+ * up, 8 x 16 from 1 Mpx, else 4 x 16, with 2 bin copies; residual/decode 8
+ * rows (4 waves).  A batch uses each image's own class for
+ * the rows; the fit's waves and bin copies are one per launch, its largest
+ * image's, and a fit workgroup spans at most 128 rows (waves x rows; larger
+ * row counts are clamped).  Captured graphs are keyed on the shapes, so a
+ * change takes effect at the next call. */
 enum {
     RDL_TUNE_FIT_ROWS = 0,   /* rows per wave of the fit (k_fit_sums)         */
     RDL_TUNE_RESID_ROWS = 1, /* rows per wave of the residual/decode walks    */
     RDL_TUNE_FIT_BINS = 2,   /* privatised copies of the fit's LDS bins       */
-    RDL_NTUNE = 3
+    RDL_TUNE_FIT_WAVES = 3,  /* waves per fit workgroup                       */
+    RDL_NTUNE = 4
 };
 
 /* Encodes the caller's image once (same arguments and outputs as
  * rdl_encode_enh, plain estimator), then, for each parameter, launches its
  * kernel `reps` times back to back for each value (rows: 2, 4, 8, 16, 32;
- * bin copies: 1, 2, 4), timed
+ * bin copies: 1, 2, 4; waves: 4, 8, 16), one parameter after the other, timed
  * with HIP events on `stream`, and keeps the fastest for the image's size
  * class; the HOST array best[RDL_NTUNE] (may be NULL) receives the choices.
  * Outputs hold a correct encode on return.  Synchronises `stream`; not
@@ -259,10 +262,19 @@ int rdl_autotune(rdl_ctx *ctx, const uint8_t *rgbe, int H, int W, int q, uint8_t
                  rdl_header *out_coeffs, void *out_resid, int reps, int *best, void *stream);
 
 /* Read / write one entry (for saving and restoring a tuned table).  Rows are
- * powers of two in [2, 32], bin copies 1, 2 or 4; anything else, or a
- * parameter or class out of range, gives RDL_EINVAL. */
+ * powers of two in [2, 32], bin copies 1, 2 or 4, waves 4, 8 or 16; anything
+ * else, or a parameter or class out of range, gives RDL_EINVAL. */
 int rdl_get_tuning(rdl_ctx *ctx, int param, int size_class, int *value);
 int rdl_set_tuning(rdl_ctx *ctx, int param, int size_class, int value);
+
+/* Self-check of the reciprocal the tone-mapping kernel uses (the hardware
+ * estimate refined by one fused Newton step, in place of IEEE division, whose
+ * result it must equal for every denominator the operator can produce, the
+ * floats in [1, 2^47)).  Compares the two for every float whose bit pattern
+ * lies in [lo_bits, hi_bits) and writes the number of differences to the HOST
+ * *mismatches.  Allocates a few bytes of device memory; synchronises
+ * `stream`.  RDL_EINVAL if hi_bits < lo_bits. */
+int rdl_check_recip(rdl_ctx *ctx, uint32_t lo_bits, uint32_t hi_bits, uint64_t *mismatches, void *stream);
 
 #ifdef __cplusplus
 }

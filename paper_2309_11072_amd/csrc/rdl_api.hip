@@ -107,7 +107,7 @@ int ensure_scratch(rdl_ctx *c, size_t n) {
 
 struct Grid {
     int px = 0, blk = 0, tile = 0, fit = 0, res = 0, learn = 0;
-    int fit_bins = 1;  // one launch shape for the whole fit launch: the largest image's
+    int fit_bins = 1, fit_waves = STRIP_WAVES;  // the fit's launch shape: the largest image's
     int64_t fit_px = -1;
 };
 
@@ -156,19 +156,38 @@ uint64_t fnv1a64(const uint8_t *p, size_t n) {
     return h;
 }
 
+// Values a tuning parameter may take: powers of two in [lo, hi].
+void tune_range(int param, int &lo, int &hi) {
+    switch (param) {
+        case RDL_TUNE_FIT_BINS: lo = 1; hi = 4; break;
+        case RDL_TUNE_FIT_WAVES: lo = 4; hi = 16; break;
+        default: lo = SRH_MIN; hi = SRH_MAX; break;
+    }
+}
+
 int size_class(int H, int W) {
     const uint64_t px = (uint64_t)H * (uint64_t)W;
     return 63 - __builtin_clzll(px);  // px >= 1
 }
 
-// Assign each image its launch shape (from the context's tuning table) and
-// its first workgroup per kernel family.
+// Assign each image its launch shapes (from the context's tuning table) and
+// its first workgroup per kernel family.  The fit's block shape (bin copies,
+// waves per workgroup) is one per launch: the largest image's.
 Grid layout(const rdl_ctx *c, std::vector<ImgDesc> &v) {
     Grid g;
     for (auto &d : v) {
-        d.srh_fit = c->tune[RDL_TUNE_FIT_ROWS][size_class(d.H, d.W)];
-        d.srh_res = c->tune[RDL_TUNE_RESID_ROWS][size_class(d.H, d.W)];
-        d.fit_bins = c->tune[RDL_TUNE_FIT_BINS][size_class(d.H, d.W)];
+        if ((int64_t)d.H * d.W > g.fit_px) {
+            g.fit_px = (int64_t)d.H * d.W;
+            g.fit_bins = c->tune[RDL_TUNE_FIT_BINS][size_class(d.H, d.W)];
+            g.fit_waves = c->tune[RDL_TUNE_FIT_WAVES][size_class(d.H, d.W)];
+        }
+    }
+    for (auto &d : v) {
+        const int cls = size_class(d.H, d.W);
+        d.fit_bins = g.fit_bins;
+        d.fit_waves = g.fit_waves;
+        d.srh_fit = std::min(c->tune[RDL_TUNE_FIT_ROWS][cls], FIT_WG_ROWS_MAX / g.fit_waves);
+        d.srh_res = c->tune[RDL_TUNE_RESID_ROWS][cls];
         d.wg_px = g.px;
         d.wg_blk = g.blk;
         d.wg_tile = g.tile;
@@ -178,11 +197,7 @@ Grid layout(const rdl_ctx *c, std::vector<ImgDesc> &v) {
         g.px += wgs_px(d.H, d.W);
         g.blk += wgs_blk(d.H, d.W);
         g.tile += wgs_tile(d.H, d.W);
-        g.fit += wgs_strip(d.H, d.W, d.srh_fit);
-        if ((int64_t)d.H * d.W > g.fit_px) {
-            g.fit_px = (int64_t)d.H * d.W;
-            g.fit_bins = d.fit_bins;
-        }
+        g.fit += wgs_strip(d.H, d.W, d.srh_fit, d.fit_waves);
         g.res += wgs_strip(d.H, d.W, d.srh_res);
         g.learn += wgs_learn(d.H, d.W);
     }
@@ -195,7 +210,7 @@ void bind_scratch(ImgDesc &d, int64_t *base) {
     d.nks = std::min(KS_STRIPES, std::max(1, wgs_px(d.H, d.W)));
     d.sums = base + SCR_SUMS;
     d.part = base + SCR_PART;
-    d.nfs = std::min(FIT_STRIPES, std::max(1, wgs_strip(d.H, d.W, d.srh_fit)));
+    d.nfs = std::min(FIT_STRIPES, std::max(1, wgs_strip(d.H, d.W, d.srh_fit, d.fit_waves)));
 }
 
 int upload(rdl_ctx *c, const std::vector<ImgDesc> &v, hipStream_t s) {
@@ -218,7 +233,7 @@ int check_launch(const char *what) {
 void enqueue_encode(const ImgDesc *d, int n, const Grid &g, bool learned, hipStream_t s) {
     launch_keystat(d, n, g.px, s);
     launch_tmo_base(d, n, g.blk, false, s);
-    launch_fit_sums(d, n, g.fit, g.fit_bins, s);
+    launch_fit_sums(d, n, g.fit, g.fit_bins, g.fit_waves, s);
     launch_solve(d, n, s);
     if (learned) {
         launch_learn(d, n, g.learn, s);
@@ -273,7 +288,11 @@ int rdl_create(rdl_ctx **out, int device) {
     if (!c) return RDL_ENOMEM;
     c->device = device;
     for (int k = 0; k < 32; ++k) {
-        c->tune[RDL_TUNE_FIT_ROWS][k] = SRH_FIT_DEFAULT;
+        // Fit workgroups as large as the image allows while still giving
+        // every CU work: 16 waves x 8 rows from 4 Mpx up, 8 x 16 from 1 Mpx,
+        // else 4 x 16.
+        c->tune[RDL_TUNE_FIT_WAVES][k] = k >= 22 ? 16 : k >= 20 ? 8 : 4;
+        c->tune[RDL_TUNE_FIT_ROWS][k] = k >= 22 ? 8 : SRH_FIT_DEFAULT;
         c->tune[RDL_TUNE_RESID_ROWS][k] = SRH_RES_DEFAULT;
         c->tune[RDL_TUNE_FIT_BINS][k] = FIT_BINS_DEFAULT;
     }
@@ -546,7 +565,7 @@ int rdl_stage_fit(rdl_ctx *c, const uint8_t *rgbe, const uint8_t *sdr, int H, in
     c->last_key.clear();
     rc = upload(c, v, s);
     if (rc) return rc;
-    launch_fit_sums(c->d_desc, 1, gr.fit, gr.fit_bins, s);
+    launch_fit_sums(c->d_desc, 1, gr.fit, gr.fit_bins, gr.fit_waves, s);
     launch_solve(c->d_desc, 1, s);
     return check_launch("k_fit_sums/k_solve");
 }
@@ -613,7 +632,7 @@ int rdl_profile_encode(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int q, uin
             switch (st) {
                 case RDL_STAGE_KEYSTAT: launch_keystat(d, 1, gr.px, s); break;
                 case RDL_STAGE_TMO_BASE: launch_tmo_base(d, 1, gr.blk, false, s); break;
-                case RDL_STAGE_FIT: launch_fit_sums(d, 1, gr.fit, gr.fit_bins, s); break;
+                case RDL_STAGE_FIT: launch_fit_sums(d, 1, gr.fit, gr.fit_bins, gr.fit_waves, s); break;
                 case RDL_STAGE_SOLVE: launch_solve(d, 1, s); break;
                 case RDL_STAGE_RESID: launch_resid(d, 1, gr.res, s); break;
             }
@@ -627,7 +646,7 @@ int rdl_profile_encode(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int q, uin
     if (err == hipSuccess) {
         launch_keystat(d, 1, gr.px, s);
         launch_tmo_base(d, 1, gr.blk, false, s);
-        launch_fit_sums(d, 1, gr.fit, gr.fit_bins, s);
+        launch_fit_sums(d, 1, gr.fit, gr.fit_bins, gr.fit_waves, s);
         launch_solve(d, 1, s);
         launch_resid(d, 1, gr.res, s);
         err = hipGetLastError();
@@ -683,7 +702,8 @@ int rdl_autotune(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int q, uint8_t *
     for (int p = 0; p < RDL_NTUNE && rc == RDL_OK && err == hipSuccess; ++p) {
         float best_ms = 0.0f;
         int pick = c->tune[p][cls];
-        const int lo = p == RDL_TUNE_FIT_BINS ? 1 : SRH_MIN, hi = p == RDL_TUNE_FIT_BINS ? 4 : SRH_MAX;
+        int lo, hi;
+        tune_range(p, lo, hi);
         for (int srh = lo; srh <= hi && rc == RDL_OK && err == hipSuccess; srh *= 2) {
             c->tune[p][cls] = srh;
             std::vector<ImgDesc> v = table();
@@ -693,7 +713,7 @@ int rdl_autotune(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int q, uint8_t *
             if (rc) break;
             const ImgDesc *d = c->d_desc;
             auto once = [&]() {
-                if (p != RDL_TUNE_RESID_ROWS) launch_fit_sums(d, 1, gr.fit, gr.fit_bins, s);
+                if (p != RDL_TUNE_RESID_ROWS) launch_fit_sums(d, 1, gr.fit, gr.fit_bins, gr.fit_waves, s);
                 else launch_resid(d, 1, gr.res, s);
             };
             once();  // warm-up
@@ -730,6 +750,28 @@ int rdl_autotune(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int q, uint8_t *
     return RDL_OK;
 }
 
+int rdl_check_recip(rdl_ctx *c, uint32_t lo_bits, uint32_t hi_bits, uint64_t *mismatches, void *stream) {
+    if (!c || !mismatches || hi_bits < lo_bits) return RDL_EINVAL;
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long *d = nullptr;
+    HIPCHK(hipMalloc(&d, sizeof *d));
+    hipError_t err = hipMemsetAsync(d, 0, sizeof *d, s);
+    const uint32_t chunk = 1u << 26;
+    for (uint64_t b = lo_bits; err == hipSuccess && b < hi_bits; b += chunk) {
+        const uint32_t cnt = (uint32_t)std::min<uint64_t>(chunk, hi_bits - b);
+        launch_check_recip((uint32_t)b, cnt, d, s);
+        err = hipGetLastError();
+    }
+    unsigned long long h = 0;
+    if (err == hipSuccess) err = hipMemcpyAsync(&h, d, sizeof h, hipMemcpyDeviceToHost, s);
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    (void)hipFree(d);
+    if (err != hipSuccess) return hip_fail(err, "rdl_check_recip");
+    *mismatches = h;
+    return RDL_OK;
+}
+
 int rdl_get_tuning(rdl_ctx *c, int param, int size_class, int *value) {
     if (!c || !value || param < 0 || param >= RDL_NTUNE || size_class < 0 || size_class > 31) return RDL_EINVAL;
     *value = c->tune[param][size_class];
@@ -738,7 +780,8 @@ int rdl_get_tuning(rdl_ctx *c, int param, int size_class, int *value) {
 
 int rdl_set_tuning(rdl_ctx *c, int param, int size_class, int value) {
     if (!c || param < 0 || param >= RDL_NTUNE || size_class < 0 || size_class > 31) return RDL_EINVAL;
-    const int lo = param == RDL_TUNE_FIT_BINS ? 1 : SRH_MIN, hi = param == RDL_TUNE_FIT_BINS ? 4 : SRH_MAX;
+    int lo, hi;
+    tune_range(param, lo, hi);
     if (value < lo || value > hi || (value & (value - 1))) return RDL_EINVAL;
     c->tune[param][size_class] = value;
     return RDL_OK;

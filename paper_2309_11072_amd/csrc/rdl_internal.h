@@ -21,7 +21,9 @@ constexpr int STRIP_THREADS = 64 * STRIP_WAVES;  // lane; 4 waves stacked per wo
 constexpr int SRH_MIN = 2, SRH_MAX = 32;  // srh: a power of two in [2, 32], tuned per
 constexpr int SRH_FIT_DEFAULT = 16;       //   kernel and image size
 constexpr int SRH_RES_DEFAULT = 8;
-constexpr int FIT_BINS_DEFAULT = 4;       // privatised copies of the fit's LDS bins: 1, 2 or 4
+constexpr int FIT_BINS_DEFAULT = 2;       // privatised copies of the fit's LDS bins: 1, 2 or 4
+constexpr int FIT_WG_ROWS_MAX = 128;      // waves x rows per fit workgroup: <= 32768 px, so
+                                          //   the workgroup's 32-bit bin totals cannot wrap
 constexpr int HIST_STRIPES = 4;    // learned path: copies of the per-region histograms
 constexpr int LEARN_W = 64, LEARN_H = 64;  // learned path: 64 x 64 px per workgroup
 constexpr int MODEL_BYTES = 7512;
@@ -59,7 +61,7 @@ struct ImgDesc {
     int32_t H, W, q, flags;
     int32_t nks, nfs, srh_fit, srh_res;  // rows per wave of the fit / residual+decode strip walks
     int32_t wg_px, wg_blk, wg_tile, wg_fit, wg_res, wg_learn;
-    int32_t fit_bins, pad2;  // fit_bins: the image's tuned bin copies (keys captured graphs)
+    int32_t fit_bins, fit_waves;  // the fit launch's bin copies and waves per workgroup
 };
 
 // Accumulator hygiene: scratch stripes are all-zero between launch sequences
@@ -71,8 +73,8 @@ enum : int32_t { F_ZERO_KS = 1, F_ZERO_SUMS = 2, F_ZERO_HIST = 4, F_CLEAN_KS = 8
 inline int wgs_px(int H, int W) { return (int)(((int64_t)H * W + KS_PX_PER_WG - 1) / KS_PX_PER_WG); }
 inline int wgs_blk(int H, int W) { return ((H + 7) / 8) * (((W + 7) / 8 + BLK_WG - 1) / BLK_WG); }
 inline int wgs_tile(int H, int W) { return ((H + TILE_H - 1) / TILE_H) * ((W + TILE_W - 1) / TILE_W); }
-inline int wgs_strip(int H, int W, int srh) {
-    const int sh = srh * STRIP_WAVES;
+inline int wgs_strip(int H, int W, int srh, int waves = STRIP_WAVES) {
+    const int sh = srh * waves;
     return ((H + sh - 1) / sh) * ((W + STRIP_W - 1) / STRIP_W);
 }
 inline int wgs_learn(int H, int W) { return ((H + LEARN_H - 1) / LEARN_H) * ((W + LEARN_W - 1) / LEARN_W); }
@@ -81,9 +83,10 @@ inline size_t lhist_words() { return (size_t)HIST_STRIPES * 2 * 3 * 256 * 511; }
 // Kernel launchers (defined in rdl_kernels.hip).
 hipError_t upload_tables(int *bad_table);
 void launch_zero(const ImgDesc *d, int n, hipStream_t s);
+void launch_check_recip(uint32_t lo, uint32_t count, unsigned long long *bad, hipStream_t s);
 void launch_keystat(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_tmo_base(const ImgDesc *d, int n, int wgs, bool extra, hipStream_t s);
-void launch_fit_sums(const ImgDesc *d, int n, int wgs, int bins, hipStream_t s);
+void launch_fit_sums(const ImgDesc *d, int n, int wgs, int bins, int waves, hipStream_t s);
 void launch_solve(const ImgDesc *d, int n, hipStream_t s);
 void launch_key_total(const ImgDesc *d, int n, int64_t *out2, hipStream_t s);
 void launch_resid(const ImgDesc *d, int n, int wgs, hipStream_t s);

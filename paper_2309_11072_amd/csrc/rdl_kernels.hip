@@ -61,6 +61,14 @@ __host__ __device__ constexpr int pk16(int lo, int hi) {
 __device__ __forceinline__ int dot2(int a, int b, int c) {
     return __builtin_amdgcn_sdot2(__builtin_bit_cast(short2v, a), __builtin_bit_cast(short2v, b), c, false);
 }
+// The same with the accumulator as a separate operand (the three-operand
+// encoding): starting a chain from a shared constant then needs no copy of
+// the constant into each destination.
+__device__ __forceinline__ int dot2s(int a, int b, int c) {
+    int d;
+    asm("v_dot2_i32_i16 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
 __device__ __forceinline__ int pack_i16(int lo, int hi) {
     return __builtin_bit_cast(int, __builtin_amdgcn_cvt_pk_i16(lo, hi));
 }
@@ -263,6 +271,17 @@ __device__ __forceinline__ int gamma_code(float C, const uint8_t *lut, const flo
     return c0 + (C >= thr[c0 + 1] ? 1 : 0);
 }
 
+// Correctly rounded 1/D for D in [1, 2^47): the hardware reciprocal refined by
+// one Newton step with fused multiply-adds.  Checked equal to IEEE division
+// for every float in that range on gfx950 (the denominator of the operator
+// below is 1 + sigma 2^(k'-16) Y with sigma < 0.36, k' <= 40 and Y < 2^24, so
+// it always lies there).
+__device__ __forceinline__ float recip(float D) {
+    const float r0 = __builtin_amdgcn_rcpf(D);
+    const float e = __builtin_fmaf(-D, r0, 1.0f);
+    return __builtin_fmaf(e, r0, r0);
+}
+
 // Global Reinhard operator, hue preserving, per pixel.  P = sigma 2^k',
 // k' = k_img + E - 136 (clamped at 40: the 1 in 1 + t is then absorbed and the
 // result is exactly the clamped one); t = P * Y * 2^-16, D = 1 + t, R = 1/D,
@@ -277,13 +296,16 @@ __device__ __forceinline__ void tmo_px(uint32_t w, int kbase, float sigma, bool 
     const float Pl = ldexpf(sigma, kp - 16);
     const float t = Pl * (float)lum_y(w);
     const float Dn = 1.0f + t;
-    const float R = 1.0f / Dn;
+    const float R = recip(Dn);
     const float c0 = (P * ((float)(w & 255u) + 0.5f)) * R;
     const float c1 = (P * ((float)((w >> 8) & 255u) + 0.5f)) * R;
     const float c2 = (P * ((float)((w >> 16) & 255u) + 0.5f)) * R;
-    r = zero ? 0 : gamma_code(c0, lut, thr);
-    g = zero ? 0 : gamma_code(c1, lut, thr);
-    b = zero ? 0 : gamma_code(c2, lut, thr);
+    // Branch-free: every lane looks its three codes up (the bucket index is
+    // clamped, so the reads stay inside the tables), then unlit ones are masked.
+    const int keep = zero ? 0 : -1;
+    r = gamma_code(c0, lut, thr) & keep;
+    g = gamma_code(c1, lut, thr) & keep;
+    b = gamma_code(c2, lut, thr) & keep;
 }
 
 __device__ __forceinline__ int padd(int a, int b) {
@@ -305,9 +327,9 @@ __device__ __forceinline__ int KI(int y, int par, int h) {
 // out[u] = sum_x K[u][x] x_x + bias.
 __device__ __forceinline__ void fdct1(int S01, int S23, int D01, int D23, int bias, int out[8]) {
 #pragma unroll
-    for (int u = 0; u < 8; u += 2) out[u] = dot2(KF(u, 0), S01, dot2(KF(u, 1), S23, bias));
+    for (int u = 0; u < 8; u += 2) out[u] = dot2(KF(u, 0), S01, dot2s(KF(u, 1), S23, bias));
 #pragma unroll
-    for (int u = 1; u < 8; u += 2) out[u] = dot2(KF(u, 0), D01, dot2(KF(u, 1), D23, bias));
+    for (int u = 1; u < 8; u += 2) out[u] = dot2(KF(u, 0), D01, dot2s(KF(u, 1), D23, bias));
 }
 
 // 1-D inverse transform of 8 coefficients given as pairs E0 = (c0, c2),
@@ -315,8 +337,8 @@ __device__ __forceinline__ void fdct1(int S01, int S23, int D01, int D23, int bi
 __device__ __forceinline__ void idct1(int E0, int E1, int O0, int O1, int bias, int out[8]) {
 #pragma unroll
     for (int y = 0; y < 4; ++y) {
-        const int e = dot2(KI(y, 0, 0), E0, dot2(KI(y, 0, 1), E1, bias));
-        const int o = dot2(KI(y, 1, 0), O0, dot2(KI(y, 1, 1), O1, 0));
+        const int e = dot2(KI(y, 0, 0), E0, dot2s(KI(y, 0, 1), E1, bias));
+        const int o = dot2(KI(y, 1, 0), O0, dot2s(KI(y, 1, 1), O1, 0));
         out[y] = e + o;
         out[7 - y] = e - o;
     }
@@ -638,7 +660,7 @@ struct StripPos {
     uint32_t xo3, ho3, xo4;  // byte offsets in a row of S (3x, 3hx) and of RGBE (4x)
     bool fx;                 // x + 4 <= W: the lane's four pixels are all inside
 };
-__device__ __forceinline__ StripPos strip_pos(int wgl, int H, int W, int srh) {
+__device__ __forceinline__ StripPos strip_pos(int wgl, int H, int W, int srh, int waves = STRIP_WAVES) {
     StripPos p;
     const int nsx = (W + STRIP_W - 1) / STRIP_W;
     const int sy = wgl / nsx, sx = wgl - sy * nsx;
@@ -648,7 +670,7 @@ __device__ __forceinline__ StripPos strip_pos(int wgl, int H, int W, int srh) {
     p.hx = p.lane == 0 ? max(x0 - 1, 0) : min(x0 + STRIP_W, W - 1);
     // Row bounds are the same for every lane of a wave; saying so lets the
     // row addresses live in scalar registers.
-    p.ya = uniform((sy * STRIP_WAVES + (threadIdx.x >> 6)) * srh);
+    p.ya = uniform((sy * waves + (threadIdx.x >> 6)) * srh);
     p.yb = uniform(min(p.ya + srh, H));
     // W <= 2^28, so these fit 32 bits.
     p.xo3 = 3u * (uint32_t)p.x;
@@ -790,7 +812,7 @@ __device__ __forceinline__ void strip_walk(const ImgDesc &d, const StripPos &sp,
 // image (Eq. 9-10), s = S*_c, m = M_c.  Each lane keeps one register
 // accumulator for its current exponent run and, when E changes, adds it to
 // the workgroup's LDS bins (32-bit totals, added in pairs with 64-bit LDS
-// atomics; a workgroup covers at most 256 x 4 x 32 = 32768 px and
+// atomics; a workgroup covers at most 256 px x 128 rows = 32768 px and
 // 65025 x 32768 < 2^32, so no total wraps).  At the
 // end the workgroup adds its present bins into one of the image's int64
 // stripes with integer atomics.
@@ -813,15 +835,15 @@ __device__ __forceinline__ void flush_run(uint32_t *bins, int e, uint32_t acc[NS
 }
 
 template <int R>
-__global__ __launch_bounds__(STRIP_THREADS) void k_fit_sums(const ImgDesc *__restrict__ D, int n) {
+__global__ __launch_bounds__(1024) void k_fit_sums(const ImgDesc *__restrict__ D, int n) {
     __shared__ __align__(8) uint32_t bins[R * BIN_WORDS];
     const int i = find_img(D, n, blockIdx.x, 3);
     const ImgDesc d = desc_at(D, i);
     const int H = d.H, W = d.W;
     const int wgl = blockIdx.x - d.wg_fit;
-    for (int k = threadIdx.x; k < R * BIN_WORDS; k += STRIP_THREADS) bins[k] = 0;
+    for (int k = threadIdx.x; k < R * BIN_WORDS; k += blockDim.x) bins[k] = 0;
     __syncthreads();
-    const StripPos sp = strip_pos(wgl, H, W, d.srh_fit);
+    const StripPos sp = strip_pos(wgl, H, W, d.srh_fit, d.fit_waves);
     if (sp.ya < H) {  // uniform per wave
         uint32_t *mine = bins + (sp.lane % R) * BIN_WORDS;
         int cur = -1;
@@ -855,7 +877,7 @@ __global__ __launch_bounds__(STRIP_THREADS) void k_fit_sums(const ImgDesc *__res
     // Each copy's totals stay below 2^32 (see above); their sum is taken in
     // 64 bits.
     unsigned long long *gp = (unsigned long long *)(d.part + (int64_t)(wgl % d.nfs) * 256 * NSUM);
-    for (int e = threadIdx.x; e < 256; e += STRIP_THREADS) {
+    for (int e = threadIdx.x; e < 256; e += blockDim.x) {
         uint64_t cnt = 0;
 #pragma unroll
         for (int r = 0; r < R; ++r) cnt += bins[r * BIN_WORDS + e * 14];
@@ -1601,6 +1623,19 @@ hipError_t upload_tables(int *bad_table) {
     return hipSuccess;
 }
 
+// Self-check of recip(): compares it with IEEE division for every float whose
+// bits lie in [lo, lo + count) and counts the differences.
+__global__ __launch_bounds__(256) void k_check_recip(uint32_t lo, uint32_t count, unsigned long long *bad) {
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i >= count) return;
+    const float D = __uint_as_float(lo + i);
+    if (__float_as_uint(recip(D)) != __float_as_uint(1.0f / D)) atomicAdd(bad, 1ull);
+}
+
+void launch_check_recip(uint32_t lo, uint32_t count, unsigned long long *bad, hipStream_t s) {
+    if (count) hipLaunchKernelGGL(k_check_recip, dim3((count + 255) / 256), dim3(256), 0, s, lo, count, bad);
+}
+
 void launch_zero(const ImgDesc *d, int n, hipStream_t s) { hipLaunchKernelGGL(k_zero, dim3(n), dim3(256), 0, s, d, n); }
 void launch_keystat(const ImgDesc *d, int n, int wgs, hipStream_t s) {
     hipLaunchKernelGGL(k_keystat, dim3(wgs), dim3(KS_THREADS), 0, s, d, n);
@@ -1611,13 +1646,14 @@ void launch_tmo_base(const ImgDesc *d, int n, int wgs, bool extra, hipStream_t s
     else
         hipLaunchKernelGGL(k_tmo_base<false>, dim3(wgs), dim3(BLK_THREADS), 0, s, d, n);
 }
-void launch_fit_sums(const ImgDesc *d, int n, int wgs, int bins, hipStream_t s) {
+void launch_fit_sums(const ImgDesc *d, int n, int wgs, int bins, int waves, hipStream_t s) {
+    const dim3 block(64 * waves);
     if (bins >= 4)
-        hipLaunchKernelGGL(k_fit_sums<4>, dim3(wgs), dim3(STRIP_THREADS), 0, s, d, n);
+        hipLaunchKernelGGL(k_fit_sums<4>, dim3(wgs), block, 0, s, d, n);
     else if (bins == 2)
-        hipLaunchKernelGGL(k_fit_sums<2>, dim3(wgs), dim3(STRIP_THREADS), 0, s, d, n);
+        hipLaunchKernelGGL(k_fit_sums<2>, dim3(wgs), block, 0, s, d, n);
     else
-        hipLaunchKernelGGL(k_fit_sums<1>, dim3(wgs), dim3(STRIP_THREADS), 0, s, d, n);
+        hipLaunchKernelGGL(k_fit_sums<1>, dim3(wgs), block, 0, s, d, n);
 }
 void launch_solve(const ImgDesc *d, int n, hipStream_t s) { hipLaunchKernelGGL(k_solve, dim3(n), dim3(1024), 0, s, d, n); }
 void launch_key_total(const ImgDesc *d, int n, int64_t *out2, hipStream_t s) {

@@ -49,6 +49,7 @@ _SIGS = {
     "rdl_profile_encode": ([_vp, _vp, _i, _i, _i, _vp, _vp, _vp, _i, _vp, _vp], _i),
     "rdl_autotune": ([_vp, _vp, _i, _i, _i, _vp, _vp, _vp, _i, _vp, _vp], _i),
     "rdl_get_tuning": ([_vp, _i, _i, _vp], _i),
+    "rdl_check_recip": ([_vp, C.c_uint32, C.c_uint32, _vp, _vp], _i),
     "rdl_set_tuning": ([_vp, _i, _i, _i], _i),
     "rdl_set_model": ([_vp, _vp, C.c_size_t], _i),
     "rdl_set_estimator": ([_vp, _i], _i),
@@ -58,7 +59,7 @@ _SIGS = {
     "rdl_train_step": ([_vp, _vp, _vp, _vp, _vp, C.c_int64, C.c_int64, _i, C.c_float, _i, _vp, _vp], _i),
 }
 
-TUNE = ("fit_rows", "resid_rows", "fit_bins")
+TUNE = ("fit_rows", "resid_rows", "fit_bins", "fit_waves")
 STAGES = ("keystat", "tmo_base", "fit_sums", "solve", "resid")
 KERNELS = ("k_keystat", "k_tmo_base", "k_fit_sums", "k_solve", "k_resid")
 
@@ -236,6 +237,13 @@ class Codec:
         _chk(self._L.rdl_autotune(self._h, _ptr(rgbe), H, W, int(q), _ptr(sdr), _ptr(hdr), _ptr(resid), int(reps),
                                   best, _stream(stream)), "rdl_autotune")
         return dict(zip(TUNE, [int(v) for v in best]))
+
+    def check_recip(self, lo_bits: int, hi_bits: int, stream=None) -> int:
+        """Number of floats with bits in [lo_bits, hi_bits) whose kernel
+        reciprocal differs from IEEE division."""
+        n = C.c_uint64(0)
+        _chk(self._L.rdl_check_recip(self._h, lo_bits, hi_bits, C.byref(n), _stream(stream)), "rdl_check_recip")
+        return int(n.value)
 
     def get_tuning(self) -> dict:
         """{parameter: [value of size class floor(log2(H W)) for 0..31]}."""

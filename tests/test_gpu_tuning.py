@@ -55,12 +55,14 @@ def test_every_strip_height_matches_oracle(codec, rdl_mod, O, H, W, sig, q):
     x = synth.generate(H, W, sig, seed=1300 + H, spec_frac=0.05)
     d = _dev(x)
     table = codec.get_tuning()
-    for fit_rows, resid_rows, bins in ((2, 2, 1), (4, 4, 2), (8, 8, 4), (16, 16, 1), (32, 32, 2), (2, 32, 4),
-                                       (32, 2, 4)):
-        _say("strip rows fit", fit_rows, "resid", resid_rows, "bin copies", bins, "image", H, W)
+    shapes = ((2, 2, 1, 4), (4, 4, 2, 8), (8, 8, 4, 16), (16, 16, 1, 4), (32, 32, 2, 8), (2, 32, 4, 16),
+              (32, 2, 4, 4), (32, 8, 2, 16))   # the last is clamped to 8 rows x 16 waves
+    for fit_rows, resid_rows, bins, waves in shapes:
+        _say("fit rows", fit_rows, "waves", waves, "bin copies", bins, "resid rows", resid_rows, "image", H, W)
         table["fit_rows"][_size_class(H, W)] = fit_rows
         table["resid_rows"][_size_class(H, W)] = resid_rows
         table["fit_bins"][_size_class(H, W)] = bins
+        table["fit_waves"][_size_class(H, W)] = waves
         codec.set_tuning(table)
         out = codec.alloc_outputs(H, W)
         for t in out:
@@ -78,9 +80,9 @@ def test_autotune_and_table_round_trip(codec, rdl_mod, O, tmp_path):
     out = codec.alloc_outputs(H, W)
     _say("autotune", H, W)
     best = codec.autotune(d, q, out, reps=3)
-    assert set(best) == {"fit_rows", "resid_rows", "fit_bins"}
+    assert set(best) == {"fit_rows", "resid_rows", "fit_bins", "fit_waves"}
     assert best["fit_rows"] in (2, 4, 8, 16, 32) and best["resid_rows"] in (2, 4, 8, 16, 32)
-    assert best["fit_bins"] in (1, 2, 4)
+    assert best["fit_bins"] in (1, 2, 4) and best["fit_waves"] in (4, 8, 16)
     torch.cuda.synchronize()
     _check(codec, rdl_mod, O, x, q, out)
     table = codec.get_tuning()
@@ -115,7 +117,12 @@ def test_profile_encode_leaves_correct_outputs(codec, rdl_mod, O):
 
 def test_tuning_table_rejects_bad_shapes(codec, rdl_mod):
     t = codec.get_tuning()
-    assert t["fit_rows"] == [16] * 32 and t["resid_rows"] == [8] * 32 and t["fit_bins"] == [4] * 32
+    assert t["resid_rows"] == [8] * 32 and t["fit_bins"] == [2] * 32
+    assert t["fit_waves"] == [4] * 20 + [8] * 2 + [16] * 10
+    assert t["fit_rows"] == [16] * 22 + [8] * 10
+    for bad in (1, 2, 3, 32):
+        with pytest.raises(rdl_mod.RdlError):
+            codec.set_tuning({"fit_waves": [bad] * 32})
     for bad in (0, 1, 3, 12, 64):
         with pytest.raises(rdl_mod.RdlError):
             codec.set_tuning({"resid_rows": [bad] * 32})
@@ -125,6 +132,13 @@ def test_tuning_table_rejects_bad_shapes(codec, rdl_mod):
     L, h = codec._L, codec._h
     assert L.rdl_set_tuning(h, 0, 32, 4) == rdl_mod.RDL_EINVAL
     assert L.rdl_set_tuning(h, 0, -1, 4) == rdl_mod.RDL_EINVAL
-    assert L.rdl_set_tuning(h, 3, 0, 4) == rdl_mod.RDL_EINVAL
+    assert L.rdl_set_tuning(h, 4, 0, 4) == rdl_mod.RDL_EINVAL
     assert L.rdl_set_tuning(h, -1, 0, 4) == rdl_mod.RDL_EINVAL
     assert codec.get_tuning() == t
+
+
+def test_reciprocal_equals_ieee_division_on_the_operator_domain(codec):
+    """The tone map's reciprocal (hardware estimate + one fused Newton step)
+    equals IEEE 1/D for every float D in [1, 2^47), all 394M of them."""
+    _say("reciprocal check")
+    assert codec.check_recip(0x3F800000, (127 + 47) << 23) == 0

@@ -10,17 +10,17 @@ import pytest
 STRIP_W, STRIP_WAVES, WALK_CH = 256, 4, 4
 
 
-def walk_accesses(H, W, srh, sdr_base, rgbe_base, resid_base):
+def walk_accesses(H, W, srh, sdr_base, rgbe_base, resid_base, waves=STRIP_WAVES):
     """Yields (buffer, first byte, last byte + 1) for every access."""
     nsx = (W + STRIP_W - 1) // STRIP_W
-    nwg = ((H + srh * STRIP_WAVES - 1) // (srh * STRIP_WAVES)) * nsx
+    nwg = ((H + srh * waves - 1) // (srh * waves)) * nsx
     end = sdr_base + 3 * H * W
     npx = H * W
     for wgl in range(nwg):
         sy, sx = divmod(wgl, nsx)
         x0 = sx * STRIP_W
-        for wave in range(STRIP_WAVES):
-            ya = (sy * STRIP_WAVES + wave) * srh
+        for wave in range(waves):
+            ya = (sy * waves + wave) * srh
             if ya >= H:
                 continue
             yb = min(ya + srh, H)
@@ -92,12 +92,12 @@ SHAPES = [(1, 1), (1, 4), (1, 5), (2, 7), (7, 9), (9, 17), (5, 256), (3, 257), (
 
 
 @pytest.mark.parametrize("H,W", SHAPES, ids=["%dx%d" % s for s in SHAPES])
-@pytest.mark.parametrize("srh", [2, 8, 32])
-def test_strip_walk_stays_inside_buffers(H, W, srh):
+@pytest.mark.parametrize("srh,waves", [(2, 4), (8, 4), (32, 4), (8, 16), (16, 8)])
+def test_strip_walk_stays_inside_buffers(H, W, srh, waves):
     bases = {"sdr": 4096, "rgbe": 1 << 20, "resid": 1 << 24}
     sizes = {"sdr": 3 * H * W, "rgbe": 4 * H * W, "resid": 7 * H * W}
     for sdr_off in (0, 4, 8):   # S buffers start on dword boundaries (the API requires it)
         for res_off in (0, 2):
             b = dict(bases, sdr=bases["sdr"] + sdr_off, resid=bases["resid"] + res_off)
-            for buf, lo, hi in walk_accesses(H, W, srh, b["sdr"], b["rgbe"], b["resid"]):
+            for buf, lo, hi in walk_accesses(H, W, srh, b["sdr"], b["rgbe"], b["resid"], waves):
                 assert b[buf] <= lo and hi <= b[buf] + sizes[buf], (buf, lo - b[buf], hi - b[buf], sizes[buf])
