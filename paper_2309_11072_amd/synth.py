@@ -23,6 +23,7 @@ Recipe (per image):
 from __future__ import annotations
 
 import hashlib
+import math
 from dataclasses import dataclass
 
 import numpy as np
@@ -81,6 +82,73 @@ def generate(H: int, W: int, sigma_l: float, seed: int, spec_frac: float = 0.0,
     return pack_rgbe(f)
 
 
+def generate_torch(H: int, W: int, sigma_l: float, seed: int, spec_frac: float = 0.0, spec_stops: float = 10.0,
+                   smooth: float = 8.0, cell: int = 32, device="cuda"):
+    """The same recipe drawn with torch's seeded generator on `device` (for
+    benchmark batches of hundreds of megapixels, where the numpy generator
+    would take minutes).  The random streams differ from generate(); the
+    distributions, the smoothing (Gaussian truncated at 4 sigma, reflected
+    borders where the image is large enough, replicated otherwise), the chroma
+    grid and the RGBE packing are the same.  Returns uint8 [H, W, 4] on
+    `device`."""
+    import torch
+    import torch.nn.functional as F
+    g = torch.Generator(device=device).manual_seed(int(seed))
+    z = torch.randn((1, 1, H, W), generator=g, device=device, dtype=torch.float32)
+    r = int(4 * smooth + 0.5)
+    k = [math.exp(-0.5 * (i / smooth) ** 2) for i in range(-r, r + 1)]
+    k = [v / sum(k) for v in k]
+    mode_x = "reflect" if W > r else "replicate"
+    mode_y = "reflect" if H > r else "replicate"
+    # Separable convolution as a sum of shifted copies (plain elementwise
+    # work, no convolution library).
+    zp = F.pad(z, (r, r, 0, 0), mode=mode_x)[0, 0]
+    acc = torch.zeros((H, W), device=device, dtype=torch.float32)
+    for i, v in enumerate(k):
+        acc += v * zp[:, i:i + W]
+    zp = F.pad(acc[None, None], (0, 0, r, r), mode=mode_y)[0, 0]
+    acc = torch.zeros((H, W), device=device, dtype=torch.float32)
+    for i, v in enumerate(k):
+        acc += v * zp[i:i + H, :]
+    z = acc.double()
+    del zp, acc
+    z = z - z.mean()
+    sd = float(z.std(unbiased=False))
+    z = z / sd if sd > 1e-6 else torch.zeros_like(z)
+    log2l = sigma_l * z
+    gh, gw = H // cell + 2, W // cell + 2
+    grid = 0.5 + 1.5 * torch.rand((3, gh, gw), generator=g, device=device, dtype=torch.float64)
+    gy = (torch.arange(H, device=device, dtype=torch.float64) + 0.5) / cell
+    gx = (torch.arange(W, device=device, dtype=torch.float64) + 0.5) / cell
+    y0, x0 = gy.floor().long(), gx.floor().long()
+    wy, wx = (gy - y0)[:, None], (gx - x0)[None, :]
+    rho = torch.empty((3, H, W), device=device, dtype=torch.float64)
+    for c in range(3):
+        a = grid[c][y0][:, x0]
+        b = grid[c][y0][:, x0 + 1]
+        cc = grid[c][y0 + 1][:, x0]
+        d = grid[c][y0 + 1][:, x0 + 1]
+        rho[c] = (a * (1 - wx) + b * wx) * (1 - wy) + (cc * (1 - wx) + d * wx) * wy
+    rho /= (0.2126 * rho[0] + 0.7152 * rho[1] + 0.0722 * rho[2])[None]
+    f = torch.exp2(log2l)[None] * rho
+    del rho, z, log2l
+    if spec_frac > 0:
+        mask = torch.rand((H, W), generator=g, device=device) < spec_frac
+        f = torch.where(mask[None], f * 2.0 ** spec_stops, f)
+    v = f.amax(dim=0)
+    _, e = torch.frexp(v)
+    lit = v >= 2.0 ** -128
+    E = torch.where(lit, e + 128, torch.zeros_like(e))
+    if bool((E > 255).any()):
+        raise ValueError("value too large for RGBE")
+    M = torch.floor(torch.ldexp(f, (8 - e)[None].double()))
+    M = torch.where(lit[None], M, torch.zeros_like(M))
+    out = torch.empty((H, W, 4), device=device, dtype=torch.uint8)
+    out[..., :3] = M.permute(1, 2, 0).to(torch.uint8)
+    out[..., 3] = E.to(torch.uint8)
+    return out
+
+
 def sha256(a: np.ndarray) -> str:
     return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
 
@@ -96,6 +164,9 @@ class ImageSpec:
 
     def make(self) -> np.ndarray:
         return generate(self.H, self.W, self.sigma_l, self.seed, self.spec_frac)
+
+    def make_torch(self, device="cuda"):
+        return generate_torch(self.H, self.W, self.sigma_l, self.seed, self.spec_frac, device=device)
 
 
 ASPECTS = (4 / 3, 16 / 9, 1.0)

@@ -503,6 +503,25 @@ def test_generator_seeded():
     assert np.array_equal(a, b) and not np.array_equal(a, c)
 
 
+def test_torch_generator_same_recipe():
+    """The torch generator (for large benchmark batches) packs canonical RGBE
+    the same way and draws the same distributions as the numpy one: exponent
+    mean and spread, speculars, mantissa range."""
+    a = synth.generate_torch(240, 320, 3.0, 7, 0.05, device="cpu").numpy()
+    b = synth.generate(240, 320, 3.0, 7, 0.05)
+    M = a[..., :3].astype(np.float64)
+    E = a[..., 3].astype(np.int64)
+    f = (M + 0.5) / 256 * np.exp2(E - 128)[..., None]
+    f[E == 0] = 0
+    assert np.array_equal(synth.pack_rgbe(f), a)
+    for x in (a, b):
+        assert np.all(x[..., :3].max(-1)[x[..., 3] > 0] >= 128)
+    Ea, Eb = a[..., 3].astype(float), b[..., 3].astype(float)
+    assert abs(Ea.mean() - Eb.mean()) < 0.5 and abs(Ea.std() - Eb.std()) < 0.5
+    assert np.array_equal(synth.generate_torch(40, 50, 2.0, 3, device="cpu").numpy(),
+                          synth.generate_torch(40, 50, 2.0, 3, device="cpu").numpy())
+
+
 # ---------------------------------------------------------------- learned estimator
 def _model(**over):
     from paper_2309_11072_amd import model_format
