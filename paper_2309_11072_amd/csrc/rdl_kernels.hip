@@ -29,10 +29,10 @@ __device__ int32_t g_log2f[4096];   // round(2^16 log2(1 + (i + 0.5)/4096))
 __device__ float g_exp2h[256];      // fl32(2^(j/256))
 __device__ float g_exp2l[256];      // fl32(2^(j/65536))
 __device__ float g_thr[257];        // [k] = fl32(((k - 0.5)/255)^2.2), [256] = +inf
-__device__ uint8_t g_glut[GAMMA_LUT_N];  // #{k : thr[k] <= bucket start}
+__device__ __align__(16) uint8_t g_glut[GAMMA_LUT_N];  // #{k : thr[k] <= bucket start}
 
 // ITU-T T.81 Annex K, Tables K.1 and K.2 (natural order).
-__constant__ int c_annex_k[2][64] = {
+constexpr int ANNEX_K[2][64] = {
     {16, 11, 10, 16, 24, 40, 51, 61,     12, 12, 14, 19, 26, 58, 60, 55,
      14, 13, 16, 24, 40, 57, 69, 56,     14, 17, 22, 29, 51, 87, 80, 62,
      18, 22, 37, 56, 68, 109, 103, 77,   24, 35, 55, 64, 81, 104, 113, 92,
@@ -41,6 +41,11 @@ __constant__ int c_annex_k[2][64] = {
      24, 26, 56, 99, 99, 99, 99, 99, 47, 66, 99, 99, 99, 99, 99, 99,
      99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99,
      99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99}};
+
+// Quantiser constants of every quality, filled once by upload_tables():
+// g_qm[q - 1][t][e] = M | Q << 24 with Q the IJG-scaled Annex K entry and
+// M = ceil(2^20 / Q).
+__device__ uint32_t g_qm[100][2][64];
 
 // DCT basis K[u][x] = round(2^13 c_u cos((2x+1) u pi / 16)), c_0 = 1/sqrt(8),
 // c_u = 1/2: the 8-point DCT-II scaled by 2^13.
@@ -118,9 +123,13 @@ __device__ __forceinline__ int find_img(const ImgDesc *__restrict__ D, int n, in
     return uniform(lo);
 }
 
-__device__ __forceinline__ int64_t floor_div64(int64_t a, int64_t b) {  // b > 0
-    int64_t q = a / b;
-    if ((a % b) != 0 && a < 0) q -= 1;
+// floor(a / b) for b > 0: a float64 quotient is within a few units of it
+// (abs(a) < 2^55 here), and the remainder corrects it exactly.
+__device__ __forceinline__ int64_t floor_div64(int64_t a, int64_t b) {
+    int64_t q = (int64_t)floor((double)a / (double)b);
+    int64_t r = a - q * b;
+    for (int k = 0; k < 8 && r < 0; ++k) { q -= 1; r += b; }
+    for (int k = 0; k < 8 && r >= b; ++k) { q += 1; r -= b; }
     return q;
 }
 
@@ -191,7 +200,12 @@ __global__ __launch_bounds__(KS_THREADS) void k_keystat(const ImgDesc *__restric
     const int64_t base = (int64_t)wgl * KS_PX_PER_WG;
     const uint32_t *p32 = (const uint32_t *)d.rgbe;
     const bool al = (reinterpret_cast<uintptr_t>(p32) & 15) == 0;
-    // Pixel loads first (they do not depend on the table), then the table.
+    // The table's loads first (L2 hits), then the pixel loads; the table is
+    // stored to LDS after waiting for its own loads only, so each chunk of
+    // pixels can be summed as soon as it arrives.
+    int32_t tl[4096 / KS_THREADS];
+#pragma unroll
+    for (int k = 0; k < 4096 / KS_THREADS; ++k) tl[k] = g_log2f[k * KS_THREADS + threadIdx.x];
     constexpr int NIT = KS_PX_PER_WG / (KS_THREADS * 4);
     uint4 v[NIT];
 #pragma unroll
@@ -206,7 +220,8 @@ __global__ __launch_bounds__(KS_THREADS) void k_keystat(const ImgDesc *__restric
             v[it].w = px + 3 < npx ? p32[px + 3] : 0u;
         }
     }
-    for (int k = threadIdx.x; k < 4096; k += KS_THREADS) s_log2f[k] = (uint16_t)g_log2f[k];
+#pragma unroll
+    for (int k = 0; k < 4096 / KS_THREADS; ++k) s_log2f[k * KS_THREADS + threadIdx.x] = (uint16_t)tl[k];
     __syncthreads();
     int64_t L = 0;
     int cnt = 0;
@@ -363,7 +378,7 @@ __global__ __launch_bounds__(BLK_THREADS) void k_tmo_base(const ImgDesc *__restr
     // 1 and 3) or column (phase 2) r = t / BLK_WG; two LDS transposes join the
     // phases.  Slot stride 33 words keeps every half-wave access conflict-free.
     // EXTRA also writes the tone-mapped SDRI and the quantised coefficients.
-    __shared__ uint8_t s_lut[GAMMA_LUT_N];
+    __shared__ __align__(16) uint8_t s_lut[GAMMA_LUT_N];
     __shared__ float s_thr[257];
     __shared__ uint32_t s_QM[2][64];
     __shared__ uint32_t s_X[3][BLK_WG][33];
@@ -371,17 +386,10 @@ __global__ __launch_bounds__(BLK_THREADS) void k_tmo_base(const ImgDesc *__restr
     const int i = find_img(D, n, blockIdx.x, 1);
     const ImgDesc d = desc_at(D, i);
     const int H = d.H, W = d.W;
-    for (int k = threadIdx.x; k < GAMMA_LUT_N; k += BLK_THREADS) s_lut[k] = g_glut[k];
+    for (int k = threadIdx.x; k < GAMMA_LUT_N / 4; k += BLK_THREADS)
+        reinterpret_cast<uint32_t *>(s_lut)[k] = reinterpret_cast<const uint32_t *>(g_glut)[k];
     for (int k = threadIdx.x; k < 257; k += BLK_THREADS) s_thr[k] = g_thr[k];
-    if (threadIdx.x < 128) {
-        // IJG quality scaling of the Annex K tables.
-        const int t = threadIdx.x >> 6, e = threadIdx.x & 63;
-        const int q = d.q;
-        const int s = q < 50 ? 5000 / q : 200 - 2 * q;
-        int Qv = (c_annex_k[t][e] * s + 50) / 100;
-        Qv = min(max(Qv, 1), 255);
-        s_QM[t][e] = (((1u << 20) + (uint32_t)Qv - 1u) / (uint32_t)Qv) | ((uint32_t)Qv << 24);
-    }
+    if (threadIdx.x < 128) (&s_QM[0][0])[threadIdx.x] = (&g_qm[d.q - 1][0][0])[threadIdx.x];
     if (threadIdx.x == 0) {
         int k_img, f_key;
         float sigma;
@@ -1614,7 +1622,17 @@ hipError_t upload_tables(int *bad_table) {
     // Below the first bucket every code is 0; from the last bucket up every
     // code is 255 or 254 + one compare.
     if (thr[1] <= ldexpf(1.0f, -20)) *bad_table = 1;
+    static uint32_t qm[100][2][64];
+    for (int q = 1; q <= 100; ++q) {
+        const int sc = q < 50 ? 5000 / q : 200 - 2 * q;  // IJG quality scaling
+        for (int t = 0; t < 2; ++t)
+            for (int k = 0; k < 64; ++k) {
+                const uint32_t Q = (uint32_t)std::min(std::max((ANNEX_K[t][k] * sc + 50) / 100, 1), 255);
+                qm[q - 1][t][k] = (((1u << 20) + Q - 1u) / Q) | (Q << 24);
+            }
+    }
     hipError_t e;
+    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(g_qm), qm, sizeof qm)) != hipSuccess) return e;
     if ((e = hipMemcpyToSymbol(HIP_SYMBOL(g_log2f), log2f, sizeof log2f)) != hipSuccess) return e;
     if ((e = hipMemcpyToSymbol(HIP_SYMBOL(g_exp2h), eh, sizeof eh)) != hipSuccess) return e;
     if ((e = hipMemcpyToSymbol(HIP_SYMBOL(g_exp2l), el, sizeof el)) != hipSuccess) return e;
