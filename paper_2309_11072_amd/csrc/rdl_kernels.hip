@@ -900,11 +900,13 @@ __global__ __launch_bounds__(1024) void k_fit_sums(const ImgDesc *__restrict__ D
     }
 }
 // ---------------------------------------------------------------------------
-// K4 solve: one workgroup per image, one lane per exponent value.  The lane
-// first adds up the image's sum stripes (and writes the totals), then solves
-// the least-squares line exactly in 128-bit integers (Eq. 6-7 / 9-10) with
+// K4 solve: one workgroup per image.  Three lanes per exponent value add up
+// the image's sum stripes (and write the totals) while one more lane fills
+// the header's key fields; then one lane per (channel, exponent) solves the
+// least-squares line exactly in 128-bit integers (Eq. 6-7 / 9-10) with
 // fixed-point rounding: a_q = rhu(2^22 num / den),
-// b_q = rhu((2^22 Sm - a_q Ss) / (2^8 n)).
+// b_q = rhu((2^22 Sm - a_q Ss) / (2^8 n)), while the last four waves mark the
+// present exponents.
 // ---------------------------------------------------------------------------
 typedef __int128 i128;
 
@@ -929,60 +931,38 @@ __device__ i128 floor_div128(i128 N, i128 D) {
 __device__ __forceinline__ i128 rhu128(i128 x, i128 y) { return floor_div128(2 * x + y, 2 * y); }
 
 __global__ __launch_bounds__(1024) void k_solve(const ImgDesc *__restrict__ D, int n) {
-    __shared__ int64_t s_b[3][256][NSUM];
+    __shared__ int64_t s_b[256][NSUM];
     __shared__ int s_cnt[4];
     const int i = blockIdx.x;
     const ImgDesc d = desc_at(D, i);
     rdl_header *h = d.hdr;
-    const int e = threadIdx.x & 255, g = threadIdx.x >> 8;
-    // Add up the stripes (lane group g takes stripes g, g+4, ...) and leave
-    // them zeroed for the next launch.
-    int64_t b[NSUM];
+    const int t = threadIdx.x;
+    if (t < 3 * 256) {
+        // Thread (g, e) adds values k = g, g + 3, ... of exponent e over the
+        // image's stripes (all loads independent), leaves the stripes zero
+        // for the next launch and keeps the totals.
+        const int e = t & 255, g = t >> 8;
+        int64_t v[5] = {0, 0, 0, 0, 0};
+        for (int st = 0; st < d.nfs; ++st) {
+            int64_t *p = d.part + ((int64_t)st * 256 + e) * NSUM;
 #pragma unroll
-    for (int k = 0; k < NSUM; ++k) b[k] = 0;
-    for (int st = g; st < d.nfs; st += 4) {
-        int64_t *p = d.part + ((int64_t)st * 256 + e) * NSUM;
-#pragma unroll
-        for (int k = 0; k < NSUM; ++k) {
-            b[k] += p[k];
-            p[k] = 0;
+            for (int j = 0; j < 5; ++j)
+                if (g + 3 * j < NSUM) v[j] += p[g + 3 * j];
         }
-    }
-    if (g > 0) {
+        for (int st = 0; st < d.nfs; ++st) {
+            int64_t *p = d.part + ((int64_t)st * 256 + e) * NSUM;
 #pragma unroll
-        for (int k = 0; k < NSUM; ++k) s_b[g - 1][e][k] = b[k];
-    }
-    __syncthreads();
-    bool present = false;
-    if (g == 0) {
+            for (int j = 0; j < 5; ++j)
+                if (g + 3 * j < NSUM) p[g + 3 * j] = 0;
+        }
 #pragma unroll
-        for (int k = 0; k < NSUM; ++k) b[k] += s_b[0][e][k] + s_b[1][e][k] + s_b[2][e][k];
-#pragma unroll
-        for (int k = 0; k < NSUM; ++k) d.sums[e * NSUM + k] = b[k];
-        const i128 nn = b[0];
-        present = nn > 0;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            int32_t aq = 0, bq = 0;
-            if (nn > 0) {
-                const i128 Ss = b[1 + 4 * c], Sm = b[2 + 4 * c], Sss = b[3 + 4 * c], Ssm = b[4 + 4 * c];
-                const i128 num = nn * Ssm - Ss * Sm;
-                const i128 den = nn * Sss - Ss * Ss;
-                const i128 a = den == 0 ? (i128)0 : rhu128(num * ((i128)1 << 22), den);
-                const i128 bb = rhu128(Sm * ((i128)1 << 22) - a * Ss, nn * 256);
-                aq = (int32_t)a;
-                bq = (int32_t)bb;
+        for (int j = 0; j < 5; ++j)
+            if (g + 3 * j < NSUM) {
+                s_b[e][g + 3 * j] = v[j];
+                d.sums[e * NSUM + g + 3 * j] = v[j];
             }
-            h->a_q[c][e] = aq;
-            h->b_q[c][e] = bq;
-            h->flag[c][e] = 0;
-        }
-        h->present[e] = present;
-        const unsigned long long bal = __ballot(present);
-        if ((e & 63) == 0) s_cnt[e >> 6] = __popcll(bal);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
+    } else if (t == 3 * 256) {
+        // Meanwhile one lane of the last waves fills the key fields.
         int k_img = 0, f_key = 0;
         float sigma = 0.0f;
         int64_t L = 0, N = 0;
@@ -1002,9 +982,36 @@ __global__ __launch_bounds__(1024) void k_solve(const ImgDesc *__restrict__ D, i
         h->lambda_sum = L;
         h->n_lit = N;
         h->estimator = 0;
-        h->n_regions = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
         h->model_hash = 0;
     }
+    __syncthreads();
+    if (t < 3 * 256) {
+        // One lane per (channel, exponent): the least-squares line in exact
+        // 128-bit integers with fixed-point rounding.
+        const int c = t >> 8, e = t & 255;
+        const i128 nn = s_b[e][0];
+        int32_t aq = 0, bq = 0;
+        if (nn > 0) {
+            const i128 Ss = s_b[e][1 + 4 * c], Sm = s_b[e][2 + 4 * c], Sss = s_b[e][3 + 4 * c], Ssm = s_b[e][4 + 4 * c];
+            const i128 num = nn * Ssm - Ss * Sm;
+            const i128 den = nn * Sss - Ss * Ss;
+            const i128 a = den == 0 ? (i128)0 : rhu128(num * ((i128)1 << 22), den);
+            const i128 bb = rhu128(Sm * ((i128)1 << 22) - a * Ss, nn * 256);
+            aq = (int32_t)a;
+            bq = (int32_t)bb;
+        }
+        h->a_q[c][e] = aq;
+        h->b_q[c][e] = bq;
+        h->flag[c][e] = 0;
+    } else {
+        const int e = t - 3 * 256;
+        const bool present = s_b[e][0] > 0;
+        h->present[e] = present;
+        const unsigned long long bal = __ballot(present);
+        if ((e & 63) == 0) s_cnt[e >> 6] = __popcll(bal);
+    }
+    __syncthreads();
+    if (t == 0) h->n_regions = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
 }
 
 // ---------------------------------------------------------------------------
