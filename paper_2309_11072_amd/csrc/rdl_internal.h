@@ -50,7 +50,7 @@ struct ImgDesc {
     uint8_t *resid;        // 7*H*W
     int64_t *ks;           // [nks][2] partial (Lambda, N'), summed by readers
     int64_t *sums;         // [256][13] regression sums (written by k_solve)
-    int64_t *part;         // [nfs][256][13] partial regression sums
+    int64_t *part;         // [nfs][13][256] partial regression sums (value-major)
     int32_t *status;       // decode only, optional
     uint8_t *out_rgbe;     // decode only
     int64_t *hist;         // [3][511] residual histograms

@@ -895,7 +895,7 @@ __global__ __launch_bounds__(1024) void k_fit_sums(const ImgDesc *__restrict__ D
             uint64_t v = 0;
 #pragma unroll
             for (int r = 0; r < R; ++r) v += bins[r * BIN_WORDS + e * 14 + k];
-            if (v) atomicAdd(gp + e * NSUM + k, (unsigned long long)v);
+            if (v) atomicAdd(gp + k * 256 + e, (unsigned long long)v);
         }
     }
 }
@@ -943,24 +943,34 @@ __global__ __launch_bounds__(1024) void k_solve(const ImgDesc *__restrict__ D, i
         // for the next launch and keeps the totals.
         const int e = t & 255, g = t >> 8;
         int64_t v[5] = {0, 0, 0, 0, 0};
-        for (int st = 0; st < d.nfs; ++st) {
-            int64_t *p = d.part + ((int64_t)st * 256 + e) * NSUM;
+        // Stripes are laid out [stripe][value][exponent], so the lanes of a
+        // wave read and clear contiguous words.  Every load is in flight
+        // before the first is added: branch-free over the largest stripe
+        // count, stripes past the image's count re-read its last one and are
+        // masked out of the sum.
+        int64_t w[FIT_STRIPES][5];
 #pragma unroll
-            for (int j = 0; j < 5; ++j)
-                if (g + 3 * j < NSUM) v[j] += p[g + 3 * j];
+        for (int st = 0; st < FIT_STRIPES; ++st) {
+            const int64_t *p = d.part + (int64_t)min(st, d.nfs - 1) * NSUM * 256 + e;
+#pragma unroll
+            for (int j = 0; j < 5; ++j) w[st][j] = g + 3 * j < NSUM ? p[(g + 3 * j) * 256] : 0;
         }
-        for (int st = 0; st < d.nfs; ++st) {
-            int64_t *p = d.part + ((int64_t)st * 256 + e) * NSUM;
 #pragma unroll
-            for (int j = 0; j < 5; ++j)
-                if (g + 3 * j < NSUM) p[g + 3 * j] = 0;
+        for (int st = 0; st < FIT_STRIPES; ++st)
+#pragma unroll
+            for (int j = 0; j < 5; ++j) v[j] += st < d.nfs ? w[st][j] : 0;
+#pragma unroll
+        for (int st = 0; st < FIT_STRIPES; ++st) {
+            if (st < d.nfs) {
+                int64_t *p = d.part + (int64_t)st * NSUM * 256 + e;
+#pragma unroll
+                for (int j = 0; j < 5; ++j)
+                    if (g + 3 * j < NSUM) p[(g + 3 * j) * 256] = 0;
+            }
         }
 #pragma unroll
         for (int j = 0; j < 5; ++j)
-            if (g + 3 * j < NSUM) {
-                s_b[e][g + 3 * j] = v[j];
-                d.sums[e * NSUM + g + 3 * j] = v[j];
-            }
+            if (g + 3 * j < NSUM) s_b[e][g + 3 * j] = v[j];
     } else if (t == 3 * 256) {
         // Meanwhile one lane of the last waves fills the key fields.
         int k_img = 0, f_key = 0;
@@ -985,6 +995,9 @@ __global__ __launch_bounds__(1024) void k_solve(const ImgDesc *__restrict__ D, i
         h->model_hash = 0;
     }
     __syncthreads();
+    // The totals, [256][13] as the stage entry point documents them, written
+    // from LDS in order.
+    for (int k = t; k < 256 * NSUM; k += 1024) d.sums[k] = (&s_b[0][0])[k];
     if (t < 3 * 256) {
         // One lane per (channel, exponent): the least-squares line in exact
         // 128-bit integers with fixed-point rounding.
