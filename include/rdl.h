@@ -97,7 +97,9 @@ int rdl_header_validate(const rdl_header *host_hdr, int H, int W);
  * rgbe: H*W*4 bytes; out_sdr: H*W*3; out_coeffs: one rdl_header; out_resid:
  * rdl_resid_bytes(H, W).  1 <= H, W; W <= 2^28; H*W < 2^31; 1 <= q <= 100.
  * rgbe, out_sdr and out_coeffs start on 4-byte boundaries, out_resid on a
- * 2-byte one.  Buffers must not overlap.  RDL_EINVAL on a bad argument. */
+ * 2-byte one.  Buffers must not overlap.  RDL_EINVAL on a bad argument.
+ * This is rdl_encode_batch with one image: plans and launch modes (below)
+ * apply to it the same way. */
 int rdl_encode_enh(rdl_ctx *ctx, const uint8_t *rgbe, int H, int W, int q, uint8_t *out_sdr,
                    rdl_header *out_coeffs, void *out_resid, void *stream);
 
@@ -114,10 +116,16 @@ int rdl_decode_enh(rdl_ctx *ctx, const uint8_t *sdr, const rdl_header *coeffs, c
 
 /* Batched encoder: n images of any sizes and qualities in one pass per stage
  * (every stage kernel walks a flattened tile space over all images).  imgs is
- * a HOST array of n descriptors.  The first call for a given set of buffers
- * captures the stage kernels in a HIP graph; later calls with the same
- * descriptors replay it.  Each image is encoded exactly as rdl_encode_enh
- * would encode it. */
+ * a HOST array of n descriptors.  Each image is encoded exactly as
+ * rdl_encode_enh would encode it.
+ *
+ * The first call for a given set of descriptors (buffers, sizes, qualities,
+ * launch shapes, model) builds a plan for it: a device copy of the descriptor
+ * table and scratch accumulators of its own (hipMalloc, synchronous).  Later
+ * calls with the same descriptors reuse it and only enqueue the stage
+ * kernels.  The context keeps the 8 most recent plans; building a ninth
+ * synchronises the device and frees the oldest.  Calls that share a plan
+ * share its scratch, so they must not overlap (same stream, or ordered). */
 typedef struct rdl_image {
     const uint8_t *rgbe;
     int32_t H, W, q;
@@ -126,6 +134,16 @@ typedef struct rdl_image {
     void *resid;
 } rdl_image;
 int rdl_encode_batch(rdl_ctx *ctx, const rdl_image *imgs, int n, void *stream);
+
+/* How the encoder's stage kernels are enqueued.  RDL_LAUNCH_DIRECT (the
+ * default): one launch per stage on the caller's stream.  RDL_LAUNCH_GRAPH:
+ * the stages of a plan are captured in a HIP graph at its first use and the
+ * graph is launched on every call.  With five stage kernels per encode the
+ * direct launches are the faster choice (a graph launch costs more host time
+ * than the five launches it replaces); the graph mode is for callers that
+ * prefer one launch per encode.  Returns RDL_EINVAL for any other mode. */
+enum { RDL_LAUNCH_DIRECT = 0, RDL_LAUNCH_GRAPH = 1 };
+int rdl_set_launch_mode(rdl_ctx *ctx, int mode);
 
 /* ---- Learned mantissa estimator (an extension beyond the paper, whose
  * estimator needs no learning, Sec. I) ----
@@ -239,7 +257,7 @@ int rdl_profile_encode(rdl_ctx *ctx, const uint8_t *rgbe, int H, int W, int q, u
  * rows (4 waves).  A batch uses each image's own class for
  * the rows; the fit's waves and bin copies are one per launch, its largest
  * image's, and a fit workgroup spans at most 128 rows (waves x rows; larger
- * row counts are clamped).  Captured graphs are keyed on the shapes, so a
+ * row counts are clamped).  Encoder plans are keyed on the shapes, so a
  * change takes effect at the next call. */
 enum {
     RDL_TUNE_FIT_ROWS = 0,   /* rows per wave of the fit (k_fit_sums)         */

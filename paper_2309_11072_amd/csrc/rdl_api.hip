@@ -18,8 +18,11 @@
 
 using namespace rdl;
 
-struct GraphEntry {
-    std::vector<ImgDesc> key;  // descriptors the graph was captured for
+// Everything the encoder needs for one set of image buffers: the bound
+// descriptor table and the scratch accumulators (left zero by every encode),
+// plus the captured graph in graph launch mode.
+struct Plan {
+    std::vector<ImgDesc> key;  // descriptors the plan was built for
     ImgDesc *d_desc = nullptr;
     int64_t *d_scratch = nullptr;
     uint8_t *d_ml = nullptr;      // learned path only
@@ -29,21 +32,17 @@ struct GraphEntry {
 
 struct rdl_ctx {
     int device = 0;
-    // scratch for direct (uncaptured) launches
+    // descriptor table and scratch of the stage entry points and the profiler
     ImgDesc *d_desc = nullptr;
     size_t desc_cap = 0;
     int64_t *d_scratch = nullptr;
     size_t scratch_cap = 0;  // images
-    std::vector<GraphEntry> graphs;  // captured encoders, oldest first
-    std::vector<ImgDesc> last_key;   // descriptors of the last direct launch
+    std::vector<Plan> plans;  // encoder plans, oldest first
+    int launch_mode = RDL_LAUNCH_DIRECT;
     // learned estimator
     uint8_t *d_model = nullptr;
     uint64_t model_hash = 0;
     int estimator = 0;
-    uint8_t *d_ml = nullptr;  // direct launches: learned estimates
-    size_t ml_cap = 0;        // bytes
-    uint32_t *d_lhist = nullptr;
-    size_t lhist_cap = 0;     // images
     // training scratch: per-workgroup gradient partials
     float *d_part = nullptr;
     size_t part_cap = 0;      // floats
@@ -55,7 +54,7 @@ struct rdl_ctx {
 namespace {
 
 thread_local char g_err[256] = "";
-constexpr size_t kMaxGraphs = 8;
+constexpr size_t kMaxPlans = 8;
 
 struct DeviceGuard {
     int prev = -1;
@@ -111,27 +110,6 @@ struct Grid {
     int64_t fit_px = -1;
 };
 
-int ensure_learn_scratch(rdl_ctx *c, size_t ml_bytes, size_t n) {
-    if (ml_bytes > c->ml_cap) {
-        if (c->d_ml) HIPCHK(hipFree(c->d_ml));
-        c->d_ml = nullptr;
-        c->ml_cap = 0;
-        HIPCHK(hipMalloc(&c->d_ml, ml_bytes));
-        c->ml_cap = ml_bytes;
-    }
-    if (n > c->lhist_cap) {
-        if (c->d_lhist) HIPCHK(hipFree(c->d_lhist));
-        c->d_lhist = nullptr;
-        c->lhist_cap = 0;
-        HIPCHK(hipMalloc(&c->d_lhist, n * lhist_words() * sizeof(uint32_t)));
-        HIPCHK(hipMemset(c->d_lhist, 0, n * lhist_words() * sizeof(uint32_t)));  // k_select keeps it zero
-        c->lhist_cap = n;
-    }
-    return RDL_OK;
-}
-
-// Point the learned-path buffers of each image into an estimate buffer of
-// sum(3*H*W) bytes and n histogram blocks.
 void bind_learn(std::vector<ImgDesc> &v, uint8_t *ml, uint32_t *lhist) {
     size_t off = 0;
     for (size_t k = 0; k < v.size(); ++k) {
@@ -252,6 +230,34 @@ bool same_key(const std::vector<ImgDesc> &a, const std::vector<ImgDesc> &b) {
     return a.size() == b.size() && memcmp(a.data(), b.data(), a.size() * sizeof(ImgDesc)) == 0;
 }
 
+void free_plan(Plan &e) {
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (e.d_desc) (void)hipFree(e.d_desc);
+    if (e.d_scratch) (void)hipFree(e.d_scratch);
+    if (e.d_ml) (void)hipFree(e.d_ml);
+    if (e.d_lhist) (void)hipFree(e.d_lhist);
+    e = Plan();
+}
+
+// Allocate a plan's scratch (zeroed) and upload its bound descriptor table;
+// synchronous, so the host vector may go as soon as it returns.
+int build_plan(Plan &e, const std::vector<ImgDesc> &v, bool learned) {
+    const size_t n = v.size();
+    HIPCHK(hipMalloc(&e.d_scratch, n * SCRATCH_I64 * sizeof(int64_t)));
+    HIPCHK(hipMemset(e.d_scratch, 0, n * SCRATCH_I64 * sizeof(int64_t)));
+    std::vector<ImgDesc> dv = v;
+    for (size_t k = 0; k < n; ++k) bind_scratch(dv[k], e.d_scratch + k * SCRATCH_I64);
+    if (learned) {
+        HIPCHK(hipMalloc(&e.d_ml, total_ml_bytes(v)));
+        HIPCHK(hipMalloc(&e.d_lhist, n * lhist_words() * sizeof(uint32_t)));
+        HIPCHK(hipMemset(e.d_lhist, 0, n * lhist_words() * sizeof(uint32_t)));
+        bind_learn(dv, e.d_ml, e.d_lhist);
+    }
+    HIPCHK(hipMalloc(&e.d_desc, n * sizeof(ImgDesc)));
+    HIPCHK(hipMemcpy(e.d_desc, dv.data(), n * sizeof(ImgDesc), hipMemcpyHostToDevice));
+    return RDL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -303,17 +309,9 @@ int rdl_create(rdl_ctx **out, int device) {
 void rdl_destroy(rdl_ctx *c) {
     if (!c) return;
     DeviceGuard g(c->device);
-    for (auto &e : c->graphs) {
-        if (e.exec) (void)hipGraphExecDestroy(e.exec);
-        if (e.d_desc) (void)hipFree(e.d_desc);
-        if (e.d_scratch) (void)hipFree(e.d_scratch);
-        if (e.d_ml) (void)hipFree(e.d_ml);
-        if (e.d_lhist) (void)hipFree(e.d_lhist);
-    }
+    for (auto &e : c->plans) free_plan(e);
     if (c->d_model) (void)hipFree(c->d_model);
     if (c->d_part) (void)hipFree(c->d_part);
-    if (c->d_ml) (void)hipFree(c->d_ml);
-    if (c->d_lhist) (void)hipFree(c->d_lhist);
     if (c->d_desc) (void)hipFree(c->d_desc);
     if (c->d_scratch) (void)hipFree(c->d_scratch);
     delete c;
@@ -378,80 +376,58 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
     }
     const Grid gr = layout(c, v);
 
-    // Replay a graph captured earlier for exactly these descriptors.
-    for (auto &e : c->graphs)
-        if (same_key(e.key, v)) {
-            HIPCHK(hipGraphLaunch(e.exec, s));
-            return RDL_OK;
+    Plan *p = nullptr;
+    for (auto &e : c->plans)
+        if (same_key(e.key, v)) p = &e;
+    if (!p) {
+        // First sight of these buffers: a descriptor table and scratch of
+        // their own, kept for later calls with the same descriptors.
+        if (c->plans.size() >= kMaxPlans) {
+            // The oldest plan may still be in use on any stream.
+            HIPCHK(hipDeviceSynchronize());
+            free_plan(c->plans.front());
+            c->plans.erase(c->plans.begin());
         }
-
-    if (!same_key(c->last_key, v)) {
-        // First sight of these buffers: launch directly from the context's
-        // own table and scratch.
-        c->last_key = v;
-        int rc = ensure_scratch(c, n);
-        if (rc) return rc;
-        std::vector<ImgDesc> dv = v;
-        for (int k = 0; k < n; ++k) bind_scratch(dv[k], c->d_scratch + (size_t)k * SCRATCH_I64);
-        if (learned) {
-            rc = ensure_learn_scratch(c, total_ml_bytes(v), n);
-            if (rc) return rc;
-            bind_learn(dv, c->d_ml, c->d_lhist);
+        Plan e;
+        e.key = v;
+        const int rc = build_plan(e, v, learned);
+        if (rc) {
+            free_plan(e);
+            return rc;
         }
-        rc = upload(c, dv, s);
-        if (rc) return rc;
-        enqueue_encode(c->d_desc, n, gr, learned, s);
+        c->plans.push_back(std::move(e));
+        p = &c->plans.back();
+    }
+    if (c->launch_mode == RDL_LAUNCH_DIRECT) {
+        enqueue_encode(p->d_desc, n, gr, learned, s);
         return check_launch("encoder kernels");
     }
+    if (!p->exec) {
+        hipStream_t cs;
+        HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipGraph_t graph;
+        hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (err == hipSuccess) {
+            enqueue_encode(p->d_desc, n, gr, learned, cs);
+            err = hipStreamEndCapture(cs, &graph);
+        }
+        if (err == hipSuccess) {
+            err = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+        }
+        (void)hipStreamDestroy(cs);
+        if (err != hipSuccess) {
+            p->exec = nullptr;
+            return hip_fail(err, "graph capture of the encoder");
+        }
+    }
+    HIPCHK(hipGraphLaunch(p->exec, s));
+    return RDL_OK;
+}
 
-    // Second call with the same buffers: capture the stage kernels once, with
-    // a table and scratch of their own, and replay the graph from now on.
-    if (c->graphs.size() >= kMaxGraphs) {
-        HIPCHK(hipStreamSynchronize(s));
-        GraphEntry &old = c->graphs.front();
-        (void)hipGraphExecDestroy(old.exec);
-        (void)hipFree(old.d_desc);
-        (void)hipFree(old.d_scratch);
-        if (old.d_ml) (void)hipFree(old.d_ml);
-        if (old.d_lhist) (void)hipFree(old.d_lhist);
-        c->graphs.erase(c->graphs.begin());
-    }
-    GraphEntry e;
-    e.key = v;
-    HIPCHK(hipMalloc(&e.d_scratch, (size_t)n * SCRATCH_I64 * sizeof(int64_t)));
-    HIPCHK(hipMemset(e.d_scratch, 0, (size_t)n * SCRATCH_I64 * sizeof(int64_t)));
-    std::vector<ImgDesc> dv = v;
-    for (int k = 0; k < n; ++k) bind_scratch(dv[k], e.d_scratch + (size_t)k * SCRATCH_I64);
-    if (learned) {
-        HIPCHK(hipMalloc(&e.d_ml, total_ml_bytes(v)));
-        HIPCHK(hipMalloc(&e.d_lhist, (size_t)n * lhist_words() * sizeof(uint32_t)));
-        HIPCHK(hipMemset(e.d_lhist, 0, (size_t)n * lhist_words() * sizeof(uint32_t)));
-        bind_learn(dv, e.d_ml, e.d_lhist);
-    }
-    HIPCHK(hipMalloc(&e.d_desc, (size_t)n * sizeof(ImgDesc)));
-    HIPCHK(hipMemcpy(e.d_desc, dv.data(), (size_t)n * sizeof(ImgDesc), hipMemcpyHostToDevice));
-    hipStream_t cs;
-    HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    hipGraph_t graph;
-    hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (err == hipSuccess) {
-        enqueue_encode(e.d_desc, n, gr, learned, cs);
-        err = hipStreamEndCapture(cs, &graph);
-    }
-    if (err == hipSuccess) {
-        err = hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-    }
-    (void)hipStreamDestroy(cs);
-    if (err != hipSuccess) {
-        (void)hipFree(e.d_desc);
-        (void)hipFree(e.d_scratch);
-        if (e.d_ml) (void)hipFree(e.d_ml);
-        if (e.d_lhist) (void)hipFree(e.d_lhist);
-        return hip_fail(err, "graph capture of the encoder");
-    }
-    HIPCHK(hipGraphLaunch(e.exec, s));
-    c->graphs.push_back(std::move(e));
+int rdl_set_launch_mode(rdl_ctx *c, int mode) {
+    if (!c || (mode != RDL_LAUNCH_DIRECT && mode != RDL_LAUNCH_GRAPH)) return RDL_EINVAL;
+    c->launch_mode = mode;
     return RDL_OK;
 }
 
@@ -511,7 +487,6 @@ int rdl_stage_keystat(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int64_t *ou
     int rc = ensure_scratch(c, 1);
     if (rc) return rc;
     bind_scratch(v[0], c->d_scratch);
-    c->last_key.clear();
     rc = upload(c, v, s);
     if (rc) return rc;
     launch_keystat(c->d_desc, 1, gr.px, s);
@@ -562,7 +537,6 @@ int rdl_stage_fit(rdl_ctx *c, const uint8_t *rgbe, const uint8_t *sdr, int H, in
     v[0].ks = (int64_t *)keystat;
     v[0].nks = 1;
     v[0].sums = out_sums;
-    c->last_key.clear();
     rc = upload(c, v, s);
     if (rc) return rc;
     launch_fit_sums(c->d_desc, 1, gr.fit, gr.fit_bins, gr.fit_waves, s);
@@ -612,7 +586,6 @@ int rdl_profile_encode(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int q, uin
     int rc = ensure_scratch(c, 1);
     if (rc) return rc;
     bind_scratch(v[0], c->d_scratch);
-    c->last_key.clear();
     rc = upload(c, v, s);
     if (rc) return rc;
     // Each stage is launched reps times back to back between two events, so
@@ -673,7 +646,6 @@ int rdl_autotune(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int q, uint8_t *
     HIPCHK(hipEventCreate(&ev[0]));
     HIPCHK(hipEventCreate(&ev[1]));
     hipError_t err = hipSuccess;
-    c->last_key.clear();
     auto table = [&]() {
         std::vector<ImgDesc> v(1, blank());
         v[0].rgbe = rgbe;

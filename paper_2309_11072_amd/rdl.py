@@ -29,6 +29,8 @@ HEADER_DTYPE = np.dtype([
 ])
 HEADER_BYTES = HEADER_DTYPE.itemsize
 
+LAUNCH_DIRECT, LAUNCH_GRAPH = 0, 1
+
 # Exported symbols of include/rdl.h with their argument types.
 _vp, _i, _i64p = C.c_void_p, C.c_int, C.c_void_p
 _SIGS = {
@@ -51,6 +53,7 @@ _SIGS = {
     "rdl_get_tuning": ([_vp, _i, _i, _vp], _i),
     "rdl_check_recip": ([_vp, C.c_uint32, C.c_uint32, _vp, _vp], _i),
     "rdl_set_tuning": ([_vp, _i, _i, _i], _i),
+    "rdl_set_launch_mode": ([_vp, _i], _i),
     "rdl_set_model": ([_vp, _vp, C.c_size_t], _i),
     "rdl_set_estimator": ([_vp, _i], _i),
     "rdl_train_sample_bytes": ([], _i),
@@ -256,6 +259,11 @@ class Codec:
                 row.append(int(v.value))
             out[name] = row
         return out
+
+    def set_launch_mode(self, graph: bool) -> None:
+        """False (default): one launch per stage kernel; True: each encoder
+        plan is captured in a HIP graph at first use and replayed."""
+        _chk(self._L.rdl_set_launch_mode(self._h, LAUNCH_GRAPH if graph else LAUNCH_DIRECT), "rdl_set_launch_mode")
 
     def set_tuning(self, table: dict) -> None:
         for p, name in enumerate(TUNE):

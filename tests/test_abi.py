@@ -84,3 +84,10 @@ def test_header_validate_bounds_host_only():
     assert check((255 << 22) + 1, 0) == bad and check(-(255 << 22) - 1, 0) == bad
     assert check(0, (65280 << 14) + 1) == bad and check(0, (-65025 << 14) - 1) == bad
     assert L.rdl_header_validate(h.ctypes.data_as(ctypes.c_void_p), 7, 10) == bad
+
+
+def test_launch_mode_rejects_null_context_host_only():
+    rdl, L = _lib()
+    assert L.rdl_set_launch_mode(None, 0) == rdl.RDL_EINVAL
+    assert L.rdl_set_launch_mode(None, 1) == rdl.RDL_EINVAL
+    assert (rdl.LAUNCH_DIRECT, rdl.LAUNCH_GRAPH) == (0, 1)

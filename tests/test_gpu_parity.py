@@ -113,10 +113,16 @@ def test_encode_decode_match_oracle(codec, O, rdl_mod, name, x, q):
     assert np.array_equal(h["a_q"], ref["a_q"]) and np.array_equal(h["b_q"], ref["b_q"])
     assert h["n_regions"] == int(ref["present"].sum())
     assert rdl_mod.load_library().rdl_header_validate(hdr.cpu().numpy().ctypes.data, H, W) == 0
-    # a second call replays the captured graph: identical outputs
-    sdr2, hdr2, resid2 = codec.encode_enh(d, q, out=out)
-    sdr3, hdr3, resid3 = codec.encode_enh(d, q, out=out)
-    assert np.array_equal(resid3.cpu().numpy(), ref["resid"]) and np.array_equal(sdr3.cpu().numpy(), ref["sdr"])
+    # later calls reuse the plan (its scratch was left zero): identical
+    # outputs, with direct launches and with the captured graph
+    for graph in (False, True, True, False):
+        codec.set_launch_mode(graph)
+        for t in out:
+            t.fill_(0xAA)
+        sdr3, hdr3, resid3 = codec.encode_enh(d, q, out=out)
+        assert np.array_equal(resid3.cpu().numpy(), ref["resid"]) and np.array_equal(sdr3.cpu().numpy(), ref["sdr"])
+        assert np.array_equal(rdl_mod.header_from_bytes(hdr3)["b_q"], ref["b_q"])
+    codec.set_launch_mode(False)
     status = torch.zeros(1, dtype=torch.int32, device="cuda")
     back = codec.decode_enh(sdr, hdr, resid, H, W, status=status)
     assert np.array_equal(back.cpu().numpy(), x), "GPU round trip"
@@ -180,6 +186,26 @@ def test_invalid_arguments(codec, rdl_mod):
                             s) == E
     assert L.rdl_resid_bytes(0, 5) == 0 and L.rdl_resid_bytes(3, 5) == 105
     assert L.rdl_encode_batch(h, None, 1, s) == E
+    assert L.rdl_set_launch_mode(h, 2) == E and L.rdl_set_launch_mode(h, -1) == E
+
+
+def test_plan_cache_eviction(codec, O):
+    """More buffer sets than the context keeps plans for: the oldest plans
+    are freed and rebuilt when seen again, with unchanged outputs."""
+    _say("plan cache: 10 shapes, twice")
+    imgs = [synth.generate(9 + k, 13 + 2 * k, 3.0, seed=900 + k, spec_frac=0.05) for k in range(10)]
+    refs = [O.encode_enh(x, 60 + k) for k, x in enumerate(imgs)]
+    devs = [torch.from_numpy(x).cuda() for x in imgs]
+    outs = [codec.alloc_outputs(*x.shape[:2]) for x in imgs]
+    for graph in (False, True):
+        codec.set_launch_mode(graph)
+        for k in list(range(10)) * 2:
+            for t in outs[k]:
+                t.fill_(0xAA)
+            sdr, hdr, resid = codec.encode_enh(devs[k], 60 + k, out=outs[k])
+            assert np.array_equal(sdr.cpu().numpy(), refs[k]["sdr"]), k
+            assert np.array_equal(resid.cpu().numpy(), refs[k]["resid"]), k
+    codec.set_launch_mode(False)
 
 
 def test_batch_uneven_matches_oracle(codec, O):
