@@ -26,6 +26,7 @@ struct Plan {
     ImgDesc *d_desc = nullptr;
     int64_t *d_scratch = nullptr;
     uint8_t *d_ml = nullptr;      // learned path only
+    uint64_t *d_lrec = nullptr;   // learned path only
     uint32_t *d_lhist = nullptr;  // learned path only
     hipGraphExec_t exec = nullptr;
 };
@@ -105,23 +106,28 @@ int ensure_scratch(rdl_ctx *c, size_t n) {
 }
 
 struct Grid {
-    int px = 0, blk = 0, tile = 0, fit = 0, res = 0, learn = 0;
+    int px = 0, blk = 0, tile = 0, fit = 0, res = 0, learn = 0, lhist = 0;
     int fit_bins = 1, fit_waves = STRIP_WAVES;  // the fit's launch shape: the largest image's
     int64_t fit_px = -1;
 };
 
-void bind_learn(std::vector<ImgDesc> &v, uint8_t *ml, uint32_t *lhist) {
+// Point the learned-path buffers of each image (scratch already bound) into
+// an estimate buffer of sum(3*H*W) bytes, a record buffer of sum(H*W) words
+// and n histogram blocks.
+void bind_learn(std::vector<ImgDesc> &v, uint8_t *ml, uint64_t *rec, uint32_t *lhist) {
     size_t off = 0;
     for (size_t k = 0; k < v.size(); ++k) {
-        v[k].ml = ml + off;
+        v[k].ml = ml + 3 * off;
+        v[k].lrec = rec + off;
         v[k].lhist = lhist + k * lhist_words();
-        off += (size_t)3 * v[k].H * v[k].W;
+        v[k].lbk = reinterpret_cast<uint32_t *>(v[k].sums - SCR_SUMS + SCR_LBK);
+        off += (size_t)v[k].H * v[k].W;
     }
 }
 
-size_t total_ml_bytes(const std::vector<ImgDesc> &v) {
+size_t total_px(const std::vector<ImgDesc> &v) {
     size_t t = 0;
-    for (auto &d : v) t += (size_t)3 * d.H * d.W;
+    for (auto &d : v) t += (size_t)d.H * d.W;
     return t;
 }
 
@@ -172,12 +178,14 @@ Grid layout(const rdl_ctx *c, std::vector<ImgDesc> &v) {
         d.wg_fit = g.fit;
         d.wg_res = g.res;
         d.wg_learn = g.learn;
+        d.wg_lhist = g.lhist;
         g.px += wgs_px(d.H, d.W);
         g.blk += wgs_blk(d.H, d.W);
         g.tile += wgs_tile(d.H, d.W);
         g.fit += wgs_strip(d.H, d.W, d.srh_fit, d.fit_waves);
         g.res += wgs_strip(d.H, d.W, d.srh_res);
         g.learn += wgs_learn(d.H, d.W);
+        g.lhist += wgs_lhist(d.H, d.W);
     }
     return g;
 }
@@ -215,6 +223,7 @@ void enqueue_encode(const ImgDesc *d, int n, const Grid &g, bool learned, hipStr
     launch_solve(d, n, s);
     if (learned) {
         launch_learn(d, n, g.learn, s);
+        launch_lhist(d, n, g.lhist, s);
         launch_select(d, n, s);
     }
     launch_resid(d, n, g.res, s);
@@ -235,6 +244,7 @@ void free_plan(Plan &e) {
     if (e.d_desc) (void)hipFree(e.d_desc);
     if (e.d_scratch) (void)hipFree(e.d_scratch);
     if (e.d_ml) (void)hipFree(e.d_ml);
+    if (e.d_lrec) (void)hipFree(e.d_lrec);
     if (e.d_lhist) (void)hipFree(e.d_lhist);
     e = Plan();
 }
@@ -248,10 +258,11 @@ int build_plan(Plan &e, const std::vector<ImgDesc> &v, bool learned) {
     std::vector<ImgDesc> dv = v;
     for (size_t k = 0; k < n; ++k) bind_scratch(dv[k], e.d_scratch + k * SCRATCH_I64);
     if (learned) {
-        HIPCHK(hipMalloc(&e.d_ml, total_ml_bytes(v)));
+        HIPCHK(hipMalloc(&e.d_ml, 3 * total_px(v)));
+        HIPCHK(hipMalloc(&e.d_lrec, total_px(v) * sizeof(uint64_t)));
         HIPCHK(hipMalloc(&e.d_lhist, n * lhist_words() * sizeof(uint32_t)));
         HIPCHK(hipMemset(e.d_lhist, 0, n * lhist_words() * sizeof(uint32_t)));
-        bind_learn(dv, e.d_ml, e.d_lhist);
+        bind_learn(dv, e.d_ml, e.d_lrec, e.d_lhist);
     }
     HIPCHK(hipMalloc(&e.d_desc, n * sizeof(ImgDesc)));
     HIPCHK(hipMemcpy(e.d_desc, dv.data(), n * sizeof(ImgDesc), hipMemcpyHostToDevice));

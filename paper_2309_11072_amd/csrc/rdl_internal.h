@@ -24,7 +24,9 @@ constexpr int SRH_RES_DEFAULT = 8;
 constexpr int FIT_BINS_DEFAULT = 2;       // privatised copies of the fit's LDS bins: 1, 2 or 4
 constexpr int FIT_WG_ROWS_MAX = 128;      // waves x rows per fit workgroup: <= 32768 px, so
                                           //   the workgroup's 32-bit bin totals cannot wrap
-constexpr int HIST_STRIPES = 4;    // learned path: copies of the per-region histograms
+constexpr int HIST_STRIPES = 1;    // learned path: copies of the per-region histograms
+constexpr int LCH = 16384;         // learned path: residual records per histogram workgroup
+constexpr int LH_COPIES = 4;       //   and its lane-interleaved LDS histogram copies
 constexpr int LEARN_W = 64, LEARN_H = 64;  // learned path: 64 x 64 px per workgroup
 constexpr int MODEL_BYTES = 7512;
 constexpr int TILE_H = 16;         // residual histogram: 16 x 128 px tiles,
@@ -36,7 +38,9 @@ constexpr int NSUM = 13;           // n, then (sum s, sum m, sum s^2, sum s m) x
 constexpr int SCR_KS = 0;
 constexpr int SCR_SUMS = SCR_KS + 2 * KS_STRIPES;
 constexpr int SCR_PART = SCR_SUMS + 256 * NSUM;
-constexpr int SCRATCH_I64 = SCR_PART + FIT_STRIPES * 256 * NSUM;
+constexpr int SCR_LBK = SCR_PART + FIT_STRIPES * 256 * NSUM;
+constexpr int LBK_WORDS = 256 + 257 + 256;  // learned path: uint32 bucket table (see ImgDesc::lbk)
+constexpr int SCRATCH_I64 = SCR_LBK + (LBK_WORDS + 1) / 2;
 constexpr int GAMMA_LUT_N = 21 * 128;             // float-bit buckets 2^-20 .. 2^1
 
 // One image of a launch.  Every kernel walks a flattened workgroup space over
@@ -56,11 +60,14 @@ struct ImgDesc {
     int64_t *hist;         // [3][511] residual histograms
     uint8_t *ml;           // learned path: [H][W][3] learned estimates
     uint32_t *lhist;       // learned path: [HIST_STRIPES][2][3][256][511] residual histograms
+    uint64_t *lrec;        // learned path: [H*W] residual records, grouped by exponent
+    uint32_t *lbk;         // learned path: [256] record cursors, [257] first histogram
+                           //   workgroup of each exponent, [256] first record of each exponent
     const uint8_t *model;  // learned path: model blob (device)
     uint64_t model_hash;
     int32_t H, W, q, flags;
     int32_t nks, nfs, srh_fit, srh_res;  // rows per wave of the fit / residual+decode strip walks
-    int32_t wg_px, wg_blk, wg_tile, wg_fit, wg_res, wg_learn;
+    int32_t wg_px, wg_blk, wg_tile, wg_fit, wg_res, wg_learn, wg_lhist;
     int32_t fit_bins, fit_waves;  // the fit launch's bin copies and waves per workgroup
 };
 
@@ -79,6 +86,9 @@ inline int wgs_strip(int H, int W, int srh, int waves = STRIP_WAVES) {
 }
 inline int wgs_learn(int H, int W) { return ((H + LEARN_H - 1) / LEARN_H) * ((W + LEARN_W - 1) / LEARN_W); }
 inline size_t lhist_words() { return (size_t)HIST_STRIPES * 2 * 3 * 256 * 511; }
+// Histogram workgroups of an image: one per LCH records of each exponent,
+// at most H*W / LCH + 1 per present exponent.
+inline int wgs_lhist(int H, int W) { return (int)(((int64_t)H * W + LCH - 1) / LCH) + 256; }
 
 // Kernel launchers (defined in rdl_kernels.hip).
 hipError_t upload_tables(int *bad_table);
@@ -93,6 +103,7 @@ void launch_resid(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_decode(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_hist(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_learn(const ImgDesc *d, int n, int wgs, hipStream_t s);
+void launch_lhist(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_select(const ImgDesc *d, int n, hipStream_t s);
 void launch_decode_learned(const ImgDesc *d, int n, int wgs, hipStream_t s);
 

@@ -108,6 +108,8 @@ __device__ __forceinline__ ImgDesc desc_at(const ImgDesc *__restrict__ D, int i)
     d.hist = glb(d.hist);
     d.ml = glb(d.ml);
     d.lhist = glb(d.lhist);
+    d.lrec = glb(d.lrec);
+    d.lbk = glb(d.lbk);
     d.model = glb(d.model);
     return d;
 }
@@ -117,7 +119,8 @@ __device__ __forceinline__ int find_img(const ImgDesc *__restrict__ D, int n, in
     int lo = 0, hi = n - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        int w = which == 0 ? D[mid].wg_px : which == 1 ? D[mid].wg_blk : which == 2 ? D[mid].wg_tile : which == 3 ? D[mid].wg_fit : which == 4 ? D[mid].wg_res : D[mid].wg_learn;
+        int w = which == 0 ? D[mid].wg_px : which == 1 ? D[mid].wg_blk : which == 2 ? D[mid].wg_tile : which == 3 ? D[mid].wg_fit : which == 4 ? D[mid].wg_res
+                : which == 5 ? D[mid].wg_learn : D[mid].wg_lhist;
         if (w <= wg) lo = mid; else hi = mid - 1;
     }
     return uniform(lo);
@@ -933,6 +936,7 @@ __device__ __forceinline__ i128 rhu128(i128 x, i128 y) { return floor_div128(2 *
 __global__ __launch_bounds__(1024) void k_solve(const ImgDesc *__restrict__ D, int n) {
     __shared__ int64_t s_b[256][NSUM];
     __shared__ int s_cnt[4];
+    __shared__ uint32_t s_tot[2][4];
     const int i = blockIdx.x;
     const ImgDesc d = desc_at(D, i);
     rdl_header *h = d.hdr;
@@ -1016,15 +1020,39 @@ __global__ __launch_bounds__(1024) void k_solve(const ImgDesc *__restrict__ D, i
         h->a_q[c][e] = aq;
         h->b_q[c][e] = bq;
         h->flag[c][e] = 0;
-    } else {
-        const int e = t - 3 * 256;
-        const bool present = s_b[e][0] > 0;
+    }
+    // The last four waves, one lane per exponent: presence and, for the
+    // learned path, inclusive scans of the region sizes and of their
+    // histogram workgroup counts (ceil(n / LCH)) within each wave.
+    const int e = t - 3 * 256, lane = t & 63;
+    uint32_t ne = 0, nc = 0, pe = 0, pc = 0;
+    if (t >= 3 * 256) {
+        ne = (uint32_t)s_b[e][0];  // n <= H*W < 2^31
+        nc = (ne + LCH - 1) / LCH;
+        const bool present = ne > 0;
         h->present[e] = present;
         const unsigned long long bal = __ballot(present);
-        if ((e & 63) == 0) s_cnt[e >> 6] = __popcll(bal);
+        if (lane == 0) s_cnt[e >> 6] = __popcll(bal);
+        pe = ne;
+        pc = nc;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t xe = __shfl_up(pe, off, 64), xc = __shfl_up(pc, off, 64);
+            if (lane >= off) { pe += xe; pc += xc; }
+        }
+        if (lane == 63) { s_tot[0][e >> 6] = pe; s_tot[1][e >> 6] = pc; }
     }
     __syncthreads();
     if (t == 0) h->n_regions = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+    if (t >= 3 * 256 && d.lbk) {
+        // Exclusive prefixes: the first record of each exponent's bucket (and
+        // its write cursor for k_learn), the first histogram workgroup.
+        for (int w = 0; w < (e >> 6); ++w) { pe += s_tot[0][w]; pc += s_tot[1][w]; }
+        d.lbk[e] = pe - ne;
+        d.lbk[256 + e] = pc - nc;
+        d.lbk[513 + e] = pe - ne;
+        if (e == 255) d.lbk[256 + 256] = pc;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1333,8 +1361,6 @@ __device__ __forceinline__ void gf_at(const uint32_t (*tile)[TW + 2], int ly, in
 }
 
 constexpr int LT_W = 64, LT_H = 16, LT_TILES = 4;  // a workgroup walks 4 tiles of 16 x 64 px
-constexpr int HB_SLOTS = 16, HB_BINS = 128;        // LDS histogram window: 16 exponents x r in [-64, 63]
-
 __device__ __forceinline__ void load_lt_tile(uint32_t (*t)[LT_W + 2], const uint8_t *__restrict__ sdr, int H, int W,
                                              int ty0, int tx0) {
     for (int k = threadIdx.x; k < (LT_H + 2) * (LT_W + 2); k += 256) {
@@ -1346,18 +1372,27 @@ __device__ __forceinline__ void load_lt_tile(uint32_t (*t)[LT_W + 2], const uint
 
 __device__ __forceinline__ int mlp_bin(int e, int k_img) { return min(max(e - 136 + k_img + 24, 0), 31); }
 
-// Encoder side: learned estimates M_L (stored for the residual stage) and,
-// per (channel, E), residual histograms of both estimators.  Histogram counts
-// go to a 16-exponent LDS window (SLR count in the low, learned count in the
-// high half of each word; a workgroup covers 4096 px so neither overflows),
-// anything outside the window or |r| range straight to the image's stripe.
+// Residual record of one pixel: r + 255 of the three channels for the SLR
+// estimate in bits 0-26 and for the learned one in bits 32-58, 9 bits each.
+__device__ __forceinline__ uint64_t lrec_pack(const int rs[3], const int rl[3]) {
+    const uint32_t lo = (uint32_t)(rs[0] + 255) | ((uint32_t)(rs[1] + 255) << 9) | ((uint32_t)(rs[2] + 255) << 18);
+    const uint32_t hi = (uint32_t)(rl[0] + 255) | ((uint32_t)(rl[1] + 255) << 9) | ((uint32_t)(rl[2] + 255) << 18);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// Encoder side: learned estimates M_L (stored for the residual stage) and
+// both estimators' residuals, written as one record per pixel into the
+// bucket of its exponent.  Bucket e starts at the number of pixels with a
+// smaller exponent (k_solve sets the cursors there); per 16-row tile the
+// workgroup ranks its pixels of each exponent in LDS, reserves that many
+// records with one atomic per exponent, and writes them.  Record order within
+// a bucket is free: only histograms are taken from it.
 __global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, int n) {
     __shared__ uint32_t t[LT_H + 2][LT_W + 2];
     __shared__ int2 s_ab[3][256];
     __shared__ int32_t B1[32][32];
     __shared__ MlpWaveLds wl[4];
-    __shared__ uint32_t hb[3][HB_SLOTS][HB_BINS];
-    __shared__ int s_ebase;
+    __shared__ uint32_t s_cnt[256], s_base[256];
     const int i = find_img(D, n, blockIdx.x, 5);
     const ImgDesc d = desc_at(D, i);
     const int H = d.H, W = d.W;
@@ -1367,25 +1402,20 @@ __global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, in
     const int ty0w = (wgl / ntx) * (LT_H * LT_TILES), tx0 = (wgl % ntx) * LT_W;
     for (int k = threadIdx.x; k < 3 * 256; k += 256) s_ab[k >> 8][k & 255] = coef_prep(h->a_q[k >> 8][k & 255], h->b_q[k >> 8][k & 255]);
     for (int k = threadIdx.x; k < 1024; k += 256) (&B1[0][0])[k] = reinterpret_cast<const int32_t *>(d.model + MB_B1)[k];
-    for (int k = threadIdx.x; k < 3 * HB_SLOTS * HB_BINS; k += 256) (&hb[0][0][0])[k] = 0;
-    if (threadIdx.x == 0) {
-        const int yy = min(ty0w, H - 1), xx = min(tx0, W - 1);
-        s_ebase = min(max((int)d.rgbe[4 * ((int64_t)yy * W + xx) + 3] - 6, 0), 256 - HB_SLOTS);
-    }
+    s_cnt[threadIdx.x] = 0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     MlpLane L;
     mlp_lane_load(L, d.model, lane);
     const int k_img = h->k_img;
-    const int64_t npx = (int64_t)H * W;
-    uint32_t *hist = d.lhist + (size_t)(wgl % HIST_STRIPES) * (2 * 3 * 256 * 511);
     for (int tt = 0; tt < LT_TILES; ++tt) {
         const int ty0 = ty0w + tt * LT_H;
         __syncthreads();
         if (ty0 < H) load_lt_tile(t, d.sdr, H, W, ty0, tx0);
         __syncthreads();
-        if (ty0 >= H) continue;  // uniform for the workgroup
-        const int ebase = s_ebase;
-#pragma unroll 1
+        if (ty0 >= H) break;  // uniform for the workgroup
+        uint64_t rec[LT_H / 4];
+        uint32_t where[LT_H / 4];  // exponent | rank << 8, or ~0 outside the image
+#pragma unroll
         for (int rr = 0; rr < LT_H / 4; ++rr) {
             const int ly = wave * (LT_H / 4) + rr, y = ty0 + ly, x = tx0 + lane;
             const bool in = y < H && x < W;
@@ -1400,34 +1430,90 @@ __global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, in
             wave_lds_sync();
             mlp_wave64(wl[wave], B1, L, lane);
             const uint32_t ml = wl[wave].ml[lane];
-            if (!in) continue;
-            int s[3];
-            gf_at<LT_W>(t, ly, lane, s);
-            const int64_t o = (int64_t)y * W + x;
-            const int slot = e - ebase;
+            rec[rr] = 0;
+            where[rr] = ~0u;
+            if (in) {
+                int s[3];
+                gf_at<LT_W>(t, ly, lane, s);
+                const int64_t o = (int64_t)y * W + x;
+                int rs[3], rl[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const int m = (int)((w >> (8 * c)) & 255u);
-                const int mlc = (int)((ml >> (8 * c)) & 255u);
-                d.ml[3 * o + c] = (uint8_t)mlc;
-                const int2 ab = s_ab[c][e];
-                const int rs = m - mstar(ab, s[c]), rl = m - mlc;
-                if (slot >= 0 && slot < HB_SLOTS && rs >= -64 && rs < 64) atomicAdd(&hb[c][slot][rs + 64], 1u);
-                else atomicAdd(&hist[((0 * 3 + c) * 256 + e) * 511 + rs + 255], 1u);
-                if (slot >= 0 && slot < HB_SLOTS && rl >= -64 && rl < 64) atomicAdd(&hb[c][slot][rl + 64], 1u << 16);
-                else atomicAdd(&hist[((1 * 3 + c) * 256 + e) * 511 + rl + 255], 1u);
+                for (int c = 0; c < 3; ++c) {
+                    const int m = (int)((w >> (8 * c)) & 255u);
+                    const int mlc = (int)((ml >> (8 * c)) & 255u);
+                    d.ml[3 * o + c] = (uint8_t)mlc;
+                    rs[c] = m - mstar(s_ab[c][e], s[c]);
+                    rl[c] = m - mlc;
+                }
+                rec[rr] = lrec_pack(rs, rl);
+                where[rr] = (uint32_t)e | (atomicAdd(&s_cnt[e], 1u) << 8);
             }
         }
+        __syncthreads();
+        {
+            // One lane per exponent reserves the tile's records of it.
+            const uint32_t c = s_cnt[threadIdx.x];
+            if (c) {
+                s_base[threadIdx.x] = atomicAdd(&d.lbk[threadIdx.x], c);
+                s_cnt[threadIdx.x] = 0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int rr = 0; rr < LT_H / 4; ++rr)
+            if (where[rr] != ~0u) {
+                // Bucket totals come from the same pixels (the fit's n_e), so
+                // the index stays below H*W; the check only guards the buffer.
+                const uint32_t idx = s_base[where[rr] & 255u] + (where[rr] >> 8);
+                if (idx < (uint32_t)(H * W)) d.lrec[idx] = rec[rr];
+            }
+    }
+}
+
+// Residual histograms per (estimator, channel, exponent) from the bucketed
+// records.  Workgroup g of an image takes records [k LCH, (k + 1) LCH) of
+// exponent e's bucket, where e is the exponent whose first histogram
+// workgroup (a prefix over ceil(n_e / LCH)) is the last one <= g.  Counts go
+// to LH_COPIES lane-interleaved LDS copies, then each non-zero bin to the
+// image's histogram with one atomic.
+__global__ __launch_bounds__(256) void k_lhist(const ImgDesc *__restrict__ D, int n) {
+    __shared__ uint32_t hb[LH_COPIES][6][512];
+    const int i = find_img(D, n, blockIdx.x, 6);
+    const ImgDesc d = desc_at(D, i);
+    const int g = blockIdx.x - d.wg_lhist;
+    const uint32_t *fw = d.lbk + 256;  // first workgroup per exponent, fw[256] = total
+    if ((uint32_t)g >= fw[256]) return;  // uniform
+    int lo = 0, hi = 256;  // fw[lo] <= g < fw[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (fw[mid] <= (uint32_t)g) lo = mid; else hi = mid;
+    }
+    const int e = uniform(lo);
+    const uint32_t k = (uint32_t)g - fw[e];
+    const uint32_t ne = (uint32_t)d.sums[e * NSUM];
+    const uint32_t first = d.lbk[513 + e] + k * LCH;
+    const uint32_t cnt = min((uint32_t)LCH, ne - k * LCH);
+    for (int q = threadIdx.x; q < LH_COPIES * 6 * 512; q += 256) (&hb[0][0][0])[q] = 0;
+    __syncthreads();
+    uint32_t(*mine)[512] = hb[threadIdx.x & (LH_COPIES - 1)];
+    const uint64_t *rp = d.lrec + first;
+    for (uint32_t j = threadIdx.x; j < cnt; j += 256) {
+        const uint64_t r = rp[j];
+        const uint32_t a = (uint32_t)r, b = (uint32_t)(r >> 32);
+        atomicAdd(&mine[0][a & 511u], 1u);
+        atomicAdd(&mine[1][(a >> 9) & 511u], 1u);
+        atomicAdd(&mine[2][a >> 18], 1u);
+        atomicAdd(&mine[3][b & 511u], 1u);
+        atomicAdd(&mine[4][(b >> 9) & 511u], 1u);
+        atomicAdd(&mine[5][b >> 18], 1u);
     }
     __syncthreads();
-    const int ebase = s_ebase;
-    for (int k = threadIdx.x; k < 3 * HB_SLOTS * HB_BINS; k += 256) {
-        const uint32_t v = (&hb[0][0][0])[k];
-        if (!v) continue;
-        const int c = k / (HB_SLOTS * HB_BINS), slot = (k / HB_BINS) % HB_SLOTS, bi = k % HB_BINS;
-        const int e = ebase + slot, r = bi - 64;
-        if (v & 0xFFFFu) atomicAdd(&hist[((0 * 3 + c) * 256 + e) * 511 + r + 255], v & 0xFFFFu);
-        if (v >> 16) atomicAdd(&hist[((1 * 3 + c) * 256 + e) * 511 + r + 255], v >> 16);
+    for (int q = threadIdx.x; q < 6 * 511; q += 256) {
+        const int hgram = q / 511, v = q - hgram * 511;  // hgram = estimator * 3 + channel
+        uint32_t c = 0;
+#pragma unroll
+        for (int cp = 0; cp < LH_COPIES; ++cp) c += hb[cp][hgram][v];
+        if (c) atomicAdd(&d.lhist[((size_t)hgram * 256 + e) * 511 + v], c);
     }
 }
 
@@ -1705,6 +1791,9 @@ void launch_decode(const ImgDesc *d, int n, int wgs, hipStream_t s) {
 }
 void launch_learn(const ImgDesc *d, int n, int wgs, hipStream_t s) {
     hipLaunchKernelGGL(k_learn, dim3(wgs), dim3(256), 0, s, d, n);
+}
+void launch_lhist(const ImgDesc *d, int n, int wgs, hipStream_t s) {
+    hipLaunchKernelGGL(k_lhist, dim3(wgs), dim3(256), 0, s, d, n);
 }
 void launch_select(const ImgDesc *d, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_select, dim3(256 * n), dim3(256), 0, s, d, n);

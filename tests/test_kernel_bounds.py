@@ -101,3 +101,103 @@ def test_strip_walk_stays_inside_buffers(H, W, srh, waves):
             b = dict(bases, sdr=bases["sdr"] + sdr_off, resid=bases["resid"] + res_off)
             for buf, lo, hi in walk_accesses(H, W, srh, b["sdr"], b["rgbe"], b["resid"], waves):
                 assert b[buf] <= lo and hi <= b[buf] + sizes[buf], (buf, lo - b[buf], hi - b[buf], sizes[buf])
+
+
+# ---------------------------------------------------------------------------
+# Learned path: exponent buckets of residual records.  k_solve turns the
+# region sizes n_e into bucket starts and the first histogram workgroup of
+# each exponent (prefixes over ceil(n_e / LCH)); k_learn reserves records per
+# tile with atomics on the bucket cursors; k_lhist maps its workgroup to an
+# exponent by binary search and histograms LCH records of that bucket.
+LCH = 16384
+
+
+def bucket_table(ne):
+    """The uint32 table k_solve writes: cursors, first workgroups (+ total),
+    bucket starts."""
+    ne = [int(v) for v in ne]
+    start = np.concatenate([[0], np.cumsum(ne)[:-1]]).astype(np.int64)
+    nc = [(v + LCH - 1) // LCH for v in ne]
+    fw = np.concatenate([[0], np.cumsum(nc)]).astype(np.int64)
+    return start.copy(), fw, start
+
+
+def lhist_ranges(ne, nwg):
+    """(e, first record, count) of each histogram workgroup that runs."""
+    _, fw, start = bucket_table(ne)
+    out = []
+    for g in range(nwg):
+        if g >= fw[256]:
+            continue
+        lo, hi = 0, 256
+        while hi - lo > 1:
+            mid = (lo + hi) >> 1
+            if fw[mid] <= g:
+                lo = mid
+            else:
+                hi = mid
+        e = lo
+        k = g - fw[e]
+        first = int(start[e]) + k * LCH
+        cnt = min(LCH, ne[e] - k * LCH)
+        out.append((e, first, cnt))
+    return out
+
+
+@pytest.mark.parametrize("case", ["one", "spread", "multiples", "sparse", "4k"])
+def test_learned_buckets_cover_each_record_once(case):
+    rng = np.random.default_rng(11)
+    if case == "one":
+        ne = np.zeros(256, np.int64); ne[0] = 1
+    elif case == "spread":
+        ne = rng.integers(0, 5000, 256)
+    elif case == "multiples":
+        ne = np.zeros(256, np.int64); ne[[3, 100, 255]] = [LCH, 2 * LCH, 3 * LCH]
+    elif case == "sparse":
+        ne = np.zeros(256, np.int64); ne[rng.choice(256, 40, replace=False)] = rng.integers(1, 200000, 40)
+    else:
+        ne = np.zeros(256, np.int64); ne[110:160] = rng.multinomial(3840 * 2160, np.ones(50) / 50)
+    npx = int(ne.sum())
+    nwg = (npx + LCH - 1) // LCH + 256  # the grid of wgs_lhist
+    runs = lhist_ranges(ne, nwg)
+    seen = np.zeros(npx, np.int32)
+    for e, first, cnt in runs:
+        assert 0 < cnt <= LCH and first >= 0 and first + cnt <= npx
+        seen[first:first + cnt] += 1
+    assert np.all(seen == 1), "every record in exactly one histogram workgroup"
+    assert len(runs) <= nwg
+    # the workgroup's records all belong to its exponent's bucket
+    _, _, start = bucket_table(ne)
+    for e, first, cnt in runs:
+        assert start[e] <= first and first + cnt <= start[e] + ne[e]
+
+
+def test_learned_reservation_stays_in_bucket():
+    """Tiles reserve their records of each exponent in any order; with
+    reservations summing to n_e every index lands inside bucket e."""
+    rng = np.random.default_rng(5)
+    H, W = 200, 333
+    E = rng.integers(120, 140, (H, W))
+    E[rng.random((H, W)) < 0.05] += 10
+    ne = np.bincount(E.reshape(-1), minlength=256)
+    cur, _, start = bucket_table(ne)
+    tiles = [(ty, tx) for ty in range(0, H, 16) for tx in range(0, W, 64)]
+    rng.shuffle(tiles)
+    hit = np.zeros(H * W, np.int32)
+    for ty, tx in tiles:
+        t = E[ty:ty + 16, tx:tx + 64].reshape(-1)
+        rank = {}
+        idx = []
+        for e in t:
+            r = rank.get(e, 0)
+            rank[e] = r + 1
+            idx.append((e, r))
+        base = {}
+        for e, c in rank.items():
+            base[e] = cur[e]
+            cur[e] += c
+        for e, r in idx:
+            k = base[e] + r
+            assert start[e] <= k < start[e] + ne[e] and k < H * W
+            hit[k] += 1
+    assert np.all(hit == 1)
