@@ -24,7 +24,6 @@ constexpr int SRH_RES_DEFAULT = 8;
 constexpr int FIT_BINS_DEFAULT = 2;       // privatised copies of the fit's LDS bins: 1, 2 or 4
 constexpr int FIT_WG_ROWS_MAX = 128;      // waves x rows per fit workgroup: <= 32768 px, so
                                           //   the workgroup's 32-bit bin totals cannot wrap
-constexpr int HIST_STRIPES = 1;    // learned path: copies of the per-region histograms
 constexpr int LCH = 16384;         // learned path: residual records per histogram workgroup
 constexpr int LH_COPIES = 4;       //   and its lane-interleaved LDS histogram copies
 constexpr int LEARN_W = 64, LEARN_H = 64;  // learned path: 64 x 64 px per workgroup
@@ -59,7 +58,7 @@ struct ImgDesc {
     uint8_t *out_rgbe;     // decode only
     int64_t *hist;         // [3][511] residual histograms
     uint8_t *ml;           // learned path: [H][W][3] learned estimates
-    uint32_t *lhist;       // learned path: [HIST_STRIPES][2][3][256][511] residual histograms
+    uint32_t *lhist;       // learned path: [2][3][256][511] residual histograms (estimator, channel)
     uint64_t *lrec;        // learned path: [H*W] residual records, grouped by exponent
     uint32_t *lbk;         // learned path: [256] record cursors, [257] first histogram
                            //   workgroup of each exponent, [256] first record of each exponent
@@ -85,7 +84,7 @@ inline int wgs_strip(int H, int W, int srh, int waves = STRIP_WAVES) {
     return ((H + sh - 1) / sh) * ((W + STRIP_W - 1) / STRIP_W);
 }
 inline int wgs_learn(int H, int W) { return ((H + LEARN_H - 1) / LEARN_H) * ((W + LEARN_W - 1) / LEARN_W); }
-inline size_t lhist_words() { return (size_t)HIST_STRIPES * 2 * 3 * 256 * 511; }
+inline size_t lhist_words() { return (size_t)2 * 3 * 256 * 511; }
 // Histogram workgroups of an image: one per LCH records of each exponent,
 // at most H*W / LCH + 1 per present exponent.
 inline int wgs_lhist(int H, int W) { return (int)(((int64_t)H * W + LCH - 1) / LCH) + 256; }

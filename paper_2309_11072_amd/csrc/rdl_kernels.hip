@@ -1225,9 +1225,16 @@ __global__ __launch_bounds__(STRIP_THREADS) void k_decode(const ImgDesc *__restr
 // 32-bit arithmetic equals the exact one.
 //
 // Each layer is an int8 MFMA D = W X with pixels along N: v_mfma_i32_16x16x32
-// takes lane l's A bytes = W[l%16][8(l/16) .. +7], B bytes = X[8(l/16) .. +7]
-// [l%16] and returns D[4(l/16) + t][l%16], t = 0..3, i.e. four output neurons
-// of one pixel per lane.
+// takes lane l's A bytes = W[l%16][k], B bytes = X[k][l%16] for the eight k of
+// lane quad q = l/16, and returns D[4q + t][l%16], t = 0..3: four output
+// neurons of one pixel per lane.  A 32-neuron layer is two MFMAs (neurons
+// 0-15 and 16-31), so after requantisation lane (j, q) holds neurons
+// 4q..4q+3 and 16+4q..16+4q+3 of pixel j.  The next layer takes exactly those
+// eight as its k = 8q..8q+7 (its weight columns are read in that order), so a
+// lane feeds its own bytes forward with no exchange between lanes.  The
+// output layer's rows repeat R, G, B, 0 in every quad, so quad q of group g's
+// result holds pixel 16g + j's estimates; lane l keeps group l/16's, which is
+// pixel l.
 // ---------------------------------------------------------------------------
 constexpr int MB_W1 = 24, MB_B1 = 1048, MB_M1 = 5144, MB_R1 = 5272, MB_W2 = 5400, MB_B2 = 6424, MB_M2 = 6552,
               MB_R2 = 6680, MB_W3 = 6808, MB_B3 = 7320, MB_M3 = 7384, MB_R3 = 7448;
@@ -1235,39 +1242,57 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 struct MlpLane {
     long w1a, w1b, w2a, w2b, w3;  // this lane's A fragments
-    int m1[8], r1[8], m2[8], r2[8], b2[8], m3[4], r3[4], b3[4];
+    int m1[8], r1[8], c1[8];      // requantisation of this lane's eight neurons: multiplier,
+    int m2[8], r2[8], c2[8];      //   shift, rounding constant 2^(r-1)
+    int b2[8];
+    int m3[3], r3[3], c3[3], b3[3];
 };
+
+// Eight weight bytes of row `row` at the columns lane quad q takes as its k:
+// 4q..4q+3, then 16+4q..16+4q+3.
+__device__ __forceinline__ long w_fwd(const uint8_t *__restrict__ w, int row, int q) {
+    const uint32_t lo = *reinterpret_cast<const uint32_t *>(w + row * 32 + 4 * q);
+    const uint32_t hi = *reinterpret_cast<const uint32_t *>(w + row * 32 + 16 + 4 * q);
+    return (long)((uint64_t)lo | ((uint64_t)hi << 32));
+}
 
 __device__ __forceinline__ void mlp_lane_load(MlpLane &L, const uint8_t *__restrict__ blob, int lane) {
     const int j = lane & 15, q = lane >> 4;
     L.w1a = *reinterpret_cast<const long *>(blob + MB_W1 + j * 32 + 8 * q);
     L.w1b = *reinterpret_cast<const long *>(blob + MB_W1 + (16 + j) * 32 + 8 * q);
-    L.w2a = *reinterpret_cast<const long *>(blob + MB_W2 + j * 32 + 8 * q);
-    L.w2b = *reinterpret_cast<const long *>(blob + MB_W2 + (16 + j) * 32 + 8 * q);
-    L.w3 = *reinterpret_cast<const long *>(blob + MB_W3 + j * 32 + 8 * q);
+    L.w2a = w_fwd(blob + MB_W2, j, q);
+    L.w2b = w_fwd(blob + MB_W2, 16 + j, q);
+    L.w3 = (j & 3) < 3 ? w_fwd(blob + MB_W3, j & 3, q) : 0;
     const int32_t *m1 = reinterpret_cast<const int32_t *>(blob + MB_M1), *r1 = reinterpret_cast<const int32_t *>(blob + MB_R1);
     const int32_t *m2 = reinterpret_cast<const int32_t *>(blob + MB_M2), *r2 = reinterpret_cast<const int32_t *>(blob + MB_R2);
     const int32_t *b2 = reinterpret_cast<const int32_t *>(blob + MB_B2);
     const int32_t *m3 = reinterpret_cast<const int32_t *>(blob + MB_M3), *r3 = reinterpret_cast<const int32_t *>(blob + MB_R3);
     const int32_t *b3 = reinterpret_cast<const int32_t *>(blob + MB_B3);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int na = 4 * q + t, nb = 16 + 4 * q + t;
-        L.m1[t] = m1[na]; L.r1[t] = r1[na]; L.m1[4 + t] = m1[nb]; L.r1[4 + t] = r1[nb];
-        L.m2[t] = m2[na]; L.r2[t] = r2[na]; L.m2[4 + t] = m2[nb]; L.r2[4 + t] = r2[nb];
-        L.b2[t] = b2[na]; L.b2[4 + t] = b2[nb];
-        L.m3[t] = m3[na]; L.r3[t] = r3[na]; L.b3[t] = b3[na];
+    for (int t = 0; t < 8; ++t) {
+        const int nn = t < 4 ? 4 * q + t : 16 + 4 * q + t - 4;
+        L.m1[t] = m1[nn]; L.r1[t] = r1[nn]; L.c1[t] = 1 << (r1[nn] - 1);
+        L.m2[t] = m2[nn]; L.r2[t] = r2[nn]; L.c2[t] = 1 << (r2[nn] - 1);
+        L.b2[t] = b2[nn];
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        L.m3[t] = m3[t]; L.r3[t] = r3[t]; L.c3[t] = 1 << (r3[t] - 1); L.b3[t] = b3[t];
     }
 }
 
-__device__ __forceinline__ uint32_t requant_u8(int h, int m, int r) {
-    const int v = (__mul24(h, m) + (1 << (r - 1))) >> r;
-    return (uint32_t)min(max(v, 0), 127);
+__device__ __forceinline__ uint32_t requant_u8(int h, int m, int r, int c) {
+    return (uint32_t)min(max((__mul24(h, m) + c) >> r, 0), 127);
 }
 
-__device__ __forceinline__ uint32_t requant4(const v4i h, const int *m, const int *r) {
-    return requant_u8(h[0], m[0], r[0]) | (requant_u8(h[1], m[1], r[1]) << 8) | (requant_u8(h[2], m[2], r[2]) << 16) |
-           (requant_u8(h[3], m[3], r[3]) << 24);
+// Four requantised bytes packed low to high: two byte permutes join pairs,
+// a third joins the pairs.
+__device__ __forceinline__ uint32_t requant4(const v4i h, const int *m, const int *r, const int *c) {
+    const uint32_t x01 = __builtin_amdgcn_perm(requant_u8(h[1], m[1], r[1], c[1]), requant_u8(h[0], m[0], r[0], c[0]),
+                                               0x0c0c0400u);
+    const uint32_t x23 = __builtin_amdgcn_perm(requant_u8(h[3], m[3], r[3], c[3]), requant_u8(h[2], m[2], r[2], c[2]),
+                                               0x0c0c0400u);
+    return __builtin_amdgcn_perm(x23, x01, 0x05040100u);
 }
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -1276,20 +1301,24 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Per-wave LDS of the estimator: 64 pixels' features (32 bytes each), their
-// bins, one 16-pixel transposition area and the 64 outputs.
+// Per-wave LDS of the estimator: 64 pixels' features (32 bytes each) and
+// their bins.
 struct MlpWaveLds {
     uint32_t feat[64][8];
-    uint32_t xp[16][8];
-    uint32_t ml[64];
     int bin[64];
 };
 
-// M_L for the 64 pixels of a wave (feat and bin filled by the caller, every
-// lane of the wave active).  B1 is the bias table in LDS.
-__device__ __forceinline__ void mlp_wave64(MlpWaveLds &w, const int32_t (*B1)[32], const MlpLane &L, int lane) {
+// M_L of pixel `lane` of the wave, packed R | G << 8 | B << 16 (feat and bin
+// filled for all 64 pixels and made visible by the caller, every lane of the
+// wave active).  B1 is the bias table in LDS.
+__device__ __forceinline__ uint32_t mlp_wave64(const MlpWaveLds &w, const int32_t (*B1)[32], const MlpLane &L,
+                                               int lane) {
     const int j = lane & 15, q = lane >> 4;
-#pragma unroll 1
+    const v4i c2a = {L.b2[0], L.b2[1], L.b2[2], L.b2[3]};
+    const v4i c2b = {L.b2[4], L.b2[5], L.b2[6], L.b2[7]};
+    const v4i c3 = {L.b3[0], L.b3[1], L.b3[2], 0};
+    v4i o[4];
+#pragma unroll
     for (int g = 0; g < 4; ++g) {
         const int p = 16 * g + j;
         const long xb = *reinterpret_cast<const long *>(&w.feat[p][2 * q]);
@@ -1298,33 +1327,22 @@ __device__ __forceinline__ void mlp_wave64(MlpWaveLds &w, const int32_t (*B1)[32
         const v4i c1b = *reinterpret_cast<const v4i *>(&B1[b][16 + 4 * q]);
         const v4i h1a = __builtin_amdgcn_mfma_i32_16x16x32_i8(L.w1a, xb, c1a, 0, 0, 0);
         const v4i h1b = __builtin_amdgcn_mfma_i32_16x16x32_i8(L.w1b, xb, c1b, 0, 0, 0);
-        w.xp[j][q] = requant4(h1a, L.m1, L.r1);
-        w.xp[j][4 + q] = requant4(h1b, L.m1 + 4, L.r1 + 4);
-        wave_lds_sync();
-        const long a1 = *reinterpret_cast<const long *>(&w.xp[j][2 * q]);
-        wave_lds_sync();
-        const v4i c2a = {L.b2[0], L.b2[1], L.b2[2], L.b2[3]};
-        const v4i c2b = {L.b2[4], L.b2[5], L.b2[6], L.b2[7]};
+        const long a1 = (long)((uint64_t)requant4(h1a, L.m1, L.r1, L.c1) |
+                               ((uint64_t)requant4(h1b, L.m1 + 4, L.r1 + 4, L.c1 + 4) << 32));
         const v4i h2a = __builtin_amdgcn_mfma_i32_16x16x32_i8(L.w2a, a1, c2a, 0, 0, 0);
         const v4i h2b = __builtin_amdgcn_mfma_i32_16x16x32_i8(L.w2b, a1, c2b, 0, 0, 0);
-        w.xp[j][q] = requant4(h2a, L.m2, L.r2);
-        w.xp[j][4 + q] = requant4(h2b, L.m2 + 4, L.r2 + 4);
-        wave_lds_sync();
-        const long a2 = *reinterpret_cast<const long *>(&w.xp[j][2 * q]);
-        wave_lds_sync();
-        const v4i c3 = {L.b3[0], L.b3[1], L.b3[2], L.b3[3]};
-        const v4i o = __builtin_amdgcn_mfma_i32_16x16x32_i8(L.w3, a2, c3, 0, 0, 0);
-        if (q == 0) {  // neurons 0, 1, 2 are the R, G, B estimates of pixel p
-            uint32_t word = 0;
-#pragma unroll
-            for (int t = 0; t < 3; ++t) {
-                const int q8 = (__mul24(o[t], L.m3[t]) + (1 << (L.r3[t] - 1))) >> L.r3[t];
-                word |= (uint32_t)min(max((q8 + 128) >> 8, 0), 255) << (8 * t);
-            }
-            w.ml[p] = word;
-        }
+        const long a2 = (long)((uint64_t)requant4(h2a, L.m2, L.r2, L.c2) |
+                               ((uint64_t)requant4(h2b, L.m2 + 4, L.r2 + 4, L.c2 + 4) << 32));
+        o[g] = __builtin_amdgcn_mfma_i32_16x16x32_i8(L.w3, a2, c3, 0, 0, 0);
     }
-    wave_lds_sync();
+    uint32_t word = 0;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        const int v = q == 0 ? o[0][t] : q == 1 ? o[1][t] : q == 2 ? o[2][t] : o[3][t];
+        const int q8 = (__mul24(v, L.m3[t]) + L.c3[t]) >> L.r3[t];
+        word |= (uint32_t)min(max((q8 + 128) >> 8, 0), 255) << (8 * t);
+    }
+    return word;
 }
 
 // Features of the pixel at tile position (ly, lx): the nine neighbours'
@@ -1344,20 +1362,22 @@ __device__ __forceinline__ void build_features(const uint32_t (*tile)[TW + 2], i
     f[7] = 0;
 }
 
-// S* of the tile pixel (ly, lx) from its 3x3 neighbourhood.
+// S* of the tile pixel (ly, lx) from its 3x3 neighbourhood, on the packed
+// fields R | B << 16 and G (no field exceeds 64 * 255 + 32 < 2^16).
 template <int TW>
 __device__ __forceinline__ void gf_at(const uint32_t (*tile)[TW + 2], int ly, int lx, int s[3]) {
+    uint32_t lo[3], hi[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        int v[3];
-#pragma unroll
-        for (int dy = 0; dy < 3; ++dy) {
-            const int a = (tile[ly + dy][lx] >> (8 * c)) & 255, b = (tile[ly + dy][lx + 1] >> (8 * c)) & 255,
-                      e = (tile[ly + dy][lx + 2] >> (8 * c)) & 255;
-            v[dy] = a + 6 * b + e;
-        }
-        s[c] = (v[0] + 6 * v[1] + v[2] + 32) >> 6;
+    for (int dy = 0; dy < 3; ++dy) {
+        const uint32_t a = tile[ly + dy][lx], b = tile[ly + dy][lx + 1], e = tile[ly + dy][lx + 2];
+        lo[dy] = __umul24(b & 0xFF00FFu, 6u) + (a & 0xFF00FFu) + (e & 0xFF00FFu);
+        hi[dy] = __umul24((b >> 8) & 255u, 6u) + ((a >> 8) & 255u) + ((e >> 8) & 255u);
     }
+    const uint32_t L = lo[0] + lo[2] + 0x200020u + (lo[1] << 2) + (lo[1] << 1);
+    const uint32_t G = hi[0] + hi[2] + 32u + (hi[1] << 2) + (hi[1] << 1);
+    s[0] = (int)((L >> 6) & 255u);
+    s[1] = (int)(G >> 6);
+    s[2] = (int)(L >> 22);
 }
 
 constexpr int LT_W = 64, LT_H = 16, LT_TILES = 4;  // a workgroup walks 4 tiles of 16 x 64 px
@@ -1428,8 +1448,8 @@ __global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, in
             *reinterpret_cast<uint4 *>(&wl[wave].feat[lane][4]) = make_uint4(f[4], f[5], f[6], f[7]);
             wl[wave].bin[lane] = mlp_bin(e, k_img);
             wave_lds_sync();
-            mlp_wave64(wl[wave], B1, L, lane);
-            const uint32_t ml = wl[wave].ml[lane];
+            const uint32_t ml = mlp_wave64(wl[wave], B1, L, lane);
+            wave_lds_sync();  // feat and bin are rewritten for the next row
             rec[rr] = 0;
             where[rr] = ~0u;
             if (in) {
@@ -1525,12 +1545,13 @@ __device__ __forceinline__ int64_t log2q16(uint32_t x) {
     return (int64_t)65536 * p + g_log2f[idx];
 }
 
-// One workgroup per (image, exponent): sums the histogram stripes (leaving them
-// zero), computes both estimators' integer entropy costs per channel and sets
-// the flag where the learned cost is strictly lower.
+// One workgroup per (image, exponent): takes both estimators' histograms of
+// the three channels (leaving them zero for the next launch), computes the
+// integer entropy costs and sets the flag where the learned cost is strictly
+// lower.  With n = the region's size (every pixel adds one count to each
+// histogram), cost = sum_v h_v (L(n) - L(h_v)) = n L(n) - sum_v h_v L(h_v).
 __global__ __launch_bounds__(256) void k_select(const ImgDesc *__restrict__ D, int n) {
-    __shared__ int64_t s_red[4][2];
-    __shared__ uint32_t s_cnt[2][511];
+    __shared__ int64_t s_red[4][6];
     const int i = blockIdx.x >> 8, e = blockIdx.x & 255;
     if (i >= n) return;
     const ImgDesc d = desc_at(D, i);
@@ -1543,42 +1564,43 @@ __global__ __launch_bounds__(256) void k_select(const ImgDesc *__restrict__ D, i
         if (threadIdx.x < 3) h->flag[threadIdx.x][e] = 0;
         return;
     }
-    for (int c = 0; c < 3; ++c) {
-        for (int v = threadIdx.x; v < 511; v += 256) {
+    // Thread t takes bins t and t + 256 of the six histograms (estimator x
+    // channel), all loads issued before the first is used.
+    uint32_t cnt[6][2];
 #pragma unroll
-            for (int est = 0; est < 2; ++est) {
-                uint32_t acc = 0;
-                for (int st = 0; st < HIST_STRIPES; ++st) {
-                    uint32_t *p = d.lhist + (size_t)st * (2 * 3 * 256 * 511) + ((est * 3 + c) * 256 + e) * 511 + v;
-                    acc += *p;
-                    *p = 0;
-                }
-                s_cnt[est][v] = acc;
-            }
+    for (int hg = 0; hg < 6; ++hg)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int v = threadIdx.x + 256 * k;
+            cnt[hg][k] = v < 511 ? d.lhist[((size_t)hg * 256 + e) * 511 + v] : 0u;
         }
-        __syncthreads();
-        // n = region size (same for both estimators)
-        int64_t part[2] = {0, 0};
-        uint32_t nn = 0;
-        for (int v = 0; v < 511; ++v) nn += s_cnt[0][v];
-        const int64_t Ln = log2q16(nn);
-        for (int v = threadIdx.x; v < 511; v += 256)
 #pragma unroll
-            for (int est = 0; est < 2; ++est) {
-                const uint32_t hv = s_cnt[est][v];
-                if (hv) part[est] += (int64_t)hv * (Ln - log2q16(hv));
-            }
+    for (int hg = 0; hg < 6; ++hg)
 #pragma unroll
-        for (int est = 0; est < 2; ++est)
-            for (int off = 32; off > 0; off >>= 1) part[est] += __shfl_down(part[est], off, 64);
-        if ((threadIdx.x & 63) == 0) { s_red[threadIdx.x >> 6][0] = part[0]; s_red[threadIdx.x >> 6][1] = part[1]; }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const int64_t cs = s_red[0][0] + s_red[1][0] + s_red[2][0] + s_red[3][0];
-            const int64_t cl = s_red[0][1] + s_red[1][1] + s_red[2][1] + s_red[3][1];
-            h->flag[c][e] = cl < cs ? 1 : 0;
+        for (int k = 0; k < 2; ++k) {
+            const int v = threadIdx.x + 256 * k;
+            if (v < 511) d.lhist[((size_t)hg * 256 + e) * 511 + v] = 0;
         }
-        __syncthreads();
+    int64_t part[6];
+#pragma unroll
+    for (int hg = 0; hg < 6; ++hg) {
+        part[hg] = 0;
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+            if (cnt[hg][k]) part[hg] += (int64_t)cnt[hg][k] * log2q16(cnt[hg][k]);
+        for (int off = 32; off > 0; off >>= 1) part[hg] += __shfl_down(part[hg], off, 64);
+    }
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int hg = 0; hg < 6; ++hg) s_red[threadIdx.x >> 6][hg] = part[hg];
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int c = threadIdx.x;
+        const int64_t nn = d.sums[e * NSUM];
+        const int64_t nL = nn * log2q16((uint32_t)nn);
+        const int64_t hs = s_red[0][c] + s_red[1][c] + s_red[2][c] + s_red[3][c];
+        const int64_t hl = s_red[0][3 + c] + s_red[1][3 + c] + s_red[2][3 + c] + s_red[3][3 + c];
+        h->flag[c][e] = (nL - hl) < (nL - hs) ? 1 : 0;
     }
 }
 
@@ -1645,8 +1667,8 @@ __global__ __launch_bounds__(256) void k_decode_learned(const ImgDesc *__restric
             *reinterpret_cast<uint4 *>(&wl[wave].feat[lane][4]) = make_uint4(f[4], f[5], f[6], f[7]);
             wl[wave].bin[lane] = mlp_bin(e, k_img);
             wave_lds_sync();
-            mlp_wave64(wl[wave], B1, L, lane);
-            const uint32_t ml = wl[wave].ml[lane];
+            const uint32_t ml = mlp_wave64(wl[wave], B1, L, lane);
+            wave_lds_sync();  // feat and bin are rewritten for the next row
             if (!in) continue;
             int s[3];
             gf_at<LT_W>(t, ly, lane, s);
