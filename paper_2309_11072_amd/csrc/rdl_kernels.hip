@@ -1390,6 +1390,36 @@ __device__ __forceinline__ void load_lt_tile(uint32_t (*t)[LT_W + 2], const uint
     }
 }
 
+// The same tile, fetched into registers (LT_PER_THREAD words per thread) so
+// that the loads of the next tile overlap the work on the current one.
+constexpr int LT_WORDS = (LT_H + 2) * (LT_W + 2);
+constexpr int LT_PER_THREAD = (LT_WORDS + 255) / 256;
+// ry[k], xx[k]: this thread's tile row and clamped image column of word k.
+__device__ __forceinline__ void lt_slots(int W, int tx0, int ry[LT_PER_THREAD], int xx[LT_PER_THREAD]) {
+#pragma unroll
+    for (int k = 0; k < LT_PER_THREAD; ++k) {
+        const int q = min((int)threadIdx.x + 256 * k, LT_WORDS - 1);
+        ry[k] = q / (LT_W + 2);
+        xx[k] = min(max(tx0 + q - ry[k] * (LT_W + 2) - 1, 0), W - 1);
+    }
+}
+__device__ __forceinline__ void fetch_lt_tile(uint32_t v[LT_PER_THREAD], const uint8_t *__restrict__ sdr, int H,
+                                              int W, int ty0, const int ry[LT_PER_THREAD],
+                                              const int xx[LT_PER_THREAD]) {
+#pragma unroll
+    for (int k = 0; k < LT_PER_THREAD; ++k) {
+        const int yy = min(max(ty0 + ry[k] - 1, 0), H - 1);
+        v[k] = load_px3(sdr + 3 * ((int64_t)yy * W + xx[k]));
+    }
+}
+__device__ __forceinline__ void store_lt_tile(uint32_t (*t)[LT_W + 2], const uint32_t v[LT_PER_THREAD]) {
+#pragma unroll
+    for (int k = 0; k < LT_PER_THREAD; ++k) {
+        const int q = threadIdx.x + 256 * k;
+        if (q < LT_WORDS) (&t[0][0])[q] = v[k];
+    }
+}
+
 __device__ __forceinline__ int mlp_bin(int e, int k_img) { return min(max(e - 136 + k_img + 24, 0), 31); }
 
 // Residual record of one pixel: r + 255 of the three channels for the SLR
@@ -1427,20 +1457,43 @@ __global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, in
     MlpLane L;
     mlp_lane_load(L, d.model, lane);
     const int k_img = h->k_img;
+    // Tile tt + 1's S words and RGBE words are in flight while tile tt is
+    // worked on (every condition below is uniform for the workgroup).
+    uint32_t sv[LT_PER_THREAD], wv[LT_H / 4];
+    int lry[LT_PER_THREAD], lxx[LT_PER_THREAD];
+    lt_slots(W, tx0, lry, lxx);
+    const uint32_t *rgbe32 = reinterpret_cast<const uint32_t *>(d.rgbe);
+    const auto fetch_rgbe = [&](int ty, uint32_t out[LT_H / 4]) {
+#pragma unroll
+        for (int rr = 0; rr < LT_H / 4; ++rr) {
+            const int y = ty + wave * (LT_H / 4) + rr, x = tx0 + lane;
+            out[rr] = y < H && x < W ? rgbe32[(int64_t)y * W + x] : 0u;
+        }
+    };
+    if (ty0w < H) {
+        fetch_lt_tile(sv, d.sdr, H, W, ty0w, lry, lxx);
+        fetch_rgbe(ty0w, wv);
+    }
     for (int tt = 0; tt < LT_TILES; ++tt) {
         const int ty0 = ty0w + tt * LT_H;
+        if (ty0 >= H) break;
         __syncthreads();
-        if (ty0 < H) load_lt_tile(t, d.sdr, H, W, ty0, tx0);
+        store_lt_tile(t, sv);
         __syncthreads();
-        if (ty0 >= H) break;  // uniform for the workgroup
+        uint32_t wc[LT_H / 4];
+#pragma unroll
+        for (int rr = 0; rr < LT_H / 4; ++rr) wc[rr] = wv[rr];
+        if (tt + 1 < LT_TILES && ty0 + LT_H < H) {
+            fetch_lt_tile(sv, d.sdr, H, W, ty0 + LT_H, lry, lxx);
+            fetch_rgbe(ty0 + LT_H, wv);
+        }
         uint64_t rec[LT_H / 4];
         uint32_t where[LT_H / 4];  // exponent | rank << 8, or ~0 outside the image
 #pragma unroll
         for (int rr = 0; rr < LT_H / 4; ++rr) {
             const int ly = wave * (LT_H / 4) + rr, y = ty0 + ly, x = tx0 + lane;
             const bool in = y < H && x < W;
-            uint32_t w = 0;
-            if (in) w = reinterpret_cast<const uint32_t *>(d.rgbe)[(int64_t)y * W + x];
+            const uint32_t w = wc[rr];
             const int e = (int)(w >> 24);
             uint32_t f[8];
             build_features<LT_W>(t, ly, lane, f);
