@@ -25,7 +25,7 @@ constexpr int FIT_BINS_DEFAULT = 2;       // privatised copies of the fit's LDS 
 constexpr int FIT_WG_ROWS_MAX = 128;      // waves x rows per fit workgroup: <= 32768 px, so
                                           //   the workgroup's 32-bit bin totals cannot wrap
 constexpr int LCH = 16384;         // learned path: residual records per histogram workgroup
-constexpr int LH_COPIES = 4;       //   and its lane-interleaved LDS histogram copies
+constexpr int LH_COPIES = 8;       //   and its lane-interleaved LDS histogram copies
 constexpr int LEARN_W = 64, LEARN_H = 64;  // learned path: 64 x 64 px per workgroup
 constexpr int MODEL_BYTES = 7512;
 constexpr int TILE_H = 16;         // residual histogram: 16 x 128 px tiles,

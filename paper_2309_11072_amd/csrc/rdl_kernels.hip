@@ -28,8 +28,8 @@ typedef short short2v __attribute__((ext_vector_type(2)));
 __device__ int32_t g_log2f[4096];   // round(2^16 log2(1 + (i + 0.5)/4096))
 __device__ float g_exp2h[256];      // fl32(2^(j/256))
 __device__ float g_exp2l[256];      // fl32(2^(j/65536))
-__device__ float g_thr[257];        // [k] = fl32(((k - 0.5)/255)^2.2), [256] = +inf
-__device__ __align__(16) uint8_t g_glut[GAMMA_LUT_N];  // #{k : thr[k] <= bucket start}
+// Gamma quantiser table, one word per float-bit bucket (see gamma_code).
+__device__ __align__(16) uint32_t g_glut[GAMMA_LUT_N];
 
 // ITU-T T.81 Annex K, Tables K.1 and K.2 (natural order).
 constexpr int ANNEX_K[2][64] = {
@@ -279,14 +279,19 @@ __global__ void k_key_total(const ImgDesc *__restrict__ D, int n, int64_t *out2)
 // (K[u][7-x] = (-1)^u K[u][x]) on int16 pairs with v_dot2_i32_i16; this is an
 // exact refactoring of the sums, so the results equal the plain matrix form.
 // ---------------------------------------------------------------------------
-// code = #{k : thr[k] <= C}: the float's bucket (exponent + 7 mantissa bits)
-// gives the count at the bucket start, and at most one threshold lies inside
-// a bucket (checked on the host when the table is built).
-__device__ __forceinline__ int gamma_code(float C, const uint8_t *lut, const float *thr) {
-    int idx = (int)(__float_as_uint(C) >> 16) - ((127 - 20) << 7);
-    idx = min(max(idx, 0), GAMMA_LUT_N - 1);
-    int c0 = lut[idx];
-    return c0 + (C >= thr[c0 + 1] ? 1 : 0);
+// code = #{k : T[k] <= C} with T[k] = fl32(((k - 0.5)/255)^2.2).  A float's
+// bucket is its top 16 bits (exponent + 7 mantissa bits); at most one
+// threshold lies strictly inside a bucket (checked on the host when the table
+// is built).  The bucket's word holds c0 2^17 + 2^17 - t, where c0 counts the
+// thresholds <= the bucket start and t is the low 16 bits of the threshold
+// inside it (t = 2^16 if none), so adding C's low 16 bits carries into bit 17
+// exactly when C >= that threshold.  Buckets below 2^-20 and from 2 up share
+// the first and last word, which hold no threshold.
+constexpr uint32_t GAMMA_B0 = (127 - 20) << 7;
+__device__ __forceinline__ int gamma_code(float C, const uint32_t *lut) {
+    const uint32_t bits = __float_as_uint(C);
+    const uint32_t b = min(max(bits >> 16, GAMMA_B0), GAMMA_B0 + GAMMA_LUT_N - 1);
+    return (int)((lut[b - GAMMA_B0] + (bits & 0xFFFFu)) >> 17);
 }
 
 // Correctly rounded 1/D for D in [1, 2^47): the hardware reciprocal refined by
@@ -303,27 +308,29 @@ __device__ __forceinline__ float recip(float D) {
 // Global Reinhard operator, hue preserving, per pixel.  P = sigma 2^k',
 // k' = k_img + E - 136 (clamped at 40: the 1 in 1 + t is then absorbed and the
 // result is exactly the clamped one); t = P * Y * 2^-16, D = 1 + t, R = 1/D,
-// C_c = (P * (M_c + 0.5)) * R.
-__device__ __forceinline__ void tmo_px(uint32_t w, int kbase, float sigma, bool any_lit, const uint8_t *lut,
-                                       const float *thr, int &r, int &g, int &b) {
+// C_c = (P * (M_c + 0.5)) * R.  The first product is one fused multiply-add,
+// P M_c + P/2, whose single rounding is that of P (M_c + 0.5) (the sum is exact
+// before rounding).  Black pixels (E = 0, k' < -64, or no lit pixel in the
+// image: the caller passes kbase < -64 - 255 then) take k' = -200, so P = 0,
+// C = 0 and every code is 0.
+__device__ __forceinline__ void tmo_px(uint32_t w, int kbase, float sigma, const uint32_t *lut, int &r, int &g,
+                                       int &b) {
     const int E = (int)(w >> 24);
     int kp = kbase + E;
-    const bool zero = (E == 0) | (kp < -64) | !any_lit;
-    kp = min(kp, 40);
+    kp = ((E == 0) | (kp < -64)) ? -200 : min(kp, 40);
+    // P/2 and P 2^-16 are exact: P is 0 or a normal float >= 0.18 2^-64.
     const float P = ldexpf(sigma, kp);
-    const float Pl = ldexpf(sigma, kp - 16);
+    const float Ph = P * 0.5f;
+    const float Pl = P * 0x1p-16f;
     const float t = Pl * (float)lum_y(w);
     const float Dn = 1.0f + t;
     const float R = recip(Dn);
-    const float c0 = (P * ((float)(w & 255u) + 0.5f)) * R;
-    const float c1 = (P * ((float)((w >> 8) & 255u) + 0.5f)) * R;
-    const float c2 = (P * ((float)((w >> 16) & 255u) + 0.5f)) * R;
-    // Branch-free: every lane looks its three codes up (the bucket index is
-    // clamped, so the reads stay inside the tables), then unlit ones are masked.
-    const int keep = zero ? 0 : -1;
-    r = gamma_code(c0, lut, thr) & keep;
-    g = gamma_code(c1, lut, thr) & keep;
-    b = gamma_code(c2, lut, thr) & keep;
+    const float c0 = __builtin_fmaf(P, (float)(w & 255u), Ph) * R;
+    const float c1 = __builtin_fmaf(P, (float)((w >> 8) & 255u), Ph) * R;
+    const float c2 = __builtin_fmaf(P, (float)((w >> 16) & 255u), Ph) * R;
+    r = gamma_code(c0, lut);
+    g = gamma_code(c1, lut);
+    b = gamma_code(c2, lut);
 }
 
 __device__ __forceinline__ int padd(int a, int b) {
@@ -381,26 +388,28 @@ __global__ __launch_bounds__(BLK_THREADS) void k_tmo_base(const ImgDesc *__restr
     // 1 and 3) or column (phase 2) r = t / BLK_WG; two LDS transposes join the
     // phases.  Slot stride 33 words keeps every half-wave access conflict-free.
     // EXTRA also writes the tone-mapped SDRI and the quantised coefficients.
-    __shared__ __align__(16) uint8_t s_lut[GAMMA_LUT_N];
-    __shared__ float s_thr[257];
+    __shared__ __align__(16) uint32_t s_lut[GAMMA_LUT_N];
     __shared__ uint32_t s_QM[2][64];
     __shared__ uint32_t s_X[3][BLK_WG][33];
-    __shared__ int s_key[3];
+    __shared__ int s_key[2];
     const int i = find_img(D, n, blockIdx.x, 1);
     const ImgDesc d = desc_at(D, i);
     const int H = d.H, W = d.W;
-    for (int k = threadIdx.x; k < GAMMA_LUT_N / 4; k += BLK_THREADS)
-        reinterpret_cast<uint32_t *>(s_lut)[k] = reinterpret_cast<const uint32_t *>(g_glut)[k];
-    for (int k = threadIdx.x; k < 257; k += BLK_THREADS) s_thr[k] = g_thr[k];
-    if (threadIdx.x < 128) (&s_QM[0][0])[threadIdx.x] = (&g_qm[d.q - 1][0][0])[threadIdx.x];
-    if (threadIdx.x == 0) {
+    // Prologue: the last wave derives the tone map's parameters from the key
+    // statistic while the others copy the tables, so the two chains of
+    // dependent loads overlap.
+    if (threadIdx.x < BLK_THREADS - 64) {
+        for (int k = threadIdx.x; k < GAMMA_LUT_N / 4; k += BLK_THREADS - 64)
+            reinterpret_cast<uint4 *>(s_lut)[k] = reinterpret_cast<const uint4 *>(g_glut)[k];
+        if (threadIdx.x < 128) (&s_QM[0][0])[threadIdx.x] = (&g_qm[d.q - 1][0][0])[threadIdx.x];
+    } else if (threadIdx.x == BLK_THREADS - 64) {
         int k_img, f_key;
         float sigma;
         int64_t L, N;
         key_params(d.ks, d.nks, k_img, f_key, sigma, L, N);
-        s_key[0] = k_img - 136;
+        // No lit pixel: every pixel is black (k' below -64 for any E).
+        s_key[0] = N > 0 ? k_img - 136 : -100000;
         s_key[1] = __float_as_int(sigma);
-        s_key[2] = N > 0;
     }
 
     const int nbx = (W + 7) >> 3, nby = (H + 7) >> 3;
@@ -414,7 +423,6 @@ __global__ __launch_bounds__(BLK_THREADS) void k_tmo_base(const ImgDesc *__restr
     __syncthreads();
     const int kbase = s_key[0];
     const float sigma = __int_as_float(s_key[1]);
-    const bool any_lit = s_key[2] != 0;
 
     // Phase 1: lane = row r.  RGBE -> TMO -> YCbCr - 128 -> FDCT row pass; the
     // row outputs go to the slot transposed, at position r ^ (r >> 2) of
@@ -434,7 +442,7 @@ __global__ __launch_bounds__(BLK_THREADS) void k_tmo_base(const ImgDesc *__restr
 #pragma unroll
         for (int x = 0; x < 8; ++x) {
             int cr, cg, cb;
-            tmo_px(px[x], kbase, sigma, any_lit, s_lut, s_thr, cr, cg, cb);
+            tmo_px(px[x], kbase, sigma, s_lut, cr, cg, cb);
             if (EXTRA && d.sdr0 && yl < H && x0 + x < W) {
                 uint8_t *o = d.sdr0 + 3 * ((int64_t)yl * W + x0 + x);
                 o[0] = (uint8_t)cr; o[1] = (uint8_t)cg; o[2] = (uint8_t)cb;
@@ -1547,10 +1555,31 @@ __global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, in
 // records.  Workgroup g of an image takes records [k LCH, (k + 1) LCH) of
 // exponent e's bucket, where e is the exponent whose first histogram
 // workgroup (a prefix over ceil(n_e / LCH)) is the last one <= g.  Counts go
-// to LH_COPIES lane-interleaved LDS copies, then each non-zero bin to the
-// image's histogram with one atomic.
-__global__ __launch_bounds__(256) void k_lhist(const ImgDesc *__restrict__ D, int n) {
-    __shared__ uint32_t hb[LH_COPIES][6][512];
+// to LH_COPIES lane-interleaved LDS copies as 16-bit halves of 32-bit words
+// (at most LCH = 2^14 records per workgroup, so a half cannot carry), then
+// each non-zero bin to the image's histogram with one atomic.  Residuals
+// cluster near zero, so many lanes of a wave hit the same bin; the copies
+// split those collisions LH_COPIES ways, and their odd word stride puts the
+// copies of one bin in different LDS banks.
+constexpr int LH_STRIDE = 6 * 256 + 1;
+__device__ __forceinline__ void lh_inc(uint32_t *h, int hg, uint32_t v) {
+    atomicAdd(&h[hg * 256 + (v >> 1)], 1u << ((v & 1u) << 4));
+}
+
+constexpr int LH_THREADS = 512;
+__device__ __forceinline__ void lh_count(uint32_t *mine, uint64_t r) {
+    if (r == ~0ull) return;
+    const uint32_t a = (uint32_t)r, b = (uint32_t)(r >> 32);
+    lh_inc(mine, 0, a & 511u);
+    lh_inc(mine, 1, (a >> 9) & 511u);
+    lh_inc(mine, 2, a >> 18);
+    lh_inc(mine, 3, b & 511u);
+    lh_inc(mine, 4, (b >> 9) & 511u);
+    lh_inc(mine, 5, b >> 18);
+}
+
+__global__ __launch_bounds__(LH_THREADS) void k_lhist(const ImgDesc *__restrict__ D, int n) {
+    __shared__ uint32_t hb[LH_COPIES * LH_STRIDE];
     const int i = find_img(D, n, blockIdx.x, 6);
     const ImgDesc d = desc_at(D, i);
     const int g = blockIdx.x - d.wg_lhist;
@@ -1566,26 +1595,37 @@ __global__ __launch_bounds__(256) void k_lhist(const ImgDesc *__restrict__ D, in
     const uint32_t ne = (uint32_t)d.sums[e * NSUM];
     const uint32_t first = d.lbk[513 + e] + k * LCH;
     const uint32_t cnt = min((uint32_t)LCH, ne - k * LCH);
-    for (int q = threadIdx.x; q < LH_COPIES * 6 * 512; q += 256) (&hb[0][0][0])[q] = 0;
+    for (int q = threadIdx.x; q < LH_COPIES * LH_STRIDE; q += LH_THREADS) hb[q] = 0;
     __syncthreads();
-    uint32_t(*mine)[512] = hb[threadIdx.x & (LH_COPIES - 1)];
+    uint32_t *mine = hb + (threadIdx.x & (LH_COPIES - 1)) * LH_STRIDE;
     const uint64_t *rp = d.lrec + first;
-    for (uint32_t j = threadIdx.x; j < cnt; j += 256) {
-        const uint64_t r = rp[j];
-        const uint32_t a = (uint32_t)r, b = (uint32_t)(r >> 32);
-        atomicAdd(&mine[0][a & 511u], 1u);
-        atomicAdd(&mine[1][(a >> 9) & 511u], 1u);
-        atomicAdd(&mine[2][a >> 18], 1u);
-        atomicAdd(&mine[3][b & 511u], 1u);
-        atomicAdd(&mine[4][(b >> 9) & 511u], 1u);
-        atomicAdd(&mine[5][b >> 18], 1u);
+    // Batches of U records per thread; the next batch's loads are issued
+    // before the current one is counted (a valid record never has its top
+    // bits set, so ~0 marks a slot past the end).
+    constexpr int U = 4, STEP = LH_THREADS * U;
+    uint64_t cur[U], nxt[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint32_t j = LH_THREADS * u + threadIdx.x;
+        cur[u] = j < cnt ? rp[j] : ~0ull;
+    }
+    for (uint32_t j0 = 0; j0 < cnt; j0 += STEP) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t j = j0 + STEP + LH_THREADS * u + threadIdx.x;
+            nxt[u] = j < cnt ? rp[j] : ~0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) lh_count(mine, cur[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) cur[u] = nxt[u];
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < 6 * 511; q += 256) {
+    for (int q = threadIdx.x; q < 6 * 511; q += LH_THREADS) {
         const int hgram = q / 511, v = q - hgram * 511;  // hgram = estimator * 3 + channel
         uint32_t c = 0;
 #pragma unroll
-        for (int cp = 0; cp < LH_COPIES; ++cp) c += hb[cp][hgram][v];
+        for (int cp = 0; cp < LH_COPIES; ++cp) c += (hb[cp * LH_STRIDE + hgram * 256 + (v >> 1)] >> ((v & 1) << 4)) & 0xFFFFu;
         if (c) atomicAdd(&d.lhist[((size_t)hgram * 256 + e) * 511 + v], c);
     }
 }
@@ -1776,7 +1816,7 @@ hipError_t upload_tables(int *bad_table) {
     *bad_table = 0;
     static int32_t log2f[4096];
     static float eh[256], el[256], thr[257];
-    static uint8_t glut[GAMMA_LUT_N];
+    static uint32_t glut[GAMMA_LUT_N];
     for (int k = 0; k < 4096; ++k) log2f[k] = (int32_t)std::llround(65536.0 * std::log2(1.0 + (k + 0.5) / 4096.0));
     for (int j = 0; j < 256; ++j) {
         eh[j] = (float)std::exp2(j / 256.0);
@@ -1785,24 +1825,32 @@ hipError_t upload_tables(int *bad_table) {
     thr[0] = 0.0f;
     for (int k = 1; k < 256; ++k) thr[k] = (float)std::pow((k - 0.5) / 255.0, 2.2);
     thr[256] = INFINITY;
-    // Bucket b covers floats whose top 16 bits are b + ((127 - 20) << 7).
+    // Bucket b covers floats whose top 16 bits are b + GAMMA_B0.
     for (int b = 0; b < GAMMA_LUT_N; ++b) {
-        uint32_t lo_bits = (uint32_t)(b + ((127 - 20) << 7)) << 16;
+        uint32_t lo_bits = (uint32_t)(b + GAMMA_B0) << 16;
         uint32_t hi_bits = lo_bits + (1u << 16);
         float lo, hi;
         memcpy(&lo, &lo_bits, 4);
         memcpy(&hi, &hi_bits, 4);
         int cnt = 0, inside = 0;
+        uint32_t t = 1u << 16;
         for (int k = 1; k < 256; ++k) {
-            if (thr[k] <= lo) cnt++;
-            else if (thr[k] < hi) inside++;
+            if (thr[k] <= lo) {
+                cnt++;
+            } else if (thr[k] < hi) {
+                inside++;
+                uint32_t tb;
+                memcpy(&tb, &thr[k], 4);
+                t = tb & 0xFFFFu;  // >= 1: the threshold is above the bucket start
+            }
         }
         if (inside > 1) *bad_table = 1;
-        glut[b] = (uint8_t)cnt;
+        // The clamped end buckets stand for every float below / above them.
+        if ((b == 0 || b == GAMMA_LUT_N - 1) && inside) *bad_table = 1;
+        glut[b] = ((uint32_t)cnt << 17) + (1u << 17) - t;
     }
-    // Below the first bucket every code is 0; from the last bucket up every
-    // code is 255 or 254 + one compare.
-    if (thr[1] <= ldexpf(1.0f, -20)) *bad_table = 1;
+    // Below the first bucket every code is 0, from the last one up 255.
+    if (thr[1] <= ldexpf(1.0f, -20) || thr[255] >= 2.0f) *bad_table = 1;
     static uint32_t qm[100][2][64];
     for (int q = 1; q <= 100; ++q) {
         const int sc = q < 50 ? 5000 / q : 200 - 2 * q;  // IJG quality scaling
@@ -1817,7 +1865,6 @@ hipError_t upload_tables(int *bad_table) {
     if ((e = hipMemcpyToSymbol(HIP_SYMBOL(g_log2f), log2f, sizeof log2f)) != hipSuccess) return e;
     if ((e = hipMemcpyToSymbol(HIP_SYMBOL(g_exp2h), eh, sizeof eh)) != hipSuccess) return e;
     if ((e = hipMemcpyToSymbol(HIP_SYMBOL(g_exp2l), el, sizeof el)) != hipSuccess) return e;
-    if ((e = hipMemcpyToSymbol(HIP_SYMBOL(g_thr), thr, sizeof thr)) != hipSuccess) return e;
     if ((e = hipMemcpyToSymbol(HIP_SYMBOL(g_glut), glut, sizeof glut)) != hipSuccess) return e;
     return hipSuccess;
 }
@@ -1868,7 +1915,7 @@ void launch_learn(const ImgDesc *d, int n, int wgs, hipStream_t s) {
     hipLaunchKernelGGL(k_learn, dim3(wgs), dim3(256), 0, s, d, n);
 }
 void launch_lhist(const ImgDesc *d, int n, int wgs, hipStream_t s) {
-    hipLaunchKernelGGL(k_lhist, dim3(wgs), dim3(256), 0, s, d, n);
+    hipLaunchKernelGGL(k_lhist, dim3(wgs), dim3(LH_THREADS), 0, s, d, n);
 }
 void launch_select(const ImgDesc *d, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_select, dim3(256 * n), dim3(256), 0, s, d, n);
