@@ -112,12 +112,12 @@ struct Grid {
 };
 
 // Point the learned-path buffers of each image (scratch already bound) into
-// an estimate buffer of sum(3*H*W) bytes, a record buffer of sum(H*W) words
+// an estimate buffer of sum(H*W) words, a record buffer of sum(H*W) words
 // and n histogram blocks.
 void bind_learn(std::vector<ImgDesc> &v, uint8_t *ml, uint64_t *rec, uint32_t *lhist) {
     size_t off = 0;
     for (size_t k = 0; k < v.size(); ++k) {
-        v[k].ml = ml + 3 * off;
+        v[k].ml = ml + 4 * off;
         v[k].lrec = rec + off;
         v[k].lhist = lhist + k * lhist_words();
         v[k].lbk = reinterpret_cast<uint32_t *>(v[k].sums - SCR_SUMS + SCR_LBK);
@@ -258,7 +258,7 @@ int build_plan(Plan &e, const std::vector<ImgDesc> &v, bool learned) {
     std::vector<ImgDesc> dv = v;
     for (size_t k = 0; k < n; ++k) bind_scratch(dv[k], e.d_scratch + k * SCRATCH_I64);
     if (learned) {
-        HIPCHK(hipMalloc(&e.d_ml, 3 * total_px(v)));
+        HIPCHK(hipMalloc(&e.d_ml, 4 * total_px(v)));
         HIPCHK(hipMalloc(&e.d_lrec, total_px(v) * sizeof(uint64_t)));
         HIPCHK(hipMalloc(&e.d_lhist, n * lhist_words() * sizeof(uint32_t)));
         HIPCHK(hipMemset(e.d_lhist, 0, n * lhist_words() * sizeof(uint32_t)));

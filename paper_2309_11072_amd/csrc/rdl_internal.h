@@ -57,7 +57,7 @@ struct ImgDesc {
     int32_t *status;       // decode only, optional
     uint8_t *out_rgbe;     // decode only
     int64_t *hist;         // [3][511] residual histograms
-    uint8_t *ml;           // learned path: [H][W][3] learned estimates
+    uint8_t *ml;           // learned path: [H][W] learned estimates, R | G << 8 | B << 16 words
     uint32_t *lhist;       // learned path: [2][3][256][511] residual histograms (estimator, channel)
     uint64_t *lrec;        // learned path: [H*W] residual records, grouped by exponent
     uint32_t *lbk;         // learned path: [256] record cursors, [257] first histogram

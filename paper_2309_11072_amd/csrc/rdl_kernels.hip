@@ -779,12 +779,14 @@ __device__ __forceinline__ void gf_row_finish(GfWindow &g, int slot, const RowRa
     g.hhi[slot] = (h >> 8) & 0xFFu;
 }
 
-// Calls row(y, s, w) for y = ya .. yb-1 in order, with s[c][j] = S*_c of the
-// lane's pixels x+j of row y and w[j] their RGBE words.  The whole wave must
-// call it (DPP); ya < yb is uniform per wave.
+// Calls row(y, s, w, x) for y = ya .. yb-1 in order, with s[c][j] = S*_c of
+// the lane's pixels x+j of row y, w[j] their RGBE words and, if XW, x[j] their
+// words of a second 4-byte-per-pixel buffer xw (loaded like the RGBE words).
+// The whole wave must call it (DPP); ya < yb is uniform per wave.
 constexpr int WALK_CH = 4;
-template <class RowFn>
-__device__ __forceinline__ void strip_walk(const ImgDesc &d, const StripPos &sp, RowFn &&row) {
+template <bool XW, class RowFn>
+__device__ __forceinline__ void strip_walk_x(const ImgDesc &d, const StripPos &sp, const uint8_t *__restrict__ xw,
+                                             RowFn &&row) {
     const int H = d.H, W = d.W;
     // The 16-byte read stays inside S on every row but the last (there the
     // lane's bytes are followed by a whole row); on the last row it must end
@@ -804,13 +806,14 @@ __device__ __forceinline__ void strip_walk(const ImgDesc &d, const StripPos &sp,
     }
     for (int y0 = sp.ya; y0 < sp.yb; y0 += WALK_CH) {
         RowRaw nr[WALK_CH];
-        uint32_t w[WALK_CH][4];
+        uint32_t w[WALK_CH][4], x[WALK_CH][4];
 #pragma unroll
         for (int k = 0; k < WALK_CH; ++k) {
             // Rows past the strip repeat its last needed row (cache hits, unused).
             const int ys = min(min(y0 + k + 1, sp.yb), H - 1);
             gf_row_issue(nr[k], d.sdr, W, ys, fast(ys), sp);
             strip_rgbe4(d.rgbe, W, min(y0 + k, sp.yb - 1), sp, w[k]);
+            if (XW) strip_rgbe4(xw, W, min(y0 + k, sp.yb - 1), sp, x[k]);
         }
 #pragma unroll
         for (int k = 0; k < WALK_CH; ++k) {
@@ -820,10 +823,16 @@ __device__ __forceinline__ void strip_walk(const ImgDesc &d, const StripPos &sp,
                 int sv[3][4];
                 gf_quad(g, sp.lane, sv);
                 gf_roll(g);
-                row(y, sv, w[k]);
+                row(y, sv, w[k], x[k]);
             }
         }
     }
+}
+
+template <class RowFn>
+__device__ __forceinline__ void strip_walk(const ImgDesc &d, const StripPos &sp, RowFn &&row) {
+    strip_walk_x<false>(d, sp, nullptr, [&](int y, const int (&s)[3][4], const uint32_t (&w)[4],
+                                            const uint32_t (&)[4]) { row(y, s, w); });
 }
 
 // ---------------------------------------------------------------------------
@@ -1116,10 +1125,11 @@ __global__ __launch_bounds__(STRIP_THREADS) void k_resid(const ImgDesc *__restri
     int16_t *r = (int16_t *)d.resid;
     uint8_t *Ep = d.resid + 6 * npx;
     const bool al = (W & 3) == 0 && ((reinterpret_cast<uintptr_t>(d.resid) & 7) == 0);
-    strip_walk(d, sp, [&](int y, const int (&s)[3][4], const uint32_t (&w)[4]) {
+    // Residuals of the lane's four pixels of row y; ml[j] (learned path) holds
+    // M_L of pixel j as R | G << 8 | B << 16, used where the region is flagged.
+    const auto emit = [&](int y, const int (&s)[3][4], const uint32_t (&w)[4], const uint32_t *ml) {
         if (sp.x >= W) return;
         const int64_t ro = (int64_t)uniform(y) * W;  // row bases are scalar
-        const uint8_t *mlr = learned ? d.ml + 3 * ro : nullptr;
         int rv[3][4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -1128,7 +1138,7 @@ __global__ __launch_bounds__(STRIP_THREADS) void k_resid(const ImgDesc *__restri
             for (int c = 0; c < 3; ++c) {
                 const int2 ab = s_ab[c][e];
                 int est = mstar(ab, s[c][j]);
-                if (learned && s_fl[c][e] && sp.x + j < W) est = mlr[sp.xo3 + 3u * j + c];
+                if (ml && s_fl[c][e]) est = (int)((ml[j] >> (8 * c)) & 255u);
                 rv[c][j] = (int)((w[j] >> (8 * c)) & 255u) - est;
             }
         }
@@ -1152,7 +1162,12 @@ __global__ __launch_bounds__(STRIP_THREADS) void k_resid(const ImgDesc *__restri
                 er[sp.x + j] = (uint8_t)(w[j] >> 24);
             }
         }
-    });
+    };
+    if (learned)
+        strip_walk_x<true>(d, sp, d.ml, [&](int y, const int (&s)[3][4], const uint32_t (&w)[4],
+                                            const uint32_t (&x)[4]) { emit(y, s, w, x); });
+    else
+        strip_walk(d, sp, [&](int y, const int (&s)[3][4], const uint32_t (&w)[4]) { emit(y, s, w, nullptr); });
 }
 
 // ---------------------------------------------------------------------------
@@ -1522,10 +1537,10 @@ __global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, in
                 for (int c = 0; c < 3; ++c) {
                     const int m = (int)((w >> (8 * c)) & 255u);
                     const int mlc = (int)((ml >> (8 * c)) & 255u);
-                    d.ml[3 * o + c] = (uint8_t)mlc;
                     rs[c] = m - mstar(s_ab[c][e], s[c]);
                     rl[c] = m - mlc;
                 }
+                reinterpret_cast<uint32_t *>(d.ml)[o] = ml;
                 rec[rr] = lrec_pack(rs, rl);
                 where[rr] = (uint32_t)e | (atomicAdd(&s_cnt[e], 1u) << 8);
             }
