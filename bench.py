@@ -15,6 +15,8 @@ Also measured, outside the timed region:
   * the batched encoder on 64 uneven images (~275 Mpx, one launch per stage);
   * the learned estimator with per-region SLR fallback: bits/pixel against
     plain SLR on 16 held-out 1920x1080 images, and its throughput;
+  * 256 uneven images of 1 to 33 MP (~4.4 Gpx) batched, plain and learned:
+    Mpixel/s, GB/s, bits/pixel, lossless round trip of every image;
   * the CPU oracle on the host's cores, on the same image (cpu_baseline).
 """
 import argparse
@@ -147,6 +149,36 @@ def time_calls(fn, steps, stream):
     return e0.elapsed_time(e1) / steps
 
 
+def tune_classes(codec, imgs, specs, items):
+    """One autotuning per size class floor(log2(H W)), on its largest image."""
+    best = {}
+    for im, s, it in zip(imgs, specs, items):
+        c = (s.H * s.W).bit_length() - 1
+        if c not in best or s.H * s.W > best[c][0]:
+            best[c] = (s.H * s.W, im, s.q, it[2:])
+    for _, im, qq, o in best.values():
+        codec.autotune(im, qq, o, reps=5)
+    return len(best)
+
+
+def cond_bits(resid, H, W):
+    """Bits/pixel of the three residual planes coded given the exponent:
+    sum over (channel, E) of sum_v h log2(n_E / h), over H W (computed on the
+    GPU from the residual buffer).  This is the code length the per-region
+    estimator selection minimises."""
+    import torch
+    npx = H * W
+    r = resid[:6 * npx].view(torch.int16).reshape(3, npx).long()
+    E = resid[6 * npx:7 * npx].long()
+    tot = 0.0
+    for c in range(3):
+        h = torch.bincount(E * 511 + r[c] + 255, minlength=256 * 511).reshape(256, 511).double()
+        n = h.sum(dim=1, keepdim=True)
+        nz = h > 0
+        tot += float((h[nz] * torch.log2((n.expand_as(h))[nz] / h[nz])).sum())
+    return tot / npx
+
+
 def resid_bits(codec, resid, H, W):
     h = codec.resid_hist(resid, H, W).cpu().numpy()
     return sum(entropy_bits(h[c].tolist()) for c in range(3))
@@ -163,6 +195,8 @@ def main():
     ap.add_argument("--profile-reps", type=int, default=50)
     ap.add_argument("--batch-steps", type=int, default=10, help="timed launches of the 64-image batch (0 = skip)")
     ap.add_argument("--learned-steps", type=int, default=20, help="timed learned encodes (0 = skip)")
+    ap.add_argument("--large-steps", type=int, default=3,
+                    help="timed launches of the 256-image batch, plain and learned (0 = skip)")
     ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch shapes")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -252,15 +286,8 @@ def main():
                 say("batch images generated: %d" % (k + 1))
         items = [(im, s.q) + tuple(codec.alloc_outputs(s.H, s.W)) for im, s in zip(imgs, specs)]
         npx = sum(s.H * s.W for s in specs)
-        if not args.no_tune:  # one tuning per size class, on its largest image
-            best = {}
-            for im, s, it in zip(imgs, specs, items):
-                c = (s.H * s.W).bit_length() - 1
-                if c not in best or s.H * s.W > best[c][0]:
-                    best[c] = (s.H * s.W, im, s.q, it[2:])
-            for _, im, qq, o in best.values():
-                codec.autotune(im, qq, o, reps=5)
-            say("batch tuned for %d size classes" % len(best))
+        if not args.no_tune:
+            say("batch tuned for %d size classes" % tune_classes(codec, imgs, specs, items))
         for _ in range(3):
             codec.encode_batch(items)
         ms_b = time_calls(lambda: codec.encode_batch(items), args.batch_steps, stream)
@@ -283,6 +310,7 @@ def main():
             codec.set_model(fh.read())
         say("learned estimator: evaluating")
         bits = {0: 0.0, 1: 0.0}
+        cbits = {0: 0.0, 1: 0.0}
         npx_eval = 0
         ok = True
         regions = [0, 0]
@@ -293,6 +321,7 @@ def main():
                 codec.set_estimator(mode)
                 codec.encode_enh(xe, s.q, out=oe)
                 bits[mode] += resid_bits(codec, oe[2], s.H, s.W) * s.H * s.W
+                cbits[mode] += cond_bits(oe[2], s.H, s.W) * s.H * s.W
                 if mode == 1:
                     ok &= bool(torch.equal(codec.decode_enh(oe[0], oe[1], oe[2], s.H, s.W), xe))
                     he = rdl.header_from_bytes(oe[1])
@@ -309,10 +338,55 @@ def main():
         learned = {"eval": "16 held-out 1920x1080 images (sigma_L 4, 5% speculars, q 75)",
                    "bits_per_pixel_slr": round(bits[0] / npx_eval, 4),
                    "bits_per_pixel_learned": round(bits[1] / npx_eval, 4),
+                   "bits_per_pixel_given_E_slr": round(cbits[0] / npx_eval, 4),
+                   "bits_per_pixel_given_E_learned": round(cbits[1] / npx_eval, 4),
                    "regions_learned": regions[0], "regions": regions[1], "lossless": ok,
                    "Mpixel_s": round(H * W / (ms_l * 1e-3) / 1e6, 1), "ms_per_step": round(ms_l, 5),
                    "throughput_workload": "the 3840x2160 benchmark image",
                    "model_hash": "%016x" % int(rdl.header_from_bytes(outl[1])["model_hash"])}
+        del outl
+
+    # ---- 256 uneven images up to 33 MP: learned + fallback vs plain SLR ------
+    large = None
+    if learned is not None and args.large_steps > 0:
+        torch.cuda.empty_cache()
+        specs = synth.config5()
+        imgs = []
+        for k, s in enumerate(specs):
+            imgs.append(s.make_torch())
+            if k % 64 == 63:
+                say("large batch images generated: %d" % (k + 1))
+        items = [(im, s.q) + tuple(codec.alloc_outputs(s.H, s.W)) for im, s in zip(imgs, specs)]
+        npx = sum(s.H * s.W for s in specs)
+        if not args.no_tune:
+            say("large batch tuned for %d size classes" % tune_classes(codec, imgs, specs, items))
+        res = {}
+        for mode in (0, 1):
+            codec.set_estimator(mode)
+            for _ in range(2):
+                codec.encode_batch(items)
+            ms = time_calls(lambda: codec.encode_batch(items), args.large_steps, stream)
+            bits = sum(resid_bits(codec, it[4], s.H, s.W) * s.H * s.W for it, s in zip(items, specs)) / npx
+            cb = sum(cond_bits(it[4], s.H, s.W) * s.H * s.W for it, s in zip(items, specs)) / npx
+            ok = all(torch.equal(codec.decode_enh(it[2], it[3], it[4], s.H, s.W), im)
+                     for it, s, im in zip(items, specs, imgs))
+            flagged = sum(int(rdl.header_from_bytes(it[3])["flag"].sum()) for it in items) if mode else 0
+            res[mode] = (ms, bits, ok, flagged, cb)
+            say("large batch, %s: %.2f ms (%.1f Mpixel/s)" % ("learned" if mode else "plain", ms,
+                                                             npx / (ms * 1e-3) / 1e6))
+        codec.set_estimator(0)
+        large = {"workload": "256 uneven RGBE images of 1 to 33 MP (config-5 sizes and parameters, drawn on the "
+                             "GPU), one launch per stage", "images": len(specs), "Mpixel": round(npx / 1e6, 1)}
+        for mode, name in ((0, "slr"), (1, "learned")):
+            ms, bits, ok, flagged, cb = res[mode]
+            gbps = PIPELINE_BYTES_PER_PX * npx / (ms * 1e-3) / 1e9
+            large[name] = {"ms_per_step": round(ms, 3), "Mpixel_s": round(npx / (ms * 1e-3) / 1e6, 1),
+                           "pipeline_algorithmic_GBps": round(gbps, 1), "bits_per_pixel": round(bits, 4),
+                           "bits_per_pixel_given_E": round(cb, 4),
+                           "lossless": ok}
+        large["learned"]["regions_learned"] = res[1][3]
+        del imgs, items
+        torch.cuda.empty_cache()
 
     line = {
         "metric": "encoded Mpixel/s on 1 MI355X + residual bits/pixel, learned vs SLR, lossless",
@@ -332,6 +406,7 @@ def main():
         "device_copy_GBps": round(copy_gbps, 1),
         "batch": batch,
         "learned": learned,
+        "large_batch": large,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
