@@ -43,9 +43,9 @@ constexpr int ANNEX_K[2][64] = {
      99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99, 99}};
 
 // Quantiser constants of every quality, filled once by upload_tables():
-// g_qm[q - 1][t][e] = M | Q << 24 with Q the IJG-scaled Annex K entry and
-// M = ceil(2^20 / Q).
-__device__ uint32_t g_qm[100][2][64];
+// g_qm[q - 1][t][e] = {M | Q << 24, h, even, 0} with Q the IJG-scaled Annex K
+// entry, M = ceil(2^20 / Q), h = floor(Q / 2) and even = -1 if Q is even, else 0.
+__device__ uint4 g_qm[100][2][64];
 
 // DCT basis K[u][x] = round(2^13 c_u cos((2x+1) u pi / 16)), c_0 = 1/sqrt(8),
 // c_u = 1/2: the 8-point DCT-II scaled by 2^13.
@@ -369,16 +369,19 @@ __device__ __forceinline__ void idct1(int E0, int E1, int O0, int O1, int bias, 
     }
 }
 
-// Per-lane constants of the quantiser for coefficient (v, u): qm = M | Q << 24
-// with M = ceil(2^20 / Q), so floor(a / Q) == (a * M) >> 20 for a < 4096.
-__device__ __forceinline__ int quant_dequant(int F, uint32_t qm, int &Fq) {
-    const int f = F >> 15;
-    const int sg = f >> 31;                          // 0 or -1
-    const uint32_t af = (uint32_t)((f ^ sg) - sg);   // |f|
-    const uint32_t qa = __umul24(af + (qm >> 25), qm) >> 20;
-    Fq = ((int)qa ^ sg) - sg;
-    const int da = (int)__umul24(qa, qm >> 24);
-    return (da ^ sg) - sg;
+// Quantise and dequantise coefficient F (before its >> 15) with the
+// constants qc of its table entry: Fq = sign(f) floor((|f| + h) / Q), f = F >> 15,
+// returns Fq Q.  Rounding half away from zero equals floor((f + h - e) / Q)
+// for either sign, e = 1 for negative f and even Q (no ties exist for odd Q),
+// and that floor is (a M + 2^11) >> 20 with a = f + h - e: the magic
+// multiplier's relative error stays below 2^-9 while |a| <= 1151, and the
+// 2^11 offset lifts exact multiples of Q above the truncation.  The 8x8
+// transforms of 8-bit level-shifted samples keep |f| <= 1024, so every
+// product fits in 31 bits.
+__device__ __forceinline__ int quant_dequant(int F, uint4 qc, int &Fq) {
+    const int a = (F >> 15) + (int)qc.y + ((F >> 31) & (int)qc.z);
+    Fq = (__mul24(a, (int)qc.x) + 2048) >> 20;  // the low 24 bits of qc.x are M
+    return __mul24(Fq, (int)(qc.x >> 24));
 }
 
 template <bool EXTRA>
@@ -389,7 +392,7 @@ __global__ __launch_bounds__(BLK_THREADS) void k_tmo_base(const ImgDesc *__restr
     // phases.  Slot stride 33 words keeps every half-wave access conflict-free.
     // EXTRA also writes the tone-mapped SDRI and the quantised coefficients.
     __shared__ __align__(16) uint32_t s_lut[GAMMA_LUT_N];
-    __shared__ uint32_t s_QM[2][64];
+    __shared__ uint4 s_QM[2][64];
     __shared__ uint32_t s_X[3][BLK_WG][33];
     __shared__ int s_key[2];
     const int i = find_img(D, n, blockIdx.x, 1);
@@ -477,11 +480,6 @@ __global__ __launch_bounds__(BLK_THREADS) void k_tmo_base(const ImgDesc *__restr
     for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int k = 0; k < 4; ++k) col[c][k] = (int)s_X[c][j][u * 4 + k];
-    uint32_t qm[2][8];
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int v = 0; v < 8; ++v) qm[t][v] = s_QM[t][v * 8 + u];
     __syncthreads();
     if (active) {
         const int H8 = nby * 8, W8 = nbx * 8;
@@ -495,7 +493,7 @@ __global__ __launch_bounds__(BLK_THREADS) void k_tmo_base(const ImgDesc *__restr
 #pragma unroll
             for (int v = 0; v < 8; ++v) {
                 int Fq;
-                dq[v] = quant_dequant(F[v], qm[c ? 1 : 0][v], Fq);
+                dq[v] = quant_dequant(F[v], s_QM[c ? 1 : 0][v * 8 + u], Fq);
                 if (EXTRA && d.dct) d.dct[((int64_t)c * H8 + by * 8 + v) * W8 + x0 + u] = (int16_t)Fq;
             }
             int t[8];
@@ -1866,13 +1864,16 @@ hipError_t upload_tables(int *bad_table) {
     }
     // Below the first bucket every code is 0, from the last one up 255.
     if (thr[1] <= ldexpf(1.0f, -20) || thr[255] >= 2.0f) *bad_table = 1;
-    static uint32_t qm[100][2][64];
+    static uint32_t qm[100][2][64][4];
     for (int q = 1; q <= 100; ++q) {
         const int sc = q < 50 ? 5000 / q : 200 - 2 * q;  // IJG quality scaling
         for (int t = 0; t < 2; ++t)
             for (int k = 0; k < 64; ++k) {
                 const uint32_t Q = (uint32_t)std::min(std::max((ANNEX_K[t][k] * sc + 50) / 100, 1), 255);
-                qm[q - 1][t][k] = (((1u << 20) + Q - 1u) / Q) | (Q << 24);
+                qm[q - 1][t][k][0] = (((1u << 20) + Q - 1u) / Q) | (Q << 24);
+                qm[q - 1][t][k][1] = Q / 2;
+                qm[q - 1][t][k][2] = (Q & 1u) ? 0u : 0xFFFFFFFFu;
+                qm[q - 1][t][k][3] = 0;
             }
     }
     hipError_t e;

@@ -73,3 +73,53 @@ def test_gf_packed_fields_never_carry():
     the largest sum, 64 * 255 + 32, stays below 2^16, and >> 6 of it is 255."""
     top = 64 * 255 + 32
     assert top < 1 << 16 and top >> 6 == 255
+
+
+# ---------------------------------------------------------------------------
+# Base layer: bound of the quantiser's input and its signed magic-multiplier form.
+def dct_basis():
+    """K[u][x] = round(2^13 c_u cos((2x + 1) u pi / 16)), c_0 = 1/sqrt(8), else 1/2."""
+    import math
+    return np.array([[round(8192 * (math.sqrt(1 / 8) if u == 0 else 0.5) * math.cos((2 * x + 1) * u * math.pi / 16))
+                      for x in range(8)] for u in range(8)], dtype=np.int64)
+
+
+def test_quantiser_input_bound():
+    """f = F >> 15 of the integer FDCT (row pass (T + 2^10) >> 11, column pass
+    + 2^14) stays within +-1024 for every 8x8 block of level-shifted samples in
+    [-128, 128] (Y - 128 reaches 127, Cb - 128 and Cr - 128 reach 128).  Rows
+    are independent inputs and both passes are monotone in them, so each
+    column's extremes come from sign patterns: the maximum below is exact."""
+    K = dct_basis()
+    lo, hi = -128, 128
+    best = 0
+    for u in range(8):
+        tmax = (int((K[u] * np.where(K[u] > 0, hi, lo)).sum()) + 1024) >> 11
+        tmin = (int((K[u] * np.where(K[u] > 0, lo, hi)).sum()) + 1024) >> 11
+        for v in range(8):
+            fmax = (sum(int(K[v][y]) * (tmax if K[v][y] > 0 else tmin) for y in range(8)) + 16384) >> 15
+            fmin = (sum(int(K[v][y]) * (tmin if K[v][y] > 0 else tmax) for y in range(8)) + 16384) >> 15
+            best = max(best, abs(fmax), abs(fmin))
+    assert best == 1024
+    # brute force on random blocks never exceeds it
+    rng = np.random.default_rng(3)
+    X = rng.integers(lo, hi + 1, (2000, 8, 8))
+    T = (np.einsum("ux,byx->byu", K, X) + 1024) >> 11
+    F = (np.einsum("vy,byu->bvu", K, T) + 16384) >> 15
+    assert np.abs(F).max() <= 1024
+
+
+def test_quantiser_signed_magic_form_equals_definition():
+    """sign(f) floor((|f| + h) / Q) == (a M + 2^11) >> 20 with a = f + h - e,
+    e = [f < 0 and Q even], M = ceil(2^20 / Q), h = floor(Q / 2): every Q in
+    [1, 255], every f in [-1024, 1024]; a and M fit the 24-bit multiplier and
+    the sum 32 bits."""
+    f = np.arange(-1024, 1025, dtype=np.int64)
+    for Q in range(1, 256):
+        h, M = Q // 2, ((1 << 20) + Q - 1) // Q
+        ref = np.sign(f) * ((np.abs(f) + h) // Q)
+        a = f + h - ((f < 0) & (Q % 2 == 0))
+        assert np.abs(a).max() < 1 << 23 and M < 1 << 23
+        t = a * M + 2048
+        assert np.abs(t).max() < 1 << 31
+        assert np.array_equal(t >> 20, ref), Q
