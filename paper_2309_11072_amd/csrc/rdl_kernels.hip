@@ -305,21 +305,22 @@ __device__ __forceinline__ float recip(float D) {
     return __builtin_fmaf(e, r0, r0);
 }
 
-// Global Reinhard operator, hue preserving, per pixel.  P = sigma 2^k',
-// k' = k_img + E - 136 (clamped at 40: the 1 in 1 + t is then absorbed and the
-// result is exactly the clamped one); t = P * Y * 2^-16, D = 1 + t, R = 1/D,
-// C_c = (P * (M_c + 0.5)) * R.  The first product is one fused multiply-add,
-// P M_c + P/2, whose single rounding is that of P (M_c + 0.5) (the sum is exact
-// before rounding).  Black pixels (E = 0, k' < -64, or no lit pixel in the
-// image: the caller passes kbase < -64 - 255 then) take k' = -200, so P = 0,
-// C = 0 and every code is 0.
-__device__ __forceinline__ void tmo_px(uint32_t w, int kbase, float sigma, const uint32_t *lut, int &r, int &g,
-                                       int &b) {
-    const int E = (int)(w >> 24);
-    int kp = kbase + E;
-    kp = ((E == 0) | (kp < -64)) ? -200 : min(kp, 40);
+// Global Reinhard operator, hue preserving.  Per image, for each exponent E:
+// P(E) = sigma 2^k', k' = k_img + E - 136 (clamped at 40: the 1 in 1 + t is
+// then absorbed and the result is exactly the clamped one), and P = 0 for
+// black pixels (E = 0, k' < -64, or nothing lit in the image); tmo_p fills
+// that table.  Per pixel: t = P Y 2^-16, D = 1 + t, R = 1/D,
+// C_c = (P (M_c + 0.5)) R, the first product as one fused multiply-add
+// P M_c + P/2 whose single rounding is that of P (M_c + 0.5) (the sum is
+// exact before rounding).  With P = 0 every C is 0 and every code 0.
+__device__ __forceinline__ float tmo_p(int E, int kbase, float sigma) {
+    const int kp = kbase + E;
+    return ((E == 0) | (kp < -64)) ? 0.0f : ldexpf(sigma, min(kp, 40));
+}
+
+__device__ __forceinline__ void tmo_px(uint32_t w, const float *ptab, const uint32_t *lut, int &r, int &g, int &b) {
     // P/2 and P 2^-16 are exact: P is 0 or a normal float >= 0.18 2^-64.
-    const float P = ldexpf(sigma, kp);
+    const float P = ptab[w >> 24];
     const float Ph = P * 0.5f;
     const float Pl = P * 0x1p-16f;
     const float t = Pl * (float)lum_y(w);
@@ -394,7 +395,7 @@ __global__ __launch_bounds__(BLK_THREADS) void k_tmo_base(const ImgDesc *__restr
     __shared__ __align__(16) uint32_t s_lut[GAMMA_LUT_N];
     __shared__ uint4 s_QM[2][64];
     __shared__ uint32_t s_X[3][BLK_WG][33];
-    __shared__ int s_key[2];
+    __shared__ float s_ptab[256];
     const int i = find_img(D, n, blockIdx.x, 1);
     const ImgDesc d = desc_at(D, i);
     const int H = d.H, W = d.W;
@@ -405,14 +406,23 @@ __global__ __launch_bounds__(BLK_THREADS) void k_tmo_base(const ImgDesc *__restr
         for (int k = threadIdx.x; k < GAMMA_LUT_N / 4; k += BLK_THREADS - 64)
             reinterpret_cast<uint4 *>(s_lut)[k] = reinterpret_cast<const uint4 *>(g_glut)[k];
         if (threadIdx.x < 128) (&s_QM[0][0])[threadIdx.x] = (&g_qm[d.q - 1][0][0])[threadIdx.x];
-    } else if (threadIdx.x == BLK_THREADS - 64) {
-        int k_img, f_key;
-        float sigma;
-        int64_t L, N;
-        key_params(d.ks, d.nks, k_img, f_key, sigma, L, N);
-        // No lit pixel: every pixel is black (k' below -64 for any E).
-        s_key[0] = N > 0 ? k_img - 136 : -100000;
-        s_key[1] = __float_as_int(sigma);
+    } else {
+        // The last wave: one lane derives k_img and sigma, then the wave
+        // fills the per-exponent table of P.
+        int kb = 0;
+        float sigma = 0.0f;
+        if (threadIdx.x == BLK_THREADS - 64) {
+            int k_img, f_key;
+            int64_t L, N;
+            key_params(d.ks, d.nks, k_img, f_key, sigma, L, N);
+            // No lit pixel: every pixel is black (k' below -64 for any E).
+            kb = N > 0 ? k_img - 136 : -100000;
+        }
+        kb = __shfl(kb, 0, 64);
+        sigma = __shfl(sigma, 0, 64);
+        const int l = threadIdx.x & 63;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s_ptab[l + 64 * k] = tmo_p(l + 64 * k, kb, sigma);
     }
 
     const int nbx = (W + 7) >> 3, nby = (H + 7) >> 3;
@@ -424,8 +434,6 @@ __global__ __launch_bounds__(BLK_THREADS) void k_tmo_base(const ImgDesc *__restr
     const bool active = bx < nbx && by < nby;
     const int x0 = bx * 8;
     __syncthreads();
-    const int kbase = s_key[0];
-    const float sigma = __int_as_float(s_key[1]);
 
     // Phase 1: lane = row r.  RGBE -> TMO -> YCbCr - 128 -> FDCT row pass; the
     // row outputs go to the slot transposed, at position r ^ (r >> 2) of
@@ -445,7 +453,7 @@ __global__ __launch_bounds__(BLK_THREADS) void k_tmo_base(const ImgDesc *__restr
 #pragma unroll
         for (int x = 0; x < 8; ++x) {
             int cr, cg, cb;
-            tmo_px(px[x], kbase, sigma, s_lut, cr, cg, cb);
+            tmo_px(px[x], s_ptab, s_lut, cr, cg, cb);
             if (EXTRA && d.sdr0 && yl < H && x0 + x < W) {
                 uint8_t *o = d.sdr0 + 3 * ((int64_t)yl * W + x0 + x);
                 o[0] = (uint8_t)cr; o[1] = (uint8_t)cg; o[2] = (uint8_t)cb;
