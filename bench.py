@@ -207,7 +207,7 @@ def main():
     import numpy as np
     from paper_2309_11072_amd import rdl, synth
 
-    sp = synth.config2()
+    sp = synth.image_3840x2160()
     H, W, q = sp.H, sp.W, sp.q
     x = sp.make()
     print("bench: workload %dx%d q=%d generated" % (W, H, q), file=sys.stderr, flush=True)
@@ -278,7 +278,7 @@ def main():
     # ---- batch: 64 uneven images, one launch per stage ----------------------
     batch = None
     if args.batch_steps > 0:
-        specs = synth.config3()
+        specs = synth.batch_64_uneven()
         imgs = []
         for k, s in enumerate(specs):
             imgs.append(s.make_torch())
@@ -294,7 +294,7 @@ def main():
         ok = all(torch.equal(codec.decode_enh(it[2], it[3], it[4], s.H, s.W), im)
                  for it, s, im in zip(items, specs, imgs))
         gbps_b = PIPELINE_BYTES_PER_PX * npx / (ms_b * 1e-3) / 1e9
-        batch = {"workload": "64 uneven RGBE images (config-3 sizes and parameters, drawn on the GPU), one launch "
+        batch = {"workload": "64 uneven RGBE images of 0.3 to 8.3 MP (sigma_L 1.5-4, q 50-95, drawn on the GPU), one launch "
                              "per stage, plain SLR", "images": len(specs), "Mpixel": round(npx / 1e6, 2),
                  "ms_per_step": round(ms_b, 4), "Mpixel_s": round(npx / (ms_b * 1e-3) / 1e6, 1),
                  "pipeline_algorithmic_GBps": round(gbps_b, 1), "pipeline_frac_of_hbm": round(gbps_b / HBM_PEAK_GBPS, 4),
@@ -314,7 +314,7 @@ def main():
         npx_eval = 0
         ok = True
         regions = [0, 0]
-        for s in synth.config4_eval():
+        for s in synth.learned_eval_set():
             xe = torch.from_numpy(s.make()).cuda()
             oe = codec.alloc_outputs(s.H, s.W)
             for mode in (0, 1):
@@ -350,7 +350,7 @@ def main():
     large = None
     if learned is not None and args.large_steps > 0:
         torch.cuda.empty_cache()
-        specs = synth.config5()
+        specs = synth.batch_256_large()
         imgs = []
         for k, s in enumerate(specs):
             imgs.append(s.make_torch())
@@ -375,7 +375,7 @@ def main():
             say("large batch, %s: %.2f ms (%.1f Mpixel/s)" % ("learned" if mode else "plain", ms,
                                                              npx / (ms * 1e-3) / 1e6))
         codec.set_estimator(0)
-        large = {"workload": "256 uneven RGBE images of 1 to 33 MP (config-5 sizes and parameters, drawn on the "
+        large = {"workload": "256 uneven RGBE images of 1 to 33 MP (sigma_L 1-5, q 30-98, drawn on the "
                              "GPU), one launch per stage", "images": len(specs), "Mpixel": round(npx / 1e6, 1)}
         for mode, name in ((0, "slr"), (1, "learned")):
             ms, bits, ok, flagged, cb = res[mode]

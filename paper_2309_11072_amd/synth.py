@@ -183,17 +183,17 @@ def _draw_sizes(n, a_lo, a_hi, rng):
     return out
 
 
-def config1() -> ImageSpec:
+def small_512x384() -> ImageSpec:
     """512x384 image, sigma 2.5, no speculars, q 90 (oracle-sized case)."""
     return ImageSpec(384, 512, 2.5, 90, 1)
 
 
-def config2() -> ImageSpec:
+def image_3840x2160() -> ImageSpec:
     """3840x2160 image, sigma 4, 5% speculars at +10 stops, q 75."""
     return ImageSpec(2160, 3840, 4.0, 75, 2, 0.05)
 
 
-def config3(n: int = 64) -> list:
+def batch_64_uneven(n: int = 64) -> list:
     """64 uneven images, 640x480 .. 3840x2160 pixels' worth of area,
     sigma in [1.5, 4], q in [50, 95]."""
     rng = np.random.Generator(np.random.PCG64(3))
@@ -202,15 +202,18 @@ def config3(n: int = 64) -> list:
             for i, (H, W) in enumerate(sizes)]
 
 
-def config4_train() -> list:
+def learned_train_set() -> list:
+    """Two 3840x2160 images (sigma 4, 5% speculars, q 75) to train the learned
+    estimator on."""
     return [ImageSpec(2160, 3840, 4.0, 75, 4000 + i, 0.05) for i in range(2)]
 
 
-def config4_eval() -> list:
+def learned_eval_set() -> list:
+    """Sixteen held-out 1920x1080 images with the same parameters."""
     return [ImageSpec(1080, 1920, 4.0, 75, 4100 + i, 0.05) for i in range(16)]
 
 
-def config5(n: int = 256) -> list:
+def batch_256_large(n: int = 256) -> list:
     """256 uneven images of 1 MP .. 33 MP, sigma in [1, 5], q in [30, 98]."""
     rng = np.random.Generator(np.random.PCG64(5))
     sizes = _draw_sizes(n, 1.0e6, 7680 * 4320, rng)

@@ -169,7 +169,7 @@ def main():
     args = ap.parse_args()
     t0 = time.time()
     codec = rdl.Codec(0)
-    samples = make_samples(codec, synth.config4_train(), args.samples, seed=4000)
+    samples = make_samples(codec, synth.learned_train_set(), args.samples, seed=4000)
     print("samples: %d records in %.1f s" % (samples.shape[0], time.time() - t0), flush=True)
     params = train(codec, samples, args.epochs, args.batch, args.lr, log=lambda s: print(s, flush=True))
     calib = samples[:200_000].cpu().numpy()
@@ -179,7 +179,7 @@ def main():
     print("model written: %s (%d bytes, hash %016x) after %.1f s" % (args.out, len(blob), model_format.blob_hash(blob),
                                                                    time.time() - t0), flush=True)
     codec.set_model(blob)
-    ev = synth.config4_eval()[: args.eval]
+    ev = synth.learned_eval_set()[: args.eval]
     b_slr = bits_per_pixel(codec, ev, False)
     b_l = bits_per_pixel(codec, ev, True)
     print("eval (%d x 1920x1080): bits/px SLR %.4f  learned+fallback %.4f" % (len(ev), b_slr, b_l), flush=True)

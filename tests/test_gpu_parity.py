@@ -50,8 +50,8 @@ def _images():
     g = np.zeros((24, 16, 4), np.uint8)
     g[...] = [150, 150, 150, 140]
     out.append(("grey", g, 90))
-    sp = synth.config1()
-    out.append(("config1-512x384", sp.make(), sp.q))
+    sp = synth.small_512x384()
+    out.append(("small_512x384-512x384", sp.make(), sp.q))
     return out
 
 
@@ -228,11 +228,11 @@ def test_batch_uneven_matches_oracle(codec, O):
             assert np.array_equal(it[4].cpu().numpy(), ref["resid"]), (rep, H, W)
 
 
-def test_full_size_config2(codec, O, rdl_mod):
+def test_full_size_3840x2160(codec, O, rdl_mod):
     """3840x2160, sigma 4, 5% speculars, q 75: the benchmark's workload and
     launch configuration, compared with the oracle on every output."""
-    sp = synth.config2()
-    _say("config2 full size", sp.H, sp.W)
+    sp = synth.image_3840x2160()
+    _say("3840x2160 full size", sp.H, sp.W)
     x = sp.make()
     d = _dev(x)
     out = codec.alloc_outputs(sp.H, sp.W)

@@ -473,7 +473,7 @@ def test_slrme_lowers_entropy_vs_plain_difference(O):
     """Direction of the paper's ablation (Table I, w/o vs with SLRME): on the
     512x384 synthetic image the SLR residuals have lower zeroth-order entropy
     than r = M - S."""
-    sp = synth.config1()
+    sp = synth.small_512x384()
     x = sp.make()
     r = O.encode_enh(x, sp.q)
     with_ = O.bits_per_pixel(O.resid_hist(r["resid"], sp.H * sp.W))
