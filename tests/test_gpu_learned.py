@@ -164,3 +164,31 @@ def test_training_step_deterministic_and_learns(codec):
         assert torch.equal(codec.decode_enh(sdr, hdr, resid, 90, 120), d)
     finally:
         codec.set_estimator(0)
+
+
+def test_learned_graph_mode_replays_match_oracle(codec, rdl_mod, O):
+    """The learned encoder captured as a graph: every replay equals the oracle
+    (its record cursors, histograms and flags are rebuilt or cleared each time)."""
+    H, W, q, ms = 150, 222, 60, 21
+    _say("learned graph mode", H, W)
+    x = synth.generate(H, W, 3.0, seed=7021, spec_frac=0.05)
+    blob = synth.random_model(ms)
+    codec.set_model(blob)
+    codec.set_estimator(1)
+    codec.set_launch_mode(True)
+    try:
+        ref = O.encode_learned(x, q, blob)
+        d = _dev(x)
+        out = codec.alloc_outputs(H, W)
+        for rep in range(3):
+            for t in out:
+                t.fill_(0xAA)
+            sdr, hdr, resid = codec.encode_enh(d, q, out=out)
+            torch.cuda.synchronize()
+            h = rdl_mod.header_from_bytes(hdr)
+            assert np.array_equal(h["flag"], ref["flag"]), rep
+            assert np.array_equal(resid.cpu().numpy(), ref["resid"]), rep
+            assert np.array_equal(sdr.cpu().numpy(), ref["sdr"]), rep
+    finally:
+        codec.set_launch_mode(False)
+        codec.set_estimator(0)
