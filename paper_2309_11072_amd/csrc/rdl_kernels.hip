@@ -172,7 +172,7 @@ __global__ __launch_bounds__(256) void k_zero(const ImgDesc *__restrict__ D, int
     const int i = blockIdx.x;
     if (i >= n) return;
     const ImgDesc d = desc_at(D, i);
-    if ((d.flags & F_ZERO_KS) && d.ks && threadIdx.x < 2 * d.nks) d.ks[threadIdx.x] = 0;
+    if ((d.flags & F_ZERO_KS) && d.ks && (int)threadIdx.x < 2 * d.nks) d.ks[threadIdx.x] = 0;
     if ((d.flags & F_ZERO_SUMS) && d.part)
         for (int k = threadIdx.x; k < d.nfs * 256 * NSUM; k += 256) d.part[k] = 0;
     if ((d.flags & F_ZERO_HIST) && d.hist)
@@ -956,7 +956,8 @@ __device__ i128 floor_div128(i128 N, i128 D) {
 
 __device__ __forceinline__ i128 rhu128(i128 x, i128 y) { return floor_div128(2 * x + y, 2 * y); }
 
-__global__ __launch_bounds__(1024) void k_solve(const ImgDesc *__restrict__ D, int n) {
+__global__ __launch_bounds__(1024) void k_solve(const ImgDesc *__restrict__ D, int) {
+    // One workgroup per image (the launch has exactly n).
     __shared__ int64_t s_b[256][NSUM];
     __shared__ int s_cnt[4];
     __shared__ uint32_t s_tot[2][4];
