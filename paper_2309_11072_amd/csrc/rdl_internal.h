@@ -9,8 +9,8 @@
 namespace rdl {
 
 // Work decomposition, fixed for every stage kernel.
-constexpr int KS_THREADS = 512;    // key statistic: 512 lanes x 32 px
-constexpr int KS_PX_PER_WG = 16384;
+constexpr int KS_THREADS = 1024;   // key statistic: 1024 lanes x 32 px
+constexpr int KS_PX_PER_WG = 32768;
 constexpr int KS_STRIPES = 16;     // partial-sum copies per image, so that no
 constexpr int FIT_STRIPES = 4;     //   address takes more than a few atomics
 constexpr int BLK_WG = 32;        // tone map + base layer: 32 blocks of one block row,
