@@ -195,6 +195,59 @@ int rdl_train_step(rdl_ctx *ctx, float *params, float *adam_m, float *adam_v, co
  * [3][511], hist[c][r + 255] counts residual value r of channel c. */
 int rdl_resid_hist(rdl_ctx *ctx, const void *resid, int H, int W, int64_t *hist, void *stream);
 
+/* ---- Entropy code of the enhancement layer (an extension: the paper codes
+ * the residual and exponent planes with JPEG 2000, Sec. IV) ----
+ * A static rANS coder (J. Duda, "Asymmetric numeral systems", 2013, the range
+ * variant): probability scale M = 2^15, states in [2^16, 2^32), 16-bit
+ * renormalisation.  Encoding s: if x >= 2^17 f[s], emit x mod 2^16 and
+ * x = x div 2^16; then x = (x div f[s]) M + (x mod f[s]) + c[s], with
+ * c[s] = sum of f[t] for t < s.  Decoding reverses it.
+ *
+ * Planes p = 0, 1, 2: the residuals of channel R, G, B as symbols r + 255
+ * (511 symbols); p = 3: the exponents (256 symbols); each N = H W symbols in
+ * raster order.  Frequencies of a plane from its counts h (P symbols present):
+ * f[s] = 1 + floor(h[s] (M - P) / N) where h[s] > 0, else 0; the smallest
+ * symbol of the largest count takes the remainder M - sum f.
+ *
+ * Groups: K = 2^log2_k steps (4 <= log2_k <= 12); a plane is cut into
+ * G = ceil(N / 64K) groups of 64K consecutive symbols (the last one shorter),
+ * symbol i of a group going to lane i mod 64 at step i div 64.  The encoder
+ * starts each lane at 2^16, runs the steps last to first and the lanes 63 to
+ * 0 (skipping lanes without a symbol), then emits each lane's state, lanes 63
+ * to 0, low half first.  A group's stored words are its emitted words in
+ * reverse: lane states 0..63 (high, low), then per step from the first the
+ * words of the lanes that renormalise, in lane order.  Each group costs
+ * 64 x 32 bits of states, i.e. 32 / K bits per symbol.
+ *
+ * Stream, little-endian: u32 magic 0x454C4452 ("RDLE"), u32 version 1,
+ * i32 H, i32 W, i32 log2_k, i32 prob_bits (15), u32 G, u32 0, u64 total bytes,
+ * u16 freq[4][512] (entries past a plane's alphabet 0) -- RDL_ENT_HEADER_BYTES
+ * in all -- then u64 start[4][G] (first word of each group, counted from the
+ * payload), then the payload of u16 words, groups in plane-major order.
+ *
+ * rdl_ent_encode: resid (device, rdl_resid_bytes(H, W), 2-byte aligned) ->
+ * out (device, 8-byte aligned, cap >= rdl_ent_bound bytes); the stream length
+ * goes to *out_len (DEVICE u64, 8-byte aligned).  A residual outside
+ * [-255, 255] yields a stream with magic 0 and *out_len = 0.  The context
+ * keeps a workspace sized for the largest layer seen (the plane histograms,
+ * the coder tables and every group's words before they are put in order,
+ * about 8 bytes per pixel; allocated synchronously when it grows), so calls on
+ * one context must not overlap.  rdl_ent_bound is 0 for bad sizes.
+ *
+ * rdl_ent_decode: code (device, 8-byte aligned, len bytes) and a HOST copy of
+ * its first RDL_ENT_HEADER_BYTES bytes, which is validated first (magic,
+ * version, sizes, log2_k, G, frequency sums, total <= len: RDL_ECORRUPT) ->
+ * out_resid (device, rdl_resid_bytes(H, W), 2-byte aligned).  If status
+ * (device int32, may be NULL) is given it receives RDL_OK, or RDL_ECORRUPT
+ * when the device copy's tables or a group's offsets or words do not decode
+ * exactly (every read stays inside the stream). */
+#define RDL_ENT_HEADER_BYTES 4136
+size_t rdl_ent_bound(int H, int W, int log2_k);
+int rdl_ent_encode(rdl_ctx *ctx, const void *resid, int H, int W, int log2_k, void *out, size_t cap,
+                   uint64_t *out_len, void *stream);
+int rdl_ent_decode(rdl_ctx *ctx, const void *code, size_t len, const void *header, int H, int W,
+                   void *out_resid, int32_t *status, void *stream);
+
 /* ---- Stage entry points (each is one step of rdl_encode_enh, for checks) ---- */
 
 /* Key statistic (Sec. IV, Reinhard's operator needs the log-average

@@ -2,7 +2,8 @@
 
 TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
 leg of the benchmark call this module; the product path never does.  It loads
-``liboracle.so`` built from ``rdl_oracle.c`` by :func:`build` (plain gcc, no
+``liboracle.so`` built from ``rdl_oracle.c`` and ``rdl_ent_oracle.c`` (the
+entropy code of the enhancement layer) by :func:`build` (plain gcc, no
 fast-math, no FMA contraction) and wraps each stage so that it takes and
 returns numpy arrays.  Nothing here does any of the method's arithmetic.
 """
@@ -16,6 +17,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rdl_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "rdl_ent_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
 
@@ -24,9 +26,9 @@ _lib = None
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc into ``oracle/liboracle.so``."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in _SRCS):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -68,6 +70,14 @@ def lib():
         L.oracle_encode_learned.restype = C.c_int
         L.oracle_decode_learned.argtypes = [vp, vp, vp, vp, i32, vp, vp, C.c_int, C.c_int, vp]
         L.oracle_decode_learned.restype = C.c_int
+        L.oracle_ent_freqs.argtypes = [vp, C.c_int, vp]
+        L.oracle_ent_freqs.restype = C.c_int
+        L.oracle_ent_bound.argtypes = [C.c_int, C.c_int, C.c_int]
+        L.oracle_ent_bound.restype = i64
+        L.oracle_ent_encode.argtypes = [vp, C.c_int, C.c_int, C.c_int, vp, i64]
+        L.oracle_ent_encode.restype = i64
+        L.oracle_ent_decode.argtypes = [vp, i64, C.c_int, C.c_int, vp]
+        L.oracle_ent_decode.restype = C.c_int
         _lib = L
     return _lib
 
@@ -296,4 +306,42 @@ def decode_learned(sdr, a_q, b_q, flag, k_img, blob, resid, H, W) -> np.ndarray:
                                      k_img, _p(bb), _p(np.ascontiguousarray(resid).view(np.uint8)), H, W, _p(out))
     if rc:
         raise ValueError("oracle_decode_learned failed with %d" % rc)
+    return out
+
+
+# ---------------------------------------------------------------- entropy code of the layer
+ENT_HDR = 4136
+
+
+def ent_freqs(h) -> np.ndarray:
+    """Quantised frequencies (sum 2^15) of one plane's symbol counts."""
+    h = np.ascontiguousarray(h, np.int64)
+    f = np.zeros(len(h), np.uint16)
+    if lib().oracle_ent_freqs(_p(h), len(h), _p(f)):
+        raise ValueError("oracle_ent_freqs: bad counts")
+    return f
+
+
+def ent_bound(H: int, W: int, log2_k: int = 8) -> int:
+    return int(lib().oracle_ent_bound(H, W, log2_k))
+
+
+def ent_encode(resid: np.ndarray, H: int, W: int, log2_k: int = 8) -> bytes:
+    """Code stream of an enhancement layer (7 H W bytes)."""
+    buf = np.ascontiguousarray(resid).view(np.uint8).reshape(-1)
+    assert buf.size == 7 * H * W
+    out = np.zeros(max(ent_bound(H, W, log2_k), 1), np.uint8)
+    n = lib().oracle_ent_encode(_p(buf), H, W, log2_k, _p(out), out.size)
+    if n < 0:
+        raise ValueError("oracle_ent_encode failed with %d" % n)
+    return out[:n].tobytes()
+
+
+def ent_decode(stream: bytes, H: int, W: int) -> np.ndarray:
+    """Enhancement layer (7 H W bytes) from a code stream."""
+    st = np.frombuffer(stream, np.uint8).copy()
+    out = np.zeros(7 * H * W, np.uint8)
+    rc = lib().oracle_ent_decode(_p(st), st.size, H, W, _p(out))
+    if rc:
+        raise ValueError("oracle_ent_decode failed with %d" % rc)
     return out

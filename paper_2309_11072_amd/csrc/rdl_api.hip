@@ -44,6 +44,9 @@ struct rdl_ctx {
     uint8_t *d_model = nullptr;
     uint64_t model_hash = 0;
     int estimator = 0;
+    // entropy coder workspace (EntWs, then group word counts and words)
+    uint8_t *d_ent = nullptr;
+    size_t ent_cap = 0;
     // training scratch: per-workgroup gradient partials
     float *d_part = nullptr;
     size_t part_cap = 0;      // floats
@@ -103,6 +106,32 @@ int ensure_scratch(rdl_ctx *c, size_t n) {
     HIPCHK(hipMemset(c->d_scratch, 0, n * SCRATCH_I64 * sizeof(int64_t)));  // accumulators start at zero
     c->scratch_cap = n;
     return RDL_OK;
+}
+
+int ensure_ent(rdl_ctx *c, size_t bytes) {
+    if (bytes <= c->ent_cap) return RDL_OK;
+    if (c->d_ent) HIPCHK(hipFree(c->d_ent));
+    c->d_ent = nullptr;
+    c->ent_cap = 0;
+    HIPCHK(hipMalloc(&c->d_ent, bytes));
+    HIPCHK(hipMemset(c->d_ent, 0, sizeof(EntWs)));  // the histograms start at zero
+    c->ent_cap = bytes;
+    return RDL_OK;
+}
+
+EntArgs ent_args(rdl_ctx *c, int H, int W, int log2_k) {
+    EntArgs a;
+    memset(&a, 0, sizeof a);
+    const int64_t G = ent_groups(H, W, log2_k);
+    a.ws = reinterpret_cast<EntWs *>(c->d_ent);
+    a.cnt = reinterpret_cast<uint32_t *>(c->d_ent + ent_cnt_off());
+    a.tmp = reinterpret_cast<uint16_t *>(c->d_ent + ent_tmp_off(G));
+    a.N = (int64_t)H * W;
+    a.H = H;
+    a.W = W;
+    a.log2_k = log2_k;
+    a.G = (int32_t)G;
+    return a;
 }
 
 struct Grid {
@@ -325,6 +354,7 @@ void rdl_destroy(rdl_ctx *c) {
     if (c->d_part) (void)hipFree(c->d_part);
     if (c->d_desc) (void)hipFree(c->d_desc);
     if (c->d_scratch) (void)hipFree(c->d_scratch);
+    if (c->d_ent) (void)hipFree(c->d_ent);
     delete c;
 }
 
@@ -483,6 +513,66 @@ int rdl_resid_hist(rdl_ctx *c, const void *resid, int H, int W, int64_t *hist, v
     launch_zero(c->d_desc, 1, s);
     launch_hist(c->d_desc, 1, gr.tile, s);
     return check_launch("k_hist");
+}
+
+size_t rdl_ent_bound(int H, int W, int log2_k) {
+    if (!size_ok(H, W) || log2_k < 4 || log2_k > 12) return 0;
+    const int64_t G = ent_groups(H, W, log2_k), N = (int64_t)H * W;
+    return (size_t)(ENT_HDR + 32 * G + 2 * (4 * N + 4 * G * 128));
+}
+
+int rdl_ent_encode(rdl_ctx *c, const void *resid, int H, int W, int log2_k, void *out, size_t cap,
+                   uint64_t *out_len, void *stream) {
+    if (!c || !resid || !out || !out_len || !size_ok(H, W) || log2_k < 4 || log2_k > 12) return RDL_EINVAL;
+    if (cap < rdl_ent_bound(H, W, log2_k)) return RDL_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(resid) & 1) || (reinterpret_cast<uintptr_t>(out) & 7) ||
+        (reinterpret_cast<uintptr_t>(out_len) & 7))
+        return RDL_EINVAL;
+    DeviceGuard g(c->device);
+    int rc = ensure_ent(c, ent_ws_bytes(H, W, log2_k));
+    if (rc) return rc;
+    EntArgs a = ent_args(c, H, W, log2_k);
+    a.resid = (const uint8_t *)resid;
+    a.out = (uint8_t *)out;
+    a.out_len = out_len;
+    launch_ent_encode(a, (hipStream_t)stream);
+    return check_launch("k_ent_encode");
+}
+
+int rdl_ent_decode(rdl_ctx *c, const void *code, size_t len, const void *header, int H, int W, void *out_resid,
+                   int32_t *status, void *stream) {
+    if (!c || !code || !header || !out_resid || !size_ok(H, W)) return RDL_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(code) & 7) || (reinterpret_cast<uintptr_t>(out_resid) & 1)) return RDL_EINVAL;
+    const uint8_t *h = (const uint8_t *)header;
+    uint32_t w[8];
+    uint64_t total;
+    memcpy(w, h, sizeof w);
+    memcpy(&total, h + 32, sizeof total);
+    const int log2_k = (int)w[4];
+    if (w[0] != 0x454C4452u || w[1] != 1u || (int)w[2] != H || (int)w[3] != W || log2_k < 4 || log2_k > 12 ||
+        w[5] != (uint32_t)ENT_PB)
+        return RDL_ECORRUPT;
+    const int64_t G = ent_groups(H, W, log2_k);
+    const uint64_t fixed = (uint64_t)ENT_HDR + 32 * (uint64_t)G;
+    if (w[6] != (uint32_t)G || total < fixed || total > len || (total - fixed) % 2) return RDL_ECORRUPT;
+    for (int p = 0; p < 4; ++p) {
+        uint32_t sum = 0;
+        for (int s = 0; s < 512; ++s) {
+            uint16_t f;
+            memcpy(&f, h + 40 + 2 * (512 * p + s), 2);
+            if (f && s >= (p < 3 ? 511 : 256)) return RDL_ECORRUPT;
+            sum += f;
+        }
+        if (sum != ENT_M) return RDL_ECORRUPT;
+    }
+    DeviceGuard g(c->device);
+    EntArgs a = ent_args(c, H, W, log2_k);
+    a.code = (const uint8_t *)code;
+    a.dst = (uint8_t *)out_resid;
+    a.status = status;
+    a.nwords = (int64_t)((total - fixed) / 2);
+    launch_ent_decode(a, (hipStream_t)stream);
+    return check_launch("k_ent_decode");
 }
 
 int rdl_stage_keystat(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int64_t *out2, void *stream) {

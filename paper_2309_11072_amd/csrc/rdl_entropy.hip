@@ -1,0 +1,457 @@
+// rdl_entropy.hip -- gfx950 kernels of the entropy code of the enhancement
+// layer: a static rANS coder (Duda, "Asymmetric numeral systems", 2013, the
+// range variant) over the three residual planes and the exponent plane, with
+// 64 interleaved coder states per group of symbols, one wave per group.  The
+// paper hands these planes to an off-the-shelf lossless coder (JPEG 2000,
+// Sec. IV); this coder stands in for it.  The stream format is described in
+// rdl.h.
+//
+// Encoder: k_ent_hist (plane histograms) -> k_ent_freq (frequencies, header)
+// -> k_ent_enc (one wave per group, words in emission order into a workspace)
+// -> k_ent_scan (group offsets) -> k_ent_pack (each group's words reversed
+// into place).  Decoder: k_ent_dec (tables in LDS, one wave per group).
+// Everything is integer arithmetic except the encoder's division by a
+// frequency, which takes a float reciprocal estimate and corrects it to the
+// exact quotient.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rdl_internal.h"
+
+namespace rdl {
+
+namespace {
+
+constexpr int ENT_HC = 8;                  // privatised LDS copies of the histograms, each
+constexpr int ENT_HSTRIDE = 1024 + 1;      //   2048 16-bit counters in 1024 words (odd stride:
+                                           //   copies of a bin fall in different banks)
+constexpr int ENT_HIST_THREADS = 512;
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum over a block of NW waves (every thread receives it).
+template <int NW>
+__device__ uint32_t block_sum(uint32_t v, uint32_t *sh) {
+    v = wave_sum(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    uint32_t t = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) t += sh[k];
+    return t;
+}
+
+template <int NW>
+__device__ unsigned long long block_max64(unsigned long long v, unsigned long long *sh) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)v, off, 64), hi = __shfl_xor((uint32_t)(v >> 32), off, 64);
+        const unsigned long long o = (unsigned long long)hi << 32 | lo;
+        v = o > v ? o : v;
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    unsigned long long t = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) t = sh[k] > t ? sh[k] : t;
+    return t;
+}
+
+// Exclusive prefix sum over a block of NW waves; total receives the sum.
+template <int NW>
+__device__ uint32_t block_excl_scan(uint32_t v, uint32_t *sh, uint32_t &total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t inc = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += y;
+    }
+    __syncthreads();
+    if (lane == 63) sh[w] = inc;
+    __syncthreads();
+    uint32_t before = 0, t = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        const uint32_t x = sh[k];
+        before += k < w ? x : 0u;
+        t += x;
+    }
+    total = t;
+    return before + inc - v;
+}
+
+// Plane histograms: residual symbols r + 255 (511 for a value outside
+// [-255, 255], never a legal symbol) and exponents.  Counters are 16-bit
+// halves of LDS words in ENT_HC copies (lane l counts into copy l mod ENT_HC);
+// a bin of one workgroup never exceeds ENT_HIST_PX = 16384 < 2^16, so halves
+// cannot carry.  Exponents are smooth across neighbouring pixels, so a wave
+// adds each run of equal exponents over consecutive lanes with one atomic (the
+// run's first lane adds its length).  The copies are then added into the
+// image's histograms with integer atomics.
+__device__ __forceinline__ void ent_count(uint32_t *copy, uint32_t bin, uint32_t k) {
+    atomicAdd(copy + (bin >> 1), k << ((bin & 1) * 16));
+}
+
+__global__ __launch_bounds__(ENT_HIST_THREADS) void k_ent_hist(EntArgs a) {
+    __shared__ uint32_t h[ENT_HC * ENT_HSTRIDE];
+    for (int k = threadIdx.x; k < ENT_HC * ENT_HSTRIDE; k += ENT_HIST_THREADS) h[k] = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    uint32_t *mine = h + (lane & (ENT_HC - 1)) * ENT_HSTRIDE;
+    const int64_t i0 = (int64_t)blockIdx.x * ENT_HIST_PX;
+    const int n = (int)(a.N - i0 < ENT_HIST_PX ? a.N - i0 : ENT_HIST_PX);
+    constexpr int PER = ENT_HIST_PX / ENT_HIST_THREADS;  // 32 px per thread and plane
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        const int16_t *rp = (const int16_t *)a.resid + p * a.N + i0;
+        int v[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int i = j * ENT_HIST_THREADS + threadIdx.x;
+            v[j] = (int)rp[min(i, n - 1)];  // clamped: every load is valid, counted below only if i < n
+        }
+#pragma unroll
+        for (int j = 0; j < PER; ++j)
+            if (j * ENT_HIST_THREADS + (int)threadIdx.x < n)
+                ent_count(mine, p * 512 + min((uint32_t)(v[j] + 255), 511u), 1u);
+    }
+    const uint8_t *e8 = a.resid + 6 * a.N + i0;
+    int ev[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int i = j * ENT_HIST_THREADS + threadIdx.x;
+        const int v = (int)e8[min(i, n - 1)];
+        ev[j] = i < n ? v : -1;
+    }
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int v = ev[j];
+        const int left = __shfl_up(v, 1, 64);
+        const bool head = lane == 0 || v != left;
+        const unsigned long long m = __ballot(head);
+        // the run ends at the next head (a lane past the end has v = -1, a head of its own)
+        const unsigned long long after = lane == 63 ? 0ull : m >> (lane + 1);
+        const int len = after ? (int)__builtin_ctzll(after) + 1 : 64 - lane;
+        if (head && v >= 0) ent_count(mine, 3 * 512 + v, (uint32_t)len);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < 2048; b += ENT_HIST_THREADS) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int k = 0; k < ENT_HC; ++k) v += (h[k * ENT_HSTRIDE + (b >> 1)] >> ((b & 1) * 16)) & 0xFFFFu;
+        if (v) atomicAdd(&a.ws->hist[b >> 9][b & 511], v);
+    }
+}
+
+// Frequencies of plane blockIdx.x (512 threads, one per symbol):
+// f = 1 + floor(h (M - P) / N) for the P present symbols, the remainder to
+// the smallest symbol of the largest count; c = exclusive prefix sum.  Writes
+// the stream's frequency table and the encoder's table, clears the histogram;
+// plane 0's workgroup writes the fixed header words.
+__global__ __launch_bounds__(512) void k_ent_freq(EntArgs a) {
+    __shared__ uint32_t sh[8];
+    __shared__ unsigned long long shm[8];
+    const int p = blockIdx.x, s = threadIdx.x, nsym = p < 3 ? 511 : 256;
+    const uint32_t h = a.ws->hist[p][s];
+    a.ws->hist[p][s] = 0;
+    const bool pres = s < nsym && h > 0;
+    const uint32_t nbad = block_sum<8>(s >= nsym && h > 0 ? 1u : 0u, sh);
+    const uint32_t P = block_sum<8>(pres ? 1u : 0u, sh);
+    uint32_t f = pres ? 1u + (uint32_t)(((uint64_t)h * (ENT_M - P)) / (uint64_t)a.N) : 0u;
+    const uint32_t sum = block_sum<8>(f, sh);
+    const unsigned long long key = pres ? ((unsigned long long)h << 16 | (0xFFFFu - (uint32_t)s)) : 0ull;
+    const unsigned long long best = block_max64<8>(key, shm);
+    if (pres && key == best) f += ENT_M - sum;
+    uint32_t tot;
+    const uint32_t c = block_excl_scan<8>(f, sh, tot);
+    const bool bad = nbad != 0;
+    reinterpret_cast<uint16_t *>(a.out + 40)[512 * p + s] = bad ? 0 : (uint16_t)f;
+    a.ws->tab[p][s] = make_uint2(f | c << 16, f ? __float_as_uint(1.0f / (float)f) : 0u);
+    if (s == 0) a.ws->bad[p] = bad ? 1u : 0u;
+    if (p == 0 && s < 8) {
+        const uint32_t v = s == 0 ? 0x454C4452u
+                         : s == 1 ? 1u
+                         : s == 2 ? (uint32_t)a.H
+                         : s == 3 ? (uint32_t)a.W
+                         : s == 4 ? (uint32_t)a.log2_k
+                         : s == 5 ? (uint32_t)ENT_PB
+                         : s == 6 ? (uint32_t)a.G
+                                  : 0u;
+        reinterpret_cast<uint32_t *>(a.out)[s] = v;
+    }
+}
+
+// One wave per group: lane l codes symbols l, l + 64, ... of the group from
+// the last step to the first.  A lane renormalises (emits its low 16 bits)
+// when x >= 2^17 f; the words of a step go out in descending lane order, so
+// that the stored (reversed) stream lists them in ascending order.  Then
+// x = (x div f) M + (x mod f) + c, with the quotient from a float reciprocal:
+// x < 2^17 f, so the estimate is within 3 * 2^-24 * 2^17 < 0.03 of x / f and
+// one correction step in either direction makes it exact.  Finally every
+// lane's state, lanes 63 down to 0, low half first.  RES: a residual plane
+// (int16 values, symbol r + 255), else the exponent plane (bytes).
+template <bool RES, typename V>
+__device__ __forceinline__ void enc_group(const V *src, int n, const uint2 *tb, uint16_t *out, uint32_t *cnt_out,
+                                          int lane) {
+    const int T = (n + 63) >> 6;
+    // Symbols of steps t0, t0 - 1, ..., t0 - 7 and a mask of the lane's valid
+    // ones.  Every load reads a valid address (the index is clamped) and its
+    // value is used unconditionally, so the loads stay free of branches; the
+    // next block's loads are issued before the current block is coded.  Steps
+    // before the first (t < 0) have no symbol in any lane and change nothing.
+    auto load_block = [&](int t0, uint32_t (&sv)[8]) -> uint32_t {
+        uint32_t vm = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int t = t0 - k, i = t * 64 + lane;
+            const int v = (int)src[min(max(i, 0), n - 1)];
+            sv[k] = RES ? min((uint32_t)(v + 255), 511u) : (uint32_t)v;
+            vm |= (t >= 0 && i < n ? 1u : 0u) << k;
+        }
+        return vm;
+    };
+    uint32_t x = ENT_L, wpos = 0;
+    uint32_t cur[8], nxt[8];
+    uint32_t vcur = load_block(T - 1, cur);
+    for (int t0 = T - 1; t0 >= 0; t0 -= 8) {
+        const uint32_t vnxt = load_block(t0 - 8, nxt);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t s = cur[k];
+            const bool have = (vcur >> k) & 1u;
+            const uint2 e = tb[s];
+            const uint32_t f = e.x & 0xFFFFu, c = e.x >> 16;
+            const bool ren = have && (x >> 17) >= f;
+            const unsigned long long m = __ballot(ren);
+            if (ren) out[wpos + __popcll(m & ~((2ull << lane) - 1ull))] = (uint16_t)x;
+            wpos += __popcll(m);
+            const uint32_t xr = ren ? x >> 16 : x;
+            uint32_t q = (uint32_t)((float)xr * __uint_as_float(e.y));
+            uint32_t r = xr - q * f;
+            const bool lo = (int32_t)r < 0, hi = !lo && r >= f;
+            q = lo ? q - 1 : hi ? q + 1 : q;
+            r = lo ? r + f : hi ? r - f : r;
+            x = have ? (q << ENT_PB) + r + c : xr;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) cur[k] = nxt[k];
+        vcur = vnxt;
+    }
+    const uint32_t fp = wpos + 2 * (63 - lane);
+    out[fp] = (uint16_t)x;
+    out[fp + 1] = (uint16_t)(x >> 16);
+    if (lane == 0) *cnt_out = wpos + 128;
+}
+
+__global__ __launch_bounds__(256) void k_ent_enc(EntArgs a) {
+    __shared__ uint2 stab[4][512];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int G = a.G;
+    const int64_t gi = (int64_t)blockIdx.x * 4 + w;
+    const bool live = gi < 4 * (int64_t)G;
+    const int p = live ? (int)(gi / G) : 0;
+    for (int k = lane; k < 512; k += 64) stab[w][k] = a.ws->tab[p][k];
+    __syncthreads();
+    if (!live) return;
+    if (a.ws->bad[p]) {
+        if (lane == 0) a.cnt[gi] = 0;
+        return;
+    }
+    const int64_t Z = (int64_t)64 << a.log2_k, g = gi - (int64_t)p * G, base = g * Z;
+    const int n = (int)(a.N - base < Z ? a.N - base : Z);
+    uint16_t *out = a.tmp + gi * (Z + 128);
+    if (p < 3)
+        enc_group<true>((const int16_t *)a.resid + p * a.N + base, n, stab[w], out, a.cnt + gi, lane);
+    else
+        enc_group<false>(a.resid + 6 * a.N + base, n, stab[w], out, a.cnt + gi, lane);
+}
+
+// Group offsets (exclusive prefix sum of the word counts) into the stream's
+// table, the total length into the header and *out_len; an invalid layer
+// (a residual outside [-255, 255]) yields magic 0 and length 0.
+__global__ __launch_bounds__(1024) void k_ent_scan(EntArgs a) {
+    __shared__ uint32_t sh[16];
+    const bool ok = (a.ws->bad[0] | a.ws->bad[1] | a.ws->bad[2] | a.ws->bad[3]) == 0;
+    const int64_t n = 4 * (int64_t)a.G;
+    uint64_t *start = reinterpret_cast<uint64_t *>(a.out + ENT_HDR);
+    uint64_t carry = 0;
+    for (int64_t b = 0; b < n; b += 1024) {
+        const int64_t k = b + threadIdx.x;
+        const uint32_t v = k < n ? a.cnt[k] : 0u;
+        uint32_t tot;
+        const uint32_t e = block_excl_scan<16>(v, sh, tot);
+        if (k < n) start[k] = carry + e;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) {
+        const uint64_t total = (uint64_t)ENT_HDR + 32 * (uint64_t)a.G + 2 * carry;
+        reinterpret_cast<uint64_t *>(a.out)[4] = ok ? total : 0ull;
+        if (!ok) reinterpret_cast<uint32_t *>(a.out)[0] = 0u;
+        *a.out_len = ok ? total : 0ull;
+        a.ws->ok = ok ? 1u : 0u;
+    }
+}
+
+// Each group's words, reversed, at its offset in the payload.
+__global__ __launch_bounds__(256) void k_ent_pack(EntArgs a) {
+    if (!a.ws->ok) return;
+    const int64_t gi = blockIdx.x;
+    const uint32_t n = a.cnt[gi];
+    const uint64_t st = reinterpret_cast<const uint64_t *>(a.out + ENT_HDR)[gi];
+    const int64_t Z = (int64_t)64 << a.log2_k;
+    const uint16_t *src = a.tmp + gi * (Z + 128);
+    uint16_t *dst = reinterpret_cast<uint16_t *>(a.out + ENT_HDR + 32 * (int64_t)a.G) + st;
+    for (uint32_t k = threadIdx.x; k < n; k += 256) dst[k] = src[n - 1 - k];
+}
+
+__global__ void k_ent_status(int32_t *st) {
+    if (threadIdx.x == 0) st[0] = RDL_OK;
+}
+
+// Decodes one group into dst (RES: int16 residuals, else exponent bytes);
+// returns whether it failed to end exactly at its last word with every state
+// back at L.  The symbol search and state update run for every lane and are
+// kept only where the lane has a symbol, so that only the stores and the
+// short search loop are predicated.
+template <bool RES, typename V, typename LD>
+__device__ __forceinline__ bool dec_group(V *dst, int n, const uint2 *dtab, const uint16_t *bucket, uint16_t *rg,
+                                          uint32_t (&R)[4], int64_t b, int64_t pos, uint32_t x, int64_t w1,
+                                          const LD &ld, int lane) {
+    const int T = (n + 63) >> 6;
+    bool bad = false;
+    for (int t = 0; t < T; ++t) {
+        if (pos >= b + 256) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) rg[(b + 512 + k * 64 + lane) & 511] = (uint16_t)R[k];
+            b += 256;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) R[k] = ld(b + 512 + k * 64 + lane);
+        }
+        const int i = t * 64 + lane;
+        const bool have = i < n;
+        const uint32_t slot = x & (ENT_M - 1);
+        uint32_t j = bucket[slot >> 3];
+        while ((dtab[j + 1].x & 0xFFFFu) <= slot) ++j;
+        const uint2 e = dtab[j];
+        const uint32_t xn = (e.x >> 16) * (x >> ENT_PB) + slot - (e.x & 0xFFFFu);
+        x = have ? xn : x;
+        const bool ren = have && x < ENT_L;
+        const unsigned long long m = __ballot(ren);
+        const int64_t idx = pos + __popcll(m & ((1ull << lane) - 1ull));
+        const bool inside = idx < w1;
+        const uint32_t wv = rg[idx & 511];
+        bad = bad || (ren && !inside);
+        x = ren ? x << 16 | (inside ? wv : 0u) : x;
+        pos += __popcll(m);
+        if (have) dst[i] = RES ? (V)((int)e.y - 255) : (V)e.y;
+    }
+    return bad || pos != w1 || x != ENT_L;
+}
+
+// Decoder: ENT_DEC_WAVES groups of one plane per workgroup.  The workgroup
+// builds the plane's tables from the stream's frequencies: the present
+// symbols in order, {c | f << 16, symbol} (then a sentinel with c = M), and
+// for every 8-slot bucket the present symbol holding the bucket's first
+// slot.  A slot's symbol is then at most 7 entries past its bucket's.  Each
+// wave reads its lanes' states, and per step: slot = x mod M, the symbol,
+// x = f (x div M) + slot - c, and the lanes with x < L read the next words in
+// lane order.  A group must end exactly at its last word with every state
+// back at L; a frequency table, group offset or word count that does not fit
+// sets *status = RDL_ECORRUPT (reads stay inside the group).
+__global__ __launch_bounds__(256) void k_ent_dec(EntArgs a) {
+    __shared__ uint2 dtab[513];
+    __shared__ uint16_t bucket[ENT_M >> 3];
+    __shared__ uint32_t sh[4];
+    __shared__ uint16_t ring[ENT_DEC_WAVES][512];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int G = a.G, gpp = (G + ENT_DEC_WAVES - 1) / ENT_DEC_WAVES;
+    const int p = blockIdx.x / gpp, g = (blockIdx.x % gpp) * ENT_DEC_WAVES + w;
+    const int nsym = p < 3 ? 511 : 256;
+    const uint32_t fw = reinterpret_cast<const uint32_t *>(a.code + 40 + 1024 * p)[threadIdx.x];
+    const uint32_t s0 = 2 * threadIdx.x, f0 = fw & 0xFFFFu, f1 = fw >> 16;
+    uint32_t tot, P;
+    const uint32_t c0 = block_excl_scan<4>(f0 + f1, sh, tot);
+    const uint32_t j0 = block_excl_scan<4>((f0 > 0) + (f1 > 0), sh, P);
+    const uint32_t nbad = block_sum<4>(((int)s0 >= nsym && f0) + ((int)s0 + 1 >= nsym && f1), sh);
+    if (tot != ENT_M || nbad) {
+        if (threadIdx.x == 0 && a.status) atomicExch(a.status, RDL_ECORRUPT);
+        return;
+    }
+    if (f0) dtab[j0] = make_uint2(c0 | f0 << 16, s0);
+    if (f1) dtab[j0 + (f0 > 0)] = make_uint2((c0 + f0) | f1 << 16, s0 + 1);
+    if (threadIdx.x == 0) dtab[P] = make_uint2(ENT_M, 0u);
+    __syncthreads();
+    for (int u = threadIdx.x; u < (int)(ENT_M >> 3); u += 256) {
+        const uint32_t v = (uint32_t)u << 3;
+        int lo = 0, hi = (int)P - 1;  // the last present symbol with c <= v holds slot v
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if ((dtab[mid].x & 0xFFFFu) <= v) lo = mid;
+            else hi = mid - 1;
+        }
+        bucket[u] = (uint16_t)lo;
+    }
+    __syncthreads();
+    if (g >= G) return;
+    const int64_t gi = (int64_t)p * G + g;
+    const uint64_t *start = reinterpret_cast<const uint64_t *>(a.code + ENT_HDR);
+    const uint16_t *words = reinterpret_cast<const uint16_t *>(a.code + ENT_HDR + 32 * (int64_t)G);
+    const uint64_t u0 = start[gi], u1 = gi + 1 < 4 * (int64_t)G ? start[gi + 1] : (uint64_t)a.nwords;
+    if (!(u0 <= u1 && u1 <= (uint64_t)a.nwords && u1 - u0 >= 128)) {
+        if (lane == 0 && a.status) atomicExch(a.status, RDL_ECORRUPT);
+        return;
+    }
+    const int64_t w0 = (int64_t)u0, w1 = (int64_t)u1;
+    uint32_t x = (uint32_t)words[w0 + 2 * lane] << 16 | words[w0 + 2 * lane + 1];
+    int64_t pos = w0 + 128;
+    // The wave's words [b, b + 512) sit in an LDS ring (slot = position mod 512)
+    // and the next 256 in registers; once the first half is consumed the
+    // registers refill it and load the following 256.  A step consumes at
+    // most 64 words and starts below b + 256, so its reads stay in the ring.
+    // Words past the group's end read as 0 and are never consumed by a
+    // well-formed group.
+    uint16_t *rg = ring[w];
+    int64_t b = pos;
+    auto ld = [&](int64_t q) -> uint32_t {
+        const uint32_t v = words[q < w1 ? q : w1 - 1];  // clamped: w1 - 1 >= w0 + 127
+        return q < w1 ? v : 0u;
+    };
+#pragma unroll
+    for (int k = 0; k < 8; ++k) rg[(b + k * 64 + lane) & 511] = (uint16_t)ld(b + k * 64 + lane);
+    uint32_t R[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) R[k] = ld(b + 512 + k * 64 + lane);
+    const int64_t Z = (int64_t)64 << a.log2_k, base = (int64_t)g * Z;
+    const int n = (int)(a.N - base < Z ? a.N - base : Z);
+    bool bad;
+    if (p < 3)
+        bad = dec_group<true>(reinterpret_cast<int16_t *>(a.dst) + p * a.N + base, n, dtab, bucket, rg, R, b, pos,
+                              x, w1, ld, lane);
+    else
+        bad = dec_group<false>(a.dst + 6 * a.N + base, n, dtab, bucket, rg, R, b, pos, x, w1, ld, lane);
+    if (__ballot(bad) && lane == 0 && a.status) atomicExch(a.status, RDL_ECORRUPT);
+}
+
+}  // namespace
+
+void launch_ent_encode(const EntArgs &a, hipStream_t s) {
+    const int64_t ng = 4 * (int64_t)a.G;
+    hipLaunchKernelGGL(k_ent_hist, dim3((unsigned)((a.N + ENT_HIST_PX - 1) / ENT_HIST_PX)), dim3(ENT_HIST_THREADS), 0,
+                       s, a);
+    hipLaunchKernelGGL(k_ent_freq, dim3(4), dim3(512), 0, s, a);
+    hipLaunchKernelGGL(k_ent_enc, dim3((unsigned)((ng + 3) / 4)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_ent_scan, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_ent_pack, dim3((unsigned)ng), dim3(256), 0, s, a);
+}
+
+void launch_ent_decode(const EntArgs &a, hipStream_t s) {
+    if (a.status) hipLaunchKernelGGL(k_ent_status, dim3(1), dim3(64), 0, s, a.status);
+    const int gpp = (a.G + ENT_DEC_WAVES - 1) / ENT_DEC_WAVES;
+    hipLaunchKernelGGL(k_ent_dec, dim3((unsigned)(4 * gpp)), dim3(64 * ENT_DEC_WAVES), 0, s, a);
+}
+
+}  // namespace rdl

@@ -106,6 +106,48 @@ void launch_lhist(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_select(const ImgDesc *d, int n, hipStream_t s);
 void launch_decode_learned(const ImgDesc *d, int n, int wgs, hipStream_t s);
 
+// Entropy code of the enhancement layer (static rANS with 64 interleaved
+// states per group; kernels in rdl_entropy.hip, format in rdl.h).
+constexpr int ENT_PB = 15;                 // probability scale M = 2^15
+constexpr uint32_t ENT_M = 1u << ENT_PB;
+constexpr uint32_t ENT_L = 1u << 16;       // states lie in [2^16, 2^32)
+constexpr int ENT_HDR = 4136;              // fixed header bytes before the group table
+constexpr int ENT_HIST_PX = 16384;         // histogram workgroup: pixels per workgroup
+constexpr int ENT_DEC_WAVES = 4;           // decoder: groups (waves) per workgroup
+struct EntWs {
+    uint32_t hist[4][512];  // plane histograms; zero between calls (k_ent_freq clears)
+    uint2 tab[4][512];      // encoder table: {f | c << 16, bits of fl(1/f)}
+    uint32_t bad[4];        // plane holds a residual outside [-255, 255]
+    uint32_t ok;            // the stream is valid (set by k_ent_scan)
+    uint32_t pad[3];
+};
+struct EntArgs {
+    const uint8_t *resid;   // encoder input / decoder output: 7*H*W bytes
+    uint8_t *out;           // encoder: the code stream
+    const uint8_t *code;    // decoder: the code stream
+    uint8_t *dst;           // decoder: the enhancement layer
+    uint64_t *out_len;
+    int32_t *status;
+    EntWs *ws;
+    uint32_t *cnt;          // [4 G] words of each group
+    uint16_t *tmp;          // [4 G][64 K + 128] each group's words in emission order
+    int64_t N;
+    int64_t nwords;         // decoder: payload words
+    int32_t H, W, log2_k, G;
+};
+inline int64_t ent_groups(int H, int W, int log2_k) {
+    const int64_t z = (int64_t)64 << log2_k;
+    return ((int64_t)H * W + z - 1) / z;
+}
+inline size_t ent_cnt_off() { return (sizeof(EntWs) + 255) & ~(size_t)255; }
+inline size_t ent_tmp_off(int64_t G) { return (ent_cnt_off() + 4 * (size_t)G * 4 + 255) & ~(size_t)255; }
+inline size_t ent_ws_bytes(int H, int W, int log2_k) {
+    const int64_t G = ent_groups(H, W, log2_k);
+    return ent_tmp_off(G) + 4 * (size_t)G * (((size_t)64 << log2_k) + 128) * 2;
+}
+void launch_ent_encode(const EntArgs &a, hipStream_t s);
+void launch_ent_decode(const EntArgs &a, hipStream_t s);
+
 // Training kernels (defined in rdl_train.hip).
 void launch_train_samples(const uint8_t *rgbe, const uint8_t *sdr, int H, int W, int k_img, const int64_t *idx,
                           int64_t n, void *out, hipStream_t s);

@@ -31,6 +31,10 @@ HEADER_BYTES = HEADER_DTYPE.itemsize
 
 LAUNCH_DIRECT, LAUNCH_GRAPH = 0, 1
 
+#: Entropy code of the enhancement layer: fixed header bytes, default group size.
+ENT_HEADER_BYTES = 4136
+ENT_LOG2K_DEFAULT = 8
+
 # Exported symbols of include/rdl.h with their argument types.
 _vp, _i, _i64p = C.c_void_p, C.c_int, C.c_void_p
 _SIGS = {
@@ -44,6 +48,9 @@ _SIGS = {
     "rdl_decode_enh": ([_vp, _vp, _vp, _vp, _i, _i, _vp, _vp, _vp], _i),
     "rdl_encode_batch": ([_vp, _vp, _i, _vp], _i),
     "rdl_resid_hist": ([_vp, _vp, _i, _i, _vp, _vp], _i),
+    "rdl_ent_bound": ([_i, _i, _i], C.c_size_t),
+    "rdl_ent_encode": ([_vp, _vp, _i, _i, _i, _vp, C.c_size_t, _vp, _vp], _i),
+    "rdl_ent_decode": ([_vp, _vp, C.c_size_t, _vp, _i, _i, _vp, _vp, _vp], _i),
     "rdl_stage_keystat": ([_vp, _vp, _i, _i, _vp, _vp], _i),
     "rdl_stage_tmo_base": ([_vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp], _i),
     "rdl_stage_fit": ([_vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp], _i),
@@ -220,6 +227,39 @@ class Codec:
         hist = torch.empty((3, 511), dtype=torch.int64, device=resid.device)
         _chk(self._L.rdl_resid_hist(self._h, _ptr(resid), H, W, _ptr(hist), _stream(stream)), "rdl_resid_hist")
         return hist
+
+    # ------------------------------------------------- entropy code of the layer
+    def ent_bound(self, H: int, W: int, log2_k: int = ENT_LOG2K_DEFAULT) -> int:
+        return int(self._L.rdl_ent_bound(H, W, log2_k))
+
+    def ent_encode_into(self, resid: torch.Tensor, H: int, W: int, out: torch.Tensor, out_len: torch.Tensor,
+                        log2_k: int = ENT_LOG2K_DEFAULT, stream=None) -> None:
+        """Code stream of resid into out (uint8, >= ent_bound bytes); its length
+        goes to out_len (one int64 on the device).  Does not synchronise."""
+        assert out.dtype == torch.uint8 and out_len.dtype == torch.int64 and out_len.numel() == 1
+        _chk(self._L.rdl_ent_encode(self._h, _ptr(resid), H, W, int(log2_k), _ptr(out), out.numel(), _ptr(out_len),
+                                    _stream(stream)), "rdl_ent_encode")
+
+    def ent_encode(self, resid: torch.Tensor, H: int, W: int, log2_k: int = ENT_LOG2K_DEFAULT,
+                   stream=None) -> torch.Tensor:
+        """Code stream of an enhancement layer, trimmed to its length (synchronises)."""
+        out = torch.empty(self.ent_bound(H, W, log2_k), dtype=torch.uint8, device=resid.device)
+        n = torch.zeros(1, dtype=torch.int64, device=resid.device)
+        self.ent_encode_into(resid, H, W, out, n, log2_k, stream)
+        length = int(n.item())
+        if length == 0:
+            raise RdlError(RDL_EINVAL, "rdl_ent_encode (residual outside [-255, 255])")
+        return out[:length]
+
+    def ent_decode(self, code: torch.Tensor, H: int, W: int, out: torch.Tensor | None = None,
+                   status: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Enhancement layer (7 H W bytes) from a device code stream."""
+        hdr = code[:ENT_HEADER_BYTES].cpu().numpy()
+        if out is None:
+            out = torch.empty(7 * H * W, dtype=torch.uint8, device=code.device)
+        _chk(self._L.rdl_ent_decode(self._h, _ptr(code), code.numel(), hdr.ctypes.data, H, W, _ptr(out), _ptr(status),
+                                    _stream(stream)), "rdl_ent_decode")
+        return out
 
     def profile_encode(self, rgbe: torch.Tensor, q: int, out, reps: int = 20, stream=None):
         """Mean duration in ms of each stage kernel (HIP events on the stream)."""

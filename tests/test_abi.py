@@ -91,3 +91,17 @@ def test_launch_mode_rejects_null_context_host_only():
     assert L.rdl_set_launch_mode(None, 0) == rdl.RDL_EINVAL
     assert L.rdl_set_launch_mode(None, 1) == rdl.RDL_EINVAL
     assert (rdl.LAUNCH_DIRECT, rdl.LAUNCH_GRAPH) == (0, 1)
+
+
+def test_entropy_bound_and_argument_checks_host_only(O):
+    """The library's stream bound equals the oracle's; bad sizes, group sizes
+    and null pointers are rejected before any device work."""
+    rdl, L = _lib()
+    src = open(HDR).read()
+    assert int(re.search(r"#define RDL_ENT_HEADER_BYTES (\d+)", src).group(1)) == rdl.ENT_HEADER_BYTES == O.ENT_HDR
+    for H, W, k in [(1, 1, 4), (7, 9, 8), (2160, 3840, 8), (4321, 7679, 12), (1, 1 << 20, 4)]:
+        assert L.rdl_ent_bound(H, W, k) == O.ent_bound(H, W, k)
+    for H, W, k in [(0, 5, 8), (5, 0, 8), (3, 3, 3), (3, 3, 13), (1 << 16, 1 << 15, 8)]:
+        assert L.rdl_ent_bound(H, W, k) == 0
+    assert L.rdl_ent_encode(None, None, 3, 3, 8, None, 0, None, None) == rdl.RDL_EINVAL
+    assert L.rdl_ent_decode(None, None, 0, None, 3, 3, None, None, None) == rdl.RDL_EINVAL
