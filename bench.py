@@ -12,6 +12,8 @@ Also measured, outside the timed region:
   * per-kernel durations (each stage launched back to back between HIP events
     on the encoder's stream) -> roofline of the dominant kernel;
   * the lossless round trip through the GPU decoder, residual bits/pixel;
+  * the entropy code of the image's enhancement layer (static rANS): encode
+    and decode times, coded bits/pixel against the planes' H0, round trip;
   * the batched encoder on 64 uneven images (~275 Mpx, one launch per stage);
   * the learned estimator with per-region SLR fallback: bits/pixel against
     plain SLR on 16 held-out 1920x1080 images, and its throughput;
@@ -197,6 +199,8 @@ def main():
     ap.add_argument("--learned-steps", type=int, default=20, help="timed learned encodes (0 = skip)")
     ap.add_argument("--large-steps", type=int, default=3,
                     help="timed launches of the 256-image batch, plain and learned (0 = skip)")
+    ap.add_argument("--entropy-steps", type=int, default=50,
+                    help="timed entropy encodes/decodes of the image's enhancement layer (0 = skip)")
     ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch shapes")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -267,6 +271,38 @@ def main():
                     "unit": "GB/s", "frac": round(hbm_gbps / HBM_PEAK_GBPS, 4), "traffic": tr,
                     "bytes_per_px": ALGO_BYTES_PER_PX[dom], "avg_ms": round(stage_ms[dom], 5)}
     pipe_gbps = PIPELINE_BYTES_PER_PX * H * W / (ms_step * 1e-3) / 1e9
+
+    # ---- entropy code of the enhancement layer (static rANS) -----------------
+    entropy = None
+    if args.entropy_steps > 0:
+        k = rdl.ENT_LOG2K_DEFAULT
+        code = torch.empty(codec.ent_bound(H, W, k), dtype=torch.uint8, device="cuda")
+        clen = torch.zeros(1, dtype=torch.int64, device="cuda")
+        for _ in range(3):
+            codec.ent_encode_into(resid, H, W, code, clen, k)
+        ms_e = time_calls(lambda: codec.ent_encode_into(resid, H, W, code, clen, k), args.entropy_steps, stream)
+        nbytes = int(clen.item())
+        cview = code[:nbytes]
+        chdr = cview[:rdl.ENT_HEADER_BYTES].cpu().numpy()
+        back = torch.empty_like(resid)
+        st = torch.zeros(1, dtype=torch.int32, device="cuda")
+        for _ in range(3):
+            codec.ent_decode(cview, H, W, out=back, status=st, header=chdr)
+        ms_d = time_calls(lambda: codec.ent_decode(cview, H, W, out=back, status=st, header=chdr),
+                          args.entropy_steps, stream)
+        ok = bool(torch.equal(back, resid)) and int(st.item()) == 0
+        npx = H * W
+        entropy = {"workload": "the 3840x2160 image's enhancement layer (3 int16 residual planes + the exponent "
+                               "plane), static rANS, 64 interleaved states per group of %d symbols" % (64 << k),
+                   "log2_k": k, "ms_encode": round(ms_e, 5), "Mpixel_s_encode": round(npx / (ms_e * 1e-3) / 1e6, 1),
+                   "ms_decode": round(ms_d, 5), "Mpixel_s_decode": round(npx / (ms_d * 1e-3) / 1e6, 1),
+                   "bytes": nbytes, "bits_per_pixel_coded": round(8 * nbytes / npx, 4),
+                   "bits_per_pixel_h0": round(bpp + e_bits, 4), "lossless": ok,
+                   "encode_plus_entropy_ms": round(ms_step + ms_e, 5),
+                   "encode_plus_entropy_Mpixel_s": round(npx / ((ms_step + ms_e) * 1e-3) / 1e6, 1)}
+        say("entropy code: %.1f us encode, %.1f us decode, %.4f bits/px (H0 %.4f)" % (
+            ms_e * 1e3, ms_d * 1e3, entropy["bits_per_pixel_coded"], entropy["bits_per_pixel_h0"]))
+        del code, back
 
     # plain device copy of 1 GiB for scale (reads + writes 2 GiB)
     a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
@@ -404,6 +440,7 @@ def main():
         "pipeline_frac_of_hbm": round(pipe_gbps / HBM_PEAK_GBPS, 4),
         "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
         "device_copy_GBps": round(copy_gbps, 1),
+        "entropy": entropy,
         "batch": batch,
         "learned": learned,
         "large_batch": large,

@@ -22,9 +22,12 @@ namespace rdl {
 
 namespace {
 
-constexpr int ENT_HC = 8;                  // privatised LDS copies of the histograms, each
-constexpr int ENT_HSTRIDE = 1024 + 1;      //   2048 16-bit counters in 1024 words (odd stride:
-                                           //   copies of a bin fall in different banks)
+constexpr int ENT_HC = 4;                  // privatised LDS copies of the histograms
+constexpr bool ENT_PACK16 = false;         // 16-bit counters, two per word
+constexpr bool ENT_CMINOR = true;          // copies of a bin in adjacent words (else one block per copy)
+constexpr int ENT_HWORDS = ENT_PACK16 ? 1024 : 2048;   // words per copy
+constexpr int ENT_HSTRIDE = ENT_HWORDS + 1;            // odd stride between copy blocks
+constexpr int ENT_HTOTAL = ENT_CMINOR ? ENT_HC * ENT_HWORDS : ENT_HC * ENT_HSTRIDE;
 constexpr int ENT_HIST_THREADS = 512;
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
@@ -92,16 +95,21 @@ __device__ uint32_t block_excl_scan(uint32_t v, uint32_t *sh, uint32_t &total) {
 // adds each run of equal exponents over consecutive lanes with one atomic (the
 // run's first lane adds its length).  The copies are then added into the
 // image's histograms with integer atomics.
-__device__ __forceinline__ void ent_count(uint32_t *copy, uint32_t bin, uint32_t k) {
-    atomicAdd(copy + (bin >> 1), k << ((bin & 1) * 16));
+__device__ __forceinline__ uint32_t ent_word(uint32_t c, uint32_t bin) {
+    const uint32_t wb = ENT_PACK16 ? bin >> 1 : bin;
+    return ENT_CMINOR ? wb * ENT_HC + c : c * ENT_HSTRIDE + wb;
+}
+
+__device__ __forceinline__ void ent_count(uint32_t *h, uint32_t c, uint32_t bin, uint32_t k) {
+    atomicAdd(h + ent_word(c, bin), ENT_PACK16 ? k << ((bin & 1) * 16) : k);
 }
 
 __global__ __launch_bounds__(ENT_HIST_THREADS) void k_ent_hist(EntArgs a) {
-    __shared__ uint32_t h[ENT_HC * ENT_HSTRIDE];
-    for (int k = threadIdx.x; k < ENT_HC * ENT_HSTRIDE; k += ENT_HIST_THREADS) h[k] = 0;
+    __shared__ uint32_t h[ENT_HTOTAL];
+    for (int k = threadIdx.x; k < ENT_HTOTAL; k += ENT_HIST_THREADS) h[k] = 0;
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    uint32_t *mine = h + (lane & (ENT_HC - 1)) * ENT_HSTRIDE;
+    const uint32_t mine = (uint32_t)lane & (ENT_HC - 1);
     const int64_t i0 = (int64_t)blockIdx.x * ENT_HIST_PX;
     const int n = (int)(a.N - i0 < ENT_HIST_PX ? a.N - i0 : ENT_HIST_PX);
     constexpr int PER = ENT_HIST_PX / ENT_HIST_THREADS;  // 32 px per thread and plane
@@ -117,7 +125,7 @@ __global__ __launch_bounds__(ENT_HIST_THREADS) void k_ent_hist(EntArgs a) {
 #pragma unroll
         for (int j = 0; j < PER; ++j)
             if (j * ENT_HIST_THREADS + (int)threadIdx.x < n)
-                ent_count(mine, p * 512 + min((uint32_t)(v[j] + 255), 511u), 1u);
+                ent_count(h, mine, p * 512 + min((uint32_t)(v[j] + 255), 511u), 1u);
     }
     const uint8_t *e8 = a.resid + 6 * a.N + i0;
     int ev[PER];
@@ -136,14 +144,110 @@ __global__ __launch_bounds__(ENT_HIST_THREADS) void k_ent_hist(EntArgs a) {
         // the run ends at the next head (a lane past the end has v = -1, a head of its own)
         const unsigned long long after = lane == 63 ? 0ull : m >> (lane + 1);
         const int len = after ? (int)__builtin_ctzll(after) + 1 : 64 - lane;
-        if (head && v >= 0) ent_count(mine, 3 * 512 + v, (uint32_t)len);
+        if (head && v >= 0) ent_count(h, mine, 3 * 512 + v, (uint32_t)len);
     }
     __syncthreads();
     for (int b = threadIdx.x; b < 2048; b += ENT_HIST_THREADS) {
         uint32_t v = 0;
 #pragma unroll
-        for (int k = 0; k < ENT_HC; ++k) v += (h[k * ENT_HSTRIDE + (b >> 1)] >> ((b & 1) * 16)) & 0xFFFFu;
-        if (v) atomicAdd(&a.ws->hist[b >> 9][b & 511], v);
+        for (int k = 0; k < ENT_HC; ++k) {
+            const uint32_t wv = h[ent_word(k, b)];
+            v += ENT_PACK16 ? (wv >> ((b & 1) * 16)) & 0xFFFFu : wv;
+        }
+        if (v) atomicAdd(&a.ws->hist[blockIdx.x % ENT_HSTRIPES][b >> 9][b & 511], v);
+    }
+}
+
+// The same histograms from 16-byte loads, for a layer at a 16-byte aligned
+// address with at least 16 pixels.  Workgroups [0, nr) read the residual
+// planes as one array of 3N int16 values (element e is in plane
+// (e >= N) + (e >= 2N)), 8 per lane and load; the rest read the exponent
+// bytes, 16 per lane and load, and count each run of equal exponents within
+// the lane's 16 bytes with one atomic.  Loads cover whole aligned 16-byte
+// chunks: the residual chunks end at most 14 bytes past the residuals, inside
+// the exponent plane (N >= 16); the exponent chunks stop at the last chunk
+// that ends inside the layer, and the remaining bytes (fewer than 16) are
+// counted one per lane by the last workgroup.
+constexpr int ENT_VEC_CHUNKS = 8;  // 16-byte chunks per lane and workgroup
+constexpr int ENT_VEC_SPAN = ENT_HIST_THREADS * ENT_VEC_CHUNKS * 16;  // bytes per workgroup
+
+__global__ __launch_bounds__(ENT_HIST_THREADS) void k_ent_hist_vec(EntArgs a, int nr) {
+    __shared__ uint32_t h[ENT_HTOTAL];
+    for (int k = threadIdx.x; k < ENT_HTOTAL; k += ENT_HIST_THREADS) h[k] = 0;
+    __syncthreads();
+    const uint32_t mine = threadIdx.x & (ENT_HC - 1);
+    const int64_t N = a.N;
+    if ((int)blockIdx.x < nr) {
+        const int64_t nchunk = (6 * N + 15) >> 4;
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.resid);
+        uint4 q[ENT_VEC_CHUNKS];
+        int64_t ch[ENT_VEC_CHUNKS];
+#pragma unroll
+        for (int j = 0; j < ENT_VEC_CHUNKS; ++j) {
+            ch[j] = ((int64_t)blockIdx.x * ENT_VEC_CHUNKS + j) * ENT_HIST_THREADS + threadIdx.x;
+            q[j] = src[ch[j] < nchunk ? ch[j] : nchunk - 1];
+        }
+#pragma unroll
+        for (int j = 0; j < ENT_VEC_CHUNKS; ++j) {
+            const uint32_t w4[4] = {q[j].x, q[j].y, q[j].z, q[j].w};
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int64_t e = ch[j] * 8 + k;
+                if (ch[j] < nchunk && e < 3 * N) {
+                    const int r = (int)(int16_t)(w4[k >> 1] >> (16 * (k & 1)));
+                    const uint32_t p = (e >= N) + (e >= 2 * N);
+                    ent_count(h, mine, p * 512 + min((uint32_t)(r + 255), 511u), 1u);
+                }
+            }
+        }
+    } else {
+        const uintptr_t e_lo = reinterpret_cast<uintptr_t>(a.resid) + 6 * N, e_hi = e_lo + N;
+        const uintptr_t c_lo = e_lo & ~(uintptr_t)15;
+        const int64_t nchunk = (int64_t)((e_hi & ~(uintptr_t)15) - c_lo) >> 4;  // whole chunks inside the layer
+        const int wb = (int)blockIdx.x - nr;
+        uint4 q[ENT_VEC_CHUNKS];
+        int64_t ch[ENT_VEC_CHUNKS];
+#pragma unroll
+        for (int j = 0; j < ENT_VEC_CHUNKS; ++j) {
+            ch[j] = ((int64_t)wb * ENT_VEC_CHUNKS + j) * ENT_HIST_THREADS + threadIdx.x;
+            const int64_t cc = ch[j] < nchunk ? ch[j] : (nchunk > 0 ? nchunk - 1 : 0);
+            q[j] = nchunk > 0 ? reinterpret_cast<const uint4 *>(c_lo)[cc] : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < ENT_VEC_CHUNKS; ++j) {
+            if (ch[j] >= nchunk) continue;
+            const uint32_t w4[4] = {q[j].x, q[j].y, q[j].z, q[j].w};
+            const uintptr_t at = c_lo + (uintptr_t)ch[j] * 16;
+            int cur = -1;
+            uint32_t len = 0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int v = (int)((w4[k >> 2] >> (8 * (k & 3))) & 255u);
+                const int key = at + k >= e_lo ? v : -1;  // bytes before the plane are residuals
+                if (key != cur) {
+                    if (cur >= 0) ent_count(h, mine, 3 * 512 + cur, len);
+                    cur = key;
+                    len = 0;
+                }
+                ++len;
+            }
+            if (cur >= 0) ent_count(h, mine, 3 * 512 + cur, len);
+        }
+        if (wb == (int)gridDim.x - nr - 1) {  // bytes after the last whole chunk
+            const uintptr_t t0 = c_lo + (uintptr_t)nchunk * 16;
+            const uintptr_t b = (t0 > e_lo ? t0 : e_lo) + threadIdx.x;
+            if (b < e_hi) ent_count(h, mine, 3 * 512 + *reinterpret_cast<const uint8_t *>(b), 1u);
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < 2048; b += ENT_HIST_THREADS) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int k = 0; k < ENT_HC; ++k) {
+            const uint32_t wv = h[ent_word(k, b)];
+            v += ENT_PACK16 ? (wv >> ((b & 1) * 16)) & 0xFFFFu : wv;
+        }
+        if (v) atomicAdd(&a.ws->hist[blockIdx.x % ENT_HSTRIPES][b >> 9][b & 511], v);
     }
 }
 
@@ -156,8 +260,12 @@ __global__ __launch_bounds__(512) void k_ent_freq(EntArgs a) {
     __shared__ uint32_t sh[8];
     __shared__ unsigned long long shm[8];
     const int p = blockIdx.x, s = threadIdx.x, nsym = p < 3 ? 511 : 256;
-    const uint32_t h = a.ws->hist[p][s];
-    a.ws->hist[p][s] = 0;
+    uint32_t h = 0;
+#pragma unroll
+    for (int k = 0; k < ENT_HSTRIPES; ++k) {
+        h += a.ws->hist[k][p][s];
+        a.ws->hist[k][p][s] = 0;
+    }
     const bool pres = s < nsym && h > 0;
     const uint32_t nbad = block_sum<8>(s >= nsym && h > 0 ? 1u : 0u, sh);
     const uint32_t P = block_sum<8>(pres ? 1u : 0u, sh);
@@ -196,20 +304,27 @@ __global__ __launch_bounds__(512) void k_ent_freq(EntArgs a) {
 // (int16 values, symbol r + 255), else the exponent plane (bytes).
 template <bool RES, typename V>
 __device__ __forceinline__ void enc_group(const V *src, int n, const uint2 *tb, uint16_t *out, uint32_t *cnt_out,
-                                          int lane) {
+                                          int lane, int64_t dummy) {
     const int T = (n + 63) >> 6;
+    const int tfull = (n >> 6) - 1;  // steps 0..tfull hold a symbol in every lane
     // Symbols of steps t0, t0 - 1, ..., t0 - 7 and a mask of the lane's valid
     // ones.  Every load reads a valid address (the index is clamped) and its
     // value is used unconditionally, so the loads stay free of branches; the
     // next block's loads are issued before the current block is coded.  Steps
     // before the first (t < 0) have no symbol in any lane and change nothing.
+    auto sym_of = [](int v) -> uint32_t { return RES ? min((uint32_t)(v + 255), 511u) : (uint32_t)v; };
     auto load_block = [&](int t0, uint32_t (&sv)[8]) -> uint32_t {
+        if (t0 - 7 >= 0 && t0 <= tfull) {  // whole block inside the group: fixed offsets
+            const V *q = src + t0 * 64 + lane;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) sv[k] = sym_of((int)q[-64 * k]);
+            return 0xFFu;
+        }
         uint32_t vm = 0;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int t = t0 - k, i = t * 64 + lane;
-            const int v = (int)src[min(max(i, 0), n - 1)];
-            sv[k] = RES ? min((uint32_t)(v + 255), 511u) : (uint32_t)v;
+            sv[k] = sym_of((int)src[min(max(i, 0), n - 1)]);
             vm |= (t >= 0 && i < n ? 1u : 0u) << k;
         }
         return vm;
@@ -227,11 +342,12 @@ __device__ __forceinline__ void enc_group(const V *src, int n, const uint2 *tb, 
             const uint32_t f = e.x & 0xFFFFu, c = e.x >> 16;
             const bool ren = have && (x >> 17) >= f;
             const unsigned long long m = __ballot(ren);
-            if (ren) out[wpos + __popcll(m & ~((2ull << lane) - 1ull))] = (uint16_t)x;
+            // every lane stores (no branch): lanes without a word write their dummy slot
+            out[ren ? (int64_t)(wpos + __popcll(m & ~((2ull << lane) - 1ull))) : dummy] = (uint16_t)x;
             wpos += __popcll(m);
             const uint32_t xr = ren ? x >> 16 : x;
             uint32_t q = (uint32_t)((float)xr * __uint_as_float(e.y));
-            uint32_t r = xr - q * f;
+            uint32_t r = xr - __umul24(q, f);  // q < 2^18, f <= 2^15: 24-bit product exact
             const bool lo = (int32_t)r < 0, hi = !lo && r >= f;
             q = lo ? q - 1 : hi ? q + 1 : q;
             r = lo ? r + f : hi ? r - f : r;
@@ -263,11 +379,12 @@ __global__ __launch_bounds__(256) void k_ent_enc(EntArgs a) {
     }
     const int64_t Z = (int64_t)64 << a.log2_k, g = gi - (int64_t)p * G, base = g * Z;
     const int n = (int)(a.N - base < Z ? a.N - base : Z);
-    uint16_t *out = a.tmp + gi * (Z + 128);
+    uint16_t *out = a.tmp + gi * ent_slot(a.log2_k);
+    const int64_t dummy = Z + 128 + lane;
     if (p < 3)
-        enc_group<true>((const int16_t *)a.resid + p * a.N + base, n, stab[w], out, a.cnt + gi, lane);
+        enc_group<true>((const int16_t *)a.resid + p * a.N + base, n, stab[w], out, a.cnt + gi, lane, dummy);
     else
-        enc_group<false>(a.resid + 6 * a.N + base, n, stab[w], out, a.cnt + gi, lane);
+        enc_group<false>(a.resid + 6 * a.N + base, n, stab[w], out, a.cnt + gi, lane, dummy);
 }
 
 // Group offsets (exclusive prefix sum of the word counts) into the stream's
@@ -303,7 +420,7 @@ __global__ __launch_bounds__(256) void k_ent_pack(EntArgs a) {
     const uint32_t n = a.cnt[gi];
     const uint64_t st = reinterpret_cast<const uint64_t *>(a.out + ENT_HDR)[gi];
     const int64_t Z = (int64_t)64 << a.log2_k;
-    const uint16_t *src = a.tmp + gi * (Z + 128);
+    const uint16_t *src = a.tmp + gi * ent_slot(a.log2_k);
     uint16_t *dst = reinterpret_cast<uint16_t *>(a.out + ENT_HDR + 32 * (int64_t)a.G) + st;
     for (uint32_t k = threadIdx.x; k < n; k += 256) dst[k] = src[n - 1 - k];
 }
@@ -440,8 +557,14 @@ __global__ __launch_bounds__(256) void k_ent_dec(EntArgs a) {
 
 void launch_ent_encode(const EntArgs &a, hipStream_t s) {
     const int64_t ng = 4 * (int64_t)a.G;
-    hipLaunchKernelGGL(k_ent_hist, dim3((unsigned)((a.N + ENT_HIST_PX - 1) / ENT_HIST_PX)), dim3(ENT_HIST_THREADS), 0,
-                       s, a);
+    if ((reinterpret_cast<uintptr_t>(a.resid) & 15) == 0 && a.N >= 16) {
+        const int64_t nr = ((6 * a.N + 15) / 16 + ENT_VEC_SPAN / 16 - 1) / (ENT_VEC_SPAN / 16);
+        const int64_t ne = (a.N + 16 + ENT_VEC_SPAN - 1) / ENT_VEC_SPAN;
+        hipLaunchKernelGGL(k_ent_hist_vec, dim3((unsigned)(nr + ne)), dim3(ENT_HIST_THREADS), 0, s, a, (int)nr);
+    } else {
+        hipLaunchKernelGGL(k_ent_hist, dim3((unsigned)((a.N + ENT_HIST_PX - 1) / ENT_HIST_PX)), dim3(ENT_HIST_THREADS),
+                           0, s, a);
+    }
     hipLaunchKernelGGL(k_ent_freq, dim3(4), dim3(512), 0, s, a);
     hipLaunchKernelGGL(k_ent_enc, dim3((unsigned)((ng + 3) / 4)), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_ent_scan, dim3(1), dim3(1024), 0, s, a);

@@ -114,8 +114,10 @@ constexpr uint32_t ENT_L = 1u << 16;       // states lie in [2^16, 2^32)
 constexpr int ENT_HDR = 4136;              // fixed header bytes before the group table
 constexpr int ENT_HIST_PX = 16384;         // histogram workgroup: pixels per workgroup
 constexpr int ENT_DEC_WAVES = 4;           // decoder: groups (waves) per workgroup
+constexpr int ENT_HSTRIPES = 16;           // copies of the image's histograms (workgroup w adds
+                                           //   into copy w mod 16, so hot bins take few atomics)
 struct EntWs {
-    uint32_t hist[4][512];  // plane histograms; zero between calls (k_ent_freq clears)
+    uint32_t hist[ENT_HSTRIPES][4][512];  // plane histograms; zero between calls (k_ent_freq clears)
     uint2 tab[4][512];      // encoder table: {f | c << 16, bits of fl(1/f)}
     uint32_t bad[4];        // plane holds a residual outside [-255, 255]
     uint32_t ok;            // the stream is valid (set by k_ent_scan)
@@ -130,7 +132,7 @@ struct EntArgs {
     int32_t *status;
     EntWs *ws;
     uint32_t *cnt;          // [4 G] words of each group
-    uint16_t *tmp;          // [4 G][64 K + 128] each group's words in emission order
+    uint16_t *tmp;          // [4 G][ent_slot] each group's words in emission order
     int64_t N;
     int64_t nwords;         // decoder: payload words
     int32_t H, W, log2_k, G;
@@ -139,11 +141,14 @@ inline int64_t ent_groups(int H, int W, int log2_k) {
     const int64_t z = (int64_t)64 << log2_k;
     return ((int64_t)H * W + z - 1) / z;
 }
+// Workspace words per group: at most one word per symbol plus the 128 state
+// words, then 64 words that lanes without a word to emit write instead.
+__host__ __device__ inline int64_t ent_slot(int log2_k) { return ((int64_t)64 << log2_k) + 128 + 64; }
 inline size_t ent_cnt_off() { return (sizeof(EntWs) + 255) & ~(size_t)255; }
 inline size_t ent_tmp_off(int64_t G) { return (ent_cnt_off() + 4 * (size_t)G * 4 + 255) & ~(size_t)255; }
 inline size_t ent_ws_bytes(int H, int W, int log2_k) {
     const int64_t G = ent_groups(H, W, log2_k);
-    return ent_tmp_off(G) + 4 * (size_t)G * (((size_t)64 << log2_k) + 128) * 2;
+    return ent_tmp_off(G) + 4 * (size_t)G * (size_t)ent_slot(log2_k) * 2;
 }
 void launch_ent_encode(const EntArgs &a, hipStream_t s);
 void launch_ent_decode(const EntArgs &a, hipStream_t s);

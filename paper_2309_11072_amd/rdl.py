@@ -252,9 +252,12 @@ class Codec:
         return out[:length]
 
     def ent_decode(self, code: torch.Tensor, H: int, W: int, out: torch.Tensor | None = None,
-                   status: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-        """Enhancement layer (7 H W bytes) from a device code stream."""
-        hdr = code[:ENT_HEADER_BYTES].cpu().numpy()
+                   status: torch.Tensor | None = None, header: np.ndarray | None = None, stream=None) -> torch.Tensor:
+        """Enhancement layer (7 H W bytes) from a device code stream.  header: a
+        host copy of the stream's first ENT_HEADER_BYTES bytes (read from the
+        device, synchronously, when not given)."""
+        hdr = np.ascontiguousarray(header if header is not None else code[:ENT_HEADER_BYTES].cpu().numpy())
+        assert hdr.dtype == np.uint8 and hdr.size >= ENT_HEADER_BYTES
         if out is None:
             out = torch.empty(7 * H * W, dtype=torch.uint8, device=code.device)
         _chk(self._L.rdl_ent_decode(self._h, _ptr(code), code.numel(), hdr.ctypes.data, H, W, _ptr(out), _ptr(status),

@@ -39,8 +39,15 @@ def make_layer(H, W, seed, spread=3.0, e_lo=110, e_hi=150, outlier=0.0):
     return np.concatenate([r.astype(np.int16).reshape(-1).view(np.uint8), E.astype(np.uint8).reshape(-1)])
 
 
-def gpu_roundtrip(codec, O, x, H, W, log2_k):
-    d = torch.from_numpy(x).cuda()
+def gpu_roundtrip(codec, O, x, H, W, log2_k, offset=0):
+    """offset: place the layer that many bytes into a device buffer (a layer
+    that is not 16-byte aligned takes the library's narrow-load histogram)."""
+    if offset:
+        buf = torch.zeros(x.size + offset, dtype=torch.uint8, device="cuda")
+        buf[offset:] = torch.from_numpy(x).cuda()
+        d = buf[offset:]
+    else:
+        d = torch.from_numpy(x).cuda()
     code = codec.ent_encode(d, H, W, log2_k)
     got = code.cpu().numpy().tobytes()
     ref = O.ent_encode(x, H, W, log2_k)
@@ -76,6 +83,14 @@ def test_wide_and_degenerate_planes(codec, O):
     r[2, ::7, ::3] = 0
     x = np.concatenate([r.reshape(-1).view(np.uint8), np.full(H * W, 255, np.uint8)])
     gpu_roundtrip(codec, O, x, H, W, 4)
+
+
+@pytest.mark.parametrize("H,W,offset", [(3, 5, 0), (97, 131, 2), (300, 401, 6), (17, 1, 0), (4, 4, 0)])
+def test_histogram_paths(codec, O, H, W, offset):
+    """Both histogram kernels: 16-byte loads (aligned layer, at least 16 pixels)
+    and 2-byte loads (any other), with residual and exponent tails."""
+    _say("entropy histogram path", H, W, offset)
+    gpu_roundtrip(codec, O, make_layer(H, W, 31 * H + W, spread=5.0, e_lo=0, e_hi=256), H, W, 4, offset=offset)
 
 
 def test_workspace_reuse_across_sizes(codec, O):
