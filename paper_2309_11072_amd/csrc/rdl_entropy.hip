@@ -419,10 +419,22 @@ __global__ __launch_bounds__(256) void k_ent_pack(EntArgs a) {
     const int64_t gi = blockIdx.x;
     const uint32_t n = a.cnt[gi];
     const uint64_t st = reinterpret_cast<const uint64_t *>(a.out + ENT_HDR)[gi];
-    const int64_t Z = (int64_t)64 << a.log2_k;
-    const uint16_t *src = a.tmp + gi * ent_slot(a.log2_k);
-    uint16_t *dst = reinterpret_cast<uint16_t *>(a.out + ENT_HDR + 32 * (int64_t)a.G) + st;
-    for (uint32_t k = threadIdx.x; k < n; k += 256) dst[k] = src[n - 1 - k];
+    const uint16_t *__restrict__ src = a.tmp + gi * ent_slot(a.log2_k);
+    uint16_t *__restrict__ dst = reinterpret_cast<uint16_t *>(a.out + ENT_HDR + 32 * (int64_t)a.G) + st;
+    // 8 loads in flight per lane (indices clamped: a group has n >= 128 words)
+    for (uint32_t k0 = 0; k0 < n; k0 += 8 * 256) {
+        uint16_t v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint32_t k = k0 + j * 256 + threadIdx.x;
+            v[j] = src[k < n ? n - 1 - k : 0];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint32_t k = k0 + j * 256 + threadIdx.x;
+            if (k < n) dst[k] = v[j];
+        }
+    }
 }
 
 __global__ void k_ent_status(int32_t *st) {
