@@ -108,11 +108,44 @@ int rdl_encode_enh(rdl_ctx *ctx, const uint8_t *rgbe, int H, int W, int q, uint8
  * S* = GF(sdr), M = M*(a_E, b_E, S*) + r, out_rgbe = (M, E).  coeffs is a
  * DEVICE header (as written by rdl_encode_enh); sdr, coeffs and out_rgbe
  * start on 4-byte boundaries, resid on a 2-byte one.  If status (device int32,
- * may be NULL) is given it receives RDL_OK, or RDL_ECORRUPT when the header's
- * magic, version or size do not match, a coefficient is outside the bounds
- * rdl_header_validate checks, or a decoded mantissa leaves [0, 255]. */
+ * may be NULL) is given it is set to RDL_OK first, then to RDL_ECORRUPT if the
+ * header's magic, version or size do not match, a coefficient is outside the
+ * bounds rdl_header_validate checks, or a decoded mantissa leaves [0, 255]. */
 int rdl_decode_enh(rdl_ctx *ctx, const uint8_t *sdr, const rdl_header *coeffs, const void *resid,
                    int H, int W, uint8_t *out_rgbe, int32_t *status, void *stream);
+
+/* Decoder of the base layer (Sec. II.B: the base layer's JPEG decoder returns
+ * S; Sec. IV: quality Q): from the quantised coefficients dct (device, int16
+ * [3][H8][W8], H8 and W8 rounded up to 8, block (bx, by)'s coefficient (v, u)
+ * at row 8 by + v, column 8 bx + u, as rdl_stage_tmo_base writes them) and
+ * the quality in the DEVICE header coeffs: D = Fq Q, the normative integer
+ * IDCT, + 128, clamp, JFIF inverse colour transform, crop -> out_sdr (device,
+ * H*W*3).  For coefficients the encoder wrote this returns exactly the
+ * encoder's S (the decoded values of any other coefficients whose products
+ * Fq Q exceed 16 bits are unspecified, but stay in [0, 255]).  dct on a
+ * 2-byte boundary, coeffs and out_sdr on 4-byte ones.  status (device int32,
+ * may be NULL): RDL_OK, or RDL_ECORRUPT when the header's magic, version or
+ * size do not match or its quality is outside [1, 100]. */
+int rdl_base_decode(rdl_ctx *ctx, const int16_t *dct, const rdl_header *coeffs, int H, int W, uint8_t *out_sdr,
+                    int32_t *status, void *stream);
+
+/* Batched decoder: n images of any sizes in one pass per stage.  imgs is a
+ * HOST array.  For an image with dct (may be NULL) the base layer is first
+ * decoded from its coefficients into sdr (as rdl_base_decode); otherwise sdr
+ * holds S.  Then every image is decoded as rdl_decode_enh would decode it,
+ * the learned ones with the context's model.  Alignments and status as for
+ * those two calls.  The context's descriptor table is shared with the other
+ * single-call entry points: calls on one context must not overlap. */
+typedef struct rdl_dimage {
+    const int16_t *dct;
+    uint8_t *sdr;
+    const rdl_header *hdr;
+    const void *resid;
+    int32_t H, W;
+    uint8_t *out_rgbe;
+    int32_t *status;
+} rdl_dimage;
+int rdl_decode_batch(rdl_ctx *ctx, const rdl_dimage *imgs, int n, void *stream);
 
 /* Batched encoder: n images of any sizes and qualities in one pass per stage
  * (every stage kernel walks a flattened tile space over all images).  imgs is

@@ -50,6 +50,8 @@ def lib():
         L.oracle_quantise.restype = i32
         L.oracle_base_layer.argtypes = [vp, C.c_int, C.c_int, C.c_int, vp, vp]
         L.oracle_gf.argtypes = [vp, C.c_int, C.c_int, vp]
+        L.oracle_base_decode.argtypes = [vp, C.c_int, C.c_int, C.c_int, vp]
+        L.oracle_base_decode.restype = C.c_int
         L.oracle_sums.argtypes = [vp, vp, i64, vp]
         L.oracle_solve.argtypes = [vp, vp, vp, vp]
         L.oracle_mstar.argtypes = [i32, i32, i32]
@@ -155,6 +157,17 @@ def base_layer(sdr0: np.ndarray, q: int, want_dct: bool = False):
         dct = np.zeros((3, (H + 7) // 8 * 8, (W + 7) // 8 * 8), np.int16)
     lib().oracle_base_layer(_p(sdr0), H, W, q, _p(S), _p(dct) if dct is not None else None)
     return (S, dct) if want_dct else S
+
+
+def base_decode(dctq: np.ndarray, H: int, W: int, q: int) -> np.ndarray:
+    """S from the quantised coefficients int16 [3][H8][W8] at quality q."""
+    dctq = np.ascontiguousarray(dctq, np.int16)
+    H8, W8 = (H + 7) // 8 * 8, (W + 7) // 8 * 8
+    assert dctq.size == 3 * H8 * W8
+    S = np.zeros((H, W, 3), np.uint8)
+    if lib().oracle_base_decode(_p(dctq), H, W, q, _p(S)):
+        raise ValueError("oracle_base_decode: bad arguments")
+    return S
 
 
 def gf(S: np.ndarray) -> np.ndarray:

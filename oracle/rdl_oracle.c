@@ -358,6 +358,44 @@ void oracle_base_layer(const uint8_t *sdr0, int H, int W, int q, uint8_t *S, int
         }
 }
 
+/* Decoder 1 of the base layer (Sec. II.B: the JPEG decoder returns S): from
+ * the quantised coefficients dctq (layout of oracle_base_layer) at quality q,
+ * D = Fq * Q, inverse DCT, inverse colour transform, crop to H x W.  For the
+ * coefficients oracle_base_layer writes this is the second half of that
+ * function and returns the same S.  Returns -1 for bad arguments. */
+int oracle_base_decode(const int16_t *dctq, int H, int W, int q, uint8_t *S)
+{
+    if (!dctq || !S || H < 1 || W < 1 || q < 1 || q > 100) return -1;
+    init_tables();
+    int32_t qt[2][64];
+    oracle_quant_table(q, 0, qt[0]);
+    oracle_quant_table(q, 1, qt[1]);
+    int H8 = (H + 7) / 8 * 8, W8 = (W + 7) / 8 * 8;
+    for (int by = 0; by < H8 / 8; by++)
+        for (int bx = 0; bx < W8 / 8; bx++) {
+            int D[8][8], rec[3][8][8];
+            for (int c = 0; c < 3; c++) {
+                for (int v = 0; v < 8; v++)
+                    for (int u = 0; u < 8; u++)
+                        D[v][u] = dctq[((int64_t)c * H8 + by * 8 + v) * W8 + bx * 8 + u] *
+                                  qt[c == 0 ? 0 : 1][v * 8 + u];
+                idct8x8(D, rec[c]);
+            }
+            for (int y = 0; y < 8; y++)
+                for (int x = 0; x < 8; x++) {
+                    int yy = by * 8 + y, xx = bx * 8 + x;
+                    if (yy >= H || xx >= W) continue;
+                    int R, G, B;
+                    ycc_to_rgb(rec[0][y][x], rec[1][y][x], rec[2][y][x], &R, &G, &B);
+                    uint8_t *o = S + 3 * ((int64_t)yy * W + xx);
+                    o[0] = (uint8_t)R;
+                    o[1] = (uint8_t)G;
+                    o[2] = (uint8_t)B;
+                }
+        }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* C10: GF restoration S* = GF(S): 3x3 binomial (1, 6, 1) x (1, 6, 1) / 64, */
 /* round half up, borders replicated at the image edge, per channel.        */

@@ -492,9 +492,67 @@ int rdl_decode_enh(rdl_ctx *c, const uint8_t *sdr, const rdl_header *coeffs, con
     const Grid gr = layout(c, v);
     int rc = upload(c, v, s);
     if (rc) return rc;
+    if (status) launch_status_init(c->d_desc, 1, s);
     launch_decode(c->d_desc, 1, gr.res, s);
     if (c->d_model) launch_decode_learned(c->d_desc, 1, gr.learn, s);
     return check_launch("k_decode");
+}
+
+int rdl_decode_batch(rdl_ctx *c, const rdl_dimage *imgs, int n, void *stream) {
+    if (!c || !imgs || n < 1) return RDL_EINVAL;
+    std::vector<ImgDesc> v((size_t)n, blank());
+    bool any_dct = false, any_status = false;
+    for (int k = 0; k < n; ++k) {
+        const rdl_dimage &m = imgs[k];
+        if (!m.sdr || !m.hdr || !m.resid || !m.out_rgbe || !size_ok(m.H, m.W)) return RDL_EINVAL;
+        if (!aligned4(m.sdr) || !aligned4(m.hdr) || !aligned4(m.out_rgbe) ||
+            (reinterpret_cast<uintptr_t>(m.resid) & 1) || (reinterpret_cast<uintptr_t>(m.dct) & 1))
+            return RDL_EINVAL;
+        ImgDesc &d = v[k];
+        d.dct = (int16_t *)m.dct;
+        d.sdr = m.sdr;
+        d.hdr = (rdl_header *)m.hdr;
+        d.resid = (uint8_t *)m.resid;
+        d.out_rgbe = m.out_rgbe;
+        d.status = m.status;
+        d.H = m.H;
+        d.W = m.W;
+        d.model = c->d_model;
+        d.model_hash = c->model_hash;
+        any_dct = any_dct || m.dct;
+        any_status = any_status || m.status;
+    }
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    const Grid gr = layout(c, v);
+    int rc = upload(c, v, s);
+    if (rc) return rc;
+    if (any_status) launch_status_init(c->d_desc, n, s);
+    if (any_dct) launch_base_decode(c->d_desc, n, gr.blk, s);
+    launch_decode(c->d_desc, n, gr.res, s);
+    if (c->d_model) launch_decode_learned(c->d_desc, n, gr.learn, s);
+    return check_launch("rdl_decode_batch");
+}
+
+int rdl_base_decode(rdl_ctx *c, const int16_t *dct, const rdl_header *coeffs, int H, int W, uint8_t *out_sdr,
+                    int32_t *status, void *stream) {
+    if (!c || !dct || !coeffs || !out_sdr || !size_ok(H, W)) return RDL_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(dct) & 1) || !aligned4(coeffs) || !aligned4(out_sdr)) return RDL_EINVAL;
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<ImgDesc> v(1, blank());
+    v[0].dct = (int16_t *)dct;
+    v[0].hdr = (rdl_header *)coeffs;
+    v[0].sdr = out_sdr;
+    v[0].status = status;
+    v[0].H = H;
+    v[0].W = W;
+    const Grid gr = layout(c, v);
+    int rc = upload(c, v, s);
+    if (rc) return rc;
+    if (status) launch_status_init(c->d_desc, 1, s);
+    launch_base_decode(c->d_desc, 1, gr.blk, s);
+    return check_launch("k_base_decode");
 }
 
 int rdl_resid_hist(rdl_ctx *c, const void *resid, int H, int W, int64_t *hist, void *stream) {

@@ -100,6 +100,8 @@ void launch_solve(const ImgDesc *d, int n, hipStream_t s);
 void launch_key_total(const ImgDesc *d, int n, int64_t *out2, hipStream_t s);
 void launch_resid(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_decode(const ImgDesc *d, int n, int wgs, hipStream_t s);
+void launch_base_decode(const ImgDesc *d, int n, int wgs, hipStream_t s);
+void launch_status_init(const ImgDesc *d, int n, hipStream_t s);
 void launch_hist(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_learn(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_lhist(const ImgDesc *d, int n, int wgs, hipStream_t s);

@@ -385,6 +385,52 @@ __device__ __forceinline__ int quant_dequant(int F, uint4 qc, int &Fq) {
     return __mul24(Fq, (int)(qc.x >> 24));
 }
 
+// Last phase of the base layer (shared by the encoder and the base-layer
+// decoder): lane = row y of block j, whose IDCT column outputs sit in
+// s_X[c][j] (two int16 per word, transposed as the column pass leaves them).
+// IDCT row pass, + 128, clamp, inverse colour transform, crop, store S.
+__device__ __forceinline__ void base_store_row(const ImgDesc &d, const uint32_t (*s_X)[BLK_WG][33], int j, int r,
+                                               int by, int x0) {
+    const int H = d.H, W = d.W;
+    const int y = r;
+    const int yy = by * 8 + y;
+    if (yy >= H) return;
+    int smp[3][8];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const uint32_t *rw = &s_X[c][j][y * 4];
+        int o[8];
+        idct1((int)rw[0], (int)rw[1], (int)rw[2], (int)rw[3], 16384 + (128 << 15), o);
+#pragma unroll
+        for (int x = 0; x < 8; ++x) smp[c][x] = min(max(o[x] >> 15, 0), 255);
+    }
+    uint32_t ow[6];
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+        // JFIF inverse transform; the chroma offset of 128 is folded into the
+        // rounding constants.
+        const int Yv = smp[0][x], cb = smp[1][x], cr = smp[2][x];
+        const int R = min(max(Yv + ((91881 * cr + 32768 - 91881 * 128) >> 16), 0), 255);
+        const int G = min(max(Yv + ((-22554 * cb - 46802 * cr + 32768 + (22554 + 46802) * 128) >> 16), 0), 255);
+        const int B = min(max(Yv + ((116130 * cb + 32768 - 116130 * 128) >> 16), 0), 255);
+        const uint32_t rgb = (uint32_t)R | ((uint32_t)G << 8) | ((uint32_t)B << 16);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int p = 3 * x + k;
+            const uint32_t byte = (rgb >> (8 * k)) & 255u;
+            if ((p & 3) == 0) ow[p >> 2] = byte; else ow[p >> 2] |= byte << (8 * (p & 3));
+        }
+    }
+    uint8_t *orow = d.sdr + 3 * ((int64_t)yy * W + x0);
+    if (x0 + 8 <= W && ((reinterpret_cast<uintptr_t>(orow) & 3) == 0)) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) reinterpret_cast<uint32_t *>(orow)[k] = ow[k];
+    } else {
+        const int nx = min(8, W - x0);
+        for (int k = 0; k < 3 * nx; ++k) orow[k] = (uint8_t)(ow[k >> 2] >> (8 * (k & 3)));
+    }
+}
+
 template <bool EXTRA>
 __global__ __launch_bounds__(BLK_THREADS) void k_tmo_base(const ImgDesc *__restrict__ D, int n) {
     // A workgroup owns a strip of BLK_WG horizontally adjacent 8x8 blocks of
@@ -516,43 +562,69 @@ __global__ __launch_bounds__(BLK_THREADS) void k_tmo_base(const ImgDesc *__restr
     // Phase 3: lane = row y = r.  IDCT row pass, + 128, clamp, inverse colour
     // transform, crop, store S.
     if (!active) return;
-    const int y = r;
-    const int yy = by * 8 + y;
-    if (yy >= H) return;
-    int smp[3][8];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const uint32_t *rw = &s_X[c][j][y * 4];
-        int o[8];
-        idct1((int)rw[0], (int)rw[1], (int)rw[2], (int)rw[3], 16384 + (128 << 15), o);
-#pragma unroll
-        for (int x = 0; x < 8; ++x) smp[c][x] = min(max(o[x] >> 15, 0), 255);
+    base_store_row(d, s_X, j, r, by, x0);
+}
+
+// ---------------------------------------------------------------------------
+// Base-layer decoder (Sec. II.B: the JPEG decoder of the base layer returns
+// S): from the quantised coefficients int16 [3][H8][W8] (block (bx, by)'s
+// (v, u) at row 8 by + v, column 8 bx + u, as the encoder writes them) and
+// the header's quality: D = Fq Q, the integer IDCT and the inverse colour
+// transform of the encoder's own round trip, crop, store S.  Same workgroup
+// shape as k_tmo_base: lane = column (dequantise + IDCT column pass), LDS
+// transpose, lane = row (base_store_row).  A header whose magic, version,
+// size or quality does not fit sets *status = RDL_ECORRUPT.  Only images with
+// coefficients take part.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLK_THREADS) void k_base_decode(const ImgDesc *__restrict__ D, int n) {
+    __shared__ int32_t s_Q[2][64];
+    __shared__ uint32_t s_X[3][BLK_WG][33];
+    const int i = find_img(D, n, blockIdx.x, 1);
+    const ImgDesc d = desc_at(D, i);
+    if (!d.dct) return;  // uniform
+    const int H = d.H, W = d.W;
+    const rdl_header *h = d.hdr;
+    const int q = h->q;
+    if (!(h->magic == RDL_MAGIC && h->version == RDL_VERSION && h->H == H && h->W == W && q >= 1 && q <= 100)) {
+        if (threadIdx.x == 0 && d.status) atomicExch(d.status, RDL_ECORRUPT);
+        return;
     }
-    uint32_t ow[6];
+    if (threadIdx.x < 128) (&s_Q[0][0])[threadIdx.x] = (int32_t)((&g_qm[q - 1][0][0])[threadIdx.x].x >> 24);
+    const int nbx = (W + 7) >> 3, nby = (H + 7) >> 3;
+    const int nstrip = (nbx + BLK_WG - 1) / BLK_WG;
+    const int wgi = blockIdx.x - d.wg_blk;
+    const int by = wgi / nstrip;
+    const int j = threadIdx.x % BLK_WG, r = threadIdx.x / BLK_WG;
+    const int bx = (wgi - by * nstrip) * BLK_WG + j;
+    const bool active = bx < nbx && by < nby;
+    const int x0 = bx * 8;
+    __syncthreads();
+    if (active) {
+        const int H8 = nby * 8, W8 = nbx * 8;
+        const int u = r, pos2 = (u & 1) * 4 + (u >> 1);
 #pragma unroll
-    for (int x = 0; x < 8; ++x) {
-        // JFIF inverse transform; the chroma offset of 128 is folded into the
-        // rounding constants.
-        const int Yv = smp[0][x], cb = smp[1][x], cr = smp[2][x];
-        const int R = min(max(Yv + ((91881 * cr + 32768 - 91881 * 128) >> 16), 0), 255);
-        const int G = min(max(Yv + ((-22554 * cb - 46802 * cr + 32768 + (22554 + 46802) * 128) >> 16), 0), 255);
-        const int B = min(max(Yv + ((116130 * cb + 32768 - 116130 * 128) >> 16), 0), 255);
-        const uint32_t rgb = (uint32_t)R | ((uint32_t)G << 8) | ((uint32_t)B << 16);
+        for (int c = 0; c < 3; ++c) {
+            int dq[8];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const int p = 3 * x + k;
-            const uint32_t byte = (rgb >> (8 * k)) & 255u;
-            if ((p & 3) == 0) ow[p >> 2] = byte; else ow[p >> 2] |= byte << (8 * (p & 3));
+            for (int v = 0; v < 8; ++v)
+                dq[v] = (int)d.dct[((int64_t)c * H8 + by * 8 + v) * W8 + x0 + u] * s_Q[c ? 1 : 0][v * 8 + u];
+            int t[8];
+            idct1(pack_i16(dq[0], dq[2]), pack_i16(dq[4], dq[6]), pack_i16(dq[1], dq[3]), pack_i16(dq[5], dq[7]), 1024, t);
+            int16_t *slot = reinterpret_cast<int16_t *>(&s_X[c][j][0]);
+#pragma unroll
+            for (int y = 0; y < 8; ++y) slot[y * 8 + pos2] = (int16_t)(t[y] >> 11);
         }
     }
-    uint8_t *orow = d.sdr + 3 * ((int64_t)yy * W + x0);
-    if (x0 + 8 <= W && ((reinterpret_cast<uintptr_t>(orow) & 3) == 0)) {
-#pragma unroll
-        for (int k = 0; k < 6; ++k) reinterpret_cast<uint32_t *>(orow)[k] = ow[k];
-    } else {
-        const int nx = min(8, W - x0);
-        for (int k = 0; k < 3 * nx; ++k) orow[k] = (uint8_t)(ow[k >> 2] >> (8 * (k & 3)));
-    }
+    __syncthreads();
+    if (!active) return;
+    base_store_row(d, s_X, j, r, by, x0);
+}
+
+// Every image's status word (if given) starts at RDL_OK; the decoders only
+// ever replace it with RDL_ECORRUPT.
+__global__ void k_status_init(const ImgDesc *__restrict__ D, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && D[i].status) glb(D[i].status)[0] = RDL_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1932,6 +2004,12 @@ void launch_key_total(const ImgDesc *d, int n, int64_t *out2, hipStream_t s) {
 }
 void launch_resid(const ImgDesc *d, int n, int wgs, hipStream_t s) {
     hipLaunchKernelGGL(k_resid, dim3(wgs), dim3(STRIP_THREADS), 0, s, d, n);
+}
+void launch_base_decode(const ImgDesc *d, int n, int wgs, hipStream_t s) {
+    hipLaunchKernelGGL(k_base_decode, dim3(wgs), dim3(BLK_THREADS), 0, s, d, n);
+}
+void launch_status_init(const ImgDesc *d, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_status_init, dim3((n + 255) / 256), dim3(256), 0, s, d, n);
 }
 void launch_decode(const ImgDesc *d, int n, int wgs, hipStream_t s) {
     hipLaunchKernelGGL(k_decode, dim3(wgs), dim3(STRIP_THREADS), 0, s, d, n);

@@ -47,6 +47,8 @@ _SIGS = {
     "rdl_encode_enh": ([_vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp], _i),
     "rdl_decode_enh": ([_vp, _vp, _vp, _vp, _i, _i, _vp, _vp, _vp], _i),
     "rdl_encode_batch": ([_vp, _vp, _i, _vp], _i),
+    "rdl_decode_batch": ([_vp, _vp, _i, _vp], _i),
+    "rdl_base_decode": ([_vp, _vp, _vp, _i, _i, _vp, _vp, _vp], _i),
     "rdl_resid_hist": ([_vp, _vp, _i, _i, _vp, _vp], _i),
     "rdl_ent_bound": ([_i, _i, _i], C.c_size_t),
     "rdl_ent_encode": ([_vp, _vp, _i, _i, _i, _vp, C.c_size_t, _vp, _vp], _i),
@@ -77,6 +79,11 @@ KERNELS = ("k_keystat", "k_tmo_base", "k_fit_sums", "k_solve", "k_resid")
 class RdlImage(C.Structure):
     _fields_ = [("rgbe", C.c_void_p), ("H", C.c_int32), ("W", C.c_int32), ("q", C.c_int32),
                 ("sdr", C.c_void_p), ("hdr", C.c_void_p), ("resid", C.c_void_p)]
+
+
+class RdlDImage(C.Structure):
+    _fields_ = [("dct", C.c_void_p), ("sdr", C.c_void_p), ("hdr", C.c_void_p), ("resid", C.c_void_p),
+                ("H", C.c_int32), ("W", C.c_int32), ("out_rgbe", C.c_void_p), ("status", C.c_void_p)]
 
 
 _lib = None
@@ -215,6 +222,23 @@ class Codec:
             arr[k] = RdlImage(_ptr(rgbe), int(rgbe.shape[0]), int(rgbe.shape[1]), int(q), _ptr(sdr), _ptr(hdr),
                               _ptr(resid))
         _chk(self._L.rdl_encode_batch(self._h, arr, len(items), _stream(stream)), "rdl_encode_batch")
+
+    def decode_batch(self, items, stream=None):
+        """items: list of (dct or None, sdr, hdr, resid, out_rgbe, status or None) device
+        tensors; with dct, sdr is written from the coefficients first."""
+        arr = (RdlDImage * len(items))()
+        for k, (dct, sdr, hdr, resid, out, status) in enumerate(items):
+            arr[k] = RdlDImage(_ptr(dct), _ptr(sdr), _ptr(hdr), _ptr(resid), int(out.shape[0]), int(out.shape[1]),
+                               _ptr(out), _ptr(status))
+        _chk(self._L.rdl_decode_batch(self._h, arr, len(items), _stream(stream)), "rdl_decode_batch")
+
+    def base_decode(self, dct: torch.Tensor, hdr: torch.Tensor, H: int, W: int, out: torch.Tensor | None = None,
+                    status: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Base layer S (H x W x 3) from its quantised coefficients and the header's quality."""
+        out = out if out is not None else torch.empty((H, W, 3), dtype=torch.uint8, device=dct.device)
+        _chk(self._L.rdl_base_decode(self._h, _ptr(dct), _ptr(hdr), H, W, _ptr(out), _ptr(status), _stream(stream)),
+             "rdl_base_decode")
+        return out
 
     def decode_enh(self, sdr: torch.Tensor, hdr: torch.Tensor, resid: torch.Tensor, H: int, W: int,
                    out: torch.Tensor | None = None, status: torch.Tensor | None = None, stream=None):

@@ -627,3 +627,31 @@ def test_learned_round_trip_and_flags(O):
                 hl = np.bincount((x[..., c][sel].astype(int) - ML[..., c][sel]) + 255, minlength=511)
                 assert r["flag"][c, e] == int(O.hist_cost(hl) < O.hist_cost(hs))
         assert r["flag"][:, plain["present"] == 0].sum() == 0
+
+
+@pytest.mark.parametrize("H,W,q", [(8, 8, 75), (13, 21, 30), (40, 33, 90), (17, 9, 100), (9, 64, 1)])
+def test_base_decode_is_the_second_half_of_the_base_layer(O, H, W, q):
+    """Decoding the coefficients the base layer writes returns its S exactly."""
+    rng = np.random.default_rng(H * W + q)
+    sdr0 = rng.integers(0, 256, (H, W, 3)).astype(np.uint8)
+    S, dct = O.base_layer(sdr0, q, want_dct=True)
+    assert np.array_equal(O.base_decode(dct, H, W, q), S)
+
+
+def test_base_decode_grey_dc_blocks(O):
+    """A grey image whose coefficients are DC-only luma gives flat blocks of
+    128 + D/8 (the orthonormal 2-D DCT's DC gain is 8), within one code."""
+    H, W, q = 16, 24, 50
+    dct = np.zeros((3, H, W), np.int16)
+    levels = [-60, -7, 0, 5, 33, 100]
+    for k in range(6):
+        by, bx = divmod(k, 3)
+        dct[0, 8 * by, 8 * bx] = levels[k]
+    S = O.base_decode(dct, H, W, q)
+    Q = int(O.quant_table(q, False)[0, 0])
+    for k in range(6):
+        by, bx = divmod(k, 3)
+        blk = S[8 * by:8 * by + 8, 8 * bx:8 * bx + 8]
+        want = min(max(128 + levels[k] * Q / 8.0, 0), 255)
+        assert np.all(blk == blk[0, 0, 0]), "a DC-only grey block decodes flat and grey"
+        assert abs(int(blk[0, 0, 0]) - want) <= 1
