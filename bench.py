@@ -14,6 +14,8 @@ Also measured, outside the timed region:
   * the lossless round trip through the GPU decoder, residual bits/pixel;
   * the entropy code of the image's enhancement layer (static rANS): encode
     and decode times, coded bits/pixel against the planes' H0, round trip;
+  * the batched decoder, quantised coefficients -> S -> RGBE, on the image
+    and on the 64-image batch;
   * the batched encoder on 64 uneven images (~275 Mpx, one launch per stage);
   * the learned estimator with per-region SLR fallback: bits/pixel against
     plain SLR on 16 held-out 1920x1080 images, and its throughput;
@@ -201,6 +203,8 @@ def main():
                     help="timed launches of the 256-image batch, plain and learned (0 = skip)")
     ap.add_argument("--entropy-steps", type=int, default=50,
                     help="timed entropy encodes/decodes of the image's enhancement layer (0 = skip)")
+    ap.add_argument("--decode-steps", type=int, default=20,
+                    help="timed batched decodes (coefficients -> S -> RGBE) of the image and the 64-image batch (0 = skip)")
     ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch shapes")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -304,6 +308,29 @@ def main():
             ms_e * 1e3, ms_d * 1e3, entropy["bits_per_pixel_coded"], entropy["bits_per_pixel_h0"]))
         del code, back
 
+    # ---- decoder: quantised coefficients -> S -> RGBE ------------------------
+    decoder = None
+    if args.decode_steps > 0:
+        ks = codec.stage_keystat(d)
+        s_ref, _, dct = codec.stage_tmo_base(d, q, ks, want_dct=True)
+        s_dec = torch.empty_like(sdr)
+        rgbe_dec = torch.empty_like(d)
+        st = torch.zeros(1, dtype=torch.int32, device="cuda")
+        item = [(dct, s_dec, hdr, resid, rgbe_dec, st)]
+        for _ in range(3):
+            codec.decode_batch(item)
+        ms_full = time_calls(lambda: codec.decode_batch(item), args.decode_steps, stream)
+        ms_base = time_calls(lambda: codec.base_decode(dct, hdr, H, W, out=s_dec), args.decode_steps, stream)
+        ms_enh = time_calls(lambda: codec.decode_enh(sdr, hdr, resid, H, W, out=rgbe_dec), args.decode_steps, stream)
+        codec.decode_batch(item)
+        ok = bool(torch.equal(rgbe_dec, d)) and bool(torch.equal(s_dec, sdr)) and int(st.item()) == 0
+        decoder = {"workload": "the 3840x2160 image: base layer from its quantised coefficients, then the enhancement layer",
+                   "ms_per_image": round(ms_full, 5), "Mpixel_s": round(H * W / (ms_full * 1e-3) / 1e6, 1),
+                   "ms_base_layer": round(ms_base, 5), "ms_enhancement_layer": round(ms_enh, 5), "lossless": ok}
+        say("decoder: %.1f us per image (base %.1f us, enhancement %.1f us)" % (ms_full * 1e3, ms_base * 1e3,
+                                                                            ms_enh * 1e3))
+        del dct, s_dec, rgbe_dec
+
     # plain device copy of 1 GiB for scale (reads + writes 2 GiB)
     a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
     b = torch.empty_like(a)
@@ -336,6 +363,22 @@ def main():
                  "pipeline_algorithmic_GBps": round(gbps_b, 1), "pipeline_frac_of_hbm": round(gbps_b / HBM_PEAK_GBPS, 4),
                  "lossless": ok}
         print("bench: batch %.3f ms (%.1f Mpixel/s)" % (ms_b, batch["Mpixel_s"]), file=sys.stderr, flush=True)
+        if args.decode_steps > 0:
+            dec = []
+            for (im, qq, sdr_b, hdr_b, resid_b), s in zip(items, specs):
+                ks = codec.stage_keystat(im)
+                _, _, dct_b = codec.stage_tmo_base(im, qq, ks, want_dct=True)
+                dec.append((dct_b, torch.empty_like(sdr_b), hdr_b, resid_b, torch.empty_like(im),
+                            torch.zeros(1, dtype=torch.int32, device="cuda")))
+            for _ in range(2):
+                codec.decode_batch(dec)
+            ms_db = time_calls(lambda: codec.decode_batch(dec), max(3, args.decode_steps // 4), stream)
+            okd = all(torch.equal(dv[4], im) and torch.equal(dv[1], it[2]) and int(dv[5].item()) == 0
+                      for dv, it, im in zip(dec, items, imgs))
+            batch["decode"] = {"what": "quantised coefficients -> S -> RGBE, one launch per stage for the 64 images",
+                               "ms": round(ms_db, 4), "Mpixel_s": round(npx / (ms_db * 1e-3) / 1e6, 1), "lossless": okd}
+            say("batch decode %.3f ms (%.1f Mpixel/s)" % (ms_db, batch["decode"]["Mpixel_s"]))
+            del dec
         del imgs, items
 
     # ---- learned estimator with per-region SLR fallback ----------------------
@@ -441,6 +484,7 @@ def main():
         "stage_ms": {k: round(v, 5) for k, v in stage_ms.items()},
         "device_copy_GBps": round(copy_gbps, 1),
         "entropy": entropy,
+        "decoder": decoder,
         "batch": batch,
         "learned": learned,
         "large_batch": large,

@@ -641,42 +641,6 @@ __device__ __forceinline__ uint32_t load_px3(const uint8_t *p) {
     return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
 }
 
-// Pixels x .. x+3 of row y of S as R | G << 8 | B << 16 (top byte
-// unspecified); a pixel at x >= W repeats pixel W-1.  `end` bounds the S
-// buffer: the aligned 16-byte read is used only when it stays inside.
-__device__ __forceinline__ void load_quad(const uint8_t *__restrict__ sdr, uintptr_t end, int W, int y, int x,
-                                          uint32_t p[4]) {
-    const uint8_t *a = sdr + 3 * ((int64_t)y * W + x);
-    const uintptr_t al = reinterpret_cast<uintptr_t>(a) & ~(uintptr_t)3;
-    if (x + 4 <= W && al + 16 <= end) {
-        const uint32_t *q = reinterpret_cast<const uint32_t *>(a - (reinterpret_cast<uintptr_t>(a) & 3));
-        const uint32_t sh = (uint32_t)(reinterpret_cast<uintptr_t>(a) & 3);
-        const uint32_t d0 = q[0], d1 = q[1], d2 = q[2], d3 = q[3];
-        const uint32_t e0 = __builtin_amdgcn_alignbyte(d1, d0, sh);
-        const uint32_t e1 = __builtin_amdgcn_alignbyte(d2, d1, sh);
-        const uint32_t e2 = __builtin_amdgcn_alignbyte(d3, d2, sh);
-        p[0] = e0;
-        p[1] = __builtin_amdgcn_alignbyte(e1, e0, 3);
-        p[2] = __builtin_amdgcn_alignbyte(e2, e1, 2);
-        p[3] = e2 >> 8;
-    } else {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) p[j] = load_px3(sdr + 3 * ((int64_t)y * W + min(x + j, W - 1)));
-    }
-}
-
-// RGBE words of pixels x .. x+3 of row y (x >= W repeats W-1).
-__device__ __forceinline__ void load_rgbe4(const uint8_t *__restrict__ rgbe, int W, int y, int x, uint32_t w[4]) {
-    const uint32_t *row = reinterpret_cast<const uint32_t *>(rgbe + (int64_t)y * (4 * (int64_t)W));
-    if (x + 4 <= W && (reinterpret_cast<uintptr_t>(row + x) & 15) == 0) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(row + x);
-        w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
-    } else {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) w[j] = row[min(x + j, W - 1)];
-    }
-}
-
 __device__ __forceinline__ uint32_t dpp_from_left(uint32_t v) {  // lane l gets lane l-1
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xF, 0xF, false);
 }
@@ -688,21 +652,6 @@ struct GfWindow {
     uint32_t lo[3][4], hi[3][4];  // rows y-1, y, y+1 of the lane's pixels
     uint32_t hlo[3], hhi[3];      // the same rows of the lane's halo pixel
 };
-
-__device__ __forceinline__ void gf_load_row(GfWindow &g, int slot, const uint8_t *__restrict__ sdr, uintptr_t end,
-                                            int H, int W, int y, int x, int hx) {
-    const int yy = min(max(y, 0), H - 1);
-    uint32_t p[4];
-    load_quad(sdr, end, W, yy, x, p);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        g.lo[slot][j] = p[j] & 0x00FF00FFu;
-        g.hi[slot][j] = (p[j] >> 8) & 0xFFu;
-    }
-    const uint32_t h = load_px3(sdr + 3 * ((int64_t)yy * W + hx));
-    g.hlo[slot] = h & 0x00FF00FFu;
-    g.hhi[slot] = (h >> 8) & 0xFFu;
-}
 
 __device__ __forceinline__ void gf_roll(GfWindow &g) {
 #pragma unroll
@@ -911,6 +860,48 @@ template <class RowFn>
 __device__ __forceinline__ void strip_walk(const ImgDesc &d, const StripPos &sp, RowFn &&row) {
     strip_walk_x<false>(d, sp, nullptr, [&](int y, const int (&s)[3][4], const uint32_t (&w)[4],
                                             const uint32_t (&)[4]) { row(y, s, w); });
+}
+
+// The same chunked walk with other per-row data: issue(yy, side) loads the
+// lane's data of row yy (issued with the S rows of the chunk), and
+// row(y, s, side) receives it with S* of row y.
+template <class Side, class IssueFn, class RowFn>
+__device__ __forceinline__ void strip_walk_side(const ImgDesc &d, const StripPos &sp, IssueFn &&issue, RowFn &&row) {
+    const int H = d.H, W = d.W;
+    const uint8_t *last = d.sdr + (int64_t)(H - 1) * (3 * (int64_t)W);
+    const uint32_t shl = (uint32_t)(reinterpret_cast<uintptr_t>(last) + sp.xo3) & 3u;
+    const bool fast_last = sp.fx && (uint64_t)sp.xo3 - shl + 16u <= 3ull * (uint64_t)W;
+    auto fast = [&](int yy) { return yy < H - 1 ? sp.fx : fast_last; };
+    GfWindow g;
+    {
+        RowRaw r0, r1;
+        const int y0 = max(sp.ya - 1, 0), y1 = sp.ya;
+        gf_row_issue(r0, d.sdr, W, y0, fast(y0), sp);
+        gf_row_issue(r1, d.sdr, W, y1, fast(y1), sp);
+        gf_row_finish(g, 0, r0);
+        gf_row_finish(g, 1, r1);
+    }
+    for (int y0 = sp.ya; y0 < sp.yb; y0 += WALK_CH) {
+        RowRaw nr[WALK_CH];
+        Side sd[WALK_CH];
+#pragma unroll
+        for (int k = 0; k < WALK_CH; ++k) {
+            const int ys = min(min(y0 + k + 1, sp.yb), H - 1);
+            gf_row_issue(nr[k], d.sdr, W, ys, fast(ys), sp);
+            issue(min(y0 + k, sp.yb - 1), sd[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < WALK_CH; ++k) {
+            const int y = y0 + k;
+            if (y < sp.yb) {  // uniform per wave
+                gf_row_finish(g, 2, nr[k]);
+                int sv[3][4];
+                gf_quad(g, sp.lane, sv);
+                gf_roll(g);
+                row(y, sv, sd[k]);
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1281,36 +1272,71 @@ __global__ __launch_bounds__(STRIP_THREADS) void k_decode(const ImgDesc *__restr
     }
     const StripPos sp = strip_pos(blockIdx.x - d.wg_res, H, W, d.srh_res);
     if (sp.ya >= H) return;
-    const uintptr_t end = reinterpret_cast<uintptr_t>(d.sdr) + 3 * (uintptr_t)H * W;
     const int64_t npx = (int64_t)H * W;
     const int16_t *r = (const int16_t *)d.resid;
     const uint8_t *Ep = d.resid + 6 * npx;
     uint32_t *out = reinterpret_cast<uint32_t *>(d.out_rgbe);
+    // Wide accesses where every row starts on the boundary they need: W a
+    // multiple of 4 (so y W + x is), the layer on 8 bytes and the output on
+    // 16; the lane's four pixels are then inside the image or all past it.
+    const bool wide = (W & 3) == 0 && (reinterpret_cast<uintptr_t>(d.resid) & 7) == 0 &&
+                      (reinterpret_cast<uintptr_t>(d.out_rgbe) & 15) == 0;
+    struct Side {
+        uint32_t e;        // the exponents of the lane's four pixels, one byte each
+        uint32_t r[3][2];  // their residuals per channel, two int16 per word
+    };
     bool bad = false;
-    GfWindow g;
-    gf_load_row(g, 0, d.sdr, end, H, W, sp.ya - 1, sp.x, sp.hx);
-    gf_load_row(g, 1, d.sdr, end, H, W, sp.ya, sp.x, sp.hx);
-    for (int y = sp.ya; y < sp.yb; ++y) {
-        gf_load_row(g, 2, d.sdr, end, H, W, y + 1, sp.x, sp.hx);
-        int s[3][4];
-        gf_quad(g, sp.lane, s);
-        gf_roll(g);
-        if (sp.x >= W) continue;
-        const int64_t o = (int64_t)y * W + sp.x;
-        const int nx = min(4, W - sp.x);
-        for (int j = 0; j < nx; ++j) {
-            const int e = Ep[o + j];
-            uint32_t word = (uint32_t)e << 24;
+    strip_walk_side<Side>(
+        d, sp,
+        [&](int yy, Side &o) {
+            const int64_t off = (int64_t)yy * W + sp.x;
+            if (wide && sp.fx) {
+                o.e = *reinterpret_cast<const uint32_t *>(Ep + off);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const int2 ab = s_ab[c][e];
-                const int m = mstar(ab, s[c][j]) + r[c * npx + o + j];
-                bad |= (m < 0) | (m > 255);
-                word |= (uint32_t)(m & 255) << (8 * c);
+                for (int c = 0; c < 3; ++c) {
+                    const uint2 v = *reinterpret_cast<const uint2 *>(r + c * npx + off);
+                    o.r[c][0] = v.x;
+                    o.r[c][1] = v.y;
+                }
+            } else {
+                o.e = 0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) o.r[c][0] = o.r[c][1] = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int64_t oj = (int64_t)yy * W + min(sp.x + j, W - 1);
+                    o.e |= (uint32_t)Ep[oj] << (8 * j);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        o.r[c][j >> 1] |= (uint32_t)(uint16_t)r[c * npx + oj] << (16 * (j & 1));
+                }
             }
-            out[o + j] = word;
-        }
-    }
+        },
+        [&](int y, const int (&s)[3][4], const Side &o) {
+            if (sp.x >= W) return;
+            uint32_t wd[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int e = (int)((o.e >> (8 * j)) & 255u);
+                uint32_t word = (uint32_t)e << 24;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int rv = (int)(int16_t)(o.r[c][j >> 1] >> (16 * (j & 1)));
+                    const int m = mstar(s_ab[c][e], s[c][j]) + rv;
+                    bad |= ((m < 0) | (m > 255)) && sp.x + j < W;
+                    word |= (uint32_t)(m & 255) << (8 * c);
+                }
+                wd[j] = word;
+            }
+            const int64_t o4 = (int64_t)y * W + sp.x;
+            if (wide && sp.fx) {
+                *reinterpret_cast<uint4 *>(out + o4) = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (sp.x + j < W) out[o4 + j] = wd[j];
+            }
+        });
     if (bad && d.status) atomicExch(d.status, RDL_ECORRUPT);
 }
 // ---------------------------------------------------------------------------
