@@ -599,17 +599,47 @@ __global__ __launch_bounds__(BLK_THREADS) void k_base_decode(const ImgDesc *__re
     const bool active = bx < nbx && by < nby;
     const int x0 = bx * 8;
     __syncthreads();
+    // Lane = row v of its block: the row's eight coefficients (one 16-byte load
+    // per channel where the array is 16-byte aligned: every row then is),
+    // dequantised, go to the column slots at position (v & 1) * 4 + (v >> 1),
+    // so column u reads back the pairs (0,2), (4,6), (1,3), (5,7).
+    const int H8 = nby * 8, W8 = nbx * 8;
+    const bool wide = (reinterpret_cast<uintptr_t>(d.dct) & 15) == 0;
+    const int pos = (r & 1) * 4 + (r >> 1);
     if (active) {
-        const int H8 = nby * 8, W8 = nbx * 8;
-        const int u = r, pos2 = (u & 1) * 4 + (u >> 1);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            int dq[8];
+            const int16_t *row = d.dct + ((int64_t)c * H8 + by * 8 + r) * W8 + x0;
+            int cf[8];
+            if (wide) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(row);
+                const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-            for (int v = 0; v < 8; ++v)
-                dq[v] = (int)d.dct[((int64_t)c * H8 + by * 8 + v) * W8 + x0 + u] * s_Q[c ? 1 : 0][v * 8 + u];
+                for (int u = 0; u < 8; ++u) cf[u] = (int)(int16_t)(w4[u >> 1] >> (16 * (u & 1)));
+            } else {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) cf[u] = (int)row[u];
+            }
+            int16_t *slot = reinterpret_cast<int16_t *>(&s_X[c][j][0]);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) slot[u * 8 + pos] = (int16_t)(cf[u] * s_Q[c ? 1 : 0][r * 8 + u]);
+        }
+    }
+    __syncthreads();
+    // Lane = column u: IDCT column pass; outputs back to the slot as the
+    // encoder's column pass leaves them (row y at (u & 1) * 4 + (u >> 1)).
+    const int u = r, pos2 = (u & 1) * 4 + (u >> 1);
+    int col[3][4];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) col[c][k] = (int)s_X[c][j][u * 4 + k];
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
             int t[8];
-            idct1(pack_i16(dq[0], dq[2]), pack_i16(dq[4], dq[6]), pack_i16(dq[1], dq[3]), pack_i16(dq[5], dq[7]), 1024, t);
+            idct1(col[c][0], col[c][1], col[c][2], col[c][3], 1024, t);
             int16_t *slot = reinterpret_cast<int16_t *>(&s_X[c][j][0]);
 #pragma unroll
             for (int y = 0; y < 8; ++y) slot[y * 8 + pos2] = (int16_t)(t[y] >> 11);
