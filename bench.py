@@ -16,6 +16,8 @@ Also measured, outside the timed region:
     and decode times, coded bits/pixel against the planes' H0, round trip;
   * the batched decoder, quantised coefficients -> S -> RGBE, on the image
     and on the 64-image batch;
+  * the ablations (SLR without the Gaussian filter, one line per channel, no
+    estimator) and a quality sweep: residual bits/pixel on the image;
   * the batched encoder on 64 uneven images (~275 Mpx, one launch per stage);
   * the learned estimator with per-region SLR fallback: bits/pixel against
     plain SLR on 16 held-out 1920x1080 images, and its throughput;
@@ -205,6 +207,7 @@ def main():
                     help="timed entropy encodes/decodes of the image's enhancement layer (0 = skip)")
     ap.add_argument("--decode-steps", type=int, default=20,
                     help="timed batched decodes (coefficients -> S -> RGBE) of the image and the 64-image batch (0 = skip)")
+    ap.add_argument("--ablation", type=int, default=1, help="bits/pixel of the ablations and the quality sweep (0 = skip)")
     ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch shapes")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -307,6 +310,38 @@ def main():
         say("entropy code: %.1f us encode, %.1f us decode, %.4f bits/px (H0 %.4f)" % (
             ms_e * 1e3, ms_d * 1e3, entropy["bits_per_pixel_coded"], entropy["bits_per_pixel_h0"]))
         del code, back
+
+    # ---- ablations (the comparisons of Table I) and a quality sweep (Fig. 4) --
+    ablation = None
+    if args.ablation:
+        outa = codec.alloc_outputs(H, W)
+        rows = {}
+        for name, est, gf in (("slr_gf (proposed)", 0, True), ("slr_no_gf", 0, False), ("global_line_gf", 2, True),
+                              ("no_slrme (M* = S, no GF)", 3, False)):
+            codec.set_estimator(est)
+            codec.set_gf(gf)
+            codec.encode_enh(d, q, out=outa)
+            ms_m = time_calls(lambda: codec.encode_enh(d, q, out=outa), 5, stream)
+            ok_m = bool(torch.equal(codec.decode_enh(*outa, H, W), d))
+            rows[name] = {"bits_per_pixel": round(resid_bits(codec, outa[2], H, W), 4),
+                          "bits_per_pixel_given_E": round(cond_bits(outa[2], H, W), 4), "ms": round(ms_m, 4),
+                          "lossless": ok_m}
+        sweep = {}
+        for qq in (10, 30, 50, 70, 90, 100):
+            row = {}
+            for name, est, gf in (("slr_gf", 0, True), ("no_slrme", 3, False)):
+                codec.set_estimator(est)
+                codec.set_gf(gf)
+                codec.encode_enh(d, qq, out=outa)
+                row[name] = round(resid_bits(codec, outa[2], H, W), 4)
+            sweep[str(qq)] = row
+        codec.set_estimator(0)
+        codec.set_gf(True)
+        ablation = {"workload": "the 3840x2160 image, residual bits/pixel (sum of the three planes' H0; exponent plane "
+                                "%.4f bits/pixel in every mode)" % e_bits, "q": q, "modes": rows,
+                    "quality_sweep_bits_per_pixel": sweep}
+        say("ablation: %s" % {k: v["bits_per_pixel"] for k, v in rows.items()})
+        del outa
 
     # ---- decoder: quantised coefficients -> S -> RGBE ------------------------
     decoder = None
@@ -485,6 +520,7 @@ def main():
         "device_copy_GBps": round(copy_gbps, 1),
         "entropy": entropy,
         "decoder": decoder,
+        "ablation": ablation,
         "batch": batch,
         "learned": learned,
         "large_batch": large,

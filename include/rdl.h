@@ -60,7 +60,10 @@ typedef struct rdl_header {
     float sigma;         /* 0.18 * 2^(f_key / 2^16)                    */
     int64_t lambda_sum;  /* Q16 sum of log2 luminance over lit pixels  */
     int64_t n_lit;       /* number of pixels with E != 0               */
-    int32_t estimator;   /* 0: SLR in every region; 1: flag[][] chooses */
+    int32_t estimator;   /* bits 0-3: 0 SLR per region, 1 flag[][]      */
+                         /* chooses SLR or learned, 2 one SLR line per  */
+                         /* channel (ablation), 3 M* = S (ablation: no  */
+                         /* estimator); bit 4: Gaussian filter off      */
     int32_t n_regions;   /* number of exponent values present          */
     uint64_t model_hash; /* learned estimator in use (0 if none)       */
     int32_t a_q[3][256]; /* slope per (channel, E), Q22                */
@@ -203,6 +206,20 @@ int rdl_set_launch_mode(rdl_ctx *ctx, int mode);
 #define RDL_MODEL_BYTES 7512
 int rdl_set_model(rdl_ctx *ctx, const void *blob, size_t nbytes);
 int rdl_set_estimator(rdl_ctx *ctx, int mode);
+
+/* ---- Ablations of the paper's method (Sec. III, the comparisons of Table I
+ * and Fig. 4), as encoder settings of a context ----
+ * rdl_set_estimator(ctx, 2): one least-squares line per channel for the whole
+ * image (every exponent's sums pooled, Eq. 9-10 over all pixels; written to
+ * every present exponent's a_q, b_q).  rdl_set_estimator(ctx, 3): no
+ * estimator, M* = S (a_q = 2^22, b_q = 0 for every present exponent), the
+ * plain residual of a layer without SLRME.  rdl_set_gf(ctx, 0): S* = S, no
+ * Gaussian-filter restoration (Sec. III.B); 1 restores it.  The header's
+ * estimator field records both (bit 4 = filter off), so rdl_decode_enh and
+ * rdl_decode_batch decode every mode.  The learned estimator needs the filter:
+ * encoding with mode 1 and the filter off gives RDL_EUNSUPPORTED.
+ * RDL_EINVAL for another mode or switch value. */
+int rdl_set_gf(rdl_ctx *ctx, int on);
 
 /* ---- Training of the learned estimator (FP32, off the encoder's path) ----
  * Float model: x = (S - 128)/128 over the 3x3 x 3 neighbourhood, h1 =

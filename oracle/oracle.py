@@ -61,6 +61,10 @@ def lib():
         L.oracle_encode_enh.restype = C.c_int
         L.oracle_decode_enh.argtypes = [vp, vp, vp, vp, C.c_int, C.c_int, vp]
         L.oracle_decode_enh.restype = C.c_int
+        L.oracle_encode_mode.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, vp]
+        L.oracle_encode_mode.restype = C.c_int
+        L.oracle_decode_mode.argtypes = [vp, vp, vp, vp, C.c_int, C.c_int, C.c_int, vp]
+        L.oracle_decode_mode.restype = C.c_int
         L.oracle_resid_hist.argtypes = [vp, i64, vp]
         L.oracle_mlp_estimate.argtypes = [vp, vp, vp, C.c_int, C.c_int, i32, vp, vp]
         L.oracle_mlp_estimate.restype = C.c_int
@@ -358,3 +362,32 @@ def ent_decode(stream: bytes, H: int, W: int) -> np.ndarray:
     if rc:
         raise ValueError("oracle_ent_decode failed with %d" % rc)
     return out
+
+
+# ---------------------------------------------------------------- ablations
+def encode_mode(rgbe: np.ndarray, q: int, est: int, gf: bool) -> dict:
+    """Encoder with estimator est (0 SLR per region, 2 one line per channel,
+    3 M* = S) and the Gaussian filter on or off."""
+    rgbe = np.ascontiguousarray(rgbe, np.uint8)
+    H, W = rgbe.shape[:2]
+    sdr = np.zeros((H, W, 3), np.uint8)
+    a_q = np.zeros((3, 256), np.int32)
+    b_q = np.zeros((3, 256), np.int32)
+    present = np.zeros(256, np.uint8)
+    resid = np.zeros(7 * H * W, np.uint8)
+    rc = lib().oracle_encode_mode(_p(rgbe), H, W, q, est, int(bool(gf)), _p(sdr), _p(a_q), _p(b_q), _p(present),
+                                  _p(resid))
+    if rc:
+        raise ValueError("oracle_encode_mode failed with %d" % rc)
+    return {"sdr": sdr, "a_q": a_q, "b_q": b_q, "present": present, "resid": resid}
+
+
+def decode_mode(sdr, a_q, b_q, resid, H: int, W: int, gf: bool) -> np.ndarray:
+    out = np.zeros((H, W, 4), np.uint8)
+    rc = lib().oracle_decode_mode(_p(np.ascontiguousarray(sdr, np.uint8)), _p(np.ascontiguousarray(a_q, np.int32)),
+                                  _p(np.ascontiguousarray(b_q, np.int32)), _p(np.ascontiguousarray(resid)), H, W,
+                                  int(bool(gf)), _p(out))
+    if rc:
+        raise ValueError("oracle_decode_mode failed with %d" % rc)
+    return out
+

@@ -538,16 +538,81 @@ int oracle_encode_enh(const uint8_t *rgbe, int H, int W, int q, uint8_t *out_sdr
     return 0;
 }
 
+/* Ablations of the method (the comparisons of Table I and Fig. 4): the
+ * encoder with est = 0 (SLR per exponent region, as oracle_encode_enh), 2
+ * (one least-squares line per channel for the whole image: every region's
+ * sums pooled and solved as one region, the line written to every present
+ * exponent) or 3 (no estimator: M* = S, i.e. slope 1 and intercept 0), and
+ * gf = 1 (S* = GF(S), Sec. III.B) or 0 (S* = S). */
+int oracle_encode_mode(const uint8_t *rgbe, int H, int W, int q, int est, int gf, uint8_t *out_sdr, int32_t *a_q,
+                       int32_t *b_q, uint8_t *present, void *out_resid)
+{
+    if (!rgbe || !out_sdr || !a_q || !b_q || !present || !out_resid) return -1;
+    if (H < 1 || W < 1 || q < 1 || q > 100 || (est != 0 && est != 2 && est != 3)) return -1;
+    init_tables();
+    int64_t npx = (int64_t)H * W;
+    int64_t L, N;
+    oracle_keystat(rgbe, npx, &L, &N);
+    int32_t k, f;
+    float sig;
+    oracle_key_params(L, N, &k, &f, &sig);
+    uint8_t *s0 = (uint8_t *)malloc(3 * npx);
+    uint8_t *ss = (uint8_t *)malloc(3 * npx);
+    int64_t *sm = (int64_t *)malloc(sizeof(int64_t) * 256 * 13);
+    if (!s0 || !ss || !sm) return -4;
+    oracle_tmo(rgbe, H, W, k, sig, N, s0);
+    oracle_base_layer(s0, H, W, q, out_sdr, NULL);
+    if (gf)
+        oracle_gf(out_sdr, H, W, ss);
+    else
+        memcpy(ss, out_sdr, 3 * npx);
+    oracle_sums(ss, rgbe, npx, sm);
+    if (est == 2) {
+        int64_t pool[13] = {0};
+        for (int e = 0; e < 256; e++)
+            for (int j = 0; j < 13; j++) pool[j] += sm[e * 13 + j];
+        for (int e = 0; e < 256; e++)
+            if (sm[e * 13] > 0)
+                for (int j = 0; j < 13; j++) sm[e * 13 + j] = pool[j];
+    }
+    oracle_solve(sm, a_q, b_q, present);
+    if (est == 3)
+        for (int c = 0; c < 3; c++)
+            for (int e = 0; e < 256; e++) {
+                a_q[c * 256 + e] = present[e] ? 1 << 22 : 0;
+                b_q[c * 256 + e] = 0;
+            }
+    oracle_resid(ss, rgbe, npx, a_q, b_q, out_resid);
+    free(s0);
+    free(ss);
+    free(sm);
+    return 0;
+}
+
 /* C14: decode.  The decoder rebuilds S* from S, reads (a_E, b_E) as sent
  * (never recomputes them) and adds the residual: M = M* + r. */
+int oracle_decode_mode(const uint8_t *sdr, const int32_t *a_q, const int32_t *b_q, const void *resid,
+                       int H, int W, int gf, uint8_t *out_rgbe);
+
 int oracle_decode_enh(const uint8_t *sdr, const int32_t *a_q, const int32_t *b_q, const void *resid,
                       int H, int W, uint8_t *out_rgbe)
+{
+    return oracle_decode_mode(sdr, a_q, b_q, resid, H, W, 1, out_rgbe);
+}
+
+/* Decoder with the Gaussian filter on (gf = 1, as the method has it) or off
+ * (S* = S, the ablation). */
+int oracle_decode_mode(const uint8_t *sdr, const int32_t *a_q, const int32_t *b_q, const void *resid,
+                       int H, int W, int gf, uint8_t *out_rgbe)
 {
     if (!sdr || !a_q || !b_q || !resid || !out_rgbe || H < 1 || W < 1) return -1;
     int64_t npx = (int64_t)H * W;
     uint8_t *ss = (uint8_t *)malloc(3 * npx);
     if (!ss) return -4;
-    oracle_gf(sdr, H, W, ss);
+    if (gf)
+        oracle_gf(sdr, H, W, ss);
+    else
+        memcpy(ss, sdr, 3 * npx);
     const int16_t *r = (const int16_t *)resid;
     const uint8_t *Ep = (const uint8_t *)resid + 6 * npx;
     int bad = 0;

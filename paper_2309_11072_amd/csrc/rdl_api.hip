@@ -43,7 +43,8 @@ struct rdl_ctx {
     // learned estimator
     uint8_t *d_model = nullptr;
     uint64_t model_hash = 0;
-    int estimator = 0;
+    int estimator = 0;  // 0 SLR per region, 1 learned, 2 one line per channel, 3 M* = S
+    bool gf = true;     // Gaussian-filter restoration of S before the estimate
     // entropy coder workspace (EntWs, then group word counts and words)
     uint8_t *d_ent = nullptr;
     size_t ent_cap = 0;
@@ -245,17 +246,17 @@ int check_launch(const char *what) {
 
 // Enqueue the full encoder for the images of d (device table) on s.  The
 // scratch accumulators are zero on entry and k_solve leaves them zero.
-void enqueue_encode(const ImgDesc *d, int n, const Grid &g, bool learned, hipStream_t s) {
+void enqueue_encode(const ImgDesc *d, int n, const Grid &g, bool learned, hipStream_t s, bool gf = true) {
     launch_keystat(d, n, g.px, s);
     launch_tmo_base(d, n, g.blk, false, s);
-    launch_fit_sums(d, n, g.fit, g.fit_bins, g.fit_waves, s);
+    launch_fit_sums(d, n, g.fit, g.fit_bins, g.fit_waves, s, gf);
     launch_solve(d, n, s);
     if (learned) {
         launch_learn(d, n, g.learn, s);
         launch_lhist(d, n, g.lhist, s);
         launch_select(d, n, s);
     }
-    launch_resid(d, n, g.res, s);
+    launch_resid(d, n, g.res, s, gf);
 }
 
 ImgDesc blank() {
@@ -361,7 +362,9 @@ void rdl_destroy(rdl_ctx *c) {
 int rdl_header_validate(const rdl_header *h, int H, int W) {
     if (!h) return RDL_EINVAL;
     if (h->magic != RDL_MAGIC || h->version != RDL_VERSION || h->H != H || h->W != W) return RDL_ECORRUPT;
-    if (h->q < 1 || h->q > 100 || h->estimator < 0 || h->estimator > 1) return RDL_ECORRUPT;
+    const int est = h->estimator & 15;
+    if (h->q < 1 || h->q > 100 || (h->estimator & ~31) || est > 3 || (est == 1 && (h->estimator & 16)))
+        return RDL_ECORRUPT;
     const int64_t amax = (int64_t)255 << 22;
     for (int c = 0; c < 3; ++c)
         for (int e = 0; e < 256; ++e) {
@@ -396,7 +399,8 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
             return RDL_EINVAL;
     }
     const bool learned = c->estimator == 1;
-    if (learned && !c->d_model) return RDL_EUNSUPPORTED;
+    if (learned && (!c->d_model || !c->gf)) return RDL_EUNSUPPORTED;
+    const int32_t mode = (c->estimator == 2 ? F_EST_GLOBAL : c->estimator == 3 ? F_EST_IDENT : 0) | (c->gf ? 0 : F_NOGF);
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
     std::vector<ImgDesc> v(n, blank());
@@ -409,7 +413,7 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
         d.H = imgs[k].H;
         d.W = imgs[k].W;
         d.q = imgs[k].q;
-        d.flags = F_CLEAN_KS;
+        d.flags = F_CLEAN_KS | mode;
         if (learned) {
             d.model = c->d_model;
             d.model_hash = c->model_hash;
@@ -440,7 +444,7 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
         p = &c->plans.back();
     }
     if (c->launch_mode == RDL_LAUNCH_DIRECT) {
-        enqueue_encode(p->d_desc, n, gr, learned, s);
+        enqueue_encode(p->d_desc, n, gr, learned, s, c->gf);
         return check_launch("encoder kernels");
     }
     if (!p->exec) {
@@ -449,7 +453,7 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
         hipGraph_t graph;
         hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (err == hipSuccess) {
-            enqueue_encode(p->d_desc, n, gr, learned, cs);
+            enqueue_encode(p->d_desc, n, gr, learned, cs, c->gf);
             err = hipStreamEndCapture(cs, &graph);
         }
         if (err == hipSuccess) {
@@ -963,9 +967,15 @@ int rdl_set_model(rdl_ctx *c, const void *blob, size_t nbytes) {
 }
 
 int rdl_set_estimator(rdl_ctx *c, int mode) {
-    if (!c || mode < 0 || mode > 1) return RDL_EINVAL;
+    if (!c || mode < 0 || mode > 3) return RDL_EINVAL;
     if (mode == 1 && !c->d_model) return RDL_EUNSUPPORTED;
     c->estimator = mode;
+    return RDL_OK;
+}
+
+int rdl_set_gf(rdl_ctx *c, int on) {
+    if (!c || (on != 0 && on != 1)) return RDL_EINVAL;
+    c->gf = on != 0;
     return RDL_OK;
 }
 

@@ -74,7 +74,10 @@ struct ImgDesc {
 // (zeroed at allocation; k_solve and k_key_total zero what they consume).
 // F_ZERO_* ask k_zero to clear a caller's buffer; F_CLEAN_KS lets the last
 // consumer zero the key-statistic stripes (set only when they are scratch).
-enum : int32_t { F_ZERO_KS = 1, F_ZERO_SUMS = 2, F_ZERO_HIST = 4, F_CLEAN_KS = 8 };
+// F_EST_GLOBAL / F_EST_IDENT / F_NOGF select the ablation estimators of the
+// encoder (one line per channel for the whole image; M* = S; S* = S).
+enum : int32_t { F_ZERO_KS = 1, F_ZERO_SUMS = 2, F_ZERO_HIST = 4, F_CLEAN_KS = 8, F_EST_GLOBAL = 16, F_EST_IDENT = 32,
+                 F_NOGF = 64 };
 
 inline int wgs_px(int H, int W) { return (int)(((int64_t)H * W + KS_PX_PER_WG - 1) / KS_PX_PER_WG); }
 inline int wgs_blk(int H, int W) { return ((H + 7) / 8) * (((W + 7) / 8 + BLK_WG - 1) / BLK_WG); }
@@ -95,10 +98,10 @@ void launch_zero(const ImgDesc *d, int n, hipStream_t s);
 void launch_check_recip(uint32_t lo, uint32_t count, unsigned long long *bad, hipStream_t s);
 void launch_keystat(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_tmo_base(const ImgDesc *d, int n, int wgs, bool extra, hipStream_t s);
-void launch_fit_sums(const ImgDesc *d, int n, int wgs, int bins, int waves, hipStream_t s);
+void launch_fit_sums(const ImgDesc *d, int n, int wgs, int bins, int waves, hipStream_t s, bool gf = true);
 void launch_solve(const ImgDesc *d, int n, hipStream_t s);
 void launch_key_total(const ImgDesc *d, int n, int64_t *out2, hipStream_t s);
-void launch_resid(const ImgDesc *d, int n, int wgs, hipStream_t s);
+void launch_resid(const ImgDesc *d, int n, int wgs, hipStream_t s, bool gf = true);
 void launch_decode(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_base_decode(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_status_init(const ImgDesc *d, int n, hipStream_t s);

@@ -730,6 +730,17 @@ __device__ __forceinline__ void gf_quad(const GfWindow &g, int lane, int s[3][4]
     }
 }
 
+// The lane's four pixels of the middle row unfiltered (S* = S when the
+// Gaussian filter is off).
+__device__ __forceinline__ void gf_centre(const GfWindow &g, int s[3][4]) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        s[0][j] = (int)(g.lo[1][j] & 255u);
+        s[2][j] = (int)((g.lo[1][j] >> 16) & 255u);
+        s[1][j] = (int)(g.hi[1][j] & 255u);
+    }
+}
+
 // The strip of a workgroup and the rows of its wave.
 struct StripPos {
     int lane, x, hx, ya, yb;
@@ -841,7 +852,7 @@ __device__ __forceinline__ void gf_row_finish(GfWindow &g, int slot, const RowRa
 // words of a second 4-byte-per-pixel buffer xw (loaded like the RGBE words).
 // The whole wave must call it (DPP); ya < yb is uniform per wave.
 constexpr int WALK_CH = 4;
-template <bool XW, class RowFn>
+template <bool XW, bool GF = true, class RowFn>
 __device__ __forceinline__ void strip_walk_x(const ImgDesc &d, const StripPos &sp, const uint8_t *__restrict__ xw,
                                              RowFn &&row) {
     const int H = d.H, W = d.W;
@@ -878,7 +889,8 @@ __device__ __forceinline__ void strip_walk_x(const ImgDesc &d, const StripPos &s
             if (y < sp.yb) {  // uniform per wave
                 gf_row_finish(g, 2, nr[k]);
                 int sv[3][4];
-                gf_quad(g, sp.lane, sv);
+                if (GF) gf_quad(g, sp.lane, sv);
+                else gf_centre(g, sv);
                 gf_roll(g);
                 row(y, sv, w[k], x[k]);
             }
@@ -886,16 +898,16 @@ __device__ __forceinline__ void strip_walk_x(const ImgDesc &d, const StripPos &s
     }
 }
 
-template <class RowFn>
+template <bool GF = true, class RowFn>
 __device__ __forceinline__ void strip_walk(const ImgDesc &d, const StripPos &sp, RowFn &&row) {
-    strip_walk_x<false>(d, sp, nullptr, [&](int y, const int (&s)[3][4], const uint32_t (&w)[4],
-                                            const uint32_t (&)[4]) { row(y, s, w); });
+    strip_walk_x<false, GF>(d, sp, nullptr, [&](int y, const int (&s)[3][4], const uint32_t (&w)[4],
+                                                const uint32_t (&)[4]) { row(y, s, w); });
 }
 
 // The same chunked walk with other per-row data: issue(yy, side) loads the
 // lane's data of row yy (issued with the S rows of the chunk), and
 // row(y, s, side) receives it with S* of row y.
-template <class Side, class IssueFn, class RowFn>
+template <class Side, bool GF = true, class IssueFn, class RowFn>
 __device__ __forceinline__ void strip_walk_side(const ImgDesc &d, const StripPos &sp, IssueFn &&issue, RowFn &&row) {
     const int H = d.H, W = d.W;
     const uint8_t *last = d.sdr + (int64_t)(H - 1) * (3 * (int64_t)W);
@@ -926,7 +938,8 @@ __device__ __forceinline__ void strip_walk_side(const ImgDesc &d, const StripPos
             if (y < sp.yb) {  // uniform per wave
                 gf_row_finish(g, 2, nr[k]);
                 int sv[3][4];
-                gf_quad(g, sp.lane, sv);
+                if (GF) gf_quad(g, sp.lane, sv);
+                else gf_centre(g, sv);
                 gf_roll(g);
                 row(y, sv, sd[k]);
             }
@@ -961,7 +974,7 @@ __device__ __forceinline__ void flush_run(uint32_t *bins, int e, uint32_t acc[NS
     for (int k = 0; k < NSUM; ++k) acc[k] = 0;
 }
 
-template <int R>
+template <int R, bool GF = true>
 __global__ __launch_bounds__(1024) void k_fit_sums(const ImgDesc *__restrict__ D, int n) {
     __shared__ __align__(8) uint32_t bins[R * BIN_WORDS];
     const int i = find_img(D, n, blockIdx.x, 3);
@@ -977,7 +990,7 @@ __global__ __launch_bounds__(1024) void k_fit_sums(const ImgDesc *__restrict__ D
         uint32_t acc[NSUM];
 #pragma unroll
         for (int k = 0; k < NSUM; ++k) acc[k] = 0;
-        strip_walk(d, sp, [&](int, const int (&s)[3][4], const uint32_t (&w)[4]) {
+        strip_walk<GF>(d, sp, [&](int, const int (&s)[3][4], const uint32_t (&w)[4]) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 if (sp.x + j < W) {
@@ -1112,10 +1125,22 @@ __global__ __launch_bounds__(1024) void k_solve(const ImgDesc *__restrict__ D, i
         h->sigma = sigma;
         h->lambda_sum = L;
         h->n_lit = N;
-        h->estimator = 0;
+        h->estimator = ((d.flags & F_EST_GLOBAL) ? 2 : (d.flags & F_EST_IDENT) ? 3 : 0) | ((d.flags & F_NOGF) ? 16 : 0);
         h->model_hash = 0;
     }
     __syncthreads();
+    // One line per channel for the whole image: every exponent's sums pooled
+    // (value k summed over exponents by thread k), then solved like a region.
+    __shared__ int64_t s_g[NSUM];
+    const bool global = (d.flags & F_EST_GLOBAL) != 0;  // uniform
+    if (global) {
+        if (t < NSUM) {
+            int64_t acc = 0;
+            for (int e2 = 0; e2 < 256; ++e2) acc += s_b[e2][t];
+            s_g[t] = acc;
+        }
+        __syncthreads();
+    }
     // The totals, [256][13] as the stage entry point documents them, written
     // from LDS in order.
     for (int k = t; k < 256 * NSUM; k += 1024) d.sums[k] = (&s_b[0][0])[k];
@@ -1123,10 +1148,13 @@ __global__ __launch_bounds__(1024) void k_solve(const ImgDesc *__restrict__ D, i
         // One lane per (channel, exponent): the least-squares line in exact
         // 128-bit integers with fixed-point rounding.
         const int c = t >> 8, e = t & 255;
-        const i128 nn = s_b[e][0];
+        const int64_t *sb = global ? s_g : s_b[e];
+        const i128 nn = sb[0];
         int32_t aq = 0, bq = 0;
-        if (nn > 0) {
-            const i128 Ss = s_b[e][1 + 4 * c], Sm = s_b[e][2 + 4 * c], Sss = s_b[e][3 + 4 * c], Ssm = s_b[e][4 + 4 * c];
+        if (s_b[e][0] > 0 && (d.flags & F_EST_IDENT)) {
+            aq = 1 << 22;  // M* = S: slope 1, intercept 0
+        } else if (s_b[e][0] > 0) {
+            const i128 Ss = sb[1 + 4 * c], Sm = sb[2 + 4 * c], Sss = sb[3 + 4 * c], Ssm = sb[4 + 4 * c];
             const i128 num = nn * Ssm - Ss * Sm;
             const i128 den = nn * Sss - Ss * Ss;
             const i128 a = den == 0 ? (i128)0 : rhu128(num * ((i128)1 << 22), den);
@@ -1204,6 +1232,7 @@ __device__ __forceinline__ int mstar(int2 k, int s) {
     return min(max((v + u) >> 14, 0), 255);
 }
 
+template <bool GF = true>
 __global__ __launch_bounds__(STRIP_THREADS) void k_resid(const ImgDesc *__restrict__ D, int n) {
     __shared__ int2 s_ab[3][256];
     __shared__ uint8_t s_fl[3][256];
@@ -1264,10 +1293,10 @@ __global__ __launch_bounds__(STRIP_THREADS) void k_resid(const ImgDesc *__restri
         }
     };
     if (learned)
-        strip_walk_x<true>(d, sp, d.ml, [&](int y, const int (&s)[3][4], const uint32_t (&w)[4],
-                                            const uint32_t (&x)[4]) { emit(y, s, w, x); });
+        strip_walk_x<true, GF>(d, sp, d.ml, [&](int y, const int (&s)[3][4], const uint32_t (&w)[4],
+                                                const uint32_t (&x)[4]) { emit(y, s, w, x); });
     else
-        strip_walk(d, sp, [&](int y, const int (&s)[3][4], const uint32_t (&w)[4]) { emit(y, s, w, nullptr); });
+        strip_walk<GF>(d, sp, [&](int y, const int (&s)[3][4], const uint32_t (&w)[4]) { emit(y, s, w, nullptr); });
 }
 
 // ---------------------------------------------------------------------------
@@ -1280,12 +1309,17 @@ __global__ __launch_bounds__(STRIP_THREADS) void k_decode(const ImgDesc *__restr
     const ImgDesc d = desc_at(D, i);
     const int H = d.H, W = d.W;
     const rdl_header *h = d.hdr;
-    const bool ok = h->magic == RDL_MAGIC && h->version == RDL_VERSION && h->H == H && h->W == W;
-    if (!ok || (h->estimator != 0 && !d.model)) {
+    // estimator: bits 0-3 the estimator (0 SLR per region, 1 learned, 2 one
+    // line per channel, 3 M* = S), bit 4 the Gaussian filter off.
+    const int est = h->estimator & 15;
+    const bool gf = (h->estimator & 16) == 0;
+    const bool ok = h->magic == RDL_MAGIC && h->version == RDL_VERSION && h->H == H && h->W == W &&
+                    (h->estimator & ~31) == 0 && est <= 3 && (est != 1 || (gf && d.model));
+    if (!ok) {
         if (threadIdx.x == 0 && d.status) atomicExch(d.status, RDL_ECORRUPT);
         return;
     }
-    if (h->estimator != 0) return;  // decoded by k_decode_learned
+    if (est == 1) return;  // decoded by k_decode_learned
     __shared__ int s_bad;
     if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
@@ -1316,57 +1350,59 @@ __global__ __launch_bounds__(STRIP_THREADS) void k_decode(const ImgDesc *__restr
         uint32_t r[3][2];  // their residuals per channel, two int16 per word
     };
     bool bad = false;
-    strip_walk_side<Side>(
-        d, sp,
-        [&](int yy, Side &o) {
-            const int64_t off = (int64_t)yy * W + sp.x;
-            if (wide && sp.fx) {
-                o.e = *reinterpret_cast<const uint32_t *>(Ep + off);
+    const auto issue = [&](int yy, Side &o) {
+        const int64_t off = (int64_t)yy * W + sp.x;
+        if (wide && sp.fx) {
+            o.e = *reinterpret_cast<const uint32_t *>(Ep + off);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const uint2 v = *reinterpret_cast<const uint2 *>(r + c * npx + off);
-                    o.r[c][0] = v.x;
-                    o.r[c][1] = v.y;
-                }
-            } else {
-                o.e = 0;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) o.r[c][0] = o.r[c][1] = 0;
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int64_t oj = (int64_t)yy * W + min(sp.x + j, W - 1);
-                    o.e |= (uint32_t)Ep[oj] << (8 * j);
-#pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        o.r[c][j >> 1] |= (uint32_t)(uint16_t)r[c * npx + oj] << (16 * (j & 1));
-                }
+            for (int c = 0; c < 3; ++c) {
+                const uint2 v = *reinterpret_cast<const uint2 *>(r + c * npx + off);
+                o.r[c][0] = v.x;
+                o.r[c][1] = v.y;
             }
-        },
-        [&](int y, const int (&s)[3][4], const Side &o) {
-            if (sp.x >= W) return;
-            uint32_t wd[4];
+        } else {
+            o.e = 0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) o.r[c][0] = o.r[c][1] = 0;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int e = (int)((o.e >> (8 * j)) & 255u);
-                uint32_t word = (uint32_t)e << 24;
+                const int64_t oj = (int64_t)yy * W + min(sp.x + j, W - 1);
+                o.e |= (uint32_t)Ep[oj] << (8 * j);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const int rv = (int)(int16_t)(o.r[c][j >> 1] >> (16 * (j & 1)));
-                    const int m = mstar(s_ab[c][e], s[c][j]) + rv;
-                    bad |= ((m < 0) | (m > 255)) && sp.x + j < W;
-                    word |= (uint32_t)(m & 255) << (8 * c);
-                }
-                wd[j] = word;
+                for (int c = 0; c < 3; ++c)
+                    o.r[c][j >> 1] |= (uint32_t)(uint16_t)r[c * npx + oj] << (16 * (j & 1));
             }
-            const int64_t o4 = (int64_t)y * W + sp.x;
-            if (wide && sp.fx) {
-                *reinterpret_cast<uint4 *>(out + o4) = make_uint4(wd[0], wd[1], wd[2], wd[3]);
-            } else {
+        }
+    };
+    const auto rowf = [&](int y, const int (&s)[3][4], const Side &o) {
+        if (sp.x >= W) return;
+        uint32_t wd[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (sp.x + j < W) out[o4 + j] = wd[j];
+        for (int j = 0; j < 4; ++j) {
+            const int e = (int)((o.e >> (8 * j)) & 255u);
+            uint32_t word = (uint32_t)e << 24;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int rv = (int)(int16_t)(o.r[c][j >> 1] >> (16 * (j & 1)));
+                const int m = mstar(s_ab[c][e], s[c][j]) + rv;
+                bad |= ((m < 0) | (m > 255)) && sp.x + j < W;
+                word |= (uint32_t)(m & 255) << (8 * c);
             }
-        });
+            wd[j] = word;
+        }
+        const int64_t o4 = (int64_t)y * W + sp.x;
+        if (wide && sp.fx) {
+            *reinterpret_cast<uint4 *>(out + o4) = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (sp.x + j < W) out[o4 + j] = wd[j];
+        }
+    };
+    if (gf)
+        strip_walk_side<Side, true>(d, sp, issue, rowf);
+    else
+        strip_walk_side<Side, false>(d, sp, issue, rowf);
     if (bad && d.status) atomicExch(d.status, RDL_ECORRUPT);
 }
 // ---------------------------------------------------------------------------
@@ -2045,9 +2081,11 @@ void launch_tmo_base(const ImgDesc *d, int n, int wgs, bool extra, hipStream_t s
     else
         hipLaunchKernelGGL(k_tmo_base<false>, dim3(wgs), dim3(BLK_THREADS), 0, s, d, n);
 }
-void launch_fit_sums(const ImgDesc *d, int n, int wgs, int bins, int waves, hipStream_t s) {
+void launch_fit_sums(const ImgDesc *d, int n, int wgs, int bins, int waves, hipStream_t s, bool gf) {
     const dim3 block(64 * waves);
-    if (bins >= 4)
+    if (!gf)
+        hipLaunchKernelGGL((k_fit_sums<2, false>), dim3(wgs), block, 0, s, d, n);
+    else if (bins >= 4)
         hipLaunchKernelGGL(k_fit_sums<4>, dim3(wgs), block, 0, s, d, n);
     else if (bins == 2)
         hipLaunchKernelGGL(k_fit_sums<2>, dim3(wgs), block, 0, s, d, n);
@@ -2058,8 +2096,11 @@ void launch_solve(const ImgDesc *d, int n, hipStream_t s) { hipLaunchKernelGGL(k
 void launch_key_total(const ImgDesc *d, int n, int64_t *out2, hipStream_t s) {
     hipLaunchKernelGGL(k_key_total, dim3(n), dim3(64), 0, s, d, n, out2);
 }
-void launch_resid(const ImgDesc *d, int n, int wgs, hipStream_t s) {
-    hipLaunchKernelGGL(k_resid, dim3(wgs), dim3(STRIP_THREADS), 0, s, d, n);
+void launch_resid(const ImgDesc *d, int n, int wgs, hipStream_t s, bool gf) {
+    if (gf)
+        hipLaunchKernelGGL(k_resid<true>, dim3(wgs), dim3(STRIP_THREADS), 0, s, d, n);
+    else
+        hipLaunchKernelGGL(k_resid<false>, dim3(wgs), dim3(STRIP_THREADS), 0, s, d, n);
 }
 void launch_base_decode(const ImgDesc *d, int n, int wgs, hipStream_t s) {
     hipLaunchKernelGGL(k_base_decode, dim3(wgs), dim3(BLK_THREADS), 0, s, d, n);

@@ -31,6 +31,10 @@ HEADER_BYTES = HEADER_DTYPE.itemsize
 
 LAUNCH_DIRECT, LAUNCH_GRAPH = 0, 1
 
+#: Encoder estimators (header field `estimator`, bits 0-3) and the filter-off bit.
+EST_SLR, EST_LEARNED, EST_GLOBAL, EST_NONE = 0, 1, 2, 3
+EST_GF_OFF = 16
+
 #: Entropy code of the enhancement layer: fixed header bytes, default group size.
 ENT_HEADER_BYTES = 4136
 ENT_LOG2K_DEFAULT = 8
@@ -65,6 +69,7 @@ _SIGS = {
     "rdl_set_launch_mode": ([_vp, _i], _i),
     "rdl_set_model": ([_vp, _vp, C.c_size_t], _i),
     "rdl_set_estimator": ([_vp, _i], _i),
+    "rdl_set_gf": ([_vp, _i], _i),
     "rdl_train_sample_bytes": ([], _i),
     "rdl_train_nparam": ([], _i),
     "rdl_train_samples": ([_vp, _vp, _vp, _i, _i, _i, _vp, C.c_int64, _vp, _vp], _i),
@@ -177,8 +182,13 @@ class Codec:
         _chk(self._L.rdl_set_model(self._h, buf, len(blob)), "rdl_set_model")
 
     def set_estimator(self, mode: int):
-        """0: plain SLR; 1: learned estimate where it beats SLR per region."""
+        """0: plain SLR; 1: learned estimate where it beats SLR per region;
+        2: one SLR line per channel (ablation); 3: M* = S (ablation)."""
         _chk(self._L.rdl_set_estimator(self._h, int(mode)), "rdl_set_estimator")
+
+    def set_gf(self, on: bool):
+        """Gaussian-filter restoration of S before the estimate (on by default)."""
+        _chk(self._L.rdl_set_gf(self._h, int(bool(on))), "rdl_set_gf")
 
     # -------------------------------------------------------------- training
     def train_samples(self, rgbe: torch.Tensor, sdr: torch.Tensor, k_img: int, idx: torch.Tensor,

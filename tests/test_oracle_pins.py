@@ -655,3 +655,79 @@ def test_base_decode_grey_dc_blocks(O):
         want = min(max(128 + levels[k] * Q / 8.0, 0), 255)
         assert np.all(blk == blk[0, 0, 0]), "a DC-only grey block decodes flat and grey"
         assert abs(int(blk[0, 0, 0]) - want) <= 1
+
+
+# ---------------------------------------------------------------- ablations (Table I, Fig. 4)
+def _rhu(num: Fraction) -> int:
+    return math.floor(num + Fraction(1, 2))
+
+
+def _line(sv, mv):
+    """Exact least-squares line of m on s in the oracle's fixed point:
+    a_q = rhu(2^22 slope), b_q = rhu(2^14 (mean m - slope_q mean s)), den = 0 -> a = 0."""
+    n = len(sv)
+    Ss, Sm = int(sv.sum()), int(mv.sum())
+    Sss, Ssm = int((sv * sv).sum()), int((sv * mv).sum())
+    den = n * Sss - Ss * Ss
+    a = 0 if den == 0 else _rhu(Fraction((n * Ssm - Ss * Sm) * 2 ** 22, den))
+    b = _rhu(Fraction(Sm * 2 ** 22 - a * Ss, n * 256))
+    return a, b
+
+
+def test_no_estimator_residual_is_m_minus_s(O):
+    """Estimator 3 with the filter off: r = M - S exactly (the residual of a
+    layer without SLRME)."""
+    x = synth.generate(29, 41, 3.5, seed=21, spec_frac=0.05)
+    r = O.encode_mode(x, 75, 3, False)
+    planes = r["resid"][:6 * 29 * 41].view(np.int16).reshape(3, 29, 41)
+    want = x[..., :3].astype(np.int16).transpose(2, 0, 1) - r["sdr"].astype(np.int16).transpose(2, 0, 1)
+    assert np.array_equal(planes, want)
+    assert np.array_equal(r["resid"][6 * 29 * 41:], x[..., 3].reshape(-1))
+
+
+@pytest.mark.parametrize("gf", [True, False])
+def test_global_line_is_the_least_squares_line_over_all_pixels(O, gf):
+    """Estimator 2: one line per channel, the exact least-squares fit over every
+    pixel (rational arithmetic), written to every present exponent."""
+    x = synth.generate(23, 31, 3.0, seed=22, spec_frac=0.05)
+    r = O.encode_mode(x, 60, 2, gf)
+    sstar = O.gf(r["sdr"]) if gf else r["sdr"]
+    present = np.unique(x[..., 3])
+    for c in range(3):
+        a, b = _line(sstar[..., c].astype(np.int64).reshape(-1), x[..., c].astype(np.int64).reshape(-1))
+        assert np.all(r["a_q"][c, present] == a) and np.all(r["b_q"][c, present] == b)
+        absent = np.setdiff1d(np.arange(256), present)
+        assert np.all(r["a_q"][c, absent] == 0) and np.all(r["b_q"][c, absent] == 0)
+
+
+def test_filter_off_lines_fit_raw_s(O):
+    """The filter off: each region's line is the least-squares fit of M on S
+    itself (rational arithmetic per exponent)."""
+    x = synth.generate(19, 27, 3.0, seed=23, spec_frac=0.05)
+    r = O.encode_mode(x, 75, 0, False)
+    E = x[..., 3].reshape(-1)
+    for e in np.unique(E):
+        m = E == e
+        for c in range(3):
+            a, b = _line(r["sdr"][..., c].reshape(-1)[m].astype(np.int64), x[..., c].reshape(-1)[m].astype(np.int64))
+            assert (r["a_q"][c, e], r["b_q"][c, e]) == (a, b)
+
+
+def test_global_equals_per_region_with_one_exponent(O):
+    """With a single exponent present, pooling the regions changes nothing."""
+    x = synth.generate(20, 24, 3.0, seed=24)
+    x[..., 3] = 130
+    a = O.encode_mode(x, 75, 0, True)
+    b = O.encode_mode(x, 75, 2, True)
+    assert np.array_equal(a["resid"], b["resid"]) and np.array_equal(a["a_q"], b["a_q"])
+
+
+@pytest.mark.parametrize("est", [0, 2, 3])
+@pytest.mark.parametrize("gf", [True, False])
+def test_ablation_modes_round_trip(O, est, gf):
+    x = synth.generate(33, 37, 4.0, seed=25 + est, spec_frac=0.05)
+    r = O.encode_mode(x, 50, est, gf)
+    assert np.array_equal(O.decode_mode(r["sdr"], r["a_q"], r["b_q"], r["resid"], 33, 37, gf), x)
+    if est == 0 and gf:
+        ref = O.encode_enh(x, 50)
+        assert np.array_equal(r["resid"], ref["resid"]) and np.array_equal(r["a_q"], ref["a_q"])
