@@ -17,7 +17,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rdl_oracle.c")
-_SRCS = [_SRC, os.path.join(_HERE, "rdl_ent_oracle.c")]
+_SRCS = [_SRC, os.path.join(_HERE, "rdl_ent_oracle.c"), os.path.join(_HERE, "rdl_jpeg_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
 
@@ -76,6 +76,10 @@ def lib():
         L.oracle_encode_learned.restype = C.c_int
         L.oracle_decode_learned.argtypes = [vp, vp, vp, vp, i32, vp, vp, C.c_int, C.c_int, vp]
         L.oracle_decode_learned.restype = C.c_int
+        L.oracle_jpeg_huff_table.argtypes = [vp, vp, vp]
+        L.oracle_jpeg_huff_table.restype = C.c_int
+        L.oracle_jpeg_write.argtypes = [vp, C.c_int, C.c_int, C.c_int, vp, i64]
+        L.oracle_jpeg_write.restype = i64
         L.oracle_ent_freqs.argtypes = [vp, C.c_int, vp]
         L.oracle_ent_freqs.restype = C.c_int
         L.oracle_ent_bound.argtypes = [C.c_int, C.c_int, C.c_int]
@@ -390,4 +394,26 @@ def decode_mode(sdr, a_q, b_q, resid, H: int, W: int, gf: bool) -> np.ndarray:
     if rc:
         raise ValueError("oracle_decode_mode failed with %d" % rc)
     return out
+
+
+# ---------------------------------------------------------------- base-layer JPEG file
+def jpeg_huff_table(freq):
+    """Annex K.2 table of symbol counts freq[256]: (bits[1..16], huffval)."""
+    f = np.ascontiguousarray(freq, np.int64)
+    assert f.size == 256
+    bits = np.zeros(17, np.uint8)
+    hv = np.zeros(256, np.uint8)
+    n = lib().oracle_jpeg_huff_table(_p(f), _p(bits), _p(hv))
+    return bits[1:].copy(), hv[:n].copy()
+
+
+def jpeg_write(dctq: np.ndarray, H: int, W: int, q: int) -> bytes:
+    """Baseline JFIF file of the quantised coefficients int16 [3][H8][W8]."""
+    dctq = np.ascontiguousarray(dctq, np.int16)
+    cap = 4096 + 3 * dctq.size * 8
+    out = np.zeros(cap, np.uint8)
+    n = lib().oracle_jpeg_write(_p(dctq), H, W, q, _p(out), cap)
+    if n < 0:
+        raise ValueError("oracle_jpeg_write failed with %d" % n)
+    return out[:n].tobytes()
 
