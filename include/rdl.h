@@ -245,6 +245,30 @@ int rdl_train_step(rdl_ctx *ctx, float *params, float *adam_m, float *adam_v, co
  * [3][511], hist[c][r + 255] counts residual value r of channel c. */
 int rdl_resid_hist(rdl_ctx *ctx, const void *resid, int H, int W, int64_t *hist, void *stream);
 
+/* ---- The base layer as a JPEG file (Sec. II.B and Sec. IV: the base layer
+ * is a JPEG file that any viewer shows) ----
+ * rdl_jpeg_encode writes the quantised coefficients dct (device, int16
+ * [3][H8][W8] as rdl_stage_tmo_base writes them, 2-byte aligned) at quality q
+ * as a baseline sequential JPEG (ITU-T T.81) in a JFIF file -> out (device,
+ * cap >= rdl_jpeg_bound(H, W) bytes); the file's length goes to *out_len
+ * (DEVICE u64, 8-byte aligned).  Layout: SOI; APP0 "JFIF" 1.01, no thumbnail;
+ * DQT with the two tables of quality q in zig-zag order; SOF0 (8 bits, H x W,
+ * components 1, 2, 3 = Y, Cb, Cr, 1x1 sampling, tables 0, 1, 1); DHT with the
+ * four Huffman tables (Y DC, Y AC, chroma DC, chroma AC), each optimised for
+ * this image by Annex K.2 (Figure K.1 takes the larger symbol on equal
+ * counts) with codes as Annex C assigns them; then one scan per component
+ * (SOS: one component, tables 0/0 for Y and 1/1 for Cb and Cr, Ss 0, Se 63),
+ * blocks in raster order, the DC predicted from the previous block of the
+ * scan, each scan's last byte padded with 1-bits and every 0xFF data byte
+ * followed by 0x00; EOI.  A decoder's IDCT gives S to within its own rounding
+ * (rdl_base_decode gives it exactly).  1 <= H, W <= 65535 (RDL_EINVAL
+ * otherwise).  The context keeps a workspace for the largest image seen
+ * (about 800 bytes per 8x8 block; allocated synchronously when it grows), so
+ * calls on one context must not overlap.  rdl_jpeg_bound is 0 for bad sizes. */
+size_t rdl_jpeg_bound(int H, int W);
+int rdl_jpeg_encode(rdl_ctx *ctx, const int16_t *dct, int H, int W, int q, uint8_t *out, size_t cap,
+                    uint64_t *out_len, void *stream);
+
 /* ---- Entropy code of the enhancement layer (an extension: the paper codes
  * the residual and exponent planes with JPEG 2000, Sec. IV) ----
  * A static rANS coder (J. Duda, "Asymmetric numeral systems", 2013, the range

@@ -108,8 +108,8 @@ int oracle_jpeg_huff_table(const int64_t *freq_in, uint8_t bits[17], uint8_t huf
             nb[j]--;
         }
     int i = 16;
-    while (nb[i] == 0) i--;
-    nb[i]--;  /* drop the reserved code point */
+    while (i > 1 && nb[i] == 0) i--;
+    if (nb[i] > 0) nb[i]--;  /* drop the reserved code point */
     memset(bits, 0, 17);
     for (int k = 1; k <= 16; k++) bits[k] = (uint8_t)nb[k];
     int n = 0;
@@ -204,7 +204,9 @@ static void block_symbols(const int16_t *dct, int64_t W8, int by, int bx, int *p
             run -= 16;
         }
         s = ssss(v[k]);
-        f(ctx, 1, run * 16 + s, (uint32_t)(v[k] < 0 ? v[k] - 1 : v[k]) & ((1u << s) - 1u), s);
+        /* a size above 15 is outside baseline JPEG (never made by the
+           encoder); clamped so that the symbol stays a byte */
+        f(ctx, 1, run * 16 + (s > 15 ? 15 : s), (uint32_t)(v[k] < 0 ? v[k] - 1 : v[k]) & ((1u << s) - 1u), s);
         run = 0;
     }
     if (run > 0) f(ctx, 1, 0x00, 0, 0);

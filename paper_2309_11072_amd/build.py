@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librdl.so")
-SOURCES = ["rdl_kernels.hip", "rdl_train.hip", "rdl_entropy.hip", "rdl_api.hip"]
+SOURCES = ["rdl_kernels.hip", "rdl_train.hip", "rdl_entropy.hip", "rdl_jpeg.hip", "rdl_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

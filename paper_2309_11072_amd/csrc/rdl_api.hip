@@ -48,6 +48,9 @@ struct rdl_ctx {
     // entropy coder workspace (EntWs, then group word counts and words)
     uint8_t *d_ent = nullptr;
     size_t ent_cap = 0;
+    // base-layer JPEG workspace (JpgWs, then per-block and per-chunk arrays)
+    uint8_t *d_jpg = nullptr;
+    size_t jpg_cap = 0;
     // training scratch: per-workgroup gradient partials
     float *d_part = nullptr;
     size_t part_cap = 0;      // floats
@@ -133,6 +136,25 @@ EntArgs ent_args(rdl_ctx *c, int H, int W, int log2_k) {
     a.log2_k = log2_k;
     a.G = (int32_t)G;
     return a;
+}
+
+// Base-layer JPEG workspace: JpgWs, then blen, wsum, woff, raw, ffcnt, cpos
+// (each on a 256-byte boundary).
+struct JpgLayout {
+    size_t blen, wsum, woff, raw, ffcnt, cpos, total;
+};
+JpgLayout jpg_layout(int H, int W) {
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const int64_t nblk = jpg_blocks(H, W), wpc = (nblk + JPG_BLK_WG - 1) / JPG_BLK_WG, cpc = jpg_cpc(H, W);
+    JpgLayout l;
+    l.blen = up(sizeof(JpgWs));
+    l.wsum = up(l.blen + 3 * nblk * 4);
+    l.woff = up(l.wsum + 3 * wpc * 4);
+    l.raw = up(l.woff + 3 * wpc * 8);
+    l.ffcnt = up(l.raw + (size_t)jpg_raw_words(H, W) * 4);
+    l.cpos = up(l.ffcnt + 3 * cpc * 4);
+    l.total = up(l.cpos + 3 * cpc * 8);
+    return l;
 }
 
 struct Grid {
@@ -356,6 +378,7 @@ void rdl_destroy(rdl_ctx *c) {
     if (c->d_desc) (void)hipFree(c->d_desc);
     if (c->d_scratch) (void)hipFree(c->d_scratch);
     if (c->d_ent) (void)hipFree(c->d_ent);
+    if (c->d_jpg) (void)hipFree(c->d_jpg);
     delete c;
 }
 
@@ -635,6 +658,49 @@ int rdl_ent_decode(rdl_ctx *c, const void *code, size_t len, const void *header,
     a.nwords = (int64_t)((total - fixed) / 2);
     launch_ent_decode(a, (hipStream_t)stream);
     return check_launch("k_ent_decode");
+}
+
+size_t rdl_jpeg_bound(int H, int W) {
+    if (!size_ok(H, W) || H > 65535 || W > 65535) return 0;
+    return (size_t)(1024 + 3 * (10 + 2 * ((jpg_blocks(H, W) * JPG_BLOCK_BITS + 7) / 8)) + 2);
+}
+
+int rdl_jpeg_encode(rdl_ctx *c, const int16_t *dct, int H, int W, int q, uint8_t *out, size_t cap, uint64_t *out_len,
+                    void *stream) {
+    if (!c || !dct || !out || !out_len || !size_ok(H, W) || H > 65535 || W > 65535 || q < 1 || q > 100)
+        return RDL_EINVAL;
+    if (cap < rdl_jpeg_bound(H, W) || (reinterpret_cast<uintptr_t>(dct) & 1) ||
+        (reinterpret_cast<uintptr_t>(out_len) & 7))
+        return RDL_EINVAL;
+    DeviceGuard g(c->device);
+    const JpgLayout l = jpg_layout(H, W);
+    if (l.total > c->jpg_cap) {
+        if (c->d_jpg) HIPCHK(hipFree(c->d_jpg));
+        c->d_jpg = nullptr;
+        c->jpg_cap = 0;
+        HIPCHK(hipMalloc(&c->d_jpg, l.total));
+        HIPCHK(hipMemset(c->d_jpg, 0, sizeof(JpgWs)));  // the symbol counts start at zero
+        c->jpg_cap = l.total;
+    }
+    JpgArgs a;
+    memset(&a, 0, sizeof a);
+    a.dct = dct;
+    a.out = out;
+    a.out_len = out_len;
+    a.ws = reinterpret_cast<JpgWs *>(c->d_jpg);
+    a.blen = reinterpret_cast<uint32_t *>(c->d_jpg + l.blen);
+    a.wsum = reinterpret_cast<uint32_t *>(c->d_jpg + l.wsum);
+    a.woff = reinterpret_cast<uint64_t *>(c->d_jpg + l.woff);
+    a.raw = reinterpret_cast<uint32_t *>(c->d_jpg + l.raw);
+    a.ffcnt = reinterpret_cast<uint32_t *>(c->d_jpg + l.ffcnt);
+    a.cpos = reinterpret_cast<uint64_t *>(c->d_jpg + l.cpos);
+    a.H = H;
+    a.W = W;
+    a.q = q;
+    a.cpc = jpg_cpc(H, W);
+    quant_tables_host(q, a.qt);
+    launch_jpeg(a, (hipStream_t)stream);
+    return check_launch("k_jpg");
 }
 
 int rdl_stage_keystat(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int64_t *out2, void *stream) {

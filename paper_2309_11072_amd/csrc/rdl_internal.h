@@ -158,6 +158,39 @@ inline size_t ent_ws_bytes(int H, int W, int log2_k) {
 void launch_ent_encode(const EntArgs &a, hipStream_t s);
 void launch_ent_decode(const EntArgs &a, hipStream_t s);
 
+// Base-layer JPEG file (kernels in rdl_jpeg.hip, format in rdl.h).
+constexpr int JPG_BLK_WG = 256;        // blocks (threads) per workgroup
+constexpr int JPG_CHUNK = 4096;        // raw bytes per stuffing workgroup
+constexpr int JPG_BLOCK_BITS = 2048;   // most bits of one block for any int16 input: DC 16 + 17,
+                                       //   at most 63 AC symbols of 16 + 15 bits, ZRLs and EOB
+struct JpgWs {
+    uint32_t cnt[2][2][256];   // symbol counts per (table, DC/AC); zero between calls
+    uint32_t code[2][2][256];  // code | size << 16
+    uint64_t bits[3];          // bits of each scan
+    uint64_t raw_word[3];      // first raw-buffer word of each scan
+    uint64_t raw_words;
+    uint64_t hdr_len;          // bytes before the first SOS
+};
+struct JpgArgs {
+    const int16_t *dct;        // quantised coefficients [3][H8][W8]
+    uint8_t *out;
+    uint64_t *out_len;
+    JpgWs *ws;
+    uint32_t *blen;            // [3][nblk] bits of each block
+    uint32_t *wsum;            // [3][wpc] bits of each workgroup's blocks
+    uint64_t *woff;            // [3][wpc] their first bit within the scan
+    uint32_t *raw;             // scans' bits, MSB first, bytes in memory order
+    uint32_t *ffcnt;           // [3][cpc] 0xFF bytes per chunk
+    uint64_t *cpos;            // [3][cpc] file position of each chunk
+    int32_t H, W, q, cpc;
+    uint8_t qt[2][64];         // quantisation tables, natural order
+};
+void quant_tables_host(int q, uint8_t out[2][64]);
+void launch_jpeg(const JpgArgs &a, hipStream_t s);
+inline int64_t jpg_blocks(int H, int W) { return (int64_t)((H + 7) / 8) * ((W + 7) / 8); }
+inline int64_t jpg_raw_words(int H, int W) { return 3 * (jpg_blocks(H, W) * JPG_BLOCK_BITS / 32 + 2); }
+inline int jpg_cpc(int H, int W) { return (int)((jpg_blocks(H, W) * JPG_BLOCK_BITS / 8 + 1) / JPG_CHUNK + 1); }
+
 // Training kernels (defined in rdl_train.hip).
 void launch_train_samples(const uint8_t *rgbe, const uint8_t *sdr, int H, int W, int k_img, const int64_t *idx,
                           int64_t n, void *out, hipStream_t s);

@@ -1,0 +1,551 @@
+// rdl_jpeg.hip -- gfx950 kernels that write the base layer's quantised
+// coefficients as a baseline sequential JPEG file (ITU-T T.81) in JFIF: the
+// file a viewer shows (the paper's base layer is a JPEG file, Sec. II.B and
+// Sec. IV).  One scan per component, Huffman tables optimised for the image
+// (Annex K.2), codes as Annex C assigns them.  The file layout is described in
+// rdl.h; every byte equals what a plain sequential writer produces.
+//
+// k_jpg_count (symbol counts per table) -> k_jpg_tables (four Huffman tables,
+// the file header) -> k_jpg_bits (bit length of every 8x8 block, sums per
+// workgroup) -> k_jpg_offsets (bit offset of every workgroup's blocks, scan
+// sizes) -> k_jpg_zero (raw bit buffer) -> k_jpg_emit (every block's bits at
+// its offset) -> k_jpg_ffcount (0xFF bytes per chunk) -> k_jpg_layout
+// (where every chunk goes, SOS headers, EOI, length) -> k_jpg_stuff (bytes
+// with a 0x00 after each 0xFF).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rdl_internal.h"
+
+namespace rdl {
+
+namespace {
+
+// Zig-zag order (Figure A.6): the anti-diagonals s = u + v from the top left,
+// downwards on odd s, upwards on even s; zz[k] = natural index of the k-th.
+struct ZigZag {
+    int zz[64];
+    constexpr ZigZag() : zz() {
+        int k = 0;
+        for (int s = 0; s <= 14; ++s) {
+            const int lo = s > 7 ? s - 7 : 0, hi = s < 7 ? s : 7;
+            if (s & 1)
+                for (int r = lo; r <= hi; ++r) zz[k++] = r * 8 + (s - r);
+            else
+                for (int r = hi; r >= lo; --r) zz[k++] = r * 8 + (s - r);
+        }
+    }
+};
+__constant__ ZigZag c_zz = ZigZag();
+
+__device__ __forceinline__ int ssss(int v) {
+    const uint32_t a = (uint32_t)(v < 0 ? -v : v);
+    return a ? 32 - __clz(a) : 0;
+}
+
+struct Geo {
+    int nbx, nby, nblk, wpc;  // blocks per row / column / component, workgroups per component
+    int64_t H8, W8;
+};
+__device__ __forceinline__ Geo geo(const JpgArgs &a) {
+    Geo g;
+    g.nbx = (a.W + 7) >> 3;
+    g.nby = (a.H + 7) >> 3;
+    g.nblk = g.nbx * g.nby;
+    g.wpc = (g.nblk + JPG_BLK_WG - 1) / JPG_BLK_WG;
+    g.H8 = (int64_t)g.nby * 8;
+    g.W8 = (int64_t)g.nbx * 8;
+    return g;
+}
+
+// The coefficients of block k of component c, in zig-zag order, and the DC of
+// the block before it in raster order (0 for the first).
+__device__ __forceinline__ void load_block(const JpgArgs &a, const Geo &g, int c, int k, int v[64], int &pred) {
+    const int by = k / g.nbx, bx = k - by * g.nbx;
+    const int16_t *base = a.dct + (int64_t)c * g.H8 * g.W8 + (int64_t)by * 8 * g.W8 + bx * 8;
+    int nat[64];
+    if ((reinterpret_cast<uintptr_t>(a.dct) & 15) == 0) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const uint4 q = *reinterpret_cast<const uint4 *>(base + r * g.W8);
+            const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int u = 0; u < 8; ++u) nat[r * 8 + u] = (int)(int16_t)(w4[u >> 1] >> (16 * (u & 1)));
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) nat[r * 8 + u] = base[r * g.W8 + u];
+    }
+#pragma unroll
+    for (int i = 0; i < 64; ++i) v[i] = nat[c_zz.zz[i]];
+    pred = 0;
+    if (k > 0) {
+        const int pk = k - 1, pby = pk / g.nbx, pbx = pk - pby * g.nbx;
+        pred = a.dct[(int64_t)c * g.H8 * g.W8 + (int64_t)pby * 8 * g.W8 + pbx * 8];
+    }
+}
+
+// Calls f(ac, symbol, extra, n) for the block's symbols (Annex F.1.2).  An AC
+// size above 15 (a coefficient of 2^15 in magnitude, which baseline JPEG does
+// not allow and the encoder never makes) is clamped into the symbol so that
+// every symbol stays below 256.
+template <class F>
+__device__ __forceinline__ void block_symbols(const int v[64], int pred, F &&f) {
+    const int diff = v[0] - pred;
+    int s = ssss(diff);
+    f(0, s, (uint32_t)(diff < 0 ? diff - 1 : diff) & ((1u << s) - 1u), s);
+    int run = 0;
+    for (int k = 1; k < 64; ++k) {
+        if (v[k] == 0) {
+            ++run;
+            continue;
+        }
+        while (run > 15) {
+            f(1, 0xF0, 0u, 0);
+            run -= 16;
+        }
+        s = ssss(v[k]);
+        f(1, run * 16 + min(s, 15), (uint32_t)(v[k] < 0 ? v[k] - 1 : v[k]) & ((1u << s) - 1u), s);
+        run = 0;
+    }
+    if (run > 0) f(1, 0x00, 0u, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Symbol counts: one thread per block; table 0 = Y, 1 = Cb and Cr.
+__global__ __launch_bounds__(JPG_BLK_WG) void k_jpg_count(JpgArgs a) {
+    __shared__ uint32_t h[2][2][256];
+    for (int k = threadIdx.x; k < 2 * 2 * 256; k += JPG_BLK_WG) (&h[0][0][0])[k] = 0;
+    __syncthreads();
+    const Geo g = geo(a);
+    const int c = blockIdx.x / g.wpc, k = (blockIdx.x - c * g.wpc) * JPG_BLK_WG + threadIdx.x;
+    const int t = c ? 1 : 0;
+    if (k < g.nblk) {
+        int v[64], pred;
+        load_block(a, g, c, k, v, pred);
+        block_symbols(v, pred, [&](int ac, int sym, uint32_t, int) { atomicAdd(&h[t][ac][sym], 1u); });
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2 * 2 * 256; i += JPG_BLK_WG) {
+        const uint32_t x = (&h[0][0][0])[i];
+        if (x) atomicAdd(&a.ws->cnt[0][0][0] + i, x);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Huffman tables (Annex K.2) and the file header: one wave per table
+// (t = Y / chroma, ac), 4 waves.
+//   Figure K.1: while two symbols with a count remain, merge the least (ties:
+//   the larger value) into the next least; every symbol of the two merged
+//   groups gains one bit.  Groups are tracked by a label per symbol, so a
+//   merge is one pass over the 257 symbols (256 + the reserved point).
+//   Figure K.3: sizes above 16 are cut; K.4: symbols listed by size, then value;
+//   Annex C: canonical codes.  Then the waves write SOI, APP0, DQT, SOF0, DHT.
+__device__ __forceinline__ unsigned long long wave_min64(unsigned long long v) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)v, off, 64), hi = __shfl_xor((uint32_t)(v >> 32), off, 64);
+        const unsigned long long o = (unsigned long long)hi << 32 | lo;
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ void put_be16(uint8_t *p, int v) {
+    p[0] = (uint8_t)(v >> 8);
+    p[1] = (uint8_t)v;
+}
+
+__global__ __launch_bounds__(256) void k_jpg_tables(JpgArgs a) {
+    __shared__ uint64_t s_f[4][260];
+    __shared__ int s_cs[4][260], s_grp[4][260];
+    __shared__ int s_nb[4][34];
+    __shared__ uint8_t s_hv[4][256];
+    __shared__ int s_n[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;  // table w: t = w >> 1, ac = w & 1
+    const int t = w >> 1, ac = w & 1;
+    for (int i = lane; i < 257; i += 64) {
+        s_f[w][i] = i < 256 ? a.ws->cnt[t][ac][i] : 1u;
+        s_cs[w][i] = 0;
+        s_grp[w][i] = i;
+    }
+    for (int i = lane; i < 34; i += 64) s_nb[w][i] = 0;
+    __builtin_amdgcn_wave_barrier();
+    __syncthreads();
+    // Figure K.1
+    for (;;) {
+        unsigned long long k1 = ~0ull;
+        for (int i = lane; i < 257; i += 64)
+            if (s_f[w][i]) {
+                const unsigned long long key = s_f[w][i] << 9 | (uint64_t)(511 - i);
+                k1 = key < k1 ? key : k1;
+            }
+        k1 = wave_min64(k1);
+        const int v1 = 511 - (int)(k1 & 511);
+        unsigned long long k2 = ~0ull;
+        for (int i = lane; i < 257; i += 64)
+            if (s_f[w][i] && i != v1) {
+                const unsigned long long key = s_f[w][i] << 9 | (uint64_t)(511 - i);
+                k2 = key < k2 ? key : k2;
+            }
+        k2 = wave_min64(k2);
+        if (k2 == ~0ull) break;  // uniform
+        const int v2 = 511 - (int)(k2 & 511);
+        const int g1 = s_grp[w][v1], g2 = s_grp[w][v2];
+        __builtin_amdgcn_wave_barrier();
+        for (int i = lane; i < 257; i += 64) {
+            const int gi = s_grp[w][i];
+            if (gi == g1 || gi == g2) {
+                s_cs[w][i] += 1;
+                s_grp[w][i] = g1;
+            }
+        }
+        if (lane == 0) {
+            s_f[w][v1] += s_f[w][v2];
+            s_f[w][v2] = 0;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // sizes histogram, Figure K.3, the reserved point dropped
+    if (lane == 0) {
+        int *nb = s_nb[w];
+        for (int i = 0; i < 257; ++i)
+            if (s_cs[w][i]) nb[min(s_cs[w][i], 32)] += 1;
+        for (int i = 32; i > 16; --i)
+            while (nb[i] > 0) {
+                int j = i - 2;
+                while (nb[j] == 0) --j;
+                nb[i] -= 2;
+                nb[i - 1] += 1;
+                nb[j + 1] += 2;
+                nb[j] -= 1;
+            }
+        int i = 16;
+        while (i > 1 && nb[i] == 0) --i;
+        if (nb[i] > 0) nb[i] -= 1;
+    }
+    __syncthreads();
+    // Figure K.4: rank of each present symbol by (size, value); the symbol of
+    // rank r takes the r-th code of the bits[] list
+    int nsym = 0;
+    for (int i = 0; i < 256; ++i) nsym += s_cs[w][i] ? 1 : 0;
+    for (int s = lane; s < 256; s += 64) {
+        const int cs = s_cs[w][s];
+        if (!cs) continue;
+        int rank = 0;
+        for (int i = 0; i < 256; ++i) {
+            const int ci = s_cs[w][i];
+            rank += (ci && (ci < cs || (ci == cs && i < s))) ? 1 : 0;
+        }
+        s_hv[w][rank] = (uint8_t)s;
+    }
+    if (lane == 0) s_n[w] = nsym;
+    __syncthreads();
+    // Annex C: canonical codes by rank; code | size << 16 per symbol
+    if (lane == 0) {
+        uint32_t code = 0;
+        int r = 0;
+        for (int len = 1; len <= 16; ++len) {
+            for (int j = 0; j < s_nb[w][len]; ++j, ++r)
+                if (r < nsym) a.ws->code[t][ac][s_hv[w][r]] = code++ | (uint32_t)len << 16;
+            code <<= 1;
+        }
+    }
+    // File header: SOI, APP0, DQT, SOF0, DHT (wave 0 writes the fixed part,
+    // each wave its DHT table)
+    uint8_t *o = a.out;
+    if (w == 0 && lane == 0) {
+        put_be16(o + 0, 0xFFD8);
+        put_be16(o + 2, 0xFFE0);
+        put_be16(o + 4, 16);
+        const uint8_t jfif[14] = {'J', 'F', 'I', 'F', 0, 1, 1, 0, 0, 1, 0, 1, 0, 0};
+        for (int k = 0; k < 14; ++k) o[6 + k] = jfif[k];
+        put_be16(o + 20, 0xFFDB);
+        put_be16(o + 22, 2 + 2 * 65);
+        for (int tt = 0; tt < 2; ++tt) {
+            o[24 + 65 * tt] = (uint8_t)tt;
+            for (int k = 0; k < 64; ++k) o[25 + 65 * tt + k] = a.qt[tt][c_zz.zz[k]];
+        }
+        uint8_t *sf = o + 154;
+        put_be16(sf, 0xFFC0);
+        put_be16(sf + 2, 17);
+        sf[4] = 8;
+        put_be16(sf + 5, a.H);
+        put_be16(sf + 7, a.W);
+        sf[9] = 3;
+        for (int c = 0; c < 3; ++c) {
+            sf[10 + 3 * c] = (uint8_t)(c + 1);
+            sf[11 + 3 * c] = 0x11;
+            sf[12 + 3 * c] = (uint8_t)(c ? 1 : 0);
+        }
+        int dl = 2;
+        for (int k = 0; k < 4; ++k) dl += 17 + s_n[k];
+        put_be16(o + 173, 0xFFC4);
+        put_be16(o + 175, dl);
+        a.ws->hdr_len = 175 + dl;
+    }
+    // DHT tables in the order (Y DC, Y AC, chroma DC, chroma AC) = waves 0..3
+    if (lane == 0) {
+        int at = 177;
+        for (int k = 0; k < w; ++k) at += 17 + s_n[k];
+        o[at] = (uint8_t)(ac * 16 + t);
+        for (int len = 1; len <= 16; ++len) o[at + len] = (uint8_t)s_nb[w][len];
+        for (int r = 0; r < nsym; ++r) o[at + 17 + r] = s_hv[w][r];
+    }
+    // counts back to zero for the next call
+    for (int i = lane; i < 256; i += 64) a.ws->cnt[t][ac][i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Bit length of every block; sums per workgroup.
+__global__ __launch_bounds__(JPG_BLK_WG) void k_jpg_bits(JpgArgs a) {
+    __shared__ uint8_t s_sz[2][256];
+    __shared__ uint32_t s_red[JPG_BLK_WG / 64];
+    const Geo g = geo(a);
+    const int c = blockIdx.x / g.wpc, k = (blockIdx.x - c * g.wpc) * JPG_BLK_WG + threadIdx.x;
+    const int t = c ? 1 : 0;
+    for (int i = threadIdx.x; i < 512; i += JPG_BLK_WG) (&s_sz[0][0])[i] = (uint8_t)(a.ws->code[t][i >> 8][i & 255] >> 16);
+    __syncthreads();
+    uint32_t bits = 0;
+    if (k < g.nblk) {
+        int v[64], pred;
+        load_block(a, g, c, k, v, pred);
+        block_symbols(v, pred, [&](int ac, int sym, uint32_t, int n) { bits += s_sz[ac][sym] + n; });
+        a.blen[(int64_t)c * g.nblk + k] = bits;
+    }
+    for (int off = 32; off > 0; off >>= 1) bits += __shfl_xor(bits, off, 64);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = bits;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t s = 0;
+        for (int i = 0; i < JPG_BLK_WG / 64; ++i) s += s_red[i];
+        a.wsum[blockIdx.x] = s;
+    }
+}
+
+// Exclusive scan of the workgroup sums per component (bit offsets within the
+// component's scan), the scans' bit counts and their raw-buffer word offsets.
+__global__ __launch_bounds__(1024) void k_jpg_offsets(JpgArgs a) {
+    __shared__ uint32_t sh[16];
+    __shared__ uint64_t s_carry;
+    const Geo g = geo(a);
+    for (int c = 0; c < 3; ++c) {
+        if (threadIdx.x == 0) s_carry = 0;
+        __syncthreads();
+        for (int b = 0; b < g.wpc; b += 1024) {
+            const int i = b + threadIdx.x;
+            const uint32_t v = i < g.wpc ? a.wsum[c * g.wpc + i] : 0u;
+            // block exclusive scan
+            const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+            uint32_t inc = v;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(inc, off, 64);
+                if (lane >= off) inc += y;
+            }
+            if (lane == 63) sh[wv] = inc;
+            __syncthreads();
+            uint32_t before = 0, tot = 0;
+            for (int k = 0; k < 16; ++k) {
+                before += k < wv ? sh[k] : 0u;
+                tot += sh[k];
+            }
+            if (i < g.wpc) a.woff[c * g.wpc + i] = s_carry + before + inc - v;
+            __syncthreads();
+            if (threadIdx.x == 0) s_carry += tot;
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) a.ws->bits[c] = s_carry;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        uint64_t wo = 0;
+        for (int c = 0; c < 3; ++c) {
+            a.ws->raw_word[c] = wo;
+            wo += (a.ws->bits[c] + 31) / 32;
+        }
+        a.ws->raw_words = wo;
+    }
+}
+
+__global__ void k_jpg_zero(JpgArgs a) {
+    const uint64_t n = a.ws->raw_words;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        a.raw[i] = 0;
+}
+
+// Every block's bits at its offset: bit p of a scan is bit 7 - (p mod 8) of its
+// byte p / 8, so a 32-bit word of the raw buffer holds 4 bytes in memory order
+// (bits are ORed in byte-swapped).  The last block of a scan pads the last
+// byte with 1-bits.
+__device__ __forceinline__ void or_bits(uint32_t *raw, uint64_t pos, uint32_t v, int n) {
+    if (n == 0) return;
+    const uint64_t wi = pos >> 5;
+    const int sh = (int)(pos & 31);
+    if (sh + n <= 32) {
+        atomicOr(raw + wi, __builtin_bswap32(v << (32 - sh - n)));
+    } else {
+        const int n1 = 32 - sh, n2 = n - n1;
+        atomicOr(raw + wi, __builtin_bswap32(v >> n2));
+        atomicOr(raw + wi + 1, __builtin_bswap32(v << (32 - n2)));
+    }
+}
+
+__global__ __launch_bounds__(JPG_BLK_WG) void k_jpg_emit(JpgArgs a) {
+    __shared__ uint32_t s_code[2][256];
+    __shared__ uint32_t sh[JPG_BLK_WG / 64];
+    const Geo g = geo(a);
+    const int c = blockIdx.x / g.wpc, k = (blockIdx.x - c * g.wpc) * JPG_BLK_WG + threadIdx.x;
+    const int t = c ? 1 : 0;
+    for (int i = threadIdx.x; i < 512; i += JPG_BLK_WG) (&s_code[0][0])[i] = a.ws->code[t][i >> 8][i & 255];
+    const uint32_t len = k < g.nblk ? a.blen[(int64_t)c * g.nblk + k] : 0u;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t inc = len;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += y;
+    }
+    if (lane == 63) sh[wv] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int i = 0; i < wv; ++i) before += sh[i];
+    if (k >= g.nblk) return;
+    uint64_t pos = a.woff[blockIdx.x] + before + inc - len;
+    uint32_t *raw = a.raw + a.ws->raw_word[c];
+    int v[64], pred;
+    load_block(a, g, c, k, v, pred);
+    block_symbols(v, pred, [&](int ac, int sym, uint32_t extra, int n) {
+        const uint32_t cs = s_code[ac][sym];
+        const int cl = (int)(cs >> 16);
+        or_bits(raw, pos, cs & 0xFFFFu, cl);
+        pos += cl;
+        or_bits(raw, pos, extra, n);
+        pos += n;
+    });
+    if (k == g.nblk - 1 && (pos & 7)) {
+        const int pad = 8 - (int)(pos & 7);
+        or_bits(raw, pos, (1u << pad) - 1u, pad);
+    }
+}
+
+// 0xFF bytes per chunk of JPG_CHUNK raw bytes of each scan.
+__global__ __launch_bounds__(256) void k_jpg_ffcount(JpgArgs a) {
+    __shared__ uint32_t sh[4];
+    const int c = blockIdx.x / a.cpc, j = blockIdx.x - c * a.cpc;
+    const uint64_t nbytes = (a.ws->bits[c] + 7) / 8;
+    const uint8_t *raw = reinterpret_cast<const uint8_t *>(a.raw + a.ws->raw_word[c]);
+    uint32_t n = 0;
+    for (int i = threadIdx.x; i < JPG_CHUNK; i += 256) {
+        const uint64_t b = (uint64_t)j * JPG_CHUNK + i;
+        if (b < nbytes && raw[b] == 0xFF) ++n;
+    }
+    for (int off = 32; off > 0; off >>= 1) n += __shfl_xor(n, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = n;
+    __syncthreads();
+    if (threadIdx.x == 0) a.ffcnt[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// Where every chunk's bytes go in the file; SOS headers, EOI, the length.
+__global__ __launch_bounds__(1024) void k_jpg_layout(JpgArgs a) {
+    __shared__ uint32_t sh[16];
+    __shared__ uint64_t s_carry, s_at;
+    if (threadIdx.x == 0) s_at = a.ws->hdr_len;
+    __syncthreads();
+    for (int c = 0; c < 3; ++c) {
+        const uint64_t nbytes = (a.ws->bits[c] + 7) / 8;
+        if (threadIdx.x == 0) {
+            uint8_t *sos = a.out + s_at;
+            put_be16(sos, 0xFFDA);
+            put_be16(sos + 2, 8);
+            sos[4] = 1;
+            sos[5] = (uint8_t)(c + 1);
+            sos[6] = (uint8_t)(c ? 0x11 : 0x00);
+            sos[7] = 0;
+            sos[8] = 63;
+            sos[9] = 0;
+            s_at += 10;
+            s_carry = 0;
+        }
+        __syncthreads();
+        for (int b = 0; b < a.cpc; b += 1024) {
+            const int i = b + threadIdx.x;
+            const uint32_t v = i < a.cpc ? a.ffcnt[c * a.cpc + i] : 0u;
+            const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+            uint32_t inc = v;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(inc, off, 64);
+                if (lane >= off) inc += y;
+            }
+            if (lane == 63) sh[wv] = inc;
+            __syncthreads();
+            uint32_t before = 0, tot = 0;
+            for (int k = 0; k < 16; ++k) {
+                before += k < wv ? sh[k] : 0u;
+                tot += sh[k];
+            }
+            // file position of chunk i's first byte: scan start + bytes before + stuffed zeros before
+            if (i < a.cpc) a.cpos[c * a.cpc + i] = s_at + (uint64_t)i * JPG_CHUNK + s_carry + before + inc - v;
+            __syncthreads();
+            if (threadIdx.x == 0) s_carry += tot;
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) s_at += nbytes + s_carry;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        put_be16(a.out + s_at, 0xFFD9);
+        *a.out_len = s_at + 2;
+    }
+}
+
+// Raw bytes of a chunk into the file, a 0x00 after each 0xFF (16 per thread).
+__global__ __launch_bounds__(256) void k_jpg_stuff(JpgArgs a) {
+    __shared__ uint32_t sh[4];
+    const int c = blockIdx.x / a.cpc, j = blockIdx.x - c * a.cpc;
+    const uint64_t nbytes = (a.ws->bits[c] + 7) / 8;
+    const uint8_t *raw = reinterpret_cast<const uint8_t *>(a.raw + a.ws->raw_word[c]);
+    const uint64_t b0 = (uint64_t)j * JPG_CHUNK + (uint64_t)threadIdx.x * 16;
+    uint8_t by[16];
+    uint32_t n = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        by[i] = b0 + i < nbytes ? raw[b0 + i] : 0;
+        n += (b0 + i < nbytes && by[i] == 0xFF) ? 1u : 0u;
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t inc = n;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += y;
+    }
+    if (lane == 63) sh[wv] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int i = 0; i < wv; ++i) before += sh[i];
+    uint64_t at = a.cpos[blockIdx.x] + (uint64_t)threadIdx.x * 16 + before + inc - n;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (b0 + i >= nbytes) break;
+        a.out[at++] = by[i];
+        if (by[i] == 0xFF) a.out[at++] = 0;
+    }
+}
+
+}  // namespace
+
+void launch_jpeg(const JpgArgs &a, hipStream_t s) {
+    const int nbx = (a.W + 7) >> 3, nby = (a.H + 7) >> 3, nblk = nbx * nby;
+    const int wpc = (nblk + JPG_BLK_WG - 1) / JPG_BLK_WG;
+    hipLaunchKernelGGL(k_jpg_count, dim3(3 * wpc), dim3(JPG_BLK_WG), 0, s, a);
+    hipLaunchKernelGGL(k_jpg_tables, dim3(1), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_jpg_bits, dim3(3 * wpc), dim3(JPG_BLK_WG), 0, s, a);
+    hipLaunchKernelGGL(k_jpg_offsets, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_jpg_zero, dim3(1024), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_jpg_emit, dim3(3 * wpc), dim3(JPG_BLK_WG), 0, s, a);
+    hipLaunchKernelGGL(k_jpg_ffcount, dim3(3 * a.cpc), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_jpg_layout, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_jpg_stuff, dim3(3 * a.cpc), dim3(256), 0, s, a);
+}
+
+}  // namespace rdl

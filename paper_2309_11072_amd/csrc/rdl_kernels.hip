@@ -1998,6 +1998,12 @@ __global__ __launch_bounds__(TILE_THREADS) void k_hist(const ImgDesc *__restrict
 // ---------------------------------------------------------------------------
 // Host side: tables and launchers.
 // ---------------------------------------------------------------------------
+void quant_tables_host(int q, uint8_t out[2][64]) {
+    const int sc = q < 50 ? 5000 / q : 200 - 2 * q;  // IJG quality scaling
+    for (int t = 0; t < 2; ++t)
+        for (int k = 0; k < 64; ++k) out[t][k] = (uint8_t)std::min(std::max((ANNEX_K[t][k] * sc + 50) / 100, 1), 255);
+}
+
 hipError_t upload_tables(int *bad_table) {
     *bad_table = 0;
     static int32_t log2f[4096];
@@ -2039,10 +2045,11 @@ hipError_t upload_tables(int *bad_table) {
     if (thr[1] <= ldexpf(1.0f, -20) || thr[255] >= 2.0f) *bad_table = 1;
     static uint32_t qm[100][2][64][4];
     for (int q = 1; q <= 100; ++q) {
-        const int sc = q < 50 ? 5000 / q : 200 - 2 * q;  // IJG quality scaling
+        uint8_t qt[2][64];
+        quant_tables_host(q, qt);
         for (int t = 0; t < 2; ++t)
             for (int k = 0; k < 64; ++k) {
-                const uint32_t Q = (uint32_t)std::min(std::max((ANNEX_K[t][k] * sc + 50) / 100, 1), 255);
+                const uint32_t Q = qt[t][k];
                 qm[q - 1][t][k][0] = (((1u << 20) + Q - 1u) / Q) | (Q << 24);
                 qm[q - 1][t][k][1] = Q / 2;
                 qm[q - 1][t][k][2] = (Q & 1u) ? 0u : 0xFFFFFFFFu;

@@ -54,6 +54,8 @@ _SIGS = {
     "rdl_decode_batch": ([_vp, _vp, _i, _vp], _i),
     "rdl_base_decode": ([_vp, _vp, _vp, _i, _i, _vp, _vp, _vp], _i),
     "rdl_resid_hist": ([_vp, _vp, _i, _i, _vp, _vp], _i),
+    "rdl_jpeg_bound": ([_i, _i], C.c_size_t),
+    "rdl_jpeg_encode": ([_vp, _vp, _i, _i, _i, _vp, C.c_size_t, _vp, _vp], _i),
     "rdl_ent_bound": ([_i, _i, _i], C.c_size_t),
     "rdl_ent_encode": ([_vp, _vp, _i, _i, _i, _vp, C.c_size_t, _vp, _vp], _i),
     "rdl_ent_decode": ([_vp, _vp, C.c_size_t, _vp, _i, _i, _vp, _vp, _vp], _i),
@@ -261,6 +263,22 @@ class Codec:
         hist = torch.empty((3, 511), dtype=torch.int64, device=resid.device)
         _chk(self._L.rdl_resid_hist(self._h, _ptr(resid), H, W, _ptr(hist), _stream(stream)), "rdl_resid_hist")
         return hist
+
+    # ------------------------------------------------- base layer as a JPEG file
+    def jpeg_encode_into(self, dct: torch.Tensor, H: int, W: int, q: int, out: torch.Tensor, out_len: torch.Tensor,
+                         stream=None) -> None:
+        """JFIF file of the quantised coefficients into out (uint8, >= rdl_jpeg_bound
+        bytes); its length to out_len (one int64 on the device).  Does not synchronise."""
+        assert out.dtype == torch.uint8 and out_len.dtype == torch.int64 and out_len.numel() == 1
+        _chk(self._L.rdl_jpeg_encode(self._h, _ptr(dct), H, W, int(q), _ptr(out), out.numel(), _ptr(out_len),
+                                     _stream(stream)), "rdl_jpeg_encode")
+
+    def jpeg_encode(self, dct: torch.Tensor, H: int, W: int, q: int, stream=None) -> torch.Tensor:
+        """The JFIF file (uint8 device tensor, trimmed; synchronises)."""
+        out = torch.empty(int(self._L.rdl_jpeg_bound(H, W)), dtype=torch.uint8, device=dct.device)
+        n = torch.zeros(1, dtype=torch.int64, device=dct.device)
+        self.jpeg_encode_into(dct, H, W, q, out, n, stream)
+        return out[:int(n.item())]
 
     # ------------------------------------------------- entropy code of the layer
     def ent_bound(self, H: int, W: int, log2_k: int = ENT_LOG2K_DEFAULT) -> int:

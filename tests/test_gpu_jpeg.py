@@ -1,0 +1,75 @@
+"""GPU JPEG file of the base layer against the oracle's writer, byte for
+byte, and read back by an independent decoder (libjpeg through Pillow)."""
+import io
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2309_11072_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def rdl_mod():
+    from paper_2309_11072_amd import rdl
+    return rdl
+
+
+@pytest.fixture(scope="module")
+def codec(rdl_mod):
+    c = rdl_mod.Codec(0)
+    yield c
+    c.close()
+
+
+def coefficients(codec, H, W, q, seed):
+    x = synth.generate(H, W, 3.5, seed=seed, spec_frac=0.05)
+    d = torch.from_numpy(x).cuda()
+    ks = codec.stage_keystat(d)
+    sdr, _, dct = codec.stage_tmo_base(d, q, ks, want_dct=True)
+    return sdr, dct
+
+
+def check(codec, O, H, W, q, seed, offset=0):
+    sdr, dct = coefficients(codec, H, W, q, seed)
+    if offset:
+        buf = torch.zeros(dct.numel() + offset // 2, dtype=torch.int16, device="cuda")
+        buf[offset // 2:] = dct.reshape(-1)
+        dct = buf[offset // 2:].reshape(dct.shape)
+    jp = codec.jpeg_encode(dct, H, W, q).cpu().numpy().tobytes()
+    ref = O.jpeg_write(dct.cpu().numpy(), H, W, q)
+    assert len(jp) == len(ref), (len(jp), len(ref))
+    assert jp == ref
+    PIL = pytest.importorskip("PIL.Image")
+    im = PIL.open(io.BytesIO(jp))
+    im.load()
+    assert im.size == (W, H)
+    d = np.abs(np.asarray(im.convert("RGB")).astype(int) - sdr.cpu().numpy().astype(int))
+    assert d.max() <= 3 and d.mean() <= 0.5
+    return len(jp)
+
+
+@pytest.mark.parametrize("H,W,q", [(1, 1, 75), (7, 9, 50), (8, 8, 100), (61, 83, 90), (217, 301, 1),
+                                   (256, 384, 100), (1081, 1921, 75)])
+def test_file_equals_oracle(codec, O, H, W, q):
+    _say("jpeg", H, W, q)
+    check(codec, O, H, W, q, H + 3 * W)
+
+
+def test_unaligned_coefficients_and_reuse(codec, O):
+    for H, W, q, off in [(97, 131, 60, 2), (480, 640, 95, 0), (33, 65, 20, 6), (2, 2, 100, 0)]:
+        _say("jpeg reuse / alignment", H, W, q, off)
+        check(codec, O, H, W, q, H * W + q, offset=off)
+
+
+def test_full_size_3840x2160(codec, O):
+    sp = synth.image_3840x2160()
+    _say("jpeg 3840x2160")
+    n = check(codec, O, sp.H, sp.W, sp.q, sp.seed)
+    _say("bytes", n, "bits/px %.3f" % (8 * n / (sp.H * sp.W)))
