@@ -16,6 +16,8 @@ Also measured, outside the timed region:
     and decode times, coded bits/pixel against the planes' H0, round trip;
   * the batched decoder, quantised coefficients -> S -> RGBE, on the image
     and on the 64-image batch;
+  * the base layer written as a JPEG file, and the size of the whole
+    dual-layer stream (JPEG + entropy-coded enhancement layer);
   * the ablations (SLR without the Gaussian filter, one line per channel, no
     estimator) and a quality sweep: residual bits/pixel on the image;
   * the batched encoder on 64 uneven images (~275 Mpx, one launch per stage);
@@ -345,9 +347,27 @@ def main():
 
     # ---- decoder: quantised coefficients -> S -> RGBE ------------------------
     decoder = None
+    jpeg = None
     if args.decode_steps > 0:
         ks = codec.stage_keystat(d)
         s_ref, _, dct = codec.stage_tmo_base(d, q, ks, want_dct=True)
+        # the base layer as a JPEG file (baseline, optimised Huffman tables)
+        jbuf = torch.empty(int(codec._L.rdl_jpeg_bound(H, W)), dtype=torch.uint8, device="cuda")
+        jlen = torch.zeros(1, dtype=torch.int64, device="cuda")
+        for _ in range(3):
+            codec.jpeg_encode_into(dct, H, W, q, jbuf, jlen)
+        ms_j = time_calls(lambda: codec.jpeg_encode_into(dct, H, W, q, jbuf, jlen), args.decode_steps, stream)
+        jbytes = int(jlen.item())
+        jpeg = {"workload": "the 3840x2160 image's base layer: quantised coefficients -> baseline JFIF file "
+                            "(Huffman tables optimised per image, one scan per component)",
+                "ms": round(ms_j, 5), "Mpixel_s": round(H * W / (ms_j * 1e-3) / 1e6, 1), "bytes": jbytes,
+                "bits_per_pixel": round(8 * jbytes / (H * W), 4)}
+        if entropy is not None:
+            jpeg["dual_layer_bits_per_pixel"] = round(jpeg["bits_per_pixel"] + entropy["bits_per_pixel_coded"], 4)
+            jpeg["dual_layer_encode_ms"] = round(ms_step + ms_j + entropy["ms_encode"], 5)
+            jpeg["dual_layer_Mpixel_s"] = round(H * W / (jpeg["dual_layer_encode_ms"] * 1e-3) / 1e6, 1)
+        say("jpeg: %.1f us, %.4f bits/px" % (ms_j * 1e3, jpeg["bits_per_pixel"]))
+        del jbuf
         s_dec = torch.empty_like(sdr)
         rgbe_dec = torch.empty_like(d)
         st = torch.zeros(1, dtype=torch.int32, device="cuda")
@@ -520,6 +540,7 @@ def main():
         "device_copy_GBps": round(copy_gbps, 1),
         "entropy": entropy,
         "decoder": decoder,
+        "jpeg": jpeg,
         "ablation": ablation,
         "batch": batch,
         "learned": learned,

@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "rdl_internal.h"
 
 namespace rdl {
@@ -143,14 +145,13 @@ __global__ __launch_bounds__(JPG_BLK_WG) void k_jpg_count(JpgArgs a) {
 //   merge is one pass over the 257 symbols (256 + the reserved point).
 //   Figure K.3: sizes above 16 are cut; K.4: symbols listed by size, then value;
 //   Annex C: canonical codes.  Then the waves write SOI, APP0, DQT, SOF0, DHT.
-__device__ __forceinline__ unsigned long long wave_min64(unsigned long long v) {
-    for (int off = 32; off > 0; off >>= 1) {
-        const uint32_t lo = __shfl_xor((uint32_t)v, off, 64), hi = __shfl_xor((uint32_t)(v >> 32), off, 64);
-        const unsigned long long o = (unsigned long long)hi << 32 | lo;
-        v = o < v ? o : v;
-    }
-    return v;
-}
+}  // namespace
+}  // namespace rdl
+// The device library's wave reduction (DPP; every lane must be active).
+extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_min_u64(unsigned long long);
+namespace rdl {
+namespace {
+__device__ __forceinline__ unsigned long long wave_min64(unsigned long long v) { return __ockl_wfred_min_u64(v); }
 
 __device__ __forceinline__ void put_be16(uint8_t *p, int v) {
     p[0] = (uint8_t)(v >> 8);
@@ -158,61 +159,72 @@ __device__ __forceinline__ void put_be16(uint8_t *p, int v) {
 }
 
 __global__ __launch_bounds__(256) void k_jpg_tables(JpgArgs a) {
-    __shared__ uint64_t s_f[4][260];
-    __shared__ int s_cs[4][260], s_grp[4][260];
+    __shared__ int s_cs[4][256];
     __shared__ int s_nb[4][34];
     __shared__ uint8_t s_hv[4][256];
     __shared__ int s_n[4];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;  // table w: t = w >> 1, ac = w & 1
     const int t = w >> 1, ac = w & 1;
-    for (int i = lane; i < 257; i += 64) {
-        s_f[w][i] = i < 256 ? a.ws->cnt[t][ac][i] : 1u;
-        s_cs[w][i] = 0;
-        s_grp[w][i] = i;
+    // Lane l holds symbols l + 64 j (j < 5; symbol 256 is the reserved point):
+    // count, group label and code size in registers.
+    uint64_t f[5];
+    int grp[5], cs[5];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        const int i = lane + 64 * j;
+        f[j] = i < 256 ? a.ws->cnt[t][ac][i] : (i == 256 ? 1u : 0u);
+        grp[j] = i;
+        cs[j] = 0;
     }
     for (int i = lane; i < 34; i += 64) s_nb[w][i] = 0;
-    __builtin_amdgcn_wave_barrier();
-    __syncthreads();
     // Figure K.1
     for (;;) {
         unsigned long long k1 = ~0ull;
-        for (int i = lane; i < 257; i += 64)
-            if (s_f[w][i]) {
-                const unsigned long long key = s_f[w][i] << 9 | (uint64_t)(511 - i);
-                k1 = key < k1 ? key : k1;
-            }
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            const unsigned long long key = f[j] << 9 | (uint64_t)(511 - (lane + 64 * j));
+            k1 = (f[j] && key < k1) ? key : k1;
+        }
         k1 = wave_min64(k1);
         const int v1 = 511 - (int)(k1 & 511);
         unsigned long long k2 = ~0ull;
-        for (int i = lane; i < 257; i += 64)
-            if (s_f[w][i] && i != v1) {
-                const unsigned long long key = s_f[w][i] << 9 | (uint64_t)(511 - i);
-                k2 = key < k2 ? key : k2;
-            }
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            const int i = lane + 64 * j;
+            const unsigned long long key = f[j] << 9 | (uint64_t)(511 - i);
+            k2 = (f[j] && i != v1 && key < k2) ? key : k2;
+        }
         k2 = wave_min64(k2);
         if (k2 == ~0ull) break;  // uniform
         const int v2 = 511 - (int)(k2 & 511);
-        const int g1 = s_grp[w][v1], g2 = s_grp[w][v2];
-        __builtin_amdgcn_wave_barrier();
-        for (int i = lane; i < 257; i += 64) {
-            const int gi = s_grp[w][i];
-            if (gi == g1 || gi == g2) {
-                s_cs[w][i] += 1;
-                s_grp[w][i] = g1;
+        // the group labels of v1 and v2 from their owner lanes
+        int l1 = 0, l2 = 0;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            l1 = (v1 >> 6) == j ? grp[j] : l1;
+            l2 = (v2 >> 6) == j ? grp[j] : l2;
+        }
+        const int g1 = __shfl(l1, v1 & 63, 64), g2 = __shfl(l2, v2 & 63, 64);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            const int i = lane + 64 * j;
+            if (grp[j] == g1 || grp[j] == g2) {
+                cs[j] += 1;
+                grp[j] = g1;
             }
+            if (i == v1) f[j] += k2 >> 9;
+            if (i == v2) f[j] = 0;
         }
-        if (lane == 0) {
-            s_f[w][v1] += s_f[w][v2];
-            s_f[w][v2] = 0;
-        }
-        __builtin_amdgcn_wave_barrier();
     }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s_cs[w][lane + 64 * j] = cs[j];
     __syncthreads();
     // sizes histogram, Figure K.3, the reserved point dropped
     if (lane == 0) {
         int *nb = s_nb[w];
-        for (int i = 0; i < 257; ++i)
+        for (int i = 0; i < 256; ++i)
             if (s_cs[w][i]) nb[min(s_cs[w][i], 32)] += 1;
+        if (cs[4]) nb[min(cs[4], 32)] += 1;  // the reserved point (symbol 256 is lane 0's fifth)
         for (int i = 32; i > 16; --i)
             while (nb[i] > 0) {
                 int j = i - 2;
@@ -226,20 +238,17 @@ __global__ __launch_bounds__(256) void k_jpg_tables(JpgArgs a) {
         while (i > 1 && nb[i] == 0) --i;
         if (nb[i] > 0) nb[i] -= 1;
     }
-    __syncthreads();
-    // Figure K.4: rank of each present symbol by (size, value); the symbol of
-    // rank r takes the r-th code of the bits[] list
+    // Figure K.4: symbols listed by (size, value), with ballots over 64-symbol
+    // chunks; the symbol of rank r takes the r-th code of the bits[] list
     int nsym = 0;
-    for (int i = 0; i < 256; ++i) nsym += s_cs[w][i] ? 1 : 0;
-    for (int s = lane; s < 256; s += 64) {
-        const int cs = s_cs[w][s];
-        if (!cs) continue;
-        int rank = 0;
-        for (int i = 0; i < 256; ++i) {
-            const int ci = s_cs[w][i];
-            rank += (ci && (ci < cs || (ci == cs && i < s))) ? 1 : 0;
+    for (int len = 1; len <= 32; ++len) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool in = cs[j] == len;
+            const unsigned long long m = __ballot(in);
+            if (in) s_hv[w][nsym + __popcll(m & ((1ull << lane) - 1ull))] = (uint8_t)(lane + 64 * j);
+            nsym += __popcll(m);
         }
-        s_hv[w][rank] = (uint8_t)s;
     }
     if (lane == 0) s_n[w] = nsym;
     __syncthreads();
@@ -377,20 +386,31 @@ __global__ void k_jpg_zero(JpgArgs a) {
 
 // Every block's bits at its offset: bit p of a scan is bit 7 - (p mod 8) of its
 // byte p / 8, so a 32-bit word of the raw buffer holds 4 bytes in memory order
-// (bits are ORed in byte-swapped).  The last block of a scan pads the last
-// byte with 1-bits.
-__device__ __forceinline__ void or_bits(uint32_t *raw, uint64_t pos, uint32_t v, int n) {
-    if (n == 0) return;
-    const uint64_t wi = pos >> 5;
-    const int sh = (int)(pos & 31);
-    if (sh + n <= 32) {
-        atomicOr(raw + wi, __builtin_bswap32(v << (32 - sh - n)));
-    } else {
-        const int n1 = 32 - sh, n2 = n - n1;
-        atomicOr(raw + wi, __builtin_bswap32(v >> n2));
-        atomicOr(raw + wi + 1, __builtin_bswap32(v << (32 - n2)));
+// (written byte-swapped).  A block builds its words in a register and stores
+// them; its first and last words may hold bits of the neighbouring blocks and
+// are ORed in instead.  The last block of a scan pads the last byte with 1-bits.
+struct WordOut {
+    uint32_t *raw;
+    uint64_t w;        // next word to write
+    uint64_t first;    // the block's first word (shared with the block before)
+    uint64_t acc;      // pending bits, the oldest at the top of the nacc low bits
+    int nacc;
+    __device__ __forceinline__ void put(uint32_t v, int n) {
+        if (n == 0) return;
+        acc = (acc << n) | v;
+        nacc += n;
+        if (nacc >= 32) {
+            const uint32_t word = (uint32_t)(acc >> (nacc - 32));
+            nacc -= 32;
+            if (w == first) atomicOr(raw + w, __builtin_bswap32(word));
+            else raw[w] = __builtin_bswap32(word);
+            ++w;
+        }
     }
-}
+    __device__ __forceinline__ void finish() {  // the last, partial word is shared with the next block
+        if (nacc > 0) atomicOr(raw + w, __builtin_bswap32((uint32_t)(acc << (32 - nacc))));
+    }
+};
 
 __global__ __launch_bounds__(JPG_BLK_WG) void k_jpg_emit(JpgArgs a) {
     __shared__ uint32_t s_code[2][256];
@@ -411,39 +431,47 @@ __global__ __launch_bounds__(JPG_BLK_WG) void k_jpg_emit(JpgArgs a) {
     uint32_t before = 0;
     for (int i = 0; i < wv; ++i) before += sh[i];
     if (k >= g.nblk) return;
-    uint64_t pos = a.woff[blockIdx.x] + before + inc - len;
-    uint32_t *raw = a.raw + a.ws->raw_word[c];
+    const uint64_t pos = a.woff[blockIdx.x] + before + inc - len;
+    WordOut o;
+    o.raw = a.raw + a.ws->raw_word[c];
+    o.w = o.first = pos >> 5;
+    o.acc = 0;
+    o.nacc = (int)(pos & 31);  // the block starts inside its first word: leading zero bits
     int v[64], pred;
     load_block(a, g, c, k, v, pred);
     block_symbols(v, pred, [&](int ac, int sym, uint32_t extra, int n) {
         const uint32_t cs = s_code[ac][sym];
-        const int cl = (int)(cs >> 16);
-        or_bits(raw, pos, cs & 0xFFFFu, cl);
-        pos += cl;
-        or_bits(raw, pos, extra, n);
-        pos += n;
+        o.put(cs & 0xFFFFu, (int)(cs >> 16));
+        o.put(extra, n);
     });
-    if (k == g.nblk - 1 && (pos & 7)) {
-        const int pad = 8 - (int)(pos & 7);
-        or_bits(raw, pos, (1u << pad) - 1u, pad);
+    if (k == g.nblk - 1 && ((pos + len) & 7)) {
+        const int pad = 8 - (int)((pos + len) & 7);
+        o.put((1u << pad) - 1u, pad);
     }
+    o.finish();
 }
 
 // 0xFF bytes per chunk of JPG_CHUNK raw bytes of each scan.
+// (A fixed grid walks the chunks that hold data.)
 __global__ __launch_bounds__(256) void k_jpg_ffcount(JpgArgs a) {
     __shared__ uint32_t sh[4];
-    const int c = blockIdx.x / a.cpc, j = blockIdx.x - c * a.cpc;
-    const uint64_t nbytes = (a.ws->bits[c] + 7) / 8;
-    const uint8_t *raw = reinterpret_cast<const uint8_t *>(a.raw + a.ws->raw_word[c]);
-    uint32_t n = 0;
-    for (int i = threadIdx.x; i < JPG_CHUNK; i += 256) {
-        const uint64_t b = (uint64_t)j * JPG_CHUNK + i;
-        if (b < nbytes && raw[b] == 0xFF) ++n;
+    for (int c = 0; c < 3; ++c) {
+        const uint64_t nbytes = (a.ws->bits[c] + 7) / 8;
+        const int64_t nch = (int64_t)((nbytes + JPG_CHUNK - 1) / JPG_CHUNK);
+        const uint8_t *raw = reinterpret_cast<const uint8_t *>(a.raw + a.ws->raw_word[c]);
+        for (int64_t j = blockIdx.x; j < nch; j += gridDim.x) {
+            uint32_t n = 0;
+            for (int i = threadIdx.x; i < JPG_CHUNK; i += 256) {
+                const uint64_t b = (uint64_t)j * JPG_CHUNK + i;
+                if (b < nbytes && raw[b] == 0xFF) ++n;
+            }
+            for (int off = 32; off > 0; off >>= 1) n += __shfl_xor(n, off, 64);
+            __syncthreads();
+            if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = n;
+            __syncthreads();
+            if (threadIdx.x == 0) a.ffcnt[c * a.cpc + j] = sh[0] + sh[1] + sh[2] + sh[3];
+        }
     }
-    for (int off = 32; off > 0; off >>= 1) n += __shfl_xor(n, off, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = n;
-    __syncthreads();
-    if (threadIdx.x == 0) a.ffcnt[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
 // Where every chunk's bytes go in the file; SOS headers, EOI, the length.
@@ -468,9 +496,10 @@ __global__ __launch_bounds__(1024) void k_jpg_layout(JpgArgs a) {
             s_carry = 0;
         }
         __syncthreads();
-        for (int b = 0; b < a.cpc; b += 1024) {
+        const int nch = (int)((nbytes + JPG_CHUNK - 1) / JPG_CHUNK);
+        for (int b = 0; b < nch; b += 1024) {
             const int i = b + threadIdx.x;
-            const uint32_t v = i < a.cpc ? a.ffcnt[c * a.cpc + i] : 0u;
+            const uint32_t v = i < nch ? a.ffcnt[c * a.cpc + i] : 0u;
             const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
             uint32_t inc = v;
             for (int off = 1; off < 64; off <<= 1) {
@@ -485,7 +514,7 @@ __global__ __launch_bounds__(1024) void k_jpg_layout(JpgArgs a) {
                 tot += sh[k];
             }
             // file position of chunk i's first byte: scan start + bytes before + stuffed zeros before
-            if (i < a.cpc) a.cpos[c * a.cpc + i] = s_at + (uint64_t)i * JPG_CHUNK + s_carry + before + inc - v;
+            if (i < nch) a.cpos[c * a.cpc + i] = s_at + (uint64_t)i * JPG_CHUNK + s_carry + before + inc - v;
             __syncthreads();
             if (threadIdx.x == 0) s_carry += tot;
             __syncthreads();
@@ -499,36 +528,43 @@ __global__ __launch_bounds__(1024) void k_jpg_layout(JpgArgs a) {
     }
 }
 
-// Raw bytes of a chunk into the file, a 0x00 after each 0xFF (16 per thread).
+// Raw bytes of a chunk into the file, a 0x00 after each 0xFF (16 per thread;
+// a fixed grid walks the chunks that hold data).
 __global__ __launch_bounds__(256) void k_jpg_stuff(JpgArgs a) {
     __shared__ uint32_t sh[4];
-    const int c = blockIdx.x / a.cpc, j = blockIdx.x - c * a.cpc;
-    const uint64_t nbytes = (a.ws->bits[c] + 7) / 8;
-    const uint8_t *raw = reinterpret_cast<const uint8_t *>(a.raw + a.ws->raw_word[c]);
-    const uint64_t b0 = (uint64_t)j * JPG_CHUNK + (uint64_t)threadIdx.x * 16;
-    uint8_t by[16];
-    uint32_t n = 0;
+    for (int c = 0; c < 3; ++c) {
+        const uint64_t nbytes = (a.ws->bits[c] + 7) / 8;
+        const int64_t nch = (int64_t)((nbytes + JPG_CHUNK - 1) / JPG_CHUNK);
+        const uint8_t *raw = reinterpret_cast<const uint8_t *>(a.raw + a.ws->raw_word[c]);
+        for (int64_t j = blockIdx.x; j < nch; j += gridDim.x) {
+            const uint64_t b0 = (uint64_t)j * JPG_CHUNK + (uint64_t)threadIdx.x * 16;
+            uint8_t by[16];
+            uint32_t n = 0;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        by[i] = b0 + i < nbytes ? raw[b0 + i] : 0;
-        n += (b0 + i < nbytes && by[i] == 0xFF) ? 1u : 0u;
-    }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    uint32_t inc = n;
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(inc, off, 64);
-        if (lane >= off) inc += y;
-    }
-    if (lane == 63) sh[wv] = inc;
-    __syncthreads();
-    uint32_t before = 0;
-    for (int i = 0; i < wv; ++i) before += sh[i];
-    uint64_t at = a.cpos[blockIdx.x] + (uint64_t)threadIdx.x * 16 + before + inc - n;
+            for (int i = 0; i < 16; ++i) {
+                by[i] = b0 + i < nbytes ? raw[b0 + i] : 0;
+                n += (b0 + i < nbytes && by[i] == 0xFF) ? 1u : 0u;
+            }
+            const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+            uint32_t inc = n;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(inc, off, 64);
+                if (lane >= off) inc += y;
+            }
+            __syncthreads();
+            if (lane == 63) sh[wv] = inc;
+            __syncthreads();
+            uint32_t before = 0;
+            for (int i = 0; i < wv; ++i) before += sh[i];
+            uint64_t at = a.cpos[c * a.cpc + j] + (uint64_t)threadIdx.x * 16 + before + inc - n;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        if (b0 + i >= nbytes) break;
-        a.out[at++] = by[i];
-        if (by[i] == 0xFF) a.out[at++] = 0;
+            for (int i = 0; i < 16; ++i) {
+                if (b0 + i < nbytes) {
+                    a.out[at++] = by[i];
+                    if (by[i] == 0xFF) a.out[at++] = 0;
+                }
+            }
+        }
     }
 }
 
@@ -543,9 +579,10 @@ void launch_jpeg(const JpgArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_jpg_offsets, dim3(1), dim3(1024), 0, s, a);
     hipLaunchKernelGGL(k_jpg_zero, dim3(1024), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_jpg_emit, dim3(3 * wpc), dim3(JPG_BLK_WG), 0, s, a);
-    hipLaunchKernelGGL(k_jpg_ffcount, dim3(3 * a.cpc), dim3(256), 0, s, a);
+    const int sgrid = (int)std::min<int64_t>(a.cpc, 1024);
+    hipLaunchKernelGGL(k_jpg_ffcount, dim3(sgrid), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_jpg_layout, dim3(1), dim3(1024), 0, s, a);
-    hipLaunchKernelGGL(k_jpg_stuff, dim3(3 * a.cpc), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_jpg_stuff, dim3(sgrid), dim3(256), 0, s, a);
 }
 
 }  // namespace rdl
