@@ -352,7 +352,7 @@ def main():
         ks = codec.stage_keystat(d)
         s_ref, _, dct = codec.stage_tmo_base(d, q, ks, want_dct=True)
         # the base layer as a JPEG file (baseline, optimised Huffman tables)
-        jbuf = torch.empty(int(codec._L.rdl_jpeg_bound(H, W)), dtype=torch.uint8, device="cuda")
+        jbuf = torch.empty(codec.jpeg_bound(H, W), dtype=torch.uint8, device="cuda")
         jlen = torch.zeros(1, dtype=torch.int64, device="cuda")
         for _ in range(3):
             codec.jpeg_encode_into(dct, H, W, q, jbuf, jlen)

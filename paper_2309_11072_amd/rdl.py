@@ -273,9 +273,12 @@ class Codec:
         _chk(self._L.rdl_jpeg_encode(self._h, _ptr(dct), H, W, int(q), _ptr(out), out.numel(), _ptr(out_len),
                                      _stream(stream)), "rdl_jpeg_encode")
 
+    def jpeg_bound(self, H: int, W: int) -> int:
+        return int(self._L.rdl_jpeg_bound(H, W))
+
     def jpeg_encode(self, dct: torch.Tensor, H: int, W: int, q: int, stream=None) -> torch.Tensor:
         """The JFIF file (uint8 device tensor, trimmed; synchronises)."""
-        out = torch.empty(int(self._L.rdl_jpeg_bound(H, W)), dtype=torch.uint8, device=dct.device)
+        out = torch.empty(self.jpeg_bound(H, W), dtype=torch.uint8, device=dct.device)
         n = torch.zeros(1, dtype=torch.int64, device=dct.device)
         self.jpeg_encode_into(dct, H, W, q, out, n, stream)
         return out[:int(n.item())]

@@ -105,3 +105,12 @@ def test_entropy_bound_and_argument_checks_host_only(O):
         assert L.rdl_ent_bound(H, W, k) == 0
     assert L.rdl_ent_encode(None, None, 3, 3, 8, None, 0, None, None) == rdl.RDL_EINVAL
     assert L.rdl_ent_decode(None, None, 0, None, 3, 3, None, None, None) == rdl.RDL_EINVAL
+
+
+def test_jpeg_bound_host_only():
+    rdl, L = _lib()
+    assert L.rdl_jpeg_bound(0, 5) == 0 and L.rdl_jpeg_bound(70000, 5) == 0 and L.rdl_jpeg_bound(5, 65536) == 0
+    # 1024 header bytes, then per scan a 10-byte SOS and twice the most bytes of its blocks, then EOI
+    assert L.rdl_jpeg_bound(8, 8) == 1024 + 3 * (10 + 2 * 256) + 2
+    assert L.rdl_jpeg_encode(None, None, 8, 8, 75, None, 0, None, None) == rdl.RDL_EINVAL
+    assert L.rdl_set_gf(None, 1) == rdl.RDL_EINVAL and L.rdl_decode_batch(None, None, 0, None) == rdl.RDL_EINVAL

@@ -201,3 +201,88 @@ def test_learned_reservation_stays_in_bucket():
             assert start[e] <= k < start[e] + ne[e] and k < H * W
             hit[k] += 1
     assert np.all(hit == 1)
+
+
+# ---------------------------------------------------------------- JPEG writer: word ownership
+def jpeg_emit_words(lengths):
+    """Model of k_jpg_emit's stores: block b covers bits [pos_b, pos_b + len_b);
+    it ORs its first word and its last partial word and plain-stores the words
+    it fills completely past its first.  Returns (plain, ored) lists of
+    (block, word)."""
+    plain, ored = [], []
+    pos = 0
+    for b, n in enumerate(lengths):
+        first = pos >> 5
+        nacc = pos & 31
+        w = first
+        for _ in range(n):  # bit by bit: a word goes out when 32 bits are pending
+            nacc += 1
+            if nacc == 32:
+                (ored if w == first else plain).append((b, w))
+                w += 1
+                nacc = 0
+        if nacc:
+            ored.append((b, w))
+        pos += n
+    return plain, ored, pos
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_jpeg_emit_plain_stores_are_exclusive(seed):
+    """Every plain-stored word lies wholly inside one block's bit range (no
+    other block touches it), and every word of the scan is written; shared
+    words are only ever ORed."""
+    rng = np.random.default_rng(seed)
+    lengths = list(rng.integers(0, 120, int(rng.integers(1, 60))))
+    lengths[int(rng.integers(len(lengths)))] = 0  # a block of no bits (the encoder makes none) is harmless too
+    plain, ored, total = jpeg_emit_words(lengths)
+    owners = {}
+    for b, w in plain + ored:
+        owners.setdefault(w, []).append(b)
+    starts = np.concatenate([[0], np.cumsum(lengths)])
+    for b, w in plain:
+        assert starts[b] <= 32 * w and 32 * (w + 1) <= starts[b + 1], "plain store outside its block"
+        assert owners[w] == [b], "a plain-stored word is touched by another block"
+    assert set(owners) == set(range((total + 31) // 32)), "every word of the scan is written"
+
+
+# ---------------------------------------------------------------- entropy decoder: ring of words
+def test_entropy_decoder_ring_reads_stay_inside():
+    """Model of k_ent_dec's ring: words [b, b + 512) in LDS, the next 256 in
+    registers; before a step, pos >= b + 256 moves b by 256.  For any sequence
+    of per-step consumptions (0..64 words), every word a step reads was put in
+    the ring and not overwritten."""
+    rng = np.random.default_rng(7)
+    for trial in range(200):
+        w0 = int(rng.integers(0, 1000))
+        b = pos = w0 + 128
+        ring_lo, ring_hi = b, b + 512          # words currently held
+        for step in range(400):
+            if pos >= b + 256:
+                b += 256
+                ring_lo, ring_hi = b, b + 512
+            k = int(rng.integers(0, 65)) if trial % 2 else int(rng.choice([0, 64]))
+            assert ring_lo <= pos and pos + k <= ring_hi, (trial, step, pos, k, b)
+            pos += k
+
+
+# ---------------------------------------------------------------- enhancement decoder: wide accesses
+@pytest.mark.parametrize("W", [4, 8, 12, 256, 260, 1024, 3840])
+@pytest.mark.parametrize("H", [1, 3, 17])
+def test_decode_wide_accesses_stay_inside(H, W):
+    """k_decode reads 4 exponent bytes and 3 x 8 residual bytes per lane and
+    row, and stores 16 bytes of RGBE, only when W % 4 == 0 and the lane's four
+    pixels are inside: every such access lies inside its plane and row and
+    on its alignment."""
+    npx = H * W
+    assert W % 4 == 0
+    for y in range(H):
+        for x in range(0, W, 4):
+            off = y * W + x
+            e_byte = 6 * npx + off
+            assert e_byte % 4 == 0 and e_byte + 4 <= 7 * npx
+            for c in range(3):
+                r_byte = 2 * (c * npx + off)
+                assert r_byte % 8 == 0 and r_byte + 8 <= 2 * (c + 1) * npx
+            o_byte = 4 * off
+            assert o_byte % 16 == 0 and o_byte + 16 <= 4 * npx
