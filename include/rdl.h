@@ -168,6 +168,9 @@ typedef struct rdl_image {
     uint8_t *sdr;
     rdl_header *hdr;
     void *resid;
+    int16_t *dct;  /* optional (may be NULL): also the base layer's quantised
+                      coefficients, int16 [3][H8][W8] as rdl_stage_tmo_base
+                      writes them (for rdl_jpeg_encode); 2-byte aligned */
 } rdl_image;
 int rdl_encode_batch(rdl_ctx *ctx, const rdl_image *imgs, int n, void *stream);
 

@@ -268,9 +268,10 @@ int check_launch(const char *what) {
 
 // Enqueue the full encoder for the images of d (device table) on s.  The
 // scratch accumulators are zero on entry and k_solve leaves them zero.
-void enqueue_encode(const ImgDesc *d, int n, const Grid &g, bool learned, hipStream_t s, bool gf = true) {
+void enqueue_encode(const ImgDesc *d, int n, const Grid &g, bool learned, hipStream_t s, bool gf = true,
+                    bool dct = false) {
     launch_keystat(d, n, g.px, s);
-    launch_tmo_base(d, n, g.blk, false, s);
+    launch_tmo_base(d, n, g.blk, dct, s);
     launch_fit_sums(d, n, g.fit, g.fit_bins, g.fit_waves, s, gf);
     launch_solve(d, n, s);
     if (learned) {
@@ -409,6 +410,7 @@ int rdl_encode_enh(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int q, uint8_t
     im.sdr = out_sdr;
     im.hdr = out_coeffs;
     im.resid = out_resid;
+    im.dct = nullptr;
     return rdl_encode_batch(c, &im, 1, stream);
 }
 
@@ -418,9 +420,12 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
         const rdl_image &m = imgs[k];
         if (!m.rgbe || !m.sdr || !m.hdr || !m.resid) return RDL_EINVAL;
         if (!size_ok(m.H, m.W) || m.q < 1 || m.q > 100) return RDL_EINVAL;
-        if (!aligned4(m.rgbe) || !aligned4(m.sdr) || !aligned4(m.hdr) || (reinterpret_cast<uintptr_t>(m.resid) & 1))
+        if (!aligned4(m.rgbe) || !aligned4(m.sdr) || !aligned4(m.hdr) || (reinterpret_cast<uintptr_t>(m.resid) & 1) ||
+            (reinterpret_cast<uintptr_t>(m.dct) & 1))
             return RDL_EINVAL;
     }
+    bool any_dct = false;
+    for (int k = 0; k < n; ++k) any_dct = any_dct || imgs[k].dct;
     const bool learned = c->estimator == 1;
     if (learned && (!c->d_model || !c->gf)) return RDL_EUNSUPPORTED;
     const int32_t mode = (c->estimator == 2 ? F_EST_GLOBAL : c->estimator == 3 ? F_EST_IDENT : 0) | (c->gf ? 0 : F_NOGF);
@@ -433,6 +438,7 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
         d.sdr = imgs[k].sdr;
         d.hdr = imgs[k].hdr;
         d.resid = (uint8_t *)imgs[k].resid;
+        d.dct = imgs[k].dct;
         d.H = imgs[k].H;
         d.W = imgs[k].W;
         d.q = imgs[k].q;
@@ -467,7 +473,7 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
         p = &c->plans.back();
     }
     if (c->launch_mode == RDL_LAUNCH_DIRECT) {
-        enqueue_encode(p->d_desc, n, gr, learned, s, c->gf);
+        enqueue_encode(p->d_desc, n, gr, learned, s, c->gf, any_dct);
         return check_launch("encoder kernels");
     }
     if (!p->exec) {
@@ -476,7 +482,7 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
         hipGraph_t graph;
         hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (err == hipSuccess) {
-            enqueue_encode(p->d_desc, n, gr, learned, cs, c->gf);
+            enqueue_encode(p->d_desc, n, gr, learned, cs, c->gf, any_dct);
             err = hipStreamEndCapture(cs, &graph);
         }
         if (err == hipSuccess) {

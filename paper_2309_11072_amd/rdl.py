@@ -85,7 +85,7 @@ KERNELS = ("k_keystat", "k_tmo_base", "k_fit_sums", "k_solve", "k_resid")
 
 class RdlImage(C.Structure):
     _fields_ = [("rgbe", C.c_void_p), ("H", C.c_int32), ("W", C.c_int32), ("q", C.c_int32),
-                ("sdr", C.c_void_p), ("hdr", C.c_void_p), ("resid", C.c_void_p)]
+                ("sdr", C.c_void_p), ("hdr", C.c_void_p), ("resid", C.c_void_p), ("dct", C.c_void_p)]
 
 
 class RdlDImage(C.Structure):
@@ -228,11 +228,14 @@ class Codec:
         return sdr, hdr, resid
 
     def encode_batch(self, items, stream=None):
-        """items: list of (rgbe, q, sdr, hdr, resid) device tensors."""
+        """items: list of (rgbe, q, sdr, hdr, resid) or (rgbe, q, sdr, hdr, resid, dct)
+        device tensors (dct: the base layer's quantised coefficients, also written)."""
         arr = (RdlImage * len(items))()
-        for k, (rgbe, q, sdr, hdr, resid) in enumerate(items):
+        for k, it in enumerate(items):
+            rgbe, q, sdr, hdr, resid = it[:5]
+            dct = it[5] if len(it) > 5 else None
             arr[k] = RdlImage(_ptr(rgbe), int(rgbe.shape[0]), int(rgbe.shape[1]), int(q), _ptr(sdr), _ptr(hdr),
-                              _ptr(resid))
+                              _ptr(resid), _ptr(dct))
         _chk(self._L.rdl_encode_batch(self._h, arr, len(items), _stream(stream)), "rdl_encode_batch")
 
     def decode_batch(self, items, stream=None):
@@ -272,6 +275,15 @@ class Codec:
         assert out.dtype == torch.uint8 and out_len.dtype == torch.int64 and out_len.numel() == 1
         _chk(self._L.rdl_jpeg_encode(self._h, _ptr(dct), H, W, int(q), _ptr(out), out.numel(), _ptr(out_len),
                                      _stream(stream)), "rdl_jpeg_encode")
+
+    def encode_files(self, rgbe: torch.Tensor, q: int, log2_k: int = 8, stream=None):
+        """The dual-layer files of one image: (JPEG file of the base layer, device
+        header, entropy-coded enhancement layer); synchronises."""
+        H, W = int(rgbe.shape[0]), int(rgbe.shape[1])
+        sdr, hdr, resid = self.alloc_outputs(H, W)
+        dct = torch.empty((3, (H + 7) // 8 * 8, (W + 7) // 8 * 8), dtype=torch.int16, device=rgbe.device)
+        self.encode_batch([(rgbe, q, sdr, hdr, resid, dct)], stream)
+        return self.jpeg_encode(dct, H, W, q, stream), hdr, self.ent_encode(resid, H, W, log2_k, stream)
 
     def jpeg_bound(self, H: int, W: int) -> int:
         return int(self._L.rdl_jpeg_bound(H, W))

@@ -73,3 +73,30 @@ def test_full_size_3840x2160(codec, O):
     _say("jpeg 3840x2160")
     n = check(codec, O, sp.H, sp.W, sp.q, sp.seed)
     _say("bytes", n, "bits/px %.3f" % (8 * n / (sp.H * sp.W)))
+
+
+def test_batched_encoder_writes_the_coefficients(codec, O):
+    """rdl_image.dct: the batched encoder also writes the quantised
+    coefficients, equal to the stage kernel's, and leaves S and the layer
+    unchanged; encode_files returns the JPEG file and the coded layer."""
+    specs = [(61, 83, 75), (217, 301, 40), (8, 8, 95), (480, 641, 60)]
+    items, ref = [], []
+    for k, (H, W, q) in enumerate(specs):
+        x = synth.generate(H, W, 3.5, seed=600 + k, spec_frac=0.05)
+        d = torch.from_numpy(x).cuda()
+        sdr, hdr, resid = codec.alloc_outputs(H, W)
+        dct = torch.full((3, (H + 7) // 8 * 8, (W + 7) // 8 * 8), 12345, dtype=torch.int16, device="cuda")
+        items.append((d, q, sdr, hdr, resid, dct))
+        s2, h2, r2 = codec.encode_enh(d, q)
+        ks = codec.stage_keystat(d)
+        _, _, dct_ref = codec.stage_tmo_base(d, q, ks, want_dct=True)
+        ref.append((s2.clone(), r2.clone(), dct_ref))
+    codec.encode_batch(items)
+    torch.cuda.synchronize()
+    for (d, q, sdr, hdr, resid, dct), (s2, r2, dref) in zip(items, ref):
+        assert torch.equal(dct, dref) and torch.equal(sdr, s2) and torch.equal(resid, r2)
+    d, q = items[1][0], items[1][1]
+    H, W = d.shape[:2]
+    jpg, hdr, code = codec.encode_files(d, q)
+    assert jpg.cpu().numpy().tobytes() == O.jpeg_write(items[1][5].cpu().numpy(), H, W, q)
+    assert torch.equal(codec.ent_decode(code, H, W), items[1][4])
