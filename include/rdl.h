@@ -282,7 +282,10 @@ int rdl_jpeg_encode(rdl_ctx *ctx, const int16_t *dct, int H, int W, int q, uint8
  *
  * Planes p = 0, 1, 2: the residuals of channel R, G, B as symbols r + 255
  * (511 symbols); p = 3: the exponents (256 symbols); each N = H W symbols in
- * raster order.  Frequencies of a plane from its counts h (P symbols present):
+ * raster order.  With flags bit 0 set, plane 3 holds the exponents' left
+ * differences instead, (E[y][x] - E[y][x-1]) mod 256 with E[y][0] itself:
+ * the shared exponent is smooth, so these are mostly 0 (the residuals, close
+ * to white, are never differenced).  Frequencies of a plane from its counts h (P symbols present):
  * f[s] = 1 + floor(h[s] (M - P) / N) where h[s] > 0, else 0; the smallest
  * symbol of the largest count takes the remainder M - sum f.
  *
@@ -297,7 +300,7 @@ int rdl_jpeg_encode(rdl_ctx *ctx, const int16_t *dct, int H, int W, int q, uint8
  * 64 x 32 bits of states, i.e. 32 / K bits per symbol.
  *
  * Stream, little-endian: u32 magic 0x454C4452 ("RDLE"), u32 version 1,
- * i32 H, i32 W, i32 log2_k, i32 prob_bits (15), u32 G, u32 0, u64 total bytes,
+ * i32 H, i32 W, i32 log2_k, i32 prob_bits (15), u32 G, u32 flags (0 or 1), u64 total bytes,
  * u16 freq[4][512] (entries past a plane's alphabet 0) -- RDL_ENT_HEADER_BYTES
  * in all -- then u64 start[4][G] (first word of each group, counted from the
  * payload), then the payload of u16 words, groups in plane-major order.
@@ -307,14 +310,20 @@ int rdl_jpeg_encode(rdl_ctx *ctx, const int16_t *dct, int H, int W, int q, uint8
  * goes to *out_len (DEVICE u64, 8-byte aligned).  A residual outside
  * [-255, 255] yields a stream with magic 0 and *out_len = 0.  The context
  * keeps a workspace sized for the largest layer seen (the plane histograms,
- * the coder tables and every group's words before they are put in order,
- * about 8 bytes per pixel; allocated synchronously when it grows), so calls on
- * one context must not overlap.  rdl_ent_bound is 0 for bad sizes.
+ * the coder tables, every group's words before they are put in order and the
+ * exponents' differences, about 9 bytes per pixel; allocated synchronously
+ * when it grows), so calls on one context must not overlap.  rdl_ent_bound is
+ * 0 for bad sizes.  rdl_set_ent_predict(ctx, 1) (the default) makes the
+ * encoder set flags bit 0; 0 codes the exponents as they are; RDL_EINVAL for
+ * another value.
  *
  * rdl_ent_decode: code (device, 8-byte aligned, len bytes) and a HOST copy of
  * its first RDL_ENT_HEADER_BYTES bytes, which is validated first (magic,
  * version, sizes, log2_k, G, frequency sums, total <= len: RDL_ECORRUPT) ->
- * out_resid (device, rdl_resid_bytes(H, W), 2-byte aligned).  If status
+ * out_resid (device, rdl_resid_bytes(H, W), 2-byte aligned); a stream with
+ * flags bit 0 uses the context's workspace (8 bytes per 4096 pixels) to sum
+ * the differences back, so it must not overlap other calls on the context
+ * either.  If status
  * (device int32, may be NULL) is given it receives RDL_OK, or RDL_ECORRUPT
  * when the device copy's tables or a group's offsets or words do not decode
  * exactly (every read stays inside the stream). */
@@ -324,6 +333,7 @@ int rdl_ent_encode(rdl_ctx *ctx, const void *resid, int H, int W, int log2_k, vo
                    uint64_t *out_len, void *stream);
 int rdl_ent_decode(rdl_ctx *ctx, const void *code, size_t len, const void *header, int H, int W,
                    void *out_resid, int32_t *status, void *stream);
+int rdl_set_ent_predict(rdl_ctx *ctx, int on);
 
 /* ---- Stage entry points (each is one step of rdl_encode_enh, for checks) ---- */
 

@@ -84,7 +84,7 @@ def lib():
         L.oracle_ent_freqs.restype = C.c_int
         L.oracle_ent_bound.argtypes = [C.c_int, C.c_int, C.c_int]
         L.oracle_ent_bound.restype = i64
-        L.oracle_ent_encode.argtypes = [vp, C.c_int, C.c_int, C.c_int, vp, i64]
+        L.oracle_ent_encode.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, vp, i64]
         L.oracle_ent_encode.restype = i64
         L.oracle_ent_decode.argtypes = [vp, i64, C.c_int, C.c_int, vp]
         L.oracle_ent_decode.restype = C.c_int
@@ -347,12 +347,13 @@ def ent_bound(H: int, W: int, log2_k: int = 8) -> int:
     return int(lib().oracle_ent_bound(H, W, log2_k))
 
 
-def ent_encode(resid: np.ndarray, H: int, W: int, log2_k: int = 8) -> bytes:
-    """Code stream of an enhancement layer (7 H W bytes)."""
+def ent_encode(resid: np.ndarray, H: int, W: int, log2_k: int = 8, predict: bool = True) -> bytes:
+    """Code stream of an enhancement layer (7 H W bytes); predict codes the
+    exponent plane as differences from the left neighbour."""
     buf = np.ascontiguousarray(resid).view(np.uint8).reshape(-1)
     assert buf.size == 7 * H * W
     out = np.zeros(max(ent_bound(H, W, log2_k), 1), np.uint8)
-    n = lib().oracle_ent_encode(_p(buf), H, W, log2_k, _p(out), out.size)
+    n = lib().oracle_ent_encode(_p(buf), H, W, log2_k, 1 if predict else 0, _p(out), out.size)
     if n < 0:
         raise ValueError("oracle_ent_encode failed with %d" % n)
     return out[:n].tobytes()

@@ -27,6 +27,13 @@
  * r + 255 (511 symbols); p = 3 holds the exponent E (256 symbols).  Each
  * plane is N = H W symbols in raster order.
  *
+ * Exponent prediction (flags bit 0): the shared exponent changes little from
+ * one pixel to the next, so plane 3 may instead hold the difference from the
+ * left neighbour, (E[y][x] - E[y][x-1]) mod 256, with E[y][x] itself at
+ * x = 0.  The residual planes are always coded as they are: they are close to
+ * white (the JPEG quantisation error of the base layer plus the estimator's),
+ * and differencing them raises their entropy.
+ *
  * Frequencies of a plane, from its counts h[s] (P symbols present, N total):
  *   f[s] = 0 where h[s] = 0, else 1 + floor(h[s] (M - P) / N);
  *   then the smallest s with the largest count takes the remainder M - sum f.
@@ -43,7 +50,7 @@
  *
  * Stream (little-endian):
  *   0 u32 magic 0x454C4452   4 u32 version 1    8 i32 H       12 i32 W
- *  16 i32 log2_k            20 i32 prob_bits 15 24 u32 G      28 u32 0
+ *  16 i32 log2_k            20 i32 prob_bits 15 24 u32 G      28 u32 flags (0 or 1)
  *  32 u64 total bytes       40 u16 freq[4][512]  (unused entries 0)
  *  4136 u64 start[4][G]: first word of each group, counted from the payload
  *  4136 + 32 G: payload, u16 words, groups in plane-major order.
@@ -68,9 +75,13 @@ static uint64_t get64(const uint8_t *p) { uint64_t v = 0; for (int k = 7; k >= 0
 static uint32_t get16(const uint8_t *p) { return (uint32_t)p[0] | (uint32_t)p[1] << 8; }
 
 /* Symbol i of plane p, or -1 when a residual lies outside [-255, 255]. */
-static int plane_sym(const uint8_t *resid, int64_t N, int p, int64_t i)
+static int plane_sym(const uint8_t *resid, int64_t N, int W, int flags, int p, int64_t i)
 {
-    if (p == 3) return resid[6 * N + i];
+    if (p == 3) {
+        const uint8_t *E = resid + 6 * N;
+        if (!(flags & 1) || i % W == 0) return E[i];
+        return (E[i] - E[i - 1]) & 255;
+    }
     int16_t r;
     memcpy(&r, resid + 2 * (p * N + i), 2);
     return (r < -255 || r > 255) ? -1 : r + 255;
@@ -112,13 +123,13 @@ int64_t oracle_ent_bound(int H, int W, int log2_k)
     return ENT_HDR + 32 * G + 2 * (4 * N + 4 * G * 128);
 }
 
-/* Encode the enhancement layer resid (int16 r[3][H][W], then uint8 E[H][W]).
- * Returns the stream length, -1 for bad arguments, -2 when cap is too small,
+/* Encode the enhancement layer resid (int16 r[3][H][W], then uint8 E[H][W]);
+ * flags bit 0 codes the exponents as left differences.  Returns the stream length, -1 for bad arguments, -2 when cap is too small,
  * -3 when a residual lies outside [-255, 255]. */
-int64_t oracle_ent_encode(const void *resid_v, int H, int W, int log2_k, uint8_t *out, int64_t cap)
+int64_t oracle_ent_encode(const void *resid_v, int H, int W, int log2_k, int flags, uint8_t *out, int64_t cap)
 {
     const uint8_t *resid = (const uint8_t *)resid_v;
-    if (!resid || !out || H < 1 || W < 1 || log2_k < 4 || log2_k > 12) return -1;
+    if (!resid || !out || H < 1 || W < 1 || log2_k < 4 || log2_k > 12 || (flags & ~1)) return -1;
     const int64_t N = (int64_t)H * W, Z = (int64_t)64 << log2_k, G = oracle_ent_groups(H, W, log2_k);
     if (cap < oracle_ent_bound(H, W, log2_k)) return -2;
     memset(out, 0, ENT_HDR + 32 * G);
@@ -127,7 +138,7 @@ int64_t oracle_ent_encode(const void *resid_v, int H, int W, int log2_k, uint8_t
     for (int p = 0; p < 4; p++) {
         int64_t h[512] = {0};
         for (int64_t i = 0; i < N; i++) {
-            int s = plane_sym(resid, N, p, i);
+            int s = plane_sym(resid, N, W, flags, p, i);
             if (s < 0) return -3;
             h[s]++;
         }
@@ -154,7 +165,7 @@ int64_t oracle_ent_encode(const void *resid_v, int H, int W, int log2_k, uint8_t
                 for (int j = 63; j >= 0; j--) {
                     const int64_t i = t * 64 + j;
                     if (i >= n) continue;
-                    const int s = plane_sym(resid, N, p, base + i);
+                    const int s = plane_sym(resid, N, W, flags, p, base + i);
                     const uint32_t fs = f[p][s];
                     if ((uint64_t)x[j] >= ((uint64_t)fs << 17)) {
                         emit[ne++] = (uint16_t)(x[j] & 0xFFFF);
@@ -181,7 +192,7 @@ int64_t oracle_ent_encode(const void *resid_v, int H, int W, int log2_k, uint8_t
     put32(out + 16, (uint32_t)log2_k);
     put32(out + 20, ENT_PB);
     put32(out + 24, (uint32_t)G);
-    put32(out + 28, 0);
+    put32(out + 28, (uint32_t)flags);
     put64(out + 32, (uint64_t)total);
     return total;
 }
@@ -200,6 +211,8 @@ int oracle_ent_decode(const uint8_t *st, int64_t len, int H, int W, void *resid_
     const int64_t total = (int64_t)get64(st + 32);
     if (get32(st + 24) != (uint32_t)G || total > len || total < ENT_HDR + 32 * G || (total - ENT_HDR - 32 * G) % 2)
         return -5;
+    const uint32_t flags = get32(st + 28);
+    if (flags > 1) return -5;
     const int64_t nwords = (total - ENT_HDR - 32 * G) / 2;
     uint32_t f[4][512], c[4][513];
     for (int p = 0; p < 4; p++) {
@@ -253,6 +266,11 @@ int oracle_ent_decode(const uint8_t *st, int64_t len, int H, int W, void *resid_
             for (int j = 0; j < 64; j++)
                 if (x[j] != ENT_L) return -6;
         }
+    }
+    if (flags & 1) {  /* undo the left differences, row by row */
+        uint8_t *E = resid + 6 * N;
+        for (int64_t i = 0; i < N; i++)
+            if (i % W) E[i] = (uint8_t)(E[i - 1] + E[i]);
     }
     return 0;
 }

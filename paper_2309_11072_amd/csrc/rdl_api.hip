@@ -45,6 +45,7 @@ struct rdl_ctx {
     uint64_t model_hash = 0;
     int estimator = 0;  // 0 SLR per region, 1 learned, 2 one line per channel, 3 M* = S
     bool gf = true;     // Gaussian-filter restoration of S before the estimate
+    bool ent_pred = true;  // entropy code: exponents as left differences
     // entropy coder workspace (EntWs, then group word counts and words)
     uint8_t *d_ent = nullptr;
     size_t ent_cap = 0;
@@ -626,6 +627,9 @@ int rdl_ent_encode(rdl_ctx *c, const void *resid, int H, int W, int log2_k, void
     a.resid = (const uint8_t *)resid;
     a.out = (uint8_t *)out;
     a.out_len = out_len;
+    a.flags = c->ent_pred ? 1 : 0;
+    a.ediff = c->d_ent + ent_ediff_off(H, W, log2_k) + ((reinterpret_cast<uintptr_t>(resid) + 6 * a.N) & 15);
+    a.eplane = a.flags ? a.ediff : a.resid + 6 * a.N;
     launch_ent_encode(a, (hipStream_t)stream);
     return check_launch("k_ent_encode");
 }
@@ -645,7 +649,7 @@ int rdl_ent_decode(rdl_ctx *c, const void *code, size_t len, const void *header,
         return RDL_ECORRUPT;
     const int64_t G = ent_groups(H, W, log2_k);
     const uint64_t fixed = (uint64_t)ENT_HDR + 32 * (uint64_t)G;
-    if (w[6] != (uint32_t)G || total < fixed || total > len || (total - fixed) % 2) return RDL_ECORRUPT;
+    if (w[6] != (uint32_t)G || w[7] > 1u || total < fixed || total > len || (total - fixed) % 2) return RDL_ECORRUPT;
     for (int p = 0; p < 4; ++p) {
         uint32_t sum = 0;
         for (int s = 0; s < 512; ++s) {
@@ -657,7 +661,13 @@ int rdl_ent_decode(rdl_ctx *c, const void *code, size_t len, const void *header,
         if (sum != ENT_M) return RDL_ECORRUPT;
     }
     DeviceGuard g(c->device);
+    if (w[7]) {
+        const int rc = ensure_ent(c, ent_dec_ws_bytes((int64_t)H * W));
+        if (rc) return rc;
+    }
     EntArgs a = ent_args(c, H, W, log2_k);
+    a.flags = (int32_t)w[7];
+    a.eagg = reinterpret_cast<uint32_t *>(c->d_ent + ent_cnt_off());
     a.code = (const uint8_t *)code;
     a.dst = (uint8_t *)out_resid;
     a.status = status;
@@ -1042,6 +1052,12 @@ int rdl_set_estimator(rdl_ctx *c, int mode) {
     if (!c || mode < 0 || mode > 3) return RDL_EINVAL;
     if (mode == 1 && !c->d_model) return RDL_EUNSUPPORTED;
     c->estimator = mode;
+    return RDL_OK;
+}
+
+int rdl_set_ent_predict(rdl_ctx *c, int on) {
+    if (!c || (on != 0 && on != 1)) return RDL_EINVAL;
+    c->ent_pred = on != 0;
     return RDL_OK;
 }
 

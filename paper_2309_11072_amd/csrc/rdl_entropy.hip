@@ -6,10 +6,13 @@
 // Sec. IV); this coder stands in for it.  The stream format is described in
 // rdl.h.
 //
-// Encoder: k_ent_hist (plane histograms) -> k_ent_freq (frequencies, header)
-// -> k_ent_enc (one wave per group, words in emission order into a workspace)
-// -> k_ent_scan (group offsets) -> k_ent_pack (each group's words reversed
-// into place).  Decoder: k_ent_dec (tables in LDS, one wave per group).
+// Encoder: [k_ent_ediff (left differences of the exponents)] -> k_ent_hist
+// (plane histograms) -> k_ent_freq (frequencies, header) -> k_ent_enc (one
+// wave per group, words in emission order into a workspace) -> k_ent_scan
+// (group offsets) -> k_ent_pack (each group's words reversed into place).
+// Decoder: k_ent_dec (tables in LDS, one wave per group) [-> k_ent_eseg,
+// k_ent_ecarry, k_ent_eundo: the differences summed back along each row, a
+// segmented prefix sum].
 // Everything is integer arithmetic except the encoder's division by a
 // frequency, which takes a float reciprocal estimate and corrects it to the
 // exact quotient.
@@ -127,7 +130,7 @@ __global__ __launch_bounds__(ENT_HIST_THREADS) void k_ent_hist(EntArgs a) {
             if (j * ENT_HIST_THREADS + (int)threadIdx.x < n)
                 ent_count(h, mine, p * 512 + min((uint32_t)(v[j] + 255), 511u), 1u);
     }
-    const uint8_t *e8 = a.resid + 6 * a.N + i0;
+    const uint8_t *e8 = a.eplane + i0;
     int ev[PER];
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
@@ -201,7 +204,7 @@ __global__ __launch_bounds__(ENT_HIST_THREADS) void k_ent_hist_vec(EntArgs a, in
             }
         }
     } else {
-        const uintptr_t e_lo = reinterpret_cast<uintptr_t>(a.resid) + 6 * N, e_hi = e_lo + N;
+        const uintptr_t e_lo = reinterpret_cast<uintptr_t>(a.eplane), e_hi = e_lo + N;
         const uintptr_t c_lo = e_lo & ~(uintptr_t)15;
         const int64_t nchunk = (int64_t)((e_hi & ~(uintptr_t)15) - c_lo) >> 4;  // whole chunks inside the layer
         const int wb = (int)blockIdx.x - nr;
@@ -288,7 +291,7 @@ __global__ __launch_bounds__(512) void k_ent_freq(EntArgs a) {
                          : s == 4 ? (uint32_t)a.log2_k
                          : s == 5 ? (uint32_t)ENT_PB
                          : s == 6 ? (uint32_t)a.G
-                                  : 0u;
+                                  : (uint32_t)a.flags;
         reinterpret_cast<uint32_t *>(a.out)[s] = v;
     }
 }
@@ -384,7 +387,7 @@ __global__ __launch_bounds__(256) void k_ent_enc(EntArgs a) {
     if (p < 3)
         enc_group<true>((const int16_t *)a.resid + p * a.N + base, n, stab[w], out, a.cnt + gi, lane, dummy);
     else
-        enc_group<false>(a.resid + 6 * a.N + base, n, stab[w], out, a.cnt + gi, lane, dummy);
+        enc_group<false>(a.eplane + base, n, stab[w], out, a.cnt + gi, lane, dummy);
 }
 
 // Group offsets (exclusive prefix sum of the word counts) into the stream's
@@ -565,10 +568,179 @@ __global__ __launch_bounds__(256) void k_ent_dec(EntArgs a) {
     if (__ballot(bad) && lane == 0 && a.status) atomicExch(a.status, RDL_ECORRUPT);
 }
 
+// ---- Left differences of the exponent plane (stream flag bit 0) ----------
+// Plane 3 may hold d = (E[i] - E[i-1]) mod 256, with d = E[i] at the first
+// pixel of a row.  The encoder writes d into its workspace; the decoder sums
+// d back along each row.  The plane is cut into the 16-byte aligned chunks
+// that cover it, one per lane (256 lanes per tile): with lead = the plane's
+// address mod 16, chunk t holds pixels [16 t - lead, + 16).  A chunk wholly
+// inside the plane moves with one 16-byte load or store, the (at most two)
+// others byte by byte, so no access leaves the plane.
+
+// Decoder.  A run of pixels is summarised by a segment value: the sum mod 256
+// of its d since the last row start inside it (or of all of them), in bits
+// 0-7, and bit 8 set when a row starts inside.  Joining run a then run b is
+// associative: b if a row starts in b, else the sums added with a's bit.  The
+// exponent before pixel i is then the value of the join of all runs before
+// it (its own row started inside them).
+__device__ __forceinline__ uint32_t seg_join(uint32_t a, uint32_t b) {
+    return (b & 256u) ? b : (((a + b) & 255u) | (a & 256u));
+}
+
+struct EChunk {
+    uint32_t v[16];  // the chunk's bytes (0 outside the plane)
+    int64_t i0;      // pixel index of byte 0 (negative in a leading partial chunk)
+    uint32_t col0;   // column of byte 0, as if the rows continued before pixel 0
+    bool full;       // all 16 bytes inside the plane
+};
+
+__device__ __forceinline__ void echunk_load(const uint8_t *e, int64_t N, int W, int64_t t, EChunk &c) {
+    const int lead = (int)(reinterpret_cast<uintptr_t>(e) & 15);
+    c.i0 = 16 * t - lead;
+    c.full = c.i0 >= 0 && c.i0 + 16 <= N;
+    // |i0| < 2^31: one 32-bit modulo; byte -i0 (pixel 0) then falls on column 0
+    const uint32_t m = (uint32_t)(c.i0 < 0 ? -c.i0 : c.i0) % (uint32_t)W;
+    c.col0 = c.i0 < 0 && m ? (uint32_t)W - m : m;
+    if (c.full) {
+        const uint4 q = *reinterpret_cast<const uint4 *>(e + c.i0);
+        const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int k = 0; k < 16; ++k) c.v[k] = (w4[k >> 2] >> (8 * (k & 3))) & 255u;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int64_t i = c.i0 + k;
+            c.v[k] = i >= 0 && i < N ? (uint32_t)e[i] : 0u;
+        }
+    }
+}
+
+__device__ __forceinline__ void echunk_store(uint8_t *e, int64_t N, const EChunk &c, const uint32_t (&o)[16]) {
+    if (c.full) {
+        uint32_t w4[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int k = 0; k < 16; ++k) w4[k >> 2] |= (o[k] & 255u) << (8 * (k & 3));
+        *reinterpret_cast<uint4 *>(e + c.i0) = make_uint4(w4[0], w4[1], w4[2], w4[3]);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int64_t i = c.i0 + k;
+            if (i >= 0 && i < N) e[i] = (uint8_t)o[k];
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t echunk_seg(const EChunk &c, int64_t N, int W) {
+    uint32_t seg = 0, col = c.col0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int64_t i = c.i0 + k;
+        if (i >= 0 && i < N) seg = col == 0 ? (c.v[k] | 256u) : seg_join(seg, c.v[k]);
+        col = col + 1 == (uint32_t)W ? 0u : col + 1;
+    }
+    return seg;
+}
+
+// Encoder: d of chunk t into out, which has the plane's lead (a workspace).
+__global__ __launch_bounds__(256) void k_ent_ediff(const uint8_t *__restrict__ e, uint8_t *__restrict__ out,
+                                                   int64_t N, int W) {
+    EChunk c;
+    echunk_load(e, N, W, (int64_t)blockIdx.x * 256 + threadIdx.x, c);
+    if (c.i0 >= N) return;
+    uint32_t prev = c.i0 >= 1 ? (uint32_t)e[c.i0 - 1] : 0u;  // used only past a row's first pixel
+    uint32_t o[16], col = c.col0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        o[k] = (col == 0 ? c.v[k] : c.v[k] - prev) & 255u;
+        prev = c.v[k];
+        col = col + 1 == (uint32_t)W ? 0u : col + 1;
+    }
+    echunk_store(out, N, c, o);
+}
+
+// Exclusive scan of segment values over a workgroup of NW waves (0 is the
+// identity); total receives the join of all of them.
+template <int NW>
+__device__ uint32_t seg_excl_scan(uint32_t v, uint32_t *sh, uint32_t &total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t inc = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(inc, off, 64);
+        if (lane >= off) inc = seg_join(y, inc);
+    }
+    __syncthreads();
+    if (lane == 63) sh[w] = inc;
+    __syncthreads();
+    uint32_t before = 0, t = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        if (k < w) before = seg_join(before, sh[k]);
+        t = seg_join(t, sh[k]);
+    }
+    uint32_t ex = __shfl_up(inc, 1, 64);
+    ex = lane == 0 ? 0u : ex;
+    total = t;
+    return seg_join(before, ex);
+}
+
+// Segment value of each tile of 256 chunks.
+__global__ __launch_bounds__(256) void k_ent_eseg(const uint8_t *__restrict__ e, int64_t N, int W,
+                                                  uint32_t *__restrict__ seg) {
+    __shared__ uint32_t sh[4];
+    EChunk c;
+    echunk_load(e, N, W, (int64_t)blockIdx.x * 256 + threadIdx.x, c);
+    uint32_t tot;
+    seg_excl_scan<4>(echunk_seg(c, N, W), sh, tot);
+    if (threadIdx.x == 0) seg[blockIdx.x] = tot;
+}
+
+// Exclusive scan of the tiles' values (one workgroup).
+__global__ __launch_bounds__(1024) void k_ent_ecarry(const uint32_t *__restrict__ seg, uint32_t *__restrict__ carry,
+                                                     int64_t ntiles) {
+    __shared__ uint32_t sh[16];
+    uint32_t run = 0;
+    for (int64_t b = 0; b < ntiles; b += 1024) {
+        const int64_t k = b + threadIdx.x;
+        uint32_t tot;
+        const uint32_t ex = seg_excl_scan<16>(k < ntiles ? seg[k] : 0u, sh, tot);
+        if (k < ntiles) carry[k] = seg_join(run, ex);
+        run = seg_join(run, tot);
+    }
+}
+
+// E along each row from d, in place: a lane reads its own chunk before it
+// writes it, and no lane reads another's.  The value carried into tile b is
+// the join of the tiles before it; when rows are at most ENT_ETILE pixels
+// wide (direct), tile b - 1 holds a row start (tile 0 holds pixel 0, any
+// other is ENT_ETILE consecutive pixels), so that join is tile b - 1's value
+// and the carry scan is skipped.
+__global__ __launch_bounds__(256) void k_ent_eundo(uint8_t *e, int64_t N, int W, const uint32_t *__restrict__ seg,
+                                                   const uint32_t *__restrict__ carry, int direct) {
+    __shared__ uint32_t sh[4];
+    EChunk c;
+    echunk_load(e, N, W, (int64_t)blockIdx.x * 256 + threadIdx.x, c);
+    uint32_t tot;
+    const uint32_t ex = seg_excl_scan<4>(echunk_seg(c, N, W), sh, tot);
+    const uint32_t cin = direct ? (blockIdx.x ? seg[blockIdx.x - 1] : 0u) : carry[blockIdx.x];
+    uint32_t acc = seg_join(cin, ex) & 255u, col = c.col0, o[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        acc = (col == 0 ? c.v[k] : acc + c.v[k]) & 255u;
+        o[k] = acc;
+        col = col + 1 == (uint32_t)W ? 0u : col + 1;
+    }
+    echunk_store(e, N, c, o);
+}
+
 }  // namespace
 
 void launch_ent_encode(const EntArgs &a, hipStream_t s) {
     const int64_t ng = 4 * (int64_t)a.G;
+    if (a.flags & 1) {
+        const uint8_t *e = a.resid + 6 * a.N;
+        const int lead = (int)(reinterpret_cast<uintptr_t>(e) & 15);
+        hipLaunchKernelGGL(k_ent_ediff, dim3((unsigned)ent_etiles(a.N, lead)), dim3(256), 0, s, e, a.ediff, a.N, a.W);
+    }
     if ((reinterpret_cast<uintptr_t>(a.resid) & 15) == 0 && a.N >= 16) {
         const int64_t nr = ((6 * a.N + 15) / 16 + ENT_VEC_SPAN / 16 - 1) / (ENT_VEC_SPAN / 16);
         const int64_t ne = (a.N + 16 + ENT_VEC_SPAN - 1) / ENT_VEC_SPAN;
@@ -587,6 +759,15 @@ void launch_ent_decode(const EntArgs &a, hipStream_t s) {
     if (a.status) hipLaunchKernelGGL(k_ent_status, dim3(1), dim3(64), 0, s, a.status);
     const int gpp = (a.G + ENT_DEC_WAVES - 1) / ENT_DEC_WAVES;
     hipLaunchKernelGGL(k_ent_dec, dim3((unsigned)(4 * gpp)), dim3(64 * ENT_DEC_WAVES), 0, s, a);
+    if (a.flags & 1) {
+        uint8_t *e = a.dst + 6 * a.N;
+        const int64_t nt = ent_etiles(a.N, (int)(reinterpret_cast<uintptr_t>(e) & 15));
+        const int direct = a.W <= ENT_ETILE;
+        hipLaunchKernelGGL(k_ent_eseg, dim3((unsigned)nt), dim3(256), 0, s, e, a.N, a.W, a.eagg);
+        if (!direct) hipLaunchKernelGGL(k_ent_ecarry, dim3(1), dim3(1024), 0, s, a.eagg, a.eagg + nt, nt);
+        hipLaunchKernelGGL(k_ent_eundo, dim3((unsigned)nt), dim3(256), 0, s, e, a.N, a.W, a.eagg, a.eagg + nt,
+                           direct);
+    }
 }
 
 }  // namespace rdl

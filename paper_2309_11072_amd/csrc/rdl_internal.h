@@ -130,6 +130,10 @@ struct EntWs {
 };
 struct EntArgs {
     const uint8_t *resid;   // encoder input / decoder output: 7*H*W bytes
+    const uint8_t *eplane;  // encoder: plane 3's symbols (the exponents, or their left differences)
+    uint8_t *ediff;         // encoder: where the left differences go (workspace, 16-byte aligned)
+    uint32_t *eagg;         // decoder: [2][tiles] segment values of the inverse (workspace)
+    int32_t flags;          // bit 0: plane 3 holds left differences
     uint8_t *out;           // encoder: the code stream
     const uint8_t *code;    // decoder: the code stream
     uint8_t *dst;           // decoder: the enhancement layer
@@ -151,10 +155,20 @@ inline int64_t ent_groups(int H, int W, int log2_k) {
 __host__ __device__ inline int64_t ent_slot(int log2_k) { return ((int64_t)64 << log2_k) + 128 + 64; }
 inline size_t ent_cnt_off() { return (sizeof(EntWs) + 255) & ~(size_t)255; }
 inline size_t ent_tmp_off(int64_t G) { return (ent_cnt_off() + 4 * (size_t)G * 4 + 255) & ~(size_t)255; }
-inline size_t ent_ws_bytes(int H, int W, int log2_k) {
+inline size_t ent_ediff_off(int H, int W, int log2_k) {
     const int64_t G = ent_groups(H, W, log2_k);
-    return ent_tmp_off(G) + 4 * (size_t)G * (size_t)ent_slot(log2_k) * 2;
+    return (ent_tmp_off(G) + 4 * (size_t)G * (size_t)ent_slot(log2_k) * 2 + 255) & ~(size_t)255;
 }
+// The exponents' differences sit at the workspace offset + the plane's
+// address mod 16 (lead), so that both share their 16-byte chunks.
+inline size_t ent_ws_bytes(int H, int W, int log2_k) {
+    return ent_ediff_off(H, W, log2_k) + (((size_t)H * W + 16 + 255) & ~(size_t)255);
+}
+// Workgroups of the left-difference kernels: 256 lanes of one 16-byte chunk.
+constexpr int ENT_ETILE = 4096;
+inline int64_t ent_etiles(int64_t N, int lead) { return (N + lead + ENT_ETILE - 1) / ENT_ETILE; }
+// The decoder's workspace: the segment values of the inverse, after EntWs.
+inline size_t ent_dec_ws_bytes(int64_t N) { return ent_cnt_off() + 8 * (size_t)ent_etiles(N, 15); }
 void launch_ent_encode(const EntArgs &a, hipStream_t s);
 void launch_ent_decode(const EntArgs &a, hipStream_t s);
 

@@ -72,6 +72,7 @@ _SIGS = {
     "rdl_set_model": ([_vp, _vp, C.c_size_t], _i),
     "rdl_set_estimator": ([_vp, _i], _i),
     "rdl_set_gf": ([_vp, _i], _i),
+    "rdl_set_ent_predict": ([_vp, _i], _i),
     "rdl_train_sample_bytes": ([], _i),
     "rdl_train_nparam": ([], _i),
     "rdl_train_samples": ([_vp, _vp, _vp, _i, _i, _i, _vp, C.c_int64, _vp, _vp], _i),
@@ -191,6 +192,10 @@ class Codec:
     def set_gf(self, on: bool):
         """Gaussian-filter restoration of S before the estimate (on by default)."""
         _chk(self._L.rdl_set_gf(self._h, int(bool(on))), "rdl_set_gf")
+
+    def set_ent_predict(self, on: bool):
+        """Entropy code: the exponent plane as left differences (on by default)."""
+        _chk(self._L.rdl_set_ent_predict(self._h, int(bool(on))), "rdl_set_ent_predict")
 
     # -------------------------------------------------------------- training
     def train_samples(self, rgbe: torch.Tensor, sdr: torch.Tensor, k_img: int, idx: torch.Tensor,

@@ -105,6 +105,7 @@ def test_entropy_bound_and_argument_checks_host_only(O):
         assert L.rdl_ent_bound(H, W, k) == 0
     assert L.rdl_ent_encode(None, None, 3, 3, 8, None, 0, None, None) == rdl.RDL_EINVAL
     assert L.rdl_ent_decode(None, None, 0, None, 3, 3, None, None, None) == rdl.RDL_EINVAL
+    assert L.rdl_set_ent_predict(None, 1) == rdl.RDL_EINVAL
 
 
 def test_jpeg_bound_host_only():

@@ -58,13 +58,52 @@ def test_two_pixel_states_by_hand(O):
     f = 1 + floor((2^15 - 2) / 2) = 16384 each, c = (0, 16384).  Lane 0 codes a:
     65536 -> (65536 div 16384) 2^15 + 0 + 0 = 131072 = (2, 0); lane 1 codes b:
     4 * 2^15 + 16384 = 147456 = (2, 16384).  Residual planes are constant."""
-    st = O.ent_encode(layer(np.zeros((3, 1, 2)), np.array([[100, 200]])), 1, 2, log2_k=4)
+    st = O.ent_encode(layer(np.zeros((3, 1, 2)), np.array([[100, 200]])), 1, 2, log2_k=4, predict=False)
+    assert u32(st, 28) == 0
     fe = [u16(st, 40 + 2 * (512 * 3 + s)) for s in range(256)]
     assert fe[100] == fe[200] == 16384 and sum(fe) == M
     w = payload_words(st, 1)
     assert len(w) == 4 * 128
     assert w[3 * 128:4 * 128] == [2, 0, 2, 16384] + [1, 0] * 62
     assert w[:128] == [1, 0] * 64  # constant residual planes cost nothing
+
+
+def test_exponent_prediction_by_hand(O):
+    """2 x 2 exponents [[100, 200], [50, 49]] coded as left differences: each
+    row starts with its own value, so the symbols are 100, 100, 50, 255
+    (49 - 50 mod 256).  Counts (2, 1, 1), P = 3, N = 4: f = 1 + floor(h 32765 / 4)
+    = 16383, 8192, 8192, and the remainder 1 goes to symbol 100."""
+    E = np.array([[100, 200], [50, 49]])
+    st = O.ent_encode(layer(np.zeros((3, 2, 2)), E), 2, 2, log2_k=4)
+    assert u32(st, 28) == 1
+    fe = [u16(st, 40 + 2 * (512 * 3 + s)) for s in range(256)]
+    assert (fe[100], fe[50], fe[255]) == (16384, 8192, 8192) and sum(fe) == M
+    assert np.array_equal(O.ent_decode(st, 2, 2), layer(np.zeros((3, 2, 2)), E))
+    # one row: 100, 100 is a single symbol, every state stays at L
+    st = O.ent_encode(layer(np.zeros((3, 1, 2)), np.array([[100, 200]])), 1, 2, log2_k=4)
+    assert u16(st, 40 + 2 * (512 * 3 + 100)) == M
+    assert payload_words(st, 1)[3 * 128:] == [1, 0] * 64
+
+
+@pytest.mark.parametrize("H,W", [(1, 1), (5, 1), (1, 300), (37, 41), (120, 160)])
+def test_exponent_prediction_counts(O, H, W):
+    """The exponent plane's frequencies are the rule applied to the counts of
+    the left differences (numpy, row by row); the residual planes' tables and
+    the decoded layer do not depend on the prediction."""
+    x = synth.generate(H, W, 4.0, seed=H + 7 * W, spec_frac=0.05)
+    E = x[..., 3].astype(np.int64)
+    d = E.copy()
+    d[:, 1:] = (E[:, 1:] - E[:, :-1]) % 256
+    want = O.ent_freqs(np.bincount(d.reshape(-1), minlength=256))
+    rng = np.random.default_rng(H * W)
+    res = layer(np.clip(np.round(rng.laplace(0, 3, (3, H, W))), -255, 255), E)
+    st1 = O.ent_encode(res, H, W, 4, predict=True)
+    st0 = O.ent_encode(res, H, W, 4, predict=False)
+    assert (u32(st1, 28), u32(st0, 28)) == (1, 0)
+    f1 = np.array([u16(st1, 40 + 2 * (512 * 3 + s)) for s in range(256)])
+    assert np.array_equal(f1, want)
+    assert st1[40:40 + 3 * 1024] == st0[40:40 + 3 * 1024]
+    assert np.array_equal(O.ent_decode(st1, H, W), res) and np.array_equal(O.ent_decode(st0, H, W), res)
 
 
 def _info(h, f):
@@ -144,10 +183,11 @@ def _rand_layer(rng, H, W, kind):
 @pytest.mark.parametrize("H,W", [(1, 1), (7, 9), (1, 1025), (64, 65), (33, 257)])
 @pytest.mark.parametrize("log2_k", [4, 5, 8, 12])
 @pytest.mark.parametrize("kind", ["laplace", "wide", "extreme", "constant"])
-def test_round_trip(O, H, W, log2_k, kind):
+@pytest.mark.parametrize("predict", [True, False])
+def test_round_trip(O, H, W, log2_k, kind, predict):
     rng = np.random.default_rng(H * 1000 + W + log2_k)
     x = _rand_layer(rng, H, W, kind)
-    st = O.ent_encode(x, H, W, log2_k)
+    st = O.ent_encode(x, H, W, log2_k, predict=predict)
     assert len(st) <= O.ent_bound(H, W, log2_k)
     G = -(-H * W // (64 << log2_k))
     starts = [u64(st, HDR + 8 * k) for k in range(4 * G)] + [(len(st) - HDR - 32 * G) // 2]
@@ -207,6 +247,10 @@ def test_rejects_out_of_range_and_corrupt_streams(O):
         O.ent_decode(bytes(bad), 40, 30)
     with pytest.raises(ValueError, match="-5"):
         O.ent_decode(bytes(st), 40, 31)
+    bad = bytearray(st)
+    bad[28] = 2  # unknown flag
+    with pytest.raises(ValueError, match="-5"):
+        O.ent_decode(bytes(bad), 40, 30)
     bad = bytearray(st)
     bad[40 + 2 * 300] ^= 1  # frequencies no longer sum to 2^15
     with pytest.raises(ValueError, match="-5"):

@@ -39,18 +39,23 @@ def make_layer(H, W, seed, spread=3.0, e_lo=110, e_hi=150, outlier=0.0):
     return np.concatenate([r.astype(np.int16).reshape(-1).view(np.uint8), E.astype(np.uint8).reshape(-1)])
 
 
-def gpu_roundtrip(codec, O, x, H, W, log2_k, offset=0):
+def gpu_roundtrip(codec, O, x, H, W, log2_k, offset=0, predict=True):
     """offset: place the layer that many bytes into a device buffer (a layer
-    that is not 16-byte aligned takes the library's narrow-load histogram)."""
+    that is not 16-byte aligned takes the library's narrow-load histogram);
+    predict: the exponents as left differences (the library's default)."""
     if offset:
         buf = torch.zeros(x.size + offset, dtype=torch.uint8, device="cuda")
         buf[offset:] = torch.from_numpy(x).cuda()
         d = buf[offset:]
     else:
         d = torch.from_numpy(x).cuda()
-    code = codec.ent_encode(d, H, W, log2_k)
+    codec.set_ent_predict(predict)
+    try:
+        code = codec.ent_encode(d, H, W, log2_k)
+    finally:
+        codec.set_ent_predict(True)
     got = code.cpu().numpy().tobytes()
-    ref = O.ent_encode(x, H, W, log2_k)
+    ref = O.ent_encode(x, H, W, log2_k, predict=predict)
     assert len(got) == len(ref), (len(got), len(ref))
     assert got == ref
     status = torch.full((1,), 77, dtype=torch.int32, device="cuda")
@@ -91,6 +96,31 @@ def test_histogram_paths(codec, O, H, W, offset):
     and 2-byte loads (any other), with residual and exponent tails."""
     _say("entropy histogram path", H, W, offset)
     gpu_roundtrip(codec, O, make_layer(H, W, 31 * H + W, spread=5.0, e_lo=0, e_hi=256), H, W, 4, offset=offset)
+
+
+def smooth_layer(H, W, seed):
+    """Residuals as make_layer's, exponents of the synthetic image generator
+    (smooth, with the runs and steps the differences code)."""
+    x = make_layer(H, W, seed)
+    x[6 * H * W:] = synth.generate(H, W, 4.0, seed=seed, spec_frac=0.05)[..., 3].reshape(-1)
+    return x
+
+
+@pytest.mark.parametrize("H,W", [(1, 1), (1, 17), (17, 1), (3, 5), (5, 4097), (97, 131), (2, 70000), (700, 1510)])
+@pytest.mark.parametrize("predict", [True, False])
+def test_exponent_prediction(codec, O, H, W, predict):
+    """Exponents as left differences and as they are: the stream equals the
+    oracle's and decodes exactly; rows inside one lane (W = 1, 5), rows across
+    tiles (70,000 wide) and more tiles than one carry chunk (700 x 1510)."""
+    _say("entropy prediction", H, W, predict)
+    gpu_roundtrip(codec, O, smooth_layer(H, W, H + 3 * W), H, W, 4, predict=predict)
+    if H * W >= 16:
+        gpu_roundtrip(codec, O, smooth_layer(H, W, H + 5 * W), H, W, 8, offset=2, predict=predict)
+
+
+def test_prediction_switch(codec, rdl_mod):
+    assert codec._L.rdl_set_ent_predict(codec._h, 2) == rdl_mod.RDL_EINVAL
+    assert codec._L.rdl_set_ent_predict(None, 1) == rdl_mod.RDL_EINVAL
 
 
 def test_workspace_reuse_across_sizes(codec, O):
@@ -151,6 +181,10 @@ def test_corrupt_streams_are_reported(codec, O, rdl_mod):
         codec.ent_decode(code, H, W + 1)
     bad = code.clone()
     bad[40 + 2 * 600] ^= 1
+    with pytest.raises(rdl_mod.RdlError):
+        codec.ent_decode(bad, H, W)
+    bad = code.clone()
+    bad[28] = 2  # unknown flag
     with pytest.raises(rdl_mod.RdlError):
         codec.ent_decode(bad, H, W)
     # device checks: a group offset one word late, a truncated group

@@ -146,3 +146,35 @@ def test_max_size_learned_matches_oracle(codec, rdl_mod, O, big):
         assert torch.equal(back, d)
     finally:
         codec.set_estimator(0)
+
+
+@pytest.mark.gpu
+def test_max_size_files_and_decoder(codec, O, big):
+    """At 33 MP: the JPEG file of the base layer equals the oracle's writer,
+    the base layer decoded from its coefficients equals the oracle's S, and
+    the two files (JPEG coefficients + rANS-coded layer) decode to the image."""
+    x, ref = big
+    H, W = x.shape[:2]
+    d = torch.from_numpy(x).cuda()
+    sdr, hdr, resid = codec.alloc_outputs(H, W)
+    dct = torch.empty((3, (H + 7) // 8 * 8, (W + 7) // 8 * 8), dtype=torch.int16, device="cuda")
+    _say("max size: batched encode with coefficients")
+    codec.encode_batch([(d, Q_MAX, sdr, hdr, resid, dct)])
+    torch.cuda.synchronize()
+    assert np.array_equal(sdr.cpu().numpy(), ref["sdr"])
+    dct_h = dct.cpu().numpy()
+    _say("max size: oracle base decode and JPEG writer")
+    assert np.array_equal(O.base_decode(dct_h, H, W, Q_MAX), ref["sdr"])
+    jpg, hdr2, code = codec.encode_files(d, Q_MAX)
+    torch.cuda.synchronize()
+    assert jpg.cpu().numpy().tobytes() == O.jpeg_write(dct_h, H, W, Q_MAX)
+    _say("max size: decode from the files, bytes", int(jpg.numel()), int(code.numel()))
+    layer = codec.ent_decode(code, H, W)
+    assert np.array_equal(layer.cpu().numpy(), ref["resid"])
+    out = torch.full((H, W, 4), 0x55, dtype=torch.uint8, device="cuda")
+    st = torch.full((1,), 77, dtype=torch.int32, device="cuda")
+    s_in = torch.full_like(sdr, 0xAA)
+    codec.decode_batch([(dct, s_in, hdr2, layer, out, st)])
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    assert torch.equal(s_in, sdr) and torch.equal(out, d)

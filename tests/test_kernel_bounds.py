@@ -286,3 +286,135 @@ def test_decode_wide_accesses_stay_inside(H, W):
                 assert r_byte % 8 == 0 and r_byte + 8 <= 2 * (c + 1) * npx
             o_byte = 4 * off
             assert o_byte % 16 == 0 and o_byte + 16 <= 4 * npx
+
+
+# ---- left differences of the exponent plane ---------------------------------
+def _seg_join(a, b):
+    return b if b & 256 else ((a + b) & 255) | (a & 256)
+
+
+def _block_excl_scan(vals, nw=4):
+    """The workgroup scan as the kernel runs it: per wave the shuffle-up
+    ladder (offsets 1 .. 32), then the waves' totals joined in order."""
+    n = 64 * nw
+    vals = list(vals) + [0] * (n - len(vals))
+    inc = list(vals)
+    for w in range(nw):
+        lanes = inc[64 * w:64 * w + 64]
+        off = 1
+        while off < 64:
+            lanes = [_seg_join(lanes[l - off], lanes[l]) if l >= off else lanes[l] for l in range(64)]
+            off <<= 1
+        inc[64 * w:64 * w + 64] = lanes
+    sh = [inc[64 * w + 63] for w in range(nw)]
+    out, total = [], 0
+    for k in range(nw):
+        total = _seg_join(total, sh[k])
+    for t in range(n):
+        w, l = divmod(t, 64)
+        before = 0
+        for k in range(w):
+            before = _seg_join(before, sh[k])
+        ex = inc[t - 1] if l else 0
+        out.append(_seg_join(before, ex))
+    return out, total
+
+
+def _chunk(N, W, lead, t, touched):
+    """echunk_load: (i0, col0, full, indices read); records the bytes read."""
+    i0 = 16 * t - lead
+    full = i0 >= 0 and i0 + 16 <= N
+    m = abs(i0) % W
+    col0 = W - m if i0 < 0 and m else m
+    idx = [i0 + k for k in range(16) if 0 <= i0 + k < N]
+    if full:
+        assert (lead + i0) % 16 == 0  # the 16-byte access is aligned
+    touched.update(idx)
+    return i0, col0, full
+
+
+def _undo_model(d, W, lead):
+    """k_ent_eseg, k_ent_ecarry and k_ent_eundo on a flat plane d (uint8) at
+    an address with the given lead; checks every access stays in the plane."""
+    N = d.size
+    ntiles = (N + lead + 4095) // 4096
+    assert ntiles <= (N + 15 + 4095) // 4096  # the workspace holds 2 values per tile for any lead
+    touched = set()
+    lanes = []
+    for t in range(ntiles * 256):
+        i0, col0, full = _chunk(N, W, lead, t, touched)
+        v = [int(d[i0 + k]) if 0 <= i0 + k < N else 0 for k in range(16)]
+        seg, col = 0, col0
+        for k in range(16):
+            if 0 <= i0 + k < N:
+                seg = (v[k] | 256) if col == 0 else _seg_join(seg, v[k])
+            col = 0 if col + 1 == W else col + 1
+        lanes.append((i0, col0, v, seg))
+    assert touched == set(range(N))
+    tile_seg, tile_ex = [], []
+    for b in range(ntiles):
+        ex, tot = _block_excl_scan([ln[3] for ln in lanes[256 * b:256 * b + 256]])
+        tile_seg.append(tot)
+        tile_ex.append(ex)
+    carry, run = [], 0
+    for b0 in range(0, ntiles, 1024):
+        ex, tot = _block_excl_scan(tile_seg[b0:b0 + 1024], nw=16)
+        carry += [_seg_join(run, e) for e in ex[:min(1024, ntiles - b0)]]
+        run = _seg_join(run, tot)
+    if W <= 4096:  # the kernel's direct carry: the previous tile's value
+        assert carry == [0] + tile_seg[:-1]
+    out = np.full(N, -1, np.int64)
+    for t, (i0, col, v, _) in enumerate(lanes):
+        b = t // 256
+        acc = _seg_join(carry[b], tile_ex[b][t % 256]) & 255
+        for k in range(16):
+            acc = (v[k] if col == 0 else acc + v[k]) & 255
+            if 0 <= i0 + k < N:
+                assert out[i0 + k] < 0  # written once
+                out[i0 + k] = acc
+            col = 0 if col + 1 == W else col + 1
+    return out
+
+
+def _diff_model(E, W, lead):
+    """k_ent_ediff: d of every chunk, with the previous byte read from before
+    the chunk only past a row's first pixel."""
+    N = E.size
+    out = np.full(N, -1, np.int64)
+    touched = set()
+    for t in range((N + lead + 4095) // 4096 * 256):
+        i0, col, full = _chunk(N, W, lead, t, touched)
+        if i0 >= N:
+            continue
+        prev = int(E[i0 - 1]) if i0 >= 1 else 0
+        for k in range(16):
+            i = i0 + k
+            v = int(E[i]) if 0 <= i < N else 0
+            dv = (v if col == 0 else v - prev) & 255
+            prev = v
+            if 0 <= i < N:
+                out[i] = dv
+            col = 0 if col + 1 == W else col + 1
+    assert touched == set(range(N))
+    return out
+
+
+_SMALL = [(1, 1), (1, 2), (3, 1), (1, 17), (5, 4097), (300, 37), (2, 70000), (41, 1000)]
+
+
+@pytest.mark.parametrize("H,W,lead", [(H, W, lead) for H, W in _SMALL for lead in (0, 6, 15)]
+                         + [(700, 1510, 15), (1100, 3900, 6)])
+def test_exponent_difference_kernels_model(H, W, lead):
+    """The encoder's differences and the decoder's segmented scan (lanes,
+    waves, tiles, carry chunks of 1024 tiles) give d and back E exactly, for a
+    plane at any address mod 16: rows inside one lane (W = 1, 2, 37), rows
+    across tiles (70,000 wide), 1100 x 3900 needs two carry chunks; with rows
+    of at most 4096 pixels the carry is the previous tile's value."""
+    rng = np.random.default_rng(H * W + lead)
+    E = rng.integers(0, 256, (H, W))
+    E[:, W // 3:] = E[:, W // 3:] // 64 + 120  # runs of close values too
+    d = E.copy()
+    d[:, 1:] = (E[:, 1:] - E[:, :-1]) % 256
+    flat = E.reshape(-1).astype(np.uint8)
+    assert np.array_equal(_diff_model(flat, W, lead), d.reshape(-1))
+    assert np.array_equal(_undo_model(d.reshape(-1).astype(np.uint8), W, lead), E.reshape(-1))
