@@ -67,6 +67,25 @@ __device__ unsigned long long block_max64(unsigned long long v, unsigned long lo
     return t;
 }
 
+// Exclusive prefix maximum over a block of NW waves (0 before lane 0).
+template <int NW>
+__device__ uint32_t block_excl_max(uint32_t v, uint32_t *sh) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t inc = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(inc, off, 64);
+        if (lane >= off) inc = max(inc, y);
+    }
+    __syncthreads();
+    if (lane == 63) sh[w] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) before = k < w ? max(before, sh[k]) : before;
+    const uint32_t ex = __shfl_up(inc, 1, 64);
+    return max(before, lane == 0 ? 0u : ex);
+}
+
 // Exclusive prefix sum over a block of NW waves; total receives the sum.
 template <int NW>
 __device__ uint32_t block_excl_scan(uint32_t v, uint32_t *sh, uint32_t &total) {
@@ -450,7 +469,7 @@ __global__ void k_ent_status(int32_t *st) {
 // kept only where the lane has a symbol, so that only the stores and the
 // short search loop are predicated.
 template <bool RES, typename V, typename LD>
-__device__ __forceinline__ bool dec_group(V *dst, int n, const uint2 *dtab, const uint16_t *bucket, uint16_t *rg,
+__device__ __forceinline__ bool dec_group(V *dst, int n, const uint2 *dtab, const uint16_t *slot_sym, uint16_t *rg,
                                           uint32_t (&R)[4], int64_t b, int64_t pos, uint32_t x, int64_t w1,
                                           const LD &ld, int lane) {
     const int T = (n + 63) >> 6;
@@ -466,9 +485,7 @@ __device__ __forceinline__ bool dec_group(V *dst, int n, const uint2 *dtab, cons
         const int i = t * 64 + lane;
         const bool have = i < n;
         const uint32_t slot = x & (ENT_M - 1);
-        uint32_t j = bucket[slot >> 3];
-        while ((dtab[j + 1].x & 0xFFFFu) <= slot) ++j;
-        const uint2 e = dtab[j];
+        const uint2 e = dtab[slot_sym[slot]];
         const uint32_t xn = (e.x >> 16) * (x >> ENT_PB) + slot - (e.x & 0xFFFFu);
         x = have ? xn : x;
         const bool ren = have && x < ENT_L;
@@ -486,17 +503,16 @@ __device__ __forceinline__ bool dec_group(V *dst, int n, const uint2 *dtab, cons
 
 // Decoder: ENT_DEC_WAVES groups of one plane per workgroup.  The workgroup
 // builds the plane's tables from the stream's frequencies: the present
-// symbols in order, {c | f << 16, symbol} (then a sentinel with c = M), and
-// for every 8-slot bucket the present symbol holding the bucket's first
-// slot.  A slot's symbol is then at most 7 entries past its bucket's.  Each
-// wave reads its lanes' states, and per step: slot = x mod M, the symbol,
-// x = f (x div M) + slot - c, and the lanes with x < L read the next words in
-// lane order.  A group must end exactly at its last word with every state
+// symbols in order, {c | f << 16, symbol}, and for every one of the M slots
+// the index of the present symbol holding it (64 KB of LDS).  Each wave reads
+// its lanes' states, and per step: slot = x mod M, the symbol in two LDS
+// reads, x = f (x div M) + slot - c, and the lanes with x < L read the next
+// words in lane order.  A group must end exactly at its last word with every state
 // back at L; a frequency table, group offset or word count that does not fit
 // sets *status = RDL_ECORRUPT (reads stay inside the group).
 __global__ __launch_bounds__(256) void k_ent_dec(EntArgs a) {
-    __shared__ uint2 dtab[513];
-    __shared__ uint16_t bucket[ENT_M >> 3];
+    __shared__ uint2 dtab[512];
+    __shared__ __align__(16) uint16_t slot_sym[ENT_M];
     __shared__ uint32_t sh[4];
     __shared__ uint16_t ring[ENT_DEC_WAVES][512];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -515,17 +531,38 @@ __global__ __launch_bounds__(256) void k_ent_dec(EntArgs a) {
     }
     if (f0) dtab[j0] = make_uint2(c0 | f0 << 16, s0);
     if (f1) dtab[j0 + (f0 > 0)] = make_uint2((c0 + f0) | f1 << 16, s0 + 1);
-    if (threadIdx.x == 0) dtab[P] = make_uint2(ENT_M, 0u);
+    // The slot table: each present symbol's index marked at its first slot
+    // (the slots in between left 0), then a prefix maximum over the M slots
+    // (indices grow with c), lane t owning slots [128 t, 128 t + 128).
+    uint4 *st4 = reinterpret_cast<uint4 *>(slot_sym) + 16 * threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) st4[k] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
-    for (int u = threadIdx.x; u < (int)(ENT_M >> 3); u += 256) {
-        const uint32_t v = (uint32_t)u << 3;
-        int lo = 0, hi = (int)P - 1;  // the last present symbol with c <= v holds slot v
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if ((dtab[mid].x & 0xFFFFu) <= v) lo = mid;
-            else hi = mid - 1;
+    if (f0) slot_sym[c0] = (uint16_t)j0;
+    if (f1) slot_sym[c0 + f0] = (uint16_t)(j0 + (f0 > 0));
+    __syncthreads();
+    uint4 sv[16];
+    uint32_t run = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) sv[k] = st4[k];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        uint32_t *w = reinterpret_cast<uint32_t *>(&sv[k]);
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const uint32_t lo = max(run, w[h] & 0xFFFFu);
+            run = max(lo, w[h] >> 16);
+            w[h] = lo | run << 16;
         }
-        bucket[u] = (uint16_t)lo;
+    }
+    const uint32_t before = block_excl_max<4>(run, sh);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const uint32_t *w = reinterpret_cast<const uint32_t *>(&sv[k]);
+        uint32_t o[4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) o[h] = max(w[h] & 0xFFFFu, before) | max(w[h] >> 16, before) << 16;
+        st4[k] = make_uint4(o[0], o[1], o[2], o[3]);
     }
     __syncthreads();
     if (g >= G) return;
@@ -561,10 +598,10 @@ __global__ __launch_bounds__(256) void k_ent_dec(EntArgs a) {
     const int n = (int)(a.N - base < Z ? a.N - base : Z);
     bool bad;
     if (p < 3)
-        bad = dec_group<true>(reinterpret_cast<int16_t *>(a.dst) + p * a.N + base, n, dtab, bucket, rg, R, b, pos,
+        bad = dec_group<true>(reinterpret_cast<int16_t *>(a.dst) + p * a.N + base, n, dtab, slot_sym, rg, R, b, pos,
                               x, w1, ld, lane);
     else
-        bad = dec_group<false>(a.dst + 6 * a.N + base, n, dtab, bucket, rg, R, b, pos, x, w1, ld, lane);
+        bad = dec_group<false>(a.dst + 6 * a.N + base, n, dtab, slot_sym, rg, R, b, pos, x, w1, ld, lane);
     if (__ballot(bad) && lane == 0 && a.status) atomicExch(a.status, RDL_ECORRUPT);
 }
 
