@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "rdl_internal.h"
 
 namespace rdl {
@@ -300,7 +302,8 @@ __global__ __launch_bounds__(512) void k_ent_freq(EntArgs a) {
     const uint32_t c = block_excl_scan<8>(f, sh, tot);
     const bool bad = nbad != 0;
     reinterpret_cast<uint16_t *>(a.out + 40)[512 * p + s] = bad ? 0 : (uint16_t)f;
-    a.ws->tab[p][s] = make_uint2(f | c << 16, f ? __float_as_uint(1.0f / (float)f) : 0u);
+    // fl(1/f) lowered by 4 ulps: x fl(.) then stays below x / f (see enc_group)
+    a.ws->tab[p][s] = make_uint2(f | c << 16, f ? __float_as_uint(1.0f / (float)f) - 4u : 0u);
     if (s == 0) a.ws->bad[p] = bad ? 1u : 0u;
     if (p == 0 && s < 8) {
         const uint32_t v = s == 0 ? 0x454C4452u
@@ -319,14 +322,17 @@ __global__ __launch_bounds__(512) void k_ent_freq(EntArgs a) {
 // the last step to the first.  A lane renormalises (emits its low 16 bits)
 // when x >= 2^17 f; the words of a step go out in descending lane order, so
 // that the stored (reversed) stream lists them in ascending order.  Then
-// x = (x div f) M + (x mod f) + c, with the quotient from a float reciprocal:
-// x < 2^17 f, so the estimate is within 3 * 2^-24 * 2^17 < 0.03 of x / f and
-// one correction step in either direction makes it exact.  Finally every
+// x = (x div f) M + (x mod f) + c, with the quotient from a float reciprocal
+// r' = fl(1/f) lowered by 4 ulps (relative decrease between 2^-22 and 2^-21):
+// fl(fl(x) r') <= x/f (1 + 2^-24)^3 (1 - 2^-22) < x / f, and x < 2^17 f
+// bounds its shortfall by 2^17 (2^-21 + 3 2^-24) < 0.11, so the truncated
+// estimate is x div f or one less and one upward correction makes it exact.
+// Finally every
 // lane's state, lanes 63 down to 0, low half first.  RES: a residual plane
 // (int16 values, symbol r + 255), else the exponent plane (bytes).
 template <bool RES, typename V>
 __device__ __forceinline__ void enc_group(const V *src, int n, const uint2 *tb, uint16_t *out, uint32_t *cnt_out,
-                                          int lane, int64_t dummy) {
+                                          int lane, uint32_t dummy) {
     const int T = (n + 63) >> 6;
     const int tfull = (n >> 6) - 1;  // steps 0..tfull hold a symbol in every lane
     // Symbols of steps t0, t0 - 1, ..., t0 - 7 and a mask of the lane's valid
@@ -353,27 +359,41 @@ __device__ __forceinline__ void enc_group(const V *src, int n, const uint2 *tb, 
     };
     uint32_t x = ENT_L, wpos = 0;
     uint32_t cur[8], nxt[8];
+    // One step.  ALL: every lane has a symbol (a block inside the full steps).
+    // The quotient estimate never exceeds x div f (the table holds fl(1/f)
+    // lowered by 4 ulps) and falls short by less than 1, so one upward
+    // correction makes it exact.  A lane that renormalises writes at
+    // wpos + (number of renormalising lanes above it).
+    auto step = [&](auto all, uint32_t s, bool valid) {
+        constexpr bool ALL = decltype(all)::value;
+        const bool have = ALL || valid;
+        const uint2 e = tb[s];
+        const uint32_t f = e.x & 0xFFFFu, c = e.x >> 16;
+        const bool ren = have && (x >> 17) >= f;
+        const uint64_t m = __builtin_amdgcn_ballot_w64(ren);
+        const uint32_t tot = (uint32_t)__builtin_popcountll(m);
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        // every lane stores (no branch): lanes without a word write their dummy slot
+        out[ren ? wpos + tot - 1u - below : dummy] = (uint16_t)x;
+        wpos += tot;
+        const uint32_t xr = ren ? x >> 16 : x;
+        uint32_t q = (uint32_t)((float)xr * __uint_as_float(e.y));
+        uint32_t r = xr - __umul24(q, f);  // q < 2^18, f <= 2^15: 24-bit product exact
+        const bool up = r >= f;
+        q = up ? q + 1 : q;
+        r = up ? r - f : r;
+        const uint32_t xn = (q << ENT_PB) + r + c;
+        x = ALL ? xn : (have ? xn : xr);
+    };
     uint32_t vcur = load_block(T - 1, cur);
     for (int t0 = T - 1; t0 >= 0; t0 -= 8) {
         const uint32_t vnxt = load_block(t0 - 8, nxt);
+        if (t0 - 7 >= 0 && t0 <= tfull) {  // wave-uniform
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const uint32_t s = cur[k];
-            const bool have = (vcur >> k) & 1u;
-            const uint2 e = tb[s];
-            const uint32_t f = e.x & 0xFFFFu, c = e.x >> 16;
-            const bool ren = have && (x >> 17) >= f;
-            const unsigned long long m = __ballot(ren);
-            // every lane stores (no branch): lanes without a word write their dummy slot
-            out[ren ? (int64_t)(wpos + __popcll(m & ~((2ull << lane) - 1ull))) : dummy] = (uint16_t)x;
-            wpos += __popcll(m);
-            const uint32_t xr = ren ? x >> 16 : x;
-            uint32_t q = (uint32_t)((float)xr * __uint_as_float(e.y));
-            uint32_t r = xr - __umul24(q, f);  // q < 2^18, f <= 2^15: 24-bit product exact
-            const bool lo = (int32_t)r < 0, hi = !lo && r >= f;
-            q = lo ? q - 1 : hi ? q + 1 : q;
-            r = lo ? r + f : hi ? r - f : r;
-            x = have ? (q << ENT_PB) + r + c : xr;
+            for (int k = 0; k < 8; ++k) step(std::true_type{}, cur[k], true);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) step(std::false_type{}, cur[k], (vcur >> k) & 1u);
         }
 #pragma unroll
         for (int k = 0; k < 8; ++k) cur[k] = nxt[k];
@@ -402,7 +422,7 @@ __global__ __launch_bounds__(256) void k_ent_enc(EntArgs a) {
     const int64_t Z = (int64_t)64 << a.log2_k, g = gi - (int64_t)p * G, base = g * Z;
     const int n = (int)(a.N - base < Z ? a.N - base : Z);
     uint16_t *out = a.tmp + gi * ent_slot(a.log2_k);
-    const int64_t dummy = Z + 128 + lane;
+    const uint32_t dummy = (uint32_t)(Z + 128 + lane);
     if (p < 3)
         enc_group<true>((const int16_t *)a.resid + p * a.N + base, n, stab[w], out, a.cnt + gi, lane, dummy);
     else

@@ -127,24 +127,28 @@ def test_quantiser_signed_magic_form_equals_definition():
 
 def test_entropy_quotient_from_float_reciprocal():
     """The entropy encoder divides a state x in [2 f, 2^17 f) by a frequency f in
-    [1, 2^15] as q = trunc(fl(fl(x) * fl(1/f))) and one correction step in
-    either direction (IEEE single rounding, which numpy's float32 follows).
-    Every f, with quotients spread over [2, 2^17) and remainders 0, 1, f/2 and
-    f - 1 (the extremes of the estimate's error), gives x div f and x mod f."""
+    [1, 2^15] as q = trunc(fl(fl(x) * r)), r = fl(1/f) lowered by 4 ulps, and
+    one upward correction (IEEE single rounding, which numpy's float32
+    follows).  The estimate never exceeds x / f and falls short by less than
+    1, for every f with quotients spread over [2, 2^17) and remainders 0, 1,
+    f/2, f - 1 and random ones; q and x - q f are then x div f and x mod f."""
     rng = np.random.default_rng(11)
     f = np.arange(1, (1 << 15) + 1, dtype=np.int64)
     ks = np.concatenate([[2, 3, 255, 256, 65535, 65536, (1 << 17) - 2, (1 << 17) - 1],
-                         rng.integers(2, 1 << 17, 24)])
+                         rng.integers(2, 1 << 17, 40)])
     rcp = (np.float32(1.0) / f.astype(np.float32)).astype(np.float32)
+    rcp = (rcp.view(np.uint32) - 4).view(np.float32)
     for k in ks:
-        for rem in (np.zeros_like(f), np.ones_like(f) % f, f // 2, f - 1):
+        for rem in (np.zeros_like(f), np.ones_like(f) % f, f // 2, f - 1, rng.integers(0, 1 << 15, f.size) % f):
             x = k * f + rem
             assert np.all((x >= 2 * f) & (x < (f << 17)) & (x < 2 ** 32))
             est = x.astype(np.float32) * rcp
-            assert np.all(np.abs(est.astype(np.float64) - x / f) < 0.03)
+            short = x / f - est.astype(np.float64)
+            assert np.all(short >= 0) and np.all(short < 0.11)
             q = np.trunc(est).astype(np.int64)
             r = x - q * f
-            lo, hi = r < 0, r >= f
-            q = np.where(lo, q - 1, np.where(hi, q + 1, q))
-            r = np.where(lo, r + f, np.where(hi, r - f, r))
+            assert np.all(r >= 0) and np.all(r < 2 * f) and np.all(r < 1 << 24)
+            up = r >= f
+            q = np.where(up, q + 1, q)
+            r = np.where(up, r - f, r)
             assert np.array_equal(q, x // f) and np.array_equal(r, x % f)
