@@ -374,7 +374,8 @@ __device__ __forceinline__ void enc_group(const V *src, int n, const uint2 *tb, 
         const uint32_t tot = (uint32_t)__builtin_popcountll(m);
         const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
         // every lane stores (no branch): lanes without a word write their dummy slot
-        out[ren ? wpos + tot - 1u - below : dummy] = (uint16_t)x;
+        const uint32_t keep = 0u - (uint32_t)ren;  // all ones where the lane writes a word
+        out[((wpos + tot - 1u - below) & keep) | (dummy & ~keep)] = (uint16_t)x;
         wpos += tot;
         const uint32_t xr = ren ? x >> 16 : x;
         uint32_t q = (uint32_t)((float)xr * __uint_as_float(e.y));
