@@ -486,16 +486,16 @@ __global__ void k_ent_status(int32_t *st) {
 
 // Decodes one group into dst (RES: int16 residuals, else exponent bytes);
 // returns whether it failed to end exactly at its last word with every state
-// back at L.  The symbol search and state update run for every lane and are
-// kept only where the lane has a symbol, so that only the stores and the
-// short search loop are predicated.
+// back at L.  Word positions count from the group's first word; pos and b
+// are wave-uniform.  Steps where every lane has a symbol run without the
+// lane mask; only the group's last, partial step keeps it.
 template <bool RES, typename V, typename LD>
 __device__ __forceinline__ bool dec_group(V *dst, int n, const uint2 *dtab, const uint16_t *slot_sym, uint16_t *rg,
-                                          uint32_t (&R)[4], int64_t b, int64_t pos, uint32_t x, int64_t w1,
+                                          uint32_t (&R)[4], uint32_t b, uint32_t pos, uint32_t x, uint32_t nw,
                                           const LD &ld, int lane) {
-    const int T = (n + 63) >> 6;
     bool bad = false;
-    for (int t = 0; t < T; ++t) {
+    auto step = [&](auto all, int t) {
+        constexpr bool ALL = decltype(all)::value;
         if (pos >= b + 256) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) rg[(b + 512 + k * 64 + lane) & 511] = (uint16_t)R[k];
@@ -504,22 +504,25 @@ __device__ __forceinline__ bool dec_group(V *dst, int n, const uint2 *dtab, cons
             for (int k = 0; k < 4; ++k) R[k] = ld(b + 512 + k * 64 + lane);
         }
         const int i = t * 64 + lane;
-        const bool have = i < n;
+        const bool have = ALL || i < n;
         const uint32_t slot = x & (ENT_M - 1);
         const uint2 e = dtab[slot_sym[slot]];
         const uint32_t xn = (e.x >> 16) * (x >> ENT_PB) + slot - (e.x & 0xFFFFu);
-        x = have ? xn : x;
+        x = ALL ? xn : (have ? xn : x);
         const bool ren = have && x < ENT_L;
-        const unsigned long long m = __ballot(ren);
-        const int64_t idx = pos + __popcll(m & ((1ull << lane) - 1ull));
-        const bool inside = idx < w1;
+        const uint64_t m = __builtin_amdgcn_ballot_w64(ren);
+        const uint32_t idx = pos + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        const bool inside = idx < nw;
         const uint32_t wv = rg[idx & 511];
         bad = bad || (ren && !inside);
         x = ren ? x << 16 | (inside ? wv : 0u) : x;
-        pos += __popcll(m);
-        if (have) dst[i] = RES ? (V)((int)e.y - 255) : (V)e.y;
-    }
-    return bad || pos != w1 || x != ENT_L;
+        pos += (uint32_t)__builtin_popcountll(m);
+        if (ALL || have) dst[i] = RES ? (V)((int)e.y - 255) : (V)e.y;
+    };
+    const int tfull = n >> 6;
+    for (int t = 0; t < tfull; ++t) step(std::true_type{}, t);
+    if (n & 63) step(std::false_type{}, tfull);
+    return bad || pos != nw || x != ENT_L;
 }
 
 // Decoder: ENT_DEC_WAVES groups of one plane per workgroup.  The workgroup
@@ -536,7 +539,7 @@ __global__ __launch_bounds__(256) void k_ent_dec(EntArgs a) {
     __shared__ __align__(16) uint16_t slot_sym[ENT_M];
     __shared__ uint32_t sh[4];
     __shared__ uint16_t ring[ENT_DEC_WAVES][512];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int G = a.G, gpp = (G + ENT_DEC_WAVES - 1) / ENT_DEC_WAVES;
     const int p = blockIdx.x / gpp, g = (blockIdx.x % gpp) * ENT_DEC_WAVES + w;
     const int nsym = p < 3 ? 511 : 256;
@@ -591,13 +594,14 @@ __global__ __launch_bounds__(256) void k_ent_dec(EntArgs a) {
     const uint64_t *start = reinterpret_cast<const uint64_t *>(a.code + ENT_HDR);
     const uint16_t *words = reinterpret_cast<const uint16_t *>(a.code + ENT_HDR + 32 * (int64_t)G);
     const uint64_t u0 = start[gi], u1 = gi + 1 < 4 * (int64_t)G ? start[gi + 1] : (uint64_t)a.nwords;
-    if (!(u0 <= u1 && u1 <= (uint64_t)a.nwords && u1 - u0 >= 128)) {
+    // a group holds its 128 state words and at most one word per symbol
+    if (!(u0 <= u1 && u1 <= (uint64_t)a.nwords && u1 - u0 >= 128 && u1 - u0 <= (uint64_t)ent_slot(a.log2_k))) {
         if (lane == 0 && a.status) atomicExch(a.status, RDL_ECORRUPT);
         return;
     }
-    const int64_t w0 = (int64_t)u0, w1 = (int64_t)u1;
-    uint32_t x = (uint32_t)words[w0 + 2 * lane] << 16 | words[w0 + 2 * lane + 1];
-    int64_t pos = w0 + 128;
+    const uint16_t *gw = words + u0;  // the group's words
+    const uint32_t nw = (uint32_t)(u1 - u0);
+    uint32_t x = (uint32_t)gw[2 * lane] << 16 | gw[2 * lane + 1];
     // The wave's words [b, b + 512) sit in an LDS ring (slot = position mod 512)
     // and the next 256 in registers; once the first half is consumed the
     // registers refill it and load the following 256.  A step consumes at
@@ -605,10 +609,10 @@ __global__ __launch_bounds__(256) void k_ent_dec(EntArgs a) {
     // Words past the group's end read as 0 and are never consumed by a
     // well-formed group.
     uint16_t *rg = ring[w];
-    int64_t b = pos;
-    auto ld = [&](int64_t q) -> uint32_t {
-        const uint32_t v = words[q < w1 ? q : w1 - 1];  // clamped: w1 - 1 >= w0 + 127
-        return q < w1 ? v : 0u;
+    const uint32_t pos = 128, b = 128;
+    auto ld = [&](uint32_t q) -> uint32_t {
+        const uint32_t v = gw[q < nw ? q : nw - 1];  // clamped: nw - 1 >= 127
+        return q < nw ? v : 0u;
     };
 #pragma unroll
     for (int k = 0; k < 8; ++k) rg[(b + k * 64 + lane) & 511] = (uint16_t)ld(b + k * 64 + lane);
@@ -620,9 +624,9 @@ __global__ __launch_bounds__(256) void k_ent_dec(EntArgs a) {
     bool bad;
     if (p < 3)
         bad = dec_group<true>(reinterpret_cast<int16_t *>(a.dst) + p * a.N + base, n, dtab, slot_sym, rg, R, b, pos,
-                              x, w1, ld, lane);
+                              x, nw, ld, lane);
     else
-        bad = dec_group<false>(a.dst + 6 * a.N + base, n, dtab, slot_sym, rg, R, b, pos, x, w1, ld, lane);
+        bad = dec_group<false>(a.dst + 6 * a.N + base, n, dtab, slot_sym, rg, R, b, pos, x, nw, ld, lane);
     if (__ballot(bad) && lane == 0 && a.status) atomicExch(a.status, RDL_ECORRUPT);
 }
 
