@@ -408,7 +408,7 @@ __device__ __forceinline__ void enc_group(const V *src, int n, const uint2 *tb, 
 
 __global__ __launch_bounds__(256) void k_ent_enc(EntArgs a) {
     __shared__ uint2 stab[4][512];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int G = a.G;
     const int64_t gi = (int64_t)blockIdx.x * 4 + w;
     const bool live = gi < 4 * (int64_t)G;
