@@ -321,9 +321,9 @@ int rdl_jpeg_encode(rdl_ctx *ctx, const int16_t *dct, int H, int W, int q, uint8
  * its first RDL_ENT_HEADER_BYTES bytes, which is validated first (magic,
  * version, sizes, log2_k, G, frequency sums, total <= len: RDL_ECORRUPT) ->
  * out_resid (device, rdl_resid_bytes(H, W), 2-byte aligned); a stream with
- * flags bit 0 uses the context's workspace (8 bytes per 4096 pixels) to sum
- * the differences back, so it must not overlap other calls on the context
- * either.  If status
+ * flags bit 0 uses the context's workspace (about one byte per pixel: the
+ * differences, summed back along each row into out_resid), so it must not
+ * overlap other calls on the context either.  If status
  * (device int32, may be NULL) is given it receives RDL_OK, or RDL_ECORRUPT
  * when the device copy's tables or a group's offsets or words do not decode
  * exactly (every read stays inside the stream). */

@@ -668,6 +668,10 @@ int rdl_ent_decode(rdl_ctx *c, const void *code, size_t len, const void *header,
     EntArgs a = ent_args(c, H, W, log2_k);
     a.flags = (int32_t)w[7];
     a.eagg = reinterpret_cast<uint32_t *>(c->d_ent + ent_cnt_off());
+    {
+        uint8_t *e = (uint8_t *)out_resid + 6 * (int64_t)H * W;
+        a.dplane = a.flags ? c->d_ent + ent_dplane_off((int64_t)H * W) + (reinterpret_cast<uintptr_t>(e) & 15) : e;
+    }
     a.code = (const uint8_t *)code;
     a.dst = (uint8_t *)out_resid;
     a.status = status;

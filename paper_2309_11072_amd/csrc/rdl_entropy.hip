@@ -10,9 +10,9 @@
 // (plane histograms) -> k_ent_freq (frequencies, header) -> k_ent_enc (one
 // wave per group, words in emission order into a workspace) -> k_ent_scan
 // (group offsets) -> k_ent_pack (each group's words reversed into place).
-// Decoder: k_ent_dec (tables in LDS, one wave per group) [-> k_ent_eseg,
-// k_ent_ecarry, k_ent_eundo: the differences summed back along each row, a
-// segmented prefix sum].
+// Decoder: k_ent_dec (tables in LDS, one wave per group) [-> (k_ent_eseg,
+// k_ent_ecarry: rows wider than a tile) -> k_ent_eundo: the differences
+// summed back along each row, a segmented prefix sum].
 // Everything is integer arithmetic except the encoder's division by a
 // frequency, which takes a float reciprocal estimate and corrects it to the
 // exact quotient.
@@ -626,7 +626,7 @@ __global__ __launch_bounds__(256) void k_ent_dec(EntArgs a) {
         bad = dec_group<true>(reinterpret_cast<int16_t *>(a.dst) + p * a.N + base, n, dtab, slot_sym, rg, R, b, pos,
                               x, nw, ld, lane);
     else
-        bad = dec_group<false>(a.dst + 6 * a.N + base, n, dtab, slot_sym, rg, R, b, pos, x, nw, ld, lane);
+        bad = dec_group<false>(a.dplane + base, n, dtab, slot_sym, rg, R, b, pos, x, nw, ld, lane);
     if (__ballot(bad) && lane == 0 && a.status) atomicExch(a.status, RDL_ECORRUPT);
 }
 
@@ -770,20 +770,28 @@ __global__ __launch_bounds__(1024) void k_ent_ecarry(const uint32_t *__restrict_
     }
 }
 
-// E along each row from d, in place: a lane reads its own chunk before it
-// writes it, and no lane reads another's.  The value carried into tile b is
-// the join of the tiles before it; when rows are at most ENT_ETILE pixels
-// wide (direct), tile b - 1 holds a row start (tile 0 holds pixel 0, any
-// other is ENT_ETILE consecutive pixels), so that join is tile b - 1's value
-// and the carry scan is skipped.
-__global__ __launch_bounds__(256) void k_ent_eundo(uint8_t *e, int64_t N, int W, const uint32_t *__restrict__ seg,
-                                                   const uint32_t *__restrict__ carry, int direct) {
+// E along each row from d (src, in the workspace) into the layer's plane
+// (dst, at the same address mod 16).  The value carried into tile b is the
+// join of the tiles before it.  When rows are at most ENT_ETILE pixels wide
+// (direct), tile b - 1 holds a row start (tile 0 holds pixel 0, any other is
+// ENT_ETILE consecutive pixels), so that join is tile b - 1's own value: the
+// workgroup reads tile b - 1 as well and no separate pass is needed.
+// Otherwise the carry comes from k_ent_eseg and k_ent_ecarry.
+__global__ __launch_bounds__(256) void k_ent_eundo(const uint8_t *__restrict__ src, uint8_t *__restrict__ dst,
+                                                   int64_t N, int W, const uint32_t *__restrict__ carry, int direct) {
     __shared__ uint32_t sh[4];
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     EChunk c;
-    echunk_load(e, N, W, (int64_t)blockIdx.x * 256 + threadIdx.x, c);
-    uint32_t tot;
+    echunk_load(src, N, W, t, c);
+    uint32_t cin = 0, tot;
+    if (!direct) {
+        cin = carry[blockIdx.x];
+    } else if (blockIdx.x > 0) {
+        EChunk pc;
+        echunk_load(src, N, W, t - 256, pc);
+        seg_excl_scan<4>(echunk_seg(pc, N, W), sh, cin);
+    }
     const uint32_t ex = seg_excl_scan<4>(echunk_seg(c, N, W), sh, tot);
-    const uint32_t cin = direct ? (blockIdx.x ? seg[blockIdx.x - 1] : 0u) : carry[blockIdx.x];
     uint32_t acc = seg_join(cin, ex) & 255u, col = c.col0, o[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
@@ -791,7 +799,7 @@ __global__ __launch_bounds__(256) void k_ent_eundo(uint8_t *e, int64_t N, int W,
         o[k] = acc;
         col = col + 1 == (uint32_t)W ? 0u : col + 1;
     }
-    echunk_store(e, N, c, o);
+    echunk_store(dst, N, c, o);
 }
 
 }  // namespace
@@ -825,9 +833,11 @@ void launch_ent_decode(const EntArgs &a, hipStream_t s) {
         uint8_t *e = a.dst + 6 * a.N;
         const int64_t nt = ent_etiles(a.N, (int)(reinterpret_cast<uintptr_t>(e) & 15));
         const int direct = a.W <= ENT_ETILE;
-        hipLaunchKernelGGL(k_ent_eseg, dim3((unsigned)nt), dim3(256), 0, s, e, a.N, a.W, a.eagg);
-        if (!direct) hipLaunchKernelGGL(k_ent_ecarry, dim3(1), dim3(1024), 0, s, a.eagg, a.eagg + nt, nt);
-        hipLaunchKernelGGL(k_ent_eundo, dim3((unsigned)nt), dim3(256), 0, s, e, a.N, a.W, a.eagg, a.eagg + nt,
+        if (!direct) {
+            hipLaunchKernelGGL(k_ent_eseg, dim3((unsigned)nt), dim3(256), 0, s, a.dplane, a.N, a.W, a.eagg);
+            hipLaunchKernelGGL(k_ent_ecarry, dim3(1), dim3(1024), 0, s, a.eagg, a.eagg + nt, nt);
+        }
+        hipLaunchKernelGGL(k_ent_eundo, dim3((unsigned)nt), dim3(256), 0, s, a.dplane, e, a.N, a.W, a.eagg + nt,
                            direct);
     }
 }

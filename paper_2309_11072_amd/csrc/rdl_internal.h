@@ -133,6 +133,7 @@ struct EntArgs {
     const uint8_t *eplane;  // encoder: plane 3's symbols (the exponents, or their left differences)
     uint8_t *ediff;         // encoder: where the left differences go (workspace, 16-byte aligned)
     uint32_t *eagg;         // decoder: [2][tiles] segment values of the inverse (workspace)
+    uint8_t *dplane;        // decoder: where plane 3's symbols go (the layer, or the workspace)
     int32_t flags;          // bit 0: plane 3 holds left differences
     uint8_t *out;           // encoder: the code stream
     const uint8_t *code;    // decoder: the code stream
@@ -167,8 +168,10 @@ inline size_t ent_ws_bytes(int H, int W, int log2_k) {
 // Workgroups of the left-difference kernels: 256 lanes of one 16-byte chunk.
 constexpr int ENT_ETILE = 4096;
 inline int64_t ent_etiles(int64_t N, int lead) { return (N + lead + ENT_ETILE - 1) / ENT_ETILE; }
-// The decoder's workspace: the segment values of the inverse, after EntWs.
-inline size_t ent_dec_ws_bytes(int64_t N) { return ent_cnt_off() + 8 * (size_t)ent_etiles(N, 15); }
+// The decoder's workspace: the segment values of the inverse after EntWs,
+// then the exponents' differences (at the plane's lead, as in the encoder).
+inline size_t ent_dplane_off(int64_t N) { return (ent_cnt_off() + 8 * (size_t)ent_etiles(N, 15) + 255) & ~(size_t)255; }
+inline size_t ent_dec_ws_bytes(int64_t N) { return ent_dplane_off(N) + (((size_t)N + 16 + 255) & ~(size_t)255); }
 void launch_ent_encode(const EntArgs &a, hipStream_t s);
 void launch_ent_decode(const EntArgs &a, hipStream_t s);
 
