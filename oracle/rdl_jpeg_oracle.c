@@ -24,8 +24,11 @@
  *     Annex C (Figures C.1 to C.3);
  *   - bytes of the entropy-coded data are written MSB first, each 0xFF byte
  *     followed by a stuffed 0x00, and a scan's last byte padded with 1-bits.
- * Reading where the standard leaves a choice: when Figure K.1 meets two
- * symbols of equal least count it takes the one with the larger value.
+ * Readings where the standard leaves a choice: when Figure K.1 meets two
+ * symbols of equal least count it takes the one with the larger value; where
+ * Figure K.1 gives code sizes above 32 (a chain of counts each about twice
+ * the one before, totals above 2^32), the size histogram and Figure K.3's
+ * loop extend to the longest size instead of stopping at 32.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -67,7 +70,7 @@ static int ssss(int v)
 int oracle_jpeg_huff_table(const int64_t *freq_in, uint8_t bits[17], uint8_t huffval[256])
 {
     int64_t freq[257];
-    int codesize[257], others[257], nb[33];
+    int codesize[257], others[257], nb[258];
     for (int i = 0; i < 256; i++) freq[i] = freq_in[i];
     freq[256] = 1;
     for (int i = 0; i < 257; i++) {
@@ -95,10 +98,16 @@ int oracle_jpeg_huff_table(const int64_t *freq_in, uint8_t bits[17], uint8_t huf
             codesize[v2]++;
         }
     }
+    /* Figure K.2's size histogram runs to the longest size K.1 gave (at most
+     * 256): cut at 32, as the figure's arrays are, the sizes above would no
+     * longer pair up as siblings and Figure K.3 would not yield a code */
     memset(nb, 0, sizeof nb);
-    for (int i = 0; i < 257; i++)
-        if (codesize[i]) nb[codesize[i] > 32 ? 32 : codesize[i]]++;
-    for (int i = 32; i > 16; i--)  /* Figure K.3 */
+    int maxlen = 0;
+    for (int i = 0; i < 257; i++) {
+        if (codesize[i]) nb[codesize[i]]++;
+        if (codesize[i] > maxlen) maxlen = codesize[i];
+    }
+    for (int i = maxlen; i > 16; i--)  /* Figure K.3 */
         while (nb[i] > 0) {
             int j = i - 2;
             while (nb[j] == 0) j--;
@@ -113,7 +122,7 @@ int oracle_jpeg_huff_table(const int64_t *freq_in, uint8_t bits[17], uint8_t huf
     memset(bits, 0, 17);
     for (int k = 1; k <= 16; k++) bits[k] = (uint8_t)nb[k];
     int n = 0;
-    for (int len = 1; len <= 32; len++)  /* Figure K.4 */
+    for (int len = 1; len <= maxlen; len++)  /* Figure K.4 */
         for (int s = 0; s < 256; s++)
             if (codesize[s] == len) huffval[n++] = (uint8_t)s;
     int total = 0;

@@ -149,9 +149,11 @@ __global__ __launch_bounds__(JPG_BLK_WG) void k_jpg_count(JpgArgs a) {
 }  // namespace rdl
 // The device library's wave reduction (DPP; every lane must be active).
 extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_min_u64(unsigned long long);
+extern "C" __device__ __attribute__((const)) unsigned int __ockl_wfred_min_u32(unsigned int);
 namespace rdl {
 namespace {
-__device__ __forceinline__ unsigned long long wave_min64(unsigned long long v) { return __ockl_wfred_min_u64(v); }
+__device__ __forceinline__ unsigned long long wave_min(unsigned long long v) { return __ockl_wfred_min_u64(v); }
+__device__ __forceinline__ unsigned int wave_min(unsigned int v) { return __ockl_wfred_min_u32(v); }
 
 __device__ __forceinline__ void put_be16(uint8_t *p, int v) {
     p[0] = (uint8_t)(v >> 8);
@@ -159,8 +161,7 @@ __device__ __forceinline__ void put_be16(uint8_t *p, int v) {
 }
 
 __global__ __launch_bounds__(256) void k_jpg_tables(JpgArgs a) {
-    __shared__ int s_cs[4][256];
-    __shared__ int s_nb[4][34];
+    __shared__ int s_nb[4][258];
     __shared__ uint8_t s_hv[4][256];
     __shared__ int s_n[4];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;  // table w: t = w >> 1, ac = w & 1
@@ -176,56 +177,88 @@ __global__ __launch_bounds__(256) void k_jpg_tables(JpgArgs a) {
         grp[j] = i;
         cs[j] = 0;
     }
-    for (int i = lane; i < 34; i += 64) s_nb[w][i] = 0;
-    // Figure K.1
-    for (;;) {
-        unsigned long long k1 = ~0ull;
+    for (int i = lane; i < 258; i += 64) s_nb[w][i] = 0;
+    // Figure K.1.  A group's key is (count, 511 - representative): the least
+    // key is the least count, ties to the larger symbol.  Keys fit 32 bits
+    // when the table's total count is below 2^22 (every group count is then
+    // below it, and no key reaches the all-ones "none"), else 64.
+    uint64_t total = 0;
 #pragma unroll
-        for (int j = 0; j < 5; ++j) {
-            const unsigned long long key = f[j] << 9 | (uint64_t)(511 - (lane + 64 * j));
-            k1 = (f[j] && key < k1) ? key : k1;
-        }
-        k1 = wave_min64(k1);
-        const int v1 = 511 - (int)(k1 & 511);
-        unsigned long long k2 = ~0ull;
-#pragma unroll
-        for (int j = 0; j < 5; ++j) {
-            const int i = lane + 64 * j;
-            const unsigned long long key = f[j] << 9 | (uint64_t)(511 - i);
-            k2 = (f[j] && i != v1 && key < k2) ? key : k2;
-        }
-        k2 = wave_min64(k2);
-        if (k2 == ~0ull) break;  // uniform
-        const int v2 = 511 - (int)(k2 & 511);
-        // the group labels of v1 and v2 from their owner lanes
-        int l1 = 0, l2 = 0;
-#pragma unroll
-        for (int j = 0; j < 5; ++j) {
-            l1 = (v1 >> 6) == j ? grp[j] : l1;
-            l2 = (v2 >> 6) == j ? grp[j] : l2;
-        }
-        const int g1 = __shfl(l1, v1 & 63, 64), g2 = __shfl(l2, v2 & 63, 64);
-#pragma unroll
-        for (int j = 0; j < 5; ++j) {
-            const int i = lane + 64 * j;
-            if (grp[j] == g1 || grp[j] == g2) {
-                cs[j] += 1;
-                grp[j] = g1;
-            }
-            if (i == v1) f[j] += k2 >> 9;
-            if (i == v2) f[j] = 0;
-        }
+    for (int j = 0; j < 5; ++j) total += f[j];
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)total, off, 64), hi = __shfl_xor((uint32_t)(total >> 32), off, 64);
+        total += (uint64_t)hi << 32 | lo;
     }
+    auto merge_all = [&](auto key_type) {
+        using KT = decltype(key_type);
+        constexpr KT NONE = (KT)~(KT)0;
+        for (;;) {
+            KT k1 = NONE;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) s_cs[w][lane + 64 * j] = cs[j];
-    __syncthreads();
-    // sizes histogram, Figure K.3, the reserved point dropped
+            for (int j = 0; j < 5; ++j) {
+                const KT key = (KT)f[j] << 9 | (KT)(511 - (lane + 64 * j));
+                k1 = (f[j] && key < k1) ? key : k1;
+            }
+            k1 = wave_min(k1);
+            const int v1 = 511 - (int)(k1 & 511);
+            KT k2 = NONE;
+#pragma unroll
+            for (int j = 0; j < 5; ++j) {
+                const int i = lane + 64 * j;
+                const KT key = (KT)f[j] << 9 | (KT)(511 - i);
+                k2 = (f[j] && i != v1 && key < k2) ? key : k2;
+            }
+            k2 = wave_min(k2);
+            if (k2 == NONE) break;  // uniform
+            const int v2 = 511 - (int)(k2 & 511);
+            // Only a group's representative (the symbol holding its count) has
+            // a count, and a group's label is its representative: true at the
+            // start, and a merge relabels v2's group to v1.  So v1 and v2 are
+            // the labels of the two groups.
+#pragma unroll
+            for (int j = 0; j < 5; ++j) {
+                const int i = lane + 64 * j;
+                if (grp[j] == v1 || grp[j] == v2) {
+                    cs[j] += 1;
+                    grp[j] = v1;
+                }
+                if (i == v1) f[j] += (uint64_t)(k2 >> 9);
+                if (i == v2) f[j] = 0;
+            }
+        }
+    };
+    if (total < (1u << 22))
+        merge_all(0u);
+    else
+        merge_all(0ull);
+    // Figure K.2's size histogram and Figure K.4's list, by ballots over the
+    // 64-symbol chunks, up to the longest size (at most 256: cut at 32, as
+    // the figure's arrays are, sizes above would no longer pair up and
+    // Figure K.3 would not yield a code); the reserved point (symbol 256,
+    // lane 0's fifth entry) is counted, not listed.
+    int maxlen = 0;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) maxlen = max(maxlen, cs[j]);
+    for (int off = 32; off > 0; off >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, off, 64));
+    int nsym = 0;
+    for (int len = 1; len <= maxlen; ++len) {
+        int cnt = 0;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            const bool in = cs[j] == len;
+            const unsigned long long m = __ballot(in);
+            if (j < 4) {
+                if (in) s_hv[w][nsym + __popcll(m & ((1ull << lane) - 1ull))] = (uint8_t)(lane + 64 * j);
+                nsym += __popcll(m);
+            }
+            cnt += __popcll(m);
+        }
+        if (lane == 0) s_nb[w][len] = cnt;
+    }
+    // Figure K.3 (sizes above 16 cut), then the reserved point dropped
     if (lane == 0) {
         int *nb = s_nb[w];
-        for (int i = 0; i < 256; ++i)
-            if (s_cs[w][i]) nb[min(s_cs[w][i], 32)] += 1;
-        if (cs[4]) nb[min(cs[4], 32)] += 1;  // the reserved point (symbol 256 is lane 0's fifth)
-        for (int i = 32; i > 16; --i)
+        for (int i = maxlen; i > 16; --i)
             while (nb[i] > 0) {
                 int j = i - 2;
                 while (nb[j] == 0) --j;
@@ -237,29 +270,20 @@ __global__ __launch_bounds__(256) void k_jpg_tables(JpgArgs a) {
         int i = 16;
         while (i > 1 && nb[i] == 0) --i;
         if (nb[i] > 0) nb[i] -= 1;
+        s_n[w] = nsym;
     }
-    // Figure K.4: symbols listed by (size, value), with ballots over 64-symbol
-    // chunks; the symbol of rank r takes the r-th code of the bits[] list
-    int nsym = 0;
-    for (int len = 1; len <= 32; ++len) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const bool in = cs[j] == len;
-            const unsigned long long m = __ballot(in);
-            if (in) s_hv[w][nsym + __popcll(m & ((1ull << lane) - 1ull))] = (uint8_t)(lane + 64 * j);
-            nsym += __popcll(m);
-        }
-    }
-    if (lane == 0) s_n[w] = nsym;
     __syncthreads();
-    // Annex C: canonical codes by rank; code | size << 16 per symbol
-    if (lane == 0) {
+    // Annex C: canonical codes by rank, code | size << 16 per symbol; the
+    // rank-r symbol of size len takes the first code of that size + its place
+    {
         uint32_t code = 0;
-        int r = 0;
+        int r0 = 0;
         for (int len = 1; len <= 16; ++len) {
-            for (int j = 0; j < s_nb[w][len]; ++j, ++r)
-                if (r < nsym) a.ws->code[t][ac][s_hv[w][r]] = code++ | (uint32_t)len << 16;
-            code <<= 1;
+            const int nl = s_nb[w][len];
+            for (int r = r0 + lane; r < r0 + nl; r += 64)
+                if (r < nsym) a.ws->code[t][ac][s_hv[w][r]] = (code + (uint32_t)(r - r0)) | (uint32_t)len << 16;
+            code = (code + (uint32_t)nl) << 1;
+            r0 += nl;
         }
     }
     // File header: SOI, APP0, DQT, SOF0, DHT (wave 0 writes the fixed part,

@@ -100,3 +100,18 @@ def test_batched_encoder_writes_the_coefficients(codec, O):
     jpg, hdr, code = codec.encode_files(d, q)
     assert jpg.cpu().numpy().tobytes() == O.jpeg_write(items[1][5].cpu().numpy(), H, W, q)
     assert torch.equal(codec.ent_decode(code, H, W), items[1][4])
+
+
+def test_large_counts_take_64_bit_keys(codec, O):
+    """At q = 100 the chroma AC table of a 3840 x 2160 image counts more than
+    2^22 symbols (one per nonzero AC coefficient at least), so the table
+    builder keys its merges with 64-bit values instead of 32-bit ones; the
+    file must still equal the oracle's."""
+    H, W, q = 2160, 3840, 100
+    _say("jpeg 64-bit keys", H, W, q)
+    sdr, dct = coefficients(codec, H, W, q, 4242)
+    d = dct.cpu().numpy()
+    ac = d[1:].reshape(2, H // 8, 8, W // 8, 8).transpose(0, 1, 3, 2, 4).reshape(2, -1, 64)[:, :, 1:]
+    assert int((ac != 0).sum()) >= 1 << 22
+    jp = codec.jpeg_encode(dct, H, W, q).cpu().numpy().tobytes()
+    assert jp == O.jpeg_write(d, H, W, q)

@@ -137,6 +137,20 @@ def test_huffman_lengths_are_limited_to_16(O):
     assert sum(2.0 ** -L for L in lens.values()) < 1.0
 
 
+def test_code_sizes_above_32_are_listed(O):
+    """Counts 1, 2, 4, ..., 2^39 (40 symbols; with the reserved point each
+    merge joins the chain to the next symbol) make Figure K.1's code sizes
+    run to 40, past 32, where Figure K.2's arrays end; with the histogram and
+    Figure K.3 extended to the longest size every symbol is listed once, with
+    a code of at most 16 bits, and the code stays prefix-free."""
+    freq = np.zeros(256, np.int64)
+    freq[:40] = 2 ** np.arange(40, dtype=np.int64)
+    bits, hv = O.jpeg_huff_table(freq)
+    lens = _code_lengths(bits, hv)
+    assert sorted(lens) == list(range(40)) and max(lens.values()) <= 16
+    assert sum(2.0 ** -L for L in lens.values()) < 1.0
+
+
 def test_codes_are_canonical_and_prefix_free(O):
     rng = np.random.default_rng(3)
     freq = np.zeros(256, np.int64)
