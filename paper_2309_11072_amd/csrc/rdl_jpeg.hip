@@ -116,22 +116,28 @@ __device__ __forceinline__ void block_symbols(const int v[64], int pred, F &&f) 
 }
 
 // ---------------------------------------------------------------------------
-// Symbol counts: one thread per block; table 0 = Y, 1 = Cb and Cr.
+// Symbol counts: one thread per block; table 0 = Y, 1 = Cb and Cr.  A few
+// symbols (EOB, the small sizes) take most counts, so lane l counts into copy
+// l mod JPG_HC, the copies of a bin in adjacent words (different banks).
+constexpr int JPG_HC = 8;
 __global__ __launch_bounds__(JPG_BLK_WG) void k_jpg_count(JpgArgs a) {
-    __shared__ uint32_t h[2][2][256];
-    for (int k = threadIdx.x; k < 2 * 2 * 256; k += JPG_BLK_WG) (&h[0][0][0])[k] = 0;
+    __shared__ uint32_t h[2][2][256][JPG_HC];
+    for (int k = threadIdx.x; k < 2 * 2 * 256 * JPG_HC; k += JPG_BLK_WG) (&h[0][0][0][0])[k] = 0;
     __syncthreads();
     const Geo g = geo(a);
     const int c = blockIdx.x / g.wpc, k = (blockIdx.x - c * g.wpc) * JPG_BLK_WG + threadIdx.x;
     const int t = c ? 1 : 0;
+    const int cp = threadIdx.x & (JPG_HC - 1);
     if (k < g.nblk) {
         int v[64], pred;
         load_block(a, g, c, k, v, pred);
-        block_symbols(v, pred, [&](int ac, int sym, uint32_t, int) { atomicAdd(&h[t][ac][sym], 1u); });
+        block_symbols(v, pred, [&](int ac, int sym, uint32_t, int) { atomicAdd(&h[t][ac][sym][cp], 1u); });
     }
     __syncthreads();
     for (int i = threadIdx.x; i < 2 * 2 * 256; i += JPG_BLK_WG) {
-        const uint32_t x = (&h[0][0][0])[i];
+        uint32_t x = 0;
+#pragma unroll
+        for (int q = 0; q < JPG_HC; ++q) x += (&h[0][0][0][0])[i * JPG_HC + q];
         if (x) atomicAdd(&a.ws->cnt[0][0][0] + i, x);
     }
 }
