@@ -99,6 +99,7 @@ __device__ __forceinline__ void block_symbols(const int v[64], int pred, F &&f) 
     int s = ssss(diff);
     f(0, s, (uint32_t)(diff < 0 ? diff - 1 : diff) & ((1u << s) - 1u), s);
     int run = 0;
+#pragma unroll
     for (int k = 1; k < 64; ++k) {
         if (v[k] == 0) {
             ++run;
