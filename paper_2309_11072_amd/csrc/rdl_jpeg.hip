@@ -484,18 +484,33 @@ __global__ __launch_bounds__(JPG_BLK_WG) void k_jpg_emit(JpgArgs a) {
 
 // 0xFF bytes per chunk of JPG_CHUNK raw bytes of each scan.
 // (A fixed grid walks the chunks that hold data.)
+// Bytes [b0, b0 + 16) of a scan's raw bits (nbytes > 0), from four word
+// loads whose indices are clamped to the scan's last word, so every load is
+// issued unconditionally; bytes past the scan read as 0.
+__device__ __forceinline__ void raw16(const uint32_t *w, uint64_t nbytes, uint64_t b0, uint32_t (&by)[16]) {
+    const uint64_t last = (nbytes + 3) / 4 - 1;
+    uint32_t x[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const uint64_t q = b0 / 4 + m;
+        x[m] = w[q < last ? q : last];
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) by[i] = b0 + i < nbytes ? (x[i >> 2] >> (8 * (i & 3))) & 255u : 0u;
+}
+
 __global__ __launch_bounds__(256) void k_jpg_ffcount(JpgArgs a) {
+    static_assert(JPG_CHUNK == 256 * 16, "one 16-byte piece per lane and chunk");
     __shared__ uint32_t sh[4];
     for (int c = 0; c < 3; ++c) {
         const uint64_t nbytes = (a.ws->bits[c] + 7) / 8;
         const int64_t nch = (int64_t)((nbytes + JPG_CHUNK - 1) / JPG_CHUNK);
-        const uint8_t *raw = reinterpret_cast<const uint8_t *>(a.raw + a.ws->raw_word[c]);
+        const uint32_t *raw = a.raw + a.ws->raw_word[c];
         for (int64_t j = blockIdx.x; j < nch; j += gridDim.x) {
-            uint32_t n = 0;
-            for (int i = threadIdx.x; i < JPG_CHUNK; i += 256) {
-                const uint64_t b = (uint64_t)j * JPG_CHUNK + i;
-                if (b < nbytes && raw[b] == 0xFF) ++n;
-            }
+            uint32_t n = 0, by[16];
+            raw16(raw, nbytes, (uint64_t)j * JPG_CHUNK + (uint64_t)threadIdx.x * 16, by);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) n += by[i] == 0xFFu ? 1u : 0u;
             for (int off = 32; off > 0; off >>= 1) n += __shfl_xor(n, off, 64);
             __syncthreads();
             if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = n;
@@ -566,16 +581,17 @@ __global__ __launch_bounds__(256) void k_jpg_stuff(JpgArgs a) {
     for (int c = 0; c < 3; ++c) {
         const uint64_t nbytes = (a.ws->bits[c] + 7) / 8;
         const int64_t nch = (int64_t)((nbytes + JPG_CHUNK - 1) / JPG_CHUNK);
-        const uint8_t *raw = reinterpret_cast<const uint8_t *>(a.raw + a.ws->raw_word[c]);
+        const uint32_t *raw = a.raw + a.ws->raw_word[c];
         for (int64_t j = blockIdx.x; j < nch; j += gridDim.x) {
             const uint64_t b0 = (uint64_t)j * JPG_CHUNK + (uint64_t)threadIdx.x * 16;
-            uint8_t by[16];
+            uint32_t by[16];
             uint32_t n = 0;
+            if (b0 < nbytes) raw16(raw, nbytes, b0, by);
+            else
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                by[i] = b0 + i < nbytes ? raw[b0 + i] : 0;
-                n += (b0 + i < nbytes && by[i] == 0xFF) ? 1u : 0u;
-            }
+                for (int i = 0; i < 16; ++i) by[i] = 0u;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) n += by[i] == 0xFFu ? 1u : 0u;
             const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
             uint32_t inc = n;
             for (int off = 1; off < 64; off <<= 1) {
@@ -591,8 +607,8 @@ __global__ __launch_bounds__(256) void k_jpg_stuff(JpgArgs a) {
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 if (b0 + i < nbytes) {
-                    a.out[at++] = by[i];
-                    if (by[i] == 0xFF) a.out[at++] = 0;
+                    a.out[at++] = (uint8_t)by[i];
+                    if (by[i] == 0xFFu) a.out[at++] = 0;
                 }
             }
         }
