@@ -200,22 +200,20 @@ __global__ __launch_bounds__(256) void k_jpg_tables(JpgArgs a) {
         using KT = decltype(key_type);
         constexpr KT NONE = (KT)~(KT)0;
         for (;;) {
-            KT k1 = NONE;
+            // the lane's least and second least keys; the second least of the
+            // wave is the owner lane's second or another lane's least (keys
+            // are distinct)
+            KT m1 = NONE, m2 = NONE;
 #pragma unroll
             for (int j = 0; j < 5; ++j) {
                 const KT key = (KT)f[j] << 9 | (KT)(511 - (lane + 64 * j));
-                k1 = (f[j] && key < k1) ? key : k1;
+                const bool lt1 = f[j] && key < m1, lt2 = f[j] && !lt1 && key < m2;
+                m2 = lt1 ? m1 : (lt2 ? key : m2);
+                m1 = lt1 ? key : m1;
             }
-            k1 = wave_min(k1);
+            const KT k1 = wave_min(m1);
             const int v1 = 511 - (int)(k1 & 511);
-            KT k2 = NONE;
-#pragma unroll
-            for (int j = 0; j < 5; ++j) {
-                const int i = lane + 64 * j;
-                const KT key = (KT)f[j] << 9 | (KT)(511 - i);
-                k2 = (f[j] && i != v1 && key < k2) ? key : k2;
-            }
-            k2 = wave_min(k2);
+            const KT k2 = wave_min(m1 == k1 ? m2 : m1);
             if (k2 == NONE) break;  // uniform
             const int v2 = 511 - (int)(k2 & 511);
             // Only a group's representative (the symbol holding its count) has
