@@ -115,3 +115,33 @@ def test_large_counts_take_64_bit_keys(codec, O):
     assert int((ac != 0).sum()) >= 1 << 22
     jp = codec.jpeg_encode(dct, H, W, q).cpu().numpy().tobytes()
     assert jp == O.jpeg_write(d, H, W, q)
+
+
+def test_coefficients_in_graph_mode(codec):
+    """The coefficient output through a captured graph: two replays with the
+    coefficients cleared in between (eager work between them) equal the
+    direct launch's; a plan without coefficients stays a plan of its own."""
+    H, W, q = 217, 301, 70
+    d = torch.from_numpy(synth.generate(H, W, 3.5, seed=77, spec_frac=0.05)).cuda()
+    shape = (3, (H + 7) // 8 * 8, (W + 7) // 8 * 8)
+    sdr, hdr, resid = codec.alloc_outputs(H, W)
+    want = torch.zeros(shape, dtype=torch.int16, device="cuda")
+    codec.encode_batch([(d, q, sdr, hdr, resid, want)])
+    torch.cuda.synchronize()
+    codec.set_launch_mode(graph=True)
+    try:
+        dct = torch.zeros(shape, dtype=torch.int16, device="cuda")
+        s2, h2, r2 = codec.alloc_outputs(H, W)
+        for rep in range(2):
+            dct.fill_(7)
+            torch.cuda.synchronize()
+            codec.encode_batch([(d, q, s2, h2, r2, dct)])
+            torch.cuda.synchronize()
+            assert torch.equal(dct, want), rep
+            assert torch.equal(s2, sdr) and torch.equal(r2, resid)
+        dct.fill_(7)
+        codec.encode_batch([(d, q, s2, h2, r2)])  # no coefficients: its own plan
+        torch.cuda.synchronize()
+        assert bool((dct == 7).all()) and torch.equal(r2, resid)
+    finally:
+        codec.set_launch_mode(graph=False)
