@@ -165,16 +165,20 @@ __global__ __launch_bounds__(256) void k_train_grad(const float *__restrict__ pr
 }
 
 // Sums the nwg partial gradients of each parameter in order and applies Adam.
+// b1, b2 and their complements ob1 = 1 - b1, ob2 = 1 - b2 are the float32
+// values nearest the exact ones (a complement taken in float32 from a rounded
+// b2 = 0.999 would be off by 1.3e-5 relative); c1, c2 are the bias
+// corrections 1 / (1 - b^step), also rounded once from their exact values.
 __global__ __launch_bounds__(256) void k_train_adam(float *__restrict__ prm, float *__restrict__ m1, float *__restrict__ m2,
                                                     const float *__restrict__ part, const float *__restrict__ ploss,
-                                                    int nwg, float lr, float b1, float b2, float eps, float c1, float c2,
-                                                    float *__restrict__ loss_out) {
+                                                    int nwg, float lr, float b1, float b2, float ob1, float ob2,
+                                                    float eps, float c1, float c2, float *__restrict__ loss_out) {
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p < NPARAM) {
         float g = 0.0f;
         for (int k = 0; k < nwg; ++k) g += part[(int64_t)k * NPARAM + p];
-        const float a = b1 * m1[p] + (1.0f - b1) * g;
-        const float v = b2 * m2[p] + (1.0f - b2) * (g * g);
+        const float a = b1 * m1[p] + ob1 * g;
+        const float v = b2 * m2[p] + ob2 * (g * g);
         m1[p] = a;
         m2[p] = v;
         prm[p] -= lr * (a * c1) / (sqrtf(v * c2) + eps);
@@ -199,10 +203,10 @@ void launch_train_step(float *prm, float *m1, float *m2, const void *smp, int64_
     const float inv = 1.0f / (3.0f * (float)(avail > 0 ? avail : 1));
     hipLaunchKernelGGL(k_train_grad, dim3(nwg), dim3(256), 0, s, prm, reinterpret_cast<const Sample *>(smp), base,
                        base + avail, inv, part, ploss);
-    const float b1 = 0.9f, b2 = 0.999f;
-    const float c1 = 1.0f / (1.0f - powf(b1, (float)step)), c2 = 1.0f / (1.0f - powf(b2, (float)step));
+    const double b1 = 0.9, b2 = 0.999;
+    const float c1 = (float)(1.0 / (1.0 - pow(b1, step))), c2 = (float)(1.0 / (1.0 - pow(b2, step)));
     hipLaunchKernelGGL(k_train_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, s, prm, m1, m2, part, ploss, nwg, lr,
-                       b1, b2, 1e-8f, c1, c2, loss_out);
+                       (float)b1, (float)b2, (float)(1.0 - b1), (float)(1.0 - b2), 1e-8f, c1, c2, loss_out);
 }
 
 int train_nparam() { return NPARAM; }
