@@ -49,7 +49,7 @@ def test_learned_encode_decode_match_oracle(codec, rdl_mod, O, name, shape, sig,
         out = codec.alloc_outputs(H, W)
         for t in out:
             t.fill_(0xAA)
-        for _ in range(3):  # direct launch, capture, replay
+        for _ in range(3):  # the first call builds the plan, the later ones reuse it
             sdr, hdr, resid = codec.encode_enh(d, q, out=out)
         torch.cuda.synchronize()
         ref = O.encode_learned(x, q, blob)

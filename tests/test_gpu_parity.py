@@ -216,16 +216,24 @@ def test_batch_uneven_matches_oracle(codec, O):
     for x, (H, W, s, q) in zip(xs, specs):
         sdr, hdr, resid = codec.alloc_outputs(H, W)
         items.append((_dev(x), q, sdr, hdr, resid))
-    for rep in range(3):  # direct launch, then capture, then replay
-        for it in items:
-            for t in it[2:]:
-                t.fill_(0xAA)
-        codec.encode_batch(items)
-        torch.cuda.synchronize()
-        for x, it, (H, W, s, q) in zip(xs, items, specs):
-            ref = O.encode_enh(x, q)
-            assert np.array_equal(it[2].cpu().numpy(), ref["sdr"]), (rep, H, W)
-            assert np.array_equal(it[4].cpu().numpy(), ref["resid"]), (rep, H, W)
+    refs = [O.encode_enh(x, q) for x, (H, W, s, q) in zip(xs, specs)]
+    try:
+        for graph in (False, True):
+            codec.set_launch_mode(graph)
+            # direct: the first call builds the plan, the later ones reuse it;
+            # graph: the first call captures the plan's graph, the later ones
+            # replay it
+            for rep in range(3):
+                for it in items:
+                    for t in it[2:]:
+                        t.fill_(0xAA)
+                codec.encode_batch(items)
+                torch.cuda.synchronize()
+                for ref, it, (H, W, s, q) in zip(refs, items, specs):
+                    assert np.array_equal(it[2].cpu().numpy(), ref["sdr"]), (graph, rep, H, W)
+                    assert np.array_equal(it[4].cpu().numpy(), ref["resid"]), (graph, rep, H, W)
+    finally:
+        codec.set_launch_mode(False)
 
 
 def test_full_size_3840x2160(codec, O, rdl_mod):
