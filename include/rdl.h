@@ -174,6 +174,26 @@ typedef struct rdl_image {
 } rdl_image;
 int rdl_encode_batch(rdl_ctx *ctx, const rdl_image *imgs, int n, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the batched
+ * encoder above with no allocation of any kind.  Its scratch (the descriptor
+ * table and the per-image accumulators, about 136 KB per image) lives in a
+ * static device array of the library sized for RDL_NOALLOC_MAX_IMAGES images
+ * (2.2 MB), one copy per GPU, held until the process ends; the descriptors
+ * are written there by a kernel (no host-to-device copy) and the
+ * accumulators are cleared by a kernel at the start of every call.  Inputs,
+ * outputs, layouts, alignments and the result are those of
+ * rdl_encode_batch; launch shapes come from the context's tuning table; the
+ * stages are always launched directly on `stream` (a caller may capture
+ * them).  Every call on one GPU, from any context, shares that GPU's array:
+ * calls that overlap on one GPU race (order them on one stream).  Errors:
+ * RDL_ENOMEM if n > RDL_NOALLOC_MAX_IMAGES (rdl_strerror names the limit),
+ * RDL_EUNSUPPORTED if the context's estimator is the learned one (it needs
+ * per-pixel buffers), otherwise as rdl_encode_batch.  Nothing is enqueued on
+ * an error. */
+#define RDL_NOALLOC_MAX_IMAGES 16
+int rdl_encode_batch_noalloc(rdl_ctx *ctx, const rdl_image *imgs, int n, void *stream);
+
 /* How the encoder's stage kernels are enqueued.  RDL_LAUNCH_DIRECT (the
  * default): one launch per stage on the caller's stream.  RDL_LAUNCH_GRAPH:
  * the stages of a plan are captured in a HIP graph at its first use and the

@@ -60,9 +60,22 @@ struct rdl_ctx {
     int tune[RDL_NTUNE][32];
 };
 
+// Scratch of rdl_encode_batch_noalloc: the descriptor table, then one
+// accumulator block (SCRATCH_I64 int64) per image, for at most
+// RDL_NOALLOC_MAX_IMAGES images.  Every GPU holds its own copy until the
+// process ends.  Host code never passes the array's name to a kernel (on the
+// host it is only a stand-in for the symbol): it uses the device address that
+// hipGetSymbolAddress returned for the current device, kept in
+// g_scratch_ptr.
+constexpr size_t NOALLOC_DESC_I64 = (RDL_NOALLOC_MAX_IMAGES * sizeof(ImgDesc) + 255) / 256 * 32;
+constexpr size_t NOALLOC_I64 = NOALLOC_DESC_I64 + (size_t)RDL_NOALLOC_MAX_IMAGES * SCRATCH_I64;
+static __device__ __align__(256) int64_t scratch[NOALLOC_I64];
+
 namespace {
 
 thread_local char g_err[256] = "";
+std::mutex g_scratch_mu;
+std::vector<int64_t *> g_scratch_ptr;  // per device: the address of `scratch` there, or null
 constexpr size_t kMaxPlans = 8;
 
 struct DeviceGuard {
@@ -261,6 +274,27 @@ int upload(rdl_ctx *c, const std::vector<ImgDesc> &v, hipStream_t s) {
     return RDL_OK;
 }
 
+// Device address of the static scratch on `device` (which must be current),
+// looked up once per device.
+int static_scratch_setup(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((size_t)device < g_scratch_ptr.size() && g_scratch_ptr[device]) return RDL_OK;
+    void *p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) {
+        snprintf(g_err, sizeof g_err, "hipGetSymbolAddress returned no address for the static scratch");
+        return RDL_EHIP;
+    }
+    if ((size_t)device >= g_scratch_ptr.size()) g_scratch_ptr.resize(device + 1, nullptr);
+    g_scratch_ptr[device] = static_cast<int64_t *>(p);
+    return RDL_OK;
+}
+
+int64_t *static_scratch(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return (size_t)device < g_scratch_ptr.size() ? g_scratch_ptr[device] : nullptr;
+}
+
 int check_launch(const char *what) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, what);
@@ -333,7 +367,7 @@ const char *rdl_strerror(int code) {
         case RDL_EINVAL: return "invalid argument";
         case RDL_EHIP: return g_err[0] ? g_err : "HIP runtime error";
         case RDL_ECORRUPT: return "corrupt header or stream";
-        case RDL_ENOMEM: return "out of memory";
+        case RDL_ENOMEM: return g_err[0] ? g_err : "out of memory";
         case RDL_EUNSUPPORTED: return "unsupported";
         default: return "unknown error";
     }
@@ -355,8 +389,13 @@ int rdl_create(rdl_ctx **out, int device) {
         snprintf(g_err, sizeof g_err, "gamma bucket table violates its one-threshold-per-bucket bound");
         return RDL_EUNSUPPORTED;
     }
+    const int rs = static_scratch_setup(device);
+    if (rs) return rs;
     rdl_ctx *c = new (std::nothrow) rdl_ctx();
-    if (!c) return RDL_ENOMEM;
+    if (!c) {
+        snprintf(g_err, sizeof g_err, "out of host memory for the context");
+        return RDL_ENOMEM;
+    }
     c->device = device;
     for (int k = 0; k < 32; ++k) {
         // Fit workgroups as large as the image allows while still giving
@@ -415,7 +454,13 @@ int rdl_encode_enh(rdl_ctx *c, const uint8_t *rgbe, int H, int W, int q, uint8_t
     return rdl_encode_batch(c, &im, 1, stream);
 }
 
-int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
+}  // extern "C"
+
+namespace {
+
+// Argument checks of the batched encoder and its unbound descriptors (image
+// buffers, sizes, estimator flags and launch shapes; no scratch yet).
+int encode_descs(rdl_ctx *c, const rdl_image *imgs, int n, std::vector<ImgDesc> &v, Grid &gr, bool &any_dct) {
     if (!c || !imgs || n < 1) return RDL_EINVAL;
     for (int k = 0; k < n; ++k) {
         const rdl_image &m = imgs[k];
@@ -425,14 +470,12 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
             (reinterpret_cast<uintptr_t>(m.dct) & 1))
             return RDL_EINVAL;
     }
-    bool any_dct = false;
+    any_dct = false;
     for (int k = 0; k < n; ++k) any_dct = any_dct || imgs[k].dct;
     const bool learned = c->estimator == 1;
     if (learned && (!c->d_model || !c->gf)) return RDL_EUNSUPPORTED;
     const int32_t mode = (c->estimator == 2 ? F_EST_GLOBAL : c->estimator == 3 ? F_EST_IDENT : 0) | (c->gf ? 0 : F_NOGF);
-    DeviceGuard g(c->device);
-    hipStream_t s = (hipStream_t)stream;
-    std::vector<ImgDesc> v(n, blank());
+    v.assign(n, blank());
     for (int k = 0; k < n; ++k) {
         ImgDesc &d = v[k];
         d.rgbe = imgs[k].rgbe;
@@ -449,7 +492,23 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
             d.model_hash = c->model_hash;
         }
     }
-    const Grid gr = layout(c, v);
+    gr = layout(c, v);
+    return RDL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
+    std::vector<ImgDesc> v;
+    Grid gr;
+    bool any_dct = false;
+    const int rc0 = encode_descs(c, imgs, n, v, gr, any_dct);
+    if (rc0) return rc0;
+    const bool learned = c->estimator == 1;
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
 
     Plan *p = nullptr;
     for (auto &e : c->plans)
@@ -498,6 +557,39 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
     }
     HIPCHK(hipGraphLaunch(p->exec, s));
     return RDL_OK;
+}
+
+int rdl_encode_batch_noalloc(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
+    if (c && n > RDL_NOALLOC_MAX_IMAGES) {
+        snprintf(g_err, sizeof g_err, "rdl_encode_batch_noalloc: %d images exceed its static scratch (at most %d)", n,
+                 RDL_NOALLOC_MAX_IMAGES);
+        return RDL_ENOMEM;
+    }
+    if (c && c->estimator == 1) {
+        snprintf(g_err, sizeof g_err, "rdl_encode_batch_noalloc: the learned estimator needs per-pixel buffers");
+        return RDL_EUNSUPPORTED;
+    }
+    std::vector<ImgDesc> v;
+    Grid gr;
+    bool any_dct = false;
+    const int rc0 = encode_descs(c, imgs, n, v, gr, any_dct);
+    if (rc0) return rc0;
+    int64_t *base = static_scratch(c->device);
+    if (!base) {
+        snprintf(g_err, sizeof g_err, "rdl_encode_batch_noalloc: no static scratch address for device %d", c->device);
+        return RDL_EHIP;
+    }
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    ImgDesc *dd = reinterpret_cast<ImgDesc *>(base);
+    for (int k = 0; k < n; ++k) {
+        bind_scratch(v[k], base + NOALLOC_DESC_I64 + (size_t)k * SCRATCH_I64);
+        v[k].flags |= F_ZERO_KS | F_ZERO_SUMS;  // the previous call's contents are not trusted
+    }
+    launch_put_desc(dd, v.data(), n, s);
+    launch_zero(dd, n, s);
+    enqueue_encode(dd, n, gr, false, s, c->gf, any_dct);
+    return check_launch("allocation-free encoder kernels");
 }
 
 int rdl_set_launch_mode(rdl_ctx *c, int mode) {

@@ -95,6 +95,8 @@ inline int wgs_lhist(int H, int W) { return (int)(((int64_t)H * W + LCH - 1) / L
 // Kernel launchers (defined in rdl_kernels.hip).
 hipError_t upload_tables(int *bad_table);
 void launch_zero(const ImgDesc *d, int n, hipStream_t s);
+constexpr int DESC_CHUNK = 4;  // descriptors per k_put_desc launch (kernel-argument bytes)
+void launch_put_desc(ImgDesc *dst, const ImgDesc *host, int n, hipStream_t s);
 void launch_check_recip(uint32_t lo, uint32_t count, unsigned long long *bad, hipStream_t s);
 void launch_keystat(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_tmo_base(const ImgDesc *d, int n, int wgs, bool extra, hipStream_t s);

@@ -2079,6 +2079,23 @@ void launch_check_recip(uint32_t lo, uint32_t count, unsigned long long *bad, hi
 }
 
 void launch_zero(const ImgDesc *d, int n, hipStream_t s) { hipLaunchKernelGGL(k_zero, dim3(n), dim3(256), 0, s, d, n); }
+
+// Descriptors passed by value (kernel arguments), written to a device table:
+// the table of a launch without a host-to-device copy.
+struct DescChunk {
+    ImgDesc d[DESC_CHUNK];
+};
+__global__ void k_put_desc(ImgDesc *dst, DescChunk c, int n) {
+    if ((int)threadIdx.x < n) dst[threadIdx.x] = c.d[threadIdx.x];
+}
+void launch_put_desc(ImgDesc *dst, const ImgDesc *host, int n, hipStream_t s) {
+    for (int k = 0; k < n; k += DESC_CHUNK) {
+        const int m = n - k < DESC_CHUNK ? n - k : DESC_CHUNK;
+        DescChunk c;
+        for (int j = 0; j < m; ++j) c.d[j] = host[k + j];
+        hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, s, dst + k, c, m);
+    }
+}
 void launch_keystat(const ImgDesc *d, int n, int wgs, hipStream_t s) {
     hipLaunchKernelGGL(k_keystat, dim3(wgs), dim3(KS_THREADS), 0, s, d, n);
 }

@@ -31,6 +31,9 @@ HEADER_BYTES = HEADER_DTYPE.itemsize
 
 LAUNCH_DIRECT, LAUNCH_GRAPH = 0, 1
 
+#: Images per call of the allocation-free encoder (its static scratch).
+NOALLOC_MAX_IMAGES = 16
+
 #: Encoder estimators (header field `estimator`, bits 0-3) and the filter-off bit.
 EST_SLR, EST_LEARNED, EST_GLOBAL, EST_NONE = 0, 1, 2, 3
 EST_GF_OFF = 16
@@ -51,6 +54,7 @@ _SIGS = {
     "rdl_encode_enh": ([_vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp], _i),
     "rdl_decode_enh": ([_vp, _vp, _vp, _vp, _i, _i, _vp, _vp, _vp], _i),
     "rdl_encode_batch": ([_vp, _vp, _i, _vp], _i),
+    "rdl_encode_batch_noalloc": ([_vp, _vp, _i, _vp], _i),
     "rdl_decode_batch": ([_vp, _vp, _i, _vp], _i),
     "rdl_base_decode": ([_vp, _vp, _vp, _i, _i, _vp, _vp, _vp], _i),
     "rdl_resid_hist": ([_vp, _vp, _i, _i, _vp, _vp], _i),
@@ -242,6 +246,18 @@ class Codec:
             arr[k] = RdlImage(_ptr(rgbe), int(rgbe.shape[0]), int(rgbe.shape[1]), int(q), _ptr(sdr), _ptr(hdr),
                               _ptr(resid), _ptr(dct))
         _chk(self._L.rdl_encode_batch(self._h, arr, len(items), _stream(stream)), "rdl_encode_batch")
+
+    def encode_batch_noalloc(self, items, stream=None):
+        """As encode_batch, through the allocation-free entry point (at most
+        NOALLOC_MAX_IMAGES images, SLR-family estimators only)."""
+        arr = (RdlImage * len(items))()
+        for k, it in enumerate(items):
+            rgbe, q, sdr, hdr, resid = it[:5]
+            dct = it[5] if len(it) > 5 else None
+            arr[k] = RdlImage(_ptr(rgbe), int(rgbe.shape[0]), int(rgbe.shape[1]), int(q), _ptr(sdr), _ptr(hdr),
+                              _ptr(resid), _ptr(dct))
+        _chk(self._L.rdl_encode_batch_noalloc(self._h, arr, len(items), _stream(stream)),
+             "rdl_encode_batch_noalloc")
 
     def decode_batch(self, items, stream=None):
         """items: list of (dct or None, sdr, hdr, resid, out_rgbe, status or None) device
