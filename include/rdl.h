@@ -393,6 +393,33 @@ enum {
     RDL_NSTAGES = 5
 };
 
+/* Stages of the encoder with the learned estimator, in launch order: the
+ * five above, then (learned path only) the learned inference with the
+ * records by exponent, their histograms and the region selection, after the
+ * solve and before the residuals.  Index into ms[] of rdl_stage_times. */
+enum {
+    RDL_STAGE_LEARN = 5,    /* learned estimate + residual records     */
+    RDL_STAGE_LHIST = 6,    /* residual histograms per (est, ch, E)    */
+    RDL_STAGE_SELECT = 7,   /* per-region estimator flags              */
+    RDL_NSTAGES_ALL = 8
+};
+
+/* Stage timing of ordinary encodes (instrumentation).  With on = 1, every
+ * later rdl_encode_enh / rdl_encode_batch call that launches its stages
+ * directly records a HIP event on its stream before the first stage kernel
+ * and after each one (library-owned events, reused; the calls of at most
+ * RDL_TIMING_MAX_CALLS encodes are kept, later ones are not recorded).
+ * Calls in graph launch mode record nothing.  rdl_stage_times waits for the
+ * recorded events, writes to the HOST array ms[RDL_NSTAGES_ALL] the mean
+ * duration in milliseconds of each stage over the recorded calls (the time
+ * between the events around its kernel on the stream; stages that did not
+ * run: 0), writes the number of recorded calls to *calls (host, may be
+ * NULL) and starts a new recording.  on = 0 stops recording and drops what
+ * was recorded. */
+#define RDL_TIMING_MAX_CALLS 64
+int rdl_set_stage_timing(rdl_ctx *ctx, int on);
+int rdl_stage_times(rdl_ctx *ctx, float *ms, int *calls);
+
 /* Runs the same kernels as rdl_encode_enh (same arguments and outputs) for
  * timing: each stage kernel is launched `reps` times back to back between a
  * pair of HIP events on `stream`, and the mean duration of one launch, in

@@ -52,6 +52,12 @@ struct rdl_ctx {
     // base-layer JPEG workspace (JpgWs, then per-block and per-chunk arrays)
     uint8_t *d_jpg = nullptr;
     size_t jpg_cap = 0;
+    // stage timing of direct encodes: per recorded call, an event before the
+    // first stage and one after each of the RDL_NSTAGES_ALL stages (-1: not run)
+    bool timing = false;
+    std::vector<hipEvent_t> tev;  // RDL_TIMING_MAX_CALLS * (RDL_NSTAGES_ALL + 1)
+    int tcalls = 0;
+    bool tlearned[RDL_TIMING_MAX_CALLS];
     // training scratch: per-workgroup gradient partials
     float *d_part = nullptr;
     size_t part_cap = 0;      // floats
@@ -303,18 +309,32 @@ int check_launch(const char *what) {
 
 // Enqueue the full encoder for the images of d (device table) on s.  The
 // scratch accumulators are zero on entry and k_solve leaves them zero.
+// ev (may be null): RDL_NSTAGES_ALL + 1 events; ev[0] is recorded before the
+// first stage and ev[1 + stage] after each stage that runs.
 void enqueue_encode(const ImgDesc *d, int n, const Grid &g, bool learned, hipStream_t s, bool gf = true,
-                    bool dct = false) {
+                    bool dct = false, hipEvent_t *ev = nullptr) {
+    auto mark = [&](int k) {
+        if (ev) (void)hipEventRecord(ev[k], s);
+    };
+    mark(0);
     launch_keystat(d, n, g.px, s);
+    mark(1 + RDL_STAGE_KEYSTAT);
     launch_tmo_base(d, n, g.blk, dct, s);
+    mark(1 + RDL_STAGE_TMO_BASE);
     launch_fit_sums(d, n, g.fit, g.fit_bins, g.fit_waves, s, gf);
+    mark(1 + RDL_STAGE_FIT);
     launch_solve(d, n, s);
+    mark(1 + RDL_STAGE_SOLVE);
     if (learned) {
         launch_learn(d, n, g.learn, s);
+        mark(1 + RDL_STAGE_LEARN);
         launch_lhist(d, n, g.lhist, s);
+        mark(1 + RDL_STAGE_LHIST);
         launch_select(d, n, s);
+        mark(1 + RDL_STAGE_SELECT);
     }
     launch_resid(d, n, g.res, s, gf);
+    mark(1 + RDL_STAGE_RESID);
 }
 
 ImgDesc blank() {
@@ -414,6 +434,8 @@ void rdl_destroy(rdl_ctx *c) {
     if (!c) return;
     DeviceGuard g(c->device);
     for (auto &e : c->plans) free_plan(e);
+    for (auto &e : c->tev)
+        if (e) (void)hipEventDestroy(e);
     if (c->d_model) (void)hipFree(c->d_model);
     if (c->d_part) (void)hipFree(c->d_part);
     if (c->d_desc) (void)hipFree(c->d_desc);
@@ -533,7 +555,12 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
         p = &c->plans.back();
     }
     if (c->launch_mode == RDL_LAUNCH_DIRECT) {
-        enqueue_encode(p->d_desc, n, gr, learned, s, c->gf, any_dct);
+        hipEvent_t *ev = nullptr;
+        if (c->timing && c->tcalls < RDL_TIMING_MAX_CALLS) {
+            ev = &c->tev[(size_t)c->tcalls * (RDL_NSTAGES_ALL + 1)];
+            c->tlearned[c->tcalls++] = learned;
+        }
+        enqueue_encode(p->d_desc, n, gr, learned, s, c->gf, any_dct, ev);
         return check_launch("encoder kernels");
     }
     if (!p->exec) {
@@ -590,6 +617,51 @@ int rdl_encode_batch_noalloc(rdl_ctx *c, const rdl_image *imgs, int n, void *str
     launch_zero(dd, n, s);
     enqueue_encode(dd, n, gr, false, s, c->gf, any_dct);
     return check_launch("allocation-free encoder kernels");
+}
+
+int rdl_set_stage_timing(rdl_ctx *c, int on) {
+    if (!c) return RDL_EINVAL;
+    DeviceGuard g(c->device);
+    if (on && c->tev.empty()) {
+        c->tev.assign((size_t)RDL_TIMING_MAX_CALLS * (RDL_NSTAGES_ALL + 1), nullptr);
+        for (auto &e : c->tev) HIPCHK(hipEventCreate(&e));
+    }
+    c->timing = on != 0;
+    c->tcalls = 0;
+    return RDL_OK;
+}
+
+int rdl_stage_times(rdl_ctx *c, float *ms, int *calls) {
+    if (!c || !ms) return RDL_EINVAL;
+    DeviceGuard g(c->device);
+    double acc[RDL_NSTAGES_ALL] = {0};
+    int nl = 0;
+    for (int k = 0; k < c->tcalls; ++k) {
+        hipEvent_t *ev = &c->tev[(size_t)k * (RDL_NSTAGES_ALL + 1)];
+        static const int order_plain[] = {RDL_STAGE_KEYSTAT, RDL_STAGE_TMO_BASE, RDL_STAGE_FIT, RDL_STAGE_SOLVE,
+                                          RDL_STAGE_RESID};
+        static const int order_learned[] = {RDL_STAGE_KEYSTAT, RDL_STAGE_TMO_BASE, RDL_STAGE_FIT, RDL_STAGE_SOLVE,
+                                            RDL_STAGE_LEARN,   RDL_STAGE_LHIST,    RDL_STAGE_SELECT, RDL_STAGE_RESID};
+        const int *order = c->tlearned[k] ? order_learned : order_plain;
+        const int ns = c->tlearned[k] ? 8 : 5;
+        nl += c->tlearned[k];
+        int prev = 0;
+        for (int j = 0; j < ns; ++j) {
+            const int st = order[j];
+            HIPCHK(hipEventSynchronize(ev[1 + st]));
+            float t = 0;
+            HIPCHK(hipEventElapsedTime(&t, ev[prev], ev[1 + st]));
+            acc[st] += t;
+            prev = 1 + st;
+        }
+    }
+    for (int st = 0; st < RDL_NSTAGES_ALL; ++st) {
+        const int den = st >= RDL_STAGE_LEARN ? nl : c->tcalls;
+        ms[st] = den ? (float)(acc[st] / den) : 0.0f;
+    }
+    if (calls) *calls = c->tcalls;
+    c->tcalls = 0;
+    return RDL_OK;
 }
 
 int rdl_set_launch_mode(rdl_ctx *c, int mode) {

@@ -73,6 +73,8 @@ _SIGS = {
     "rdl_check_recip": ([_vp, C.c_uint32, C.c_uint32, _vp, _vp], _i),
     "rdl_set_tuning": ([_vp, _i, _i, _i], _i),
     "rdl_set_launch_mode": ([_vp, _i], _i),
+    "rdl_set_stage_timing": ([_vp, _i], _i),
+    "rdl_stage_times": ([_vp, _vp, _vp], _i),
     "rdl_set_model": ([_vp, _vp, C.c_size_t], _i),
     "rdl_set_estimator": ([_vp, _i], _i),
     "rdl_set_gf": ([_vp, _i], _i),
@@ -86,6 +88,10 @@ _SIGS = {
 TUNE = ("fit_rows", "resid_rows", "fit_bins", "fit_waves")
 STAGES = ("keystat", "tmo_base", "fit_sums", "solve", "resid")
 KERNELS = ("k_keystat", "k_tmo_base", "k_fit_sums", "k_solve", "k_resid")
+#: All encoder stages (rdl_stage_times order) and their kernels.
+STAGES_ALL = STAGES + ("learn", "lhist", "select")
+KERNELS_ALL = KERNELS + ("k_learn", "k_lhist", "k_select")
+TIMING_MAX_CALLS = 64
 
 
 class RdlImage(C.Structure):
@@ -390,6 +396,18 @@ class Codec:
                 row.append(int(v.value))
             out[name] = row
         return out
+
+    def set_stage_timing(self, on: bool) -> None:
+        """Record HIP events around every stage kernel of later direct encodes."""
+        _chk(self._L.rdl_set_stage_timing(self._h, int(bool(on))), "rdl_set_stage_timing")
+
+    def stage_times(self):
+        """Mean stage durations (ms) over the recorded encodes, and their count;
+        starts a new recording."""
+        ms = (C.c_float * len(STAGES_ALL))()
+        n = C.c_int(0)
+        _chk(self._L.rdl_stage_times(self._h, ms, C.byref(n)), "rdl_stage_times")
+        return {k: float(v) for k, v in zip(STAGES_ALL, ms)}, int(n.value)
 
     def set_launch_mode(self, graph: bool) -> None:
         """False (default): one launch per stage kernel; True: each encoder
