@@ -43,6 +43,7 @@ struct rdl_ctx {
     // learned estimator
     uint8_t *d_model = nullptr;
     uint64_t model_hash = 0;
+    bool model_pow2 = false;  // every hidden requantisation multiplier is 1
     int estimator = 0;  // 0 SLR per region, 1 learned, 2 one line per channel, 3 M* = S
     bool gf = true;     // Gaussian-filter restoration of S before the estimate
     bool ent_pred = true;  // entropy code: exponents as left differences
@@ -180,6 +181,7 @@ JpgLayout jpg_layout(int H, int W) {
 struct Grid {
     int px = 0, blk = 0, tile = 0, fit = 0, res = 0, learn = 0, lhist = 0;
     int fit_bins = 1, fit_waves = STRIP_WAVES;  // the fit's launch shape: the largest image's
+    bool pow2 = false;  // the model's hidden multipliers are all 1 (faster requantisation)
     int64_t fit_px = -1;
 };
 
@@ -326,7 +328,7 @@ void enqueue_encode(const ImgDesc *d, int n, const Grid &g, bool learned, hipStr
     launch_solve(d, n, s);
     mark(1 + RDL_STAGE_SOLVE);
     if (learned) {
-        launch_learn(d, n, g.learn, s);
+        launch_learn(d, n, g.learn, g.pow2, s);
         mark(1 + RDL_STAGE_LEARN);
         launch_lhist(d, n, g.lhist, s);
         mark(1 + RDL_STAGE_LHIST);
@@ -515,6 +517,7 @@ int encode_descs(rdl_ctx *c, const rdl_image *imgs, int n, std::vector<ImgDesc> 
         }
     }
     gr = layout(c, v);
+    gr.pow2 = learned && c->model_pow2;
     return RDL_OK;
 }
 
@@ -692,7 +695,7 @@ int rdl_decode_enh(rdl_ctx *c, const uint8_t *sdr, const rdl_header *coeffs, con
     if (rc) return rc;
     if (status) launch_status_init(c->d_desc, 1, s);
     launch_decode(c->d_desc, 1, gr.res, s);
-    if (c->d_model) launch_decode_learned(c->d_desc, 1, gr.learn, s);
+    if (c->d_model) launch_decode_learned(c->d_desc, 1, gr.learn, c->model_pow2, s);
     return check_launch("k_decode");
 }
 
@@ -728,7 +731,7 @@ int rdl_decode_batch(rdl_ctx *c, const rdl_dimage *imgs, int n, void *stream) {
     if (any_status) launch_status_init(c->d_desc, n, s);
     if (any_dct) launch_base_decode(c->d_desc, n, gr.blk, s);
     launch_decode(c->d_desc, n, gr.res, s);
-    if (c->d_model) launch_decode_learned(c->d_desc, n, gr.learn, s);
+    if (c->d_model) launch_decode_learned(c->d_desc, n, gr.learn, c->model_pow2, s);
     return check_launch("rdl_decode_batch");
 }
 
@@ -1210,9 +1213,17 @@ int rdl_set_model(rdl_ctx *c, const void *blob, size_t nbytes) {
         if (std::abs(i32(6424, k)) > (1 << 18)) return RDL_ECORRUPT;
     for (int k = 0; k < 16; ++k)
         if (std::abs(i32(7320, k)) > (1 << 18)) return RDL_ECORRUPT;
+    // The estimator folds the output rounding into one shift by r3 + 8
+    // (see mlp_wave64); with |o| <= 32 * 127 * 127 + 2^18 and m3 < 2^11 the
+    // folded 32-bit numerator stays below 2^31 for r3 <= 22.
+    for (int k = 0; k < 3; ++k)
+        if (i32(7448, k) > 22) return RDL_ECORRUPT;
+    bool pow2 = true;
+    for (int k = 0; k < 32; ++k) pow2 = pow2 && i32(5144, k) == 1 && i32(6552, k) == 1;
     if (!c->d_model) HIPCHK(hipMalloc(&c->d_model, MODEL_BYTES));
     HIPCHK(hipMemcpy(c->d_model, b, MODEL_BYTES, hipMemcpyHostToDevice));
     c->model_hash = hash;
+    c->model_pow2 = pow2;
     return RDL_OK;
 }
 

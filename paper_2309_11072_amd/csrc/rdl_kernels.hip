@@ -1435,11 +1435,12 @@ constexpr int MB_W1 = 24, MB_B1 = 1048, MB_M1 = 5144, MB_R1 = 5272, MB_W2 = 5400
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 struct MlpLane {
-    long w1a, w1b, w2a, w2b, w3;  // this lane's A fragments
+    long w1a, w1b, w2a, w2b;      // this lane's A fragments of layers 1 and 2
+    long w3[4];                   // output layer, one fragment per pixel group (see mlp_wave64)
     int m1[8], r1[8], c1[8];      // requantisation of this lane's eight neurons: multiplier,
     int m2[8], r2[8], c2[8];      //   shift, rounding constant 2^(r-1)
-    int b2[8];
-    int m3[3], r3[3], c3[3], b3[3];
+    int b2[8];                    // layer-2 biases (rounding constant included when POW2)
+    int m3[3], r3[3], c3[3], b3[3];  // output: multiplier, r3 + 8, 2^(r3-1) + 2^(r3+7), bias
 };
 
 // Eight weight bytes of row `row` at the columns lane quad q takes as its k:
@@ -1450,13 +1451,21 @@ __device__ __forceinline__ long w_fwd(const uint8_t *__restrict__ w, int row, in
     return (long)((uint64_t)lo | ((uint64_t)hi << 32));
 }
 
+// POW2: every hidden multiplier of the model is 1, so a requantisation is
+// (h + 2^(r-1)) >> r and the rounding constant can be carried by the bias
+// (h is the MFMA result with the bias as its C input).
+template <bool POW2>
 __device__ __forceinline__ void mlp_lane_load(MlpLane &L, const uint8_t *__restrict__ blob, int lane) {
     const int j = lane & 15, q = lane >> 4;
     L.w1a = *reinterpret_cast<const long *>(blob + MB_W1 + j * 32 + 8 * q);
     L.w1b = *reinterpret_cast<const long *>(blob + MB_W1 + (16 + j) * 32 + 8 * q);
     L.w2a = w_fwd(blob + MB_W2, j, q);
     L.w2b = w_fwd(blob + MB_W2, 16 + j, q);
-    L.w3 = (j & 3) < 3 ? w_fwd(blob + MB_W3, j & 3, q) : 0;
+    // Output fragments: in group g only A rows 4g..4g+2 (channels R, G, B)
+    // are non-zero, so group g's estimates land in rows 4g..4g+3 of the
+    // accumulated result.
+#pragma unroll
+    for (int g = 0; g < 4; ++g) L.w3[g] = (j >> 2) == g && (j & 3) < 3 ? w_fwd(blob + MB_W3, j & 3, q) : 0;
     const int32_t *m1 = reinterpret_cast<const int32_t *>(blob + MB_M1), *r1 = reinterpret_cast<const int32_t *>(blob + MB_R1);
     const int32_t *m2 = reinterpret_cast<const int32_t *>(blob + MB_M2), *r2 = reinterpret_cast<const int32_t *>(blob + MB_R2);
     const int32_t *b2 = reinterpret_cast<const int32_t *>(blob + MB_B2);
@@ -1467,25 +1476,40 @@ __device__ __forceinline__ void mlp_lane_load(MlpLane &L, const uint8_t *__restr
         const int nn = t < 4 ? 4 * q + t : 16 + 4 * q + t - 4;
         L.m1[t] = m1[nn]; L.r1[t] = r1[nn]; L.c1[t] = 1 << (r1[nn] - 1);
         L.m2[t] = m2[nn]; L.r2[t] = r2[nn]; L.c2[t] = 1 << (r2[nn] - 1);
-        L.b2[t] = b2[nn];
+        L.b2[t] = b2[nn] + (POW2 ? L.c2[t] : 0);
     }
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
-        L.m3[t] = m3[t]; L.r3[t] = r3[t]; L.c3[t] = 1 << (r3[t] - 1); L.b3[t] = b3[t];
+        L.m3[t] = m3[t];
+        L.r3[t] = r3[t] + 8;
+        L.c3[t] = (1 << (r3[t] - 1)) + (1 << (r3[t] + 7));
+        L.b3[t] = b3[t];
     }
 }
 
+// The bias table B1[bin][neuron] in LDS, with each neuron's rounding constant
+// added when POW2 (256 threads).
+template <bool POW2>
+__device__ __forceinline__ void mlp_bias_load(int32_t (*B1)[32], const uint8_t *__restrict__ blob) {
+    const int32_t *b1 = reinterpret_cast<const int32_t *>(blob + MB_B1);
+    const int32_t *r1 = reinterpret_cast<const int32_t *>(blob + MB_R1);
+    for (int k = threadIdx.x; k < 1024; k += 256) (&B1[0][0])[k] = b1[k] + (POW2 ? 1 << (r1[k & 31] - 1) : 0);
+}
+
+template <bool POW2>
 __device__ __forceinline__ uint32_t requant_u8(int h, int m, int r, int c) {
+    if (POW2) return (uint32_t)min(max(h >> r, 0), 127);
     return (uint32_t)min(max((__mul24(h, m) + c) >> r, 0), 127);
 }
 
 // Four requantised bytes packed low to high: two byte permutes join pairs,
 // a third joins the pairs.
+template <bool POW2>
 __device__ __forceinline__ uint32_t requant4(const v4i h, const int *m, const int *r, const int *c) {
-    const uint32_t x01 = __builtin_amdgcn_perm(requant_u8(h[1], m[1], r[1], c[1]), requant_u8(h[0], m[0], r[0], c[0]),
-                                               0x0c0c0400u);
-    const uint32_t x23 = __builtin_amdgcn_perm(requant_u8(h[3], m[3], r[3], c[3]), requant_u8(h[2], m[2], r[2], c[2]),
-                                               0x0c0c0400u);
+    const uint32_t x01 = __builtin_amdgcn_perm(requant_u8<POW2>(h[1], m[1], r[1], c[1]),
+                                               requant_u8<POW2>(h[0], m[0], r[0], c[0]), 0x0c0c0400u);
+    const uint32_t x23 = __builtin_amdgcn_perm(requant_u8<POW2>(h[3], m[3], r[3], c[3]),
+                                               requant_u8<POW2>(h[2], m[2], r[2], c[2]), 0x0c0c0400u);
     return __builtin_amdgcn_perm(x23, x01, 0x05040100u);
 }
 
@@ -1495,83 +1519,108 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Per-wave LDS of the estimator: 64 pixels' features (32 bytes each) and
-// their bins.
+// Per-wave LDS of the estimator: the 64 pixels' features as four 8-byte
+// chunks, chunk-major (chunk q = feature bytes 8q..8q+7), so that the 16 lanes
+// reading one chunk of 16 consecutive pixels, and the 64 lanes writing one
+// chunk each, touch consecutive words; and the pixels' exponent bins.
 struct MlpWaveLds {
-    uint32_t feat[64][8];
+    uint64_t feat[4][64];
     int bin[64];
 };
 
 // M_L of pixel `lane` of the wave, packed R | G << 8 | B << 16 (feat and bin
 // filled for all 64 pixels and made visible by the caller, every lane of the
-// wave active).  B1 is the bias table in LDS.
+// wave active).  B1 is the bias table in LDS.  The output layer accumulates
+// the four groups in one result: group g's fragment is non-zero only in rows
+// 4g..4g+2, so lane (j, q) ends with rows 4q..4q+2 of group q, the estimates
+// of pixel 16q + j, which is the lane itself.  The output rounding is folded:
+// floor((floor((o m3 + 2^(r3-1)) / 2^r3) + 128) / 2^8) =
+// floor((o m3 + 2^(r3-1) + 2^(r3+7)) / 2^(r3+8)).
+template <bool POW2>
 __device__ __forceinline__ uint32_t mlp_wave64(const MlpWaveLds &w, const int32_t (*B1)[32], const MlpLane &L,
                                                int lane) {
     const int j = lane & 15, q = lane >> 4;
     const v4i c2a = {L.b2[0], L.b2[1], L.b2[2], L.b2[3]};
     const v4i c2b = {L.b2[4], L.b2[5], L.b2[6], L.b2[7]};
-    const v4i c3 = {L.b3[0], L.b3[1], L.b3[2], 0};
-    v4i o[4];
+    v4i o = {L.b3[0], L.b3[1], L.b3[2], 0};
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         const int p = 16 * g + j;
-        const long xb = *reinterpret_cast<const long *>(&w.feat[p][2 * q]);
+        const long xb = (long)w.feat[q][p];
         const int b = w.bin[p];
         const v4i c1a = *reinterpret_cast<const v4i *>(&B1[b][4 * q]);
         const v4i c1b = *reinterpret_cast<const v4i *>(&B1[b][16 + 4 * q]);
         const v4i h1a = __builtin_amdgcn_mfma_i32_16x16x32_i8(L.w1a, xb, c1a, 0, 0, 0);
         const v4i h1b = __builtin_amdgcn_mfma_i32_16x16x32_i8(L.w1b, xb, c1b, 0, 0, 0);
-        const long a1 = (long)((uint64_t)requant4(h1a, L.m1, L.r1, L.c1) |
-                               ((uint64_t)requant4(h1b, L.m1 + 4, L.r1 + 4, L.c1 + 4) << 32));
+        const long a1 = (long)((uint64_t)requant4<POW2>(h1a, L.m1, L.r1, L.c1) |
+                               ((uint64_t)requant4<POW2>(h1b, L.m1 + 4, L.r1 + 4, L.c1 + 4) << 32));
         const v4i h2a = __builtin_amdgcn_mfma_i32_16x16x32_i8(L.w2a, a1, c2a, 0, 0, 0);
         const v4i h2b = __builtin_amdgcn_mfma_i32_16x16x32_i8(L.w2b, a1, c2b, 0, 0, 0);
-        const long a2 = (long)((uint64_t)requant4(h2a, L.m2, L.r2, L.c2) |
-                               ((uint64_t)requant4(h2b, L.m2 + 4, L.r2 + 4, L.c2 + 4) << 32));
-        o[g] = __builtin_amdgcn_mfma_i32_16x16x32_i8(L.w3, a2, c3, 0, 0, 0);
+        const long a2 = (long)((uint64_t)requant4<POW2>(h2a, L.m2, L.r2, L.c2) |
+                               ((uint64_t)requant4<POW2>(h2b, L.m2 + 4, L.r2 + 4, L.c2 + 4) << 32));
+        o = __builtin_amdgcn_mfma_i32_16x16x32_i8(L.w3[g], a2, o, 0, 0, 0);
     }
     uint32_t word = 0;
 #pragma unroll
-    for (int t = 0; t < 3; ++t) {
-        const int v = q == 0 ? o[0][t] : q == 1 ? o[1][t] : q == 2 ? o[2][t] : o[3][t];
-        const int q8 = (__mul24(v, L.m3[t]) + L.c3[t]) >> L.r3[t];
-        word |= (uint32_t)min(max((q8 + 128) >> 8, 0), 255) << (8 * t);
-    }
+    for (int t = 0; t < 3; ++t)
+        word |= (uint32_t)min(max((__mul24(o[t], L.m3[t]) + L.c3[t]) >> L.r3[t], 0), 255) << (8 * t);
     return word;
 }
 
-// Features of the pixel at tile position (ly, lx): the nine neighbours'
-// bytes (S - 128) concatenated, 27 bytes, then 5 zero bytes.
-template <int TW>
-__device__ __forceinline__ void build_features(const uint32_t (*tile)[TW + 2], int ly, int lx, uint32_t f[8]) {
-    uint32_t w[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) w[k] = (tile[ly + k / 3][lx + k % 3] & 0xFFFFFFu) ^ 0x808080u;
-    f[0] = w[0] | (w[1] << 24);
-    f[1] = (w[1] >> 8) | (w[2] << 16);
-    f[2] = (w[2] >> 16) | (w[3] << 8);
-    f[3] = w[4] | (w[5] << 24);
-    f[4] = (w[5] >> 8) | (w[6] << 16);
-    f[5] = (w[6] >> 16) | (w[7] << 8);
-    f[6] = w[8];
-    f[7] = 0;
+// The 3x3 neighbourhood of a pixel as three rows of (left, centre, right) S
+// words (R | G << 8 | B << 16); a wave walks down its rows and rolls it.
+struct Win3 {
+    uint32_t w[3][3];
+    uint32_t rb[3], g[3];  // horizontal (1, 6, 1) sums of each row: R | B << 16, and G
+};
+
+__device__ __forceinline__ void win_row(Win3 &v, int slot, const uint32_t *trow, int lx) {
+    const uint32_t a = trow[lx], b = trow[lx + 1], e = trow[lx + 2];
+    v.w[slot][0] = a;
+    v.w[slot][1] = b;
+    v.w[slot][2] = e;
+    // no field exceeds 8 * 255 < 2^16
+    v.rb[slot] = __umul24(b & 0xFF00FFu, 6u) + (a & 0xFF00FFu) + (e & 0xFF00FFu);
+    v.g[slot] = __umul24((b >> 8) & 255u, 6u) + ((a >> 8) & 255u) + ((e >> 8) & 255u);
 }
 
-// S* of the tile pixel (ly, lx) from its 3x3 neighbourhood, on the packed
-// fields R | B << 16 and G (no field exceeds 64 * 255 + 32 < 2^16).
-template <int TW>
-__device__ __forceinline__ void gf_at(const uint32_t (*tile)[TW + 2], int ly, int lx, int s[3]) {
-    uint32_t lo[3], hi[3];
+__device__ __forceinline__ void win_roll(Win3 &v) {
 #pragma unroll
-    for (int dy = 0; dy < 3; ++dy) {
-        const uint32_t a = tile[ly + dy][lx], b = tile[ly + dy][lx + 1], e = tile[ly + dy][lx + 2];
-        lo[dy] = __umul24(b & 0xFF00FFu, 6u) + (a & 0xFF00FFu) + (e & 0xFF00FFu);
-        hi[dy] = __umul24((b >> 8) & 255u, 6u) + ((a >> 8) & 255u) + ((e >> 8) & 255u);
+    for (int k = 0; k < 3; ++k) {
+        v.w[0][k] = v.w[1][k];
+        v.w[1][k] = v.w[2][k];
     }
-    const uint32_t L = lo[0] + lo[2] + 0x200020u + (lo[1] << 2) + (lo[1] << 1);
-    const uint32_t G = hi[0] + hi[2] + 32u + (hi[1] << 2) + (hi[1] << 1);
+    v.rb[0] = v.rb[1];
+    v.rb[1] = v.rb[2];
+    v.g[0] = v.g[1];
+    v.g[1] = v.g[2];
+}
+
+// S* of the window's centre pixel (no field exceeds 64 * 255 + 32 < 2^16).
+__device__ __forceinline__ void win_gf(const Win3 &v, int s[3]) {
+    const uint32_t L = v.rb[0] + v.rb[2] + 0x200020u + (v.rb[1] << 2) + (v.rb[1] << 1);  // B sits above bit 23
+    const uint32_t G = v.g[0] + v.g[2] + 32u + __umul24(v.g[1], 6u);
     s[0] = (int)((L >> 6) & 255u);
     s[1] = (int)(G >> 6);
     s[2] = (int)(L >> 22);
+}
+
+// The window's features as the four 8-byte chunks of the MFMA operand: the
+// nine neighbours' bytes (S - 128) concatenated row by row, 27 bytes, then 5
+// zero bytes.
+__device__ __forceinline__ void win_features(const Win3 &v, uint64_t f[4]) {
+    const uint32_t *n = &v.w[0][0];  // n[k] = neighbour k, row-major
+    const uint32_t f0 = __builtin_amdgcn_perm(n[1], n[0], 0x04020100u) ^ 0x80808080u;
+    const uint32_t f1 = __builtin_amdgcn_perm(n[2], n[1], 0x05040201u) ^ 0x80808080u;
+    const uint32_t f2 = __builtin_amdgcn_perm(n[3], n[2], 0x06050402u) ^ 0x80808080u;
+    const uint32_t f3 = __builtin_amdgcn_perm(n[5], n[4], 0x04020100u) ^ 0x80808080u;
+    const uint32_t f4 = __builtin_amdgcn_perm(n[6], n[5], 0x05040201u) ^ 0x80808080u;
+    const uint32_t f5 = __builtin_amdgcn_perm(n[7], n[6], 0x06050402u) ^ 0x80808080u;
+    const uint32_t f6 = n[8] ^ 0x808080u;
+    f[0] = (uint64_t)f0 | ((uint64_t)f1 << 32);
+    f[1] = (uint64_t)f2 | ((uint64_t)f3 << 32);
+    f[2] = (uint64_t)f4 | ((uint64_t)f5 << 32);
+    f[3] = (uint64_t)f6;
 }
 
 constexpr int LT_W = 64, LT_H = 16, LT_TILES = 4;  // a workgroup walks 4 tiles of 16 x 64 px
@@ -1614,7 +1663,66 @@ __device__ __forceinline__ void store_lt_tile(uint32_t (*t)[LT_W + 2], const uin
     }
 }
 
+// Row-wise fetch of a tile into registers: wave w takes tile rows w, w + 4,
+// ..., lane l column l (image column tx0 - 1 + l, clamped); lanes 0-35 of
+// wave 0 also take the last two columns of every row (row l / 2, column
+// 64 + l % 2).  Row bases are wave-uniform, so only the column offsets are
+// per lane, computed once.
+constexpr int LT_ROWS_PER_WAVE = (LT_H + 2 + 3) / 4;  // 5
+struct LtCols {
+    uint32_t off;    // 3 * clamped image column of tile column `lane`
+    uint32_t off2;   // 3 * clamped image column of tile column 64 + lane % 2
+};
+__device__ __forceinline__ LtCols lt_cols(int W, int tx0, int lane) {
+    LtCols c;
+    c.off = 3u * (uint32_t)min(max(tx0 - 1 + lane, 0), W - 1);
+    c.off2 = 3u * (uint32_t)min(tx0 + 63 + (lane & 1), W - 1);
+    return c;
+}
+__device__ __forceinline__ const uint8_t *lt_row(const uint8_t *__restrict__ sdr, int H, int W, int ty0, int ry) {
+    const int yy = uniform(min(max(ty0 + ry - 1, 0), H - 1));
+    return sdr + (int64_t)yy * (3 * (int64_t)W);
+}
+__device__ __forceinline__ void fetch_lt_rows(uint32_t v[LT_ROWS_PER_WAVE + 1], const uint8_t *__restrict__ sdr, int H,
+                                              int W, int ty0, int wave, int lane, const LtCols &c) {
+#pragma unroll
+    for (int k = 0; k < LT_ROWS_PER_WAVE; ++k) {
+        const int ry = wave + 4 * k;
+        v[k] = ry < LT_H + 2 ? load_px3(lt_row(sdr, H, W, ty0, ry) + c.off) : 0u;
+    }
+    v[LT_ROWS_PER_WAVE] = 0u;
+    if (wave == 0 && lane < 2 * (LT_H + 2)) {
+        const int yy = min(max(ty0 + (lane >> 1) - 1, 0), H - 1);
+        v[LT_ROWS_PER_WAVE] = load_px3(sdr + (int64_t)yy * (3 * (int64_t)W) + c.off2);
+    }
+}
+__device__ __forceinline__ void store_lt_rows(uint32_t (*t)[LT_W + 2], const uint32_t v[LT_ROWS_PER_WAVE + 1],
+                                              int wave, int lane) {
+#pragma unroll
+    for (int k = 0; k < LT_ROWS_PER_WAVE; ++k) {
+        const int ry = wave + 4 * k;
+        if (ry < LT_H + 2) t[ry][lane] = v[k];
+    }
+    if (wave == 0 && lane < 2 * (LT_H + 2)) t[lane >> 1][64 + (lane & 1)] = v[LT_ROWS_PER_WAVE];
+}
+
 __device__ __forceinline__ int mlp_bin(int e, int k_img) { return min(max(e - 136 + k_img + 24, 0), 31); }
+
+// One wave row of the estimator: the window's features and bins to LDS, then
+// the three layers; returns M_L of this lane's pixel.
+template <bool POW2>
+__device__ __forceinline__ uint32_t mlp_row(MlpWaveLds &wl, const int32_t (*B1)[32], const MlpLane &L, const Win3 &v,
+                                            int e, int k_img, int lane) {
+    uint64_t f[4];
+    win_features(v, f);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) wl.feat[k][lane] = f[k];
+    wl.bin[lane] = mlp_bin(e, k_img);
+    wave_lds_sync();
+    const uint32_t ml = mlp_wave64<POW2>(wl, B1, L, lane);
+    wave_lds_sync();  // feat and bin are rewritten for the next row
+    return ml;
+}
 
 // Residual record of one pixel: r + 255 of the three channels for the SLR
 // estimate in bits 0-26 and for the learned one in bits 32-58, 9 bits each.
@@ -1628,15 +1736,19 @@ __device__ __forceinline__ uint64_t lrec_pack(const int rs[3], const int rl[3]) 
 // both estimators' residuals, written as one record per pixel into the
 // bucket of its exponent.  Bucket e starts at the number of pixels with a
 // smaller exponent (k_solve sets the cursors there); per 16-row tile the
-// workgroup ranks its pixels of each exponent in LDS, reserves that many
-// records with one atomic per exponent, and writes them.  Record order within
-// a bucket is free: only histograms are taken from it.
+// workgroup ranks its pixels of each exponent with LDS atomics, reserves
+// that many records with one global atomic per exponent, and writes them.
+// Record order within a bucket is free: only histograms are taken from it.  Each wave walks 4 consecutive rows of a tile with a rolling 3x3
+// window of S, which serves both the features and the Gaussian filter.
+template <bool POW2>
 __global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, int n) {
     __shared__ uint32_t t[LT_H + 2][LT_W + 2];
     __shared__ int2 s_ab[3][256];
     __shared__ int32_t B1[32][32];
     __shared__ MlpWaveLds wl[4];
     __shared__ uint32_t s_cnt[256], s_base[256];
+    __shared__ uint64_t s_rec[LT_H][64];   // the tile's records,
+    __shared__ uint32_t s_where[LT_H][64];  // and exponent | rank << 8 (~0 outside the image)
     const int i = find_img(D, n, blockIdx.x, 5);
     const ImgDesc d = desc_at(D, i);
     const int H = d.H, W = d.W;
@@ -1645,76 +1757,76 @@ __global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, in
     const int ntx = (W + LT_W - 1) / LT_W;
     const int ty0w = (wgl / ntx) * (LT_H * LT_TILES), tx0 = (wgl % ntx) * LT_W;
     for (int k = threadIdx.x; k < 3 * 256; k += 256) s_ab[k >> 8][k & 255] = coef_prep(h->a_q[k >> 8][k & 255], h->b_q[k >> 8][k & 255]);
-    for (int k = threadIdx.x; k < 1024; k += 256) (&B1[0][0])[k] = reinterpret_cast<const int32_t *>(d.model + MB_B1)[k];
+    mlp_bias_load<POW2>(B1, d.model);
     s_cnt[threadIdx.x] = 0;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = uniform(threadIdx.x >> 6);
     MlpLane L;
-    mlp_lane_load(L, d.model, lane);
+    mlp_lane_load<POW2>(L, d.model, lane);
     const int k_img = h->k_img;
     // Tile tt + 1's S words and RGBE words are in flight while tile tt is
     // worked on (every condition below is uniform for the workgroup).
-    uint32_t sv[LT_PER_THREAD], wv[LT_H / 4];
-    int lry[LT_PER_THREAD], lxx[LT_PER_THREAD];
-    lt_slots(W, tx0, lry, lxx);
+    uint32_t sv[LT_ROWS_PER_WAVE + 1], wv[LT_H / 4];
+    const LtCols cols = lt_cols(W, tx0, lane);
+    const int x = tx0 + lane;
+    const bool xin = x < W;
     const uint32_t *rgbe32 = reinterpret_cast<const uint32_t *>(d.rgbe);
     const auto fetch_rgbe = [&](int ty, uint32_t out[LT_H / 4]) {
 #pragma unroll
         for (int rr = 0; rr < LT_H / 4; ++rr) {
-            const int y = ty + wave * (LT_H / 4) + rr, x = tx0 + lane;
-            out[rr] = y < H && x < W ? rgbe32[(int64_t)y * W + x] : 0u;
+            const int y = uniform(ty + wave * (LT_H / 4) + rr);
+            out[rr] = y < H && xin ? (rgbe32 + (int64_t)y * W)[x] : 0u;
         }
     };
     if (ty0w < H) {
-        fetch_lt_tile(sv, d.sdr, H, W, ty0w, lry, lxx);
+        fetch_lt_rows(sv, d.sdr, H, W, ty0w, wave, lane, cols);
         fetch_rgbe(ty0w, wv);
     }
+    uint32_t *ml_out = reinterpret_cast<uint32_t *>(d.ml);
     for (int tt = 0; tt < LT_TILES; ++tt) {
         const int ty0 = ty0w + tt * LT_H;
         if (ty0 >= H) break;
         __syncthreads();
-        store_lt_tile(t, sv);
+        store_lt_rows(t, sv, wave, lane);
         __syncthreads();
         uint32_t wc[LT_H / 4];
 #pragma unroll
         for (int rr = 0; rr < LT_H / 4; ++rr) wc[rr] = wv[rr];
         if (tt + 1 < LT_TILES && ty0 + LT_H < H) {
-            fetch_lt_tile(sv, d.sdr, H, W, ty0 + LT_H, lry, lxx);
+            fetch_lt_rows(sv, d.sdr, H, W, ty0 + LT_H, wave, lane, cols);
             fetch_rgbe(ty0 + LT_H, wv);
         }
-        uint64_t rec[LT_H / 4];
-        uint32_t where[LT_H / 4];  // exponent | rank << 8, or ~0 outside the image
-#pragma unroll
+        const int ly0 = wave * (LT_H / 4);
+        Win3 v;
+        win_row(v, 0, t[ly0], lane);      // tile row ly0 = image row ty0 + ly0 - 1
+        win_row(v, 1, t[ly0 + 1], lane);
+        // One row per iteration, not unrolled: the estimator's registers are
+        // then the only large live set, which keeps several waves per SIMD.
+#pragma unroll 1
         for (int rr = 0; rr < LT_H / 4; ++rr) {
-            const int ly = wave * (LT_H / 4) + rr, y = ty0 + ly, x = tx0 + lane;
-            const bool in = y < H && x < W;
-            const uint32_t w = wc[rr];
-            const int e = (int)(w >> 24);
-            uint32_t f[8];
-            build_features<LT_W>(t, ly, lane, f);
-            *reinterpret_cast<uint4 *>(&wl[wave].feat[lane][0]) = make_uint4(f[0], f[1], f[2], f[3]);
-            *reinterpret_cast<uint4 *>(&wl[wave].feat[lane][4]) = make_uint4(f[4], f[5], f[6], f[7]);
-            wl[wave].bin[lane] = mlp_bin(e, k_img);
-            wave_lds_sync();
-            const uint32_t ml = mlp_wave64(wl[wave], B1, L, lane);
-            wave_lds_sync();  // feat and bin are rewritten for the next row
-            rec[rr] = 0;
-            where[rr] = ~0u;
-            if (in) {
-                int s[3];
-                gf_at<LT_W>(t, ly, lane, s);
-                const int64_t o = (int64_t)y * W + x;
-                int rs[3], rl[3];
+            const int ly = ly0 + rr, y = uniform(ty0 + ly);
+            win_row(v, 2, t[ly + 2], lane);
+            const bool in = xin && y < H;
+            const uint32_t w = wc[0];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const int m = (int)((w >> (8 * c)) & 255u);
-                    const int mlc = (int)((ml >> (8 * c)) & 255u);
-                    rs[c] = m - mstar(s_ab[c][e], s[c]);
-                    rl[c] = m - mlc;
-                }
-                reinterpret_cast<uint32_t *>(d.ml)[o] = ml;
-                rec[rr] = lrec_pack(rs, rl);
-                where[rr] = (uint32_t)e | (atomicAdd(&s_cnt[e], 1u) << 8);
+            for (int k = 0; k + 1 < LT_H / 4; ++k) wc[k] = wc[k + 1];
+            const int e = (int)(w >> 24);
+            const uint32_t ml = mlp_row<POW2>(wl[wave], B1, L, v, e, k_img, lane);
+            int s[3];
+            win_gf(v, s);
+            win_roll(v);
+            int rs[3], rl[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int m = (int)((w >> (8 * c)) & 255u);
+                rs[c] = m - mstar(s_ab[c][e], s[c]);
+                rl[c] = m - (int)((ml >> (8 * c)) & 255u);
             }
+            s_rec[ly][lane] = lrec_pack(rs, rl);
+            if (in) (ml_out + (int64_t)y * W)[x] = ml;
+            // Rank among the tile's pixels of the same exponent (a row holds
+            // about a dozen exponents, so one atomic per lane beats a loop
+            // over them).
+            s_where[ly][lane] = in ? ((uint32_t)e | (atomicAdd(&s_cnt[e], 1u) << 8)) : ~0u;
         }
         __syncthreads();
         {
@@ -1727,13 +1839,15 @@ __global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, in
         }
         __syncthreads();
 #pragma unroll
-        for (int rr = 0; rr < LT_H / 4; ++rr)
-            if (where[rr] != ~0u) {
+        for (int rr = 0; rr < LT_H / 4; ++rr) {
+            const uint32_t wh = s_where[ly0 + rr][lane];
+            if (wh != ~0u) {
                 // Bucket totals come from the same pixels (the fit's n_e), so
                 // the index stays below H*W; the check only guards the buffer.
-                const uint32_t idx = s_base[where[rr] & 255u] + (where[rr] >> 8);
-                if (idx < (uint32_t)(H * W)) d.lrec[idx] = rec[rr];
+                const uint32_t idx = s_base[wh & 255u] + (wh >> 8);
+                if (idx < (uint32_t)(H * W)) d.lrec[idx] = s_rec[ly0 + rr][lane];
             }
+        }
     }
 }
 
@@ -1884,6 +1998,7 @@ __global__ __launch_bounds__(256) void k_select(const ImgDesc *__restrict__ D, i
 }
 
 // Learned decoder: M = (flag ? M_L : M*) + r for headers with estimator 1.
+template <bool POW2>
 __global__ __launch_bounds__(256) void k_decode_learned(const ImgDesc *__restrict__ D, int n) {
     __shared__ uint32_t t[LT_H + 2][LT_W + 2];
     __shared__ int2 s_ab[3][256];
@@ -1913,7 +2028,7 @@ __global__ __launch_bounds__(256) void k_decode_learned(const ImgDesc *__restric
         s_ab[k >> 8][k & 255] = coef_prep(aq, bq);
         s_fl[k >> 8][k & 255] = h->flag[k >> 8][k & 255];
     }
-    for (int k = threadIdx.x; k < 1024; k += 256) (&B1[0][0])[k] = reinterpret_cast<const int32_t *>(d.model + MB_B1)[k];
+    mlp_bias_load<POW2>(B1, d.model);
     __syncthreads();
     if (s_bad) {  // uniform
         if (threadIdx.x == 0 && d.status) atomicExch(d.status, RDL_ECORRUPT);
@@ -1921,12 +2036,13 @@ __global__ __launch_bounds__(256) void k_decode_learned(const ImgDesc *__restric
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     MlpLane L;
-    mlp_lane_load(L, d.model, lane);
+    mlp_lane_load<POW2>(L, d.model, lane);
     const int k_img = h->k_img;
     const int64_t npx = (int64_t)H * W;
     const int16_t *r = (const int16_t *)d.resid;
     const uint8_t *Ep = d.resid + 6 * npx;
     uint32_t *out = reinterpret_cast<uint32_t *>(d.out_rgbe);
+    const int x = tx0 + lane;
     bool bad = false;
     for (int tt = 0; tt < LT_TILES; ++tt) {
         const int ty0 = ty0w + tt * LT_H;
@@ -1934,23 +2050,22 @@ __global__ __launch_bounds__(256) void k_decode_learned(const ImgDesc *__restric
         if (ty0 < H) load_lt_tile(t, d.sdr, H, W, ty0, tx0);
         __syncthreads();
         if (ty0 >= H) continue;
+        const int ly0 = wave * (LT_H / 4);
+        Win3 v;
+        win_row(v, 0, t[ly0], lane);
+        win_row(v, 1, t[ly0 + 1], lane);
 #pragma unroll 1
         for (int rr = 0; rr < LT_H / 4; ++rr) {
-            const int ly = wave * (LT_H / 4) + rr, y = ty0 + ly, x = tx0 + lane;
+            const int ly = ly0 + rr, y = ty0 + ly;
+            win_row(v, 2, t[ly + 2], lane);
             const bool in = y < H && x < W;
             const int64_t o = (int64_t)y * W + x;
             const int e = in ? (int)Ep[o] : 0;
-            uint32_t f[8];
-            build_features<LT_W>(t, ly, lane, f);
-            *reinterpret_cast<uint4 *>(&wl[wave].feat[lane][0]) = make_uint4(f[0], f[1], f[2], f[3]);
-            *reinterpret_cast<uint4 *>(&wl[wave].feat[lane][4]) = make_uint4(f[4], f[5], f[6], f[7]);
-            wl[wave].bin[lane] = mlp_bin(e, k_img);
-            wave_lds_sync();
-            const uint32_t ml = mlp_wave64(wl[wave], B1, L, lane);
-            wave_lds_sync();  // feat and bin are rewritten for the next row
-            if (!in) continue;
+            const uint32_t ml = mlp_row<POW2>(wl[wave], B1, L, v, e, k_img, lane);
             int s[3];
-            gf_at<LT_W>(t, ly, lane, s);
+            win_gf(v, s);
+            win_roll(v);
+            if (!in) continue;
             uint32_t word = (uint32_t)e << 24;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -2135,8 +2250,11 @@ void launch_status_init(const ImgDesc *d, int n, hipStream_t s) {
 void launch_decode(const ImgDesc *d, int n, int wgs, hipStream_t s) {
     hipLaunchKernelGGL(k_decode, dim3(wgs), dim3(STRIP_THREADS), 0, s, d, n);
 }
-void launch_learn(const ImgDesc *d, int n, int wgs, hipStream_t s) {
-    hipLaunchKernelGGL(k_learn, dim3(wgs), dim3(256), 0, s, d, n);
+void launch_learn(const ImgDesc *d, int n, int wgs, bool pow2, hipStream_t s) {
+    if (pow2)
+        hipLaunchKernelGGL(k_learn<true>, dim3(wgs), dim3(256), 0, s, d, n);
+    else
+        hipLaunchKernelGGL(k_learn<false>, dim3(wgs), dim3(256), 0, s, d, n);
 }
 void launch_lhist(const ImgDesc *d, int n, int wgs, hipStream_t s) {
     hipLaunchKernelGGL(k_lhist, dim3(wgs), dim3(LH_THREADS), 0, s, d, n);
@@ -2144,8 +2262,11 @@ void launch_lhist(const ImgDesc *d, int n, int wgs, hipStream_t s) {
 void launch_select(const ImgDesc *d, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_select, dim3(256 * n), dim3(256), 0, s, d, n);
 }
-void launch_decode_learned(const ImgDesc *d, int n, int wgs, hipStream_t s) {
-    hipLaunchKernelGGL(k_decode_learned, dim3(wgs), dim3(256), 0, s, d, n);
+void launch_decode_learned(const ImgDesc *d, int n, int wgs, bool pow2, hipStream_t s) {
+    if (pow2)
+        hipLaunchKernelGGL(k_decode_learned<true>, dim3(wgs), dim3(256), 0, s, d, n);
+    else
+        hipLaunchKernelGGL(k_decode_learned<false>, dim3(wgs), dim3(256), 0, s, d, n);
 }
 void launch_hist(const ImgDesc *d, int n, int wgs, hipStream_t s) {
     hipLaunchKernelGGL(k_hist, dim3(wgs), dim3(TILE_THREADS), 0, s, d, n);

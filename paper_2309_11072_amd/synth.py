@@ -221,10 +221,11 @@ def batch_256_large(n: int = 256) -> list:
             for i, (H, W) in enumerate(sizes)]
 
 
-def random_model(seed: int, scale: int = 8) -> bytes:
+def random_model(seed: int, scale: int = 8, pow2: bool = False) -> bytes:
     """A seeded random int8 estimator model (test input), within the value
     limits of the model format, with activations that neither vanish nor
-    saturate on synthetic images."""
+    saturate on synthetic images.  pow2: every hidden requantisation
+    multiplier is 1 (scales are powers of two)."""
     from . import model_format
     rng = np.random.Generator(np.random.PCG64(seed))
     p = {
@@ -238,4 +239,9 @@ def random_model(seed: int, scale: int = 8) -> bytes:
     p["W1"][:, :27] = rng.integers(-scale, scale + 1, (32, 27))
     p["W3"][:3] = rng.integers(-scale, scale + 1, (3, 32))
     p["B3"][:3] = rng.integers(0, 2000, 3)
+    if pow2:
+        p["m1"] = np.ones(32, np.int64)
+        p["r1"] = rng.integers(5, 8, 32)
+        p["m2"] = np.ones(32, np.int64)
+        p["r2"] = rng.integers(4, 7, 32)
     return model_format.pack(p)

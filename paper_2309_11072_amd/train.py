@@ -42,13 +42,13 @@ def unflatten(p: np.ndarray) -> dict:
             "B3": p[P_B3:NPARAM]}
 
 
-def _mult_shift(ratio: np.ndarray):
-    """m / 2^r ~= ratio with m in [1, 2^11), r in [1, 28]."""
+def _mult_shift(ratio: np.ndarray, rmax: int = 28):
+    """m / 2^r ~= ratio with m in [1, 2^11), r in [1, rmax]."""
     m = np.zeros(ratio.shape, np.int64)
     r = np.zeros(ratio.shape, np.int64)
     for i, rho in enumerate(ratio.reshape(-1)):
         rho = max(float(rho), 1e-12)
-        rr = int(np.clip(math.floor(math.log2(2047.0 / rho)), 1, 28))
+        rr = int(np.clip(math.floor(math.log2(2047.0 / rho)), 1, rmax))
         mm = int(round(rho * 2 ** rr))
         while mm >= 2048 and rr > 1:
             rr -= 1
@@ -58,29 +58,56 @@ def _mult_shift(ratio: np.ndarray):
     return m, r
 
 
-def quantise(p: np.ndarray, feats: np.ndarray, bins: np.ndarray) -> bytes:
+def _pow2_shift(ratio: np.ndarray):
+    """Shift r in [1, 28] with 2^r >= ratio, the smallest such: a hidden
+    activation step of sw 2^r is at least the calibrated step, so no more
+    values clip at 127 than the calibration allows."""
+    r = np.ceil(np.log2(np.maximum(ratio, 1e-30)))
+    return np.clip(r, 1, 28).astype(np.int64)
+
+
+def quantise(p: np.ndarray, feats: np.ndarray, bins: np.ndarray, pow2: bool = True) -> bytes:
     """int8 model blob from float parameters; activation scales from the
-    float forward pass over the calibration samples (feats int8 [N, 27])."""
+    float forward pass over the calibration samples (feats int8 [N, 27]).
+
+    pow2: the hidden layers' requantisation multipliers are 1 (a shift by r
+    alone, the fast path of the library's estimator); each hidden activation
+    step then becomes sw 2^r, and the next layer's float weights are scaled
+    by that actual step before they are quantised, so the powers of two cost
+    at most one bit of activation resolution and nothing else."""
     P = unflatten(p.astype(np.float64))
     x = feats.astype(np.float64) / 128.0
     h1 = x @ P["W1"].T + P["B1"][bins]
     a1 = np.maximum(h1, 0)
     s1 = np.maximum(np.percentile(a1, 99.99, axis=0), 1e-9) / 127.0
-    a2 = np.maximum(a1 @ P["W2"].T + P["B2"], 0)
-    s2 = np.maximum(np.percentile(a2, 99.99, axis=0), 1e-9) / 127.0
     lim = 1 << 18
     W1e = P["W1"] / 128.0
     sw1 = np.maximum(np.abs(W1e).max(axis=1), 1e-12) / 127.0
     W1q = np.zeros((32, 32), np.int64)
     W1q[:, :27] = np.clip(np.round(W1e / sw1[:, None]), -127, 127)
     B1q = np.clip(np.round(P["B1"] / sw1[None, :]), -lim, lim)
-    m1, r1 = _mult_shift(sw1 / s1)
-    W2e = P["W2"] * s1[None, :]
+    if pow2:
+        r1 = _pow2_shift(s1 / sw1)
+        m1 = np.ones(32, np.int64)
+        t1 = sw1 * 2.0 ** r1  # the actual activation step
+    else:
+        m1, r1 = _mult_shift(sw1 / s1)
+        t1 = s1
+    a1q = np.clip(np.round(np.maximum(h1, 0) / t1), 0, 127) * t1  # activations as the model will see them
+    a2 = np.maximum(a1q @ P["W2"].T + P["B2"], 0)
+    s2 = np.maximum(np.percentile(a2, 99.99, axis=0), 1e-9) / 127.0
+    W2e = P["W2"] * t1[None, :]
     sw2 = np.maximum(np.abs(W2e).max(axis=1), 1e-12) / 127.0
     W2q = np.clip(np.round(W2e / sw2[:, None]), -127, 127)
     B2q = np.clip(np.round(P["B2"] / sw2), -lim, lim)
-    m2, r2 = _mult_shift(sw2 / s2)
-    W3e = P["W3"] * s2[None, :]
+    if pow2:
+        r2 = _pow2_shift(s2 / sw2)
+        m2 = np.ones(32, np.int64)
+        t2 = sw2 * 2.0 ** r2
+    else:
+        m2, r2 = _mult_shift(sw2 / s2)
+        t2 = s2
+    W3e = P["W3"] * t2[None, :]
     sw3 = np.maximum(np.abs(W3e).max(axis=1), 1e-12) / 127.0
     W3q = np.zeros((16, 32), np.int64)
     W3q[:3] = np.clip(np.round(W3e / sw3[:, None]), -127, 127)
@@ -88,7 +115,7 @@ def quantise(p: np.ndarray, feats: np.ndarray, bins: np.ndarray) -> bytes:
     B3q[:3] = np.clip(np.round(P["B3"] / sw3), -lim, lim)
     m3 = np.ones(16, np.int64)
     r3 = np.ones(16, np.int64)
-    m3[:3], r3[:3] = _mult_shift(sw3 * 65536.0)
+    m3[:3], r3[:3] = _mult_shift(sw3 * 65536.0, rmax=22)
     return model_format.pack({"W1": W1q, "B1": B1q, "m1": m1, "r1": r1, "W2": W2q, "B2": B2q, "m2": m2, "r2": r2,
                               "W3": W3q, "B3": B3q, "m3": m3, "r3": r3})
 
@@ -166,14 +193,19 @@ def main():
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--eval", type=int, default=16, help="number of 1920x1080 evaluation images")
+    ap.add_argument("--params-out", default="", help="also save the float parameters (.npy)")
+    ap.add_argument("--general", action="store_true",
+                    help="general requantisation multipliers instead of powers of two")
     args = ap.parse_args()
     t0 = time.time()
     codec = rdl.Codec(0)
     samples = make_samples(codec, synth.learned_train_set(), args.samples, seed=4000)
     print("samples: %d records in %.1f s" % (samples.shape[0], time.time() - t0), flush=True)
     params = train(codec, samples, args.epochs, args.batch, args.lr, log=lambda s: print(s, flush=True))
+    if args.params_out:
+        np.save(args.params_out, params)
     calib = samples[:200_000].cpu().numpy()
-    blob = quantise(params, calib[:, :27].view(np.int8), calib[:, 27].astype(np.int64))
+    blob = quantise(params, calib[:, :27].view(np.int8), calib[:, 27].astype(np.int64), pow2=not args.general)
     with open(args.out, "wb") as fh:
         fh.write(blob)
     print("model written: %s (%d bytes, hash %016x) after %.1f s" % (args.out, len(blob), model_format.blob_hash(blob),

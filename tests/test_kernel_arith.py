@@ -152,3 +152,35 @@ def test_entropy_quotient_from_float_reciprocal():
             q = np.where(up, q + 1, q)
             r = np.where(up, r - f, r)
             assert np.array_equal(q, x // f) and np.array_equal(r, x % f)
+
+
+def test_learned_output_rounding_fold():
+    """The estimator's output step in one shift: for every accepted r3 (1..22)
+    and multiplier, floor((floor((o m3 + 2^(r3-1)) / 2^r3) + 128) / 2^8) equals
+    floor((o m3 + 2^(r3-1) + 2^(r3+7)) / 2^(r3+8)), and the folded numerator
+    stays inside int32 for every o the model format allows
+    (|o| <= 32 * 127 * 127 + 2^18)."""
+    rng = np.random.default_rng(5)
+    omax = 32 * 127 * 127 + (1 << 18)
+    for r3 in range(1, 23):
+        for m3 in (1, 2, 777, 2047):
+            o = np.concatenate([rng.integers(-omax, omax + 1, 20000), [-omax, omax, 0, -1, 1]]).astype(np.int64)
+            num = o * m3 + (1 << (r3 - 1))
+            two_step = ((num >> r3) + 128) >> 8
+            folded_num = num + (1 << (r3 + 7))
+            assert np.array_equal(two_step, folded_num >> (r3 + 8)), (r3, m3)
+            assert folded_num.max() < 2 ** 31 and folded_num.min() >= -2 ** 31, (r3, m3)
+    # r3 = 23 would overflow at the bound: the library rejects it
+    assert omax * 2047 + (1 << 22) + (1 << 30) >= 2 ** 31
+
+
+def test_learned_pow2_bias_fold():
+    """With a hidden multiplier of 1 the rounding constant moves into the bias:
+    (h m + 2^(r-1)) >> r = (h' ) >> r with h' = h + 2^(r-1), and h' stays inside
+    int32 for every accepted bias and shift."""
+    rng = np.random.default_rng(6)
+    hmax = 27 * 128 * 127 + (1 << 18)
+    for r in range(1, 29):
+        h = rng.integers(-hmax, hmax + 1, 5000).astype(np.int64)
+        assert np.array_equal((h * 1 + (1 << (r - 1))) >> r, (h + (1 << (r - 1))) >> r)
+        assert hmax + (1 << (r - 1)) < 2 ** 31
