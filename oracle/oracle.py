@@ -72,6 +72,8 @@ def lib():
         L.oracle_log2q16.restype = i64
         L.oracle_hist_cost.argtypes = [vp, C.c_int]
         L.oracle_hist_cost.restype = i64
+        L.oracle_cross_cost.argtypes = [vp, vp, i64, C.c_int]
+        L.oracle_cross_cost.restype = i64
         L.oracle_encode_learned.argtypes = [vp, C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, vp, vp]
         L.oracle_encode_learned.restype = C.c_int
         L.oracle_decode_learned.argtypes = [vp, vp, vp, vp, i32, vp, vp, C.c_int, C.c_int, vp]
@@ -294,6 +296,14 @@ def mlp_estimate(S: np.ndarray, rgbe: np.ndarray, k_img: int, blob: bytes) -> np
 
 def log2q16(x: int) -> int:
     return int(lib().oracle_log2q16(int(x)))
+
+
+def cross_cost(h, g) -> int:
+    """Q16 code length of histogram h under the distribution of counts g
+    (-1 when h has a value g never takes)."""
+    h = np.ascontiguousarray(h, np.int64)
+    g = np.ascontiguousarray(g, np.int64)
+    return int(lib().oracle_cross_cost(_p(h), _p(g), int(g.sum()), h.size))
 
 
 def hist_cost(h) -> int:

@@ -759,9 +759,29 @@ int64_t oracle_hist_cost(const int64_t *h, int nbins)
     return cost;
 }
 
+/* Code length, in Q16 bits, of a residual histogram h (nbins bins) under the
+ * distribution of the counts g (total N): sum_v h_v (L(N) - L(g_v)).  -1 when
+ * some h_v > 0 has g_v = 0 (no finite code length). */
+int64_t oracle_cross_cost(const int64_t *h, const int64_t *g, int64_t N, int nbins)
+{
+    int64_t LN = oracle_log2q16(N), cost = 0;
+    for (int v = 0; v < nbins; v++)
+        if (h[v]) {
+            if (!g[v]) return -1;
+            cost += h[v] * (LN - oracle_log2q16(g[v]));
+        }
+    return cost;
+}
+
 /* Learned encoder: the plain encoder, then per (c, E) region the learned
- * estimate replaces M* where its residual histogram has the strictly lower
- * cost (ties keep SLR); flag[c][E] records the choice. */
+ * estimate replaces M* where its residuals cost strictly fewer bits than the
+ * SLR residuals under the distribution of channel c's SLR residuals over the
+ * whole image (ties and regions without a finite learned cost keep SLR);
+ * flag[c][E] records the choice.  Summed over the regions, the chosen
+ * residuals then cost no more under that distribution than the SLR residuals,
+ * whose cost is N H0(SLR); and a histogram's own H0 is the least cost under
+ * any distribution (Gibbs), so the chosen residuals' zeroth-order entropy is
+ * at most SLR's, up to the rounding of the Q16 logarithms. */
 int oracle_encode_learned(const uint8_t *rgbe, int H, int W, int q, const uint8_t *blob, uint8_t *out_sdr,
                           int32_t *a_q, int32_t *b_q, uint8_t *present, uint8_t *flag, int64_t *params_out,
                           void *out_resid)
@@ -786,12 +806,18 @@ int oracle_encode_learned(const uint8_t *rgbe, int H, int W, int q, const uint8_
             hl[((int64_t)c * 256 + e) * 511 + rl + 255] += 1;
         }
     }
-    for (int c = 0; c < 3; c++)
-        for (int e = 0; e < 256; e++) {
-            int64_t cs = oracle_hist_cost(hs + ((int64_t)c * 256 + e) * 511, 511);
-            int64_t cl = oracle_hist_cost(hl + ((int64_t)c * 256 + e) * 511, 511);
-            flag[c * 256 + e] = present[e] && cl < cs;
+    int64_t g[511];
+    for (int c = 0; c < 3; c++) {
+        for (int v = 0; v < 511; v++) {
+            g[v] = 0;
+            for (int e = 0; e < 256; e++) g[v] += hs[((int64_t)c * 256 + e) * 511 + v];
         }
+        for (int e = 0; e < 256; e++) {
+            int64_t cs = oracle_cross_cost(hs + ((int64_t)c * 256 + e) * 511, g, npx, 511);
+            int64_t cl = oracle_cross_cost(hl + ((int64_t)c * 256 + e) * 511, g, npx, 511);
+            flag[c * 256 + e] = present[e] && cl >= 0 && cl < cs;
+        }
+    }
     int16_t *r = (int16_t *)out_resid;
     for (int64_t i = 0; i < npx; i++) {
         int e = rgbe[4 * i + 3];
