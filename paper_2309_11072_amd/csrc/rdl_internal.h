@@ -58,7 +58,8 @@ struct ImgDesc {
     uint8_t *out_rgbe;     // decode only
     int64_t *hist;         // [3][511] residual histograms
     uint8_t *ml;           // learned path: [H][W] learned estimates, R | G << 8 | B << 16 words
-    uint32_t *lhist;       // learned path: [2][3][256][511] residual histograms (estimator, channel)
+    uint32_t *lhist;       // learned path: [2][3][256][511] residual histograms (estimator, channel),
+                           //   then [3][511] of the SLR residuals over the image
     uint64_t *lrec;        // learned path: [H*W] residual records, grouped by exponent
     uint32_t *lbk;         // learned path: [256] record cursors, [257] first histogram
                            //   workgroup of each exponent, [256] first record of each exponent
@@ -87,7 +88,11 @@ inline int wgs_strip(int H, int W, int srh, int waves = STRIP_WAVES) {
     return ((H + sh - 1) / sh) * ((W + STRIP_W - 1) / STRIP_W);
 }
 inline int wgs_learn(int H, int W) { return ((H + LEARN_H - 1) / LEARN_H) * ((W + LEARN_W - 1) / LEARN_W); }
-inline size_t lhist_words() { return (size_t)2 * 3 * 256 * 511; }
+// Learned path, per image: residual histograms [2][3][256][511] (estimator,
+// channel, exponent), then the SLR residual histogram of each channel over
+// the whole image [3][511] (at LHIST_G).
+constexpr size_t LHIST_G = (size_t)2 * 3 * 256 * 511;
+inline size_t lhist_words() { return LHIST_G + 3 * 511; }
 // Histogram workgroups of an image: one per LCH records of each exponent,
 // at most H*W / LCH + 1 per present exponent.
 inline int wgs_lhist(int H, int W) { return (int)(((int64_t)H * W + LCH - 1) / LCH) + 256; }

@@ -1071,6 +1071,9 @@ __global__ __launch_bounds__(1024) void k_solve(const ImgDesc *__restrict__ D, i
     const ImgDesc d = desc_at(D, i);
     rdl_header *h = d.hdr;
     const int t = threadIdx.x;
+    // learned path: the image's SLR residual histograms start at zero
+    if (d.lhist)
+        for (int k = t; k < 3 * 511; k += 1024) d.lhist[LHIST_G + k] = 0;
     if (t < 3 * 256) {
         // Thread (g, e) adds values k = g, g + 3, ... of exponent e over the
         // image's stripes (all loads independent), leaves the stripes zero
@@ -1926,7 +1929,10 @@ __global__ __launch_bounds__(LH_THREADS) void k_lhist(const ImgDesc *__restrict_
         uint32_t c = 0;
 #pragma unroll
         for (int cp = 0; cp < LH_COPIES; ++cp) c += (hb[cp * LH_STRIDE + hgram * 256 + (v >> 1)] >> ((v & 1) << 4)) & 0xFFFFu;
-        if (c) atomicAdd(&d.lhist[((size_t)hgram * 256 + e) * 511 + v], c);
+        if (c) {
+            atomicAdd(&d.lhist[((size_t)hgram * 256 + e) * 511 + v], c);
+            if (hgram < 3) atomicAdd(&d.lhist[LHIST_G + hgram * 511 + v], c);  // SLR, whole image
+        }
     }
 }
 
@@ -1938,13 +1944,17 @@ __device__ __forceinline__ int64_t log2q16(uint32_t x) {
     return (int64_t)65536 * p + g_log2f[idx];
 }
 
-// One workgroup per (image, exponent): takes both estimators' histograms of
-// the three channels (leaving them zero for the next launch), computes the
-// integer entropy costs and sets the flag where the learned cost is strictly
-// lower.  With n = the region's size (every pixel adds one count to each
-// histogram), cost = sum_v h_v (L(n) - L(h_v)) = n L(n) - sum_v h_v L(h_v).
+// Region selection: per (channel, exponent) the learned estimate is taken
+// where its residuals cost strictly fewer bits than the SLR residuals under
+// the distribution g of the channel's SLR residuals over the whole image:
+// cost_k = sum_v h_k[v] (L(N) - L(g_v)), and as both histograms hold the
+// region's n_E residuals, cost_L < cost_S exactly when
+// sum_v h_L[v] L(g_v) > sum_v h_S[v] L(g_v).  A learned residual value that
+// g never takes has no finite cost and keeps SLR.  One workgroup per
+// exponent; it leaves the region's six histograms zero.
 __global__ __launch_bounds__(256) void k_select(const ImgDesc *__restrict__ D, int n) {
     __shared__ int64_t s_red[4][6];
+    __shared__ int s_bad[3];
     const int i = blockIdx.x >> 8, e = blockIdx.x & 255;
     if (i >= n) return;
     const ImgDesc d = desc_at(D, i);
@@ -1957,9 +1967,11 @@ __global__ __launch_bounds__(256) void k_select(const ImgDesc *__restrict__ D, i
         if (threadIdx.x < 3) h->flag[threadIdx.x][e] = 0;
         return;
     }
+    if (threadIdx.x < 3) s_bad[threadIdx.x] = 0;
     // Thread t takes bins t and t + 256 of the six histograms (estimator x
-    // channel), all loads issued before the first is used.
-    uint32_t cnt[6][2];
+    // channel) and of the three whole-image SLR histograms, all loads issued
+    // before the first is used.
+    uint32_t cnt[6][2], gl[3][2];
 #pragma unroll
     for (int hg = 0; hg < 6; ++hg)
 #pragma unroll
@@ -1968,32 +1980,41 @@ __global__ __launch_bounds__(256) void k_select(const ImgDesc *__restrict__ D, i
             cnt[hg][k] = v < 511 ? d.lhist[((size_t)hg * 256 + e) * 511 + v] : 0u;
         }
 #pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int v = threadIdx.x + 256 * k;
+            gl[c][k] = v < 511 ? d.lhist[LHIST_G + c * 511 + v] : 0u;
+        }
+#pragma unroll
     for (int hg = 0; hg < 6; ++hg)
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             const int v = threadIdx.x + 256 * k;
             if (v < 511) d.lhist[((size_t)hg * 256 + e) * 511 + v] = 0;
         }
+    __syncthreads();  // s_bad cleared
     int64_t part[6];
 #pragma unroll
     for (int hg = 0; hg < 6; ++hg) {
+        const int c = hg % 3;
         part[hg] = 0;
 #pragma unroll
-        for (int k = 0; k < 2; ++k)
-            if (cnt[hg][k]) part[hg] += (int64_t)cnt[hg][k] * log2q16(cnt[hg][k]);
+        for (int k = 0; k < 2; ++k) part[hg] += (int64_t)cnt[hg][k] * log2q16(gl[c][k]);
         for (int off = 32; off > 0; off >>= 1) part[hg] += __shfl_down(part[hg], off, 64);
     }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        if ((cnt[3 + c][0] && !gl[c][0]) || (cnt[3 + c][1] && !gl[c][1])) s_bad[c] = 1;
     if ((threadIdx.x & 63) == 0)
 #pragma unroll
         for (int hg = 0; hg < 6; ++hg) s_red[threadIdx.x >> 6][hg] = part[hg];
     __syncthreads();
     if (threadIdx.x < 3) {
         const int c = threadIdx.x;
-        const int64_t nn = d.sums[e * NSUM];
-        const int64_t nL = nn * log2q16((uint32_t)nn);
-        const int64_t hs = s_red[0][c] + s_red[1][c] + s_red[2][c] + s_red[3][c];
-        const int64_t hl = s_red[0][3 + c] + s_red[1][3 + c] + s_red[2][3 + c] + s_red[3][3 + c];
-        h->flag[c][e] = (nL - hl) < (nL - hs) ? 1 : 0;
+        const int64_t ps = s_red[0][c] + s_red[1][c] + s_red[2][c] + s_red[3][c];
+        const int64_t pl = s_red[0][3 + c] + s_red[1][3 + c] + s_red[2][3 + c] + s_red[3][3 + c];
+        h->flag[c][e] = !s_bad[c] && pl > ps ? 1 : 0;
     }
 }
 

@@ -5,8 +5,8 @@ learned estimator with per-region selection.
 The plain encoder is compared with the CPU oracle on every output.  For the
 learned path the oracle's estimator (C, called through ctypes, which releases
 the GIL) runs on row bands in threads; the selection is then rebuilt from the
-oracle's own primitives (the SLR residuals of its encoder, its integer cost of
-a histogram) and checked first against the oracle's complete learned encoder
+oracle's own primitives (the SLR residuals of its encoder, its integer code
+length of a histogram under the image's SLR residual distribution) and checked first against the oracle's complete learned encoder
 on a small image.  No test here starts a process."""
 import os
 from concurrent.futures import ThreadPoolExecutor
@@ -79,8 +79,10 @@ def learned_selection(O, x, ref, blob, threads=16):
     for c in range(3):
         hs = np.bincount((E * 511 + rs[c] + 255).reshape(-1), minlength=256 * 511).reshape(256, 511)
         hl = np.bincount((E * 511 + rl[c] + 255).reshape(-1), minlength=256 * 511).reshape(256, 511)
+        g = hs.sum(axis=0)  # the channel's SLR residuals over the image
         for e in np.nonzero(hs.sum(axis=1))[0]:
-            flag[c, e] = 1 if O.hist_cost(hl[e]) < O.hist_cost(hs[e]) else 0
+            cl = O.cross_cost(hl[e], g)
+            flag[c, e] = 1 if 0 <= cl < O.cross_cost(hs[e], g) else 0
     sel = flag[np.arange(3)[:, None, None], E[None]] == 1
     return flag, np.where(sel, rl, rs).astype(np.int16), k_img
 
