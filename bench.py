@@ -491,9 +491,12 @@ def main():
     if args.learned_eval:
         bits = {0: 0.0, 1: 0.0}
         cbits = {0: 0.0, 1: 0.0}
+        coded = {0: 0.0, 1: 0.0}
         npx_eval = 0
         ok = True
         regions = [0, 0]
+        code = torch.empty(codec.ent_bound(1080, 1920), dtype=torch.uint8, device="cuda")
+        clen = torch.zeros(1, dtype=torch.int64, device="cuda")
         for s in synth.learned_eval_set():
             xe = torch.from_numpy(s.make()).cuda()
             oe = codec.alloc_outputs(s.H, s.W)
@@ -502,6 +505,7 @@ def main():
                 codec.encode_enh(xe, s.q, out=oe)
                 bits[mode] += resid_bits(codec, oe[2], s.H, s.W) * s.H * s.W
                 cbits[mode] += cond_bits(oe[2], s.H, s.W) * s.H * s.W
+                coded[mode] += 8 * coded_bytes(codec, oe[2], s.H, s.W, code, clen)
                 if mode == 1:
                     ok &= bool(torch.equal(codec.decode_enh(oe[0], oe[1], oe[2], s.H, s.W), xe))
                     he = rdl.header_from_bytes(oe[1])
@@ -514,10 +518,13 @@ def main():
                         "bits_per_pixel_learned": round(bits[1] / npx_eval, 4),
                         "bits_per_pixel_given_E_slr": round(cbits[0] / npx_eval, 4),
                         "bits_per_pixel_given_E_learned": round(cbits[1] / npx_eval, 4),
+                        "coded_bits_per_pixel_slr": round(coded[0] / npx_eval, 4),
+                        "coded_bits_per_pixel_learned": round(coded[1] / npx_eval, 4),
                         "regions_learned": regions[0], "regions": regions[1], "lossless": ok,
                         "model_hash": "%016x" % model_format.blob_hash(blob)}
-        say("held-out: SLR %.4f, learned %.4f bits/px" % (learned_eval["bits_per_pixel_slr"],
-                                                         learned_eval["bits_per_pixel_learned"]))
+        say("held-out: SLR %.4f, learned %.4f bits/px (coded %.4f vs %.4f)" % (
+            learned_eval["bits_per_pixel_slr"], learned_eval["bits_per_pixel_learned"],
+            learned_eval["coded_bits_per_pixel_slr"], learned_eval["coded_bits_per_pixel_learned"]))
 
     # ---- entropy code of the enhancement layer (static rANS) -----------------
     sdr, hdr, resid = out

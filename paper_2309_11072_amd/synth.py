@@ -208,6 +208,16 @@ def learned_train_set() -> list:
     return [ImageSpec(2160, 3840, 4.0, 75, 4000 + i, 0.05) for i in range(2)]
 
 
+def learned_train_set_wide(n: int = 8) -> list:
+    """Training images over the parameter ranges of the batch workloads:
+    eight 1920x1080 images, sigma in [1, 5], q in [30, 98], every second one
+    with 5% speculars (the batch of 256 images has none, the 3840x2160
+    workload has them)."""
+    rng = np.random.Generator(np.random.PCG64(4010))
+    return [ImageSpec(1080, 1920, float(rng.uniform(1.0, 5.0)), int(rng.integers(30, 99)), 4010 + i,
+                      0.05 if i % 2 else 0.0) for i in range(n)]
+
+
 def learned_eval_set() -> list:
     """Sixteen held-out 1920x1080 images with the same parameters."""
     return [ImageSpec(1080, 1920, 4.0, 75, 4100 + i, 0.05) for i in range(16)]

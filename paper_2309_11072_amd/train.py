@@ -194,12 +194,16 @@ def main():
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--eval", type=int, default=16, help="number of 1920x1080 evaluation images")
     ap.add_argument("--params-out", default="", help="also save the float parameters (.npy)")
+    ap.add_argument("--train-set", choices=("config2", "wide"), default="config2",
+                    help="config2: the two 3840x2160 images of the single-image workload's generator; wide: those "
+                         "plus eight images over the batch workloads' parameter ranges")
     ap.add_argument("--general", action="store_true",
                     help="general requantisation multipliers instead of powers of two")
     args = ap.parse_args()
     t0 = time.time()
     codec = rdl.Codec(0)
-    samples = make_samples(codec, synth.learned_train_set(), args.samples, seed=4000)
+    specs = synth.learned_train_set() + (synth.learned_train_set_wide() if args.train_set == "wide" else [])
+    samples = make_samples(codec, specs, args.samples, seed=4000)
     print("samples: %d records in %.1f s" % (samples.shape[0], time.time() - t0), flush=True)
     params = train(codec, samples, args.epochs, args.batch, args.lr, log=lambda s: print(s, flush=True))
     if args.params_out:
