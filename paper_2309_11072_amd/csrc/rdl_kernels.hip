@@ -1244,13 +1244,15 @@ __global__ __launch_bounds__(STRIP_THREADS) void k_resid(const ImgDesc *__restri
     const int H = d.H, W = d.W;
     const int wgl = blockIdx.x - d.wg_res;
     const rdl_header *h = d.hdr;
-    const bool learned = d.ml != nullptr;
+    int flagged = 0;
     for (int k = threadIdx.x; k < 3 * 256; k += STRIP_THREADS) {
         const int c = k >> 8, e = k & 255;
         s_ab[c][e] = coef_prep(h->a_q[c][e], h->b_q[c][e]);
-        s_fl[c][e] = learned ? h->flag[c][e] : 0;
+        s_fl[c][e] = d.ml ? h->flag[c][e] : 0;
+        flagged |= s_fl[c][e];
     }
-    __syncthreads();
+    // The learned estimates are read only for an image with a flagged region.
+    const bool learned = __syncthreads_or(flagged) != 0;
     const StripPos sp = strip_pos(wgl, H, W, d.srh_res);
     if (sp.ya >= H) return;  // uniform per wave; no barrier follows
     const int64_t npx = (int64_t)H * W;
