@@ -115,6 +115,48 @@ def test_profile_encode_leaves_correct_outputs(codec, rdl_mod, O):
     _check(codec, rdl_mod, O, x, q, out)
 
 
+def test_stage_timing_of_direct_encodes(codec, rdl_mod, O):
+    """Stage events: recorded only while on and only for direct launches,
+    averaged over the recorded encodes (plain: five stages; learned: eight),
+    never more than the recording limit, and the encodes' outputs are the
+    oracle's."""
+    H, W, q = 150, 222, 70
+    x = synth.generate(H, W, 3.0, seed=1510, spec_frac=0.05)
+    d = _dev(x)
+    out = codec.alloc_outputs(H, W)
+    _say("stage timing", H, W)
+    codec.set_stage_timing(True)
+    try:
+        for _ in range(3):
+            codec.encode_enh(d, q, out=out)
+        ms, n = codec.stage_times()
+        assert n == 3
+        plain = ("keystat", "tmo_base", "fit_sums", "solve", "resid")
+        assert all(ms[k] > 0 for k in plain) and all(ms[k] == 0 for k in ("learn", "lhist", "select"))
+        _check(codec, rdl_mod, O, x, q, out)
+        assert codec.stage_times()[1] == 0  # a new recording starts empty
+        codec.set_launch_mode(True)
+        codec.encode_enh(d, q, out=out)
+        codec.set_launch_mode(False)
+        assert codec.stage_times()[1] == 0  # graph replays record nothing
+        codec.set_model(synth.random_model(1511, pow2=True))
+        codec.set_estimator(1)
+        for _ in range(2):
+            codec.encode_enh(d, q, out=out)
+        ms, n = codec.stage_times()
+        assert n == 2 and all(v > 0 for k, v in ms.items() if k != "solve")
+        codec.set_estimator(0)
+        for _ in range(rdl_mod.TIMING_MAX_CALLS + 5):
+            codec.encode_enh(d, q, out=out)
+        assert codec.stage_times()[1] == rdl_mod.TIMING_MAX_CALLS
+    finally:
+        codec.set_estimator(0)
+        codec.set_launch_mode(False)
+        codec.set_stage_timing(False)
+    codec.encode_enh(d, q, out=out)
+    assert codec.stage_times()[1] == 0  # off: nothing recorded
+
+
 def test_tuning_table_rejects_bad_shapes(codec, rdl_mod):
     t = codec.get_tuning()
     assert t["resid_rows"] == [8] * 32 and t["fit_bins"] == [2] * 32
