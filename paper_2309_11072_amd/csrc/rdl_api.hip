@@ -43,7 +43,9 @@ struct rdl_ctx {
     // learned estimator
     uint8_t *d_model = nullptr;
     uint64_t model_hash = 0;
-    bool model_pow2 = false;  // every hidden requantisation multiplier is 1
+    // requantisation path of the model's hidden layers: 0 general, 1 every
+    // multiplier is 1, 2 that and every shift at most 8 (kernels' RQ_*)
+    int model_rq = 0;
     int estimator = 0;  // 0 SLR per region, 1 learned, 2 one line per channel, 3 M* = S
     bool gf = true;     // Gaussian-filter restoration of S before the estimate
     bool ent_pred = true;  // entropy code: exponents as left differences
@@ -181,7 +183,7 @@ JpgLayout jpg_layout(int H, int W) {
 struct Grid {
     int px = 0, blk = 0, tile = 0, fit = 0, res = 0, learn = 0, lhist = 0;
     int fit_bins = 1, fit_waves = STRIP_WAVES;  // the fit's launch shape: the largest image's
-    bool pow2 = false;  // the model's hidden multipliers are all 1 (faster requantisation)
+    int rq = 0;  // the learned estimator's requantisation path (the model's, see model_rq)
     int64_t fit_px = -1;
 };
 
@@ -328,7 +330,7 @@ void enqueue_encode(const ImgDesc *d, int n, const Grid &g, bool learned, hipStr
     launch_solve(d, n, s);
     mark(1 + RDL_STAGE_SOLVE);
     if (learned) {
-        launch_learn(d, n, g.learn, g.pow2, s);
+        launch_learn(d, n, g.learn, g.rq, s);
         mark(1 + RDL_STAGE_LEARN);
         launch_lhist(d, n, g.lhist, s);
         mark(1 + RDL_STAGE_LHIST);
@@ -517,7 +519,7 @@ int encode_descs(rdl_ctx *c, const rdl_image *imgs, int n, std::vector<ImgDesc> 
         }
     }
     gr = layout(c, v);
-    gr.pow2 = learned && c->model_pow2;
+    gr.rq = learned ? c->model_rq : 0;
     return RDL_OK;
 }
 
@@ -695,7 +697,7 @@ int rdl_decode_enh(rdl_ctx *c, const uint8_t *sdr, const rdl_header *coeffs, con
     if (rc) return rc;
     if (status) launch_status_init(c->d_desc, 1, s);
     launch_decode(c->d_desc, 1, gr.res, s);
-    if (c->d_model) launch_decode_learned(c->d_desc, 1, gr.learn, c->model_pow2, s);
+    if (c->d_model) launch_decode_learned(c->d_desc, 1, gr.learn, c->model_rq, s);
     return check_launch("k_decode");
 }
 
@@ -731,7 +733,7 @@ int rdl_decode_batch(rdl_ctx *c, const rdl_dimage *imgs, int n, void *stream) {
     if (any_status) launch_status_init(c->d_desc, n, s);
     if (any_dct) launch_base_decode(c->d_desc, n, gr.blk, s);
     launch_decode(c->d_desc, n, gr.res, s);
-    if (c->d_model) launch_decode_learned(c->d_desc, n, gr.learn, c->model_pow2, s);
+    if (c->d_model) launch_decode_learned(c->d_desc, n, gr.learn, c->model_rq, s);
     return check_launch("rdl_decode_batch");
 }
 
@@ -1218,12 +1220,15 @@ int rdl_set_model(rdl_ctx *c, const void *blob, size_t nbytes) {
     // folded 32-bit numerator stays below 2^31 for r3 <= 22.
     for (int k = 0; k < 3; ++k)
         if (i32(7448, k) > 22) return RDL_ECORRUPT;
-    bool pow2 = true;
-    for (int k = 0; k < 32; ++k) pow2 = pow2 && i32(5144, k) == 1 && i32(6552, k) == 1;
+    bool pow2 = true, short_shift = true;
+    for (int k = 0; k < 32; ++k) {
+        pow2 = pow2 && i32(5144, k) == 1 && i32(6552, k) == 1;
+        short_shift = short_shift && i32(5272, k) <= 8 && i32(6680, k) <= 8;
+    }
     if (!c->d_model) HIPCHK(hipMalloc(&c->d_model, MODEL_BYTES));
     HIPCHK(hipMemcpy(c->d_model, b, MODEL_BYTES, hipMemcpyHostToDevice));
     c->model_hash = hash;
-    c->model_pow2 = pow2;
+    c->model_rq = !pow2 ? 0 : short_shift ? 2 : 1;
     return RDL_OK;
 }
 

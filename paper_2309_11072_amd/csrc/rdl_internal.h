@@ -113,10 +113,10 @@ void launch_decode(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_base_decode(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_status_init(const ImgDesc *d, int n, hipStream_t s);
 void launch_hist(const ImgDesc *d, int n, int wgs, hipStream_t s);
-void launch_learn(const ImgDesc *d, int n, int wgs, bool pow2, hipStream_t s);
+void launch_learn(const ImgDesc *d, int n, int wgs, int rq, hipStream_t s);  // rq: requantisation path (RQ_*)
 void launch_lhist(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_select(const ImgDesc *d, int n, hipStream_t s);
-void launch_decode_learned(const ImgDesc *d, int n, int wgs, bool pow2, hipStream_t s);
+void launch_decode_learned(const ImgDesc *d, int n, int wgs, int rq, hipStream_t s);
 
 // Entropy code of the enhancement layer (static rANS with 64 interleaved
 // states per group; kernels in rdl_entropy.hip, format in rdl.h).

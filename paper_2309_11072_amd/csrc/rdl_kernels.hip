@@ -1438,13 +1438,25 @@ __global__ __launch_bounds__(STRIP_THREADS) void k_decode(const ImgDesc *__restr
 constexpr int MB_W1 = 24, MB_B1 = 1048, MB_M1 = 5144, MB_R1 = 5272, MB_W2 = 5400, MB_B2 = 6424, MB_M2 = 6552,
               MB_R2 = 6680, MB_W3 = 6808, MB_B3 = 7320, MB_M3 = 7384, MB_R3 = 7448;
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+// Requantisation paths of the hidden layers, chosen per model when it is
+// set: RQ_GENERAL a = clamp((h m + 2^(r-1)) >> r, 0, 127); RQ_POW2 every
+// hidden multiplier is 1, so the rounding constant 2^(r-1) rides on the
+// biases (the MFMAs' C inputs) and a = clamp(h >> r, 0, 127); RQ_PACKED is
+// RQ_POW2 with every hidden shift at most 8, where saturating h to 16 bits
+// first changes nothing (a value beyond +-2^15 shifts to at least +-128, a
+// clamp either way), so two neurons share each packed 16-bit shift, max and
+// min.
+enum { RQ_GENERAL = 0, RQ_POW2 = 1, RQ_PACKED = 2 };
 
 struct MlpLane {
     long w1a, w1b, w2a, w2b;      // this lane's A fragments of layers 1 and 2
     long w3[4];                   // output layer, one fragment per pixel group (see mlp_wave64)
     int m1[8], r1[8], c1[8];      // requantisation of this lane's eight neurons: multiplier,
     int m2[8], r2[8], c2[8];      //   shift, rounding constant 2^(r-1)
-    int b2[8];                    // layer-2 biases (rounding constant included when POW2)
+    int b2[8];                    // layer-2 biases (rounding constant included unless RQ_GENERAL)
+    s16x2 r1p[4], r2p[4];         // RQ_PACKED: the shifts of neuron pairs (0,1), (2,3), (4,5), (6,7)
     int m3[3], r3[3], c3[3], b3[3];  // output: multiplier, r3 + 8, 2^(r3-1) + 2^(r3+7), bias
 };
 
@@ -1456,10 +1468,7 @@ __device__ __forceinline__ long w_fwd(const uint8_t *__restrict__ w, int row, in
     return (long)((uint64_t)lo | ((uint64_t)hi << 32));
 }
 
-// POW2: every hidden multiplier of the model is 1, so a requantisation is
-// (h + 2^(r-1)) >> r and the rounding constant can be carried by the bias
-// (h is the MFMA result with the bias as its C input).
-template <bool POW2>
+template <int RQ>
 __device__ __forceinline__ void mlp_lane_load(MlpLane &L, const uint8_t *__restrict__ blob, int lane) {
     const int j = lane & 15, q = lane >> 4;
     L.w1a = *reinterpret_cast<const long *>(blob + MB_W1 + j * 32 + 8 * q);
@@ -1481,7 +1490,12 @@ __device__ __forceinline__ void mlp_lane_load(MlpLane &L, const uint8_t *__restr
         const int nn = t < 4 ? 4 * q + t : 16 + 4 * q + t - 4;
         L.m1[t] = m1[nn]; L.r1[t] = r1[nn]; L.c1[t] = 1 << (r1[nn] - 1);
         L.m2[t] = m2[nn]; L.r2[t] = r2[nn]; L.c2[t] = 1 << (r2[nn] - 1);
-        L.b2[t] = b2[nn] + (POW2 ? L.c2[t] : 0);
+        L.b2[t] = b2[nn] + (RQ != RQ_GENERAL ? L.c2[t] : 0);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        L.r1p[t] = s16x2{(short)L.r1[2 * t], (short)L.r1[2 * t + 1]};
+        L.r2p[t] = s16x2{(short)L.r2[2 * t], (short)L.r2[2 * t + 1]};
     }
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
@@ -1493,28 +1507,40 @@ __device__ __forceinline__ void mlp_lane_load(MlpLane &L, const uint8_t *__restr
 }
 
 // The bias table B1[bin][neuron] in LDS, with each neuron's rounding constant
-// added when POW2 (256 threads).
-template <bool POW2>
+// added unless RQ_GENERAL (256 threads).
+template <int RQ>
 __device__ __forceinline__ void mlp_bias_load(int32_t (*B1)[32], const uint8_t *__restrict__ blob) {
     const int32_t *b1 = reinterpret_cast<const int32_t *>(blob + MB_B1);
     const int32_t *r1 = reinterpret_cast<const int32_t *>(blob + MB_R1);
-    for (int k = threadIdx.x; k < 1024; k += 256) (&B1[0][0])[k] = b1[k] + (POW2 ? 1 << (r1[k & 31] - 1) : 0);
+    for (int k = threadIdx.x; k < 1024; k += 256)
+        (&B1[0][0])[k] = b1[k] + (RQ != RQ_GENERAL ? 1 << (r1[k & 31] - 1) : 0);
 }
 
-template <bool POW2>
+template <int RQ>
 __device__ __forceinline__ uint32_t requant_u8(int h, int m, int r, int c) {
-    if (POW2) return (uint32_t)min(max(h >> r, 0), 127);
+    if (RQ != RQ_GENERAL) return (uint32_t)min(max(h >> r, 0), 127);
     return (uint32_t)min(max((__mul24(h, m) + c) >> r, 0), 127);
 }
 
-// Four requantised bytes packed low to high: two byte permutes join pairs,
-// a third joins the pairs.
-template <bool POW2>
-__device__ __forceinline__ uint32_t requant4(const v4i h, const int *m, const int *r, const int *c) {
-    const uint32_t x01 = __builtin_amdgcn_perm(requant_u8<POW2>(h[1], m[1], r[1], c[1]),
-                                               requant_u8<POW2>(h[0], m[0], r[0], c[0]), 0x0c0c0400u);
-    const uint32_t x23 = __builtin_amdgcn_perm(requant_u8<POW2>(h[3], m[3], r[3], c[3]),
-                                               requant_u8<POW2>(h[2], m[2], r[2], c[2]), 0x0c0c0400u);
+// Four requantised bytes packed low to high.  RQ_PACKED: both halves of a
+// pair saturated to 16 bits in one instruction, then shifted and clamped
+// together, and one byte permute joins the pairs; otherwise two byte
+// permutes join pairs and a third joins the pairs.
+template <int RQ>
+__device__ __forceinline__ uint32_t requant4(const v4i h, const int *m, const int *r, const int *c,
+                                             const s16x2 *rp) {
+    if (RQ == RQ_PACKED) {
+        const s16x2 z = {0, 0}, hi = {127, 127};
+        s16x2 a = __builtin_amdgcn_cvt_pk_i16(h[0], h[1]);
+        s16x2 b = __builtin_amdgcn_cvt_pk_i16(h[2], h[3]);
+        a = __builtin_elementwise_min(__builtin_elementwise_max(a >> rp[0], z), hi);
+        b = __builtin_elementwise_min(__builtin_elementwise_max(b >> rp[1], z), hi);
+        return __builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, b), __builtin_bit_cast(uint32_t, a), 0x06040200u);
+    }
+    const uint32_t x01 = __builtin_amdgcn_perm(requant_u8<RQ>(h[1], m[1], r[1], c[1]),
+                                               requant_u8<RQ>(h[0], m[0], r[0], c[0]), 0x0c0c0400u);
+    const uint32_t x23 = __builtin_amdgcn_perm(requant_u8<RQ>(h[3], m[3], r[3], c[3]),
+                                               requant_u8<RQ>(h[2], m[2], r[2], c[2]), 0x0c0c0400u);
     return __builtin_amdgcn_perm(x23, x01, 0x05040100u);
 }
 
@@ -1541,7 +1567,7 @@ struct MlpWaveLds {
 // of pixel 16q + j, which is the lane itself.  The output rounding is folded:
 // floor((floor((o m3 + 2^(r3-1)) / 2^r3) + 128) / 2^8) =
 // floor((o m3 + 2^(r3-1) + 2^(r3+7)) / 2^(r3+8)).
-template <bool POW2>
+template <int RQ>
 __device__ __forceinline__ uint32_t mlp_wave64(const MlpWaveLds &w, const int32_t (*B1)[32], const MlpLane &L,
                                                int lane) {
     const int j = lane & 15, q = lane >> 4;
@@ -1557,12 +1583,12 @@ __device__ __forceinline__ uint32_t mlp_wave64(const MlpWaveLds &w, const int32_
         const v4i c1b = *reinterpret_cast<const v4i *>(&B1[b][16 + 4 * q]);
         const v4i h1a = __builtin_amdgcn_mfma_i32_16x16x32_i8(L.w1a, xb, c1a, 0, 0, 0);
         const v4i h1b = __builtin_amdgcn_mfma_i32_16x16x32_i8(L.w1b, xb, c1b, 0, 0, 0);
-        const long a1 = (long)((uint64_t)requant4<POW2>(h1a, L.m1, L.r1, L.c1) |
-                               ((uint64_t)requant4<POW2>(h1b, L.m1 + 4, L.r1 + 4, L.c1 + 4) << 32));
+        const long a1 = (long)((uint64_t)requant4<RQ>(h1a, L.m1, L.r1, L.c1, L.r1p) |
+                               ((uint64_t)requant4<RQ>(h1b, L.m1 + 4, L.r1 + 4, L.c1 + 4, L.r1p + 2) << 32));
         const v4i h2a = __builtin_amdgcn_mfma_i32_16x16x32_i8(L.w2a, a1, c2a, 0, 0, 0);
         const v4i h2b = __builtin_amdgcn_mfma_i32_16x16x32_i8(L.w2b, a1, c2b, 0, 0, 0);
-        const long a2 = (long)((uint64_t)requant4<POW2>(h2a, L.m2, L.r2, L.c2) |
-                               ((uint64_t)requant4<POW2>(h2b, L.m2 + 4, L.r2 + 4, L.c2 + 4) << 32));
+        const long a2 = (long)((uint64_t)requant4<RQ>(h2a, L.m2, L.r2, L.c2, L.r2p) |
+                               ((uint64_t)requant4<RQ>(h2b, L.m2 + 4, L.r2 + 4, L.c2 + 4, L.r2p + 2) << 32));
         o = __builtin_amdgcn_mfma_i32_16x16x32_i8(L.w3[g], a2, o, 0, 0, 0);
     }
     uint32_t word = 0;
@@ -1715,7 +1741,7 @@ __device__ __forceinline__ int mlp_bin(int e, int k_img) { return min(max(e - 13
 
 // One wave row of the estimator: the window's features and bins to LDS, then
 // the three layers; returns M_L of this lane's pixel.
-template <bool POW2>
+template <int RQ>
 __device__ __forceinline__ uint32_t mlp_row(MlpWaveLds &wl, const int32_t (*B1)[32], const MlpLane &L, const Win3 &v,
                                             int e, int k_img, int lane) {
     uint64_t f[4];
@@ -1724,7 +1750,7 @@ __device__ __forceinline__ uint32_t mlp_row(MlpWaveLds &wl, const int32_t (*B1)[
     for (int k = 0; k < 4; ++k) wl.feat[k][lane] = f[k];
     wl.bin[lane] = mlp_bin(e, k_img);
     wave_lds_sync();
-    const uint32_t ml = mlp_wave64<POW2>(wl, B1, L, lane);
+    const uint32_t ml = mlp_wave64<RQ>(wl, B1, L, lane);
     wave_lds_sync();  // feat and bin are rewritten for the next row
     return ml;
 }
@@ -1745,7 +1771,7 @@ __device__ __forceinline__ uint64_t lrec_pack(const int rs[3], const int rl[3]) 
 // that many records with one global atomic per exponent, and writes them.
 // Record order within a bucket is free: only histograms are taken from it.  Each wave walks 4 consecutive rows of a tile with a rolling 3x3
 // window of S, which serves both the features and the Gaussian filter.
-template <bool POW2>
+template <int RQ>
 __global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, int n) {
     __shared__ uint32_t t[LT_H + 2][LT_W + 2];
     __shared__ int2 s_ab[3][256];
@@ -1762,11 +1788,11 @@ __global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, in
     const int ntx = (W + LT_W - 1) / LT_W;
     const int ty0w = (wgl / ntx) * (LT_H * LT_TILES), tx0 = (wgl % ntx) * LT_W;
     for (int k = threadIdx.x; k < 3 * 256; k += 256) s_ab[k >> 8][k & 255] = coef_prep(h->a_q[k >> 8][k & 255], h->b_q[k >> 8][k & 255]);
-    mlp_bias_load<POW2>(B1, d.model);
+    mlp_bias_load<RQ>(B1, d.model);
     s_cnt[threadIdx.x] = 0;
     const int lane = threadIdx.x & 63, wave = uniform(threadIdx.x >> 6);
     MlpLane L;
-    mlp_lane_load<POW2>(L, d.model, lane);
+    mlp_lane_load<RQ>(L, d.model, lane);
     const int k_img = h->k_img;
     // Tile tt + 1's S words and RGBE words are in flight while tile tt is
     // worked on (every condition below is uniform for the workgroup).
@@ -1815,7 +1841,7 @@ __global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, in
 #pragma unroll
             for (int k = 0; k + 1 < LT_H / 4; ++k) wc[k] = wc[k + 1];
             const int e = (int)(w >> 24);
-            const uint32_t ml = mlp_row<POW2>(wl[wave], B1, L, v, e, k_img, lane);
+            const uint32_t ml = mlp_row<RQ>(wl[wave], B1, L, v, e, k_img, lane);
             int s[3];
             win_gf(v, s);
             win_roll(v);
@@ -2021,7 +2047,7 @@ __global__ __launch_bounds__(256) void k_select(const ImgDesc *__restrict__ D, i
 }
 
 // Learned decoder: M = (flag ? M_L : M*) + r for headers with estimator 1.
-template <bool POW2>
+template <int RQ>
 __global__ __launch_bounds__(256) void k_decode_learned(const ImgDesc *__restrict__ D, int n) {
     __shared__ uint32_t t[LT_H + 2][LT_W + 2];
     __shared__ int2 s_ab[3][256];
@@ -2051,7 +2077,7 @@ __global__ __launch_bounds__(256) void k_decode_learned(const ImgDesc *__restric
         s_ab[k >> 8][k & 255] = coef_prep(aq, bq);
         s_fl[k >> 8][k & 255] = h->flag[k >> 8][k & 255];
     }
-    mlp_bias_load<POW2>(B1, d.model);
+    mlp_bias_load<RQ>(B1, d.model);
     __syncthreads();
     if (s_bad) {  // uniform
         if (threadIdx.x == 0 && d.status) atomicExch(d.status, RDL_ECORRUPT);
@@ -2059,7 +2085,7 @@ __global__ __launch_bounds__(256) void k_decode_learned(const ImgDesc *__restric
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     MlpLane L;
-    mlp_lane_load<POW2>(L, d.model, lane);
+    mlp_lane_load<RQ>(L, d.model, lane);
     const int k_img = h->k_img;
     const int64_t npx = (int64_t)H * W;
     const int16_t *r = (const int16_t *)d.resid;
@@ -2084,7 +2110,7 @@ __global__ __launch_bounds__(256) void k_decode_learned(const ImgDesc *__restric
             const bool in = y < H && x < W;
             const int64_t o = (int64_t)y * W + x;
             const int e = in ? (int)Ep[o] : 0;
-            const uint32_t ml = mlp_row<POW2>(wl[wave], B1, L, v, e, k_img, lane);
+            const uint32_t ml = mlp_row<RQ>(wl[wave], B1, L, v, e, k_img, lane);
             int s[3];
             win_gf(v, s);
             win_roll(v);
@@ -2273,11 +2299,13 @@ void launch_status_init(const ImgDesc *d, int n, hipStream_t s) {
 void launch_decode(const ImgDesc *d, int n, int wgs, hipStream_t s) {
     hipLaunchKernelGGL(k_decode, dim3(wgs), dim3(STRIP_THREADS), 0, s, d, n);
 }
-void launch_learn(const ImgDesc *d, int n, int wgs, bool pow2, hipStream_t s) {
-    if (pow2)
-        hipLaunchKernelGGL(k_learn<true>, dim3(wgs), dim3(256), 0, s, d, n);
+void launch_learn(const ImgDesc *d, int n, int wgs, int rq, hipStream_t s) {
+    if (rq == RQ_PACKED)
+        hipLaunchKernelGGL(k_learn<RQ_PACKED>, dim3(wgs), dim3(256), 0, s, d, n);
+    else if (rq == RQ_POW2)
+        hipLaunchKernelGGL(k_learn<RQ_POW2>, dim3(wgs), dim3(256), 0, s, d, n);
     else
-        hipLaunchKernelGGL(k_learn<false>, dim3(wgs), dim3(256), 0, s, d, n);
+        hipLaunchKernelGGL(k_learn<RQ_GENERAL>, dim3(wgs), dim3(256), 0, s, d, n);
 }
 void launch_lhist(const ImgDesc *d, int n, int wgs, hipStream_t s) {
     hipLaunchKernelGGL(k_lhist, dim3(wgs), dim3(LH_THREADS), 0, s, d, n);
@@ -2285,11 +2313,13 @@ void launch_lhist(const ImgDesc *d, int n, int wgs, hipStream_t s) {
 void launch_select(const ImgDesc *d, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_select, dim3(256 * n), dim3(256), 0, s, d, n);
 }
-void launch_decode_learned(const ImgDesc *d, int n, int wgs, bool pow2, hipStream_t s) {
-    if (pow2)
-        hipLaunchKernelGGL(k_decode_learned<true>, dim3(wgs), dim3(256), 0, s, d, n);
+void launch_decode_learned(const ImgDesc *d, int n, int wgs, int rq, hipStream_t s) {
+    if (rq == RQ_PACKED)
+        hipLaunchKernelGGL(k_decode_learned<RQ_PACKED>, dim3(wgs), dim3(256), 0, s, d, n);
+    else if (rq == RQ_POW2)
+        hipLaunchKernelGGL(k_decode_learned<RQ_POW2>, dim3(wgs), dim3(256), 0, s, d, n);
     else
-        hipLaunchKernelGGL(k_decode_learned<false>, dim3(wgs), dim3(256), 0, s, d, n);
+        hipLaunchKernelGGL(k_decode_learned<RQ_GENERAL>, dim3(wgs), dim3(256), 0, s, d, n);
 }
 void launch_hist(const ImgDesc *d, int n, int wgs, hipStream_t s) {
     hipLaunchKernelGGL(k_hist, dim3(wgs), dim3(TILE_THREADS), 0, s, d, n);

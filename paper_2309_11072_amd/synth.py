@@ -231,11 +231,13 @@ def batch_256_large(n: int = 256) -> list:
             for i, (H, W) in enumerate(sizes)]
 
 
-def random_model(seed: int, scale: int = 8, pow2: bool = False) -> bytes:
+def random_model(seed: int, scale: int = 8, pow2: bool = False, wide_shift: bool = False) -> bytes:
     """A seeded random int8 estimator model (test input), within the value
     limits of the model format, with activations that neither vanish nor
     saturate on synthetic images.  pow2: every hidden requantisation
-    multiplier is 1 (scales are powers of two)."""
+    multiplier is 1 (scales are powers of two), with hidden shifts of at
+    most 8 and a few neurons whose biases push their pre-activations beyond
+    16 bits both ways; wide_shift: pow2 with some hidden shifts above 8."""
     from . import model_format
     rng = np.random.Generator(np.random.PCG64(seed))
     p = {
@@ -251,7 +253,15 @@ def random_model(seed: int, scale: int = 8, pow2: bool = False) -> bytes:
     p["B3"][:3] = rng.integers(0, 2000, 3)
     if pow2:
         p["m1"] = np.ones(32, np.int64)
-        p["r1"] = rng.integers(5, 8, 32)
+        p["r1"] = rng.integers(5, 9, 32)
         p["m2"] = np.ones(32, np.int64)
-        p["r2"] = rng.integers(4, 7, 32)
+        p["r2"] = rng.integers(4, 9, 32)
+        # neurons 0-3 of layer 1 and 0-1 of layer 2: biases beyond +-2^15
+        p["B1"][:, 0:2] = rng.integers(33000, 60000, (32, 2))
+        p["B1"][:, 2:4] = -rng.integers(33000, 60000, (32, 2))
+        p["B2"][0] = 40000
+        p["B2"][1] = -40000
+        if wide_shift:
+            p["r1"][::3] = rng.integers(9, 13, len(p["r1"][::3]))
+            p["r2"][::4] = rng.integers(9, 12, len(p["r2"][::4]))
     return model_format.pack(p)

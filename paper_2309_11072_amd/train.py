@@ -58,15 +58,15 @@ def _mult_shift(ratio: np.ndarray, rmax: int = 28):
     return m, r
 
 
-def _pow2_shift(ratio: np.ndarray):
-    """Shift r in [1, 28] with 2^r >= ratio, the smallest such: a hidden
+def _pow2_shift(ratio: np.ndarray, rmax: int = 28):
+    """Shift r in [1, rmax] with 2^r >= ratio, the smallest such: a hidden
     activation step of sw 2^r is at least the calibrated step, so no more
     values clip at 127 than the calibration allows."""
     r = np.ceil(np.log2(np.maximum(ratio, 1e-30)))
-    return np.clip(r, 1, 28).astype(np.int64)
+    return np.clip(r, 1, rmax).astype(np.int64)
 
 
-def quantise(p: np.ndarray, feats: np.ndarray, bins: np.ndarray, pow2: bool = True) -> bytes:
+def quantise(p: np.ndarray, feats: np.ndarray, bins: np.ndarray, pow2: bool = True, rmax: int = 28) -> bytes:
     """int8 model blob from float parameters; activation scales from the
     float forward pass over the calibration samples (feats int8 [N, 27]).
 
@@ -83,11 +83,15 @@ def quantise(p: np.ndarray, feats: np.ndarray, bins: np.ndarray, pow2: bool = Tr
     lim = 1 << 18
     W1e = P["W1"] / 128.0
     sw1 = np.maximum(np.abs(W1e).max(axis=1), 1e-12) / 127.0
+    if pow2:
+        # with shifts capped at rmax a row whose calibrated step needs more
+        # takes a coarser weight step instead, keeping its activation step
+        sw1 = np.maximum(sw1, s1 / 2.0 ** rmax)
     W1q = np.zeros((32, 32), np.int64)
     W1q[:, :27] = np.clip(np.round(W1e / sw1[:, None]), -127, 127)
     B1q = np.clip(np.round(P["B1"] / sw1[None, :]), -lim, lim)
     if pow2:
-        r1 = _pow2_shift(s1 / sw1)
+        r1 = _pow2_shift(s1 / sw1, rmax)
         m1 = np.ones(32, np.int64)
         t1 = sw1 * 2.0 ** r1  # the actual activation step
     else:
@@ -98,10 +102,12 @@ def quantise(p: np.ndarray, feats: np.ndarray, bins: np.ndarray, pow2: bool = Tr
     s2 = np.maximum(np.percentile(a2, 99.99, axis=0), 1e-9) / 127.0
     W2e = P["W2"] * t1[None, :]
     sw2 = np.maximum(np.abs(W2e).max(axis=1), 1e-12) / 127.0
+    if pow2:
+        sw2 = np.maximum(sw2, s2 / 2.0 ** rmax)
     W2q = np.clip(np.round(W2e / sw2[:, None]), -127, 127)
     B2q = np.clip(np.round(P["B2"] / sw2), -lim, lim)
     if pow2:
-        r2 = _pow2_shift(s2 / sw2)
+        r2 = _pow2_shift(s2 / sw2, rmax)
         m2 = np.ones(32, np.int64)
         t2 = sw2 * 2.0 ** r2
     else:
@@ -197,6 +203,8 @@ def main():
     ap.add_argument("--train-set", choices=("config2", "wide"), default="config2",
                     help="config2: the two 3840x2160 images of the single-image workload's generator; wide: those "
                          "plus eight images over the batch workloads' parameter ranges")
+    ap.add_argument("--rmax", type=int, default=8,
+                    help="largest hidden shift of a power-of-two model (8: the library's packed 16-bit path)")
     ap.add_argument("--general", action="store_true",
                     help="general requantisation multipliers instead of powers of two")
     args = ap.parse_args()
@@ -209,7 +217,8 @@ def main():
     if args.params_out:
         np.save(args.params_out, params)
     calib = samples[:200_000].cpu().numpy()
-    blob = quantise(params, calib[:, :27].view(np.int8), calib[:, 27].astype(np.int64), pow2=not args.general)
+    blob = quantise(params, calib[:, :27].view(np.int8), calib[:, 27].astype(np.int64), pow2=not args.general,
+                    rmax=args.rmax)
     with open(args.out, "wb") as fh:
         fh.write(blob)
     print("model written: %s (%d bytes, hash %016x) after %.1f s" % (args.out, len(blob), model_format.blob_hash(blob),

@@ -39,10 +39,12 @@ CASES = [("1x1", (1, 1), 2.0, 75, 11), ("7x9", (7, 9), 3.0, 50, 12), ("64x64", (
 @pytest.mark.parametrize("name,shape,sig,q,ms", CASES, ids=[c[0] for c in CASES])
 def test_learned_encode_decode_match_oracle(codec, rdl_mod, O, name, shape, sig, q, ms):
     H, W = shape
-    pow2 = ms % 2 == 1  # half of the models take the power-of-two requantisation path
-    _say("learned", name, q, "model", ms, "pow2" if pow2 else "")
+    # half of the models take a power-of-two requantisation path: shifts up to
+    # 8 (packed 16-bit) or some above (32-bit)
+    pow2, wide = ms % 2 == 1, ms % 4 == 3
+    _say("learned", name, q, "model", ms, "pow2" if pow2 else "", "wide shifts" if wide else "")
     x = synth.generate(H, W, sig, seed=700 + ms, spec_frac=0.05)
-    blob = synth.random_model(ms, pow2=pow2)
+    blob = synth.random_model(ms, pow2=pow2, wide_shift=wide)
     codec.set_model(blob)
     codec.set_estimator(1)
     try:
@@ -87,11 +89,11 @@ def test_learned_random_words(codec, rdl_mod, O):
         codec.set_estimator(0)
 
 
-@pytest.mark.parametrize("pow2", [False, True], ids=["general", "pow2"])
-def test_learned_batch_matches_oracle(codec, O, pow2):
+@pytest.mark.parametrize("kind", ["general", "pow2", "pow2_wide"])
+def test_learned_batch_matches_oracle(codec, O, kind):
     specs = [(40, 90, 2.0, 55), (70, 33, 4.0, 90), (129, 66, 1.5, 30)]
-    blob = synth.random_model(51, pow2=pow2)
-    _say("learned batch", "pow2" if pow2 else "general")
+    blob = synth.random_model(51, pow2=kind != "general", wide_shift=kind == "pow2_wide")
+    _say("learned batch", kind)
     codec.set_model(blob)
     codec.set_estimator(1)
     try:

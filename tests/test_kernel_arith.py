@@ -184,3 +184,16 @@ def test_learned_pow2_bias_fold():
         h = rng.integers(-hmax, hmax + 1, 5000).astype(np.int64)
         assert np.array_equal((h * 1 + (1 << (r - 1))) >> r, (h + (1 << (r - 1))) >> r)
         assert hmax + (1 << (r - 1)) < 2 ** 31
+
+
+def test_learned_packed_requantisation():
+    """The 16-bit packed requantisation: for every shift r <= 8, saturating the
+    pre-activation to int16 before the shift leaves clamp(h >> r, 0, 127)
+    unchanged, over the whole range the model format allows (|h| < 2^31 after
+    the rounding constant), and every pair of shifts fits the packed operand;
+    at r = 9 the saturation would change it."""
+    hs = np.concatenate([np.arange(-70000, 70000), np.array([-2 ** 31, 2 ** 31 - 1, -2 ** 20, 2 ** 20])]).astype(np.int64)
+    sat = np.clip(hs, -32768, 32767)
+    for r in range(1, 9):
+        assert np.array_equal(np.clip(hs >> r, 0, 127), np.clip(sat >> r, 0, 127)), r
+    assert not np.array_equal(np.clip(hs >> 9, 0, 127), np.clip(sat >> 9, 0, 127))
