@@ -389,7 +389,8 @@ enum {
     RDL_STAGE_TMO_BASE = 1, /* tone map + JPEG-style base layer -> S   */
     RDL_STAGE_FIT = 2,      /* GF + per-(channel, E) regression sums   */
     RDL_STAGE_SOLVE = 3,    /* fixed-point coefficients -> header      */
-    RDL_STAGE_RESID = 4,    /* GF + estimate + residual planes         */
+    RDL_STAGE_RESID = 4,    /* GF + estimate + residual planes (learned */
+                            /* path: the learned regions' residuals    */
     RDL_NSTAGES = 5
 };
 

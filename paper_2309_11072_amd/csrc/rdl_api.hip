@@ -190,10 +190,10 @@ struct Grid {
 // Point the learned-path buffers of each image (scratch already bound) into
 // an estimate buffer of sum(H*W) words, a record buffer of sum(H*W) words
 // and n histogram blocks.
-void bind_learn(std::vector<ImgDesc> &v, uint8_t *ml, uint64_t *rec, uint32_t *lhist) {
+void bind_learn(std::vector<ImgDesc> &v, uint8_t *lres, uint64_t *rec, uint32_t *lhist) {
     size_t off = 0;
     for (size_t k = 0; k < v.size(); ++k) {
-        v[k].ml = ml + 4 * off;
+        v[k].lres = lres + 4 * off;
         v[k].lrec = rec + off;
         v[k].lhist = lhist + k * lhist_words();
         v[k].lbk = reinterpret_cast<uint32_t *>(v[k].sums - SCR_SUMS + SCR_LBK);
@@ -336,8 +336,10 @@ void enqueue_encode(const ImgDesc *d, int n, const Grid &g, bool learned, hipStr
         mark(1 + RDL_STAGE_LHIST);
         launch_select(d, n, s);
         mark(1 + RDL_STAGE_SELECT);
+        launch_resid_patch(d, n, g.px, s);  // k_learn wrote the SLR residuals
+    } else {
+        launch_resid(d, n, g.res, s, gf);
     }
-    launch_resid(d, n, g.res, s, gf);
     mark(1 + RDL_STAGE_RESID);
 }
 

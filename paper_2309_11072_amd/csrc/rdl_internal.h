@@ -57,7 +57,7 @@ struct ImgDesc {
     int32_t *status;       // decode only, optional
     uint8_t *out_rgbe;     // decode only
     int64_t *hist;         // [3][511] residual histograms
-    uint8_t *ml;           // learned path: [H][W] learned estimates, R | G << 8 | B << 16 words
+    uint8_t *lres;         // learned path: [H][W] learned residuals, (r_c + 255) << 9c words
     uint32_t *lhist;       // learned path: [2][3][256][511] residual histograms (estimator, channel),
                            //   then [3][511] of the SLR residuals over the image
     uint64_t *lrec;        // learned path: [H*W] residual records, grouped by exponent
@@ -109,6 +109,7 @@ void launch_fit_sums(const ImgDesc *d, int n, int wgs, int bins, int waves, hipS
 void launch_solve(const ImgDesc *d, int n, hipStream_t s);
 void launch_key_total(const ImgDesc *d, int n, int64_t *out2, hipStream_t s);
 void launch_resid(const ImgDesc *d, int n, int wgs, hipStream_t s, bool gf = true);
+void launch_resid_patch(const ImgDesc *d, int n, int wgs, hipStream_t s);  // learned path; wgs = wgs_px
 void launch_decode(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_base_decode(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_status_init(const ImgDesc *d, int n, hipStream_t s);

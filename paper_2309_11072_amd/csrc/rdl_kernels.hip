@@ -106,7 +106,7 @@ __device__ __forceinline__ ImgDesc desc_at(const ImgDesc *__restrict__ D, int i)
     d.status = glb(d.status);
     d.out_rgbe = glb(d.out_rgbe);
     d.hist = glb(d.hist);
-    d.ml = glb(d.ml);
+    d.lres = glb(d.lres);
     d.lhist = glb(d.lhist);
     d.lrec = glb(d.lrec);
     d.lbk = glb(d.lbk);
@@ -1238,30 +1238,24 @@ __device__ __forceinline__ int mstar(int2 k, int s) {
 template <bool GF = true>
 __global__ __launch_bounds__(STRIP_THREADS) void k_resid(const ImgDesc *__restrict__ D, int n) {
     __shared__ int2 s_ab[3][256];
-    __shared__ uint8_t s_fl[3][256];
     const int i = find_img(D, n, blockIdx.x, 4);
     const ImgDesc d = desc_at(D, i);
     const int H = d.H, W = d.W;
     const int wgl = blockIdx.x - d.wg_res;
     const rdl_header *h = d.hdr;
-    int flagged = 0;
     for (int k = threadIdx.x; k < 3 * 256; k += STRIP_THREADS) {
         const int c = k >> 8, e = k & 255;
         s_ab[c][e] = coef_prep(h->a_q[c][e], h->b_q[c][e]);
-        s_fl[c][e] = d.ml ? h->flag[c][e] : 0;
-        flagged |= s_fl[c][e];
     }
-    // The learned estimates are read only for an image with a flagged region.
-    const bool learned = __syncthreads_or(flagged) != 0;
+    __syncthreads();
     const StripPos sp = strip_pos(wgl, H, W, d.srh_res);
     if (sp.ya >= H) return;  // uniform per wave; no barrier follows
     const int64_t npx = (int64_t)H * W;
     int16_t *r = (int16_t *)d.resid;
     uint8_t *Ep = d.resid + 6 * npx;
     const bool al = (W & 3) == 0 && ((reinterpret_cast<uintptr_t>(d.resid) & 7) == 0);
-    // Residuals of the lane's four pixels of row y; ml[j] (learned path) holds
-    // M_L of pixel j as R | G << 8 | B << 16, used where the region is flagged.
-    const auto emit = [&](int y, const int (&s)[3][4], const uint32_t (&w)[4], const uint32_t *ml) {
+    // Residuals of the lane's four pixels of row y.
+    const auto emit = [&](int y, const int (&s)[3][4], const uint32_t (&w)[4]) {
         if (sp.x >= W) return;
         const int64_t ro = (int64_t)uniform(y) * W;  // row bases are scalar
         int rv[3][4];
@@ -1270,10 +1264,7 @@ __global__ __launch_bounds__(STRIP_THREADS) void k_resid(const ImgDesc *__restri
             const int e = (int)(w[j] >> 24);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const int2 ab = s_ab[c][e];
-                int est = mstar(ab, s[c][j]);
-                if (ml && s_fl[c][e]) est = (int)((ml[j] >> (8 * c)) & 255u);
-                rv[c][j] = (int)((w[j] >> (8 * c)) & 255u) - est;
+                rv[c][j] = (int)((w[j] >> (8 * c)) & 255u) - mstar(s_ab[c][e], s[c][j]);
             }
         }
         int16_t *rr = r + ro;
@@ -1297,11 +1288,69 @@ __global__ __launch_bounds__(STRIP_THREADS) void k_resid(const ImgDesc *__restri
             }
         }
     };
-    if (learned)
-        strip_walk_x<true, GF>(d, sp, d.ml, [&](int y, const int (&s)[3][4], const uint32_t (&w)[4],
-                                                const uint32_t (&x)[4]) { emit(y, s, w, x); });
-    else
-        strip_walk<GF>(d, sp, [&](int y, const int (&s)[3][4], const uint32_t (&w)[4]) { emit(y, s, w, nullptr); });
+    strip_walk<GF>(d, sp, emit);
+}
+
+// Learned path, last stage: k_learn left the SLR residual planes, the
+// exponent plane and every pixel's learned residuals in the outputs; in the
+// regions flagged learned each channel's residual becomes the learned one.
+// The key statistic's grid (KS_PX_PER_WG consecutive pixels per workgroup,
+// 16 waves so that a small image still keeps enough loads in flight); a
+// step covers 16 x 1024 pixels, lane-consecutive so that every plane is read
+// and written in whole lines at any alignment.  An image without a flagged
+// region returns at once.
+constexpr int PATCH_THREADS = 1024, PATCH_RUN = 16;
+static_assert(KS_PX_PER_WG % (PATCH_THREADS * PATCH_RUN) == 0, "k_resid_patch: whole steps per workgroup");
+__device__ __forceinline__ int lres_field(uint32_t w, int c) { return (int)((w >> (9 * c)) & 511u) - 255; }
+
+__global__ __launch_bounds__(PATCH_THREADS) void k_resid_patch(const ImgDesc *__restrict__ D, int n) {
+    constexpr int STEP = PATCH_THREADS * PATCH_RUN, NSTEP = KS_PX_PER_WG / STEP;
+    __shared__ uint8_t s_fl[256];  // bit c set: channel c of exponent e is learned
+    const int i = find_img(D, n, blockIdx.x, 0);
+    const ImgDesc d = desc_at(D, i);
+    const int64_t npx = (int64_t)d.H * d.W;
+    const int64_t base = (int64_t)(blockIdx.x - d.wg_px) * KS_PX_PER_WG + threadIdx.x;
+    const uint8_t *__restrict__ ep = d.resid + 6 * npx;
+    int16_t *res = reinterpret_cast<int16_t *>(d.resid);
+    const uint32_t *__restrict__ lr = reinterpret_cast<const uint32_t *>(d.lres);
+    // Exponents of step it, at clamped addresses (the loads stay
+    // unconditional; pixels past the end are masked when used).
+    const auto load_e = [&](int it, uint32_t (&ev)[PATCH_RUN]) {
+#pragma unroll
+        for (int j = 0; j < PATCH_RUN; ++j) ev[j] = ep[min(base + it * STEP + j * PATCH_THREADS, npx - 1)];
+    };
+    uint32_t ev[2][PATCH_RUN];
+    load_e(0, ev[0]);  // in flight with the flags
+    int f0 = 0;
+    if (threadIdx.x < 256) {  // one exponent per thread
+        const int e = threadIdx.x;
+        f0 = d.hdr->flag[0][e] | (d.hdr->flag[1][e] << 1) | (d.hdr->flag[2][e] << 2);
+        s_fl[e] = (uint8_t)f0;
+    }
+    if (!__syncthreads_or(f0)) return;  // uniform
+#pragma unroll
+    for (int it = 0; it < NSTEP; ++it) {
+        const int64_t p0 = base + it * STEP;
+        if (p0 >= npx) break;
+        if (it + 1 < NSTEP) load_e(it + 1, ev[(it + 1) & 1]);
+        uint32_t f[PATCH_RUN], any = 0;
+#pragma unroll
+        for (int j = 0; j < PATCH_RUN; ++j) {
+            f[j] = p0 + j * PATCH_THREADS < npx ? s_fl[ev[it & 1][j]] : 0u;
+            any |= f[j];
+        }
+        if (!any) continue;
+        uint32_t w[PATCH_RUN];
+#pragma unroll
+        for (int j = 0; j < PATCH_RUN; ++j) w[j] = f[j] ? lr[p0 + j * PATCH_THREADS] : 0u;
+#pragma unroll
+        for (int j = 0; j < PATCH_RUN; ++j) {
+            const int64_t p = p0 + j * PATCH_THREADS;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if ((f[j] >> c) & 1) res[c * npx + p] = (int16_t)lres_field(w[j], c);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1763,9 +1812,10 @@ __device__ __forceinline__ uint64_t lrec_pack(const int rs[3], const int rl[3]) 
     return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
-// Encoder side: learned estimates M_L (stored for the residual stage) and
-// both estimators' residuals, written as one record per pixel into the
-// bucket of its exponent.  Bucket e starts at the number of pixels with a
+// Encoder side: the SLR residual planes and the exponent plane of the output
+// (final wherever the region stays SLR), the learned residuals M - M_L as
+// 9-bit fields (r_c + 255 at bit 9c, for the last stage), and both
+// estimators' residuals as one record per pixel in the bucket of its exponent.  Bucket e starts at the number of pixels with a
 // smaller exponent (k_solve sets the cursors there); per 16-row tile the
 // workgroup ranks its pixels of each exponent with LDS atomics, reserves
 // that many records with one global atomic per exponent, and writes them.
@@ -1812,7 +1862,10 @@ __global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, in
         fetch_lt_rows(sv, d.sdr, H, W, ty0w, wave, lane, cols);
         fetch_rgbe(ty0w, wv);
     }
-    uint32_t *ml_out = reinterpret_cast<uint32_t *>(d.ml);
+    uint32_t *lres_out = reinterpret_cast<uint32_t *>(d.lres);
+    const int64_t npx = (int64_t)H * W;
+    int16_t *res16 = reinterpret_cast<int16_t *>(d.resid);
+    uint8_t *eplane = d.resid + 6 * npx;
     for (int tt = 0; tt < LT_TILES; ++tt) {
         const int ty0 = ty0w + tt * LT_H;
         if (ty0 >= H) break;
@@ -1853,7 +1906,15 @@ __global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, in
                 rl[c] = m - (int)((ml >> (8 * c)) & 255u);
             }
             s_rec[ly][lane] = lrec_pack(rs, rl);
-            if (in) (ml_out + (int64_t)y * W)[x] = ml;
+            if (in) {
+                const int64_t ro = (int64_t)y * W;
+                (lres_out + ro)[x] = (uint32_t)(rl[0] + 255) | (uint32_t)(rl[1] + 255) << 9 | (uint32_t)(rl[2] + 255) << 18;
+                // the SLR residuals and the exponent, final unless the region
+                // is flagged learned (k_resid_patch)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) (res16 + c * npx + ro)[x] = (int16_t)rs[c];
+                (eplane + ro)[x] = (uint8_t)e;
+            }
             // Rank among the tile's pixels of the same exponent (a row holds
             // about a dozen exponents, so one atomic per lane beats a loop
             // over them).
@@ -2289,6 +2350,9 @@ void launch_resid(const ImgDesc *d, int n, int wgs, hipStream_t s, bool gf) {
         hipLaunchKernelGGL(k_resid<true>, dim3(wgs), dim3(STRIP_THREADS), 0, s, d, n);
     else
         hipLaunchKernelGGL(k_resid<false>, dim3(wgs), dim3(STRIP_THREADS), 0, s, d, n);
+}
+void launch_resid_patch(const ImgDesc *d, int n, int wgs, hipStream_t s) {
+    hipLaunchKernelGGL(k_resid_patch, dim3(wgs), dim3(PATCH_THREADS), 0, s, d, n);
 }
 void launch_base_decode(const ImgDesc *d, int n, int wgs, hipStream_t s) {
     hipLaunchKernelGGL(k_base_decode, dim3(wgs), dim3(BLK_THREADS), 0, s, d, n);

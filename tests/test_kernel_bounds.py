@@ -418,3 +418,34 @@ def test_exponent_difference_kernels_model(H, W, lead):
     flat = E.reshape(-1).astype(np.uint8)
     assert np.array_equal(_diff_model(flat, W, lead), d.reshape(-1))
     assert np.array_equal(_undo_model(d.reshape(-1).astype(np.uint8), W, lead), E.reshape(-1))
+
+
+# ---- learned path: the residual patch ----------------------------------------
+KS_PX_PER_WG, PATCH_THREADS, PATCH_RUN = 32768, 1024, 16
+
+
+@pytest.mark.parametrize("npx", [1, 63, 4095, 4097, 32767, 32768, 32769, 7 * 9, 3840 * 2160, 4492 * 5989])
+def test_resid_patch_covers_each_pixel_once(npx):
+    """k_resid_patch: workgroup g of an image (ceil(npx / KS_PX_PER_WG) of
+    them) takes pixels g KS_PX_PER_WG + it 16384 + j 1024 + lane; the exponent
+    loads use indices clamped to [0, npx) and every pixel index that passes
+    the bound is taken exactly once, so the residual stores c npx + p stay
+    inside the planes."""
+    nwg = (npx + KS_PX_PER_WG - 1) // KS_PX_PER_WG
+    lanes = np.arange(PATCH_THREADS, dtype=np.int64)
+    seen = np.zeros(npx, np.int32)
+    step = PATCH_THREADS * PATCH_RUN
+    for g in range(nwg):
+        base = g * KS_PX_PER_WG + lanes
+        for it in range(KS_PX_PER_WG // step):
+            p0 = base + it * step
+            live = p0 < npx
+            if not live.any():
+                break
+            for j in range(PATCH_RUN):
+                p = p0[live] + j * PATCH_THREADS
+                clamped = np.minimum(p, npx - 1)
+                assert clamped.min() >= 0 and clamped.max() < npx
+                ok = p[p < npx]
+                np.add.at(seen, ok, 1)
+    assert (seen == 1).all()
