@@ -208,22 +208,28 @@ int rdl_set_launch_mode(rdl_ctx *ctx, int mode);
  * estimator needs no learning, Sec. I) ----
  * A model is an int8 MLP over each pixel's 3x3 x 3-channel neighbourhood of S
  * (bytes S - 128) plus a 32-bin exponent one-hot (entering as a bias row),
- * two hidden layers of 32 (ReLU, int32 accumulate, requantised to int8) and a
- * Q8 output per channel.  Blob: RDL_MODEL_BYTES bytes, little endian:
- *   u32 magic 'RDLM', u32 version 1, u64 FNV-1a-64 hash of bytes 24..end,
+ * two hidden layers of 32 (ReLU, int32 accumulate, requantised to unsigned
+ * bytes) and a Q8 output per channel.  Blob: RDL_MODEL_BYTES bytes, little
+ * endian:
+ *   u32 magic 'RDLM', u32 version 2, u64 FNV-1a-64 hash of bytes 24..end,
  *   u32 reserved[2], i8 W1[32][32] (out, in), i32 B1[32][32] (bin, out),
  *   i32 m1[32], r1[32], i8 W2[32][32], i32 B2[32], m2[32], r2[32],
  *   i8 W3[16][32], i32 B3[16], m3[16], r3[16];
  * bin = clamp(E - 136 + k_img + 24, 0, 31); hidden a = clamp((h m + 2^(r-1))
- * >> r, 0, 127); output q8 = (o m3 + 2^(r3-1)) >> r3, estimate
- * clamp((q8 + 128) >> 8, 0, 255).  Accepted only with m in [1, 2^11),
- * r in [1, 28] and |B| <= 2^18.
+ * >> r, 0, 255); output q8 = (o m3 + 2^(r3-1)) >> r3, estimate
+ * clamp((q8 + 128) >> 8, 0, 255).  Accepted only with m in [1, 2^10),
+ * r in [1, 28] (r3 in [1, 22]) and |B| <= 2^18.  Fastest: every hidden m = 1,
+ * hidden r <= 22 and equal r in each neuron pair (2k, 2k + 1).
  *
  * rdl_set_model copies a HOST blob to the device (NULL clears it); RDL_ECORRUPT
  * for a bad magic, hash or value limit.  rdl_set_estimator(ctx, 1) makes the
- * encoders compute, per (channel, E) region, the integer zeroth-order entropy
- * cost of both estimators' residuals and use the learned estimate only where
- * it is strictly lower (flag[c][E] = 1, estimator = 1, model_hash set); 0
+ * encoders compute, per (channel, E) region, the code length of both
+ * estimators' residuals under the image's SLR residual histogram of that
+ * channel (Q16 integer log2; a learned residual value absent from that
+ * histogram rules the learned estimate out) and use the learned estimate only
+ * where it is strictly shorter (flag[c][E] = 1, estimator = 1, model_hash
+ * set), so that, up to the rounding of the Q16 logarithms, the image's
+ * zeroth-order entropy never exceeds plain SLR's (Gibbs' inequality); 0
  * restores plain SLR.  The decoder uses the context's model for headers with
  * estimator 1 (status RDL_ECORRUPT if the hash differs or no model is set). */
 #define RDL_MODEL_BYTES 7512

@@ -641,7 +641,7 @@ void oracle_resid_hist(const void *resid, int64_t npx, int64_t *hist /* [3][511]
 /* ------------------------------------------------------------------------ */
 /* C16: learned int8 mantissa estimator (an extension, not in the paper: the */
 /* paper's estimator needs no learning, Sec. I).  Model blob, little endian:  */
-/*   u32 magic 'RDLM', u32 version 1, u64 hash, u32 reserved[2];            */
+/*   u32 magic 'RDLM', u32 version 2, u64 hash, u32 reserved[2];            */
 /*   i8  W1[32][32] (out, in)   i32 B1[32][32] (bin, out)                    */
 /*   i32 m1[32], r1[32]                                                      */
 /*   i8  W2[32][32]             i32 B2[32], m2[32], r2[32]                    */
@@ -650,7 +650,7 @@ void oracle_resid_hist(const void *resid, int64_t npx, int64_t *hist /* [3][511]
 /* neighbourhood k = 3(dy+1) + (dx+1) (replicated at the image border),      */
 /* x[27..31] = 0.  Exponent bin b = clamp(E - 136 + k_img + 24, 0, 31): the  */
 /* exponent one-hot enters as the bias row B1[b].                            */
-/* Hidden layers: a = clamp((h m + 2^(r-1)) >> r, 0, 127) (64-bit product).  */
+/* Hidden layers: a = clamp((h m + 2^(r-1)) >> r, 0, 255) (64-bit product).  */
 /* Output c (0..2): q8 = (o m3 + 2^(r3-1)) >> r3, M_L = clamp((q8 + 128) >> 8). */
 /* ------------------------------------------------------------------------ */
 #define MLP_BYTES 7512
@@ -665,7 +665,7 @@ static int mlp_parse(const uint8_t *blob, mlp_view *v)
     uint32_t magic, version;
     memcpy(&magic, blob, 4);
     memcpy(&version, blob + 4, 4);
-    if (magic != 0x4D4C4452u || version != 1u) return -3;
+    if (magic != 0x4D4C4452u || version != 2u) return -3;
     const uint8_t *p = blob + 24;
     v->W1 = (const int8_t *)p; p += 1024;
     v->B1 = (const int32_t *)p; p += 4096;
@@ -692,13 +692,13 @@ static void mlp_pixel(const mlp_view *v, const int feat[32], int b, int out[3])
         int64_t h = v->B1[b * 32 + n];
         for (int k = 0; k < 32; k++) h += (int64_t)v->W1[n * 32 + k] * feat[k];
         int64_t q = shr_round(h * v->m1[n], v->r1[n]);
-        a1[n] = q < 0 ? 0 : (q > 127 ? 127 : (int)q);
+        a1[n] = q < 0 ? 0 : (q > 255 ? 255 : (int)q);
     }
     for (int n = 0; n < 32; n++) {
         int64_t h = v->B2[n];
         for (int k = 0; k < 32; k++) h += (int64_t)v->W2[n * 32 + k] * a1[k];
         int64_t q = shr_round(h * v->m2[n], v->r2[n]);
-        a2[n] = q < 0 ? 0 : (q > 127 ? 127 : (int)q);
+        a2[n] = q < 0 ? 0 : (q > 255 ? 255 : (int)q);
     }
     for (int c = 0; c < 3; c++) {
         int64_t o = v->B3[c];

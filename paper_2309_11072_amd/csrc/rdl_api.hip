@@ -1197,7 +1197,7 @@ int rdl_set_model(rdl_ctx *c, const void *blob, size_t nbytes) {
     memcpy(&magic, b, 4);
     memcpy(&version, b + 4, 4);
     memcpy(&hash, b + 8, 8);
-    if (magic != 0x4D4C4452u || version != 1u) return RDL_ECORRUPT;
+    if (magic != 0x4D4C4452u || version != 2u) return RDL_ECORRUPT;
     if (fnv1a64(b + 24, MODEL_BYTES - 24) != hash) return RDL_ECORRUPT;
     auto i32 = [&](int off, int k) {
         int32_t v;
@@ -1209,7 +1209,7 @@ int rdl_set_model(rdl_ctx *c, const void *blob, size_t nbytes) {
     for (int l = 0; l < 3; ++l)
         for (int k = 0; k < cnt[l]; ++k) {
             const int32_t m = i32(offs_m[l], k), r = i32(offs_r[l], k);
-            if (m < 1 || m >= (1 << 11) || r < 1 || r > 28) return RDL_ECORRUPT;
+            if (m < 1 || m >= (1 << 10) || r < 1 || r > 28) return RDL_ECORRUPT;
         }
     for (int k = 0; k < 1024; ++k)
         if (std::abs(i32(1048, k)) > (1 << 18)) return RDL_ECORRUPT;
@@ -1218,19 +1218,38 @@ int rdl_set_model(rdl_ctx *c, const void *blob, size_t nbytes) {
     for (int k = 0; k < 16; ++k)
         if (std::abs(i32(7320, k)) > (1 << 18)) return RDL_ECORRUPT;
     // The estimator folds the output rounding into one shift by r3 + 8
-    // (see mlp_wave64); with |o| <= 32 * 127 * 127 + 2^18 and m3 < 2^11 the
+    // (see mlp_wave64); with |o| <= 32 * 127 * 255 + 2^18 and m3 < 2^10 the
     // folded 32-bit numerator stays below 2^31 for r3 <= 22.
     for (int k = 0; k < 3; ++k)
         if (i32(7448, k) > 22) return RDL_ECORRUPT;
-    bool pow2 = true, short_shift = true;
+    // Requantisation path: multipliers of 1 with shifts up to 22 let the
+    // rounding constant and the -128 offset ride on the biases (2^(r+7) stays
+    // below 2^30); equal shifts in every neuron pair let one instruction
+    // requantise the pair.
+    bool pow2 = true, pair = true;
     for (int k = 0; k < 32; ++k) {
-        pow2 = pow2 && i32(5144, k) == 1 && i32(6552, k) == 1;
-        short_shift = short_shift && i32(5272, k) <= 8 && i32(6680, k) <= 8;
+        pow2 = pow2 && i32(5144, k) == 1 && i32(6552, k) == 1 && i32(5272, k) <= 22 && i32(6680, k) <= 22;
+        pair = pair && i32(5272, k) == i32(5272, k ^ 1) && i32(6680, k) == i32(6680, k ^ 1);
     }
-    if (!c->d_model) HIPCHK(hipMalloc(&c->d_model, MODEL_BYTES));
-    HIPCHK(hipMemcpy(c->d_model, b, MODEL_BYTES, hipMemcpyHostToDevice));
+    std::vector<uint8_t> dev(MODEL_DEV_BYTES);
+    memcpy(dev.data(), b, MODEL_BYTES);
+    const auto row_sum = [&](int off, int row) {
+        int sum = 0;
+        for (int k = 0; k < 32; ++k) sum += (int8_t)b[off + 32 * row + k];
+        return sum;
+    };
+    for (int k = 0; k < 32; ++k) {
+        const int32_t v = i32(6424, k) + 128 * row_sum(5400, k);
+        memcpy(dev.data() + MODEL_B2X + 4 * k, &v, 4);
+    }
+    for (int k = 0; k < 16; ++k) {
+        const int32_t v = i32(7320, k) + 128 * row_sum(6808, k);
+        memcpy(dev.data() + MODEL_B3X + 4 * k, &v, 4);
+    }
+    if (!c->d_model) HIPCHK(hipMalloc(&c->d_model, MODEL_DEV_BYTES));
+    HIPCHK(hipMemcpy(c->d_model, dev.data(), MODEL_DEV_BYTES, hipMemcpyHostToDevice));
     c->model_hash = hash;
-    c->model_rq = !pow2 ? 0 : short_shift ? 2 : 1;
+    c->model_rq = !pow2 ? 0 : pair ? 2 : 1;
     return RDL_OK;
 }
 

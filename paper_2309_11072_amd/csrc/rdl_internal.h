@@ -28,6 +28,10 @@ constexpr int LCH = 16384;         // learned path: residual records per histogr
 constexpr int LH_COPIES = 8;       //   and its lane-interleaved LDS histogram copies
 constexpr int LEARN_W = 64, LEARN_H = 64;  // learned path: 64 x 64 px per workgroup
 constexpr int MODEL_BYTES = 7512;
+// The device copy of a model appends biases derived on the host when it is
+// set: B2[n] + 128 sum_k W2[n][k] (32 x i32) and B3[c] + 128 sum_k W3[c][k]
+// (16 x i32), the biases for hidden activations offset by -128.
+constexpr int MODEL_B2X = MODEL_BYTES, MODEL_B3X = MODEL_BYTES + 128, MODEL_DEV_BYTES = MODEL_BYTES + 192;
 constexpr int TILE_H = 16;         // residual histogram: 16 x 128 px tiles,
 constexpr int TILE_W = 128;        //   256 lanes x 8 consecutive px
 constexpr int TILE_THREADS = 256;

@@ -1467,10 +1467,15 @@ __global__ __launch_bounds__(STRIP_THREADS) void k_decode(const ImgDesc *__restr
 // B3/m3/r3 i32[16].  Features: the 3x3 neighbourhood of S, 3 bytes per
 // neighbour (S - 128 as int8), 27 of 32 slots; the exponent enters as the bias
 // row B1[bin], bin = clamp(E - 136 + k_img + 24, 0, 31).  Hidden layers:
-// a = clamp((h m + 2^(r-1)) >> r, 0, 127); output: q8 = (o m3 + 2^(r3-1)) >>
+// a = clamp((h m + 2^(r-1)) >> r, 0, 255); output: q8 = (o m3 + 2^(r3-1)) >>
 // r3, M_L = clamp((q8 + 128) >> 8, 0, 255).  The library accepts only models
 // whose multipliers, shifts and biases keep every product below 2^31, so
 // 32-bit arithmetic equals the exact one.
+//
+// The MFMA operands are signed bytes, so a hidden activation a in [0, 255]
+// enters the next layer as a - 128 (a XOR 0x80), and the next layer's bias
+// carries 128 sum_k W[n][k]: sum_k W[n][k] (a_k - 128) + b_n + 128 sum_k
+// W[n][k] = sum_k W[n][k] a_k + b_n exactly.
 //
 // Each layer is an int8 MFMA D = W X with pixels along N: v_mfma_i32_16x16x32
 // takes lane l's A bytes = W[l%16][k], B bytes = X[k][l%16] for the eight k of
@@ -1487,26 +1492,26 @@ __global__ __launch_bounds__(STRIP_THREADS) void k_decode(const ImgDesc *__restr
 constexpr int MB_W1 = 24, MB_B1 = 1048, MB_M1 = 5144, MB_R1 = 5272, MB_W2 = 5400, MB_B2 = 6424, MB_M2 = 6552,
               MB_R2 = 6680, MB_W3 = 6808, MB_B3 = 7320, MB_M3 = 7384, MB_R3 = 7448;
 typedef int v4i __attribute__((ext_vector_type(4)));
-typedef short s16x2 __attribute__((ext_vector_type(2)));
 
 // Requantisation paths of the hidden layers, chosen per model when it is
-// set: RQ_GENERAL a = clamp((h m + 2^(r-1)) >> r, 0, 127); RQ_POW2 every
-// hidden multiplier is 1, so the rounding constant 2^(r-1) rides on the
-// biases (the MFMAs' C inputs) and a = clamp(h >> r, 0, 127); RQ_PACKED is
-// RQ_POW2 with every hidden shift at most 8, where saturating h to 16 bits
-// first changes nothing (a value beyond +-2^15 shifts to at least +-128, a
-// clamp either way), so two neurons share each packed 16-bit shift, max and
-// min.
-enum { RQ_GENERAL = 0, RQ_POW2 = 1, RQ_PACKED = 2 };
+// set.  RQ_GENERAL: a = clamp((h m + 2^(r-1)) >> r, 0, 255), bytes packed,
+// then XOR 0x80.  RQ_POW2: every hidden multiplier is 1 and every hidden
+// shift at most 22, so the rounding constant and the offset ride on the
+// biases (the MFMAs' C inputs) and a - 128 = clamp((h + 2^(r-1) - 2^(r+7))
+// >> r, -128, 127).  RQ_PAIR: RQ_POW2 with equal shifts in every neuron pair
+// (2k, 2k + 1), where one v_ashr_pk_i8_i32 shifts, saturates and packs the
+// pair.
+enum { RQ_GENERAL = 0, RQ_POW2 = 1, RQ_PAIR = 2 };
 
 struct MlpLane {
     long w1a, w1b, w2a, w2b;      // this lane's A fragments of layers 1 and 2
     long w3[4];                   // output layer, one fragment per pixel group (see mlp_wave64)
     int m1[8], r1[8], c1[8];      // requantisation of this lane's eight neurons: multiplier,
     int m2[8], r2[8], c2[8];      //   shift, rounding constant 2^(r-1)
-    int b2[8];                    // layer-2 biases (rounding constant included unless RQ_GENERAL)
-    s16x2 r1p[4], r2p[4];         // RQ_PACKED: the shifts of neuron pairs (0,1), (2,3), (4,5), (6,7)
-    int m3[3], r3[3], c3[3], b3[3];  // output: multiplier, r3 + 8, 2^(r3-1) + 2^(r3+7), bias
+    int b2[8];                    // layer-2 C input: bias + 128 sum_k W2[n][k]
+                                  //   (+ 2^(r-1) - 2^(r+7) unless RQ_GENERAL)
+    int m3[3], r3[3], c3[3], b3[3];  // output: multiplier, r3 + 8, 2^(r3-1) + 2^(r3+7),
+                                     //   bias + 128 sum_k W3[c][k]
 };
 
 // Eight weight bytes of row `row` at the columns lane quad q takes as its k:
@@ -1531,66 +1536,63 @@ __device__ __forceinline__ void mlp_lane_load(MlpLane &L, const uint8_t *__restr
     for (int g = 0; g < 4; ++g) L.w3[g] = (j >> 2) == g && (j & 3) < 3 ? w_fwd(blob + MB_W3, j & 3, q) : 0;
     const int32_t *m1 = reinterpret_cast<const int32_t *>(blob + MB_M1), *r1 = reinterpret_cast<const int32_t *>(blob + MB_R1);
     const int32_t *m2 = reinterpret_cast<const int32_t *>(blob + MB_M2), *r2 = reinterpret_cast<const int32_t *>(blob + MB_R2);
-    const int32_t *b2 = reinterpret_cast<const int32_t *>(blob + MB_B2);
+    // the biases for offset inputs, appended to the device copy of the model
+    const int32_t *b2x = reinterpret_cast<const int32_t *>(blob + MODEL_B2X);
     const int32_t *m3 = reinterpret_cast<const int32_t *>(blob + MB_M3), *r3 = reinterpret_cast<const int32_t *>(blob + MB_R3);
-    const int32_t *b3 = reinterpret_cast<const int32_t *>(blob + MB_B3);
+    const int32_t *b3x = reinterpret_cast<const int32_t *>(blob + MODEL_B3X);
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
         const int nn = t < 4 ? 4 * q + t : 16 + 4 * q + t - 4;
         L.m1[t] = m1[nn]; L.r1[t] = r1[nn]; L.c1[t] = 1 << (r1[nn] - 1);
         L.m2[t] = m2[nn]; L.r2[t] = r2[nn]; L.c2[t] = 1 << (r2[nn] - 1);
-        L.b2[t] = b2[nn] + (RQ != RQ_GENERAL ? L.c2[t] : 0);
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        L.r1p[t] = s16x2{(short)L.r1[2 * t], (short)L.r1[2 * t + 1]};
-        L.r2p[t] = s16x2{(short)L.r2[2 * t], (short)L.r2[2 * t + 1]};
+        L.b2[t] = b2x[nn] + (RQ != RQ_GENERAL ? L.c2[t] - (1 << (r2[nn] + 7)) : 0);
     }
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
         L.m3[t] = m3[t];
         L.r3[t] = r3[t] + 8;
         L.c3[t] = (1 << (r3[t] - 1)) + (1 << (r3[t] + 7));
-        L.b3[t] = b3[t];
+        L.b3[t] = b3x[t];
     }
 }
 
 // The bias table B1[bin][neuron] in LDS, with each neuron's rounding constant
-// added unless RQ_GENERAL (256 threads).
+// and offset 2^(r-1) - 2^(r+7) added unless RQ_GENERAL (256 threads).
 template <int RQ>
 __device__ __forceinline__ void mlp_bias_load(int32_t (*B1)[32], const uint8_t *__restrict__ blob) {
     const int32_t *b1 = reinterpret_cast<const int32_t *>(blob + MB_B1);
     const int32_t *r1 = reinterpret_cast<const int32_t *>(blob + MB_R1);
-    for (int k = threadIdx.x; k < 1024; k += 256)
-        (&B1[0][0])[k] = b1[k] + (RQ != RQ_GENERAL ? 1 << (r1[k & 31] - 1) : 0);
+    for (int k = threadIdx.x; k < 1024; k += 256) {
+        const int r = r1[k & 31];
+        (&B1[0][0])[k] = b1[k] + (RQ != RQ_GENERAL ? (1 << (r - 1)) - (1 << (r + 7)) : 0);
+    }
 }
 
+// One requantised neuron in the low byte: RQ_GENERAL a (XORed with 0x80 by
+// the caller), RQ_POW2 a - 128.
 template <int RQ>
-__device__ __forceinline__ uint32_t requant_u8(int h, int m, int r, int c) {
-    if (RQ != RQ_GENERAL) return (uint32_t)min(max(h >> r, 0), 127);
-    return (uint32_t)min(max((__mul24(h, m) + c) >> r, 0), 127);
+__device__ __forceinline__ uint32_t requant_byte(int h, int m, int r, int c) {
+    if (RQ != RQ_GENERAL) return (uint32_t)min(max(h >> r, -128), 127);
+    return (uint32_t)min(max((__mul24(h, m) + c) >> r, 0), 255);
 }
 
-// Four requantised bytes packed low to high.  RQ_PACKED: both halves of a
-// pair saturated to 16 bits in one instruction, then shifted and clamped
-// together, and one byte permute joins the pairs; otherwise two byte
+// Four neurons' MFMA input bytes a - 128, packed low to high.  RQ_PAIR: one
+// shift-saturate-pack per pair and one byte permute; otherwise two byte
 // permutes join pairs and a third joins the pairs.
 template <int RQ>
-__device__ __forceinline__ uint32_t requant4(const v4i h, const int *m, const int *r, const int *c,
-                                             const s16x2 *rp) {
-    if (RQ == RQ_PACKED) {
-        const s16x2 z = {0, 0}, hi = {127, 127};
-        s16x2 a = __builtin_amdgcn_cvt_pk_i16(h[0], h[1]);
-        s16x2 b = __builtin_amdgcn_cvt_pk_i16(h[2], h[3]);
-        a = __builtin_elementwise_min(__builtin_elementwise_max(a >> rp[0], z), hi);
-        b = __builtin_elementwise_min(__builtin_elementwise_max(b >> rp[1], z), hi);
-        return __builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, b), __builtin_bit_cast(uint32_t, a), 0x06040200u);
+__device__ __forceinline__ uint32_t requant4(const v4i h, const int *m, const int *r, const int *c) {
+    if (RQ == RQ_PAIR) {
+        typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+        const u16x2 p = {__builtin_amdgcn_ashr_pk_i8_i32(h[0], h[1], r[0]),
+                         __builtin_amdgcn_ashr_pk_i8_i32(h[2], h[3], r[2])};
+        return __builtin_bit_cast(uint32_t, p);
     }
-    const uint32_t x01 = __builtin_amdgcn_perm(requant_u8<RQ>(h[1], m[1], r[1], c[1]),
-                                               requant_u8<RQ>(h[0], m[0], r[0], c[0]), 0x0c0c0400u);
-    const uint32_t x23 = __builtin_amdgcn_perm(requant_u8<RQ>(h[3], m[3], r[3], c[3]),
-                                               requant_u8<RQ>(h[2], m[2], r[2], c[2]), 0x0c0c0400u);
-    return __builtin_amdgcn_perm(x23, x01, 0x05040100u);
+    const uint32_t x01 = __builtin_amdgcn_perm(requant_byte<RQ>(h[1], m[1], r[1], c[1]),
+                                               requant_byte<RQ>(h[0], m[0], r[0], c[0]), 0x0c0c0400u);
+    const uint32_t x23 = __builtin_amdgcn_perm(requant_byte<RQ>(h[3], m[3], r[3], c[3]),
+                                               requant_byte<RQ>(h[2], m[2], r[2], c[2]), 0x0c0c0400u);
+    const uint32_t x = __builtin_amdgcn_perm(x23, x01, 0x05040100u);
+    return RQ == RQ_GENERAL ? x ^ 0x80808080u : x;
 }
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -1632,12 +1634,12 @@ __device__ __forceinline__ uint32_t mlp_wave64(const MlpWaveLds &w, const int32_
         const v4i c1b = *reinterpret_cast<const v4i *>(&B1[b][16 + 4 * q]);
         const v4i h1a = __builtin_amdgcn_mfma_i32_16x16x32_i8(L.w1a, xb, c1a, 0, 0, 0);
         const v4i h1b = __builtin_amdgcn_mfma_i32_16x16x32_i8(L.w1b, xb, c1b, 0, 0, 0);
-        const long a1 = (long)((uint64_t)requant4<RQ>(h1a, L.m1, L.r1, L.c1, L.r1p) |
-                               ((uint64_t)requant4<RQ>(h1b, L.m1 + 4, L.r1 + 4, L.c1 + 4, L.r1p + 2) << 32));
+        const long a1 = (long)((uint64_t)requant4<RQ>(h1a, L.m1, L.r1, L.c1) |
+                               ((uint64_t)requant4<RQ>(h1b, L.m1 + 4, L.r1 + 4, L.c1 + 4) << 32));
         const v4i h2a = __builtin_amdgcn_mfma_i32_16x16x32_i8(L.w2a, a1, c2a, 0, 0, 0);
         const v4i h2b = __builtin_amdgcn_mfma_i32_16x16x32_i8(L.w2b, a1, c2b, 0, 0, 0);
-        const long a2 = (long)((uint64_t)requant4<RQ>(h2a, L.m2, L.r2, L.c2, L.r2p) |
-                               ((uint64_t)requant4<RQ>(h2b, L.m2 + 4, L.r2 + 4, L.c2 + 4, L.r2p + 2) << 32));
+        const long a2 = (long)((uint64_t)requant4<RQ>(h2a, L.m2, L.r2, L.c2) |
+                               ((uint64_t)requant4<RQ>(h2b, L.m2 + 4, L.r2 + 4, L.c2 + 4) << 32));
         o = __builtin_amdgcn_mfma_i32_16x16x32_i8(L.w3[g], a2, o, 0, 0, 0);
     }
     uint32_t word = 0;
@@ -1815,12 +1817,15 @@ __device__ __forceinline__ uint64_t lrec_pack(const int rs[3], const int rl[3]) 
 // Encoder side: the SLR residual planes and the exponent plane of the output
 // (final wherever the region stays SLR), the learned residuals M - M_L as
 // 9-bit fields (r_c + 255 at bit 9c, for the last stage), and both
-// estimators' residuals as one record per pixel in the bucket of its exponent.  Bucket e starts at the number of pixels with a
-// smaller exponent (k_solve sets the cursors there); per 16-row tile the
-// workgroup ranks its pixels of each exponent with LDS atomics, reserves
-// that many records with one global atomic per exponent, and writes them.
-// Record order within a bucket is free: only histograms are taken from it.  Each wave walks 4 consecutive rows of a tile with a rolling 3x3
-// window of S, which serves both the features and the Gaussian filter.
+// estimators' residuals as one record per pixel in the bucket of its
+// exponent.  Bucket e starts at the number of pixels with a smaller exponent
+// (k_solve sets the cursors there); per 16-row tile the workgroup ranks its
+// pixels of each exponent with LDS atomics, reserves that many records with
+// one global atomic per exponent before it computes the tile's estimates,
+// and writes the records after them.  Record order within a bucket is free:
+// only histograms are taken from it.  Each wave walks 4
+// consecutive rows of a tile with a rolling 3x3 window of S, which serves
+// both the features and the Gaussian filter.
 template <int RQ>
 __global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, int n) {
     __shared__ uint32_t t[LT_H + 2][LT_W + 2];
@@ -1841,6 +1846,9 @@ __global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, in
     mlp_bias_load<RQ>(B1, d.model);
     s_cnt[threadIdx.x] = 0;
     const int lane = threadIdx.x & 63, wave = uniform(threadIdx.x >> 6);
+    const int x = tx0 + lane;
+    const bool xin = x < W;
+    const uint32_t *rgbe32 = reinterpret_cast<const uint32_t *>(d.rgbe);
     MlpLane L;
     mlp_lane_load<RQ>(L, d.model, lane);
     const int k_img = h->k_img;
@@ -1848,9 +1856,6 @@ __global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, in
     // worked on (every condition below is uniform for the workgroup).
     uint32_t sv[LT_ROWS_PER_WAVE + 1], wv[LT_H / 4];
     const LtCols cols = lt_cols(W, tx0, lane);
-    const int x = tx0 + lane;
-    const bool xin = x < W;
-    const uint32_t *rgbe32 = reinterpret_cast<const uint32_t *>(d.rgbe);
     const auto fetch_rgbe = [&](int ty, uint32_t out[LT_H / 4]) {
 #pragma unroll
         for (int rr = 0; rr < LT_H / 4; ++rr) {
@@ -1871,15 +1876,31 @@ __global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, in
         if (ty0 >= H) break;
         __syncthreads();
         store_lt_rows(t, sv, wave, lane);
-        __syncthreads();
+        const int ly0 = wave * (LT_H / 4);
         uint32_t wc[LT_H / 4];
+        // Rank the tile's pixels among its pixels of the same exponent (one
+        // LDS atomic per pixel; a row holds about a dozen exponents).
 #pragma unroll
-        for (int rr = 0; rr < LT_H / 4; ++rr) wc[rr] = wv[rr];
+        for (int rr = 0; rr < LT_H / 4; ++rr) {
+            wc[rr] = wv[rr];
+            const uint32_t e = wc[rr] >> 24;
+            const bool in = xin && ty0 + ly0 + rr < H;
+            s_where[ly0 + rr][lane] = in ? (e | (atomicAdd(&s_cnt[e], 1u) << 8)) : ~0u;
+        }
+        __syncthreads();
+        // One lane per exponent reserves the tile's records of it.  The
+        // atomics on the shared cursors are slow; their results are first
+        // needed after the tile's estimates.
+        uint32_t my_base = 0;
+        {
+            const uint32_t c = s_cnt[threadIdx.x];
+            if (c) my_base = atomicAdd(&d.lbk[threadIdx.x], c);
+            s_cnt[threadIdx.x] = 0;
+        }
         if (tt + 1 < LT_TILES && ty0 + LT_H < H) {
             fetch_lt_rows(sv, d.sdr, H, W, ty0 + LT_H, wave, lane, cols);
             fetch_rgbe(ty0 + LT_H, wv);
         }
-        const int ly0 = wave * (LT_H / 4);
         Win3 v;
         win_row(v, 0, t[ly0], lane);      // tile row ly0 = image row ty0 + ly0 - 1
         win_row(v, 1, t[ly0 + 1], lane);
@@ -1915,20 +1936,8 @@ __global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, in
                 for (int c = 0; c < 3; ++c) (res16 + c * npx + ro)[x] = (int16_t)rs[c];
                 (eplane + ro)[x] = (uint8_t)e;
             }
-            // Rank among the tile's pixels of the same exponent (a row holds
-            // about a dozen exponents, so one atomic per lane beats a loop
-            // over them).
-            s_where[ly][lane] = in ? ((uint32_t)e | (atomicAdd(&s_cnt[e], 1u) << 8)) : ~0u;
         }
-        __syncthreads();
-        {
-            // One lane per exponent reserves the tile's records of it.
-            const uint32_t c = s_cnt[threadIdx.x];
-            if (c) {
-                s_base[threadIdx.x] = atomicAdd(&d.lbk[threadIdx.x], c);
-                s_cnt[threadIdx.x] = 0;
-            }
-        }
+        s_base[threadIdx.x] = my_base;
         __syncthreads();
 #pragma unroll
         for (int rr = 0; rr < LT_H / 4; ++rr) {
@@ -2364,8 +2373,8 @@ void launch_decode(const ImgDesc *d, int n, int wgs, hipStream_t s) {
     hipLaunchKernelGGL(k_decode, dim3(wgs), dim3(STRIP_THREADS), 0, s, d, n);
 }
 void launch_learn(const ImgDesc *d, int n, int wgs, int rq, hipStream_t s) {
-    if (rq == RQ_PACKED)
-        hipLaunchKernelGGL(k_learn<RQ_PACKED>, dim3(wgs), dim3(256), 0, s, d, n);
+    if (rq == RQ_PAIR)
+        hipLaunchKernelGGL(k_learn<RQ_PAIR>, dim3(wgs), dim3(256), 0, s, d, n);
     else if (rq == RQ_POW2)
         hipLaunchKernelGGL(k_learn<RQ_POW2>, dim3(wgs), dim3(256), 0, s, d, n);
     else
@@ -2378,8 +2387,8 @@ void launch_select(const ImgDesc *d, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_select, dim3(256 * n), dim3(256), 0, s, d, n);
 }
 void launch_decode_learned(const ImgDesc *d, int n, int wgs, int rq, hipStream_t s) {
-    if (rq == RQ_PACKED)
-        hipLaunchKernelGGL(k_decode_learned<RQ_PACKED>, dim3(wgs), dim3(256), 0, s, d, n);
+    if (rq == RQ_PAIR)
+        hipLaunchKernelGGL(k_decode_learned<RQ_PAIR>, dim3(wgs), dim3(256), 0, s, d, n);
     else if (rq == RQ_POW2)
         hipLaunchKernelGGL(k_decode_learned<RQ_POW2>, dim3(wgs), dim3(256), 0, s, d, n);
     else

@@ -231,37 +231,44 @@ def batch_256_large(n: int = 256) -> list:
             for i, (H, W) in enumerate(sizes)]
 
 
-def random_model(seed: int, scale: int = 8, pow2: bool = False, wide_shift: bool = False) -> bytes:
+def random_model(seed: int, scale: int = 8, rq: str = "general") -> bytes:
     """A seeded random int8 estimator model (test input), within the value
     limits of the model format, with activations that neither vanish nor
-    saturate on synthetic images.  pow2: every hidden requantisation
-    multiplier is 1 (scales are powers of two), with hidden shifts of at
-    most 8 and a few neurons whose biases push their pre-activations beyond
-    16 bits both ways; wide_shift: pow2 with some hidden shifts above 8."""
+    saturate on synthetic images.  rq chooses the library's requantisation
+    path the model takes: "general" (multipliers above 1), "pow2" (every
+    hidden multiplier 1, shifts differing within neuron pairs) or "pair"
+    (multipliers 1, equal shifts in each pair (2k, 2k + 1), one pair per
+    layer at the largest shift of that path, 22).  pow2 and pair models also
+    have neurons whose biases push them past both ends of [0, 255]."""
     from . import model_format
+    assert rq in ("general", "pow2", "pair")
     rng = np.random.Generator(np.random.PCG64(seed))
     p = {
         "W1": np.zeros((32, 32), np.int8), "B1": rng.integers(-3000, 3000, (32, 32)),
-        "m1": rng.integers(512, 2047, 32), "r1": rng.integers(15, 18, 32),
+        "m1": rng.integers(256, 1024, 32), "r1": rng.integers(14, 17, 32),
         "W2": rng.integers(-scale, scale + 1, (32, 32)), "B2": rng.integers(-2000, 4000, 32),
-        "m2": rng.integers(512, 2047, 32), "r2": rng.integers(13, 16, 32),
+        "m2": rng.integers(256, 1024, 32), "r2": rng.integers(12, 15, 32),
         "W3": np.zeros((16, 32), np.int8), "B3": np.zeros(16, np.int64),
-        "m3": np.full(16, 1024), "r3": np.full(16, 6),
+        "m3": np.full(16, 512), "r3": np.full(16, 6),
     }
     p["W1"][:, :27] = rng.integers(-scale, scale + 1, (32, 27))
     p["W3"][:3] = rng.integers(-scale, scale + 1, (3, 32))
     p["B3"][:3] = rng.integers(0, 2000, 3)
-    if pow2:
+    if rq != "general":
         p["m1"] = np.ones(32, np.int64)
-        p["r1"] = rng.integers(5, 9, 32)
+        p["r1"] = rng.integers(5, 10, 32)
         p["m2"] = np.ones(32, np.int64)
-        p["r2"] = rng.integers(4, 9, 32)
-        # neurons 0-3 of layer 1 and 0-1 of layer 2: biases beyond +-2^15
-        p["B1"][:, 0:2] = rng.integers(33000, 60000, (32, 2))
-        p["B1"][:, 2:4] = -rng.integers(33000, 60000, (32, 2))
-        p["B2"][0] = 40000
-        p["B2"][1] = -40000
-        if wide_shift:
-            p["r1"][::3] = rng.integers(9, 13, len(p["r1"][::3]))
-            p["r2"][::4] = rng.integers(9, 12, len(p["r2"][::4]))
+        p["r2"] = rng.integers(4, 10, 32)
+        if rq == "pair":
+            p["r1"][1::2] = p["r1"][0::2]
+            p["r2"][1::2] = p["r2"][0::2]
+            p["r1"][30:32] = 22
+            p["r2"][30:32] = 22
+        else:
+            p["r1"][1::2] = np.where(p["r1"][1::2] == p["r1"][0::2], p["r1"][0::2] + 1, p["r1"][1::2])
+        # neurons 0-1 of each hidden layer saturate at 255, 2-3 at 0
+        p["B1"][:, 0:2] = rng.integers(150000, 260000, (32, 2))
+        p["B1"][:, 2:4] = -rng.integers(150000, 260000, (32, 2))
+        p["B2"][0:2] = rng.integers(150000, 260000, 2)
+        p["B2"][2:4] = -rng.integers(150000, 260000, 2)
     return model_format.pack(p)

@@ -43,82 +43,88 @@ def unflatten(p: np.ndarray) -> dict:
 
 
 def _mult_shift(ratio: np.ndarray, rmax: int = 28):
-    """m / 2^r ~= ratio with m in [1, 2^11), r in [1, rmax]."""
+    """m / 2^r ~= ratio with m in [1, M_LIMIT), r in [1, rmax]."""
+    mlim = model_format.M_LIMIT
     m = np.zeros(ratio.shape, np.int64)
     r = np.zeros(ratio.shape, np.int64)
     for i, rho in enumerate(ratio.reshape(-1)):
         rho = max(float(rho), 1e-12)
-        rr = int(np.clip(math.floor(math.log2(2047.0 / rho)), 1, rmax))
+        rr = int(np.clip(math.floor(math.log2((mlim - 1) / rho)), 1, rmax))
         mm = int(round(rho * 2 ** rr))
-        while mm >= 2048 and rr > 1:
+        while mm >= mlim and rr > 1:
             rr -= 1
             mm = int(round(rho * 2 ** rr))
-        m.reshape(-1)[i] = min(max(mm, 1), 2047)
+        m.reshape(-1)[i] = min(max(mm, 1), mlim - 1)
         r.reshape(-1)[i] = rr
     return m, r
 
 
-def _pow2_shift(ratio: np.ndarray, rmax: int = 28):
+def _pow2_shift(ratio: np.ndarray, rmax: int, pair: str):
     """Shift r in [1, rmax] with 2^r >= ratio, the smallest such: a hidden
     activation step of sw 2^r is at least the calibrated step, so no more
-    values clip at 127 than the calibration allows."""
-    r = np.ceil(np.log2(np.maximum(ratio, 1e-30)))
-    return np.clip(r, 1, rmax).astype(np.int64)
+    values clip at 255 than the calibration allows.  pair "max" / "min": the
+    neurons (2k, 2k + 1) share the larger / smaller of their two shifts (the
+    library's fastest path); "" leaves every neuron its own."""
+    r = np.clip(np.ceil(np.log2(np.maximum(ratio, 1e-30))), 1, rmax).astype(np.int64)
+    if pair:
+        f = np.maximum if pair == "max" else np.minimum
+        r[0::2] = r[1::2] = f(r[0::2], r[1::2])
+    return r
 
 
-def quantise(p: np.ndarray, feats: np.ndarray, bins: np.ndarray, pow2: bool = True, rmax: int = 28) -> bytes:
+def _hidden_layer(We, B, s, pow2: bool, rmax: int, pair: str):
+    """Quantise one hidden layer whose float weights We (already scaled by
+    the input step) and biases B produce pre-activations with calibrated
+    activation step s: int8 weights, biases, multipliers, shifts and the
+    actual activation step."""
+    lim = 1 << 18
+    sw = np.maximum(np.abs(We).max(axis=1), 1e-12) / 127.0
+    if pow2:
+        # a row whose calibrated step needs a shift beyond rmax (or beyond the
+        # shift it shares with its pair neuron) takes a coarser weight step,
+        # keeping its activation step
+        sw = np.maximum(sw, s / 2.0 ** rmax)
+        r = _pow2_shift(s / sw, rmax, pair)
+        sw = np.maximum(sw, s / 2.0 ** r)
+        m = np.ones(len(s), np.int64)
+        t = sw * 2.0 ** r  # the actual activation step
+    else:
+        m, r = _mult_shift(sw / s)
+        t = s
+    Wq = np.clip(np.round(We / sw[:, None]), -127, 127)
+    Bq = np.clip(np.round(B / sw), -lim, lim)
+    return Wq, Bq, m, r, t
+
+
+def quantise(p: np.ndarray, feats: np.ndarray, bins: np.ndarray, pow2: bool = True, rmax: int = 22,
+             pair: str = "min") -> bytes:
     """int8 model blob from float parameters; activation scales from the
     float forward pass over the calibration samples (feats int8 [N, 27]).
+    Hidden activations are unsigned bytes (0 .. A_MAX = 255).
 
     pow2: the hidden layers' requantisation multipliers are 1 (a shift by r
     alone, the fast path of the library's estimator); each hidden activation
     step then becomes sw 2^r, and the next layer's float weights are scaled
     by that actual step before they are quantised, so the powers of two cost
-    at most one bit of activation resolution and nothing else."""
+    activation resolution and nothing else.  pair: see _pow2_shift."""
+    amax = model_format.A_MAX
     P = unflatten(p.astype(np.float64))
     x = feats.astype(np.float64) / 128.0
     h1 = x @ P["W1"].T + P["B1"][bins]
-    a1 = np.maximum(h1, 0)
-    s1 = np.maximum(np.percentile(a1, 99.99, axis=0), 1e-9) / 127.0
-    lim = 1 << 18
-    W1e = P["W1"] / 128.0
-    sw1 = np.maximum(np.abs(W1e).max(axis=1), 1e-12) / 127.0
-    if pow2:
-        # with shifts capped at rmax a row whose calibrated step needs more
-        # takes a coarser weight step instead, keeping its activation step
-        sw1 = np.maximum(sw1, s1 / 2.0 ** rmax)
+    s1 = np.maximum(np.percentile(np.maximum(h1, 0), 99.99, axis=0), 1e-9) / amax
+    W1p, B1q, m1, r1, t1 = _hidden_layer(P["W1"] / 128.0, P["B1"], s1, pow2, rmax, pair)
     W1q = np.zeros((32, 32), np.int64)
-    W1q[:, :27] = np.clip(np.round(W1e / sw1[:, None]), -127, 127)
-    B1q = np.clip(np.round(P["B1"] / sw1[None, :]), -lim, lim)
-    if pow2:
-        r1 = _pow2_shift(s1 / sw1, rmax)
-        m1 = np.ones(32, np.int64)
-        t1 = sw1 * 2.0 ** r1  # the actual activation step
-    else:
-        m1, r1 = _mult_shift(sw1 / s1)
-        t1 = s1
-    a1q = np.clip(np.round(np.maximum(h1, 0) / t1), 0, 127) * t1  # activations as the model will see them
+    W1q[:, :27] = W1p
+    a1q = np.clip(np.round(np.maximum(h1, 0) / t1), 0, amax) * t1  # activations as the model will see them
     a2 = np.maximum(a1q @ P["W2"].T + P["B2"], 0)
-    s2 = np.maximum(np.percentile(a2, 99.99, axis=0), 1e-9) / 127.0
-    W2e = P["W2"] * t1[None, :]
-    sw2 = np.maximum(np.abs(W2e).max(axis=1), 1e-12) / 127.0
-    if pow2:
-        sw2 = np.maximum(sw2, s2 / 2.0 ** rmax)
-    W2q = np.clip(np.round(W2e / sw2[:, None]), -127, 127)
-    B2q = np.clip(np.round(P["B2"] / sw2), -lim, lim)
-    if pow2:
-        r2 = _pow2_shift(s2 / sw2, rmax)
-        m2 = np.ones(32, np.int64)
-        t2 = sw2 * 2.0 ** r2
-    else:
-        m2, r2 = _mult_shift(sw2 / s2)
-        t2 = s2
+    s2 = np.maximum(np.percentile(a2, 99.99, axis=0), 1e-9) / amax
+    W2q, B2q, m2, r2, t2 = _hidden_layer(P["W2"] * t1[None, :], P["B2"], s2, pow2, rmax, pair)
     W3e = P["W3"] * t2[None, :]
     sw3 = np.maximum(np.abs(W3e).max(axis=1), 1e-12) / 127.0
     W3q = np.zeros((16, 32), np.int64)
     W3q[:3] = np.clip(np.round(W3e / sw3[:, None]), -127, 127)
     B3q = np.zeros(16, np.int64)
-    B3q[:3] = np.clip(np.round(P["B3"] / sw3), -lim, lim)
+    B3q[:3] = np.clip(np.round(P["B3"] / sw3), -(1 << 18), 1 << 18)
     m3 = np.ones(16, np.int64)
     r3 = np.ones(16, np.int64)
     m3[:3], r3[:3] = _mult_shift(sw3 * 65536.0, rmax=22)
@@ -203,22 +209,32 @@ def main():
     ap.add_argument("--train-set", choices=("config2", "wide"), default="config2",
                     help="config2: the two 3840x2160 images of the single-image workload's generator; wide: those "
                          "plus eight images over the batch workloads' parameter ranges")
-    ap.add_argument("--rmax", type=int, default=8,
-                    help="largest hidden shift of a power-of-two model (8: the library's packed 16-bit path)")
+    ap.add_argument("--rmax", type=int, default=22,
+                    help="largest hidden shift of a power-of-two model (22: the library's power-of-two paths)")
+    ap.add_argument("--pair", choices=("max", "min", "none"), default="min",
+                    help="shift shared by each hidden neuron pair (2k, 2k + 1): the larger or smaller of the two "
+                         "(the library's fastest path), or none")
     ap.add_argument("--general", action="store_true",
                     help="general requantisation multipliers instead of powers of two")
+    ap.add_argument("--params-in", default="",
+                    help="quantise these float parameters (.npy) instead of training; the samples are drawn for "
+                         "calibration only")
     args = ap.parse_args()
     t0 = time.time()
     codec = rdl.Codec(0)
     specs = synth.learned_train_set() + (synth.learned_train_set_wide() if args.train_set == "wide" else [])
-    samples = make_samples(codec, specs, args.samples, seed=4000)
+    n_samples = 200_000 if args.params_in else args.samples
+    samples = make_samples(codec, specs, n_samples, seed=4000)
     print("samples: %d records in %.1f s" % (samples.shape[0], time.time() - t0), flush=True)
-    params = train(codec, samples, args.epochs, args.batch, args.lr, log=lambda s: print(s, flush=True))
+    if args.params_in:
+        params = np.load(args.params_in)
+    else:
+        params = train(codec, samples, args.epochs, args.batch, args.lr, log=lambda s: print(s, flush=True))
     if args.params_out:
         np.save(args.params_out, params)
     calib = samples[:200_000].cpu().numpy()
     blob = quantise(params, calib[:, :27].view(np.int8), calib[:, 27].astype(np.int64), pow2=not args.general,
-                    rmax=args.rmax)
+                    rmax=args.rmax, pair="" if args.pair == "none" else args.pair)
     with open(args.out, "wb") as fh:
         fh.write(blob)
     print("model written: %s (%d bytes, hash %016x) after %.1f s" % (args.out, len(blob), model_format.blob_hash(blob),

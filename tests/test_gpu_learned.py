@@ -39,12 +39,12 @@ CASES = [("1x1", (1, 1), 2.0, 75, 11), ("7x9", (7, 9), 3.0, 50, 12), ("64x64", (
 @pytest.mark.parametrize("name,shape,sig,q,ms", CASES, ids=[c[0] for c in CASES])
 def test_learned_encode_decode_match_oracle(codec, rdl_mod, O, name, shape, sig, q, ms):
     H, W = shape
-    # half of the models take a power-of-two requantisation path: shifts up to
-    # 8 (packed 16-bit) or some above (32-bit)
-    pow2, wide = ms % 2 == 1, ms % 4 == 3
-    _say("learned", name, q, "model", ms, "pow2" if pow2 else "", "wide shifts" if wide else "")
+    # the models take every requantisation path: general multipliers, powers
+    # of two with per-neuron shifts, and powers of two with paired shifts
+    rq = ("general", "pow2", "pair")[ms % 3]
+    _say("learned", name, q, "model", ms, rq)
     x = synth.generate(H, W, sig, seed=700 + ms, spec_frac=0.05)
-    blob = synth.random_model(ms, pow2=pow2, wide_shift=wide)
+    blob = synth.random_model(ms, rq=rq)
     codec.set_model(blob)
     codec.set_estimator(1)
     try:
@@ -89,10 +89,10 @@ def test_learned_random_words(codec, rdl_mod, O):
         codec.set_estimator(0)
 
 
-@pytest.mark.parametrize("kind", ["general", "pow2", "pow2_wide"])
+@pytest.mark.parametrize("kind", ["general", "pow2", "pair"])
 def test_learned_batch_matches_oracle(codec, O, kind):
     specs = [(40, 90, 2.0, 55), (70, 33, 4.0, 90), (129, 66, 1.5, 30)]
-    blob = synth.random_model(51, pow2=kind != "general", wide_shift=kind == "pow2_wide")
+    blob = synth.random_model(51, rq=kind)
     _say("learned batch", kind)
     codec.set_model(blob)
     codec.set_estimator(1)
@@ -120,9 +120,15 @@ def test_model_validation_and_decoder_checks(codec, rdl_mod):
     with pytest.raises(rdl_mod.RdlError):
         codec.set_model(bytes(bad))
     p = model_format.unpack(bytes(blob))
-    p["m1"][3] = 1 << 11  # beyond the multiplier limit
+    p["m1"][3] = 1 << 10  # beyond the multiplier limit
     with pytest.raises(rdl_mod.RdlError):
         codec.set_model(model_format.pack(p))
+    p["m1"][3] = (1 << 10) - 1  # at it
+    codec.set_model(model_format.pack(p))
+    old = bytearray(blob)
+    old[4] = 1  # the first format version (activations clamped at 127) is refused
+    with pytest.raises(rdl_mod.RdlError):
+        codec.set_model(bytes(old))
     codec.set_model(None)
     with pytest.raises(rdl_mod.RdlError):
         codec.set_estimator(1)

@@ -44,7 +44,7 @@ def test_random_sweep_matches_oracle(codec, rdl_mod, O, learned):
         for t in out:
             t.fill_(0xAA)
         if learned:
-            blob = synth.random_model(seed, pow2=seed % 2 == 1, wide_shift=seed % 4 == 3)
+            blob = synth.random_model(seed, rq=("general", "pow2", "pair")[seed % 3])
             codec.set_model(blob)
             codec.set_estimator(1)
         try:

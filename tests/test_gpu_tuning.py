@@ -139,7 +139,7 @@ def test_stage_timing_of_direct_encodes(codec, rdl_mod, O):
         codec.encode_enh(d, q, out=out)
         codec.set_launch_mode(False)
         assert codec.stage_times()[1] == 0  # graph replays record nothing
-        codec.set_model(synth.random_model(1511, pow2=True))
+        codec.set_model(synth.random_model(1511, rq="pair"))
         codec.set_estimator(1)
         for _ in range(2):
             codec.encode_enh(d, q, out=out)

@@ -159,11 +159,11 @@ def test_learned_output_rounding_fold():
     and multiplier, floor((floor((o m3 + 2^(r3-1)) / 2^r3) + 128) / 2^8) equals
     floor((o m3 + 2^(r3-1) + 2^(r3+7)) / 2^(r3+8)), and the folded numerator
     stays inside int32 for every o the model format allows
-    (|o| <= 32 * 127 * 127 + 2^18)."""
+    (|o| <= 32 * 127 * 255 + 2^18, multipliers below 2^10)."""
     rng = np.random.default_rng(5)
-    omax = 32 * 127 * 127 + (1 << 18)
+    omax = 32 * 127 * 255 + (1 << 18)
     for r3 in range(1, 23):
-        for m3 in (1, 2, 777, 2047):
+        for m3 in (1, 2, 777, 1023):
             o = np.concatenate([rng.integers(-omax, omax + 1, 20000), [-omax, omax, 0, -1, 1]]).astype(np.int64)
             num = o * m3 + (1 << (r3 - 1))
             two_step = ((num >> r3) + 128) >> 8
@@ -171,29 +171,53 @@ def test_learned_output_rounding_fold():
             assert np.array_equal(two_step, folded_num >> (r3 + 8)), (r3, m3)
             assert folded_num.max() < 2 ** 31 and folded_num.min() >= -2 ** 31, (r3, m3)
     # r3 = 23 would overflow at the bound: the library rejects it
-    assert omax * 2047 + (1 << 22) + (1 << 30) >= 2 ** 31
+    assert omax * 1023 + (1 << 22) + (1 << 30) >= 2 ** 31
+
+
+def test_learned_general_requant_in_int32():
+    """General multipliers: h m + 2^(r-1) stays inside int32 for every
+    pre-activation the model format allows (|h| <= 32 * 127 * 255 + 2^18 in
+    layer 2, less in layer 1), multiplier below 2^10 and shift up to 28; at
+    multipliers up to 2^11 (the first format version's limit) it would not."""
+    hmax = 32 * 127 * 255 + (1 << 18)
+    assert hmax * 1023 + (1 << 27) < 2 ** 31
+    assert hmax * 2047 >= 2 ** 31
+
+
+def test_learned_offset_inputs():
+    """Activations a in [0, 255] enter the next layer's signed-byte MFMA as
+    a - 128 = a XOR 0x80, and the bias carried as b + 128 sum_k W[k] makes the
+    product exact: sum_k W[k] (a_k - 128) + b + 128 sum_k W[k] = sum_k W[k] a_k
+    + b, for random rows and activations including 0 and 255."""
+    rng = np.random.default_rng(8)
+    W = rng.integers(-127, 128, (200, 32)).astype(np.int64)
+    a = rng.integers(0, 256, (200, 32)).astype(np.int64)
+    a[0], a[1] = 0, 255
+    b = rng.integers(-(1 << 18), (1 << 18) + 1, 200)
+    signed = ((a ^ 0x80).astype(np.uint8)).view(np.int8).astype(np.int64)
+    assert np.array_equal(signed, a - 128)
+    lhs = (W * signed).sum(axis=1) + b + 128 * W.sum(axis=1)
+    assert np.array_equal(lhs, (W * a).sum(axis=1) + b)
 
 
 def test_learned_pow2_bias_fold():
-    """With a hidden multiplier of 1 the rounding constant moves into the bias:
-    (h m + 2^(r-1)) >> r = (h' ) >> r with h' = h + 2^(r-1), and h' stays inside
-    int32 for every accepted bias and shift."""
+    """With a hidden multiplier of 1 the rounding constant and the input offset
+    of the next layer move into the bias: for every shift the power-of-two
+    paths accept (r <= 22), clamp((h + 2^(r-1)) >> r, 0, 255) - 128 equals
+    clamp((h + 2^(r-1) - 2^(r+7)) >> r, -128, 127), and the folded value stays
+    inside int32 for every accepted bias; the pair path's one instruction
+    (shift two values, saturate to int8, pack) gives the same bytes."""
     rng = np.random.default_rng(6)
-    hmax = 27 * 128 * 127 + (1 << 18)
-    for r in range(1, 29):
-        h = rng.integers(-hmax, hmax + 1, 5000).astype(np.int64)
-        assert np.array_equal((h * 1 + (1 << (r - 1))) >> r, (h + (1 << (r - 1))) >> r)
-        assert hmax + (1 << (r - 1)) < 2 ** 31
-
-
-def test_learned_packed_requantisation():
-    """The 16-bit packed requantisation: for every shift r <= 8, saturating the
-    pre-activation to int16 before the shift leaves clamp(h >> r, 0, 127)
-    unchanged, over the whole range the model format allows (|h| < 2^31 after
-    the rounding constant), and every pair of shifts fits the packed operand;
-    at r = 9 the saturation would change it."""
-    hs = np.concatenate([np.arange(-70000, 70000), np.array([-2 ** 31, 2 ** 31 - 1, -2 ** 20, 2 ** 20])]).astype(np.int64)
-    sat = np.clip(hs, -32768, 32767)
-    for r in range(1, 9):
-        assert np.array_equal(np.clip(hs >> r, 0, 127), np.clip(sat >> r, 0, 127)), r
-    assert not np.array_equal(np.clip(hs >> 9, 0, 127), np.clip(sat >> 9, 0, 127))
+    hmax = 32 * 127 * 128 + 128 * 32 * 127 + (1 << 18)
+    for r in range(1, 23):
+        h = np.concatenate([rng.integers(-hmax, hmax + 1, 5000),
+                            (np.arange(-300, 300) << r) + rng.integers(-2, 3, 600)]).astype(np.int64)
+        a = np.clip((h + (1 << (r - 1))) >> r, 0, 255)
+        folded = h + (1 << (r - 1)) - (1 << (r + 7))
+        assert np.array_equal(a - 128, np.clip(folded >> r, -128, 127)), r
+        assert np.abs(folded).max() < 2 ** 31 and hmax + (1 << (r + 7)) < 2 ** 31, r
+        # the packed pair: low byte from the first value, high from the second
+        x, y = folded[0::2][:2500], folded[1::2][:2500]
+        pk = (np.clip(x >> r, -128, 127) & 255) | ((np.clip(y >> r, -128, 127) & 255) << 8)
+        assert np.array_equal(pk & 255, (a[0::2][:2500] - 128) & 255)
+        assert np.array_equal(pk >> 8, (a[1::2][:2500] - 128) & 255)

@@ -173,8 +173,10 @@ def test_learned_buckets_cover_each_record_once(case):
 
 
 def test_learned_reservation_stays_in_bucket():
-    """Tiles reserve their records of each exponent in any order; with
-    reservations summing to n_e every index lands inside bucket e."""
+    """k_learn's tiles (16 x 64 px) rank their pixels of each exponent, then
+    reserve that many records of it with one atomic on its cursor, the tiles
+    in any order; with reservations summing to n_e every index lands inside
+    bucket e, exactly once."""
     rng = np.random.default_rng(5)
     H, W = 200, 333
     E = rng.integers(120, 140, (H, W))

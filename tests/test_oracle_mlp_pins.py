@@ -6,12 +6,12 @@ The learned estimator is an extension beyond the paper (its regression needs
 no learning, Sec. I).  Its integer arithmetic, as the model format defines it:
 per pixel, 27 features S - 128 of the 3x3 neighbourhood (border replicated),
 a bin b = clamp(E - 136 + k_img + 24, 0, 31) choosing the first layer's bias
-row, two hidden layers a = clamp((h m + 2^(r-1)) >> r, 0, 127), and an output
+row, two hidden layers a = clamp((h m + 2^(r-1)) >> r, 0, 255), and an output
 q8 = (o m3 + 2^(r3-1)) >> r3, M_L = clamp((q8 + 128) >> 8, 0, 255).
 
 The reference below writes that arithmetic out again in numpy int64 matrix
 products, without calling the oracle's estimator, and compares every output
-byte.  The models are random (multipliers over [1, 2047], shifts over
+byte.  The models are random (multipliers over [1, 1023], shifts over
 [1, 28], biases within 2^18) plus probe neurons built so that h m lands
 exactly on 2^(r-1) mod 2^r at the largest shifts.  Each test also shows that
 its inputs discriminate: the reference with a rounding term dropped, or with
@@ -35,7 +35,7 @@ def _rnd(v, r, half):
     return np.right_shift(v + add, r)
 
 
-def mlp_ref(S, E, k_img, P, half=True, out_half=True, bin_off=24):
+def mlp_ref(S, E, k_img, P, half=True, out_half=True, bin_off=24, a_max=255):
     """Learned estimates M_L [H][W][3] in plain int64 numpy."""
     H, W, _ = S.shape
     feat = np.zeros((H * W, 32), np.int64)
@@ -49,9 +49,9 @@ def mlp_ref(S, E, k_img, P, half=True, out_half=True, bin_off=24):
     b = np.clip(E.astype(np.int64).reshape(-1) - 136 + k_img + bin_off, 0, 31)
     W1, B1 = P["W1"].astype(np.int64), P["B1"].astype(np.int64)
     h1 = feat @ W1.T + B1[b]
-    a1 = np.clip(_rnd(h1 * P["m1"].astype(np.int64), P["r1"], half), 0, 127)
+    a1 = np.clip(_rnd(h1 * P["m1"].astype(np.int64), P["r1"], half), 0, a_max)
     h2 = a1 @ P["W2"].astype(np.int64).T + P["B2"].astype(np.int64)
-    a2 = np.clip(_rnd(h2 * P["m2"].astype(np.int64), P["r2"], half), 0, 127)
+    a2 = np.clip(_rnd(h2 * P["m2"].astype(np.int64), P["r2"], half), 0, a_max)
     o = a2 @ P["W3"][:3].astype(np.int64).T + P["B3"][:3].astype(np.int64)
     q8 = _rnd(o * P["m3"][:3].astype(np.int64), P["r3"][:3], half)
     m = np.right_shift(q8 + (128 if out_half else 0), 8)
@@ -61,15 +61,15 @@ def mlp_ref(S, E, k_img, P, half=True, out_half=True, bin_off=24):
 
 
 def random_model(seed):
-    """A random model inside the library's limits (m in [1, 2^11), r in
+    """A random model inside the library's limits (m in [1, 2^10), r in
     [1, 28], |B| <= 2^18), its multipliers scaled so that most neurons
     neither die nor saturate, plus two probe neurons.
 
     Probe neuron 0 of layer 1 reads only the centre pixel's G (weight 1) with
-    bias 2^17 - 3, multiplier 1024 and shift 28: h m = 2^27 + 1024 (S_G - 131),
+    bias 2^18 - 3, multiplier 512 and shift 28: h m = 2^27 + 512 (S_G - 131),
     exactly half of 2^28 where S_G = 131, so a1[0] = [S_G >= 131] with the
     rounding term and 0 everywhere without it.  Probe neuron 0 of layer 2
-    reads a1[0] (weight 127) with bias 2^17 - 127, multiplier 1024 and shift
+    reads a1[0] (weight 127) with bias 2^18 - 127, multiplier 512 and shift
     28: h m = 2^27 exactly when a1[0] = 1, so a2[0] = a1[0] with the rounding
     term and 0 without it."""
     rng = np.random.default_rng(seed)
@@ -82,17 +82,17 @@ def random_model(seed):
     P["B3"] = rng.integers(-(1 << 18), 1 << 18, 16)
     for layer, scale in (("1", 64 / 30000.0), ("2", 64 / 25000.0)):
         r = rng.permutation(np.concatenate([np.arange(1, 29), rng.integers(1, 29, 4)]))  # every shift
-        m = np.clip(np.round(scale * np.exp2(r) * rng.uniform(0.5, 2.0, 32)), 1, 2047).astype(np.int64)
+        m = np.clip(np.round(scale * np.exp2(r) * rng.uniform(0.5, 2.0, 32)), 1, 1023).astype(np.int64)
         P["m" + layer], P["r" + layer] = m, r
     # probe neurons (layer 1 neuron 0, layer 2 neuron 0)
     P["W1"][0] = 0
     P["W1"][0, 13] = 1               # feature 13 = centre pixel, G
-    P["B1"][:, 0] = (1 << 17) - 3    # h = 2^17 - 3 + (S_G - 128): 2^17 at S_G = 131
-    P["m1"][0], P["r1"][0] = 1024, 28
+    P["B1"][:, 0] = (1 << 18) - 3    # h = 2^18 - 3 + (S_G - 128): 2^18 at S_G = 131
+    P["m1"][0], P["r1"][0] = 512, 28
     P["W2"][0] = 0
     P["W2"][0, 0] = 127
-    P["B2"][0] = (1 << 17) - 127
-    P["m2"][0], P["r2"][0] = 1024, 28
+    P["B2"][0] = (1 << 18) - 127
+    P["m2"][0], P["r2"][0] = 512, 28
     # outputs: from the spread of o over a calibration image, m3 / 2^r3 and
     # B3 such that q8 spans the mantissa range in Q8 (centre 2^15, standard
     # deviation 20000, about 78 codes)
@@ -102,10 +102,10 @@ def random_model(seed):
     o = mlp_ref(S, rng.integers(100, 160, (64, 64)), 0, P)[1]["o"]
     for c in range(3):
         sc = 20000.0 / max(float(o[:, c].std()), 1.0)
-        rmax = int(np.clip(np.floor(np.log2(2047.0 / sc)), 1, 28))
+        rmax = int(np.clip(np.floor(np.log2(1023.0 / sc)), 1, 28))
         r3 = int(rng.integers(max(1, rmax - 3), rmax + 1))
         P["r3"][c] = r3
-        P["m3"][c] = int(np.clip(round(sc * 2.0 ** r3), 1, 2047))
+        P["m3"][c] = int(np.clip(round(sc * 2.0 ** r3), 1, 1023))
         P["B3"][c] = int(np.clip(round(32768.0 * 2.0 ** r3 / P["m3"][c] - np.median(o[:, c])), -(1 << 18), 1 << 18))
     return P
 
@@ -122,14 +122,15 @@ def test_mlp_requant_rounding_vs_int64_brute_force(O, seed):
     every pixel of four sizes (1x1, 7x9, 33x47, 96x80: borders on every side),
     for three random models and three k_img.  The inputs contain exact
     half-way products h m = 2^(r-1) mod 2^r in both hidden layers (at shifts
-    up to 28) and outputs q8 = 128 mod 256, and dropping either rounding term
-    or moving the bin offset changes some estimate."""
+    up to 28) and outputs q8 = 128 mod 256, and dropping either rounding term,
+    moving the bin offset, clamping the hidden activations at 127 (the first
+    format version) or not at all changes some estimate."""
     P = random_model(seed)
     blob = model_format.pack(P)
     rng = np.random.default_rng(seed + 100)
     half_hits = {"h1m": set(), "h2m": set()}
     q8_hits = 0
-    differs = {"half": 0, "out_half": 0, "bin": 0}
+    differs = {"half": 0, "out_half": 0, "bin": 0, "a_max_127": 0, "no_upper_clamp": 0}
     for H, W in [(1, 1), (7, 9), (33, 47), (96, 80)]:
         S, x = _image(rng, H, W)
         for k_img in (-9, 0, 13):
@@ -146,6 +147,8 @@ def test_mlp_requant_rounding_vs_int64_brute_force(O, seed):
             differs["half"] += int((mlp_ref(S, x[..., 3], k_img, P, half=False)[0] != got).any())
             differs["out_half"] += int((mlp_ref(S, x[..., 3], k_img, P, out_half=False)[0] != got).any())
             differs["bin"] += int((mlp_ref(S, x[..., 3], k_img, P, bin_off=23)[0] != got).any())
+            differs["a_max_127"] += int((mlp_ref(S, x[..., 3], k_img, P, a_max=127)[0] != got).any())
+            differs["no_upper_clamp"] += int((mlp_ref(S, x[..., 3], k_img, P, a_max=1 << 40)[0] != got).any())
     # exact half-way products occurred at small and at the largest shifts
     for key in half_hits:
         assert min(half_hits[key]) <= 4 and max(half_hits[key]) == 28, (key, sorted(half_hits[key]))

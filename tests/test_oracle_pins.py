@@ -669,7 +669,7 @@ def test_learned_selection_never_raises_h0(O, seed):
     H, W = int(rng.integers(30, 90)), int(rng.integers(30, 90))
     x = sy.generate(H, W, float(rng.uniform(1.0, 5.0)), seed=600 + seed, spec_frac=float(rng.choice([0.0, 0.05])))
     q = int(rng.integers(30, 99))
-    blob = sy.random_model(700 + seed, pow2=bool(seed % 2))
+    blob = sy.random_model(700 + seed, rq=("general", "pow2", "pair")[seed % 3])
     r = O.encode_learned(x, q, blob)
     plain = O.encode_enh(x, q)
     rs, E = O.split_resid(plain["resid"], H, W)
