@@ -1765,17 +1765,28 @@ __device__ __forceinline__ const uint8_t *lt_row(const uint8_t *__restrict__ sdr
     const int yy = uniform(min(max(ty0 + ry - 1, 0), H - 1));
     return sdr + (int64_t)yy * (3 * (int64_t)W);
 }
+// S word of the pixel at p: two dwords from the dword boundary at or below
+// p, byte-aligned (S starts on a dword boundary, which the entry points
+// check), or three bytes where those 8 bytes would pass the end of S.
+__device__ __forceinline__ uint32_t load_px3w(const uint8_t *p, const uint8_t *end) {
+    const uint32_t sh = (uint32_t)reinterpret_cast<uintptr_t>(p) & 3u;
+    const uint32_t *q = reinterpret_cast<const uint32_t *>(p - sh);
+    if (reinterpret_cast<const uint8_t *>(q) + 8 <= end)
+        return __builtin_amdgcn_alignbyte(q[1], q[0], sh) & 0xFFFFFFu;
+    return load_px3(p);
+}
 __device__ __forceinline__ void fetch_lt_rows(uint32_t v[LT_ROWS_PER_WAVE + 1], const uint8_t *__restrict__ sdr, int H,
                                               int W, int ty0, int wave, int lane, const LtCols &c) {
+    const uint8_t *end = sdr + (int64_t)H * (3 * (int64_t)W);
 #pragma unroll
     for (int k = 0; k < LT_ROWS_PER_WAVE; ++k) {
         const int ry = wave + 4 * k;
-        v[k] = ry < LT_H + 2 ? load_px3(lt_row(sdr, H, W, ty0, ry) + c.off) : 0u;
+        v[k] = ry < LT_H + 2 ? load_px3w(lt_row(sdr, H, W, ty0, ry) + c.off, end) : 0u;
     }
     v[LT_ROWS_PER_WAVE] = 0u;
     if (wave == 0 && lane < 2 * (LT_H + 2)) {
         const int yy = min(max(ty0 + (lane >> 1) - 1, 0), H - 1);
-        v[LT_ROWS_PER_WAVE] = load_px3(sdr + (int64_t)yy * (3 * (int64_t)W) + c.off2);
+        v[LT_ROWS_PER_WAVE] = load_px3w(sdr + (int64_t)yy * (3 * (int64_t)W) + c.off2, end);
     }
 }
 __device__ __forceinline__ void store_lt_rows(uint32_t (*t)[LT_W + 2], const uint32_t v[LT_ROWS_PER_WAVE + 1],

@@ -451,3 +451,28 @@ def test_resid_patch_covers_each_pixel_once(npx):
                 ok = p[p < npx]
                 np.add.at(seen, ok, 1)
     assert (seen == 1).all()
+
+
+@pytest.mark.parametrize("H,W", [(1, 1), (1, 2), (2, 3), (3, 5), (17, 129), (64, 66), (5, 1001)])
+def test_learn_s_word_loads(H, W):
+    """k_learn's S tile fetch: for every pixel, two dwords from the dword
+    boundary at or below its first byte, byte-aligned by its offset, give
+    its three bytes whenever those 8 bytes end inside S (S starts on a dword
+    boundary); otherwise the three bytes are read one by one.  The two dword
+    loads never touch a byte outside S."""
+    rng = np.random.default_rng(H * 1000 + W)
+    n = 3 * H * W
+    S = rng.integers(0, 256, n, dtype=np.uint64)
+    fast = 0
+    for px in range(H * W):
+        p = 3 * px
+        sh = p & 3
+        q = p - sh
+        want = int(S[p]) | int(S[p + 1]) << 8 | int(S[p + 2]) << 16
+        if q + 8 <= n:
+            lo = sum(int(S[q + k]) << (8 * k) for k in range(4))
+            hi = sum(int(S[q + 4 + k]) << (8 * k) for k in range(4))
+            got = (((hi << 32) | lo) >> (8 * sh)) & 0xFFFFFF
+            assert q >= 0 and got == want, (px, sh)
+            fast += 1
+    assert fast >= H * W - 3
