@@ -47,8 +47,12 @@ VALU_LANE_PEAK = 256 * 4 * 16 * 2.4e9  # VALU lane-instructions/s: 256 CUs x 4 S
 # written once): RGBE 4 B, S 3 B, residual planes 6 B, E plane 1 B, learned
 # estimates 3 B.  The learned path's residual records and histograms are
 # bookkeeping of the selection, not algorithmic traffic.
+# Per pixel, what each stage must read and write at the least: k_learn reads S
+# and RGBE and leaves the SLR residual planes, the exponent plane and the
+# learned estimates (3 bytes); the learned path's last stage (k_resid_patch)
+# reads the exponent plane (flagged regions add their learned residuals).
 ALGO_BYTES_PER_PX = {"keystat": 4, "tmo_base": 4 + 3, "fit_sums": 3 + 4, "resid": 3 + 4 + 6 + 1,
-                     "learn": 3 + 4 + 3, "resid_learned": 3 + 4 + 3 + 6 + 1}
+                     "learn": 3 + 4 + 6 + 1 + 3, "resid_learned": 1}
 PIPELINE_BYTES_PER_PX = 4 + 3 + 6 + 1
 MLP_MAC_PER_PX = 27 * 32 + 32 * 32 + 32 * 3  # 1984: the learned estimator's multiply-adds per pixel
 PROFILES = os.path.join(ROOT, "profiles")
@@ -397,7 +401,7 @@ def main():
 
     # ---- roofline of the dominant kernel of the headline --------------------
     kern = {"keystat": "k_keystat", "tmo_base": "k_tmo_base", "fit_sums": "k_fit_sums", "solve": "k_solve",
-            "learn": "k_learn", "lhist": "k_lhist", "select": "k_select", "resid": "k_resid"}
+            "learn": "k_learn", "lhist": "k_lhist", "select": "k_select", "resid": "k_resid_patch"}
     stages = {k: v for k, v in stage_l.items() if k in kern}
     dom = max(stages, key=lambda k: stages[k])
     t_dom = stages[dom] * 1e-3

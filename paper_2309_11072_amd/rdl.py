@@ -88,7 +88,9 @@ _SIGS = {
 TUNE = ("fit_rows", "resid_rows", "fit_bins", "fit_waves")
 STAGES = ("keystat", "tmo_base", "fit_sums", "solve", "resid")
 KERNELS = ("k_keystat", "k_tmo_base", "k_fit_sums", "k_solve", "k_resid")
-#: All encoder stages (rdl_stage_times order) and their kernels.
+#: All encoder stages (rdl_stage_times order) and their kernels.  With the
+#: learned estimator the "resid" stage runs k_resid_patch (k_learn has
+#: already written the SLR residuals).
 STAGES_ALL = STAGES + ("learn", "lhist", "select")
 KERNELS_ALL = KERNELS + ("k_learn", "k_lhist", "k_select")
 TIMING_MAX_CALLS = 64
