@@ -184,6 +184,7 @@ struct Grid {
     int px = 0, blk = 0, tile = 0, fit = 0, res = 0, learn = 0, lhist = 0;
     int fit_bins = 1, fit_waves = STRIP_WAVES;  // the fit's launch shape: the largest image's
     int rq = 0;  // the learned estimator's requantisation path (the model's, see model_rq)
+    int learn_tiles = 8;  // tiles per learned-path workgroup (learn_tiles of the launch's pixels)
     int64_t fit_px = -1;
 };
 
@@ -235,6 +236,7 @@ int size_class(int H, int W) {
 // waves per workgroup) is one per launch: the largest image's.
 Grid layout(const rdl_ctx *c, std::vector<ImgDesc> &v) {
     Grid g;
+    g.learn_tiles = learn_tiles(total_px(v));
     for (auto &d : v) {
         if ((int64_t)d.H * d.W > g.fit_px) {
             g.fit_px = (int64_t)d.H * d.W;
@@ -260,7 +262,7 @@ Grid layout(const rdl_ctx *c, std::vector<ImgDesc> &v) {
         g.tile += wgs_tile(d.H, d.W);
         g.fit += wgs_strip(d.H, d.W, d.srh_fit, d.fit_waves);
         g.res += wgs_strip(d.H, d.W, d.srh_res);
-        g.learn += wgs_learn(d.H, d.W);
+        g.learn += wgs_learn(d.H, d.W, g.learn_tiles);
         g.lhist += wgs_lhist(d.H, d.W);
     }
     return g;
@@ -330,7 +332,7 @@ void enqueue_encode(const ImgDesc *d, int n, const Grid &g, bool learned, hipStr
     launch_solve(d, n, s);
     mark(1 + RDL_STAGE_SOLVE);
     if (learned) {
-        launch_learn(d, n, g.learn, g.rq, s);
+        launch_learn(d, n, g.learn, g.rq, g.learn_tiles, s);
         mark(1 + RDL_STAGE_LEARN);
         launch_lhist(d, n, g.lhist, s);
         mark(1 + RDL_STAGE_LHIST);
@@ -699,7 +701,7 @@ int rdl_decode_enh(rdl_ctx *c, const uint8_t *sdr, const rdl_header *coeffs, con
     if (rc) return rc;
     if (status) launch_status_init(c->d_desc, 1, s);
     launch_decode(c->d_desc, 1, gr.res, s);
-    if (c->d_model) launch_decode_learned(c->d_desc, 1, gr.learn, c->model_rq, s);
+    if (c->d_model) launch_decode_learned(c->d_desc, 1, gr.learn, c->model_rq, gr.learn_tiles, s);
     return check_launch("k_decode");
 }
 
@@ -735,7 +737,7 @@ int rdl_decode_batch(rdl_ctx *c, const rdl_dimage *imgs, int n, void *stream) {
     if (any_status) launch_status_init(c->d_desc, n, s);
     if (any_dct) launch_base_decode(c->d_desc, n, gr.blk, s);
     launch_decode(c->d_desc, n, gr.res, s);
-    if (c->d_model) launch_decode_learned(c->d_desc, n, gr.learn, c->model_rq, s);
+    if (c->d_model) launch_decode_learned(c->d_desc, n, gr.learn, c->model_rq, gr.learn_tiles, s);
     return check_launch("rdl_decode_batch");
 }
 

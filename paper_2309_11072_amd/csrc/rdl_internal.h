@@ -26,7 +26,12 @@ constexpr int FIT_WG_ROWS_MAX = 128;      // waves x rows per fit workgroup: <= 
                                           //   the workgroup's 32-bit bin totals cannot wrap
 constexpr int LCH = 16384;         // learned path: residual records per histogram workgroup
 constexpr int LH_COPIES = 8;       //   and its lane-interleaved LDS histogram copies
-constexpr int LEARN_W = 64, LEARN_H = 64;  // learned path: 64 x 64 px per workgroup
+// Learned path: a workgroup takes a 64-px-wide column of `tiles` tiles of 16
+// rows.  More tiles spread a workgroup's set-up (model fragments, bias table,
+// coefficients) over more pixels; fewer keep a small launch at several
+// workgroups per CU.  Chosen per launch from its pixel count.
+constexpr int LEARN_W = 64, LEARN_TILE_H = 16;
+inline int learn_tiles(size_t launch_px) { return launch_px >= ((size_t)1 << 25) ? 12 : 8; }
 constexpr int MODEL_BYTES = 7512;
 // The device copy of a model appends biases derived on the host when it is
 // set: B2[n] + 128 sum_k W2[n][k] (32 x i32) and B3[c] + 128 sum_k W3[c][k]
@@ -91,7 +96,10 @@ inline int wgs_strip(int H, int W, int srh, int waves = STRIP_WAVES) {
     const int sh = srh * waves;
     return ((H + sh - 1) / sh) * ((W + STRIP_W - 1) / STRIP_W);
 }
-inline int wgs_learn(int H, int W) { return ((H + LEARN_H - 1) / LEARN_H) * ((W + LEARN_W - 1) / LEARN_W); }
+inline int wgs_learn(int H, int W, int tiles) {
+    const int rows = LEARN_TILE_H * tiles;
+    return ((H + rows - 1) / rows) * ((W + LEARN_W - 1) / LEARN_W);
+}
 // Learned path, per image: residual histograms [2][3][256][511] (estimator,
 // channel, exponent), then the SLR residual histogram of each channel over
 // the whole image [3][511] (at LHIST_G).
@@ -118,10 +126,10 @@ void launch_decode(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_base_decode(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_status_init(const ImgDesc *d, int n, hipStream_t s);
 void launch_hist(const ImgDesc *d, int n, int wgs, hipStream_t s);
-void launch_learn(const ImgDesc *d, int n, int wgs, int rq, hipStream_t s);  // rq: requantisation path (RQ_*)
+void launch_learn(const ImgDesc *d, int n, int wgs, int rq, int tiles, hipStream_t s);  // rq: RQ_* path
 void launch_lhist(const ImgDesc *d, int n, int wgs, hipStream_t s);
 void launch_select(const ImgDesc *d, int n, hipStream_t s);
-void launch_decode_learned(const ImgDesc *d, int n, int wgs, int rq, hipStream_t s);
+void launch_decode_learned(const ImgDesc *d, int n, int wgs, int rq, int tiles, hipStream_t s);
 
 // Entropy code of the enhancement layer (static rANS with 64 interleaved
 // states per group; kernels in rdl_entropy.hip, format in rdl.h).

@@ -1705,7 +1705,7 @@ __device__ __forceinline__ void win_features(const Win3 &v, uint64_t f[4]) {
     f[3] = (uint64_t)f6;
 }
 
-constexpr int LT_W = 64, LT_H = 16, LT_TILES = 4;  // a workgroup walks 4 tiles of 16 x 64 px
+constexpr int LT_W = LEARN_W, LT_H = LEARN_TILE_H;  // a workgroup walks `tiles` tiles of 16 x 64 px
 __device__ __forceinline__ void load_lt_tile(uint32_t (*t)[LT_W + 2], const uint8_t *__restrict__ sdr, int H, int W,
                                              int ty0, int tx0) {
     for (int k = threadIdx.x; k < (LT_H + 2) * (LT_W + 2); k += 256) {
@@ -1838,7 +1838,7 @@ __device__ __forceinline__ uint64_t lrec_pack(const int rs[3], const int rl[3]) 
 // consecutive rows of a tile with a rolling 3x3 window of S, which serves
 // both the features and the Gaussian filter.
 template <int RQ>
-__global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, int n) {
+__global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, int n, int tiles) {
     __shared__ uint32_t t[LT_H + 2][LT_W + 2];
     __shared__ int2 s_ab[3][256];
     __shared__ int32_t B1[32][32];
@@ -1852,7 +1852,7 @@ __global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, in
     const rdl_header *h = d.hdr;
     const int wgl = blockIdx.x - d.wg_learn;
     const int ntx = (W + LT_W - 1) / LT_W;
-    const int ty0w = (wgl / ntx) * (LT_H * LT_TILES), tx0 = (wgl % ntx) * LT_W;
+    const int ty0w = (wgl / ntx) * (LT_H * tiles), tx0 = (wgl % ntx) * LT_W;
     for (int k = threadIdx.x; k < 3 * 256; k += 256) s_ab[k >> 8][k & 255] = coef_prep(h->a_q[k >> 8][k & 255], h->b_q[k >> 8][k & 255]);
     mlp_bias_load<RQ>(B1, d.model);
     s_cnt[threadIdx.x] = 0;
@@ -1882,7 +1882,7 @@ __global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, in
     const int64_t npx = (int64_t)H * W;
     int16_t *res16 = reinterpret_cast<int16_t *>(d.resid);
     uint8_t *eplane = d.resid + 6 * npx;
-    for (int tt = 0; tt < LT_TILES; ++tt) {
+    for (int tt = 0; tt < tiles; ++tt) {
         const int ty0 = ty0w + tt * LT_H;
         if (ty0 >= H) break;
         __syncthreads();
@@ -1908,7 +1908,7 @@ __global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, in
             if (c) my_base = atomicAdd(&d.lbk[threadIdx.x], c);
             s_cnt[threadIdx.x] = 0;
         }
-        if (tt + 1 < LT_TILES && ty0 + LT_H < H) {
+        if (tt + 1 < tiles && ty0 + LT_H < H) {
             fetch_lt_rows(sv, d.sdr, H, W, ty0 + LT_H, wave, lane, cols);
             fetch_rgbe(ty0 + LT_H, wv);
         }
@@ -2129,7 +2129,7 @@ __global__ __launch_bounds__(256) void k_select(const ImgDesc *__restrict__ D, i
 
 // Learned decoder: M = (flag ? M_L : M*) + r for headers with estimator 1.
 template <int RQ>
-__global__ __launch_bounds__(256) void k_decode_learned(const ImgDesc *__restrict__ D, int n) {
+__global__ __launch_bounds__(256) void k_decode_learned(const ImgDesc *__restrict__ D, int n, int tiles) {
     __shared__ uint32_t t[LT_H + 2][LT_W + 2];
     __shared__ int2 s_ab[3][256];
     __shared__ uint8_t s_fl[3][256];
@@ -2148,7 +2148,7 @@ __global__ __launch_bounds__(256) void k_decode_learned(const ImgDesc *__restric
     }
     const int wgl = blockIdx.x - d.wg_learn;
     const int ntx = (W + LT_W - 1) / LT_W;
-    const int ty0w = (wgl / ntx) * (LT_H * LT_TILES), tx0 = (wgl % ntx) * LT_W;
+    const int ty0w = (wgl / ntx) * (LT_H * tiles), tx0 = (wgl % ntx) * LT_W;
     __shared__ int s_bad;
     if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
@@ -2174,7 +2174,7 @@ __global__ __launch_bounds__(256) void k_decode_learned(const ImgDesc *__restric
     uint32_t *out = reinterpret_cast<uint32_t *>(d.out_rgbe);
     const int x = tx0 + lane;
     bool bad = false;
-    for (int tt = 0; tt < LT_TILES; ++tt) {
+    for (int tt = 0; tt < tiles; ++tt) {
         const int ty0 = ty0w + tt * LT_H;
         __syncthreads();
         if (ty0 < H) load_lt_tile(t, d.sdr, H, W, ty0, tx0);
@@ -2383,13 +2383,13 @@ void launch_status_init(const ImgDesc *d, int n, hipStream_t s) {
 void launch_decode(const ImgDesc *d, int n, int wgs, hipStream_t s) {
     hipLaunchKernelGGL(k_decode, dim3(wgs), dim3(STRIP_THREADS), 0, s, d, n);
 }
-void launch_learn(const ImgDesc *d, int n, int wgs, int rq, hipStream_t s) {
+void launch_learn(const ImgDesc *d, int n, int wgs, int rq, int tiles, hipStream_t s) {
     if (rq == RQ_PAIR)
-        hipLaunchKernelGGL(k_learn<RQ_PAIR>, dim3(wgs), dim3(256), 0, s, d, n);
+        hipLaunchKernelGGL(k_learn<RQ_PAIR>, dim3(wgs), dim3(256), 0, s, d, n, tiles);
     else if (rq == RQ_POW2)
-        hipLaunchKernelGGL(k_learn<RQ_POW2>, dim3(wgs), dim3(256), 0, s, d, n);
+        hipLaunchKernelGGL(k_learn<RQ_POW2>, dim3(wgs), dim3(256), 0, s, d, n, tiles);
     else
-        hipLaunchKernelGGL(k_learn<RQ_GENERAL>, dim3(wgs), dim3(256), 0, s, d, n);
+        hipLaunchKernelGGL(k_learn<RQ_GENERAL>, dim3(wgs), dim3(256), 0, s, d, n, tiles);
 }
 void launch_lhist(const ImgDesc *d, int n, int wgs, hipStream_t s) {
     hipLaunchKernelGGL(k_lhist, dim3(wgs), dim3(LH_THREADS), 0, s, d, n);
@@ -2397,13 +2397,13 @@ void launch_lhist(const ImgDesc *d, int n, int wgs, hipStream_t s) {
 void launch_select(const ImgDesc *d, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_select, dim3(256 * n), dim3(256), 0, s, d, n);
 }
-void launch_decode_learned(const ImgDesc *d, int n, int wgs, int rq, hipStream_t s) {
+void launch_decode_learned(const ImgDesc *d, int n, int wgs, int rq, int tiles, hipStream_t s) {
     if (rq == RQ_PAIR)
-        hipLaunchKernelGGL(k_decode_learned<RQ_PAIR>, dim3(wgs), dim3(256), 0, s, d, n);
+        hipLaunchKernelGGL(k_decode_learned<RQ_PAIR>, dim3(wgs), dim3(256), 0, s, d, n, tiles);
     else if (rq == RQ_POW2)
-        hipLaunchKernelGGL(k_decode_learned<RQ_POW2>, dim3(wgs), dim3(256), 0, s, d, n);
+        hipLaunchKernelGGL(k_decode_learned<RQ_POW2>, dim3(wgs), dim3(256), 0, s, d, n, tiles);
     else
-        hipLaunchKernelGGL(k_decode_learned<RQ_GENERAL>, dim3(wgs), dim3(256), 0, s, d, n);
+        hipLaunchKernelGGL(k_decode_learned<RQ_GENERAL>, dim3(wgs), dim3(256), 0, s, d, n, tiles);
 }
 void launch_hist(const ImgDesc *d, int n, int wgs, hipStream_t s) {
     hipLaunchKernelGGL(k_hist, dim3(wgs), dim3(TILE_THREADS), 0, s, d, n);
