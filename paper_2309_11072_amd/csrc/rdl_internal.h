@@ -24,7 +24,7 @@ constexpr int SRH_RES_DEFAULT = 8;
 constexpr int FIT_BINS_DEFAULT = 2;       // privatised copies of the fit's LDS bins: 1, 2 or 4
 constexpr int FIT_WG_ROWS_MAX = 128;      // waves x rows per fit workgroup: <= 32768 px, so
                                           //   the workgroup's 32-bit bin totals cannot wrap
-constexpr int LCH = 16384;         // learned path: residual records per histogram workgroup
+constexpr int LCH = 32768;         // learned path: residual records per histogram workgroup
 constexpr int LH_COPIES = 8;       //   and its lane-interleaved LDS histogram copies
 // Learned path: a workgroup takes a 64-px-wide column of `tiles` tiles of 16
 // rows.  More tiles spread a workgroup's set-up (model fragments, bias table,

@@ -1968,7 +1968,8 @@ __global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, in
 // exponent e's bucket, where e is the exponent whose first histogram
 // workgroup (a prefix over ceil(n_e / LCH)) is the last one <= g.  Counts go
 // to LH_COPIES lane-interleaved LDS copies as 16-bit halves of 32-bit words
-// (at most LCH = 2^14 records per workgroup, so a half cannot carry), then
+// (a copy counts the records of LH_THREADS / LH_COPIES threads, at most
+// LCH / LH_COPIES = 2^12 per workgroup, so a half cannot carry), then
 // each non-zero bin to the image's histogram with one atomic.  Residuals
 // cluster near zero, so many lanes of a wave hit the same bin; the copies
 // split those collisions LH_COPIES ways, and their odd word stride puts the
@@ -1990,6 +1991,7 @@ __device__ __forceinline__ void lh_count(uint32_t *mine, uint64_t r) {
     lh_inc(mine, 5, b >> 18);
 }
 
+static_assert(LCH / LH_COPIES < 65536, "k_lhist: a 16-bit half counts at most LCH / LH_COPIES records");
 __global__ __launch_bounds__(LH_THREADS) void k_lhist(const ImgDesc *__restrict__ D, int n) {
     __shared__ uint32_t hb[LH_COPIES * LH_STRIDE];
     const int i = find_img(D, n, blockIdx.x, 6);

@@ -109,7 +109,7 @@ def test_strip_walk_stays_inside_buffers(H, W, srh, waves):
 # each exponent (prefixes over ceil(n_e / LCH)); k_learn reserves records per
 # tile with atomics on the bucket cursors; k_lhist maps its workgroup to an
 # exponent by binary search and histograms LCH records of that bucket.
-LCH = 16384
+LCH = 32768
 
 
 def bucket_table(ne):
