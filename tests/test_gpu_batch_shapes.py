@@ -103,3 +103,44 @@ def test_mixed_batch_direct_and_graph_match_oracle(codec, rdl_mod, O, images, le
     finally:
         codec.set_launch_mode(False)
         codec.set_estimator(0)
+
+
+def test_learned_launch_of_2p25_pixels_matches_oracle(codec, rdl_mod, O, images):
+    """A learned launch of at least 2^25 pixels, where the estimator's and the
+    learned decoder's workgroups take 12 tiles of 16 rows instead of 8: one
+    5800 x 5800 image (33.6 Mpx, drawn on the GPU) plus the four smaller
+    images above, in one call.  The four small images' outputs are compared
+    with the oracle (the large one would take the oracle about a minute), and
+    the whole batch, the large image included, decodes losslessly in one
+    call (the decoder's launch is as large)."""
+    blob = open(MODEL, "rb").read()
+    big = synth.generate_torch(5800, 5800, 3.0, seed=8110, spec_frac=0.05)
+    small = [(torch.from_numpy(x).cuda(), sp) for x, sp in zip(images[1:], SPECS[1:])]
+    assert 5800 * 5800 + sum(sp[0] * sp[1] for _, sp in small) >= 1 << 25
+    refs = []
+    for x, sp in zip(images[1:], SPECS[1:]):
+        _say("oracle learned", sp[0], sp[1])
+        refs.append(O.encode_learned(x, sp[3], blob))
+    codec.set_model(blob)
+    codec.set_estimator(1)
+    try:
+        outs = [codec.alloc_outputs(5800, 5800)] + [codec.alloc_outputs(sp[0], sp[1]) for _, sp in small]
+        items = [(big, 75) + tuple(outs[0])] + [(d, sp[3]) + tuple(o) for (d, sp), o in zip(small, outs[1:])]
+        for rep in range(2):
+            _say("large learned launch, call", rep)
+            for o in outs:
+                for t in o:
+                    t.fill_(0xAA)
+            codec.encode_batch(items)
+            torch.cuda.synchronize()
+            for (d, sp), o, x, ref in zip(small, outs[1:], images[1:], refs):
+                _check(rdl_mod, x, sp[3], o, ref, True)
+        assert rdl_mod.header_from_bytes(outs[0][1])["flag"].any(), "the large image has learned regions"
+        devs = [big] + [d for d, _ in small]
+        backs = [torch.empty_like(d) for d in devs]
+        codec.decode_batch([(None, o[0], o[1], o[2], b, None) for o, b in zip(outs, backs)])
+        torch.cuda.synchronize()
+        for d, b in zip(devs, backs):
+            assert torch.equal(d, b)
+    finally:
+        codec.set_estimator(0)
