@@ -1295,32 +1295,38 @@ __global__ __launch_bounds__(STRIP_THREADS) void k_resid(const ImgDesc *__restri
 // exponent plane and every pixel's learned residuals in the outputs; in the
 // regions flagged learned each channel's residual becomes the learned one.
 // The key statistic's grid (KS_PX_PER_WG consecutive pixels per workgroup,
-// 16 waves so that a small image still keeps enough loads in flight); a
-// step covers 16 x 1024 pixels, lane-consecutive so that every plane is read
-// and written in whole lines at any alignment.  An image without a flagged
-// region returns at once.
-constexpr int PATCH_THREADS = 1024, PATCH_RUN = 16;
-static_assert(KS_PX_PER_WG % (PATCH_THREADS * PATCH_RUN) == 0, "k_resid_patch: whole steps per workgroup");
+// 16 waves so that a small image still keeps enough loads in flight).  A
+// step covers 8 x 1024 pixel pairs (2k, 2k + 1), lane-consecutive so that
+// every plane is read and written in whole lines at any alignment; a pair's
+// exponents come in one aligned 16-bit load (the exponent plane starts 6 H W
+// bytes into the 2-byte aligned residual buffer).  An odd image's last pixel
+// is done on its own.  An image without a flagged region returns at once.
+constexpr int PATCH_THREADS = 1024, PATCH_PAIRS = 8;
+static_assert(KS_PX_PER_WG % (2 * PATCH_THREADS * PATCH_PAIRS) == 0, "k_resid_patch: whole steps per workgroup");
 __device__ __forceinline__ int lres_field(uint32_t w, int c) { return (int)((w >> (9 * c)) & 511u) - 255; }
 
 __global__ __launch_bounds__(PATCH_THREADS) void k_resid_patch(const ImgDesc *__restrict__ D, int n) {
-    constexpr int STEP = PATCH_THREADS * PATCH_RUN, NSTEP = KS_PX_PER_WG / STEP;
+    constexpr int STEP = 2 * PATCH_THREADS * PATCH_PAIRS, NSTEP = KS_PX_PER_WG / STEP;
     __shared__ uint8_t s_fl[256];  // bit c set: channel c of exponent e is learned
     const int i = find_img(D, n, blockIdx.x, 0);
     const ImgDesc d = desc_at(D, i);
     const int64_t npx = (int64_t)d.H * d.W;
-    const int64_t base = (int64_t)(blockIdx.x - d.wg_px) * KS_PX_PER_WG + threadIdx.x;
+    const int64_t pe = npx & ~(int64_t)1;  // pixels in whole pairs
+    const int wgl = blockIdx.x - d.wg_px;
+    const int64_t base = (int64_t)wgl * KS_PX_PER_WG + 2 * (int)threadIdx.x;  // the thread's first pixel
     const uint8_t *__restrict__ ep = d.resid + 6 * npx;
     int16_t *res = reinterpret_cast<int16_t *>(d.resid);
     const uint32_t *__restrict__ lr = reinterpret_cast<const uint32_t *>(d.lres);
-    // Exponents of step it, at clamped addresses (the loads stay
-    // unconditional; pixels past the end are masked when used).
-    const auto load_e = [&](int it, uint32_t (&ev)[PATCH_RUN]) {
+    // Exponents of the pairs of step it, low byte = even pixel.  The address
+    // is clamped to the last whole pair (so the loads stay unconditional and
+    // inside the plane); pairs past it are masked when used.
+    const auto load_e = [&](int it, uint32_t (&ev)[PATCH_PAIRS]) {
 #pragma unroll
-        for (int j = 0; j < PATCH_RUN; ++j) ev[j] = ep[min(base + it * STEP + j * PATCH_THREADS, npx - 1)];
+        for (int j = 0; j < PATCH_PAIRS; ++j)
+            ev[j] = *reinterpret_cast<const uint16_t *>(ep + min(base + it * STEP + 2 * j * PATCH_THREADS, pe - 2));
     };
-    uint32_t ev[2][PATCH_RUN];
-    load_e(0, ev[0]);  // in flight with the flags
+    uint32_t ev[2][PATCH_PAIRS];
+    if (pe >= 2) load_e(0, ev[0]);  // in flight with the flags
     int f0 = 0;
     if (threadIdx.x < 256) {  // one exponent per thread
         const int e = threadIdx.x;
@@ -1328,28 +1334,38 @@ __global__ __launch_bounds__(PATCH_THREADS) void k_resid_patch(const ImgDesc *__
         s_fl[e] = (uint8_t)f0;
     }
     if (!__syncthreads_or(f0)) return;  // uniform
+    const auto patch = [&](int64_t p, uint32_t f, uint32_t w) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            if ((f >> c) & 1) res[c * npx + p] = (int16_t)lres_field(w, c);
+    };
 #pragma unroll
     for (int it = 0; it < NSTEP; ++it) {
         const int64_t p0 = base + it * STEP;
-        if (p0 >= npx) break;
+        if (p0 >= pe) break;
         if (it + 1 < NSTEP) load_e(it + 1, ev[(it + 1) & 1]);
-        uint32_t f[PATCH_RUN], any = 0;
+        uint32_t f[2 * PATCH_PAIRS], any = 0;
 #pragma unroll
-        for (int j = 0; j < PATCH_RUN; ++j) {
-            f[j] = p0 + j * PATCH_THREADS < npx ? s_fl[ev[it & 1][j]] : 0u;
-            any |= f[j];
+        for (int j = 0; j < PATCH_PAIRS; ++j) {
+            const bool in = p0 + 2 * j * PATCH_THREADS < pe;  // both pixels of the pair
+            const uint32_t e2 = ev[it & 1][j];
+            f[2 * j] = in ? s_fl[e2 & 255u] : 0u;
+            f[2 * j + 1] = in ? s_fl[e2 >> 8] : 0u;
+            any |= f[2 * j] | f[2 * j + 1];
         }
         if (!any) continue;
-        uint32_t w[PATCH_RUN];
+        uint32_t w[2 * PATCH_PAIRS];
 #pragma unroll
-        for (int j = 0; j < PATCH_RUN; ++j) w[j] = f[j] ? lr[p0 + j * PATCH_THREADS] : 0u;
+        for (int k = 0; k < 2 * PATCH_PAIRS; ++k) w[k] = f[k] ? lr[p0 + 2 * (k >> 1) * PATCH_THREADS + (k & 1)] : 0u;
 #pragma unroll
-        for (int j = 0; j < PATCH_RUN; ++j) {
-            const int64_t p = p0 + j * PATCH_THREADS;
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                if ((f[j] >> c) & 1) res[c * npx + p] = (int16_t)lres_field(w[j], c);
-        }
+        for (int k = 0; k < 2 * PATCH_PAIRS; ++k) patch(p0 + 2 * (k >> 1) * PATCH_THREADS + (k & 1), f[k], w[k]);
+    }
+    // An odd image's last pixel, by the first thread of the workgroup that
+    // holds it.
+    if ((npx & 1) && threadIdx.x == 0 && (npx - 1) / KS_PX_PER_WG == wgl) {
+        const int64_t p = npx - 1;
+        const uint32_t f = s_fl[ep[p]];
+        if (f) patch(p, f, lr[p]);
     }
 }
 
@@ -1834,9 +1850,10 @@ __device__ __forceinline__ uint64_t lrec_pack(const int rs[3], const int rl[3]) 
 // pixels of each exponent with LDS atomics, reserves that many records with
 // one global atomic per exponent before it computes the tile's estimates,
 // and writes the records after them.  Record order within a bucket is free:
-// only histograms are taken from it.  Each wave walks 4
-// consecutive rows of a tile with a rolling 3x3 window of S, which serves
-// both the features and the Gaussian filter.
+// only histograms are taken from it.  A workgroup takes a 64-px-wide column
+// of `tiles` tiles (learn_tiles); each wave walks 4 consecutive rows of a
+// tile with a rolling 3x3 window of S, which serves both the features and
+// the Gaussian filter.
 template <int RQ>
 __global__ __launch_bounds__(256) void k_learn(const ImgDesc *__restrict__ D, int n, int tiles) {
     __shared__ uint32_t t[LT_H + 2][LT_W + 2];

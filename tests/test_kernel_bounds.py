@@ -423,33 +423,43 @@ def test_exponent_difference_kernels_model(H, W, lead):
 
 
 # ---- learned path: the residual patch ----------------------------------------
-KS_PX_PER_WG, PATCH_THREADS, PATCH_RUN = 32768, 1024, 16
+KS_PX_PER_WG, PATCH_THREADS, PATCH_PAIRS = 32768, 1024, 8
 
 
-@pytest.mark.parametrize("npx", [1, 63, 4095, 4097, 32767, 32768, 32769, 7 * 9, 3840 * 2160, 4492 * 5989])
+@pytest.mark.parametrize("npx", [1, 2, 3, 63, 4095, 4097, 32767, 32768, 32769, 65535, 7 * 9, 3840 * 2160,
+                                 4492 * 5989])
 def test_resid_patch_covers_each_pixel_once(npx):
     """k_resid_patch: workgroup g of an image (ceil(npx / KS_PX_PER_WG) of
-    them) takes pixels g KS_PX_PER_WG + it 16384 + j 1024 + lane; the exponent
-    loads use indices clamped to [0, npx) and every pixel index that passes
-    the bound is taken exactly once, so the residual stores c npx + p stay
-    inside the planes."""
+    them) takes the pixel pairs starting at g KS_PX_PER_WG + it 16384 +
+    2 (j 1024 + lane) while they lie wholly below pe = npx rounded down to
+    even; its 16-bit exponent loads start at an even offset clamped to pe - 2,
+    so they stay 2-byte aligned and inside the plane; an odd image's last
+    pixel goes to thread 0 of the workgroup that holds it.  Every pixel is
+    taken exactly once, so the residual stores c npx + p stay inside the
+    planes."""
     nwg = (npx + KS_PX_PER_WG - 1) // KS_PX_PER_WG
+    pe = npx & ~1
     lanes = np.arange(PATCH_THREADS, dtype=np.int64)
     seen = np.zeros(npx, np.int32)
-    step = PATCH_THREADS * PATCH_RUN
+    step = 2 * PATCH_THREADS * PATCH_PAIRS
     for g in range(nwg):
-        base = g * KS_PX_PER_WG + lanes
+        base = g * KS_PX_PER_WG + 2 * lanes
         for it in range(KS_PX_PER_WG // step):
             p0 = base + it * step
-            live = p0 < npx
+            live = p0 < pe
+            if pe >= 2:
+                for j in range(PATCH_PAIRS):
+                    q = np.minimum(p0 + 2 * j * PATCH_THREADS, pe - 2)
+                    assert (q % 2 == 0).all() and q.min() >= 0 and (q + 2).max() <= npx
             if not live.any():
                 break
-            for j in range(PATCH_RUN):
-                p = p0[live] + j * PATCH_THREADS
-                clamped = np.minimum(p, npx - 1)
-                assert clamped.min() >= 0 and clamped.max() < npx
-                ok = p[p < npx]
+            for j in range(PATCH_PAIRS):
+                p = p0[live] + 2 * j * PATCH_THREADS
+                ok = p[p < pe]
                 np.add.at(seen, ok, 1)
+                np.add.at(seen, ok + 1, 1)
+        if npx % 2 and (npx - 1) // KS_PX_PER_WG == g:
+            seen[npx - 1] += 1
     assert (seen == 1).all()
 
 
