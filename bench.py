@@ -23,7 +23,9 @@ Also measured, outside the timed region:
   * the entropy code, the base layer's JPEG file and the batched decoder on
     the 3840x2160 image, and the ablations and a quality sweep;
   * the CPU oracle (learned + fallback) on a bounded sample of the 256 images,
-    image-parallel on the host's cores (cpu_baseline).
+    image-parallel on the host's cores (cpu_baseline), and with plain SLR on
+    the 512x384 and 3840x2160 images (one core, and one copy per core) and on
+    a sample of the 64-image batch (image-parallel).
 """
 import argparse
 import hashlib
@@ -153,6 +155,48 @@ class OraclePool:
             self.jobs.put(None)
         for p in self.procs:
             p.join(timeout=60)
+
+
+def oracle_per_config(pool, tmpdir, ncpu, sample_px):
+    """The oracle (plain SLR) on the smaller workloads: the 512x384 and the
+    3840x2160 image each on one core and as `ncpu` concurrent copies (one
+    per process), and a sample of the 64-image batch image-parallel (a
+    full-width band of at most `sample_px` pixels from each of `ncpu` evenly
+    spaced images, one image per process)."""
+    import numpy as np
+    from paper_2309_11072_amd import synth
+
+    def save(name, x):
+        path = os.path.join(tmpdir, name + ".npy")
+        np.save(path, x)
+        return path
+
+    out = {}
+    for key, spec in (("512x384_q90", synth.small_512x384()), ("3840x2160_q75", synth.image_3840x2160())):
+        path = save(key, spec.make_torch().cpu().numpy())
+        say("cpu oracle: %s, one core and %d copies" % (key, ncpu))
+        wall1, _, px1 = pool.run([(path, spec.q)], learned=False)
+        walln, _, pxn = pool.run([(path, spec.q)] * ncpu, learned=False)
+        os.unlink(path)
+        out[key] = {"single_thread_Mpixel_s": round(px1 / wall1 / 1e6, 4),
+                    "all_cores_Mpixel_s": round(pxn / walln / 1e6, 4), "cores": ncpu,
+                    "wall_s": round(walln, 3)}
+    specs = synth.batch_64_uneven()
+    picks = list(range(0, len(specs), max(1, len(specs) // ncpu)))[:ncpu]
+    jobs = []
+    for i in picks:
+        s = specs[i]
+        rows = max(1, min(s.H, sample_px // s.W))
+        jobs.append((save("b64_%02d" % i, s.make_torch()[:rows].cpu().numpy()), s.q))
+    say("cpu oracle: 64-image batch sample, %d processes" % len(jobs))
+    wall, sm, px = pool.run(jobs, learned=False)
+    for path, _ in jobs:
+        os.unlink(path)
+    out["batch_64_sample"] = {"all_cores_Mpixel_s": round(px / wall / 1e6, 4), "cores": len(jobs),
+                              "single_thread_Mpixel_s": round(px / sm / 1e6, 4), "wall_s": round(wall, 3),
+                              "sample": "full-width bands of at most %d px from images %s (%d px)" % (
+                                  sample_px, picks, px)}
+    return out
 
 
 def cpu_model():
@@ -327,6 +371,7 @@ def main():
         wall_l, sum_l, px_l = pool.run([(p, q) for p, q, _, _ in jobs], learned=True)
         say("cpu oracle: plain SLR")
         wall_p, sum_p, px_p = pool.run([(p, q) for p, q, _, _ in jobs], learned=False)
+        per_config = oracle_per_config(pool, tmpdir, ncpu, args.cpu_sample_px)
         pool.close()
         for p, _, _, _ in jobs:
             os.unlink(p)
@@ -339,7 +384,7 @@ def main():
                "single_thread_Mpixel_s": round(px_l / sum_l / 1e6, 4),
                "plain_slr": {"value": round(px_p / wall_p / 1e6, 4), "single_thread_Mpixel_s":
                              round(px_p / sum_p / 1e6, 4), "wall_s": round(wall_p, 3)},
-               "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+               "per_config": per_config, "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
         say("cpu oracle %.3f Mpixel/s on %d cores (plain %.3f)" % (cpu["value"], cpu["cores"],
                                                                   cpu["plain_slr"]["value"]))
 
