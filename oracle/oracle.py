@@ -84,11 +84,11 @@ def lib():
         L.oracle_jpeg_write.restype = i64
         L.oracle_ent_freqs.argtypes = [vp, C.c_int, vp]
         L.oracle_ent_freqs.restype = C.c_int
-        L.oracle_ent_bound.argtypes = [C.c_int, C.c_int, C.c_int]
+        L.oracle_ent_bound.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int]
         L.oracle_ent_bound.restype = i64
-        L.oracle_ent_encode.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int, vp, i64]
+        L.oracle_ent_encode.argtypes = [vp, vp, C.c_int, C.c_int, C.c_int, C.c_int, vp, i64]
         L.oracle_ent_encode.restype = i64
-        L.oracle_ent_decode.argtypes = [vp, i64, C.c_int, C.c_int, vp]
+        L.oracle_ent_decode.argtypes = [vp, i64, vp, C.c_int, C.c_int, vp]
         L.oracle_ent_decode.restype = C.c_int
         _lib = L
     return _lib
@@ -342,10 +342,11 @@ def decode_learned(sdr, a_q, b_q, flag, k_img, blob, resid, H, W) -> np.ndarray:
 
 # ---------------------------------------------------------------- entropy code of the layer
 ENT_HDR = 4136
+ENT_HDR_CTX = 25640  # with the residual contexts (8 tables per channel)
 
 
 def ent_freqs(h) -> np.ndarray:
-    """Quantised frequencies (sum 2^15) of one plane's symbol counts."""
+    """Quantised frequencies (sum 2^15) of one table's symbol counts."""
     h = np.ascontiguousarray(h, np.int64)
     f = np.zeros(len(h), np.uint16)
     if lib().oracle_ent_freqs(_p(h), len(h), _p(f)):
@@ -353,27 +354,41 @@ def ent_freqs(h) -> np.ndarray:
     return f
 
 
-def ent_bound(H: int, W: int, log2_k: int = 8) -> int:
-    return int(lib().oracle_ent_bound(H, W, log2_k))
+def ent_bound(H: int, W: int, log2_k: int = 8, contexts: bool = False) -> int:
+    return int(lib().oracle_ent_bound(H, W, log2_k, 2 if contexts else 0))
 
 
-def ent_encode(resid: np.ndarray, H: int, W: int, log2_k: int = 8, predict: bool = True) -> bytes:
+def _sdr_arg(sdr, H, W):
+    if sdr is None:
+        return None, None
+    s = np.ascontiguousarray(sdr, np.uint8).reshape(-1)
+    assert s.size == 3 * H * W
+    return s, _p(s)
+
+
+def ent_encode(resid: np.ndarray, H: int, W: int, log2_k: int = 8, predict: bool = True, sdr=None) -> bytes:
     """Code stream of an enhancement layer (7 H W bytes); predict codes the
-    exponent plane as differences from the left neighbour."""
+    exponent plane as differences from the left neighbour; with sdr (the
+    decoded base layer, H x W x 3) each residual is coded with the table of
+    its context sdr >> 5."""
     buf = np.ascontiguousarray(resid).view(np.uint8).reshape(-1)
     assert buf.size == 7 * H * W
-    out = np.zeros(max(ent_bound(H, W, log2_k), 1), np.uint8)
-    n = lib().oracle_ent_encode(_p(buf), H, W, log2_k, 1 if predict else 0, _p(out), out.size)
+    keep, sp = _sdr_arg(sdr, H, W)
+    flags = (1 if predict else 0) | (2 if sdr is not None else 0)
+    out = np.zeros(max(ent_bound(H, W, log2_k, sdr is not None), 1), np.uint8)
+    n = lib().oracle_ent_encode(_p(buf), sp, H, W, log2_k, flags, _p(out), out.size)
     if n < 0:
         raise ValueError("oracle_ent_encode failed with %d" % n)
     return out[:n].tobytes()
 
 
-def ent_decode(stream: bytes, H: int, W: int) -> np.ndarray:
-    """Enhancement layer (7 H W bytes) from a code stream."""
+def ent_decode(stream: bytes, H: int, W: int, sdr=None) -> np.ndarray:
+    """Enhancement layer (7 H W bytes) from a code stream (sdr: the decoded
+    base layer, needed for a stream with residual contexts)."""
     st = np.frombuffer(stream, np.uint8).copy()
     out = np.zeros(7 * H * W, np.uint8)
-    rc = lib().oracle_ent_decode(_p(st), st.size, H, W, _p(out))
+    keep, sp = _sdr_arg(sdr, H, W)
+    rc = lib().oracle_ent_decode(_p(st), st.size, sp, H, W, _p(out))
     if rc:
         raise ValueError("oracle_ent_decode failed with %d" % rc)
     return out

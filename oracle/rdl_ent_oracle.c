@@ -34,9 +34,20 @@
  * white (the JPEG quantisation error of the base layer plus the estimator's),
  * and differencing them raises their entropy.
  *
- * Frequencies of a plane, from its counts h[s] (P symbols present, N total):
+ * Residual contexts (flags bit 1): the residual of channel p at pixel i is
+ * coded with the table of its context k = S[i][p] >> 5 (k = 0..7), S being
+ * the decoded base layer (8-bit SDRI, H W x 3, channel-interleaved), which the
+ * decoder holds before it reads this layer.  The residuals' spread depends on
+ * where the tone curve put the pixel (how many mantissa steps one SDRI step
+ * spans there), so 8 tables per channel fit the data better than one.
+ * Symbols of all contexts stay interleaved in the same groups and lanes; only
+ * the table used for a symbol changes.  The exponent plane keeps one table.
+ *
+ * Frequencies of a table, from its counts h[s] (P symbols present, N = sum of
+ * h, the symbols coded with that table):
  *   f[s] = 0 where h[s] = 0, else 1 + floor(h[s] (M - P) / N);
  *   then the smallest s with the largest count takes the remainder M - sum f.
+ *   A context table with N = 0 (no pixel in that context) is all zero.
  *
  * Groups: K = 2^log2_k steps (4 <= log2_k <= 12); a plane is cut into
  * G = ceil(N / 64K) groups of 64K consecutive symbols (the last one shorter).  Symbol i of a group
@@ -50,10 +61,12 @@
  *
  * Stream (little-endian):
  *   0 u32 magic 0x454C4452   4 u32 version 1    8 i32 H       12 i32 W
- *  16 i32 log2_k            20 i32 prob_bits 15 24 u32 G      28 u32 flags (0 or 1)
- *  32 u64 total bytes       40 u16 freq[4][512]  (unused entries 0)
- *  4136 u64 start[4][G]: first word of each group, counted from the payload
- *  4136 + 32 G: payload, u16 words, groups in plane-major order.
+ *  16 i32 log2_k            20 i32 prob_bits 15 24 u32 G      28 u32 flags (0..3)
+ *  32 u64 total bytes       40 u16 freq[T][512]  (unused entries 0)
+ *  D = 40 + 1024 T: u64 start[4][G]: first word of each group, counted from the payload
+ *  D + 32 G: payload, u16 words, groups in plane-major order.
+ * T = 4 tables (plane p's at p) without contexts, D = 4136; with contexts
+ * T = 25 (channel p, context k at 8 p + k; the exponents' at 24), D = 25640.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -63,9 +76,21 @@
 #define ENT_M (1u << ENT_PB)
 #define ENT_L (1u << 16)
 #define ENT_HDR 4136
+#define ENT_HDR_CTX 25640
 #define ENT_MAGIC 0x454C4452u
+#define ENT_NCTX 8
 
-static const int ENT_NSYM[4] = {511, 511, 511, 256};
+static int64_t hdr_bytes(int flags) { return (flags & 2) ? ENT_HDR_CTX : ENT_HDR; }
+static int n_tables(int flags) { return (flags & 2) ? 3 * ENT_NCTX + 1 : 4; }
+static int table_nsym(int flags, int t) { return t == n_tables(flags) - 1 ? 256 : 511; }
+
+/* Table of symbol i of plane p. */
+static int table_of(const uint8_t *sdr, int flags, int p, int64_t i)
+{
+    if (!(flags & 2)) return p;
+    if (p == 3) return 3 * ENT_NCTX;
+    return ENT_NCTX * p + (sdr[3 * i + p] >> 5);
+}
 
 static void put32(uint8_t *p, uint32_t v) { for (int k = 0; k < 4; k++) p[k] = (uint8_t)(v >> (8 * k)); }
 static void put64(uint8_t *p, uint64_t v) { for (int k = 0; k < 8; k++) p[k] = (uint8_t)(v >> (8 * k)); }
@@ -87,7 +112,7 @@ static int plane_sym(const uint8_t *resid, int64_t N, int W, int flags, int p, i
     return (r < -255 || r > 255) ? -1 : r + 255;
 }
 
-/* Quantised frequencies of one plane (rule in the file header). */
+/* Quantised frequencies of one table (rule in the file header). */
 int oracle_ent_freqs(const int64_t *h, int nsym, uint16_t *f)
 {
     int64_t N = 0, P = 0;
@@ -96,7 +121,7 @@ int oracle_ent_freqs(const int64_t *h, int nsym, uint16_t *f)
         N += h[s];
         P += h[s] > 0;
     }
-    if (N == 0) return -1;
+    if (N == 0) return -1;  /* callers handle an unused context table themselves */
     int64_t sum = 0;
     int best = 0;
     for (int s = 0; s < nsym; s++) {
@@ -115,45 +140,57 @@ int64_t oracle_ent_groups(int H, int W, int log2_k)
     return (N + z - 1) / z;
 }
 
-/* Largest stream of an H x W layer: every symbol renormalises once. */
-int64_t oracle_ent_bound(int H, int W, int log2_k)
+/* Largest stream of an H x W layer: every symbol renormalises once (flags
+ * bit 1: the larger header of the context tables). */
+int64_t oracle_ent_bound(int H, int W, int log2_k, int flags)
 {
     if (H < 1 || W < 1 || log2_k < 4 || log2_k > 12) return -1;
     int64_t G = oracle_ent_groups(H, W, log2_k), N = (int64_t)H * W;
-    return ENT_HDR + 32 * G + 2 * (4 * N + 4 * G * 128);
+    return hdr_bytes(flags) + 32 * G + 2 * (4 * N + 4 * G * 128);
 }
 
 /* Encode the enhancement layer resid (int16 r[3][H][W], then uint8 E[H][W]);
- * flags bit 0 codes the exponents as left differences.  Returns the stream length, -1 for bad arguments, -2 when cap is too small,
- * -3 when a residual lies outside [-255, 255]. */
-int64_t oracle_ent_encode(const void *resid_v, int H, int W, int log2_k, int flags, uint8_t *out, int64_t cap)
+ * flags bit 0 codes the exponents as left differences, bit 1 codes each
+ * residual with the table of its context from sdr (the decoded base layer,
+ * H W x 3 bytes; unused otherwise).  Returns the stream length, -1 for bad
+ * arguments, -2 when cap is too small, -3 when a residual lies outside
+ * [-255, 255]. */
+int64_t oracle_ent_encode(const void *resid_v, const uint8_t *sdr, int H, int W, int log2_k, int flags, uint8_t *out,
+                          int64_t cap)
 {
     const uint8_t *resid = (const uint8_t *)resid_v;
-    if (!resid || !out || H < 1 || W < 1 || log2_k < 4 || log2_k > 12 || (flags & ~1)) return -1;
+    if (!resid || !out || H < 1 || W < 1 || log2_k < 4 || log2_k > 12 || (flags & ~3) || ((flags & 2) && !sdr))
+        return -1;
     const int64_t N = (int64_t)H * W, Z = (int64_t)64 << log2_k, G = oracle_ent_groups(H, W, log2_k);
-    if (cap < oracle_ent_bound(H, W, log2_k)) return -2;
-    memset(out, 0, ENT_HDR + 32 * G);
-    uint16_t f[4][512];
-    uint32_t c[4][512];
-    for (int p = 0; p < 4; p++) {
-        int64_t h[512] = {0};
+    const int64_t D = hdr_bytes(flags);
+    const int NT = n_tables(flags);
+    if (cap < oracle_ent_bound(H, W, log2_k, flags)) return -2;
+    memset(out, 0, D + 32 * G);
+    int64_t h[3 * ENT_NCTX + 1][512];
+    uint16_t f[3 * ENT_NCTX + 1][512];
+    uint32_t c[3 * ENT_NCTX + 1][512];
+    memset(h, 0, sizeof h);
+    memset(f, 0, sizeof f);
+    for (int p = 0; p < 4; p++)
         for (int64_t i = 0; i < N; i++) {
             int s = plane_sym(resid, N, W, flags, p, i);
             if (s < 0) return -3;
-            h[s]++;
+            h[table_of(sdr, flags, p, i)][s]++;
         }
-        memset(f[p], 0, sizeof f[p]);
-        if (oracle_ent_freqs(h, ENT_NSYM[p], f[p])) return -1;
+    for (int t = 0; t < NT; t++) {
+        int64_t n = 0;
+        for (int s = 0; s < 512; s++) n += h[t][s];
+        if (n && oracle_ent_freqs(h[t], table_nsym(flags, t), f[t])) return -1;
         uint32_t run = 0;
         for (int s = 0; s < 512; s++) {
-            c[p][s] = run;
-            run += f[p][s];
-            put16(out + 40 + 2 * (512 * p + s), f[p][s]);
+            c[t][s] = run;
+            run += f[t][s];
+            put16(out + 40 + 2 * (512 * t + s), f[t][s]);
         }
     }
     uint16_t *emit = (uint16_t *)malloc(sizeof(uint16_t) * (size_t)(Z + 128));
     if (!emit) return -4;
-    uint8_t *payload = out + ENT_HDR + 32 * G;
+    uint8_t *payload = out + D + 32 * G;
     int64_t words = 0;
     for (int p = 0; p < 4; p++) {
         for (int64_t g = 0; g < G; g++) {
@@ -166,25 +203,26 @@ int64_t oracle_ent_encode(const void *resid_v, int H, int W, int log2_k, int fla
                     const int64_t i = t * 64 + j;
                     if (i >= n) continue;
                     const int s = plane_sym(resid, N, W, flags, p, base + i);
-                    const uint32_t fs = f[p][s];
+                    const int tb = table_of(sdr, flags, p, base + i);
+                    const uint32_t fs = f[tb][s];
                     if ((uint64_t)x[j] >= ((uint64_t)fs << 17)) {
                         emit[ne++] = (uint16_t)(x[j] & 0xFFFF);
                         x[j] >>= 16;
                     }
-                    x[j] = (x[j] / fs) * ENT_M + (x[j] % fs) + c[p][s];
+                    x[j] = (x[j] / fs) * ENT_M + (x[j] % fs) + c[tb][s];
                 }
             }
             for (int j = 63; j >= 0; j--) {
                 emit[ne++] = (uint16_t)(x[j] & 0xFFFF);
                 emit[ne++] = (uint16_t)(x[j] >> 16);
             }
-            put64(out + ENT_HDR + 8 * (p * G + g), (uint64_t)words);
+            put64(out + D + 8 * (p * G + g), (uint64_t)words);
             for (int64_t k = 0; k < ne; k++) put16(payload + 2 * (words + k), emit[ne - 1 - k]);
             words += ne;
         }
     }
     free(emit);
-    const int64_t total = ENT_HDR + 32 * G + 2 * words;
+    const int64_t total = D + 32 * G + 2 * words;
     put32(out + 0, ENT_MAGIC);
     put32(out + 4, 1);
     put32(out + 8, (uint32_t)H);
@@ -197,41 +235,48 @@ int64_t oracle_ent_encode(const void *resid_v, int H, int W, int log2_k, int fla
     return total;
 }
 
-/* Decode a stream into resid (7 H W bytes).  Returns 0, or a negative code:
- * -1 bad arguments, -5 header mismatch, -6 corrupt group data. */
-int oracle_ent_decode(const uint8_t *st, int64_t len, int H, int W, void *resid_v)
+/* Decode a stream into resid (7 H W bytes); sdr (the decoded base layer)
+ * is needed when the stream has flags bit 1.  Returns 0, or a negative code:
+ * -1 bad arguments, -5 header mismatch, -6 corrupt group data (including a
+ * symbol whose context table is empty). */
+int oracle_ent_decode(const uint8_t *st, int64_t len, const uint8_t *sdr, int H, int W, void *resid_v)
 {
     uint8_t *resid = (uint8_t *)resid_v;
-    if (!st || !resid || H < 1 || W < 1 || len < ENT_HDR) return -1;
+    if (!st || !resid || H < 1 || W < 1 || len < 40) return -1;
     const int log2_k = (int)get32(st + 16);
     if (get32(st) != ENT_MAGIC || get32(st + 4) != 1 || (int)get32(st + 8) != H || (int)get32(st + 12) != W ||
         log2_k < 4 || log2_k > 12 || get32(st + 20) != ENT_PB)
         return -5;
+    const uint32_t flags = get32(st + 28);
+    if (flags > 3) return -5;
+    if ((flags & 2) && !sdr) return -1;
+    const int64_t D = hdr_bytes((int)flags);
+    const int NT = n_tables((int)flags);
+    if (len < D) return -5;
     const int64_t N = (int64_t)H * W, Z = (int64_t)64 << log2_k, G = oracle_ent_groups(H, W, log2_k);
     const int64_t total = (int64_t)get64(st + 32);
-    if (get32(st + 24) != (uint32_t)G || total > len || total < ENT_HDR + 32 * G || (total - ENT_HDR - 32 * G) % 2)
+    if (get32(st + 24) != (uint32_t)G || total > len || total < D + 32 * G || (total - D - 32 * G) % 2)
         return -5;
-    const uint32_t flags = get32(st + 28);
-    if (flags > 1) return -5;
-    const int64_t nwords = (total - ENT_HDR - 32 * G) / 2;
-    uint32_t f[4][512], c[4][513];
-    for (int p = 0; p < 4; p++) {
+    const int64_t nwords = (total - D - 32 * G) / 2;
+    uint32_t f[3 * ENT_NCTX + 1][512], c[3 * ENT_NCTX + 1][513];
+    for (int t = 0; t < NT; t++) {
         uint32_t run = 0;
         for (int s = 0; s < 512; s++) {
-            f[p][s] = get16(st + 40 + 2 * (512 * p + s));
-            if (s >= ENT_NSYM[p] && f[p][s]) return -5;
-            c[p][s] = run;
-            run += f[p][s];
+            f[t][s] = get16(st + 40 + 2 * (512 * t + s));
+            if (s >= table_nsym((int)flags, t) && f[t][s]) return -5;
+            c[t][s] = run;
+            run += f[t][s];
         }
-        c[p][512] = run;
-        if (run != ENT_M) return -5;
+        c[t][512] = run;
+        /* the exponents' table is always used; a context table may be empty */
+        if (run != ENT_M && !(run == 0 && t < NT - 1 && (flags & 2))) return -5;
     }
-    const uint8_t *payload = st + ENT_HDR + 32 * G;
+    const uint8_t *payload = st + D + 32 * G;
     for (int p = 0; p < 4; p++) {
         for (int64_t g = 0; g < G; g++) {
             const int64_t k = p * G + g;
-            const int64_t w0 = (int64_t)get64(st + ENT_HDR + 8 * k);
-            const int64_t w1 = k + 1 < 4 * G ? (int64_t)get64(st + ENT_HDR + 8 * (k + 1)) : nwords;
+            const int64_t w0 = (int64_t)get64(st + D + 8 * k);
+            const int64_t w1 = k + 1 < 4 * G ? (int64_t)get64(st + D + 8 * (k + 1)) : nwords;
             if (w0 < 0 || w1 > nwords || w1 - w0 < 128) return -6;
             const int64_t base = g * Z, n = (N - base < Z) ? N - base : Z, T = (n + 63) / 64;
             int64_t pos = w0;
@@ -244,10 +289,12 @@ int oracle_ent_decode(const uint8_t *st, int64_t len, int H, int W, void *resid_
                 for (int j = 0; j < 64; j++) {
                     const int64_t i = t * 64 + j;
                     if (i >= n) continue;
+                    const int tb = table_of(sdr, (int)flags, p, base + i);
+                    if (c[tb][512] != ENT_M) return -6;
                     const uint32_t slot = x[j] % ENT_M;
                     int s = 0;
-                    while (c[p][s + 1] <= slot) s++;
-                    x[j] = f[p][s] * (x[j] / ENT_M) + slot - c[p][s];
+                    while (c[tb][s + 1] <= slot) s++;
+                    x[j] = f[tb][s] * (x[j] / ENT_M) + slot - c[tb][s];
                     if (x[j] < ENT_L) {
                         if (pos >= w1) return -6;
                         x[j] = x[j] << 16 | get16(payload + 2 * pos);

@@ -248,9 +248,13 @@ def test_rejects_out_of_range_and_corrupt_streams(O):
     with pytest.raises(ValueError, match="-5"):
         O.ent_decode(bytes(st), 40, 31)
     bad = bytearray(st)
-    bad[28] = 2  # unknown flag
+    bad[28] = 4  # unknown flag
     with pytest.raises(ValueError, match="-5"):
         O.ent_decode(bytes(bad), 40, 30)
+    bad = bytearray(st)
+    bad[28] = 3  # the context flag on a stream without context tables (too short for their header)
+    with pytest.raises(ValueError, match="-5"):
+        O.ent_decode(bytes(bad), 40, 30, sdr=np.zeros((40, 30, 3), np.uint8))
     bad = bytearray(st)
     bad[40 + 2 * 300] ^= 1  # frequencies no longer sum to 2^15
     with pytest.raises(ValueError, match="-5"):
