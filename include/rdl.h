@@ -361,6 +361,33 @@ int rdl_ent_decode(rdl_ctx *ctx, const void *code, size_t len, const void *heade
                    void *out_resid, int32_t *status, void *stream);
 int rdl_set_ent_predict(rdl_ctx *ctx, int on);
 
+/* Residual contexts (stream flags bit 1; an extension like the coder
+ * itself).  The residual of channel p at pixel i is coded with the table of
+ * its context k = sdr[3 i + p] >> 5 (k = 0..7), sdr being the decoded base
+ * layer (the encoder's out_sdr, H x W x 3 bytes, channel-interleaved), which
+ * a decoder holds before it reads this layer: the residuals' spread follows
+ * where the tone curve put the pixel, so 8 tables per channel fit it better
+ * than one.  Symbols stay in the same groups and lanes; only the table of
+ * each symbol changes.  The stream is the format above with T = 25 tables in
+ * place of 4: u16 freq[25][512] at byte 40 (channel p, context k at table
+ * 8 p + k; the exponents' at 24; a table whose context no pixel has is all
+ * zero, the others sum to M, with N = the symbols coded with that table in
+ * the frequency rule), so the group table starts at RDL_ENT_CTX_HEADER_BYTES.
+ * The encoder's exponent plane follows rdl_set_ent_predict as above.
+ * rdl_ent_encode_ctx / rdl_ent_decode_ctx take the same arguments as
+ * rdl_ent_encode / rdl_ent_decode plus sdr (device, 3 H W bytes; RDL_EINVAL
+ * if NULL), and the decoder's header copy holds RDL_ENT_CTX_HEADER_BYTES
+ * bytes; each decoder rejects the other's streams (RDL_ECORRUPT), and a
+ * symbol whose context table is empty (a decode against another sdr) sets
+ * *status = RDL_ECORRUPT.  The larger header (21.5 KB more) pays for itself
+ * above about 0.3 Mpx. */
+#define RDL_ENT_CTX_HEADER_BYTES 25640
+size_t rdl_ent_bound_ctx(int H, int W, int log2_k);
+int rdl_ent_encode_ctx(rdl_ctx *ctx, const void *resid, const uint8_t *sdr, int H, int W, int log2_k, void *out,
+                       size_t cap, uint64_t *out_len, void *stream);
+int rdl_ent_decode_ctx(rdl_ctx *ctx, const void *code, size_t len, const void *header, const uint8_t *sdr, int H,
+                       int W, void *out_resid, int32_t *status, void *stream);
+
 /* ---- Stage entry points (each is one step of rdl_encode_enh, for checks) ---- */
 
 /* Key statistic (Sec. IV, Reinhard's operator needs the log-average

@@ -158,6 +158,8 @@ EntArgs ent_args(rdl_ctx *c, int H, int W, int log2_k) {
     a.W = W;
     a.log2_k = log2_k;
     a.G = (int32_t)G;
+    a.ntab = 4;
+    a.hdr = ENT_HDR;
     return a;
 }
 
@@ -780,16 +782,21 @@ int rdl_resid_hist(rdl_ctx *c, const void *resid, int H, int W, int64_t *hist, v
     return check_launch("k_hist");
 }
 
-size_t rdl_ent_bound(int H, int W, int log2_k) {
+}  // extern "C"
+
+namespace {
+
+size_t ent_bound_hdr(int H, int W, int log2_k, int hdr) {
     if (!size_ok(H, W) || log2_k < 4 || log2_k > 12) return 0;
     const int64_t G = ent_groups(H, W, log2_k), N = (int64_t)H * W;
-    return (size_t)(ENT_HDR + 32 * G + 2 * (4 * N + 4 * G * 128));
+    return (size_t)(hdr + 32 * G + 2 * (4 * N + 4 * G * 128));
 }
 
-int rdl_ent_encode(rdl_ctx *c, const void *resid, int H, int W, int log2_k, void *out, size_t cap,
-                   uint64_t *out_len, void *stream) {
+int ent_encode_impl(rdl_ctx *c, const void *resid, const uint8_t *sdr, int H, int W, int log2_k, void *out,
+                    size_t cap, uint64_t *out_len, void *stream) {
     if (!c || !resid || !out || !out_len || !size_ok(H, W) || log2_k < 4 || log2_k > 12) return RDL_EINVAL;
-    if (cap < rdl_ent_bound(H, W, log2_k)) return RDL_EINVAL;
+    const int hdr = sdr ? ENT_HDR_CTX : ENT_HDR;
+    if (cap < ent_bound_hdr(H, W, log2_k, hdr)) return RDL_EINVAL;
     if ((reinterpret_cast<uintptr_t>(resid) & 1) || (reinterpret_cast<uintptr_t>(out) & 7) ||
         (reinterpret_cast<uintptr_t>(out_len) & 7))
         return RDL_EINVAL;
@@ -800,15 +807,21 @@ int rdl_ent_encode(rdl_ctx *c, const void *resid, int H, int W, int log2_k, void
     a.resid = (const uint8_t *)resid;
     a.out = (uint8_t *)out;
     a.out_len = out_len;
-    a.flags = c->ent_pred ? 1 : 0;
+    a.flags = (c->ent_pred ? 1 : 0) | (sdr ? 2 : 0);
+    a.sdr = sdr;
+    a.ntab = sdr ? ENT_NTAB_CTX : 4;
+    a.hdr = hdr;
     a.ediff = c->d_ent + ent_ediff_off(H, W, log2_k) + ((reinterpret_cast<uintptr_t>(resid) + 6 * a.N) & 15);
-    a.eplane = a.flags ? a.ediff : a.resid + 6 * a.N;
+    a.eplane = (a.flags & 1) ? a.ediff : a.resid + 6 * a.N;
     launch_ent_encode(a, (hipStream_t)stream);
     return check_launch("k_ent_encode");
 }
 
-int rdl_ent_decode(rdl_ctx *c, const void *code, size_t len, const void *header, int H, int W, void *out_resid,
-                   int32_t *status, void *stream) {
+// Host-side check of a stream header (the fixed words and the frequency
+// tables), then the decode; ctx: the caller passed the decoded base layer and
+// expects a stream with residual contexts.
+int ent_decode_impl(rdl_ctx *c, const void *code, size_t len, const void *header, const uint8_t *sdr, int H, int W,
+                    void *out_resid, int32_t *status, void *stream) {
     if (!c || !code || !header || !out_resid || !size_ok(H, W)) return RDL_EINVAL;
     if ((reinterpret_cast<uintptr_t>(code) & 7) || (reinterpret_cast<uintptr_t>(out_resid) & 1)) return RDL_EINVAL;
     const uint8_t *h = (const uint8_t *)header;
@@ -820,30 +833,38 @@ int rdl_ent_decode(rdl_ctx *c, const void *code, size_t len, const void *header,
     if (w[0] != 0x454C4452u || w[1] != 1u || (int)w[2] != H || (int)w[3] != W || log2_k < 4 || log2_k > 12 ||
         w[5] != (uint32_t)ENT_PB)
         return RDL_ECORRUPT;
+    const bool ctx = sdr != nullptr;
+    if (w[7] > 3u || ((w[7] & 2u) != 0) != ctx) return RDL_ECORRUPT;
+    const int ntab = ctx ? ENT_NTAB_CTX : 4, hdr = ctx ? ENT_HDR_CTX : ENT_HDR;
     const int64_t G = ent_groups(H, W, log2_k);
-    const uint64_t fixed = (uint64_t)ENT_HDR + 32 * (uint64_t)G;
-    if (w[6] != (uint32_t)G || w[7] > 1u || total < fixed || total > len || (total - fixed) % 2) return RDL_ECORRUPT;
-    for (int p = 0; p < 4; ++p) {
+    const uint64_t fixed = (uint64_t)hdr + 32 * (uint64_t)G;
+    if (w[6] != (uint32_t)G || total < fixed || total > len || (total - fixed) % 2) return RDL_ECORRUPT;
+    for (int t = 0; t < ntab; ++t) {
         uint32_t sum = 0;
         for (int s = 0; s < 512; ++s) {
             uint16_t f;
-            memcpy(&f, h + 40 + 2 * (512 * p + s), 2);
-            if (f && s >= (p < 3 ? 511 : 256)) return RDL_ECORRUPT;
+            memcpy(&f, h + 40 + 2 * (512 * t + s), 2);
+            if (f && s >= (t < ntab - 1 ? 511 : 256)) return RDL_ECORRUPT;
             sum += f;
         }
-        if (sum != ENT_M) return RDL_ECORRUPT;
+        // a context table no pixel uses is empty; the exponents' table is always used
+        if (sum != ENT_M && !(ctx && sum == 0 && t < ntab - 1)) return RDL_ECORRUPT;
     }
     DeviceGuard g(c->device);
-    if (w[7]) {
+    if (w[7] & 1u) {
         const int rc = ensure_ent(c, ent_dec_ws_bytes((int64_t)H * W));
         if (rc) return rc;
     }
     EntArgs a = ent_args(c, H, W, log2_k);
     a.flags = (int32_t)w[7];
+    a.sdr = sdr;
+    a.ntab = ntab;
+    a.hdr = hdr;
     a.eagg = reinterpret_cast<uint32_t *>(c->d_ent + ent_cnt_off());
     {
         uint8_t *e = (uint8_t *)out_resid + 6 * (int64_t)H * W;
-        a.dplane = a.flags ? c->d_ent + ent_dplane_off((int64_t)H * W) + (reinterpret_cast<uintptr_t>(e) & 15) : e;
+        a.dplane = (a.flags & 1) ? c->d_ent + ent_dplane_off((int64_t)H * W) + (reinterpret_cast<uintptr_t>(e) & 15)
+                                 : e;
     }
     a.code = (const uint8_t *)code;
     a.dst = (uint8_t *)out_resid;
@@ -851,6 +872,36 @@ int rdl_ent_decode(rdl_ctx *c, const void *code, size_t len, const void *header,
     a.nwords = (int64_t)((total - fixed) / 2);
     launch_ent_decode(a, (hipStream_t)stream);
     return check_launch("k_ent_decode");
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t rdl_ent_bound(int H, int W, int log2_k) { return ent_bound_hdr(H, W, log2_k, ENT_HDR); }
+
+size_t rdl_ent_bound_ctx(int H, int W, int log2_k) { return ent_bound_hdr(H, W, log2_k, ENT_HDR_CTX); }
+
+int rdl_ent_encode(rdl_ctx *c, const void *resid, int H, int W, int log2_k, void *out, size_t cap,
+                   uint64_t *out_len, void *stream) {
+    return ent_encode_impl(c, resid, nullptr, H, W, log2_k, out, cap, out_len, stream);
+}
+
+int rdl_ent_encode_ctx(rdl_ctx *c, const void *resid, const uint8_t *sdr, int H, int W, int log2_k, void *out,
+                       size_t cap, uint64_t *out_len, void *stream) {
+    if (!sdr) return RDL_EINVAL;
+    return ent_encode_impl(c, resid, sdr, H, W, log2_k, out, cap, out_len, stream);
+}
+
+int rdl_ent_decode(rdl_ctx *c, const void *code, size_t len, const void *header, int H, int W, void *out_resid,
+                   int32_t *status, void *stream) {
+    return ent_decode_impl(c, code, len, header, nullptr, H, W, out_resid, status, stream);
+}
+
+int rdl_ent_decode_ctx(rdl_ctx *c, const void *code, size_t len, const void *header, const uint8_t *sdr, int H, int W,
+                       void *out_resid, int32_t *status, void *stream) {
+    if (!sdr) return RDL_EINVAL;
+    return ent_decode_impl(c, code, len, header, sdr, H, W, out_resid, status, stream);
 }
 
 size_t rdl_jpeg_bound(int H, int W) {

@@ -275,15 +275,76 @@ __global__ __launch_bounds__(ENT_HIST_THREADS) void k_ent_hist_vec(EntArgs a, in
     }
 }
 
-// Frequencies of plane blockIdx.x (512 threads, one per symbol):
-// f = 1 + floor(h (M - P) / N) for the P present symbols, the remainder to
-// the smallest symbol of the largest count; c = exclusive prefix sum.  Writes
-// the stream's frequency table and the encoder's table, clears the histogram;
-// plane 0's workgroup writes the fixed header words.
+// Histograms of a stream with residual contexts: workgroup (x, p) counts
+// ENT_HIST_PX symbols of plane p.  A residual plane's counts go to its 8
+// context tables (bin (S >> 5) 512 + r + 255, 8 x 512 bins in ENT_HC
+// copies); plane 3 counts the exponent symbols' runs as k_ent_hist does.
+__global__ __launch_bounds__(ENT_HIST_THREADS) void k_ent_hist_ctx(EntArgs a) {
+    __shared__ uint32_t h[ENT_NCTX * 512 * ENT_HC];
+    static_assert(ENT_CMINOR && !ENT_PACK16, "k_ent_hist_ctx: one 32-bit counter per bin and copy");
+    for (int k = threadIdx.x; k < ENT_NCTX * 512 * ENT_HC; k += ENT_HIST_THREADS) h[k] = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, p = blockIdx.y;
+    const uint32_t mine = (uint32_t)lane & (ENT_HC - 1);
+    const int64_t i0 = (int64_t)blockIdx.x * ENT_HIST_PX;
+    const int n = (int)(a.N - i0 < ENT_HIST_PX ? a.N - i0 : ENT_HIST_PX);
+    constexpr int PER = ENT_HIST_PX / ENT_HIST_THREADS;  // 32 px per thread
+    if (p < 3) {
+        const int16_t *rp = (const int16_t *)a.resid + p * a.N + i0;
+        const uint8_t *cp = a.sdr + 3 * i0 + p;
+        int v[PER];
+        uint32_t cx[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int i = min(j * ENT_HIST_THREADS + (int)threadIdx.x, n - 1);  // clamped: every load valid
+            v[j] = (int)rp[i];
+            cx[j] = (uint32_t)cp[3 * i] >> 5;
+        }
+#pragma unroll
+        for (int j = 0; j < PER; ++j)
+            if (j * ENT_HIST_THREADS + (int)threadIdx.x < n)
+                ent_count(h, mine, cx[j] * 512 + min((uint32_t)(v[j] + 255), 511u), 1u);
+    } else {
+        const uint8_t *e8 = a.eplane + i0;
+        int ev[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int i = j * ENT_HIST_THREADS + threadIdx.x;
+            const int v = (int)e8[min(i, n - 1)];
+            ev[j] = i < n ? v : -1;
+        }
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int v = ev[j];
+            const int left = __shfl_up(v, 1, 64);
+            const bool head = lane == 0 || v != left;
+            const unsigned long long m = __ballot(head);
+            const unsigned long long after = lane == 63 ? 0ull : m >> (lane + 1);
+            const int len = after ? (int)__builtin_ctzll(after) + 1 : 64 - lane;
+            if (head && v >= 0) ent_count(h, mine, (uint32_t)v, (uint32_t)len);
+        }
+    }
+    __syncthreads();
+    const int t0 = p < 3 ? ENT_NCTX * p : ENT_NTAB_CTX - 1, nb = p < 3 ? ENT_NCTX * 512 : 512;
+    for (int b = threadIdx.x; b < nb; b += ENT_HIST_THREADS) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int k = 0; k < ENT_HC; ++k) v += h[ent_word(k, b)];
+        if (v) atomicAdd(&a.ws->hist[blockIdx.x % ENT_HSTRIPES][t0 + (b >> 9)][b & 511], v);
+    }
+}
+
+// Frequencies of table blockIdx.x (512 threads, one per symbol):
+// f = 1 + floor(h (M - P) / N) for the P present symbols, N their total
+// count, the remainder to the smallest symbol of the largest count;
+// c = exclusive prefix sum.  A table with no symbol (a context no pixel
+// falls in) stays all zero.  Writes the stream's frequency table and the
+// encoder's table, clears the histogram; table 0's workgroup writes the fixed
+// header words.  The last table is the exponents' (256 symbols).
 __global__ __launch_bounds__(512) void k_ent_freq(EntArgs a) {
     __shared__ uint32_t sh[8];
     __shared__ unsigned long long shm[8];
-    const int p = blockIdx.x, s = threadIdx.x, nsym = p < 3 ? 511 : 256;
+    const int p = blockIdx.x, s = threadIdx.x, nsym = p < a.ntab - 1 ? 511 : 256;
     uint32_t h = 0;
 #pragma unroll
     for (int k = 0; k < ENT_HSTRIPES; ++k) {
@@ -293,7 +354,8 @@ __global__ __launch_bounds__(512) void k_ent_freq(EntArgs a) {
     const bool pres = s < nsym && h > 0;
     const uint32_t nbad = block_sum<8>(s >= nsym && h > 0 ? 1u : 0u, sh);
     const uint32_t P = block_sum<8>(pres ? 1u : 0u, sh);
-    uint32_t f = pres ? 1u + (uint32_t)(((uint64_t)h * (ENT_M - P)) / (uint64_t)a.N) : 0u;
+    const uint32_t ntot = block_sum<8>(pres ? h : 0u, sh);  // <= N < 2^31
+    uint32_t f = pres ? 1u + (uint32_t)(((uint64_t)h * (ENT_M - P)) / (uint64_t)ntot) : 0u;
     const uint32_t sum = block_sum<8>(f, sh);
     const unsigned long long key = pres ? ((unsigned long long)h << 16 | (0xFFFFu - (uint32_t)s)) : 0ull;
     const unsigned long long best = block_max64<8>(key, shm);
@@ -329,10 +391,12 @@ __global__ __launch_bounds__(512) void k_ent_freq(EntArgs a) {
 // estimate is x div f or one less and one upward correction makes it exact.
 // Finally every
 // lane's state, lanes 63 down to 0, low half first.  RES: a residual plane
-// (int16 values, symbol r + 255), else the exponent plane (bytes).
-template <bool RES, typename V>
-__device__ __forceinline__ void enc_group(const V *src, int n, const uint2 *tb, uint16_t *out, uint32_t *cnt_out,
-                                          int lane, uint32_t dummy) {
+// (int16 values, symbol r + 255), else the exponent plane (bytes).  CTX: the
+// table of symbol i is its context ctx[3 i] >> 5 (the base layer's byte of the
+// plane's channel), entry (context << 9) + symbol of tb.
+template <bool RES, bool CTX, typename V>
+__device__ __forceinline__ void enc_group(const V *src, const uint8_t *ctx, int n, const uint2 *tb, uint16_t *out,
+                                          uint32_t *cnt_out, int lane, uint32_t dummy) {
     const int T = (n + 63) >> 6;
     const int tfull = (n >> 6) - 1;  // steps 0..tfull hold a symbol in every lane
     // Symbols of steps t0, t0 - 1, ..., t0 - 7 and a mask of the lane's valid
@@ -341,18 +405,24 @@ __device__ __forceinline__ void enc_group(const V *src, int n, const uint2 *tb, 
     // next block's loads are issued before the current block is coded.  Steps
     // before the first (t < 0) have no symbol in any lane and change nothing.
     auto sym_of = [](int v) -> uint32_t { return RES ? min((uint32_t)(v + 255), 511u) : (uint32_t)v; };
+    auto tab_of = [](uint32_t sdr_byte) -> uint32_t { return CTX ? (sdr_byte >> 5) << 9 : 0u; };
     auto load_block = [&](int t0, uint32_t (&sv)[8]) -> uint32_t {
         if (t0 - 7 >= 0 && t0 <= tfull) {  // whole block inside the group: fixed offsets
             const V *q = src + t0 * 64 + lane;
 #pragma unroll
             for (int k = 0; k < 8; ++k) sv[k] = sym_of((int)q[-64 * k]);
+            if (CTX) {
+                const uint8_t *qc = ctx + 3 * (t0 * 64 + lane);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) sv[k] |= tab_of(qc[-192 * k]);
+            }
             return 0xFFu;
         }
         uint32_t vm = 0;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const int t = t0 - k, i = t * 64 + lane;
-            sv[k] = sym_of((int)src[min(max(i, 0), n - 1)]);
+            const int t = t0 - k, i = t * 64 + lane, ic = min(max(i, 0), n - 1);
+            sv[k] = sym_of((int)src[ic]) | (CTX ? tab_of(ctx[3 * ic]) : 0u);
             vm |= (t >= 0 && i < n ? 1u : 0u) << k;
         }
         return vm;
@@ -425,9 +495,39 @@ __global__ __launch_bounds__(256) void k_ent_enc(EntArgs a) {
     uint16_t *out = a.tmp + gi * ent_slot(a.log2_k);
     const uint32_t dummy = (uint32_t)(Z + 128 + lane);
     if (p < 3)
-        enc_group<true>((const int16_t *)a.resid + p * a.N + base, n, stab[w], out, a.cnt + gi, lane, dummy);
+        enc_group<true, false>((const int16_t *)a.resid + p * a.N + base, nullptr, n, stab[w], out, a.cnt + gi, lane,
+                               dummy);
     else
-        enc_group<false>(a.eplane + base, n, stab[w], out, a.cnt + gi, lane, dummy);
+        enc_group<false, false>(a.eplane + base, nullptr, n, stab[w], out, a.cnt + gi, lane, dummy);
+}
+
+// Encoder with residual contexts: the groups of plane blockIdx.y, four per
+// workgroup, which holds the plane's tables (8 contexts x 512 entries for a
+// residual plane, the exponents' one table for plane 3).
+__global__ __launch_bounds__(256) void k_ent_enc_ctx(EntArgs a) {
+    __shared__ uint2 stab[ENT_NCTX * 512];
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int p = blockIdx.y, G = a.G, g = blockIdx.x * 4 + w;
+    const int t0 = p < 3 ? ENT_NCTX * p : ENT_NTAB_CTX - 1, nt = p < 3 ? ENT_NCTX : 1;
+    for (int k = threadIdx.x; k < nt * 512; k += 256) stab[k] = a.ws->tab[t0 + (k >> 9)][k & 511];
+    uint32_t bad = 0;
+    for (int k = 0; k < nt; ++k) bad |= a.ws->bad[t0 + k];
+    __syncthreads();
+    if (g >= G) return;
+    const int64_t gi = (int64_t)p * G + g;
+    if (bad) {
+        if (lane == 0) a.cnt[gi] = 0;
+        return;
+    }
+    const int64_t Z = (int64_t)64 << a.log2_k, base = (int64_t)g * Z;
+    const int n = (int)(a.N - base < Z ? a.N - base : Z);
+    uint16_t *out = a.tmp + gi * ent_slot(a.log2_k);
+    const uint32_t dummy = (uint32_t)(Z + 128 + lane);
+    if (p < 3)
+        enc_group<true, true>((const int16_t *)a.resid + p * a.N + base, a.sdr + 3 * base + p, n, stab, out,
+                              a.cnt + gi, lane, dummy);
+    else
+        enc_group<false, false>(a.eplane + base, nullptr, n, stab, out, a.cnt + gi, lane, dummy);
 }
 
 // Group offsets (exclusive prefix sum of the word counts) into the stream's
@@ -435,9 +535,11 @@ __global__ __launch_bounds__(256) void k_ent_enc(EntArgs a) {
 // (a residual outside [-255, 255]) yields magic 0 and length 0.
 __global__ __launch_bounds__(1024) void k_ent_scan(EntArgs a) {
     __shared__ uint32_t sh[16];
-    const bool ok = (a.ws->bad[0] | a.ws->bad[1] | a.ws->bad[2] | a.ws->bad[3]) == 0;
+    uint32_t anybad = 0;
+    for (int t = 0; t < a.ntab; ++t) anybad |= a.ws->bad[t];
+    const bool ok = anybad == 0;
     const int64_t n = 4 * (int64_t)a.G;
-    uint64_t *start = reinterpret_cast<uint64_t *>(a.out + ENT_HDR);
+    uint64_t *start = reinterpret_cast<uint64_t *>(a.out + a.hdr);
     uint64_t carry = 0;
     for (int64_t b = 0; b < n; b += 1024) {
         const int64_t k = b + threadIdx.x;
@@ -448,7 +550,7 @@ __global__ __launch_bounds__(1024) void k_ent_scan(EntArgs a) {
         carry += tot;
     }
     if (threadIdx.x == 0) {
-        const uint64_t total = (uint64_t)ENT_HDR + 32 * (uint64_t)a.G + 2 * carry;
+        const uint64_t total = (uint64_t)a.hdr + 32 * (uint64_t)a.G + 2 * carry;
         reinterpret_cast<uint64_t *>(a.out)[4] = ok ? total : 0ull;
         if (!ok) reinterpret_cast<uint32_t *>(a.out)[0] = 0u;
         *a.out_len = ok ? total : 0ull;
@@ -461,9 +563,9 @@ __global__ __launch_bounds__(256) void k_ent_pack(EntArgs a) {
     if (!a.ws->ok) return;
     const int64_t gi = blockIdx.x;
     const uint32_t n = a.cnt[gi];
-    const uint64_t st = reinterpret_cast<const uint64_t *>(a.out + ENT_HDR)[gi];
+    const uint64_t st = reinterpret_cast<const uint64_t *>(a.out + a.hdr)[gi];
     const uint16_t *__restrict__ src = a.tmp + gi * ent_slot(a.log2_k);
-    uint16_t *__restrict__ dst = reinterpret_cast<uint16_t *>(a.out + ENT_HDR + 32 * (int64_t)a.G) + st;
+    uint16_t *__restrict__ dst = reinterpret_cast<uint16_t *>(a.out + a.hdr + 32 * (int64_t)a.G) + st;
     // 8 loads in flight per lane (indices clamped: a group has n >= 128 words)
     for (uint32_t k0 = 0; k0 < n; k0 += 8 * 256) {
         uint16_t v[8];
@@ -541,9 +643,10 @@ __global__ __launch_bounds__(256) void k_ent_dec(EntArgs a) {
     __shared__ uint16_t ring[ENT_DEC_WAVES][512];
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int G = a.G, gpp = (G + ENT_DEC_WAVES - 1) / ENT_DEC_WAVES;
-    const int p = blockIdx.x / gpp, g = (blockIdx.x % gpp) * ENT_DEC_WAVES + w;
-    const int nsym = p < 3 ? 511 : 256;
-    const uint32_t fw = reinterpret_cast<const uint32_t *>(a.code + 40 + 1024 * p)[threadIdx.x];
+    // with residual contexts only plane 3 comes here (k_ent_dec_ctx takes the others)
+    const int p = a.ntab == 4 ? blockIdx.x / gpp : 3, g = (blockIdx.x % gpp) * ENT_DEC_WAVES + w;
+    const int nsym = p < 3 ? 511 : 256, tix = p < 3 ? p : a.ntab - 1;
+    const uint32_t fw = reinterpret_cast<const uint32_t *>(a.code + 40 + 1024 * tix)[threadIdx.x];
     const uint32_t s0 = 2 * threadIdx.x, f0 = fw & 0xFFFFu, f1 = fw >> 16;
     uint32_t tot, P;
     const uint32_t c0 = block_excl_scan<4>(f0 + f1, sh, tot);
@@ -591,8 +694,8 @@ __global__ __launch_bounds__(256) void k_ent_dec(EntArgs a) {
     __syncthreads();
     if (g >= G) return;
     const int64_t gi = (int64_t)p * G + g;
-    const uint64_t *start = reinterpret_cast<const uint64_t *>(a.code + ENT_HDR);
-    const uint16_t *words = reinterpret_cast<const uint16_t *>(a.code + ENT_HDR + 32 * (int64_t)G);
+    const uint64_t *start = reinterpret_cast<const uint64_t *>(a.code + a.hdr);
+    const uint16_t *words = reinterpret_cast<const uint16_t *>(a.code + a.hdr + 32 * (int64_t)G);
     const uint64_t u0 = start[gi], u1 = gi + 1 < 4 * (int64_t)G ? start[gi + 1] : (uint64_t)a.nwords;
     // a group holds its 128 state words and at most one word per symbol
     if (!(u0 <= u1 && u1 <= (uint64_t)a.nwords && u1 - u0 >= 128 && u1 - u0 <= (uint64_t)ent_slot(a.log2_k))) {
@@ -627,6 +730,148 @@ __global__ __launch_bounds__(256) void k_ent_dec(EntArgs a) {
                               x, nw, ld, lane);
     else
         bad = dec_group<false>(a.dplane + base, n, dtab, slot_sym, rg, R, b, pos, x, nw, ld, lane);
+    if (__ballot(bad) && lane == 0 && a.status) atomicExch(a.status, RDL_ECORRUPT);
+}
+
+// Decoder of a residual plane with contexts: one group per wave, four groups
+// of plane blockIdx.y per workgroup.  The workgroup holds the plane's 8
+// context tables: the present symbols in order, {c | f << 16, symbol}, and per
+// table and bucket of 64 slots the index of the symbol holding the bucket's
+// first slot (the number of symbols with c <= 64 b, less one).  A step reads
+// its lanes' contexts (the base layer's bytes, loaded a block of 8 steps
+// ahead), takes slot = x mod M, and finds the symbol holding it by a binary
+// search between the bucket's entry and the next bucket's (at most 65
+// candidates, 7 halvings); the rest is dec_group's step.  A table that sums to
+// neither 0 nor M, a symbol 511, or a symbol whose context table is empty sets
+// *status = RDL_ECORRUPT.
+template <typename LD>
+__device__ __forceinline__ bool dec_group_ctx(int16_t *dst, const uint8_t *ctx, int n, const uint2 (*dtab)[512],
+                                              const uint16_t (*bk)[512], const uint32_t *np, uint16_t *rg,
+                                              uint32_t (&R)[4], uint32_t b, uint32_t pos, uint32_t x, uint32_t nw,
+                                              const LD &ld, int lane) {
+    bool bad = false;
+    auto load_ctx = [&](int t0, uint32_t (&cv)[8]) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int i = min((t0 + k) * 64 + lane, n - 1);  // clamped: every load valid
+            cv[k] = (uint32_t)ctx[3 * i] >> 5;
+        }
+    };
+    auto step = [&](int t, uint32_t k) {
+        if (pos >= b + 256) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) rg[(b + 512 + q * 64 + lane) & 511] = (uint16_t)R[q];
+            b += 256;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) R[q] = ld(b + 512 + q * 64 + lane);
+        }
+        const int i = t * 64 + lane;
+        const bool have = i < n;
+        const uint32_t slot = x & (ENT_M - 1), bb = slot >> 6, P = np[k];
+        bad = bad || (have && P == 0);
+        uint32_t lo = P ? bk[k][bb] : 0u, hi = P ? (bb < 511 ? bk[k][bb + 1] : P - 1) : 0u;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi + 1) >> 1;
+            if ((dtab[k][mid].x & 0xFFFFu) <= slot) lo = mid; else hi = mid - 1;
+        }
+        const uint2 e = dtab[k][lo];
+        const uint32_t xn = (e.x >> 16) * (x >> ENT_PB) + slot - (e.x & 0xFFFFu);
+        x = have ? xn : x;
+        const bool ren = have && x < ENT_L;
+        const uint64_t m = __builtin_amdgcn_ballot_w64(ren);
+        const uint32_t idx = pos + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        const bool inside = idx < nw;
+        const uint32_t wv = rg[idx & 511];
+        bad = bad || (ren && !inside);
+        x = ren ? x << 16 | (inside ? wv : 0u) : x;
+        pos += (uint32_t)__builtin_popcountll(m);
+        if (have) dst[i] = (int16_t)((int)e.y - 255);
+    };
+    const int T = (n + 63) >> 6;
+    uint32_t cur[8], nxt[8];
+    load_ctx(0, cur);
+    for (int t0 = 0; t0 < T; t0 += 8) {
+        load_ctx(t0 + 8, nxt);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (t0 + k < T) step(t0 + k, cur[k]);  // wave-uniform
+#pragma unroll
+        for (int k = 0; k < 8; ++k) cur[k] = nxt[k];
+    }
+    return bad || pos != nw || x != ENT_L;
+}
+
+__global__ __launch_bounds__(256) void k_ent_dec_ctx(EntArgs a) {
+    __shared__ uint2 dtab[ENT_NCTX][512];
+    __shared__ uint16_t bk[ENT_NCTX][512];
+    __shared__ uint32_t np[ENT_NCTX];
+    __shared__ uint32_t cntb[512];
+    __shared__ uint32_t sh[4];
+    __shared__ uint16_t ring[ENT_DEC_WAVES][512];
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int G = a.G, p = blockIdx.y, g = blockIdx.x * ENT_DEC_WAVES + w;
+    bool corrupt = false;
+    for (int k = 0; k < ENT_NCTX; ++k) {
+        cntb[2 * threadIdx.x] = 0;
+        cntb[2 * threadIdx.x + 1] = 0;
+        const uint32_t fw = reinterpret_cast<const uint32_t *>(a.code + 40 + 1024 * (ENT_NCTX * p + k))[threadIdx.x];
+        const uint32_t s0 = 2 * threadIdx.x, f0 = fw & 0xFFFFu, f1 = fw >> 16;
+        uint32_t tot, P;
+        const uint32_t c0 = block_excl_scan<4>(f0 + f1, sh, tot);  // its barriers also order the clears
+        const uint32_t j0 = block_excl_scan<4>((f0 > 0) + (f1 > 0), sh, P);
+        const uint32_t nbad = block_sum<4>(s0 + 1 >= 511 && f1 ? 1u : 0u, sh);
+        corrupt = corrupt || (tot != ENT_M && tot != 0) || nbad;  // uniform
+        const bool use = tot == ENT_M && !nbad;
+        if (use && f0) {
+            dtab[k][j0] = make_uint2(c0 | f0 << 16, s0);
+            if ((c0 + 63) >> 6 < 512) atomicAdd(&cntb[(c0 + 63) >> 6], 1u);
+        }
+        if (use && f1) {
+            const uint32_t c1 = c0 + f0;
+            dtab[k][j0 + (f0 > 0)] = make_uint2(c1 | f1 << 16, s0 + 1);
+            if ((c1 + 63) >> 6 < 512) atomicAdd(&cntb[(c1 + 63) >> 6], 1u);
+        }
+        if (threadIdx.x == 0) np[k] = use ? P : 0u;
+        __syncthreads();
+        const uint32_t b0 = cntb[2 * threadIdx.x], b1 = cntb[2 * threadIdx.x + 1];
+        uint32_t unused;
+        const uint32_t before = block_excl_scan<4>(b0 + b1, sh, unused);
+        // (the scan's barriers also keep the next table's clears after these reads)
+        bk[k][2 * threadIdx.x] = (uint16_t)(before + b0 - 1);
+        bk[k][2 * threadIdx.x + 1] = (uint16_t)(before + b0 + b1 - 1);
+    }
+    __syncthreads();
+    if (corrupt) {
+        if (threadIdx.x == 0 && a.status) atomicExch(a.status, RDL_ECORRUPT);
+        return;
+    }
+    if (g >= G) return;
+    const int64_t gi = (int64_t)p * G + g;
+    const uint64_t *start = reinterpret_cast<const uint64_t *>(a.code + a.hdr);
+    const uint16_t *words = reinterpret_cast<const uint16_t *>(a.code + a.hdr + 32 * (int64_t)G);
+    const uint64_t u0 = start[gi], u1 = gi + 1 < 4 * (int64_t)G ? start[gi + 1] : (uint64_t)a.nwords;
+    if (!(u0 <= u1 && u1 <= (uint64_t)a.nwords && u1 - u0 >= 128 && u1 - u0 <= (uint64_t)ent_slot(a.log2_k))) {
+        if (lane == 0 && a.status) atomicExch(a.status, RDL_ECORRUPT);
+        return;
+    }
+    const uint16_t *gw = words + u0;
+    const uint32_t nw = (uint32_t)(u1 - u0);
+    uint32_t x = (uint32_t)gw[2 * lane] << 16 | gw[2 * lane + 1];
+    uint16_t *rg = ring[w];
+    const uint32_t pos = 128, b = 128;
+    auto ld = [&](uint32_t q) -> uint32_t {
+        const uint32_t v = gw[q < nw ? q : nw - 1];  // clamped: nw - 1 >= 127
+        return q < nw ? v : 0u;
+    };
+#pragma unroll
+    for (int k = 0; k < 8; ++k) rg[(b + k * 64 + lane) & 511] = (uint16_t)ld(b + k * 64 + lane);
+    uint32_t R[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) R[k] = ld(b + 512 + k * 64 + lane);
+    const int64_t Z = (int64_t)64 << a.log2_k, base = (int64_t)g * Z;
+    const int n = (int)(a.N - base < Z ? a.N - base : Z);
+    const bool bad = dec_group_ctx(reinterpret_cast<int16_t *>(a.dst) + p * a.N + base, a.sdr + 3 * base + p, n,
+                                   dtab, bk, np, rg, R, b, pos, x, nw, ld, lane);
     if (__ballot(bad) && lane == 0 && a.status) atomicExch(a.status, RDL_ECORRUPT);
 }
 
@@ -811,6 +1056,15 @@ void launch_ent_encode(const EntArgs &a, hipStream_t s) {
         const int lead = (int)(reinterpret_cast<uintptr_t>(e) & 15);
         hipLaunchKernelGGL(k_ent_ediff, dim3((unsigned)ent_etiles(a.N, lead)), dim3(256), 0, s, e, a.ediff, a.N, a.W);
     }
+    if (a.flags & 2) {
+        hipLaunchKernelGGL(k_ent_hist_ctx, dim3((unsigned)((a.N + ENT_HIST_PX - 1) / ENT_HIST_PX), 4),
+                           dim3(ENT_HIST_THREADS), 0, s, a);
+        hipLaunchKernelGGL(k_ent_freq, dim3(ENT_NTAB_CTX), dim3(512), 0, s, a);
+        hipLaunchKernelGGL(k_ent_enc_ctx, dim3((unsigned)((a.G + 3) / 4), 4), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_ent_scan, dim3(1), dim3(1024), 0, s, a);
+        hipLaunchKernelGGL(k_ent_pack, dim3((unsigned)ng), dim3(256), 0, s, a);
+        return;
+    }
     if ((reinterpret_cast<uintptr_t>(a.resid) & 15) == 0 && a.N >= 16) {
         const int64_t nr = ((6 * a.N + 15) / 16 + ENT_VEC_SPAN / 16 - 1) / (ENT_VEC_SPAN / 16);
         const int64_t ne = (a.N + 16 + ENT_VEC_SPAN - 1) / ENT_VEC_SPAN;
@@ -828,7 +1082,12 @@ void launch_ent_encode(const EntArgs &a, hipStream_t s) {
 void launch_ent_decode(const EntArgs &a, hipStream_t s) {
     if (a.status) hipLaunchKernelGGL(k_ent_status, dim3(1), dim3(64), 0, s, a.status);
     const int gpp = (a.G + ENT_DEC_WAVES - 1) / ENT_DEC_WAVES;
-    hipLaunchKernelGGL(k_ent_dec, dim3((unsigned)(4 * gpp)), dim3(64 * ENT_DEC_WAVES), 0, s, a);
+    if (a.flags & 2) {
+        hipLaunchKernelGGL(k_ent_dec_ctx, dim3((unsigned)gpp, 3), dim3(64 * ENT_DEC_WAVES), 0, s, a);
+        hipLaunchKernelGGL(k_ent_dec, dim3((unsigned)gpp), dim3(64 * ENT_DEC_WAVES), 0, s, a);  // plane 3
+    } else {
+        hipLaunchKernelGGL(k_ent_dec, dim3((unsigned)(4 * gpp)), dim3(64 * ENT_DEC_WAVES), 0, s, a);
+    }
     if (a.flags & 1) {
         uint8_t *e = a.dst + 6 * a.N;
         const int64_t nt = ent_etiles(a.N, (int)(reinterpret_cast<uintptr_t>(e) & 15));

@@ -136,17 +136,20 @@ void launch_decode_learned(const ImgDesc *d, int n, int wgs, int rq, int tiles, 
 constexpr int ENT_PB = 15;                 // probability scale M = 2^15
 constexpr uint32_t ENT_M = 1u << ENT_PB;
 constexpr uint32_t ENT_L = 1u << 16;       // states lie in [2^16, 2^32)
-constexpr int ENT_HDR = 4136;              // fixed header bytes before the group table
+constexpr int ENT_HDR = 4136;              // fixed header bytes before the group table (4 tables)
+constexpr int ENT_NCTX = 8;                // residual contexts per channel (S >> 5)
+constexpr int ENT_NTAB_CTX = 3 * ENT_NCTX + 1;  // tables of a stream with contexts (the exponents' last)
+constexpr int ENT_HDR_CTX = 40 + 1024 * ENT_NTAB_CTX;  // 25640
 constexpr int ENT_HIST_PX = 16384;         // histogram workgroup: pixels per workgroup
 constexpr int ENT_DEC_WAVES = 4;           // decoder: groups (waves) per workgroup
 constexpr int ENT_HSTRIPES = 16;           // copies of the image's histograms (workgroup w adds
                                            //   into copy w mod 16, so hot bins take few atomics)
 struct EntWs {
-    uint32_t hist[ENT_HSTRIPES][4][512];  // plane histograms; zero between calls (k_ent_freq clears)
-    uint2 tab[4][512];      // encoder table: {f | c << 16, bits of fl(1/f)}
-    uint32_t bad[4];        // plane holds a residual outside [-255, 255]
-    uint32_t ok;            // the stream is valid (set by k_ent_scan)
-    uint32_t pad[3];
+    uint32_t hist[ENT_HSTRIPES][ENT_NTAB_CTX][512];  // table histograms; zero between calls (k_ent_freq clears)
+    uint2 tab[ENT_NTAB_CTX][512];  // encoder tables: {f | c << 16, bits of fl(1/f)}
+    uint32_t bad[ENT_NTAB_CTX];    // table counted a residual outside [-255, 255]
+    uint32_t ok;                   // the stream is valid (set by k_ent_scan)
+    uint32_t pad[2];
 };
 struct EntArgs {
     const uint8_t *resid;   // encoder input / decoder output: 7*H*W bytes
@@ -154,7 +157,10 @@ struct EntArgs {
     uint8_t *ediff;         // encoder: where the left differences go (workspace, 16-byte aligned)
     uint32_t *eagg;         // decoder: [2][tiles] segment values of the inverse (workspace)
     uint8_t *dplane;        // decoder: where plane 3's symbols go (the layer, or the workspace)
-    int32_t flags;          // bit 0: plane 3 holds left differences
+    int32_t flags;          // bit 0: plane 3 holds left differences; bit 1: residual contexts
+    const uint8_t *sdr;     // flags bit 1: the decoded base layer (H*W*3 bytes), the contexts
+    int32_t ntab;           // tables in the stream: 4, or ENT_NTAB_CTX with contexts
+    int32_t hdr;            // header bytes before the group table: ENT_HDR or ENT_HDR_CTX
     uint8_t *out;           // encoder: the code stream
     const uint8_t *code;    // decoder: the code stream
     uint8_t *dst;           // decoder: the enhancement layer

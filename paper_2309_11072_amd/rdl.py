@@ -40,6 +40,7 @@ EST_GF_OFF = 16
 
 #: Entropy code of the enhancement layer: fixed header bytes, default group size.
 ENT_HEADER_BYTES = 4136
+ENT_CTX_HEADER_BYTES = 25640  # with residual contexts (25 frequency tables)
 ENT_LOG2K_DEFAULT = 8
 
 # Exported symbols of include/rdl.h with their argument types.
@@ -63,6 +64,9 @@ _SIGS = {
     "rdl_ent_bound": ([_i, _i, _i], C.c_size_t),
     "rdl_ent_encode": ([_vp, _vp, _i, _i, _i, _vp, C.c_size_t, _vp, _vp], _i),
     "rdl_ent_decode": ([_vp, _vp, C.c_size_t, _vp, _i, _i, _vp, _vp, _vp], _i),
+    "rdl_ent_bound_ctx": ([_i, _i, _i], C.c_size_t),
+    "rdl_ent_encode_ctx": ([_vp, _vp, _vp, _i, _i, _i, _vp, C.c_size_t, _vp, _vp], _i),
+    "rdl_ent_decode_ctx": ([_vp, _vp, C.c_size_t, _vp, _vp, _i, _i, _vp, _vp, _vp], _i),
     "rdl_stage_keystat": ([_vp, _vp, _i, _i, _vp, _vp], _i),
     "rdl_stage_tmo_base": ([_vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp], _i),
     "rdl_stage_fit": ([_vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _vp], _i),
@@ -325,39 +329,55 @@ class Codec:
         return out[:int(n.item())]
 
     # ------------------------------------------------- entropy code of the layer
-    def ent_bound(self, H: int, W: int, log2_k: int = ENT_LOG2K_DEFAULT) -> int:
-        return int(self._L.rdl_ent_bound(H, W, log2_k))
+    # sdr (the decoded base layer, uint8 H x W x 3 on the device) selects the
+    # stream with residual contexts: each residual coded with the table of its
+    # context sdr >> 5.
+    def ent_bound(self, H: int, W: int, log2_k: int = ENT_LOG2K_DEFAULT, contexts: bool = False) -> int:
+        fn = self._L.rdl_ent_bound_ctx if contexts else self._L.rdl_ent_bound
+        return int(fn(H, W, log2_k))
 
     def ent_encode_into(self, resid: torch.Tensor, H: int, W: int, out: torch.Tensor, out_len: torch.Tensor,
-                        log2_k: int = ENT_LOG2K_DEFAULT, stream=None) -> None:
+                        log2_k: int = ENT_LOG2K_DEFAULT, stream=None, sdr: torch.Tensor | None = None) -> None:
         """Code stream of resid into out (uint8, >= ent_bound bytes); its length
         goes to out_len (one int64 on the device).  Does not synchronise."""
         assert out.dtype == torch.uint8 and out_len.dtype == torch.int64 and out_len.numel() == 1
-        _chk(self._L.rdl_ent_encode(self._h, _ptr(resid), H, W, int(log2_k), _ptr(out), out.numel(), _ptr(out_len),
-                                    _stream(stream)), "rdl_ent_encode")
+        if sdr is None:
+            _chk(self._L.rdl_ent_encode(self._h, _ptr(resid), H, W, int(log2_k), _ptr(out), out.numel(),
+                                        _ptr(out_len), _stream(stream)), "rdl_ent_encode")
+        else:
+            assert sdr.dtype == torch.uint8 and sdr.numel() == 3 * H * W and sdr.is_contiguous()
+            _chk(self._L.rdl_ent_encode_ctx(self._h, _ptr(resid), _ptr(sdr), H, W, int(log2_k), _ptr(out),
+                                            out.numel(), _ptr(out_len), _stream(stream)), "rdl_ent_encode_ctx")
 
     def ent_encode(self, resid: torch.Tensor, H: int, W: int, log2_k: int = ENT_LOG2K_DEFAULT,
-                   stream=None) -> torch.Tensor:
+                   stream=None, sdr: torch.Tensor | None = None) -> torch.Tensor:
         """Code stream of an enhancement layer, trimmed to its length (synchronises)."""
-        out = torch.empty(self.ent_bound(H, W, log2_k), dtype=torch.uint8, device=resid.device)
+        out = torch.empty(self.ent_bound(H, W, log2_k, sdr is not None), dtype=torch.uint8, device=resid.device)
         n = torch.zeros(1, dtype=torch.int64, device=resid.device)
-        self.ent_encode_into(resid, H, W, out, n, log2_k, stream)
+        self.ent_encode_into(resid, H, W, out, n, log2_k, stream, sdr)
         length = int(n.item())
         if length == 0:
             raise RdlError(RDL_EINVAL, "rdl_ent_encode (residual outside [-255, 255])")
         return out[:length]
 
     def ent_decode(self, code: torch.Tensor, H: int, W: int, out: torch.Tensor | None = None,
-                   status: torch.Tensor | None = None, header: np.ndarray | None = None, stream=None) -> torch.Tensor:
+                   status: torch.Tensor | None = None, header: np.ndarray | None = None, stream=None,
+                   sdr: torch.Tensor | None = None) -> torch.Tensor:
         """Enhancement layer (7 H W bytes) from a device code stream.  header: a
-        host copy of the stream's first ENT_HEADER_BYTES bytes (read from the
-        device, synchronously, when not given)."""
-        hdr = np.ascontiguousarray(header if header is not None else code[:ENT_HEADER_BYTES].cpu().numpy())
-        assert hdr.dtype == np.uint8 and hdr.size >= ENT_HEADER_BYTES
+        host copy of the stream's first ENT_HEADER_BYTES bytes (ENT_CTX_HEADER_BYTES
+        with sdr; read from the device, synchronously, when not given)."""
+        nh = ENT_HEADER_BYTES if sdr is None else ENT_CTX_HEADER_BYTES
+        hdr = np.ascontiguousarray(header if header is not None else code[:nh].cpu().numpy())
+        assert hdr.dtype == np.uint8 and hdr.size >= nh
         if out is None:
             out = torch.empty(7 * H * W, dtype=torch.uint8, device=code.device)
-        _chk(self._L.rdl_ent_decode(self._h, _ptr(code), code.numel(), hdr.ctypes.data, H, W, _ptr(out), _ptr(status),
-                                    _stream(stream)), "rdl_ent_decode")
+        if sdr is None:
+            _chk(self._L.rdl_ent_decode(self._h, _ptr(code), code.numel(), hdr.ctypes.data, H, W, _ptr(out),
+                                        _ptr(status), _stream(stream)), "rdl_ent_decode")
+        else:
+            assert sdr.dtype == torch.uint8 and sdr.numel() == 3 * H * W and sdr.is_contiguous()
+            _chk(self._L.rdl_ent_decode_ctx(self._h, _ptr(code), code.numel(), hdr.ctypes.data, _ptr(sdr), H, W,
+                                            _ptr(out), _ptr(status), _stream(stream)), "rdl_ent_decode_ctx")
         return out
 
     def profile_encode(self, rgbe: torch.Tensor, q: int, out, reps: int = 20, stream=None):

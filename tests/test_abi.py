@@ -108,6 +108,21 @@ def test_entropy_bound_and_argument_checks_host_only(O):
     assert L.rdl_set_ent_predict(None, 1) == rdl.RDL_EINVAL
 
 
+def test_entropy_context_bound_and_argument_checks_host_only(O):
+    """The context stream's header size and bound equal the oracle's; a
+    missing base layer and null pointers are rejected before device work."""
+    rdl, L = _lib()
+    src = open(HDR).read()
+    assert (int(re.search(r"#define RDL_ENT_CTX_HEADER_BYTES (\d+)", src).group(1)) == rdl.ENT_CTX_HEADER_BYTES
+            == O.ENT_HDR_CTX == 40 + 1024 * 25)
+    for H, W, k in [(1, 1, 4), (7, 9, 8), (2160, 3840, 8), (4321, 7679, 12)]:
+        assert L.rdl_ent_bound_ctx(H, W, k) == O.ent_bound(H, W, k, contexts=True)
+        assert L.rdl_ent_bound_ctx(H, W, k) == L.rdl_ent_bound(H, W, k) + O.ENT_HDR_CTX - O.ENT_HDR
+    assert L.rdl_ent_bound_ctx(0, 5, 8) == 0 and L.rdl_ent_bound_ctx(3, 3, 13) == 0
+    assert L.rdl_ent_encode_ctx(None, None, None, 3, 3, 8, None, 0, None, None) == rdl.RDL_EINVAL
+    assert L.rdl_ent_decode_ctx(None, None, 0, None, None, 3, 3, None, None, None) == rdl.RDL_EINVAL
+
+
 def test_jpeg_bound_host_only():
     rdl, L = _lib()
     assert L.rdl_jpeg_bound(0, 5) == 0 and L.rdl_jpeg_bound(70000, 5) == 0 and L.rdl_jpeg_bound(5, 65536) == 0

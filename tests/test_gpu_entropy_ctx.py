@@ -1,0 +1,157 @@
+"""GPU entropy code with residual contexts (each residual coded with the
+table of its context sdr >> 5) against the oracle: the stream must equal the
+oracle's byte for byte and the GPU decoder must return the layer exactly.
+Layers come from the GPU encoder (its sdr is the context source) or are drawn
+directly with a drawn sdr, at sizes that leave ragged groups and lanes, with
+contexts that leave tables empty."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2309_11072_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+HDR_CTX = 25640
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def rdl_mod():
+    from paper_2309_11072_amd import rdl
+    return rdl
+
+
+@pytest.fixture(scope="module")
+def codec(rdl_mod):
+    c = rdl_mod.Codec(0)
+    yield c
+    c.close()
+
+
+def make_layer(H, W, seed, spread=3.0, e_lo=110, e_hi=150, outlier=0.0):
+    rng = np.random.default_rng(seed)
+    r = np.clip(np.round(rng.laplace(0, spread, (3, H, W))), -255, 255)
+    if outlier:
+        m = rng.random((3, H, W)) < outlier
+        r[m] = rng.integers(-255, 256, int(m.sum()))
+    E = rng.integers(e_lo, e_hi, (H, W))
+    return np.concatenate([r.astype(np.int16).reshape(-1).view(np.uint8), E.astype(np.uint8).reshape(-1)])
+
+
+def make_sdr(H, W, seed, kind="uniform"):
+    rng = np.random.default_rng(seed + 1)
+    if kind == "uniform":
+        return rng.integers(0, 256, (H, W, 3)).astype(np.uint8)
+    if kind == "two":  # two contexts per channel, six tables empty
+        return rng.choice(np.array([20, 230], np.uint8), (H, W, 3))
+    return np.full((H, W, 3), 100, np.uint8)  # one context
+
+
+def ctx_roundtrip(codec, O, x, sdr, H, W, log2_k, predict=True):
+    d = torch.from_numpy(x).cuda()
+    s = torch.from_numpy(np.ascontiguousarray(sdr)).cuda()
+    codec.set_ent_predict(predict)
+    try:
+        code = codec.ent_encode(d, H, W, log2_k, sdr=s)
+    finally:
+        codec.set_ent_predict(True)
+    got = code.cpu().numpy().tobytes()
+    ref = O.ent_encode(x, H, W, log2_k, predict=predict, sdr=sdr)
+    assert len(got) == len(ref), (len(got), len(ref))
+    assert got == ref
+    status = torch.full((1,), 77, dtype=torch.int32, device="cuda")
+    back = codec.ent_decode(code, H, W, status=status, sdr=s)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    assert torch.equal(back, d)
+    return code
+
+
+CASES = [
+    (1, 1, 4, "uniform"), (7, 9, 4, "two"), (1, 1025, 4, "uniform"), (33, 257, 5, "one"),
+    (64, 65, 8, "uniform"), (97, 131, 4, "two"), (300, 401, 8, "uniform"), (512, 384, 12, "two"),
+    (1081, 1919, 8, "uniform"),
+]
+
+
+@pytest.mark.parametrize("H,W,log2_k,kind", CASES)
+@pytest.mark.parametrize("predict", [True, False])
+def test_stream_equals_oracle_and_decodes(codec, O, H, W, log2_k, kind, predict):
+    _say("entropy ctx case", H, W, log2_k, kind, predict)
+    ctx_roundtrip(codec, O, make_layer(H, W, H * 7 + W), make_sdr(H, W, H + W, kind), H, W, log2_k, predict)
+
+
+def test_wide_residuals_and_workspace_reuse(codec, O):
+    """Every residual value and exponent, then calls that alternate with the
+    plain stream on one context (the histograms of both are cleared)."""
+    for H, W, k, spread, out in [(40, 70, 4, 200.0, 0.5), (700, 900, 8, 3.0, 0.001), (50, 60, 4, 1.0, 0.0)]:
+        _say("entropy ctx wide/reuse", H, W, k)
+        x = make_layer(H, W, H + W, spread, 0, 256, out)
+        ctx_roundtrip(codec, O, x, make_sdr(H, W, H), H, W, k)
+        code = codec.ent_encode(torch.from_numpy(x).cuda(), H, W, k)
+        assert code.cpu().numpy().tobytes() == O.ent_encode(x, H, W, k)
+
+
+def test_encoder_layer_3840x2160(codec, O):
+    """The GPU encoder's layer and base layer of the 3840 x 2160 image: the
+    context stream equals the oracle's and is smaller than the plain one."""
+    sp = synth.image_3840x2160()
+    x = sp.make()
+    H, W = sp.H, sp.W
+    sdr, hdr, resid = codec.encode_enh(torch.from_numpy(x).cuda(), sp.q)
+    torch.cuda.synchronize()
+    layer = resid.cpu().numpy()
+    s = sdr.cpu().numpy()
+    _say("entropy ctx 3840x2160")
+    code = ctx_roundtrip(codec, O, layer, s, H, W, 8)
+    plain = codec.ent_encode(resid, H, W, 8)
+    assert code.numel() < plain.numel()
+
+
+def test_streams_do_not_cross_and_a_wrong_sdr_is_reported(codec, O, rdl_mod):
+    H, W = 90, 110
+    x = make_layer(H, W, 9)
+    sdr = make_sdr(H, W, 9, "two")
+    code = ctx_roundtrip(codec, O, x, sdr, H, W, 4)
+    d = torch.from_numpy(x).cuda()
+    plain = codec.ent_encode(d, H, W, 4)
+    s = torch.from_numpy(sdr).cuda()
+    with pytest.raises(rdl_mod.RdlError):
+        codec.ent_decode(code, H, W)  # a context stream without the base layer
+    with pytest.raises(rdl_mod.RdlError):
+        codec.ent_decode(plain, H, W, sdr=s)  # a plain stream to the context decoder
+    bad = code.clone()
+    bad[40 + 2 * 512 * 1] = 1  # table 1 (channel 0, context 1) was empty: no longer sums to 0 or M
+    with pytest.raises(rdl_mod.RdlError):
+        codec.ent_decode(bad, H, W, sdr=s)
+    # decoded against another base layer, symbols fall in empty tables
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    codec.ent_decode(code, H, W, status=status, sdr=torch.full((H, W, 3), 128, dtype=torch.uint8, device="cuda"))
+    torch.cuda.synchronize()
+    assert int(status.item()) == rdl_mod.RDL_ECORRUPT
+    # a group offset one word late
+    bad = code.clone()
+    bad[HDR_CTX + 8] += 1
+    status.zero_()
+    codec.ent_decode(bad, H, W, status=status, sdr=s)
+    torch.cuda.synchronize()
+    assert int(status.item()) == rdl_mod.RDL_ECORRUPT
+    status.fill_(5)
+    codec.ent_decode(code, H, W, status=status, sdr=s)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+
+
+def test_max_size_layer(codec, O):
+    """4321 x 7679 (33 MP, ragged) with a drawn base layer: the stream equals
+    the oracle's at the smallest and the largest group size."""
+    H, W = 4321, 7679
+    x = make_layer(H, W, 4321, spread=4.0, e_lo=100, e_hi=160, outlier=0.001)
+    sdr = make_sdr(H, W, 77)
+    for k in (4, 12):
+        _say("entropy ctx max size log2_k", k)
+        ctx_roundtrip(codec, O, x, sdr, H, W, k)
