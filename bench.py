@@ -270,11 +270,12 @@ def resid_bits(codec, resid, H, W):
     return sum(entropy_bits(h[c].tolist()) for c in range(3))
 
 
-def coded_bytes(codec, resid, H, W, code, clen):
+def coded_bytes(codec, resid, H, W, code, clen, sdr=None):
     """Size of the entropy-coded enhancement layer (residual planes and
-    exponent plane) of one image."""
+    exponent plane) of one image; with sdr (its decoded base layer) the
+    residuals are coded with per-context tables."""
     from paper_2309_11072_amd import rdl
-    codec.ent_encode_into(resid, H, W, code, clen, rdl.ENT_LOG2K_DEFAULT)
+    codec.ent_encode_into(resid, H, W, code, clen, rdl.ENT_LOG2K_DEFAULT, sdr=sdr)
     return int(clen.item())
 
 
@@ -416,13 +417,13 @@ def main():
 
     # ---- outside the timed region: losslessness and bits/pixel --------------
     if args.bits:
-        code = torch.empty(codec.ent_bound(max(s.H for s in specs), max(s.W for s in specs)), dtype=torch.uint8,
-                           device="cuda")
+        code = torch.empty(codec.ent_bound(max(s.H for s in specs), max(s.W for s in specs), contexts=True),
+                           dtype=torch.uint8, device="cuda")
         clen = torch.zeros(1, dtype=torch.int64, device="cuda")
         for mode, name in ((rdl.EST_SLR, "slr"), (rdl.EST_LEARNED, "learned")):
             codec.set_estimator(mode)
             codec.encode_batch(items)
-            h0 = cb = coded = 0.0
+            h0 = cb = coded = coded_ctx = 0.0
             ok = True
             flagged = 0
             for k, (it, s, im) in enumerate(zip(items, specs, imgs)):
@@ -431,12 +432,14 @@ def main():
                 h0 += resid_bits(codec, it[4], s.H, s.W) * s.H * s.W
                 cb += cond_bits(it[4], s.H, s.W) * s.H * s.W
                 coded += 8 * coded_bytes(codec, it[4], s.H, s.W, code, clen)
+                coded_ctx += 8 * coded_bytes(codec, it[4], s.H, s.W, code, clen, sdr=it[2])
                 ok &= bool(torch.equal(codec.decode_enh(it[2], it[3], it[4], s.H, s.W), im))
                 if mode == rdl.EST_LEARNED:
                     flagged += int(rdl.header_from_bytes(it[3])["flag"].sum())
             res.setdefault(name, {}).update({
                 "bits_per_pixel": round(h0 / npx, 4), "bits_per_pixel_given_E": round(cb / npx, 4),
-                "coded_bits_per_pixel": round(coded / npx, 4), "lossless": ok})
+                "coded_bits_per_pixel": round(coded / npx, 4),
+                "coded_bits_per_pixel_contexts": round(coded_ctx / npx, 4), "lossless": ok})
             if mode == rdl.EST_LEARNED:
                 res[name]["regions_learned"] = flagged
             say("%s: H0 %.4f, given E %.4f, coded %.4f bits/px, lossless %s" % (
@@ -545,10 +548,11 @@ def main():
         bits = {0: 0.0, 1: 0.0}
         cbits = {0: 0.0, 1: 0.0}
         coded = {0: 0.0, 1: 0.0}
+        coded_ctx = {0: 0.0, 1: 0.0}
         npx_eval = 0
         ok = True
         regions = [0, 0]
-        code = torch.empty(codec.ent_bound(1080, 1920), dtype=torch.uint8, device="cuda")
+        code = torch.empty(codec.ent_bound(1080, 1920, contexts=True), dtype=torch.uint8, device="cuda")
         clen = torch.zeros(1, dtype=torch.int64, device="cuda")
         for s in synth.learned_eval_set():
             xe = torch.from_numpy(s.make()).cuda()
@@ -559,6 +563,7 @@ def main():
                 bits[mode] += resid_bits(codec, oe[2], s.H, s.W) * s.H * s.W
                 cbits[mode] += cond_bits(oe[2], s.H, s.W) * s.H * s.W
                 coded[mode] += 8 * coded_bytes(codec, oe[2], s.H, s.W, code, clen)
+                coded_ctx[mode] += 8 * coded_bytes(codec, oe[2], s.H, s.W, code, clen, sdr=oe[0])
                 if mode == 1:
                     ok &= bool(torch.equal(codec.decode_enh(oe[0], oe[1], oe[2], s.H, s.W), xe))
                     he = rdl.header_from_bytes(oe[1])
@@ -573,6 +578,8 @@ def main():
                         "bits_per_pixel_given_E_learned": round(cbits[1] / npx_eval, 4),
                         "coded_bits_per_pixel_slr": round(coded[0] / npx_eval, 4),
                         "coded_bits_per_pixel_learned": round(coded[1] / npx_eval, 4),
+                        "coded_bits_per_pixel_contexts_slr": round(coded_ctx[0] / npx_eval, 4),
+                        "coded_bits_per_pixel_contexts_learned": round(coded_ctx[1] / npx_eval, 4),
                         "regions_learned": regions[0], "regions": regions[1], "lossless": ok,
                         "model_hash": "%016x" % model_format.blob_hash(blob)}
         say("held-out: SLR %.4f, learned %.4f bits/px (coded %.4f vs %.4f)" % (
@@ -607,6 +614,28 @@ def main():
                    "bits_per_pixel_coded": round(8 * nbytes / (H * W), 4), "lossless": ok}
         say("entropy code: %.1f us encode, %.1f us decode, %.4f bits/px" % (ms_e * 1e3, ms_d * 1e3,
                                                                           entropy["bits_per_pixel_coded"]))
+        # the same layer with residual contexts (the decoded base layer sdr)
+        del code
+        code = torch.empty(codec.ent_bound(H, W, k, contexts=True), dtype=torch.uint8, device="cuda")
+        for _ in range(3):
+            codec.ent_encode_into(resid, H, W, code, clen, k, sdr=sdr)
+        ms_ec = time_calls(lambda: codec.ent_encode_into(resid, H, W, code, clen, k, sdr=sdr), args.entropy_steps,
+                           stream)
+        nb_c = int(clen.item())
+        cview = code[:nb_c]
+        chdr = cview[:rdl.ENT_CTX_HEADER_BYTES].cpu().numpy()
+        for _ in range(3):
+            codec.ent_decode(cview, H, W, out=back, status=st, header=chdr, sdr=sdr)
+        ms_dc = time_calls(lambda: codec.ent_decode(cview, H, W, out=back, status=st, header=chdr, sdr=sdr),
+                           args.entropy_steps, stream)
+        ok_c = bool(torch.equal(back, resid)) and int(st.item()) == 0
+        entropy["contexts"] = {"ms_encode": round(ms_ec, 5),
+                               "Mpixel_s_encode": round(H * W / (ms_ec * 1e-3) / 1e6, 1),
+                               "ms_decode": round(ms_dc, 5),
+                               "Mpixel_s_decode": round(H * W / (ms_dc * 1e-3) / 1e6, 1),
+                               "bits_per_pixel_coded": round(8 * nb_c / (H * W), 4), "lossless": ok_c}
+        say("entropy code with contexts: %.1f us encode, %.1f us decode, %.4f bits/px" % (
+            ms_ec * 1e3, ms_dc * 1e3, entropy["contexts"]["bits_per_pixel_coded"]))
         del code, back
 
     # ---- base layer as a JPEG file, and the decoder --------------------------
