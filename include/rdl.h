@@ -160,7 +160,10 @@ int rdl_decode_batch(rdl_ctx *ctx, const rdl_dimage *imgs, int n, void *stream);
  * table and scratch accumulators of its own (hipMalloc, synchronous).  Later
  * calls with the same descriptors reuse it and only enqueue the stage
  * kernels.  The context keeps the 8 most recent plans; building a ninth
- * synchronises the device and frees the oldest.  Calls that share a plan
+ * waits for the oldest plan's last call to finish (an event recorded after
+ * it on its stream) and hands that plan's buffers to the new plan where they
+ * are large enough, so that a caller cycling through new image sets does not
+ * allocate per call once its sizes have been seen.  Calls that share a plan
  * share its scratch, so they must not overlap (same stream, or ordered). */
 typedef struct rdl_image {
     const uint8_t *rgbe;

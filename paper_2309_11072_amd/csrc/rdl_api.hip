@@ -28,6 +28,10 @@ struct Plan {
     uint8_t *d_ml = nullptr;      // learned path only
     uint64_t *d_lrec = nullptr;   // learned path only
     uint32_t *d_lhist = nullptr;  // learned path only
+    size_t cap_n = 0;   // images that d_desc and d_scratch hold
+    size_t cap_px = 0;  // pixels that d_ml and d_lrec hold
+    size_t cap_lh = 0;  // images that d_lhist holds
+    hipEvent_t done = nullptr;  // recorded after the plan's last call
     hipGraphExec_t exec = nullptr;
 };
 
@@ -359,6 +363,7 @@ bool same_key(const std::vector<ImgDesc> &a, const std::vector<ImgDesc> &b) {
 
 void free_plan(Plan &e) {
     if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (e.done) (void)hipEventDestroy(e.done);
     if (e.d_desc) (void)hipFree(e.d_desc);
     if (e.d_scratch) (void)hipFree(e.d_scratch);
     if (e.d_ml) (void)hipFree(e.d_ml);
@@ -367,22 +372,62 @@ void free_plan(Plan &e) {
     e = Plan();
 }
 
+// Move `field` of an idle plan `from` into `to` when its capacity covers
+// `need`; the caller allocates otherwise (and frees what stays in `from`).
+template <typename T>
+bool take_buf(T *&to, T *&from, size_t &to_cap, size_t from_cap, size_t need) {
+    if (!from || from_cap < need) return false;
+    to = from;
+    from = nullptr;
+    to_cap = from_cap;
+    return true;
+}
+
 // Allocate a plan's scratch (zeroed) and upload its bound descriptor table;
-// synchronous, so the host vector may go as soon as it returns.
-int build_plan(Plan &e, const std::vector<ImgDesc> &v, bool learned) {
+// synchronous, so the host vector may go as soon as it returns.  Buffers of
+// `spare` (an evicted plan whose last call has finished) serve again where
+// they are large enough, so that a caller cycling through new image sets does
+// not allocate per call; what it does not take stays in `spare`.
+int build_plan(Plan &e, const std::vector<ImgDesc> &v, bool learned, Plan &spare) {
     const size_t n = v.size();
-    HIPCHK(hipMalloc(&e.d_scratch, n * SCRATCH_I64 * sizeof(int64_t)));
+    if (!(spare.cap_n >= n && take_buf(e.d_desc, spare.d_desc, e.cap_n, spare.cap_n, n) &&
+          take_buf(e.d_scratch, spare.d_scratch, e.cap_n, spare.cap_n, n))) {
+        if (e.d_desc) {  // took the table but not the scratch: cannot happen (same capacity), kept general
+            HIPCHK(hipFree(e.d_desc));
+            e.d_desc = nullptr;
+        }
+        HIPCHK(hipMalloc(&e.d_desc, n * sizeof(ImgDesc)));
+        HIPCHK(hipMalloc(&e.d_scratch, n * SCRATCH_I64 * sizeof(int64_t)));
+        e.cap_n = n;
+    }
     HIPCHK(hipMemset(e.d_scratch, 0, n * SCRATCH_I64 * sizeof(int64_t)));
+    if (spare.done) {
+        e.done = spare.done;
+        spare.done = nullptr;
+    } else {
+        HIPCHK(hipEventCreateWithFlags(&e.done, hipEventDisableTiming));
+    }
     std::vector<ImgDesc> dv = v;
     for (size_t k = 0; k < n; ++k) bind_scratch(dv[k], e.d_scratch + k * SCRATCH_I64);
     if (learned) {
-        HIPCHK(hipMalloc(&e.d_ml, 4 * total_px(v)));
-        HIPCHK(hipMalloc(&e.d_lrec, total_px(v) * sizeof(uint64_t)));
-        HIPCHK(hipMalloc(&e.d_lhist, n * lhist_words() * sizeof(uint32_t)));
+        const size_t px = total_px(v);
+        if (!(spare.cap_px >= px && take_buf(e.d_ml, spare.d_ml, e.cap_px, spare.cap_px, px) &&
+              take_buf(e.d_lrec, spare.d_lrec, e.cap_px, spare.cap_px, px))) {
+            if (e.d_ml) {
+                HIPCHK(hipFree(e.d_ml));
+                e.d_ml = nullptr;
+            }
+            HIPCHK(hipMalloc(&e.d_ml, 4 * px));
+            HIPCHK(hipMalloc(&e.d_lrec, px * sizeof(uint64_t)));
+            e.cap_px = px;
+        }
+        if (!take_buf(e.d_lhist, spare.d_lhist, e.cap_lh, spare.cap_lh, n)) {
+            HIPCHK(hipMalloc(&e.d_lhist, n * lhist_words() * sizeof(uint32_t)));
+            e.cap_lh = n;
+        }
         HIPCHK(hipMemset(e.d_lhist, 0, n * lhist_words() * sizeof(uint32_t)));
         bind_learn(dv, e.d_ml, e.d_lrec, e.d_lhist);
     }
-    HIPCHK(hipMalloc(&e.d_desc, n * sizeof(ImgDesc)));
     HIPCHK(hipMemcpy(e.d_desc, dv.data(), n * sizeof(ImgDesc), hipMemcpyHostToDevice));
     return RDL_OK;
 }
@@ -549,15 +594,23 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
     if (!p) {
         // First sight of these buffers: a descriptor table and scratch of
         // their own, kept for later calls with the same descriptors.
+        Plan spare;
         if (c->plans.size() >= kMaxPlans) {
-            // The oldest plan may still be in use on any stream.
-            HIPCHK(hipDeviceSynchronize());
-            free_plan(c->plans.front());
+            // The oldest plan's last call may still run on its stream: wait
+            // for that call alone, then hand its buffers to the new plan.
+            Plan &old = c->plans.front();
+            HIPCHK(hipEventSynchronize(old.done));
+            spare = old;
             c->plans.erase(c->plans.begin());
+            if (spare.exec) {
+                (void)hipGraphExecDestroy(spare.exec);
+                spare.exec = nullptr;
+            }
         }
         Plan e;
         e.key = v;
-        const int rc = build_plan(e, v, learned);
+        const int rc = build_plan(e, v, learned, spare);
+        free_plan(spare);
         if (rc) {
             free_plan(e);
             return rc;
@@ -572,6 +625,7 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
             c->tlearned[c->tcalls++] = learned;
         }
         enqueue_encode(p->d_desc, n, gr, learned, s, c->gf, any_dct, ev);
+        HIPCHK(hipEventRecord(p->done, s));
         return check_launch("encoder kernels");
     }
     if (!p->exec) {
@@ -594,6 +648,7 @@ int rdl_encode_batch(rdl_ctx *c, const rdl_image *imgs, int n, void *stream) {
         }
     }
     HIPCHK(hipGraphLaunch(p->exec, s));
+    HIPCHK(hipEventRecord(p->done, s));
     return RDL_OK;
 }
 

@@ -202,3 +202,35 @@ def test_learned_graph_mode_replays_match_oracle(codec, rdl_mod, O):
     finally:
         codec.set_launch_mode(False)
         codec.set_estimator(0)
+
+
+def test_learned_plan_eviction_reuses_buffers(codec, rdl_mod, O):
+    """Twelve image sets, more than the context keeps plans for, in an order
+    whose sizes grow and shrink: every new plan past the eighth takes over the
+    evicted plan's buffers when they are large enough (else allocates), and
+    each encode still equals the oracle, on the first pass and on the second
+    (the evicted plans rebuilt), directly and through graphs."""
+    sizes = [(20, 30), (60, 90), (15, 17), (90, 120), (33, 33), (120, 150), (9, 70), (70, 9),
+             (100, 140), (8, 8), (130, 160), (40, 41)]
+    blob = synth.random_model(71, rq="pair")
+    _say("learned plan eviction: 12 sets, twice")
+    codec.set_model(blob)
+    codec.set_estimator(1)
+    try:
+        xs = [synth.generate(H, W, 3.0, seed=1200 + k, spec_frac=0.05) for k, (H, W) in enumerate(sizes)]
+        qs = [40 + 5 * k for k in range(len(sizes))]
+        refs = [O.encode_learned(x, q, blob) for x, q in zip(xs, qs)]
+        devs = [_dev(x) for x in xs]
+        outs = [codec.alloc_outputs(H, W) for H, W in sizes]
+        for graph in (False, True):
+            codec.set_launch_mode(graph)
+            for k in list(range(len(sizes))) * 2:
+                for t in outs[k]:
+                    t.fill_(0xAA)
+                sdr, hdr, resid = codec.encode_enh(devs[k], qs[k], out=outs[k])
+                torch.cuda.synchronize()
+                assert np.array_equal(resid.cpu().numpy(), refs[k]["resid"]), (graph, k)
+                assert np.array_equal(rdl_mod.header_from_bytes(hdr)["flag"], refs[k]["flag"]), (graph, k)
+    finally:
+        codec.set_launch_mode(False)
+        codec.set_estimator(0)
