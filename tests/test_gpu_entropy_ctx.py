@@ -4,6 +4,8 @@ oracle's byte for byte and the GPU decoder must return the layer exactly.
 Layers come from the GPU encoder (its sdr is the context source) or are drawn
 directly with a drawn sdr, at sizes that leave ragged groups and lanes, with
 contexts that leave tables empty."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -155,3 +157,25 @@ def test_max_size_layer(codec, O):
     for k in (4, 12):
         _say("entropy ctx max size log2_k", k)
         ctx_roundtrip(codec, O, x, sdr, H, W, k)
+
+
+def test_learned_batch_layers(codec, O, rdl_mod):
+    """Layers of a learned + fallback batch (flagged regions included), coded
+    with their own base layers as contexts: each stream equals the oracle's
+    and decodes back."""
+    specs = [(90, 130, 3.0, 45), (61, 83, 4.0, 75), (128, 97, 2.0, 95)]
+    with open(os.path.join(os.path.dirname(rdl_mod.__file__), "mlp_model.bin"), "rb") as fh:
+        blob = fh.read()
+    codec.set_model(blob)
+    codec.set_estimator(1)
+    try:
+        xs = [synth.generate(H, W, s, seed=1300 + k, spec_frac=0.05) for k, (H, W, s, q) in enumerate(specs)]
+        items = [(torch.from_numpy(x).cuda(), q) + tuple(codec.alloc_outputs(H, W))
+                 for x, (H, W, s, q) in zip(xs, specs)]
+        codec.encode_batch(items)
+        torch.cuda.synchronize()
+        for it, (H, W, s, q) in zip(items, specs):
+            _say("entropy ctx learned layer", H, W)
+            ctx_roundtrip(codec, O, it[4].cpu().numpy(), it[2].cpu().numpy(), H, W, 4)
+    finally:
+        codec.set_estimator(0)
