@@ -275,36 +275,66 @@ __global__ __launch_bounds__(ENT_HIST_THREADS) void k_ent_hist_vec(EntArgs a, in
     }
 }
 
-// Histograms of a stream with residual contexts: workgroup (x, p) counts
-// ENT_HIST_PX symbols of plane p.  A residual plane's counts go to its 8
-// context tables (bin (S >> 5) 512 + r + 255, 8 x 512 bins in ENT_HC
-// copies); plane 3 counts the exponent symbols' runs as k_ent_hist does.
+// Histograms of a stream with residual contexts: workgroup (x, 0) counts
+// ENT_HIST_PX pixels of the three residual planes, reading each pixel's three
+// context bytes once (S >> 5, kept packed in a register per pixel) and
+// counting the planes one after another in the same LDS bins (8 x 512 per
+// plane, ENT_HC copies), which it flushes between planes; workgroup (x, 1)
+// counts the exponent symbols' runs as k_ent_hist does.
 __global__ __launch_bounds__(ENT_HIST_THREADS) void k_ent_hist_ctx(EntArgs a) {
     __shared__ uint32_t h[ENT_NCTX * 512 * ENT_HC];
     static_assert(ENT_CMINOR && !ENT_PACK16, "k_ent_hist_ctx: one 32-bit counter per bin and copy");
-    for (int k = threadIdx.x; k < ENT_NCTX * 512 * ENT_HC; k += ENT_HIST_THREADS) h[k] = 0;
-    __syncthreads();
-    const int lane = threadIdx.x & 63, p = blockIdx.y;
+    const int lane = threadIdx.x & 63;
     const uint32_t mine = (uint32_t)lane & (ENT_HC - 1);
     const int64_t i0 = (int64_t)blockIdx.x * ENT_HIST_PX;
     const int n = (int)(a.N - i0 < ENT_HIST_PX ? a.N - i0 : ENT_HIST_PX);
     constexpr int PER = ENT_HIST_PX / ENT_HIST_THREADS;  // 32 px per thread
-    if (p < 3) {
-        const int16_t *rp = (const int16_t *)a.resid + p * a.N + i0;
-        const uint8_t *cp = a.sdr + 3 * i0 + p;
-        int v[PER];
-        uint32_t cx[PER];
+    auto clear = [&]() {
+        for (int k = threadIdx.x; k < ENT_NCTX * 512 * ENT_HC; k += ENT_HIST_THREADS) h[k] = 0;
+    };
+    auto flush = [&](int t0, int nb) {
+        for (int b = threadIdx.x; b < nb; b += ENT_HIST_THREADS) {
+            uint32_t v = 0;
+#pragma unroll
+            for (int k = 0; k < ENT_HC; ++k) v += h[ent_word(k, b)];
+            if (v) atomicAdd(&a.ws->hist[blockIdx.x % ENT_HSTRIPES][t0 + (b >> 9)][b & 511], v);
+        }
+    };
+    clear();
+    if (blockIdx.y == 0) {
+        const uint8_t *sp = a.sdr + 3 * i0;
+        // pixel j's contexts at bits 9 (j mod 3) + 3c of cx[j / 3], channel c
+        uint32_t cx[(PER + 2) / 3];
+#pragma unroll
+        for (int k = 0; k < (PER + 2) / 3; ++k) cx[k] = 0;
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const int i = min(j * ENT_HIST_THREADS + (int)threadIdx.x, n - 1);  // clamped: every load valid
-            v[j] = (int)rp[i];
-            cx[j] = (uint32_t)cp[3 * i] >> 5;
+            cx[j / 3] |= (((uint32_t)sp[3 * i] >> 5) | (((uint32_t)sp[3 * i + 1] >> 5) << 3) |
+                          (((uint32_t)sp[3 * i + 2] >> 5) << 6)) << (9 * (j % 3));
         }
+        __syncthreads();  // bins cleared
+#pragma unroll 1
+        for (int p = 0; p < 3; ++p) {
+            const int16_t *rp = (const int16_t *)a.resid + p * a.N + i0;
+            int v[PER];
 #pragma unroll
-        for (int j = 0; j < PER; ++j)
-            if (j * ENT_HIST_THREADS + (int)threadIdx.x < n)
-                ent_count(h, mine, cx[j] * 512 + min((uint32_t)(v[j] + 255), 511u), 1u);
+            for (int j = 0; j < PER; ++j) v[j] = (int)rp[min(j * ENT_HIST_THREADS + (int)threadIdx.x, n - 1)];
+#pragma unroll
+            for (int j = 0; j < PER; ++j)
+                if (j * ENT_HIST_THREADS + (int)threadIdx.x < n)
+                    ent_count(h, mine, ((cx[j / 3] >> (9 * (j % 3) + 3 * p)) & 7u) * 512 +
+                                           min((uint32_t)(v[j] + 255), 511u), 1u);
+            __syncthreads();
+            flush(ENT_NCTX * p, ENT_NCTX * 512);
+            if (p < 2) {
+                __syncthreads();  // every copy read before the clear
+                clear();
+                __syncthreads();
+            }
+        }
     } else {
+        __syncthreads();
         const uint8_t *e8 = a.eplane + i0;
         int ev[PER];
 #pragma unroll
@@ -323,14 +353,8 @@ __global__ __launch_bounds__(ENT_HIST_THREADS) void k_ent_hist_ctx(EntArgs a) {
             const int len = after ? (int)__builtin_ctzll(after) + 1 : 64 - lane;
             if (head && v >= 0) ent_count(h, mine, (uint32_t)v, (uint32_t)len);
         }
-    }
-    __syncthreads();
-    const int t0 = p < 3 ? ENT_NCTX * p : ENT_NTAB_CTX - 1, nb = p < 3 ? ENT_NCTX * 512 : 512;
-    for (int b = threadIdx.x; b < nb; b += ENT_HIST_THREADS) {
-        uint32_t v = 0;
-#pragma unroll
-        for (int k = 0; k < ENT_HC; ++k) v += h[ent_word(k, b)];
-        if (v) atomicAdd(&a.ws->hist[blockIdx.x % ENT_HSTRIPES][t0 + (b >> 9)][b & 511], v);
+        __syncthreads();
+        flush(ENT_NTAB_CTX - 1, 512);
     }
 }
 
@@ -1057,7 +1081,7 @@ void launch_ent_encode(const EntArgs &a, hipStream_t s) {
         hipLaunchKernelGGL(k_ent_ediff, dim3((unsigned)ent_etiles(a.N, lead)), dim3(256), 0, s, e, a.ediff, a.N, a.W);
     }
     if (a.flags & 2) {
-        hipLaunchKernelGGL(k_ent_hist_ctx, dim3((unsigned)((a.N + ENT_HIST_PX - 1) / ENT_HIST_PX), 4),
+        hipLaunchKernelGGL(k_ent_hist_ctx, dim3((unsigned)((a.N + ENT_HIST_PX - 1) / ENT_HIST_PX), 2),
                            dim3(ENT_HIST_THREADS), 0, s, a);
         hipLaunchKernelGGL(k_ent_freq, dim3(ENT_NTAB_CTX), dim3(512), 0, s, a);
         hipLaunchKernelGGL(k_ent_enc_ctx, dim3((unsigned)((a.G + 3) / 4), 4), dim3(256), 0, s, a);
