@@ -322,7 +322,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the library's default launch shapes")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: images shard across GPUs without any exchange, and this build "
+        print("bench.py measures one GPU only: images shard across GPUs without any exchange, and the library "
               "has no multi-GPU path.", file=sys.stderr)
         sys.exit(2)
 
