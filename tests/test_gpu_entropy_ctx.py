@@ -179,3 +179,26 @@ def test_learned_batch_layers(codec, O, rdl_mod):
             ctx_roundtrip(codec, O, it[4].cpu().numpy(), it[2].cpu().numpy(), H, W, 4)
     finally:
         codec.set_estimator(0)
+
+
+@pytest.mark.parametrize("H,W,res_off,sdr_off", [(97, 131, 2, 1), (300, 401, 6, 3), (17, 1, 2, 0), (3, 5, 0, 1)])
+def test_unaligned_layer_and_base_layer(codec, O, H, W, res_off, sdr_off):
+    """The layer at any 2-byte boundary and the base layer at any address: the
+    stream equals the oracle's and decodes back (into a buffer at the same
+    offsets)."""
+    _say("entropy ctx unaligned", H, W, res_off, sdr_off)
+    x = make_layer(H, W, H + 3 * W)
+    sdr = make_sdr(H, W, W)
+    rb = torch.zeros(x.size + res_off, dtype=torch.uint8, device="cuda")
+    rb[res_off:] = torch.from_numpy(x).cuda()
+    sb = torch.zeros(sdr.size + sdr_off, dtype=torch.uint8, device="cuda")
+    sb[sdr_off:] = torch.from_numpy(sdr.reshape(-1)).cuda()
+    d, s = rb[res_off:], sb[sdr_off:]
+    code = codec.ent_encode(d, H, W, 4, sdr=s)
+    assert code.cpu().numpy().tobytes() == O.ent_encode(x, H, W, 4, sdr=sdr)
+    ob = torch.zeros(x.size + res_off, dtype=torch.uint8, device="cuda")
+    status = torch.full((1,), 77, dtype=torch.int32, device="cuda")
+    codec.ent_decode(code, H, W, out=ob[res_off:], status=status, sdr=s)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    assert torch.equal(ob[res_off:], d)
