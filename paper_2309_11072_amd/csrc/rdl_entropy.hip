@@ -759,20 +759,23 @@ __global__ __launch_bounds__(256) void k_ent_dec(EntArgs a) {
 
 // Decoder of a residual plane with contexts: one group per wave, four groups
 // of plane blockIdx.y per workgroup.  The workgroup holds the plane's 8
-// context tables: the present symbols in order, {c | f << 16, symbol}, and per
-// table and bucket of 64 slots the index of the symbol holding the bucket's
-// first slot (the number of symbols with c <= 64 b, less one).  A step reads
-// its lanes' contexts (the base layer's bytes, loaded a block of 8 steps
-// ahead), takes slot = x mod M, and finds the symbol holding it by a binary
-// search between the bucket's entry and the next bucket's (at most 65
-// candidates, 7 halvings); the rest is dec_group's step.  A table that sums to
-// neither 0 nor M, a symbol 511, or a symbol whose context table is empty sets
-// *status = RDL_ECORRUPT.
+// context tables in 16-bit arrays: per table the present symbols' first slots
+// c (with M after the last) and symbols, and per bucket of 16 slots the index
+// of the symbol holding the bucket's first slot (the number of symbols with
+// c <= 16 b, less one: the last symbol whose first slot rounds up to bucket b
+// marks it, then a prefix maximum).  A step reads its lanes' contexts (the
+// base layer's bytes, loaded a block of 8 steps ahead), takes slot = x mod M,
+// and finds the symbol holding it by a binary search between the bucket's
+// entry and the next bucket's (at most 17 candidates, 5 halvings); the rest
+// is dec_group's step.  A table that sums to neither 0 nor M, a symbol 511,
+// or a symbol whose context table is empty sets *status = RDL_ECORRUPT.
+constexpr int ENT_CB = 2048;  // buckets per context table (16 slots each)
+
 template <typename LD>
-__device__ __forceinline__ bool dec_group_ctx(int16_t *dst, const uint8_t *ctx, int n, const uint2 (*dtab)[512],
-                                              const uint16_t (*bk)[512], const uint32_t *np, uint16_t *rg,
-                                              uint32_t (&R)[4], uint32_t b, uint32_t pos, uint32_t x, uint32_t nw,
-                                              const LD &ld, int lane) {
+__device__ __forceinline__ bool dec_group_ctx(int16_t *dst, const uint8_t *ctx, int n, const uint16_t (*pc)[513],
+                                              const uint16_t (*ps)[512], const uint16_t (*bk)[ENT_CB],
+                                              const uint32_t *np, uint16_t *rg, uint32_t (&R)[4], uint32_t b,
+                                              uint32_t pos, uint32_t x, uint32_t nw, const LD &ld, int lane) {
     bool bad = false;
     auto load_ctx = [&](int t0, uint32_t (&cv)[8]) {
 #pragma unroll
@@ -791,15 +794,15 @@ __device__ __forceinline__ bool dec_group_ctx(int16_t *dst, const uint8_t *ctx, 
         }
         const int i = t * 64 + lane;
         const bool have = i < n;
-        const uint32_t slot = x & (ENT_M - 1), bb = slot >> 6, P = np[k];
+        const uint32_t slot = x & (ENT_M - 1), bb = slot >> 4, P = np[k];
         bad = bad || (have && P == 0);
-        uint32_t lo = P ? bk[k][bb] : 0u, hi = P ? (bb < 511 ? bk[k][bb + 1] : P - 1) : 0u;
+        uint32_t lo = P ? bk[k][bb] : 0u, hi = P ? (bb < ENT_CB - 1 ? bk[k][bb + 1] : P - 1) : 0u;
         while (lo < hi) {
             const uint32_t mid = (lo + hi + 1) >> 1;
-            if ((dtab[k][mid].x & 0xFFFFu) <= slot) lo = mid; else hi = mid - 1;
+            if (pc[k][mid] <= slot) lo = mid; else hi = mid - 1;
         }
-        const uint2 e = dtab[k][lo];
-        const uint32_t xn = (e.x >> 16) * (x >> ENT_PB) + slot - (e.x & 0xFFFFu);
+        const uint32_t c = pc[k][lo], f = pc[k][lo + 1] - c, sym = ps[k][lo];
+        const uint32_t xn = f * (x >> ENT_PB) + slot - c;
         x = have ? xn : x;
         const bool ren = have && x < ENT_L;
         const uint64_t m = __builtin_amdgcn_ballot_w64(ren);
@@ -809,7 +812,7 @@ __device__ __forceinline__ bool dec_group_ctx(int16_t *dst, const uint8_t *ctx, 
         bad = bad || (ren && !inside);
         x = ren ? x << 16 | (inside ? wv : 0u) : x;
         pos += (uint32_t)__builtin_popcountll(m);
-        if (have) dst[i] = (int16_t)((int)e.y - 255);
+        if (have) dst[i] = (int16_t)((int)sym - 255);
     };
     const int T = (n + 63) >> 6;
     uint32_t cur[8], nxt[8];
@@ -826,18 +829,18 @@ __device__ __forceinline__ bool dec_group_ctx(int16_t *dst, const uint8_t *ctx, 
 }
 
 __global__ __launch_bounds__(256) void k_ent_dec_ctx(EntArgs a) {
-    __shared__ uint2 dtab[ENT_NCTX][512];
-    __shared__ uint16_t bk[ENT_NCTX][512];
+    __shared__ uint16_t pc[ENT_NCTX][513];
+    __shared__ uint16_t ps[ENT_NCTX][512];
+    __shared__ __align__(16) uint16_t bk[ENT_NCTX][ENT_CB];
     __shared__ uint32_t np[ENT_NCTX];
-    __shared__ uint32_t cntb[512];
     __shared__ uint32_t sh[4];
     __shared__ uint16_t ring[ENT_DEC_WAVES][512];
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int G = a.G, p = blockIdx.y, g = blockIdx.x * ENT_DEC_WAVES + w;
     bool corrupt = false;
     for (int k = 0; k < ENT_NCTX; ++k) {
-        cntb[2 * threadIdx.x] = 0;
-        cntb[2 * threadIdx.x + 1] = 0;
+        uint4 *bq = reinterpret_cast<uint4 *>(&bk[k][0]) + threadIdx.x;  // this thread's 8 buckets
+        *bq = make_uint4(0u, 0u, 0u, 0u);
         const uint32_t fw = reinterpret_cast<const uint32_t *>(a.code + 40 + 1024 * (ENT_NCTX * p + k))[threadIdx.x];
         const uint32_t s0 = 2 * threadIdx.x, f0 = fw & 0xFFFFu, f1 = fw >> 16;
         uint32_t tot, P;
@@ -846,23 +849,32 @@ __global__ __launch_bounds__(256) void k_ent_dec_ctx(EntArgs a) {
         const uint32_t nbad = block_sum<4>(s0 + 1 >= 511 && f1 ? 1u : 0u, sh);
         corrupt = corrupt || (tot != ENT_M && tot != 0) || nbad;  // uniform
         const bool use = tot == ENT_M && !nbad;
-        if (use && f0) {
-            dtab[k][j0] = make_uint2(c0 | f0 << 16, s0);
-            if ((c0 + 63) >> 6 < 512) atomicAdd(&cntb[(c0 + 63) >> 6], 1u);
+        // a present symbol at c marks bucket ceil(c / 16) unless the next
+        // present symbol (at c + f) rounds up to the same bucket
+        auto put = [&](uint32_t j, uint32_t c, uint32_t f, uint32_t sym) {
+            pc[k][j] = (uint16_t)c;
+            ps[k][j] = (uint16_t)sym;
+            const uint32_t bb = (c + 15) >> 4;
+            if (bb < ENT_CB && ((c + f + 15) >> 4) != bb) bk[k][bb] = (uint16_t)j;
+        };
+        if (use && f0) put(j0, c0, f0, s0);
+        if (use && f1) put(j0 + (f0 > 0), c0 + f0, f1, s0 + 1);
+        if (threadIdx.x == 0) {
+            np[k] = use ? P : 0u;
+            if (use) pc[k][P] = (uint16_t)ENT_M;
         }
-        if (use && f1) {
-            const uint32_t c1 = c0 + f0;
-            dtab[k][j0 + (f0 > 0)] = make_uint2(c1 | f1 << 16, s0 + 1);
-            if ((c1 + 63) >> 6 < 512) atomicAdd(&cntb[(c1 + 63) >> 6], 1u);
-        }
-        if (threadIdx.x == 0) np[k] = use ? P : 0u;
         __syncthreads();
-        const uint32_t b0 = cntb[2 * threadIdx.x], b1 = cntb[2 * threadIdx.x + 1];
-        uint32_t unused;
-        const uint32_t before = block_excl_scan<4>(b0 + b1, sh, unused);
-        // (the scan's barriers also keep the next table's clears after these reads)
-        bk[k][2 * threadIdx.x] = (uint16_t)(before + b0 - 1);
-        bk[k][2 * threadIdx.x + 1] = (uint16_t)(before + b0 + b1 - 1);
+        // prefix maximum over the 2048 marks, 8 per thread
+        uint4 v = *bq;
+        uint32_t e[8] = {v.x & 0xFFFFu, v.x >> 16, v.y & 0xFFFFu, v.y >> 16,
+                         v.z & 0xFFFFu, v.z >> 16, v.w & 0xFFFFu, v.w >> 16};
+#pragma unroll
+        for (int q = 1; q < 8; ++q) e[q] = max(e[q], e[q - 1]);
+        const uint32_t before = block_excl_max<4>(e[7], sh);
+        // (its barriers also keep the next table's clear after these reads)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) e[q] = max(e[q], before);
+        *bq = make_uint4(e[0] | e[1] << 16, e[2] | e[3] << 16, e[4] | e[5] << 16, e[6] | e[7] << 16);
     }
     __syncthreads();
     if (corrupt) {
@@ -895,7 +907,7 @@ __global__ __launch_bounds__(256) void k_ent_dec_ctx(EntArgs a) {
     const int64_t Z = (int64_t)64 << a.log2_k, base = (int64_t)g * Z;
     const int n = (int)(a.N - base < Z ? a.N - base : Z);
     const bool bad = dec_group_ctx(reinterpret_cast<int16_t *>(a.dst) + p * a.N + base, a.sdr + 3 * base + p, n,
-                                   dtab, bk, np, rg, R, b, pos, x, nw, ld, lane);
+                                   pc, ps, bk, np, rg, R, b, pos, x, nw, ld, lane);
     if (__ballot(bad) && lane == 0 && a.status) atomicExch(a.status, RDL_ECORRUPT);
 }
 
