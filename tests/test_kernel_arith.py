@@ -2,6 +2,7 @@
 with numpy (no GPU, no oracle): each kernel form must equal the plain
 definition on every input it can receive."""
 import numpy as np
+import pytest
 
 AQ_MAX = 255 << 22
 BQ_MIN, BQ_MAX = -65025 << 14, 65280 << 14
@@ -221,3 +222,57 @@ def test_learned_pow2_bias_fold():
         pk = (np.clip(x >> r, -128, 127) & 255) | ((np.clip(y >> r, -128, 127) & 255) << 8)
         assert np.array_equal(pk & 255, (a[0::2][:2500] - 128) & 255)
         assert np.array_equal(pk >> 8, (a[1::2][:2500] - 128) & 255)
+
+
+# ---------------------------------------------------------------------------
+# The context decoder's symbol lookup (k_ent_dec_ctx): per table the present
+# symbols' first slots c (with M after the last), a bucket index per 16 slots
+# marked by the last symbol whose c rounds up to the bucket, then a prefix
+# maximum; a binary search between a bucket's entry and the next one.
+def _ctx_tables(f):
+    M = 1 << 15
+    P = len(f)
+    c = np.concatenate([[0], np.cumsum(f)[:-1]])
+    pc = np.concatenate([c, [M]])
+    bk = np.zeros(2048, np.int64)
+    for j in range(P):
+        b = (int(c[j]) + 15) >> 4
+        if b < 2048 and ((int(c[j] + f[j]) + 15) >> 4) != b:
+            bk[b] = j
+    return pc, np.maximum.accumulate(bk)
+
+
+@pytest.mark.parametrize("kind", ["flat", "peaked", "ones", "single"])
+def test_context_decoder_lookup_finds_the_holder(kind):
+    """For every slot the search stays inside the table (at most 17
+    candidates, so 5 halvings) and ends at the symbol whose range holds it."""
+    M = 1 << 15
+    rng = np.random.default_rng(len(kind))
+    if kind == "flat":
+        h = rng.integers(1, 120, 400)
+    elif kind == "peaked":
+        h = np.maximum(1, (rng.laplace(0, 1, 300) ** 2 * 200).astype(np.int64))
+    elif kind == "ones":
+        h = np.ones(511, np.int64)
+    else:
+        h = np.array([12345])
+    # present symbols' frequencies by the stream's rule: 1 + floor(h (M - P) / N),
+    # the remainder to the largest count
+    h = h.astype(np.int64)
+    f = 1 + h * (M - len(h)) // h.sum()
+    f[int(np.argmax(h))] += M - f.sum()
+    assert f.min() >= 1 and f.sum() == M
+    pc, bk = _ctx_tables(f)
+    P = len(f)
+    holder = np.searchsorted(pc[:-1], np.arange(M), side="right") - 1
+    for slot in range(M):
+        bb = slot >> 4
+        lo, hi = int(bk[bb]), int(bk[bb + 1]) if bb < 2047 else P - 1
+        assert 0 <= lo <= hi <= P - 1 and hi - lo <= 16
+        while lo < hi:
+            mid = (lo + hi + 1) >> 1
+            if pc[mid] <= slot:
+                lo = mid
+            else:
+                hi = mid - 1
+        assert lo == holder[slot] and pc[lo] <= slot < pc[lo + 1]
